@@ -1,0 +1,190 @@
+/*
+ * libgmls.h -- C ABI of the MI355X (gfx950) GMLS stencil generator.
+ *
+ * Generalized moving least squares (Ha, Kuberry, Trask, Ryan, "Parallel
+ * implementation of a compatible high-order meshless method for the Stokes'
+ * equations"): for every target x_T the library finds the neighbours inside
+ * the kernel support (Section 2.1), builds the kernel-weighted polynomial
+ * sample matrix of an eps-scaled Taylor basis (Section 2.1, basis equations)
+ * or of a divergence-free vector basis (Section 2.2), solves the local
+ * least-squares problem (Section 2.1, normal equations A c = B u) and applies
+ * a target functional to the basis at x_T (Section 2.5) to give stencil
+ * weights alpha with  D u(x_T) ~ sum_j alpha_j u(x_j)  (Section 3.2).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked
+ *    "host".  The library owns only the opaque context (its stream, a
+ *    workspace that grows on demand, tuning options).
+ *  - Work is enqueued on the context's HIP stream.  Calls return without
+ *    waiting for the GPU except where a result must reach the host (marked
+ *    "synchronises").
+ *  - Arguments are validated before anything is enqueued; a failure returns
+ *    GMLS_ERR_ARG and leaves outputs untouched.  HIP runtime failures return
+ *    GMLS_ERR_HIP.  gmls_last_error() gives a message for the last non-OK
+ *    status of that context.  No C++ exception crosses this boundary.
+ *  - Floating point data are IEEE double; indices are int32 (source ids)
+ *    and int64 (CSR offsets).
+ *  - A context may be used by one host thread at a time.
+ */
+#ifndef LIBGMLS_H
+#define LIBGMLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gmls_ctx_s *gmls_ctx;
+
+typedef enum {
+  GMLS_OK = 0,
+  GMLS_ERR_ARG = 1,         /* invalid argument (nothing enqueued)              */
+  GMLS_ERR_HIP = 2,         /* HIP runtime error                                */
+  GMLS_ERR_NOMEM = 3,       /* device workspace allocation failed               */
+  GMLS_ERR_CAPACITY = 4,    /* col_capacity too small; required size returned   */
+  GMLS_ERR_UNSUPPORTED = 5, /* shape outside the compiled kernels' range        */
+  GMLS_WARN_TARGET_FLAGS = 6 /* finished; some targets are rank deficient       */
+} gmls_status;
+
+/* basis of the local polynomial space */
+enum {
+  GMLS_BASIS_SCALAR = 0, /* eps-scaled Taylor monomials of total degree <= m (Section 2.1)      */
+  GMLS_BASIS_DIVFREE = 1 /* divergence-free vector polynomials of degree <= m (Section 2.2)     */
+};
+
+/* functional bit mask; output rows appear in the order value, gradient,
+ * Laplacian, divergence.  Scalar basis: value (1 row), gradient (dim rows),
+ * Laplacian (1 row).  Divergence-free basis: value (dim rows, one per output
+ * component), vector Laplacian (dim rows), divergence (1 row, identically
+ * zero on this basis).  Gradient on the vector basis and divergence on the
+ * scalar basis return GMLS_ERR_UNSUPPORTED. */
+enum { GMLS_F_VALUE = 1, GMLS_F_GRAD = 2, GMLS_F_LAPLACIAN = 4, GMLS_F_DIV = 8 };
+
+/* arithmetic of the local solve */
+enum {
+  GMLS_PREC_FP64 = 0, /* Householder QR of sqrt(W) P in FP64                                 */
+  GMLS_PREC_MIXED = 1 /* FP32 Gram + FP32 Cholesky, FP64 residual refinement, FP64 weights,
+                         FP64 QR fallback for ill-conditioned targets                        */
+};
+
+/* neighbour search rule */
+enum {
+  GMLS_SEARCH_KNN = 0,   /* the k nearest sources, ties broken by smaller index;
+                            eps_T = eps_mult * (distance to the k-th)                       */
+  GMLS_SEARCH_RADIUS = 1 /* every source with distance < radius (eps_T = radius); when fewer
+                            than k_min, the k_min nearest with eps_T = (d_kmin + d_kmin+1)/2 */
+};
+
+/* per-target status codes written to target_status */
+enum {
+  GMLS_TARGET_OK = 0,
+  GMLS_TARGET_RANK_DEFICIENT = 1, /* fewer rows than basis functions, or the QR rank test
+                                     failed; weights are NaN                               */
+  GMLS_TARGET_FALLBACK = 2,       /* mixed path handed the target to the FP64 QR path       */
+  GMLS_TARGET_NOT_CONVERGED = 3   /* mixed refinement did not converge; FP64 QR result      */
+};
+
+typedef struct {
+  int32_t mode;    /* GMLS_SEARCH_KNN or GMLS_SEARCH_RADIUS                  */
+  int32_t k;       /* kNN: neighbour count (1 <= k <= n_src)                  */
+  double eps_mult; /* kNN: eps_T = eps_mult * d_k (must be > 1 for d_k < eps)  */
+  double radius;   /* radius mode: search radius (> 0)                         */
+  int32_t k_min;   /* radius mode: floor on the neighbour count (<= n_src - 1) */
+  int32_t reserved;
+} gmls_search;
+
+/* filled (host memory) when a non-NULL report is passed to gmls_stencils;
+ * that call then synchronises the stream */
+typedef struct {
+  int64_t n_targets;
+  int64_t n_ok;
+  int64_t n_rank_deficient;
+  int64_t n_fallback;      /* mixed: targets recomputed by FP64 QR (condition or breakdown) */
+  int64_t n_not_converged; /* mixed: refinement budget exhausted (also recomputed by QR)    */
+  int32_t sweep_hist[16];  /* mixed: targets by number of refinement sweeps used            */
+  double cond_max;         /* mixed: largest condition estimate of the equilibrated Gram    */
+  double t_bin_ms;         /* GPU time of the binning kernels                                */
+  double t_stencil_ms;     /* GPU time of the stencil kernels (all bins)                     */
+  double t_fallback_ms;    /* GPU time of the FP64 fallback kernel                           */
+} gmls_report;
+
+/* Options for gmls_set_option (mixed path). */
+enum {
+  GMLS_OPT_COND_THRESHOLD = 0, /* fallback when the Gram condition estimate exceeds it (1e6) */
+  GMLS_OPT_MAX_SWEEPS = 1,     /* refinement sweeps before giving up (8)                      */
+  GMLS_OPT_REFINE_TOL = 2,     /* stop when |correction| <= tol * |y| (1e-12)                 */
+  GMLS_OPT_FORCE_FALLBACK = 3  /* nonzero: every mixed target takes the FP64 fallback (0)      */
+};
+
+/* Create a context on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t; NULL means the null stream).  *out receives the handle. */
+gmls_status gmls_create(gmls_ctx *out, int device, void *hip_stream);
+
+/* Release the context and its device workspace (synchronises its stream). */
+void gmls_destroy(gmls_ctx ctx);
+
+/* Message for the last non-OK status on this context ("" if none).  The
+ * string stays valid until the next call on the context. */
+const char *gmls_last_error(gmls_ctx ctx);
+
+/* Set a tuning option (see GMLS_OPT_*). */
+gmls_status gmls_set_option(gmls_ctx ctx, int option, double value);
+
+/* Neighbour search (Section 2.1: the neighbours of x_T are the particles
+ * within distance eps of it).
+ *   coords   [n_src][dim] sources;  targets [n_tgt][dim]  (may alias coords)
+ *   dim      1, 2 or 3
+ *   spec     host pointer to the search rule
+ *   row_ptr  out: int64 [n_tgt + 1] CSR offsets (row_ptr[0] = 0)
+ *   col      out: int32 [col_capacity] source indices; each row is sorted by
+ *            (squared distance, index); squared distances are evaluated as
+ *            (dx*dx + dy*dy) + dz*dz in IEEE double without fused multiply-add
+ *   eps      out: [n_tgt] support radius of every target
+ *   nnz_host host out: total neighbour count
+ * kNN rows hold exactly k entries.  Radius rows hold between k_min and
+ * 2048 entries (more returns GMLS_ERR_UNSUPPORTED).  If the total exceeds
+ * col_capacity nothing is written to col, *nnz_host gets the size needed and
+ * GMLS_ERR_CAPACITY is returned.  Synchronises (to return nnz). */
+gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                           int64_t n_tgt, int dim, const gmls_search *spec, int64_t *row_ptr, int32_t *col,
+                           int64_t col_capacity, double *eps, int64_t *nnz_host);
+
+/* Output shape (host only): number of functional rows F, input components
+ * C_in (1 scalar, dim vector) and basis size Q for a basis/order/mask. */
+gmls_status gmls_stencil_shape(int dim, int order, int basis, unsigned functional_mask, int *F, int *C_in,
+                               int *Q);
+
+/* Stencil weights (Section 2.1 normal equations and Section 2.5 functionals:
+ * alpha = W P (P^T W P)^{-1} lambda, with W(r) = (1 - r/eps)^p for r < eps).
+ *   coords, targets, dim  as for gmls_neighbors
+ *   order     polynomial order m (scalar: 0..4 in 2D/3D; divergence-free: 1..4)
+ *   basis     GMLS_BASIS_*; functional_mask GMLS_F_*
+ *   weight_p  kernel power p (1..12)
+ *   eps, row_ptr, col   support radii and CSR neighbour lists (any row order)
+ *   prec      GMLS_PREC_FP64 or GMLS_PREC_MIXED
+ *   weights   out: target t owns F*C_in*row_ptr[t] ... ; inside, the entry
+ *             (f*N_t + j)*C_in + c is the weight of input component c of
+ *             neighbour j (the j-th entry of the row) in functional row f
+ *   target_status  out (nullable): uint8 [n_tgt], GMLS_TARGET_*
+ *   report    host out (nullable): summary; a non-NULL report synchronises
+ * Rows must satisfy 1 <= N_t <= 256 (N_t < Q gives a rank-deficient target).
+ * Returns GMLS_WARN_TARGET_FLAGS when a report is requested and some targets
+ * are rank deficient. */
+gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                          int64_t n_tgt, int dim, int order, int basis, unsigned functional_mask, int weight_p,
+                          const double *eps, const int64_t *row_ptr, const int32_t *col, int prec,
+                          double *weights, uint8_t *target_status, gmls_report *report);
+
+/* Apply stencils to a field (Section 3.2, the stencil sum over neighbours):
+ *   out[t*F + f] = sum_j sum_c weights[F*C_in*row_ptr[t] + (f*N_t + j)*C_in + c]
+ *                               * field[col[row_ptr[t] + j]*C_in + c]
+ * field [n_src][C_in], out [n_tgt][F]. */
+gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, const int32_t *col,
+                       const double *weights, int F, int C_in, const double *field, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBGMLS_H */

@@ -1,0 +1,218 @@
+"""Python binding of libgmls (MI355X GMLS stencil generation).
+
+Argument marshalling only: every step of neighbour search, stencil
+generation and stencil application runs in the HIP kernels of
+``libgmls.so``.  PyTorch supplies device memory and the stream.  There is no
+CPU fallback: importing works without the library (so the package can be
+inspected), but every call raises if ``libgmls.so`` is missing.
+
+The names mirror the C ABI in ``include/libgmls.h``:
+``gmls_neighbors``, ``gmls_stencil_shape``, ``gmls_stencils``, ``gmls_apply``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "LIB_PATH", "GmlsError", "Context", "SearchSpec", "Report", "load_library",
+    "gmls_neighbors", "gmls_stencil_shape", "gmls_stencils", "gmls_apply",
+    "BASIS_SCALAR", "BASIS_DIVFREE", "F_VALUE", "F_GRAD", "F_LAPLACIAN", "F_DIV",
+    "PREC_FP64", "PREC_MIXED", "SEARCH_KNN", "SEARCH_RADIUS",
+    "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK",
+    "EXPORTED_SYMBOLS",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgmls.so")
+
+BASIS_SCALAR, BASIS_DIVFREE = 0, 1
+F_VALUE, F_GRAD, F_LAPLACIAN, F_DIV = 1, 2, 4, 8
+PREC_FP64, PREC_MIXED = 0, 1
+SEARCH_KNN, SEARCH_RADIUS = 0, 1
+OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
+GMLS_OK, GMLS_ERR_CAPACITY, GMLS_WARN_TARGET_FLAGS = 0, 4, 6
+_STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY", 5: "ERR_UNSUPPORTED",
+           6: "WARN_TARGET_FLAGS"}
+EXPORTED_SYMBOLS = ("gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
+                    "gmls_stencil_shape", "gmls_stencils", "gmls_apply")
+
+
+class GmlsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libgmls {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SearchSpec(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("k", ctypes.c_int32), ("eps_mult", ctypes.c_double),
+                ("radius", ctypes.c_double), ("k_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("n_targets", ctypes.c_int64), ("n_ok", ctypes.c_int64), ("n_rank_deficient", ctypes.c_int64),
+                ("n_fallback", ctypes.c_int64), ("n_not_converged", ctypes.c_int64),
+                ("sweep_hist", ctypes.c_int32 * 16), ("cond_max", ctypes.c_double), ("t_bin_ms", ctypes.c_double),
+                ("t_stencil_ms", ctypes.c_double), ("t_fallback_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "sweep_hist"}
+        d["sweep_hist"] = list(self.sweep_hist)
+        return d
+
+
+_lib = None
+_vp, _i64, _i32, _d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+
+
+def load_library():
+    """Load libgmls.so (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    L.gmls_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _vp]
+    L.gmls_create.restype = ctypes.c_int
+    L.gmls_destroy.argtypes = [_vp]
+    L.gmls_destroy.restype = None
+    L.gmls_last_error.argtypes = [_vp]
+    L.gmls_last_error.restype = ctypes.c_char_p
+    L.gmls_set_option.argtypes = [_vp, ctypes.c_int, _d]
+    L.gmls_set_option.restype = ctypes.c_int
+    L.gmls_neighbors.argtypes = [_vp, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.POINTER(SearchSpec), _vp, _vp, _i64,
+                                 _vp, ctypes.POINTER(_i64)]
+    L.gmls_neighbors.restype = ctypes.c_int
+    L.gmls_stencil_shape.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int)]
+    L.gmls_stencil_shape.restype = ctypes.c_int
+    L.gmls_stencils.argtypes = [_vp, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.POINTER(Report)]
+    L.gmls_stencils.restype = ctypes.c_int
+    L.gmls_apply.argtypes = [_vp, _i64, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
+    L.gmls_apply.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _check_dev(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("libgmls takes device tensors only")
+
+
+class Context:
+    """Owns a libgmls context (stream, device workspace, options)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        L = load_library()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = L.gmls_create(ctypes.byref(h), device, ctypes.c_void_p(stream.cuda_stream))
+        if st != GMLS_OK:
+            raise GmlsError(st, "gmls_create failed")
+        self._h = h
+        self._col_cap = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().gmls_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st):
+        msg = load_library().gmls_last_error(self._h).decode()
+        raise GmlsError(st, msg)
+
+    def set_option(self, option: int, value: float):
+        st = load_library().gmls_set_option(self._h, option, float(value))
+        if st != GMLS_OK:
+            self._raise(st)
+
+
+def gmls_stencil_shape(dim: int, order: int, basis: int, mask: int):
+    """(F, C_in, Q) of a basis/order/functional mask."""
+    F, C, Q = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    st = load_library().gmls_stencil_shape(dim, order, basis, mask, ctypes.byref(F), ctypes.byref(C), ctypes.byref(Q))
+    if st != GMLS_OK:
+        raise GmlsError(st, "unsupported basis/functional combination")
+    return F.value, C.value, Q.value
+
+
+def gmls_neighbors(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, mode: int, k: int = 0,
+                   eps_mult: float = 1.5, radius: float = 0.0, k_min: int = 0, col: torch.Tensor | None = None):
+    """Neighbour lists: returns (row_ptr int64 [n_tgt+1], col int32 [nnz], eps float64 [n_tgt])."""
+    _check_dev(coords, targets)
+    n_src, dim = coords.shape
+    n_tgt = targets.shape[0]
+    dev = coords.device
+    spec = SearchSpec(mode, k, eps_mult, radius, k_min, 0)
+    row_ptr = torch.empty(n_tgt + 1, dtype=torch.int64, device=dev)
+    eps = torch.empty(n_tgt, dtype=torch.float64, device=dev)
+    if col is None:
+        cap = n_tgt * k if mode == SEARCH_KNN else max(ctx._col_cap, n_tgt * max(k_min, 1) * 2)
+        col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    nnz = ctypes.c_int64()
+    L = load_library()
+    args = lambda c: (ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, ctypes.byref(spec), _ptr(row_ptr),
+                      _ptr(c), c.numel(), _ptr(eps), ctypes.byref(nnz))
+    st = L.gmls_neighbors(*args(col))
+    if st == GMLS_ERR_CAPACITY:
+        col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+        st = L.gmls_neighbors(*args(col))
+    if st != GMLS_OK:
+        ctx._raise(st)
+    ctx._col_cap = max(ctx._col_cap, nnz.value)
+    return row_ptr, col[: nnz.value], eps
+
+
+def gmls_stencils(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, order: int, basis: int, mask: int,
+                  weight_p: int, eps: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor,
+                  prec: int = PREC_FP64, weights: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                  report: bool = False):
+    """Stencil weights.  Returns (weights float64, status uint8, report dict or None)."""
+    _check_dev(coords, targets, eps, row_ptr, col)
+    n_src, dim = coords.shape
+    n_tgt = targets.shape[0]
+    F, C, _ = gmls_stencil_shape(dim, order, basis, mask)
+    nnz = col.numel()
+    if weights is None:
+        weights = torch.empty(max(F * C * nnz, 1), dtype=torch.float64, device=coords.device)
+    if status is None:
+        status = torch.empty(max(n_tgt, 1), dtype=torch.uint8, device=coords.device)
+    rep = Report()
+    st = load_library().gmls_stencils(ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, order, basis, mask,
+                                      weight_p, _ptr(eps), _ptr(row_ptr), _ptr(col), prec, _ptr(weights),
+                                      _ptr(status), ctypes.byref(rep) if report else None)
+    if st not in (GMLS_OK, GMLS_WARN_TARGET_FLAGS):
+        ctx._raise(st)
+    return weights[: F * C * nnz], status[:n_tgt], (rep.as_dict() if report else None)
+
+
+def gmls_apply(ctx: Context, row_ptr: torch.Tensor, col: torch.Tensor, weights: torch.Tensor, F: int, C: int,
+               field: torch.Tensor, out: torch.Tensor | None = None):
+    """out[t, f] = sum_j sum_c alpha[t, f, j, c] field[col_j, c]."""
+    _check_dev(row_ptr, col, weights, field)
+    n_tgt = row_ptr.numel() - 1
+    if out is None:
+        out = torch.empty((max(n_tgt, 1), F), dtype=torch.float64, device=field.device)
+    st = load_library().gmls_apply(ctx._h, n_tgt, _ptr(row_ptr), _ptr(col), _ptr(weights), F, C, _ptr(field),
+                                   _ptr(out))
+    if st != GMLS_OK:
+        ctx._raise(st)
+    return out[:n_tgt]

@@ -1,0 +1,307 @@
+// api.cpp -- the C ABI of libgmls (include/libgmls.h): argument validation,
+// workspace management and the launch sequence of each call.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+
+#include "gmls_internal.hpp"
+
+using namespace gmls;
+
+void *gmls_ctx_s::ws(int slot, size_t bytes) {
+  if (slot < 0 || slot >= WS_NUM_SLOTS) return nullptr;
+  if ((int)slots.size() < WS_NUM_SLOTS) slots.resize(WS_NUM_SLOTS, {nullptr, 0});
+  auto &e = slots[slot];
+  if (bytes == 0) bytes = 1;
+  if (e.second >= bytes) return e.first;
+  if (e.first) {
+    hipStreamSynchronize(stream);
+    hipFree(e.first);
+    e.first = nullptr;
+    e.second = 0;
+  }
+  size_t want = std::max(bytes, e.second + e.second / 4);
+  void *p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    want = bytes;
+  }
+  e.first = p;
+  e.second = want;
+  return p;
+}
+
+gmls_ctx_s::~gmls_ctx_s() {
+  hipStreamSynchronize(stream);
+  for (auto &e : slots)
+    if (e.first) hipFree(e.first);
+  for (auto &e : ev)
+    if (e) hipEventDestroy(e);
+}
+
+gmls_status gmls_set_error(gmls_ctx ctx, gmls_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) hipSetDevice(prev);
+  }
+};
+
+int shape_rows(int dim, int basis, unsigned mask) {
+  if (basis == GMLS_BASIS_SCALAR) {
+    if (mask & GMLS_F_DIV) return -1;
+    return ((mask & GMLS_F_VALUE) ? 1 : 0) + ((mask & GMLS_F_GRAD) ? dim : 0) + ((mask & GMLS_F_LAPLACIAN) ? 1 : 0);
+  }
+  if (mask & GMLS_F_GRAD) return -1;
+  return ((mask & GMLS_F_VALUE) ? dim : 0) + ((mask & GMLS_F_LAPLACIAN) ? dim : 0) + ((mask & GMLS_F_DIV) ? 1 : 0);
+}
+
+long binom_l(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+}  // namespace
+
+#define GMLS_HIP(...)                                                                                     \
+  do {                                                                                                     \
+    hipError_t e_ = (__VA_ARGS__);                                                                                \
+    if (e_ != hipSuccess)                                                                                  \
+      return gmls_set_error(ctx, GMLS_ERR_HIP, std::string(#__VA_ARGS__) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+extern "C" {
+
+gmls_status gmls_create(gmls_ctx *out, int device, void *hip_stream) {
+  if (!out) return GMLS_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return GMLS_ERR_ARG;
+  }
+  gmls_ctx ctx = new (std::nothrow) gmls_ctx_s();
+  if (!ctx) return GMLS_ERR_NOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->slots.resize(WS_NUM_SLOTS, {nullptr, 0});
+  DeviceGuard g(device);
+  for (auto &e : ctx->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      delete ctx;
+      return GMLS_ERR_HIP;
+    }
+  *out = ctx;
+  return GMLS_OK;
+}
+
+void gmls_destroy(gmls_ctx ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  delete ctx;
+}
+
+const char *gmls_last_error(gmls_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
+  if (!ctx) return GMLS_ERR_ARG;
+  switch (option) {
+    case GMLS_OPT_COND_THRESHOLD:
+      if (!(value > 0)) return gmls_set_error(ctx, GMLS_ERR_ARG, "condition threshold must be > 0");
+      ctx->opt.cond_threshold = value;
+      return GMLS_OK;
+    case GMLS_OPT_MAX_SWEEPS:
+      if (!(value >= 1 && value <= 15)) return gmls_set_error(ctx, GMLS_ERR_ARG, "max sweeps must be 1..15");
+      ctx->opt.max_sweeps = (int)value;
+      return GMLS_OK;
+    case GMLS_OPT_REFINE_TOL:
+      if (!(value > 0 && value < 1)) return gmls_set_error(ctx, GMLS_ERR_ARG, "refine tol must be in (0, 1)");
+      ctx->opt.refine_tol = value;
+      return GMLS_OK;
+    case GMLS_OPT_FORCE_FALLBACK:
+      ctx->opt.force_fallback = value != 0;
+      return GMLS_OK;
+    default:
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "unknown option");
+  }
+}
+
+gmls_status gmls_stencil_shape(int dim, int order, int basis, unsigned functional_mask, int *F, int *C_in,
+                               int *Q) {
+  if (dim < 1 || dim > 3 || order < 0 || order > 8 || (basis != GMLS_BASIS_SCALAR && basis != GMLS_BASIS_DIVFREE))
+    return GMLS_ERR_ARG;
+  if (functional_mask == 0 || (functional_mask & ~15u)) return GMLS_ERR_ARG;
+  const int f = shape_rows(dim, basis, functional_mask);
+  if (f < 0) return GMLS_ERR_UNSUPPORTED;
+  const long qs = binom_l(order + dim, dim);
+  const long q = basis == GMLS_BASIS_SCALAR ? qs : dim * qs - (order >= 1 ? binom_l(order - 1 + dim, dim) : 0);
+  if (F) *F = f;
+  if (C_in) *C_in = basis == GMLS_BASIS_SCALAR ? 1 : dim;
+  if (Q) *Q = (int)q;
+  return GMLS_OK;
+}
+
+gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                           int64_t n_tgt, int dim, const gmls_search *spec, int64_t *row_ptr, int32_t *col,
+                           int64_t col_capacity, double *eps, int64_t *nnz_host) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (!spec || !nnz_host) return gmls_set_error(ctx, GMLS_ERR_ARG, "spec and nnz_host must be non-null");
+  if (dim < 1 || dim > 3) return gmls_set_error(ctx, GMLS_ERR_ARG, "dim must be 1, 2 or 3");
+  if (n_src < 1 || n_src > (1ll << 28)) return gmls_set_error(ctx, GMLS_ERR_ARG, "n_src must be in [1, 2^28]");
+  if (n_tgt < 0 || n_tgt > (1ll << 31) - 1) return gmls_set_error(ctx, GMLS_ERR_ARG, "n_tgt out of range");
+  if (!coords || !row_ptr || (n_tgt > 0 && (!targets || !eps)))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  if (col_capacity < 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "col_capacity must be >= 0");
+  if (col_capacity > 0 && !col) return gmls_set_error(ctx, GMLS_ERR_ARG, "col is null");
+  if (spec->mode == GMLS_SEARCH_KNN) {
+    if (spec->k < 1 || spec->k > 1024 || spec->k > n_src)
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "knn: k must be in [1, min(1024, n_src)]");
+    if (!(spec->eps_mult > 0) || !isfinite(spec->eps_mult))
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "knn: eps_mult must be finite and > 0");
+    if ((double)n_tgt * spec->k > 2147483647.0 * 4)
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "knn: output too large");
+  } else if (spec->mode == GMLS_SEARCH_RADIUS) {
+    if (!(spec->radius > 0) || !isfinite(spec->radius))
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "radius must be finite and > 0");
+    if (spec->k_min < 0 || spec->k_min > 1024 || spec->k_min + 1 > n_src)
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "radius: k_min must be in [0, min(1024, n_src - 1)]");
+  } else {
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "unknown search mode");
+  }
+  DeviceGuard g(ctx->device);
+  return run_neighbors(ctx, coords, n_src, targets, n_tgt, dim, *spec, row_ptr, col, col_capacity, eps, nnz_host);
+}
+
+gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                          int64_t n_tgt, int dim, int order, int basis, unsigned functional_mask, int weight_p,
+                          const double *eps, const int64_t *row_ptr, const int32_t *col, int prec,
+                          double *weights, uint8_t *target_status, gmls_report *report) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  int F = 0, C = 0, Q = 0;
+  gmls_status st = gmls_stencil_shape(dim, order, basis, functional_mask, &F, &C, &Q);
+  if (st != GMLS_OK) return gmls_set_error(ctx, st, "functional/basis combination not supported or bad shape");
+  if (!qr_supported(dim, order, basis))
+    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "compiled kernels cover dim 2-3 and order 1-4");
+  if (prec != GMLS_PREC_FP64 && prec != GMLS_PREC_MIXED) return gmls_set_error(ctx, GMLS_ERR_ARG, "bad precision");
+  if (prec == GMLS_PREC_MIXED && !mixed_supported(dim, order, basis))
+    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "mixed precision not compiled for this basis/order");
+  if (weight_p < 1 || weight_p > 12) return gmls_set_error(ctx, GMLS_ERR_ARG, "weight power must be 1..12");
+  if (n_src < 1 || n_tgt < 0 || n_tgt > (1ll << 31) - 1)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "n_src must be >= 1 and n_tgt in [0, 2^31)");
+  if (n_tgt > 0 && (!coords || !targets || !eps || !row_ptr || !col || !weights))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  if (report) memset(report, 0, sizeof(*report));
+  if (n_tgt == 0) return GMLS_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+  const int n = (int)n_tgt;
+  BinMeta *meta = (BinMeta *)ctx->ws(WS_BIN_META, sizeof(BinMeta));
+  int *list = (int *)ctx->ws(WS_BIN_LIST, sizeof(int) * (size_t)n);
+  int *fb = (int *)ctx->ws(WS_FALLBACK, sizeof(int) * (size_t)n);
+  Stats *stats = (Stats *)ctx->ws(WS_STATS, sizeof(Stats));
+  uint8_t *status = target_status ? target_status : (uint8_t *)ctx->ws(WS_STATUS_TMP, (size_t)n);
+  if (!meta || !list || !fb || !stats || !status)
+    return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+
+  StencilArgs a;
+  a.coords = coords;
+  a.targets = targets;
+  a.eps = eps;
+  a.row_ptr = row_ptr;
+  a.col = col;
+  a.weights = weights;
+  a.status = status;
+  a.mask = functional_mask;
+  a.F = F;
+  a.p = weight_p;
+  a.n_tgt = n;
+
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[0], s));
+  GMLS_HIP(launch_binning(row_ptr, n, Q, C, meta, list, s));
+  BinMeta hm;
+  GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
+  GMLS_HIP(hipStreamSynchronize(s));
+  if (hm.err) return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 256 neighbours");
+  GMLS_HIP(hipMemsetAsync(stats, 0, sizeof(Stats), s));
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[1], s));
+  if (hm.count[0] > 0) GMLS_HIP(launch_rank_deficient(a, C, list, meta, s));
+  int cus = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  for (int b = 1; b < kNumBins; ++b) {
+    if (hm.count[b] == 0) continue;
+    if (prec == GMLS_PREC_FP64) {
+      const int nb = std::min(hm.count[b], cus * 16);
+      GMLS_HIP(launch_qr_bin(dim, order, basis, b, a, list, meta, nb, s));
+    } else {
+      const int nb = std::min((hm.count[b] + 3) / 4, cus * 16);
+      GMLS_HIP(launch_mixed_bin(dim, order, basis, b, a, list, meta, fb, stats, ctx->opt, nb, s));
+    }
+  }
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
+  if (prec == GMLS_PREC_MIXED) GMLS_HIP(launch_qr_fallback(dim, order, basis, a, fb, meta, 4, cus * 8, s));
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[3], s));
+  if (!report) return GMLS_OK;
+
+  Stats hs;
+  GMLS_HIP(hipMemcpyAsync(&hs, stats, sizeof(Stats), hipMemcpyDeviceToHost, s));
+  GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
+  GMLS_HIP(hipStreamSynchronize(s));
+  float t01 = 0, t12 = 0, t23 = 0;
+  hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
+  hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
+  hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
+  report->n_targets = n_tgt;
+  report->n_rank_deficient = hm.count[0];
+  report->n_fallback = (int64_t)hs.n_fallback;
+  report->n_not_converged = (int64_t)hs.n_not_converged;
+  report->n_ok = n_tgt - hm.count[0];
+  for (int i = 0; i < 16; ++i) report->sweep_hist[i] = (int32_t)hs.sweep_hist[i];
+  double cmax;
+  memcpy(&cmax, &hs.cond_max_bits, sizeof(double));
+  report->cond_max = cmax;
+  report->t_bin_ms = t01;
+  report->t_stencil_ms = t12;
+  report->t_fallback_ms = t23;
+  return hm.count[0] > 0 ? GMLS_WARN_TARGET_FLAGS : GMLS_OK;
+}
+
+gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, const int32_t *col,
+                       const double *weights, int F, int C_in, const double *field, double *out) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (n_tgt < 0 || F < 1 || F > 16 || C_in < 1 || C_in > 3)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "bad n_tgt, F or C_in");
+  if (n_tgt > 0 && (!row_ptr || !col || !weights || !field || !out))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  DeviceGuard g(ctx->device);
+  GMLS_HIP(launch_apply(n_tgt, row_ptr, col, weights, F, C_in, field, out, ctx->stream));
+  return GMLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,143 @@
+// gmls_internal.hpp -- context, workspace and the launch interfaces shared by
+// the translation units of libgmls (host side only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/libgmls.h"
+
+namespace gmls {
+
+// Workspace slots owned by a context (device memory, grown on demand).
+enum Slot {
+  WS_BBOX = 0,
+  WS_GRID,
+  WS_CELL_KEY,
+  WS_CELL_COUNT,
+  WS_CELL_START,
+  WS_SORTED,
+  WS_TGT_KEY,
+  WS_TGT_COUNT,
+  WS_TGT_START,
+  WS_TGT_ORDER,
+  WS_ROW_COUNT,
+  WS_SCAN_TMP,
+  WS_FLAGS,
+  WS_BIN_META,
+  WS_BIN_LIST,
+  WS_FALLBACK,
+  WS_STATS,
+  WS_STATUS_TMP,
+  WS_NUM_SLOTS
+};
+
+struct Options {
+  double cond_threshold = 1e6;
+  int max_sweeps = 8;
+  double refine_tol = 1e-12;
+  int force_fallback = 0;
+};
+
+}  // namespace gmls
+
+struct gmls_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  std::vector<std::pair<void *, size_t>> slots;
+  gmls::Options opt;
+  hipEvent_t ev[8] = {};
+
+  // Device buffer of at least `bytes` for `slot`; nullptr on failure.
+  void *ws(int slot, size_t bytes);
+  ~gmls_ctx_s();
+};
+
+namespace gmls {
+
+// Source point after the cell sort: coordinates, original index.
+struct SPoint {
+  double x, y, z;
+  int idx;
+  int pad;
+};
+
+// Uniform cell grid over the sources (cells numbered x fastest).
+struct GridParams {
+  double lo[3];
+  double c, inv_c;
+  int nc[3];
+  int ncell;
+};
+
+// Bin bookkeeping of the stencil scheduler (device memory).
+struct BinMeta {
+  int count[8];    // targets per bin
+  int offset[8];   // start of the bin in the packed list
+  int cursor[8];   // fill cursor (binning) / work counter (stencils)
+  int fb_count;    // targets queued for the FP64 fallback
+  int fb_cursor;   // fallback work counter
+  int err;         // nonzero: a row longer than the compiled maximum
+  int pad;
+};
+
+// Per-call statistics accumulated on the device (mixed path).
+struct Stats {
+  unsigned long long n_fallback;
+  unsigned long long n_not_converged;
+  unsigned long long n_rank_def;
+  unsigned long long sweep_hist[16];
+  unsigned long long cond_max_bits;  // max of a non-negative double, as bits
+};
+
+// ---- search (search.hip) ----
+gmls_status run_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                          int64_t n_tgt, int dim, const gmls_search &spec, int64_t *row_ptr, int32_t *col,
+                          int64_t col_capacity, double *eps, int64_t *nnz_host);
+
+// ---- stencils (stencil_*.hip) ----
+struct StencilArgs {
+  const double *coords;
+  const double *targets;
+  const double *eps;
+  const int64_t *row_ptr;
+  const int32_t *col;
+  double *weights;
+  uint8_t *status;  // never null inside kernels (a workspace stands in)
+  unsigned mask;
+  int F;            // functional rows of this basis/mask
+  int p;            // kernel power
+  int n_tgt;
+};
+
+// Per-bin stencil launches; `bin` selects the rows-per-lane instantiation.
+hipError_t launch_qr_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,
+                         BinMeta *meta, int n_blocks, hipStream_t s);
+hipError_t launch_qr_fallback(int dim, int order, int basis, const StencilArgs &a, const int *list,
+                              BinMeta *meta, int max_bin, int n_blocks, hipStream_t s);
+hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,
+                            BinMeta *meta, int *fb_list, Stats *stats, const Options &opt, int n_blocks,
+                            hipStream_t s);
+bool qr_supported(int dim, int order, int basis);
+bool mixed_supported(int dim, int order, int basis);
+
+// binning (stencil_bins.hip)
+hipError_t launch_binning(const int64_t *row_ptr, int n_tgt, int Q, int rows_per_nbr, BinMeta *meta, int *list,
+                          hipStream_t s);
+hipError_t launch_rank_deficient(const StencilArgs &a, int C, const int *list, BinMeta *meta, hipStream_t s);
+
+// apply (apply.hip)
+hipError_t launch_apply(int64_t n_tgt, const int64_t *row_ptr, const int32_t *col, const double *weights, int F,
+                        int C, const double *field, double *out, hipStream_t s);
+
+// number of bins: 0 = rank deficient (N*C < Q), b >= 1: N <= 64*b
+constexpr int kNumBins = 5;
+constexpr int kMaxRows = 256;
+
+}  // namespace gmls
+
+gmls_status gmls_set_error(gmls_ctx ctx, gmls_status st, const std::string &msg);

@@ -1,0 +1,412 @@
+#pragma once
+// stencil_fp64.hpp -- FP64 stencils by Householder QR, one wavefront per target.
+//
+// For target T with N neighbours the weighted sample matrix M = sqrt(W) P
+// (N x Q, Section 2.1: P, W and the scaled basis) lives in registers, row j
+// on lane j % 64, slot j / 64.  Householder QR (Golub & Van Loan, Alg. 5.2.1)
+// reduces M to R with one batched wave all-reduce per column.  Since
+// P^T W P = R^T R, the weights of a functional lambda (Section 2.5) are
+//   y = R^{-1} R^{-T} lambda,   alpha_j = w_j p(s_j) . y
+// which is alpha = W P (P^T W P)^{-1} lambda (Section 2.1, normal equations)
+// evaluated through R: the semi-normal-equations form of the minimum
+// W^{-1}-norm solution of P^T alpha = lambda, stable for that problem when R
+// comes from a backward-stable QR (Paige 1979; Bjorck 1987).
+//
+// Divergence-free basis (Section 2.2): with psi = (p (x) I_d) T the vector
+// sample matrix is (sqrt(W) P (x) I_d) T = (Q1 (x) I)(R (x) I) T, so its R
+// factor is the R factor of the small matrix K = (R (x) I_d) T
+// (d*Q x Q_d); K is factored by Householder QR in LDS and
+//   y = R_K^{-1} R_K^{-T} lambda,  u = T y,  alpha_{j,c} = w_j p(s_j) . u_c.
+#include <float.h>
+#include <math.h>
+
+#include "basis.hpp"
+#include "divfree.hpp"
+#include "gmls_internal.hpp"
+
+namespace gmls {
+
+constexpr double kRankTol = 1e-12;  // QR rank test: min|R_kk| <= tol * max|R_kk|
+
+// Rows of one target held by a wavefront; loads coordinates and weights.
+template <int DIM, int RPL>
+struct Rows {
+  double s[RPL][DIM];
+  double w[RPL];
+  int N;
+  int64_t base;
+};
+
+template <int DIM, int RPL>
+__device__ __forceinline__ void load_rows(const StencilArgs &a, int t, Rows<DIM, RPL> &r, int lane) {
+  r.base = uniform_i64(a.row_ptr[t]);
+  r.N = readfirstlane_i((int)(a.row_ptr[t + 1] - r.base));
+  const double e = uniform_d(a.eps[t]);
+  const double ie = 1.0 / e;
+  double xt[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) xt[d] = uniform_d(a.targets[(int64_t)t * DIM + d]);
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int j = lane + 64 * i;
+    double rr = 0.0;
+    if (j < r.N) {
+      const int c = a.col[r.base + j];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        r.s[i][d] = (a.coords[(int64_t)c * DIM + d] - xt[d]) * ie;
+        rr += r.s[i][d] * r.s[i][d];
+      }
+      const double rad = sqrt(rr);
+      r.w[i] = rad < 1.0 ? int_pow(1.0 - rad, a.p) : 0.0;
+    } else {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) r.s[i][d] = 0.0;
+      r.w[i] = 0.0;
+    }
+  }
+}
+
+// Householder QR of the register-resident M (rows across lanes).  On return
+// lane k (k < Q) holds row k of R in M[0][k..Q-1] and rdiag = R_kk.
+template <int Q, int RPL>
+__device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rdiag, int lane) {
+  rdiag = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    double dots[Q];
+    const double x0 = lane >= k ? M[0][k] : 0.0;
+#pragma unroll
+    for (int l = k; l < Q; ++l) {
+      double v = x0 * (lane >= k ? M[0][l] : 0.0);
+#pragma unroll
+      for (int i = 1; i < RPL; ++i) v += M[i][k] * M[i][l];
+      dots[l] = v;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int l = k; l < Q; ++l) dots[l] += __shfl_xor(dots[l], off, 64);
+#pragma unroll
+    for (int l = k; l < Q; ++l) dots[l] = uniform_d(dots[l]);
+    const double sigma = dots[k];
+    const double xk = readlane_d(M[0][k], k);
+    if (sigma > 0.0) {
+      const double norm = sqrt(sigma);
+      const double beta = xk >= 0.0 ? -norm : norm;
+      const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
+      // v = x - beta e_k on rows >= k
+      const double v0 = lane > k ? M[0][k] : (lane == k ? xk - beta : 0.0);
+#pragma unroll
+      for (int l = k + 1; l < Q; ++l) {
+        const double rkl = readlane_d(M[0][l], k);
+        const double coef = 2.0 * (dots[l] - beta * rkl) * inv_vtv;
+        M[0][l] -= coef * v0;
+#pragma unroll
+        for (int i = 1; i < RPL; ++i) M[i][l] -= coef * M[i][k];
+      }
+      if (lane == k) M[0][k] = beta;
+    } else if (lane == k) {
+      M[0][k] = 0.0;
+    }
+    if (lane == k) rdiag = M[0][k];
+  }
+}
+
+// Solve R^T z = b then R y = z for a Q x Q upper-triangular R stored
+// row-major (Rm) and column-major (Rt) in LDS; lane a < Q holds b_a on entry
+// and y_a on return.  rdiag is R_aa on lane a.
+template <int Q>
+__device__ __forceinline__ double tri_solve_rtr(const double *Rm, const double *Rt, double b, double rdiag,
+                                                int lane) {
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double zk = readlane_d(b, k) / readlane_d(rdiag, k);
+    if (lane == k) b = zk;
+    if (lane > k && lane < Q) b -= Rm[k * Q + lane] * zk;
+  }
+#pragma unroll
+  for (int k = Q - 1; k >= 0; --k) {
+    const double yk = readlane_d(b, k) / readlane_d(rdiag, k);
+    if (lane == k) b = yk;
+    if (lane < k) b -= Rt[k * Q + lane] * yk;
+  }
+  return b;
+}
+
+template <int DIM, int ORDER, int RPL>
+__device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
+  constexpr Mono<DIM, ORDER> MO{};
+  constexpr int Q = MO.N;
+  const int lane = lane_id();
+  Rows<DIM, RPL> r;
+  load_rows<DIM, RPL>(a, t, r, lane);
+  double M[RPL][Q];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    double p[Q];
+    scaled_basis<DIM, ORDER, double>(r.s[i], p);
+    const double sw = sqrt(r.w[i]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q];
+  }
+  double rdiag;
+  wave_householder<Q, RPL>(M, rdiag, lane);
+  const double amax = uniform_d(wave_max(lane < Q ? fabs(rdiag) : 0.0));
+  const double amin = uniform_d(wave_min(lane < Q ? fabs(rdiag) : DBL_MAX));
+  double *Rm = lds, *Rt = lds + Q * Q, *Y = lds + 2 * Q * Q;
+  const int F = a.F;
+  const int rank_def = readfirstlane_i(!(amin > kRankTol * amax) ? 1 : 0);
+  if (rank_def) {
+    for (int i = 0; i < RPL; ++i) {
+      const int j = lane + 64 * i;
+      if (j < r.N)
+        for (int f = 0; f < F; ++f) a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = NAN;
+    }
+    if (lane == 0) a.status[t] = GMLS_TARGET_RANK_DEFICIENT;
+    __syncthreads();
+    return;
+  }
+  if (lane < Q) {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) {
+      const double v = l >= lane ? M[0][l] : 0.0;
+      Rm[lane * Q + l] = v;
+      Rt[l * Q + lane] = v;
+    }
+  }
+  __syncthreads();
+  const double ie = 1.0 / uniform_d(a.eps[t]);
+  for (int f = 0; f < F; ++f) {
+    double b = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+      if (lane == q) b = scalar_lambda<DIM, ORDER>(rk.kind[f], q, ie);
+    const double y = tri_solve_rtr<Q>(Rm, Rt, b, rdiag, lane);
+    if (lane < Q) Y[f * Q + lane] = y;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int j = lane + 64 * i;
+    if (j < r.N) {
+      double p[Q];
+      scaled_basis<DIM, ORDER, double>(r.s[i], p);
+      for (int f = 0; f < F; ++f) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc += p[q] * Y[f * Q + q];
+        a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = r.w[i] * acc;
+      }
+    }
+  }
+  if (lane == 0) a.status[t] = GMLS_TARGET_OK;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// divergence-free basis
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER, int RPL>
+__device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
+  constexpr Mono<DIM, ORDER> MO{};
+  constexpr int Q = MO.N;
+  const DivFreeTab<DIM, ORDER> &DF = kDivFree<DIM, ORDER>;
+  constexpr int QD = DivFreeTab<DIM, ORDER>::QD;
+  constexpr int KR = DIM * Q;  // rows of K
+  const int lane = lane_id();
+  Rows<DIM, RPL> r;
+  load_rows<DIM, RPL>(a, t, r, lane);
+  double M[RPL][Q];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    double p[Q];
+    scaled_basis<DIM, ORDER, double>(r.s[i], p);
+    const double sw = sqrt(r.w[i]);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q];
+  }
+  double rdiag;
+  wave_householder<Q, RPL>(M, rdiag, lane);
+  const int F = a.F;
+  // scalar R in LDS (row-major), then K = (R (x) I) T column-major [QD][KR]
+  double *Rs = lds;              // Q*Q
+  double *K = lds + Q * Q;       // QD*KR
+  double *Y = K + QD * KR;       // F*QD (y), then F*KR (u = T y)
+  double *U = Y + 8 * QD;
+  if (lane < Q) {
+#pragma unroll
+    for (int l = 0; l < Q; ++l) Rs[lane * Q + l] = l >= lane ? M[0][l] : 0.0;
+  }
+  __syncthreads();
+  // K[(alpha, c), i] = sum_beta R[alpha][beta] T[(beta, c), i]; T has at most
+  // two nonzeros per column: (ia, ca, va) and (ib, cb, vb)
+  for (int e = lane; e < QD * KR; e += 64) {
+    const int i = e / KR, row = e - i * KR;
+    const int al = row / DIM, c = row - al * DIM;
+    double v = 0.0;
+    const int ia = DF.ia[i], ib = DF.ib[i];
+    if (DF.ca[i] == c) v += DF.va[i] * Rs[al * Q + ia];
+    if (ib >= 0 && DF.cb[i] == c) v += DF.vb[i] * Rs[al * Q + ib];
+    K[e] = v;
+  }
+  __syncthreads();
+  // Householder QR of K (KR x QD, column-major) in LDS, rows across lanes
+  constexpr int KRL = (KR + 63) / 64;
+  double kdiag = 0.0;  // R_K[i][i] on lane i % 64, slot i / 64 -> kept in LDS instead
+  double *Kd = U + 8 * KR;  // QD diagonal entries
+  for (int k = 0; k < QD; ++k) {
+    double xs[KRL];
+    double part = 0.0;
+#pragma unroll
+    for (int q = 0; q < KRL; ++q) {
+      const int row = lane + 64 * q;
+      xs[q] = (row >= k && row < KR) ? K[k * KR + row] : 0.0;
+      part += xs[q] * xs[q];
+    }
+    const double sigma = uniform_d(wave_sum(part));
+    const double xk = uniform_d(K[k * KR + k]);
+    double beta = 0.0;
+    if (sigma > 0.0) {
+      const double norm = sqrt(sigma);
+      beta = xk >= 0.0 ? -norm : norm;
+      const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
+      double v[KRL];
+#pragma unroll
+      for (int q = 0; q < KRL; ++q) {
+        const int row = lane + 64 * q;
+        v[q] = row == k ? xk - beta : xs[q];
+      }
+      for (int l = k + 1; l < QD; ++l) {
+        double dp = 0.0;
+#pragma unroll
+        for (int q = 0; q < KRL; ++q) {
+          const int row = lane + 64 * q;
+          if (row >= k && row < KR) dp += v[q] * K[l * KR + row];
+        }
+        dp = uniform_d(wave_sum(dp));
+        const double coef = 2.0 * dp * inv_vtv;
+#pragma unroll
+        for (int q = 0; q < KRL; ++q) {
+          const int row = lane + 64 * q;
+          if (row >= k && row < KR) K[l * KR + row] -= coef * v[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (lane == 0) {
+      K[k * KR + k] = beta;
+      Kd[k] = beta;
+    }
+    __syncthreads();
+  }
+  (void)kdiag;
+  // rank test on both factors
+  double dmax = 0.0, dmin = DBL_MAX;
+  for (int k = lane; k < QD; k += 64) {
+    dmax = fmax(dmax, fabs(Kd[k]));
+    dmin = fmin(dmin, fabs(Kd[k]));
+  }
+  dmax = uniform_d(wave_max(dmax));
+  dmin = uniform_d(wave_min(dmin));
+  if (readfirstlane_i(!(dmin > kRankTol * dmax) ? 1 : 0)) {
+    for (int i = 0; i < RPL; ++i) {
+      const int j = lane + 64 * i;
+      if (j < r.N)
+        for (int f = 0; f < F; ++f)
+          for (int c = 0; c < DIM; ++c)
+            a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = NAN;
+    }
+    if (lane == 0) a.status[t] = GMLS_TARGET_RANK_DEFICIENT;
+    __syncthreads();
+    return;
+  }
+  const double ie = 1.0 / uniform_d(a.eps[t]);
+  // y = R_K^{-1} R_K^{-T} lambda for every row; R_K[k][l] = K[l*KR + k]
+  for (int f = 0; f < F; ++f) {
+    const int kind = rk.kind[f], comp = rk.comp[f];
+    // lambda_i = functional on psi_i: value c -> T[(0,c),i];
+    // Laplacian c -> eps^-2 sum_d T[(2e_d,c),i]; divergence -> 0
+    for (int i = lane; i < QD; i += 64) Y[f * QD + i] = divfree_lambda<DIM, ORDER>(i, kind, comp, ie);
+    __syncthreads();
+    if (kind != FK_DIV) {
+      // forward: R_K^T z = lambda (one lane walks the columns; QD <= 85)
+      for (int k = 0; k < QD; ++k) {
+        const double zk = uniform_d(Y[f * QD + k] / Kd[k]);
+        __syncthreads();
+        if (lane == 0) Y[f * QD + k] = zk;
+        for (int l = k + 1 + lane; l < QD; l += 64) Y[f * QD + l] -= K[l * KR + k] * zk;
+        __syncthreads();
+      }
+      for (int k = QD - 1; k >= 0; --k) {
+        const double yk = uniform_d(Y[f * QD + k] / Kd[k]);
+        __syncthreads();
+        if (lane == 0) Y[f * QD + k] = yk;
+        for (int l = lane; l < k; l += 64) Y[f * QD + l] -= K[k * KR + l] * yk;
+        __syncthreads();
+      }
+    } else {
+      for (int i = lane; i < QD; i += 64) Y[f * QD + i] = 0.0;
+    }
+    __syncthreads();
+    // u = T y  (KR entries)
+    for (int row = lane; row < KR; row += 64) U[f * KR + row] = 0.0;
+    __syncthreads();
+    if (lane == 0)
+      for (int i = 0; i < QD; ++i) {
+        const double yi = Y[f * QD + i];
+        U[f * KR + DF.ia[i] * DIM + DF.ca[i]] += DF.va[i] * yi;
+        if (DF.ib[i] >= 0) U[f * KR + DF.ib[i] * DIM + DF.cb[i]] += DF.vb[i] * yi;
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int j = lane + 64 * i;
+    if (j < r.N) {
+      double p[Q];
+      scaled_basis<DIM, ORDER, double>(r.s[i], p);
+      for (int f = 0; f < F; ++f)
+        for (int c = 0; c < DIM; ++c) {
+          double acc = 0.0;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) acc += p[q] * U[f * KR + q * DIM + c];
+          a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = r.w[i] * acc;
+        }
+    }
+  }
+  if (lane == 0) a.status[t] = GMLS_TARGET_OK;
+  __syncthreads();
+}
+
+template <int DIM, int ORDER, int BASIS>
+constexpr int qr_lds_doubles() {
+  constexpr int Q = num_mono(DIM, ORDER);
+  if (BASIS == 0) return 2 * Q * Q + 8 * Q;
+  constexpr int QD = DivFreeTab<DIM, ORDER>::QD;
+  constexpr int KR = DIM * Q;
+  return Q * Q + QD * KR + 8 * QD + 8 * KR + QD;
+}
+
+// Persistent kernel: waves take targets from list[0 .. *count) in turn.
+template <int DIM, int ORDER, int BASIS, int RPL>
+__global__ __launch_bounds__(64) void k_qr(StencilArgs a, const int *list, const int *count, const int *offset,
+                                           int *cursor) {
+  __shared__ double lds[qr_lds_doubles<DIM, ORDER, BASIS>()];
+  const RowKinds rk = row_kinds(DIM, BASIS, a.mask);
+  const int n = readfirstlane_i(*count);
+  const int off = readfirstlane_i(offset ? *offset : 0);
+  for (;;) {
+    int i = 0;
+    if (lane_id() == 0) i = atomicAdd(cursor, 1);
+    i = __builtin_amdgcn_readfirstlane(i);
+    if (i >= n) break;
+    const int t = readfirstlane_i(list[off + i]);
+    if (BASIS == 0)
+      qr_scalar_target<DIM, ORDER, RPL>(a, rk, t, lds);
+    else
+      qr_divfree_target<DIM, ORDER, RPL>(a, rk, t, lds);
+  }
+}
+
+}  // namespace gmls

@@ -1,0 +1,121 @@
+"""GPU neighbour search vs the oracle: bit-exact CSR (rows sorted by
+(squared distance, index)) and support radii."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_helpers import ctx, dev, flush, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_knn(src, tgt, k, eps_mult=1.5):
+    G = require_gpu()
+    same = tgt is src
+    s = dev(src)
+    t = s if same else dev(tgt)
+    rp, col, eps = G.gmls_neighbors(ctx(), s, t, G.SEARCH_KNN, k=k, eps_mult=eps_mult)
+    return host(rp), host(col), host(eps)
+
+
+def gpu_radius(src, tgt, r0, k_min):
+    G = require_gpu()
+    same = tgt is src
+    s = dev(src)
+    t = s if same else dev(tgt)
+    rp, col, eps = G.gmls_neighbors(ctx(), s, t, G.SEARCH_RADIUS, radius=r0, k_min=k_min)
+    return host(rp), host(col), host(eps)
+
+
+def assert_same(g, o, tag):
+    rp, col, eps = g
+    orp, ocol, oeps = o
+    assert np.array_equal(rp, orp), tag
+    if not np.array_equal(col, ocol):
+        bad = np.nonzero(col != ocol)[0][:5]
+        t = np.searchsorted(orp, bad, side="right") - 1
+        raise AssertionError(f"{tag}: col differs at {bad} (targets {t})")
+    np.testing.assert_allclose(eps, oeps, rtol=2e-16 * 4, atol=0, err_msg=tag)
+
+
+@pytest.mark.parametrize("case", ["c1_2d_k12", "2d_k40", "3d_k60", "3d_k170", "1d_k7"])
+def test_knn_matches_oracle(case):
+    if case == "c1_2d_k12":
+        src, k = W.make_points("c1_2d_m2"), 12
+    elif case == "2d_k40":
+        src, k = W.jittered_grid(20000, 2, 1002), 40
+    elif case == "3d_k60":
+        src, k = W.jittered_grid(27000, 3, 1003), 60
+    elif case == "3d_k170":
+        src, k = W.jittered_grid(27000, 3, 1005), 170
+    else:
+        src, k = W.rng(3).uniform(size=(500, 1)), 7
+    flush(f"knn {case} n={len(src)} k={k}")
+    assert_same(gpu_knn(src, src, k), oracle.knn(src, src, k, 1.5), case)
+
+
+def test_knn_exact_grid_ties_and_foreign_targets():
+    n = 24
+    ax = (np.arange(n) + 0.5) / n
+    src = np.stack(np.meshgrid(ax, ax, indexing="ij"), -1).reshape(-1, 2)[:, ::-1].copy()
+    for k in (1, 5, 9, 21, 50):
+        flush(f"grid ties k={k}")
+        assert_same(gpu_knn(src, src, k), oracle.knn(src, src, k, 1.5), f"ties k={k}")
+    tgt = W.rng(8).uniform(-0.5, 1.5, size=(300, 2))
+    flush("foreign targets")
+    assert_same(gpu_knn(src, tgt, 13), oracle.knn(src, tgt, 13, 1.5), "foreign")
+    assert_same(gpu_knn(src, src, n * n), oracle.knn(src, src, n * n, 1.5), "k = n")
+
+
+def test_knn_clustered_cloud():
+    g = W.rng(12)
+    src = np.concatenate([g.normal(0.3, 0.005, size=(3000, 3)), g.uniform(size=(3000, 3))])
+    flush("clustered k=40")
+    assert_same(gpu_knn(src, src, 40), oracle.knn(src, src, 40, 1.5), "clustered")
+
+
+@pytest.mark.parametrize("n", [3000, 20000])
+def test_radius_matches_oracle(n):
+    src = W.density_ramp(n, 1004)
+    r0 = W.radius_for_mean_count(n)
+    flush(f"radius n={n} r0={r0:.4f}")
+    g = gpu_radius(src, src, r0, 30)
+    o = oracle.radius(src, src, r0, 30)
+    assert_same(g, o, f"radius n={n}")
+    counts = np.diff(g[0])
+    assert (counts == 30).any() or n > 10000  # the floor is exercised on the small cloud
+
+
+def test_radius_foreign_targets_and_empty():
+    G = require_gpu()
+    src = W.density_ramp(5000, 77)
+    tgt = W.rng(9).uniform(-0.1, 1.1, size=(400, 3))
+    r0 = W.radius_for_mean_count(5000)
+    flush("radius foreign")
+    assert_same(gpu_radius(src, tgt, r0, 20), oracle.radius(src, tgt, r0, 20), "radius foreign")
+    flush("empty target set")
+    rp, col, eps = G.gmls_neighbors(ctx(), dev(src), dev(np.zeros((0, 3))), G.SEARCH_RADIUS, radius=r0, k_min=5)
+    assert host(rp).tolist() == [0] and col.numel() == 0
+
+
+def test_capacity_error_reports_required_size():
+    G = require_gpu()
+    src = W.density_ramp(4000, 5)
+    s = dev(src)
+    r0 = W.radius_for_mean_count(4000)
+    small = dev(np.zeros(10, np.int32))
+    flush("capacity")
+    rp, col, eps = G.gmls_neighbors(ctx(), s, s, G.SEARCH_RADIUS, radius=r0, k_min=10, col=small)
+    o = oracle.radius(src, src, r0, 10)
+    assert col.numel() == len(o[1])
+    assert_same((host(rp), host(col), host(eps)), o, "capacity retry")
+
+
+def test_bad_arguments_raise():
+    G = require_gpu()
+    s = dev(W.jittered_grid(100, 2, 1))
+    with pytest.raises(G.GmlsError):
+        G.gmls_neighbors(ctx(), s, s, G.SEARCH_KNN, k=101)
+    with pytest.raises(G.GmlsError):
+        G.gmls_neighbors(ctx(), s, s, G.SEARCH_RADIUS, radius=-1.0)

@@ -1,0 +1,133 @@
+"""GPU stencils vs the FP64 oracle on the same neighbour lists.
+
+Gates (per target and functional row, ||a - b|| / ||b||): FP64 path 1e-10,
+mixed path 1e-8.  Sizes span every row-count bin (N up to 256), ragged rows
+from the radius search, and both bases."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from tests.gpu_helpers import ctx, dev, flush, host, require_gpu, row_errors
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-8
+
+CASES = {
+    # name: (points, search, basis, order, mask, p)
+    "c1_2d_m2": (lambda: W.make_points("c1_2d_m2"), ("knn", 12), "scalar", 2, 2 | 4, 4),
+    "2d_m4": (lambda: W.jittered_grid(6000, 2, 1002), ("knn", 40), "scalar", 4, 1 | 2 | 4, 4),
+    "3d_m2_grad": (lambda: W.jittered_grid(8000, 3, 1003), ("knn", 60), "scalar", 2, 2, 4),
+    "3d_m3_radius": (lambda: W.density_ramp(12000, 1004), ("radius", 30), "scalar", 3, 4, 4),
+    "3d_m4_k170": (lambda: W.jittered_grid(8000, 3, 1005), ("knn", 170), "scalar", 4, 2 | 4, 6),
+    "3d_divfree_m2": (lambda: W.jittered_grid(8000, 3, 1003), ("knn", 60), "divfree", 2, 1 | 4 | 8, 4),
+    "2d_divfree_m2": (lambda: W.jittered_grid(3000, 2, 7), ("knn", 20), "divfree", 2, 1 | 4 | 8, 4),
+    "3d_divfree_m4": (lambda: W.jittered_grid(8000, 3, 1005), ("knn", 170), "divfree", 4, 4 | 8, 6),
+}
+
+_cache = {}
+
+
+def case_data(name):
+    if name not in _cache:
+        mk, search, basis, order, mask, p = CASES[name]
+        pts = mk()
+        if search[0] == "knn":
+            rp, col, eps = oracle.knn(pts, pts, search[1], 1.5)
+        else:
+            rp, col, eps = oracle.radius(pts, pts, W.radius_for_mean_count(len(pts)), search[1])
+        w, st, F, C = oracle.stencils(pts, pts, order, basis, mask, p, eps, rp, col)
+        _cache[name] = (pts, rp, col, eps, w, st, F, C)
+    return _cache[name]
+
+
+def run_gpu(name, prec, sub=None):
+    G = require_gpu()
+    pts, rp, col, eps, w, st, F, C = case_data(name)
+    _, _, basis, order, mask, p = CASES[name]
+    b = G.BASIS_SCALAR if basis == "scalar" else G.BASIS_DIVFREE
+    flush(f"stencils {name} prec={prec} n={len(pts)} nnz={len(col)}")
+    s = dev(pts)
+    gw, gst, rep = G.gmls_stencils(ctx(), s, s, order, b, mask, p, dev(eps), dev(rp), dev(col), prec=prec,
+                                   report=True)
+    return host(gw), host(gst), rep
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_matches_oracle(name):
+    G = require_gpu()
+    pts, rp, col, eps, w, st, F, C = case_data(name)
+    gw, gst, rep = run_gpu(name, G.PREC_FP64)
+    assert np.array_equal(gst, st)
+    zero = (F - 1,) if CASES[name][2] == "divfree" and CASES[name][4] & 8 else ()
+    errs = row_errors(gw, w, rp, F, C, zero_rows=zero)
+    flush(f"  fp64 max rel err {errs.max():.3e}  p99 {np.percentile(errs, 99):.3e}")
+    assert errs.max() <= FP64_TOL
+
+
+def test_rank_deficient_targets_flagged():
+    G = require_gpu()
+    pts = W.jittered_grid(500, 2, 9)
+    rp, col, eps = oracle.knn(pts, pts, 5, 1.5)  # N = 5 < Q = 6
+    s = dev(pts)
+    flush("rank deficient N<Q")
+    gw, gst, rep = G.gmls_stencils(ctx(), s, s, 2, G.BASIS_SCALAR, 4, 4, dev(eps), dev(rp), dev(col),
+                                   prec=G.PREC_FP64, report=True)
+    assert (host(gst) == 1).all() and np.isnan(host(gw)).all()
+    assert rep["n_rank_deficient"] == 500
+    flat = W.rng(4).uniform(size=(600, 3))
+    flat[:, 2] = 0.25
+    rp, col, eps = oracle.knn(flat, flat, 30, 1.5)
+    w, st, F, C = oracle.stencils(flat, flat, 2, "scalar", 4, 4, eps, rp, col)
+    s = dev(flat)
+    flush("rank deficient coplanar")
+    gw, gst, _ = G.gmls_stencils(ctx(), s, s, 2, G.BASIS_SCALAR, 4, 4, dev(eps), dev(rp), dev(col),
+                                 prec=G.PREC_FP64)
+    assert np.array_equal(host(gst), st)
+
+
+def test_empty_and_unsupported():
+    G = require_gpu()
+    s = dev(W.jittered_grid(100, 3, 1))
+    e = dev(np.zeros(0))
+    rp = dev(np.zeros(1, np.int64))
+    c = dev(np.zeros(0, np.int32))
+    flush("empty target set")
+    gw, gst, _ = G.gmls_stencils(ctx(), s, s[:0], 2, G.BASIS_SCALAR, 4, 4, e, rp, c)
+    assert gw.numel() == 0
+    with pytest.raises(G.GmlsError):
+        G.gmls_stencils(ctx(), s, s[:0], 2, G.BASIS_SCALAR, 8, 4, e, rp, c)  # divergence on scalar basis
+    with pytest.raises(G.GmlsError):
+        G.gmls_stencils(ctx(), s, s[:0], 2, G.BASIS_DIVFREE, 2, 4, e, rp, c)  # gradient on vector basis
+
+
+def test_apply_matches_numpy():
+    G = require_gpu()
+    pts, rp, col, eps, w, st, F, C = case_data("3d_divfree_m2")
+    field = W.rng(3).standard_normal((len(pts), C))
+    flush("apply")
+    out = host(G.gmls_apply(ctx(), dev(rp), dev(col), dev(w), F, C, dev(field)))
+    ref = np.zeros((len(rp) - 1, F))
+    for t in range(len(rp) - 1):
+        n = rp[t + 1] - rp[t]
+        a = w[F * C * rp[t]: F * C * rp[t + 1]].reshape(F, n, C)
+        ref[t] = np.einsum("fjc,jc->f", a, field[col[rp[t]:rp[t + 1]]])
+    np.testing.assert_allclose(out, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_end_to_end_gpu_search_then_stencils():
+    G = require_gpu()
+    pts = W.density_ramp(20000, 1004)
+    r0 = W.radius_for_mean_count(20000)
+    s = dev(pts)
+    flush("end to end radius + m3")
+    rp, col, eps = G.gmls_neighbors(ctx(), s, s, G.SEARCH_RADIUS, radius=r0, k_min=30)
+    gw, gst, _ = G.gmls_stencils(ctx(), s, s, 3, G.BASIS_SCALAR, 4, 4, eps, rp, col, prec=G.PREC_FP64)
+    orp, ocol, oeps = oracle.radius(pts, pts, r0, 30)
+    assert np.array_equal(host(rp), orp) and np.array_equal(host(col), ocol)
+    w, st, F, C = oracle.stencils(pts, pts, 3, "scalar", 4, 4, oeps, orp, ocol)
+    errs = row_errors(host(gw), w, orp, F, C)
+    flush(f"  e2e max rel err {errs.max():.3e}")
+    assert errs.max() <= FP64_TOL
