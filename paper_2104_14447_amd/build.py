@@ -3,7 +3,9 @@
 Every translation unit is compiled for gfx950 only, with packed FP32
 instructions disabled; the neighbour search additionally forbids
 floating-point contraction so that squared distances are evaluated exactly
-as (dx*dx + dy*dy) + dz*dz.
+as (dx*dx + dy*dy) + dz*dz.  The stencil kernels are compiled once per
+(dimension, order, basis) from the unit sources so that the objects build in
+parallel.
 """
 from __future__ import annotations
 
@@ -18,19 +20,6 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libgmls.so")
 ARCH = os.environ.get("GMLS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = {
-    "search.hip": ["-ffp-contract=off"],
-    "stencil_bins.hip": [],
-    "stencil_fp64.hip": [],
-    "qr_2d_scalar.hip": [],
-    "qr_3d_scalar.hip": [],
-    "qr_2d_divfree.hip": [],
-    "qr_3d_divfree.hip": [],
-    "stencil_mixed.hip": [],
-    "apply.hip": [],
-    "api.cpp": [],
-}
-
 COMMON = [
     "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -38,33 +27,47 @@ COMMON = [
 ]
 
 
+def units():
+    """(object name, source, extra flags), heaviest first."""
+    out = []
+    for unit in ("mixed_unit.hip", "qr_unit.hip"):
+        stem = unit.split("_")[0]
+        for order in (4, 3, 2, 1):
+            for basis in (1, 0):
+                for dim in (3, 2):
+                    defs = [f"-DGMLS_DIM={dim}", f"-DGMLS_ORDER={order}", f"-DGMLS_BASIS={basis}"]
+                    out.append((f"{stem}_d{dim}_o{order}_b{basis}", unit, defs))
+    out += [
+        ("search", "search.hip", ["-ffp-contract=off"]),
+        ("stencil_bins", "stencil_bins.hip", []),
+        ("stencil_fp64", "stencil_fp64.hip", []),
+        ("stencil_mixed", "stencil_mixed.hip", []),
+        ("apply", "apply.hip", []),
+        ("api", "api.cpp", ["-x", "hip"]),
+    ]
+    return out
+
+
 def hipcc() -> str:
-    for cand in ("/opt/rocm/bin/hipcc", "hipcc"):
-        if os.path.exists(cand) or cand == "hipcc":
-            return cand
-    return "hipcc"
+    return "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc"
 
 
-def _compile(name: str, extra: list[str], verbose: bool) -> str:
-    src = os.path.join(CSRC, name)
+def _compile(name: str, src: str, extra: list[str], verbose: bool) -> str:
     obj = os.path.join(BUILD, name + ".o")
-    lang = ["-x", "hip"] if name.endswith(".cpp") else []
-    cmd = [hipcc()] + COMMON + extra + lang + ["-c", src, "-o", obj]
+    cmd = [hipcc()] + COMMON + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {name}:\n{r.stdout}\n{r.stderr}")
-    if r.stderr.strip() and verbose:
-        print(r.stderr, file=sys.stderr)
     return obj
 
 
 def build(verbose: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    jobs = jobs or int(os.environ.get("MAX_JOBS", 0)) or max(1, os.cpu_count() or 2)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = [ex.submit(_compile, n, e, verbose) for n, e in SOURCES.items()]
+        futs = [ex.submit(_compile, n, s, e, verbose) for n, s, e in units()]
         objs = [f.result() for f in futs]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs

@@ -237,6 +237,7 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
   a.F = F;
   a.p = weight_p;
   a.n_tgt = n;
+  a.ok_status = GMLS_TARGET_OK;
 
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[0], s));
   GMLS_HIP(launch_binning(row_ptr, n, Q, C, meta, list, s));
@@ -259,12 +260,15 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
       const int nb = std::min(hm.count[b], cus * 16);
       GMLS_HIP(launch_qr_bin(dim, order, basis, b, a, list, meta, nb, s));
     } else {
-      const int nb = std::min((hm.count[b] + 3) / 4, cus * 16);
-      GMLS_HIP(launch_mixed_bin(dim, order, basis, b, a, list, meta, fb, stats, ctx->opt, nb, s));
+      GMLS_HIP(launch_mixed_bin(dim, order, basis, b, a, list, meta, fb, stats, ctx->opt, hm.count[b], cus, s));
     }
   }
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
-  if (prec == GMLS_PREC_MIXED) GMLS_HIP(launch_qr_fallback(dim, order, basis, a, fb, meta, 4, cus * 8, s));
+  if (prec == GMLS_PREC_MIXED) {
+    StencilArgs af = a;
+    af.ok_status = -1;  // keep the fallback/not-converged status set by the mixed kernel
+    GMLS_HIP(launch_qr_fallback(dim, order, basis, af, fb, meta, 4, cus * 8, s));
+  }
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[3], s));
   if (!report) return GMLS_OK;
 

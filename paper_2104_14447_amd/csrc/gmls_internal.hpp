@@ -112,6 +112,7 @@ struct StencilArgs {
   int F;            // functional rows of this basis/mask
   int p;            // kernel power
   int n_tgt;
+  int ok_status;    // status written on success (-1: leave the status as it is)
 };
 
 // Per-bin stencil launches; `bin` selects the rows-per-lane instantiation.
@@ -120,7 +121,7 @@ hipError_t launch_qr_bin(int dim, int order, int basis, int bin, const StencilAr
 hipError_t launch_qr_fallback(int dim, int order, int basis, const StencilArgs &a, const int *list,
                               BinMeta *meta, int max_bin, int n_blocks, hipStream_t s);
 hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,
-                            BinMeta *meta, int *fb_list, Stats *stats, const Options &opt, int n_blocks,
+                            BinMeta *meta, int *fb_list, Stats *stats, const Options &opt, int count, int cus,
                             hipStream_t s);
 bool qr_supported(int dim, int order, int basis);
 bool mixed_supported(int dim, int order, int basis);

@@ -1,0 +1,29 @@
+// qr_unit.hip -- one instantiation of the FP64 QR stencil kernels.
+// Compiled once per (GMLS_DIM, GMLS_ORDER, GMLS_BASIS) by the build, each
+// object defining launch_qr_d<DIM>_o<ORDER>_b<BASIS>.
+#include "stencil_fp64.hpp"
+
+#if !defined(GMLS_DIM) || !defined(GMLS_ORDER) || !defined(GMLS_BASIS)
+#error "compile with -DGMLS_DIM=.. -DGMLS_ORDER=.. -DGMLS_BASIS=.."
+#endif
+
+#define GMLS_CAT2(a, b, c, d, e, f) a##b##c##d##e##f
+#define GMLS_CAT(a, b, c, d, e, f) GMLS_CAT2(a, b, c, d, e, f)
+#define GMLS_FN GMLS_CAT(launch_qr_d, GMLS_DIM, _o, GMLS_ORDER, _b, GMLS_BASIS)
+
+namespace gmls {
+
+// one wavefront per target; rows per lane = bin (rows <= 64 * bin)
+hipError_t GMLS_FN(int rpl, const StencilArgs &a, const int *list, const int *count, const int *offset, int *cursor,
+                   int n_blocks, hipStream_t s) {
+  constexpr int D = GMLS_DIM, O = GMLS_ORDER, B = GMLS_BASIS;
+  switch (rpl) {
+    case 1: k_qr<D, O, B, 1><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
+    case 2: k_qr<D, O, B, 2><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
+    case 3: k_qr<D, O, B, 3><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
+    default: k_qr<D, O, B, 4><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gmls

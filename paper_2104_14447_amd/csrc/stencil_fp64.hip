@@ -1,29 +1,55 @@
-// stencil_fp64.hip -- dispatch of the FP64 QR stencil kernels (instantiated
-// per dimension and basis in qr_*.hip).
+// stencil_fp64.hip -- dispatch of the FP64 QR stencil kernels.  The kernels
+// are instantiated per (dim, order, basis) from qr_unit.hip.
 #include "gmls_internal.hpp"
 
 namespace gmls {
 
-hipError_t launch_qr_2d_scalar(int, int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+hipError_t launch_qr_d2_o1_b0(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
                                hipStream_t);
-hipError_t launch_qr_3d_scalar(int, int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+hipError_t launch_qr_d2_o1_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
                                hipStream_t);
-hipError_t launch_qr_2d_divfree(int, int, const StencilArgs &, const int *, const int *, const int *, int *, int,
-                                hipStream_t);
-hipError_t launch_qr_3d_divfree(int, int, const StencilArgs &, const int *, const int *, const int *, int *, int,
-                                hipStream_t);
+hipError_t launch_qr_d2_o2_b0(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d2_o2_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d2_o3_b0(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d2_o3_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d2_o4_b0(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d2_o4_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o1_b0(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o1_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o2_b0(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o2_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o3_b0(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o3_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o4_b0(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o4_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
 
-static hipError_t dispatch_qr(int dim, int order, int basis, int rpl, const StencilArgs &a, const int *list,
-                              const int *count, const int *offset, int *cursor, int n_blocks, hipStream_t s) {
-  if (dim == 2 && basis == 0) return launch_qr_2d_scalar(order, rpl, a, list, count, offset, cursor, n_blocks, s);
-  if (dim == 3 && basis == 0) return launch_qr_3d_scalar(order, rpl, a, list, count, offset, cursor, n_blocks, s);
-  if (dim == 2 && basis == 1) return launch_qr_2d_divfree(order, rpl, a, list, count, offset, cursor, n_blocks, s);
-  if (dim == 3 && basis == 1) return launch_qr_3d_divfree(order, rpl, a, list, count, offset, cursor, n_blocks, s);
-  return hipErrorInvalidValue;
-}
+using QrFn = hipError_t (*)(int, const StencilArgs &, const int *, const int *, const int *, int *, int, hipStream_t);
+static const QrFn kQr[2][4][2] = {
+    {{launch_qr_d2_o1_b0, launch_qr_d2_o1_b1}, {launch_qr_d2_o2_b0, launch_qr_d2_o2_b1}, {launch_qr_d2_o3_b0, launch_qr_d2_o3_b1}, {launch_qr_d2_o4_b0, launch_qr_d2_o4_b1}},
+    {{launch_qr_d3_o1_b0, launch_qr_d3_o1_b1}, {launch_qr_d3_o2_b0, launch_qr_d3_o2_b1}, {launch_qr_d3_o3_b0, launch_qr_d3_o3_b1}, {launch_qr_d3_o4_b0, launch_qr_d3_o4_b1}}};
 
 bool qr_supported(int dim, int order, int basis) {
   return (dim == 2 || dim == 3) && order >= 1 && order <= 4 && (basis == 0 || basis == 1);
+}
+
+static hipError_t dispatch_qr(int dim, int order, int basis, int rpl, const StencilArgs &a, const int *list,
+                              const int *count, const int *offset, int *cursor, int n_blocks, hipStream_t s) {
+  if (!qr_supported(dim, order, basis)) return hipErrorInvalidValue;
+  return kQr[dim - 2][order - 1][basis](rpl, a, list, count, offset, cursor, n_blocks, s);
 }
 
 hipError_t launch_qr_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,

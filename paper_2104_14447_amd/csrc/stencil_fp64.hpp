@@ -200,7 +200,7 @@ __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t
       }
     }
   }
-  if (lane == 0) a.status[t] = GMLS_TARGET_OK;
+  if (lane == 0 && a.ok_status >= 0) a.status[t] = (uint8_t)a.ok_status;
   __syncthreads();
 }
 
@@ -375,7 +375,7 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
         }
     }
   }
-  if (lane == 0) a.status[t] = GMLS_TARGET_OK;
+  if (lane == 0 && a.ok_status >= 0) a.status[t] = (uint8_t)a.ok_status;
   __syncthreads();
 }
 

@@ -131,3 +131,54 @@ def test_end_to_end_gpu_search_then_stencils():
     errs = row_errors(host(gw), w, orp, F, C)
     flush(f"  e2e max rel err {errs.max():.3e}")
     assert errs.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_matches_oracle(name):
+    G = require_gpu()
+    pts, rp, col, eps, w, st, F, C = case_data(name)
+    gw, gst, rep = run_gpu(name, G.PREC_MIXED)
+    # fallback targets keep a fallback status; everything else is OK
+    assert np.array_equal(gst == 1, st == 1)
+    zero = (F - 1,) if CASES[name][2] == "divfree" and CASES[name][4] & 8 else ()
+    errs = row_errors(gw, w, rp, F, C, zero_rows=zero)
+    flush(f"  mixed max rel err {errs.max():.3e}  p99 {np.percentile(errs, 99):.3e}  "
+          f"fallback {rep['n_fallback']} not-conv {rep['n_not_converged']} sweeps {rep['sweep_hist'][:6]} "
+          f"cond_max {rep['cond_max']:.2e}")
+    assert errs.max() <= MIXED_TOL
+
+
+def test_mixed_forced_fallback_is_fp64_exact():
+    G = require_gpu()
+    c = ctx()
+    c.set_option(G.OPT_FORCE_FALLBACK, 1)
+    try:
+        pts, rp, col, eps, w, st, F, C = case_data("3d_m3_radius")
+        gw, gst, rep = run_gpu("3d_m3_radius", G.PREC_MIXED)
+    finally:
+        c.set_option(G.OPT_FORCE_FALLBACK, 0)
+    assert (gst == 2).all() and rep["n_fallback"] == len(st)
+    errs = row_errors(gw, w, rp, F, C)
+    flush(f"  forced fallback max rel err {errs.max():.3e}")
+    assert errs.max() <= FP64_TOL
+
+
+def test_mixed_near_coplanar_triggers_fallback():
+    G = require_gpu()
+    g = W.rng(31)
+    n = 4000
+    pts = W.jittered_grid(n, 3, 13)
+    pts[:, 2] = 0.5 + (pts[:, 2] - 0.5) * 1e-4  # squashed cloud: badly conditioned z moments
+    rp, col, eps = oracle.knn(pts, pts, 40, 1.5)
+    w, st, F, C = oracle.stencils(pts, pts, 2, "scalar", 4, 4, eps, rp, col)
+    s = dev(pts)
+    flush("near-coplanar mixed")
+    gw, gst, rep = G.gmls_stencils(ctx(), s, s, 2, G.BASIS_SCALAR, 4, 4, dev(eps), dev(rp), dev(col),
+                                   prec=G.PREC_MIXED, report=True)
+    gw, gst = host(gw), host(gst)
+    flush(f"  fallback {rep['n_fallback']} not-conv {rep['n_not_converged']} cond_max {rep['cond_max']:.2e}")
+    assert rep["n_fallback"] + rep["n_not_converged"] > 0
+    ok = st == 0
+    assert np.array_equal(gst == 1, st == 1)
+    errs = row_errors(gw, w, rp, F, C)
+    assert errs[ok].max() <= MIXED_TOL
