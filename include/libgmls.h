@@ -103,7 +103,7 @@ typedef struct {
   int64_t n_fallback;      /* mixed: targets recomputed by FP64 QR (condition or breakdown) */
   int64_t n_not_converged; /* mixed: refinement budget exhausted (also recomputed by QR)    */
   int32_t sweep_hist[16];  /* mixed: targets by number of refinement sweeps used            */
-  double cond_max;         /* mixed: largest condition estimate of the equilibrated Gram    */
+  double cond_max;         /* mixed: largest 1-norm condition number of the equilibrated Gram */
   double t_bin_ms;         /* GPU time of the binning kernels                                */
   double t_stencil_ms;     /* GPU time of the stencil kernels (all bins)                     */
   double t_fallback_ms;    /* GPU time of the FP64 fallback kernel                           */
@@ -113,7 +113,8 @@ typedef struct {
 enum {
   GMLS_OPT_COND_THRESHOLD = 0, /* fallback when the Gram condition estimate exceeds it (1e6) */
   GMLS_OPT_MAX_SWEEPS = 1,     /* refinement sweeps before giving up (8)                      */
-  GMLS_OPT_REFINE_TOL = 2,     /* stop when |correction| <= tol * |y| (1e-12)                 */
+  GMLS_OPT_REFINE_TOL = 2,     /* stop when the predicted relative error after a correction,
+                                  rho*|dy|/|y| with rho = 2 n cond 2^-24, is <= tol (1e-11)   */
   GMLS_OPT_FORCE_FALLBACK = 3  /* nonzero: every mixed target takes the FP64 fallback (0)      */
 };
 

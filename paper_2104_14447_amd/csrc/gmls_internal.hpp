@@ -38,7 +38,7 @@ enum Slot {
 struct Options {
   double cond_threshold = 1e6;
   int max_sweeps = 8;
-  double refine_tol = 1e-12;
+  double refine_tol = 1e-11;
   int force_fallback = 0;
 };
 

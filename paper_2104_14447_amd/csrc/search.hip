@@ -15,7 +15,10 @@
 //    until the k-th distance is provably smaller than the distance to every
 //    unscanned cell.
 //  - radius: every source with d^2 < r^2 (count pass, scan, fill pass); a
-//    target with fewer than k_min falls back to its k_min nearest.
+//    target with fewer than k_min falls back to its k_min nearest.  Rows of
+//    up to 256 entries are compacted into a small LDS buffer and sorted in
+//    registers by a wave-wide bitonic network; longer rows take a second
+//    kernel with a large LDS buffer.
 // Every output row is sorted by (squared distance, index).
 #include <float.h>
 #include <limits.h>
@@ -316,7 +319,7 @@ __device__ void lds_sort(double *d2, int *idx, int n) {
 
 // The k nearest sources of x, sorted, in d2[0..k) / idx[0..k); returns the
 // count found (k unless there are fewer sources).  r_start: first block radius.
-template <int DIM>
+template <int DIM, int CAP>
 __device__ int knn_select(const GridParams &g, const SPoint *pts, const int *cell_start, const double *x, int k,
                           int r_start, double *d2, int *idx) {
   const int lane = lane_id();
@@ -350,7 +353,7 @@ __device__ int knn_select(const GridParams &g, const SPoint *pts, const int *cel
         const int beg = readfirstlane_i(cell_start[row + lo[0]]);
         const int end = readfirstlane_i(cell_start[row + hi[0] + 1]);
         for (int b = beg; b < end; b += 64) {
-          if (fill + 64 > kCap) {
+          if (fill + 64 > CAP) {
             lds_sort(d2, idx, fill);
             fill = fill < k ? fill : k;
             if (fill == k) {
@@ -400,7 +403,7 @@ __global__ __launch_bounds__(64) void k_knn(const GridParams *gp, const SPoint *
   const int t = readfirstlane_i(order[w]);
   double x[3] = {0, 0, 0};
   for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
-  const int got = knn_select<DIM>(g, pts, cell_start, x, k, 2, d2, idx);
+  const int got = knn_select<DIM, kCap>(g, pts, cell_start, x, k, 2, d2, idx);
   for (int q = lane_id(); q < k; q += 64) col[(int64_t)t * k + q] = q < got ? idx[q] : -1;
   if (lane_id() == 0) eps[t] = eps_mult * sqrt(d2[got - 1]);
 }
@@ -451,13 +454,86 @@ __global__ __launch_bounds__(64) void k_radius_count(const GridParams *gp, const
   if (lane == 0) counts[t] = count;
 }
 
+// Ascending bitonic sort of 64*EPL (d2, idx) keys held in registers, element
+// e = lane*EPL + r in slot r; pairs further apart than EPL are exchanged with
+// the partner lane through shuffles.
+template <int EPL>
+__device__ __forceinline__ void wave_sort(double (&kd)[EPL], int (&ki)[EPL], int lane) {
+  constexpr int E = 64 * EPL;
+#pragma unroll
+  for (int size = 2; size <= E; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= EPL) {
+        const int lmask = stride / EPL;
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          const int e = lane * EPL + r;
+          const double od = __shfl_xor(kd[r], lmask, 64);
+          const int oi = __shfl_xor(ki[r], lmask, 64);
+          const bool lower = (e & stride) == 0;
+          const bool up = (e & size) == 0;
+          const bool other_less = key_less(od, oi, kd[r], ki[r]);
+          // lower element of an ascending pair keeps the smaller key, etc.
+          const bool take = (lower == up) ? other_less : !other_less;
+          if (take) {
+            kd[r] = od;
+            ki[r] = oi;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          if (r & stride) continue;
+          const int e = lane * EPL + r;
+          const bool up = (e & size) == 0;
+          const int r2 = r + stride;
+          const bool sw = up ? key_less(kd[r2], ki[r2], kd[r], ki[r]) : key_less(kd[r], ki[r], kd[r2], ki[r2]);
+          if (sw) {
+            const double td = kd[r];
+            const int ti = ki[r];
+            kd[r] = kd[r2];
+            ki[r] = ki[r2];
+            kd[r2] = td;
+            ki[r2] = ti;
+          }
+        }
+      }
+    }
+  }
+}
+
+// load n <= 64*EPL candidates from LDS, sort them in registers, write the row
+template <int EPL>
+__device__ __forceinline__ void sort_and_store(const double *d2, const int *idx, int n, int32_t *out, int lane) {
+  double kd[EPL];
+  int ki[EPL];
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    const int e = lane * EPL + r;
+    kd[r] = e < n ? d2[e] : DBL_MAX;
+    ki[r] = e < n ? idx[e] : INT_MAX;
+  }
+  wave_sort<EPL>(kd, ki, lane);
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    const int e = lane * EPL + r;
+    if (e < n) out[e] = ki[r];
+  }
+}
+
+constexpr int kSmallCap = 256;  // candidates per target in the common-case kernel
+
+// Common case: at most kSmallCap sources inside the radius and a floor that
+// fits the small buffer.  Other targets are appended to `overflow` for
+// k_radius_fill_big.
 template <int DIM>
 __global__ __launch_bounds__(64) void k_radius_fill(const GridParams *gp, const SPoint *pts, const int *cell_start,
                                                     const double *targets, const int *order, int64_t n_tgt,
                                                     double r0, int k_min, const int64_t *row_ptr, int32_t *col,
-                                                    double *eps) {
-  __shared__ double d2[kCap];
-  __shared__ int idx[kCap];
+                                                    double *eps, int *overflow, int *n_overflow) {
+  __shared__ double d2[kSmallCap];
+  __shared__ int idx[kSmallCap];
   const int64_t w = blockIdx.x;
   if (w >= n_tgt) return;
   const GridParams g = *gp;
@@ -492,25 +568,98 @@ __global__ __launch_bounds__(64) void k_radius_fill(const GridParams *gp, const 
         }
         uint64_t m;
         const int pre = ballot_prefix(ok, &m);
-        if (ok && fill + pre < kCap) {
+        if (ok && fill + pre < kSmallCap) {
           d2[fill + pre] = dd;
           idx[fill + pre] = id;
         }
         fill += __popcll(m);
       }
     }
+  const bool big = fill > kSmallCap || (fill < k_min && k_min + 65 > kSmallCap);
+  if (big) {
+    if (lane == 0) overflow[atomicAdd(n_overflow, 1)] = t;
+    return;
+  }
   const int64_t base = row_ptr[t];
+  __syncthreads();
   if (fill >= k_min) {
-    if (fill > kCap) fill = kCap;  // flagged by the count pass; the call fails
-    __syncthreads();
-    lds_sort(d2, idx, fill);
-    for (int q = lane; q < fill; q += 64) col[base + q] = idx[q];
+    if (fill <= 64)
+      sort_and_store<1>(d2, idx, fill, col + base, lane);
+    else if (fill <= 128)
+      sort_and_store<2>(d2, idx, fill, col + base, lane);
+    else
+      sort_and_store<4>(d2, idx, fill, col + base, lane);
     if (lane == 0) eps[t] = r0;
   } else {
-    __syncthreads();
-    const int got = knn_select<DIM>(g, pts, cell_start, x, k_min + 1, 1, d2, idx);
+    const int got = knn_select<DIM, kSmallCap>(g, pts, cell_start, x, k_min + 1, 1, d2, idx);
     for (int q = lane; q < k_min; q += 64) col[base + q] = idx[q];
     if (lane == 0) eps[t] = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
+  }
+}
+
+// Targets with more candidates than the small buffer (or a large floor):
+// LDS buffer of kCap entries and a bitonic sort in LDS.
+template <int DIM>
+__global__ __launch_bounds__(64) void k_radius_fill_big(const GridParams *gp, const SPoint *pts,
+                                                        const int *cell_start, const double *targets, double r0,
+                                                        int k_min, const int64_t *row_ptr, int32_t *col, double *eps,
+                                                        const int *overflow, const int *n_overflow) {
+  __shared__ double d2[kCap];
+  __shared__ int idx[kCap];
+  const GridParams g = *gp;
+  const int lane = lane_id();
+  const int n = readfirstlane_i(*n_overflow);
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int t = readfirstlane_i(overflow[w]);
+    double x[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
+    const double r2 = r0 * r0;
+    const int R = radius_blocks(g, r0);
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+      const int c = cell_coord(g, x[d], d);
+      lo[d] = max(c - R, 0);
+      hi[d] = min(c + R, g.nc[d] - 1);
+    }
+    int fill = 0;
+    for (int cz = lo[2]; cz <= hi[2]; ++cz)
+      for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+        const int row = g.nc[0] * (cy + g.nc[1] * cz);
+        const int beg = readfirstlane_i(cell_start[row + lo[0]]);
+        const int end = readfirstlane_i(cell_start[row + hi[0] + 1]);
+        for (int b = beg; b < end; b += 64) {
+          const int p = b + lane;
+          bool ok = false;
+          double dd = 0.0;
+          int id = 0;
+          if (p < end) {
+            const SPoint sp = pts[p];
+            dd = dist2_exact<DIM>(sp, x);
+            id = sp.idx;
+            ok = dd < r2;
+          }
+          uint64_t m;
+          const int pre = ballot_prefix(ok, &m);
+          if (ok && fill + pre < kCap) {
+            d2[fill + pre] = dd;
+            idx[fill + pre] = id;
+          }
+          fill += __popcll(m);
+        }
+      }
+    const int64_t base = row_ptr[t];
+    __syncthreads();
+    if (fill >= k_min) {
+      if (fill > kCap) fill = kCap;  // flagged by the count pass; the call fails
+      lds_sort(d2, idx, fill);
+      for (int q = lane; q < fill; q += 64) col[base + q] = idx[q];
+      if (lane == 0) eps[t] = r0;
+    } else {
+      const int got = knn_select<DIM, kCap>(g, pts, cell_start, x, k_min + 1, 1, d2, idx);
+      for (int q = lane; q < k_min; q += 64) col[base + q] = idx[q];
+      if (lane == 0) eps[t] = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
+    }
+    __syncthreads();
   }
 }
 
@@ -609,9 +758,13 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
   if (nnz > col_capacity)
     return gmls_set_error(ctx, GMLS_ERR_CAPACITY,
                           "col_capacity " + std::to_string(col_capacity) + " < required " + std::to_string(nnz));
-  if (n_tgt > 0)
+  if (n_tgt > 0) {
+    GMLS_HIP(hipMemsetAsync(flags + 1, 0, sizeof(int), s));
     k_radius_fill<DIM><<<(unsigned)n_tgt, 64, 0, s>>>(gp, sorted, start, targets, order, n_tgt, spec.radius,
-                                                      spec.k_min, row_ptr, col, eps);
+                                                      spec.k_min, row_ptr, col, eps, (int *)counts, flags + 1);
+    k_radius_fill_big<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, spec.radius, spec.k_min, row_ptr, col,
+                                               eps, (int *)counts, flags + 1);
+  }
   GMLS_HIP(hipGetLastError());
   GMLS_HIP(hipStreamSynchronize(s));
   return GMLS_OK;

@@ -16,13 +16,17 @@
 //  3. Jacobi equilibration A~ = D A D, D = diag(A)^-1/2, FP32 Cholesky
 //     (Crout order, rows of L spread over the group, L in LDS); a pivot that
 //     is not positive sends the target to the FP64 QR fallback;
-//  4. 1-norm condition estimate of A~ (Hager's estimator, Higham's form); above
-//     the threshold the target goes to the fallback;
+//  4. explicit FP32 inverse A~^-1 = L^-T L^-1 (columns of L^-1 in parallel),
+//     so that every solve below is one parallel matrix-vector product, and
+//     the exact 1-norm condition number ||A~||_1 ||A~^-1||_1; above the
+//     threshold the target goes to the fallback;
 //  5. y0 = D A~^-1 D lambda in FP32;
 //  6. refinement (FP64 residual, FP32 correction):
 //        r = lambda - P^T W (P y)  evaluated over the rows in FP64,
 //        y += D A~^-1 D r
-//     until |dy| <= tol |y|, at most max_sweeps times (else fallback);
+//     until the predicted remaining error rho*|dy| <= tol*|y|, with
+//     rho = 2 n cond u_32 the contraction factor of the FP32 inverse, at most
+//     max_sweeps times (else fallback);
 //  7. weights alpha_j = w_j p(s_j) . y accumulated in FP64.
 #pragma once
 
@@ -106,7 +110,9 @@ struct MixedLDS {
   double u[Cf::FU][Cf::NV];        // T y (vector basis)
   double pw[Cf::NV];               // reduced P^T W P y of one functional
   float mu[Cf::NM];
-  float A[Cf::QA][Cf::LDM];        // equilibrated system; L overwrites it (lower part)
+  float A[Cf::QA][Cf::LDM];        // equilibrated system, then L, then its inverse
+  float B[Cf::QA][Cf::LDM];        // L^-1 (lower part)
+  float bv[Cf::QA];                // right-hand side of the current solve
   float dsc[Cf::QA];               // D
 };
 
@@ -136,34 +142,6 @@ __device__ __forceinline__ double gmaxd(double v) {
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, G));
   return v;
-}
-
-// Solve L L^T x = b for the group's factor (L lower, in A).  b is spread
-// over the group: lane lg holds b_i for i = lg + G*q in slot q.
-template <int QA, int LDM, int G, int RS>
-__device__ __forceinline__ void chol_solve(const float (*A)[LDM], float (&b)[RS], int lg) {
-  // forward: L z = b
-#pragma unroll
-  for (int k = 0; k < QA; ++k) {
-    const float zk = __shfl(b[k / G], k % G, G) / A[k][k];
-    if (lg == k % G) b[k / G] = zk;
-#pragma unroll
-    for (int q = 0; q < RS; ++q) {
-      const int i = lg + G * q;
-      if (i > k && i < QA) b[q] -= A[i][k] * zk;
-    }
-  }
-  // backward: L^T x = z
-#pragma unroll
-  for (int k = QA - 1; k >= 0; --k) {
-    const float xk = __shfl(b[k / G], k % G, G) / A[k][k];
-    if (lg == k % G) b[k / G] = xk;
-#pragma unroll
-    for (int q = 0; q < RS; ++q) {
-      const int i = lg + G * q;
-      if (i < k) b[q] -= A[k][i] * xk;
-    }
-  }
 }
 
 // u_f = T y_f for every functional row (vector basis); lane 0 of the group
@@ -338,68 +316,52 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
     __syncthreads();
   }
 
-  // ---- 4. condition estimate of A~ (1-norm, Hager) ----
-  float est = 0.f;
-  {
-    float b[RS];
-#pragma unroll
-    for (int q = 0; q < RS; ++q) b[q] = (lg + G * q < QA) ? 1.0f / QA : 0.f;
-    chol_solve<QA, Cf::LDM, G, RS>(S.A, b, lg);
-    float n1 = 0.f;
-#pragma unroll
-    for (int q = 0; q < RS; ++q) n1 += fabsf(b[q]);
-    est = gsum<G>(n1);
-    // xi = sign(y); z = A~^-1 xi; restart from e_j at j = argmax |z|
-#pragma unroll
-    for (int q = 0; q < RS; ++q) b[q] = (lg + G * q < QA) ? (b[q] >= 0.f ? 1.f : -1.f) : 0.f;
-    chol_solve<QA, Cf::LDM, G, RS>(S.A, b, lg);
-    float zmax = 0.f;
-    int jmax = 0;
-#pragma unroll
-    for (int q = 0; q < RS; ++q) {
-      const int i = lg + G * q;
-      if (i < QA && fabsf(b[q]) > zmax) {
-        zmax = fabsf(b[q]);
-        jmax = i;
-      }
-    }
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
-      const float oz = __shfl_xor(zmax, off, G);
-      const int oj = __shfl_xor(jmax, off, G);
-      if (oz > zmax || (oz == zmax && oj < jmax)) {
-        zmax = oz;
-        jmax = oj;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < RS; ++q) b[q] = (lg + G * q == jmax) ? 1.f : 0.f;
-    chol_solve<QA, Cf::LDM, G, RS>(S.A, b, lg);
-    float n2 = 0.f;
-#pragma unroll
-    for (int q = 0; q < RS; ++q) n2 += fabsf(b[q]);
-    est = fmaxf(est, gsum<G>(n2));
-  }
-  const float cond = anorm * est;
-  if (!(cond <= opt.cond_threshold)) ok = false;
-  if (opt.force_fallback) ok = false;
-
-  // ---- 5. y0 in FP32 ----
-  for (int f = 0; f < F; ++f) {
-    float b[RS];
-#pragma unroll
-    for (int q = 0; q < RS; ++q) {
-      const int i = lg + G * q;
-      b[q] = i < QA ? (float)(sys_lambda<DIM, ORDER, BASIS>(rk.kind[f], rk.comp[f], i, ie)) * S.dsc[i] : 0.f;
-    }
-    chol_solve<QA, Cf::LDM, G, RS>(S.A, b, lg);
-#pragma unroll
-    for (int q = 0; q < RS; ++q) {
-      const int i = lg + G * q;
-      if (i < QA) S.y[f][i] = (double)(b[q] * S.dsc[i]);
+  // ---- 4. explicit inverse A~^-1 = L^-T L^-1: columns of L^-1 in parallel
+  // (lane j solves L x = e_j), then the symmetric product; every later solve
+  // is one parallel matrix-vector product ----
+  for (int j = lg; j < QA; j += G) {
+    S.B[j][j] = 1.0f / S.A[j][j];
+    for (int i = j + 1; i < QA; ++i) {
+      float v = 0.f;
+      for (int k = j; k < i; ++k) v -= S.A[i][k] * S.B[k][j];
+      S.B[i][j] = v / S.A[i][i];
     }
   }
   __syncthreads();
+  for (int el = lg; el < QA * QA; el += G) {
+    const int i = el / QA, k = el - (el / QA) * QA;
+    if (k > i) continue;
+    float v = 0.f;
+    for (int m = i; m < QA; ++m) v += S.B[m][i] * S.B[m][k];
+    S.A[i][k] = v;
+    S.A[k][i] = v;
+  }
+  __syncthreads();
+  // exact 1-norm condition number of the equilibrated system
+  float inorm = 0.f;
+  for (int k = lg; k < QA; k += G) {
+    float sum = 0.f;
+    for (int i = 0; i < QA; ++i) sum += fabsf(S.A[i][k]);
+    inorm = fmaxf(inorm, sum);
+  }
+  const float cond = anorm * gmaxf<G>(inorm);
+  if (!(cond <= opt.cond_threshold)) ok = false;
+  if (opt.force_fallback) ok = false;
+  // refinement contracts errors by about rho per sweep (FP32 inverse)
+  const double rho = fmin(0.5, 2.0 * QA * (double)cond * 5.960464477539063e-08);
+
+  // ---- 5. y0 = D A~^-1 D lambda ----
+  for (int f = 0; f < F; ++f) {
+    for (int i = lg; i < QA; i += G)
+      S.bv[i] = (float)sys_lambda<DIM, ORDER, BASIS>(rk.kind[f], rk.comp[f], i, ie) * S.dsc[i];
+    __syncthreads();
+    for (int i = lg; i < QA; i += G) {
+      float v = 0.f;
+      for (int k = 0; k < QA; ++k) v += S.A[i][k] * S.bv[k];
+      S.y[f][i] = (double)(v * S.dsc[i]);
+    }
+    __syncthreads();
+  }
 
   // ---- 6. refinement: FP64 residual over the rows, FP32 correction ----
   int sweeps = 0;
@@ -453,31 +415,24 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
       }
       __syncthreads();
       // residual r = lambda - A y in system coordinates, scaled by D
-      float b[RS];
-#pragma unroll
-      for (int q = 0; q < RS; ++q) {
-        const int i = lg + G * q;
-        double ri = 0.0;
-        if (i < QA) {
-          double ay;
-          if (BASIS == 0) {
-            ay = S.pw[i];
-          } else {
-            const DivFreeTab<DIM, ORDER> &T = kDivFree<DIM, ORDER>;
-            ay = T.va[i] * S.pw[T.ia[i] * DIM + T.ca[i]];
-            if (T.ib[i] >= 0) ay += T.vb[i] * S.pw[T.ib[i] * DIM + T.cb[i]];
-          }
-          ri = sys_lambda<DIM, ORDER, BASIS>(rk.kind[f], rk.comp[f], i, ie) - ay;
+      for (int i = lg; i < QA; i += G) {
+        double ay;
+        if constexpr (BASIS == 0) {
+          ay = S.pw[i];
+        } else {
+          const DivFreeTab<DIM, ORDER> &T = kDivFree<DIM, ORDER>;
+          ay = T.va[i] * S.pw[T.ia[i] * DIM + T.ca[i]];
+          if (T.ib[i] >= 0) ay += T.vb[i] * S.pw[T.ib[i] * DIM + T.cb[i]];
         }
-        b[q] = i < QA ? (float)(ri * (double)S.dsc[i]) : 0.f;
+        const double ri = sys_lambda<DIM, ORDER, BASIS>(rk.kind[f], rk.comp[f], i, ie) - ay;
+        S.bv[i] = (float)(ri * (double)S.dsc[i]);
       }
-      chol_solve<QA, Cf::LDM, G, RS>(S.A, b, lg);
       __syncthreads();
-#pragma unroll
-      for (int q = 0; q < RS; ++q) {
-        const int i = lg + G * q;
-        if (i < QA && active) {
-          const double dy = (double)b[q] * (double)S.dsc[i];
+      for (int i = lg; i < QA; i += G) {
+        float v = 0.f;
+        for (int k = 0; k < QA; ++k) v += S.A[i][k] * S.bv[k];
+        if (active) {
+          const double dy = (double)v * (double)S.dsc[i];
           const double yn = S.y[f][i] + dy;
           S.y[f][i] = yn;
           dmax = fmax(dmax, fabs(dy));
@@ -490,7 +445,8 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
     ymax = gmaxd<G>(ymax);
     if (active) {
       sweeps = it + 1;
-      if (dmax <= opt.refine_tol * ymax) conv = true;
+      // predicted error after this correction: rho * |dy|
+      if (rho * dmax <= opt.refine_tol * ymax) conv = true;
     }
   }
   const bool not_conv = ok && !conv;
