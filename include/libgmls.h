@@ -115,7 +115,11 @@ enum {
   GMLS_OPT_MAX_SWEEPS = 1,     /* refinement sweeps before giving up (8)                      */
   GMLS_OPT_REFINE_TOL = 2,     /* stop when the predicted relative error after a correction,
                                   rho*|dy|/|y| with rho = 2 n cond 2^-24, is <= tol (1e-11)   */
-  GMLS_OPT_FORCE_FALLBACK = 3  /* nonzero: every mixed target takes the FP64 fallback (0)      */
+  GMLS_OPT_FORCE_FALLBACK = 3, /* nonzero: every mixed target takes the FP64 fallback (0)      */
+  GMLS_OPT_MIXED_RESIDUAL = 4  /* refinement residual of the mixed path: 0 = FP64 weighted-moment
+                                  Gram, one pass over the rows (default; 3D order <= 3 and 2D
+                                  order <= 4, otherwise 1); 1 = FP64 residual recomputed over the
+                                  rows each sweep (corrected semi-normal equations)            */
 };
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`

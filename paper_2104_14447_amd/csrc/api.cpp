@@ -141,6 +141,10 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
     case GMLS_OPT_FORCE_FALLBACK:
       ctx->opt.force_fallback = value != 0;
       return GMLS_OK;
+    case GMLS_OPT_MIXED_RESIDUAL:
+      if (value != 0 && value != 1) return gmls_set_error(ctx, GMLS_ERR_ARG, "mixed residual must be 0 or 1");
+      ctx->opt.residual = (int)value;
+      return GMLS_OK;
     default:
       return gmls_set_error(ctx, GMLS_ERR_ARG, "unknown option");
   }

@@ -40,6 +40,7 @@ struct Options {
   int max_sweeps = 8;
   double refine_tol = 1e-11;
   int force_fallback = 0;
+  int residual = 0;  // 0: FP64 moment Gram where compiled, 1: FP64 residual over the rows
 };
 
 }  // namespace gmls

@@ -1,7 +1,7 @@
 // mixed_unit.hip -- one instantiation of the mixed-precision stencil kernels.
 // Compiled once per (GMLS_DIM, GMLS_ORDER, GMLS_BASIS) by the build, each
 // object defining launch_mixed_d<DIM>_o<ORDER>_b<BASIS>.
-#include "stencil_mixed.hpp"
+#include "stencil_mixed64.hpp"
 
 #if !defined(GMLS_DIM) || !defined(GMLS_ORDER) || !defined(GMLS_BASIS)
 #error "compile with -DGMLS_DIM=.. -DGMLS_ORDER=.. -DGMLS_BASIS=.."
@@ -13,6 +13,12 @@
 
 namespace gmls {
 
+// moments that fit in registers as FP64 accumulators (3D m <= 3, 2D m <= 4)
+template <int DIM, int ORDER>
+constexpr bool has_gram64() {
+  return num_mono(DIM, 2 * ORDER) <= 96;
+}
+
 template <int DIM, int ORDER, int BASIS, int G>
 static hipError_t launch_one(const StencilArgs &a, const int *list, BinMeta *meta, int bin, int *fb, Stats *stats,
                              const Options &opt, int count, int cus, hipStream_t s) {
@@ -20,6 +26,13 @@ static hipError_t launch_one(const StencilArgs &a, const int *list, BinMeta *met
   int nb = (count + TPW - 1) / TPW;
   if (nb > cus * 16) nb = cus * 16;
   if (nb < 1) nb = 1;
+  if constexpr (has_gram64<DIM, ORDER>()) {
+    if (opt.residual == 0) {
+      k_mixed64<DIM, ORDER, BASIS, G><<<nb, 64, 0, s>>>(a, list, meta->count + bin, meta->offset + bin,
+                                                         meta->cursor + bin, fb, meta, stats, opt);
+      return hipGetLastError();
+    }
+  }
   k_mixed<DIM, ORDER, BASIS, G><<<nb, 64, 0, s>>>(a, list, meta->count + bin, meta->offset + bin,
                                                    meta->cursor + bin, fb, meta, stats, opt);
   return hipGetLastError();

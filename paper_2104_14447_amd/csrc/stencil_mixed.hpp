@@ -105,13 +105,11 @@ struct MixedCfg {
 template <int DIM, int ORDER, int BASIS, int G>
 struct MixedLDS {
   using Cf = MixedCfg<DIM, ORDER, BASIS, G>;
-  double rows[Cf::NMAX][DIM + 1];  // s, w
   double y[Cf::FMAX][Cf::QA];      // current solution, shared by the group
   double u[Cf::FU][Cf::NV];        // T y (vector basis)
   double pw[Cf::NV];               // reduced P^T W P y of one functional
   float mu[Cf::NM];
-  float A[Cf::QA][Cf::LDM];        // equilibrated system, then L, then its inverse
-  float B[Cf::QA][Cf::LDM];        // L^-1 (lower part)
+  float A[Cf::QA][Cf::LDM];        // equilibrated system; then L (lower) with L^-T (strict upper); then A~^-1
   float bv[Cf::QA];                // right-hand side of the current solve
   float dsc[Cf::QA];               // D
 };
@@ -201,6 +199,7 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
     for (int d = 0; d < DIM; ++d) xt[d] = a.targets[(int64_t)t * DIM + d];
   }
   const double ie = 1.0 / e;
+  double rs[RPL][DIM], rw[RPL];  // this lane's rows: scaled offsets and kernel weights (FP64)
   float mu[NM];
 #pragma unroll
   for (int m = 0; m < NM; ++m) mu[m] = 0.f;
@@ -222,8 +221,8 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
       w = rad < 1.0 ? int_pow(1.0 - rad, a.p) : 0.0;
     }
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) S.rows[j][d] = s[d];
-    S.rows[j][DIM] = w;
+    for (int d = 0; d < DIM; ++d) rs[r][d] = s[d];
+    rw[r] = w;
     // weighted moments w * s^g, |g| <= 2m (FP32): prefix monomials of the
     // first DIM-1 coordinates times powers of the last one
     constexpr MomentSplit<DIM, ORDER> MS{};
@@ -317,24 +316,45 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
   }
 
   // ---- 4. explicit inverse A~^-1 = L^-T L^-1: columns of L^-1 in parallel
-  // (lane j solves L x = e_j), then the symmetric product; every later solve
-  // is one parallel matrix-vector product ----
+  // (lane j solves L x = e_j), kept transposed in the strict upper triangle
+  // (the diagonal of L^-1 is 1/L_jj); then the symmetric product, held in
+  // registers until every lane is done reading L^-1.  Every later solve is
+  // one parallel matrix-vector product. ----
   for (int j = lg; j < QA; j += G) {
-    S.B[j][j] = 1.0f / S.A[j][j];
     for (int i = j + 1; i < QA; ++i) {
-      float v = 0.f;
-      for (int k = j; k < i; ++k) v -= S.A[i][k] * S.B[k][j];
-      S.B[i][j] = v / S.A[i][i];
+      float v = -S.A[i][j] / S.A[j][j];  // k = j term, with L^-1_jj = 1/L_jj
+      for (int k = j + 1; k < i; ++k) v -= S.A[i][k] * S.A[j][k];
+      S.A[j][i] = v / S.A[i][i];
     }
   }
   __syncthreads();
-  for (int el = lg; el < QA * QA; el += G) {
-    const int i = el / QA, k = el - (el / QA) * QA;
-    if (k > i) continue;
-    float v = 0.f;
-    for (int m = i; m < QA; ++m) v += S.B[m][i] * S.B[m][k];
-    S.A[i][k] = v;
-    S.A[k][i] = v;
+  constexpr int NE = (QA * (QA + 1) / 2 + G - 1) / G;  // lower-triangle entries per lane
+  float gi[NE];
+#pragma unroll
+  for (int q = 0; q < NE; ++q) {
+    const int el = lg + G * q;
+    gi[q] = 0.f;
+    if (el < QA * (QA + 1) / 2) {
+      int i = 0;
+      while ((i + 1) * (i + 2) / 2 <= el) ++i;
+      const int k = el - i * (i + 1) / 2;  // k <= i
+      // sum_{m >= i} L^-1[m][i] L^-1[m][k]; L^-1[m][c] = A[c][m] (m > c), 1/A[c][c] (m == c)
+      float v = (1.0f / S.A[i][i]) * (i == k ? 1.0f / S.A[k][k] : S.A[k][i]);
+      for (int m = i + 1; m < QA; ++m) v += S.A[i][m] * S.A[k][m];
+      gi[q] = v;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NE; ++q) {
+    const int el = lg + G * q;
+    if (el < QA * (QA + 1) / 2) {
+      int i = 0;
+      while ((i + 1) * (i + 2) / 2 <= el) ++i;
+      const int k = el - i * (i + 1) / 2;
+      S.A[i][k] = gi[q];
+      S.A[k][i] = gi[q];
+    }
   }
   __syncthreads();
   // exact 1-norm condition number of the equilibrated system
@@ -393,16 +413,12 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
         for (int r = 0; r < RPL; ++r) {
           const int j = lg + G * r;
           if (j < N) {
-            double sv[DIM];
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) sv[d] = S.rows[j][d];
-            const double w = S.rows[j][DIM];
             double p[Q];
-            scaled_basis<DIM, ORDER, double>(sv, p);
+            scaled_basis<DIM, ORDER, double>(rs[r], p);
             double u = 0.0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) u += p[q] * yr[q];
-            const double tw = w * u;
+            const double tw = rw[r] * u;
 #pragma unroll
             for (int q = 0; q < Q; ++q) part[q] += tw * p[q];
           }
@@ -473,15 +489,12 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
         for (int r = 0; r < RPL; ++r) {
           const int j = lg + G * r;
           if (j < N) {
-            double sv[DIM];
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) sv[d] = S.rows[j][d];
             double p[Q];
-            scaled_basis<DIM, ORDER, double>(sv, p);
+            scaled_basis<DIM, ORDER, double>(rs[r], p);
             double u = 0.0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) u += p[q] * yr[q];
-            wout[((int64_t)f * N + j) * C + c] = S.rows[j][DIM] * u;
+            wout[((int64_t)f * N + j) * C + c] = rw[r] * u;
           }
         }
       }

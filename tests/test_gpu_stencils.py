@@ -133,11 +133,17 @@ def test_end_to_end_gpu_search_then_stencils():
     assert errs.max() <= FP64_TOL
 
 
+@pytest.mark.parametrize("residual", [0, 1], ids=["gram64", "rows"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_mixed_matches_oracle(name):
+def test_mixed_matches_oracle(name, residual):
     G = require_gpu()
     pts, rp, col, eps, w, st, F, C = case_data(name)
-    gw, gst, rep = run_gpu(name, G.PREC_MIXED)
+    c = ctx()
+    c.set_option(G.OPT_MIXED_RESIDUAL, residual)
+    try:
+        gw, gst, rep = run_gpu(name, G.PREC_MIXED)
+    finally:
+        c.set_option(G.OPT_MIXED_RESIDUAL, 0)
     # fallback targets keep a fallback status; everything else is OK
     assert np.array_equal(gst == 1, st == 1)
     zero = (F - 1,) if CASES[name][2] == "divfree" and CASES[name][4] & 8 else ()
