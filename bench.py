@@ -57,7 +57,9 @@ def parse():
     ap.add_argument("--sample", type=int, default=256, help="targets checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle timing leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--residual", type=int, default=0, help="mixed refinement residual: 0 FP64 moment Gram, 1 rows")
+    ap.add_argument("--scheme", type=int, default=0,
+                    help="mixed scheme: 0 auto, 1 fused/rows residual, 2 fused/moment Gram, 3 pipeline")
+    ap.add_argument("--chunk", type=int, default=0, help="pipeline chunk (targets; 0 = whole batch)")
     return ap.parse_args()
 
 
@@ -77,7 +79,8 @@ def main():
     G.load_library()
     dev = torch.device("cuda:0")
     ctx = G.Context(0)
-    ctx.set_option(G.OPT_MIXED_RESIDUAL, args.residual)
+    ctx.set_option(G.OPT_MIXED_SCHEME, args.scheme)
+    ctx.set_option(G.OPT_PIPE_CHUNK, args.chunk)
 
     wl = W.WORKLOADS["c4_3d_m3_uneven"]
     n = args.n
@@ -205,7 +208,8 @@ def main():
         "config": {"workload": "c4_3d_m3_uneven: 2M points, density 1+3x, radius search (k_min 30), "
                                "scalar order 3, Laplacian",
                    "n_points": n, "nnz": int(nnz), "precision": prec_name, "radius": r0,
-                   "mixed_residual": ["fp64 moment Gram", "fp64 rows (CSNE)"][args.residual],
+                   "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
+                                    "pipeline"][args.scheme],
                    "parity_gate": gate, "parity_max_rel_err": max_err, "parity_sample": int(len(sample)),
                    "fallbacks": int(rep["n_fallback"]), "rank_deficient": int(rep["n_rank_deficient"])},
         "roofline": roofline,

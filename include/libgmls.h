@@ -116,10 +116,21 @@ enum {
   GMLS_OPT_REFINE_TOL = 2,     /* stop when the predicted relative error after a correction,
                                   rho*|dy|/|y| with rho = 2 n cond 2^-24, is <= tol (1e-11)   */
   GMLS_OPT_FORCE_FALLBACK = 3, /* nonzero: every mixed target takes the FP64 fallback (0)      */
-  GMLS_OPT_MIXED_RESIDUAL = 4  /* refinement residual of the mixed path: 0 = FP64 weighted-moment
-                                  Gram, one pass over the rows (default; 3D order <= 3 and 2D
-                                  order <= 4, otherwise 1); 1 = FP64 residual recomputed over the
-                                  rows each sweep (corrected semi-normal equations)            */
+  GMLS_OPT_MIXED_SCHEME = 4,   /* organisation of the mixed path (0):
+                                  0 = automatic: 3 where compiled, else 2 where compiled, else 1;
+                                  1 = one fused kernel per row-count bin, FP64 residual recomputed
+                                      over the rows every sweep (corrected semi-normal equations);
+                                  2 = one fused kernel per bin, FP64 weighted moments formed once
+                                      and the residual taken against the FP64 moment Gram
+                                      (3D order <= 3, 2D order <= 4);
+                                  3 = three-kernel pipeline: FP64 moments to device memory, one
+                                      thread per target for factorisation and refinement, then the
+                                      weights (scalar basis with at most 20 functions: 3D order
+                                      <= 3, 2D order <= 4).
+                                  A scheme not compiled for the shape makes gmls_stencils return
+                                  GMLS_ERR_UNSUPPORTED.                                         */
+  GMLS_OPT_PIPE_CHUNK = 5      /* scheme 3: targets per pipeline chunk, 0 = all at once (0); the
+                                  workspace holds (moments + F*Q) doubles per chunk target       */
 };
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`

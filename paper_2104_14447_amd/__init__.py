@@ -21,7 +21,8 @@ __all__ = [
     "gmls_neighbors", "gmls_stencil_shape", "gmls_stencils", "gmls_apply",
     "BASIS_SCALAR", "BASIS_DIVFREE", "F_VALUE", "F_GRAD", "F_LAPLACIAN", "F_DIV",
     "PREC_FP64", "PREC_MIXED", "SEARCH_KNN", "SEARCH_RADIUS",
-    "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_RESIDUAL",
+    "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
+    "OPT_PIPE_CHUNK", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -31,7 +32,9 @@ BASIS_SCALAR, BASIS_DIVFREE = 0, 1
 F_VALUE, F_GRAD, F_LAPLACIAN, F_DIV = 1, 2, 4, 8
 PREC_FP64, PREC_MIXED = 0, 1
 SEARCH_KNN, SEARCH_RADIUS = 0, 1
-OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK, OPT_MIXED_RESIDUAL = 0, 1, 2, 3, 4
+OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
+OPT_MIXED_SCHEME, OPT_PIPE_CHUNK = 4, 5
+SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE = 0, 1, 2, 3
 GMLS_OK, GMLS_ERR_CAPACITY, GMLS_WARN_TARGET_FLAGS = 0, 4, 6
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY", 5: "ERR_UNSUPPORTED",
            6: "WARN_TARGET_FLAGS"}

@@ -141,9 +141,16 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
     case GMLS_OPT_FORCE_FALLBACK:
       ctx->opt.force_fallback = value != 0;
       return GMLS_OK;
-    case GMLS_OPT_MIXED_RESIDUAL:
-      if (value != 0 && value != 1) return gmls_set_error(ctx, GMLS_ERR_ARG, "mixed residual must be 0 or 1");
-      ctx->opt.residual = (int)value;
+    case GMLS_OPT_MIXED_SCHEME:
+      if (value != 0 && value != 1 && value != 2 && value != 3)
+        return gmls_set_error(ctx, GMLS_ERR_ARG, "mixed scheme must be 0 (auto), 1, 2 or 3");
+      ctx->opt.scheme = (int)value;
+      return GMLS_OK;
+    case GMLS_OPT_PIPE_CHUNK:
+      if (!(value >= 0 && value <= 2147483647.0 && value == (double)(int64_t)value))
+        return gmls_set_error(ctx, GMLS_ERR_ARG, "pipeline chunk must be an integer in [0, 2^31)");
+      if (value != 0 && value < 64) return gmls_set_error(ctx, GMLS_ERR_ARG, "pipeline chunk must be 0 or >= 64");
+      ctx->opt.pipe_chunk = (int64_t)value;
       return GMLS_OK;
     default:
       return gmls_set_error(ctx, GMLS_ERR_ARG, "unknown option");
@@ -211,6 +218,12 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
   if (prec != GMLS_PREC_FP64 && prec != GMLS_PREC_MIXED) return gmls_set_error(ctx, GMLS_ERR_ARG, "bad precision");
   if (prec == GMLS_PREC_MIXED && !mixed_supported(dim, order, basis))
     return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "mixed precision not compiled for this basis/order");
+  Options opt = ctx->opt;
+  if (prec == GMLS_PREC_MIXED) {
+    opt.scheme = mixed_scheme(dim, order, basis, ctx->opt.scheme);
+    if (opt.scheme < 0)
+      return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "the selected mixed scheme is not compiled for this shape");
+  }
   if (weight_p < 1 || weight_p > 12) return gmls_set_error(ctx, GMLS_ERR_ARG, "weight power must be 1..12");
   if (n_src < 1 || n_tgt < 0 || n_tgt > (1ll << 31) - 1)
     return gmls_set_error(ctx, GMLS_ERR_ARG, "n_src must be >= 1 and n_tgt in [0, 2^31)");
@@ -244,7 +257,10 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
   a.ok_status = GMLS_TARGET_OK;
 
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[0], s));
-  GMLS_HIP(launch_binning(row_ptr, n, Q, C, meta, list, s));
+  const size_t bin_bytes = binning_temp_bytes(n);
+  void *bin_tmp = ctx->ws(WS_BIN_TEMP, bin_bytes);
+  if (!bin_tmp) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+  GMLS_HIP(launch_binning(row_ptr, targets, n, dim, Q, C, meta, list, bin_tmp, bin_bytes, s));
   BinMeta hm;
   GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
   GMLS_HIP(hipStreamSynchronize(s));
@@ -258,13 +274,24 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
     if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
       cus = prop.multiProcessorCount;
   }
-  for (int b = 1; b < kNumBins; ++b) {
-    if (hm.count[b] == 0) continue;
-    if (prec == GMLS_PREC_FP64) {
-      const int nb = std::min(hm.count[b], cus * 16);
-      GMLS_HIP(launch_qr_bin(dim, order, basis, b, a, list, meta, nb, s));
-    } else {
-      GMLS_HIP(launch_mixed_bin(dim, order, basis, b, a, list, meta, fb, stats, ctx->opt, hm.count[b], cus, s));
+  if (prec == GMLS_PREC_MIXED && opt.scheme == MIXED_PIPE) {
+    // moments [NM][chunk] and solutions [F][Q][chunk] of one chunk of targets
+    const int64_t n_work = (int64_t)n - hm.count[0];
+    const int64_t chunk = std::max<int64_t>(1, opt.pipe_chunk > 0 ? std::min<int64_t>(opt.pipe_chunk, n_work) : n_work);
+    double *mom = (double *)ctx->ws(WS_PIPE_MOM, sizeof(double) * (size_t)pipe_num_moments(dim, order) * chunk);
+    double *yb = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)F * Q * chunk);
+    if (!mom || !yb) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+    if (n_work > 0)
+      GMLS_HIP(launch_mixed_pipe(dim, order, basis, a, list, hm, meta, fb, stats, opt, mom, yb, chunk, cus, s));
+  } else {
+    for (int b = 1; b < kNumBins; ++b) {
+      if (hm.count[b] == 0) continue;
+      if (prec == GMLS_PREC_FP64) {
+        const int nb = std::min(hm.count[b], cus * 16);
+        GMLS_HIP(launch_qr_bin(dim, order, basis, b, a, list, meta, nb, s));
+      } else {
+        GMLS_HIP(launch_mixed_bin(dim, order, basis, b, a, list, meta, fb, stats, opt, hm.count[b], cus, s));
+      }
     }
   }
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));

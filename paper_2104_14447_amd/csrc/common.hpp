@@ -79,6 +79,19 @@ struct Mono {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i runs on
+// XCD i % 8), and each XCD has its own L2.  This renumbering gives XCD x the
+// contiguous logical range [x*nb/8, (x+1)*nb/8), so that neighbouring work
+// items (spatially ordered targets) share one L2.  gridDim.x must be a
+// multiple of 8.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// grid size rounded up to a multiple of the XCD count
+inline int xcd_grid(int nb) { return nb < 8 ? 8 : (nb + 7) & ~7; }
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   int2 b = __builtin_bit_cast(int2, v);
   b.x = __builtin_amdgcn_readlane(b.x, lane);

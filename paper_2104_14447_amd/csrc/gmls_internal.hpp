@@ -32,15 +32,22 @@ enum Slot {
   WS_FALLBACK,
   WS_STATS,
   WS_STATUS_TMP,
+  WS_BIN_TEMP,
+  WS_PIPE_MOM,
+  WS_PIPE_Y,
   WS_NUM_SLOTS
 };
+
+// mixed-precision schemes (GMLS_OPT_MIXED_SCHEME)
+enum MixedScheme { MIXED_AUTO = 0, MIXED_ROWS = 1, MIXED_GRAM = 2, MIXED_PIPE = 3 };
 
 struct Options {
   double cond_threshold = 1e6;
   int max_sweeps = 8;
   double refine_tol = 1e-11;
   int force_fallback = 0;
-  int residual = 0;  // 0: FP64 moment Gram where compiled, 1: FP64 residual over the rows
+  int scheme = MIXED_AUTO;  // resolved to ROWS, GRAM or PIPE before any launch
+  int64_t pipe_chunk = 0;   // list slots per pipeline chunk (0: the whole call)
 };
 
 }  // namespace gmls
@@ -124,12 +131,22 @@ hipError_t launch_qr_fallback(int dim, int order, int basis, const StencilArgs &
 hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,
                             BinMeta *meta, int *fb_list, Stats *stats, const Options &opt, int count, int cus,
                             hipStream_t s);
+hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a, const int *list,
+                             const BinMeta &hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt,
+                             double *mom, double *y, int64_t chunk, int cus, hipStream_t s);
 bool qr_supported(int dim, int order, int basis);
 bool mixed_supported(int dim, int order, int basis);
+// the scheme a request resolves to (MIXED_AUTO picks the fastest compiled
+// one); -1 when the requested scheme is not compiled for this shape
+int mixed_scheme(int dim, int order, int basis, int requested);
+// FP64 moments of the pipeline per target (num_mono(dim, 2*order))
+int pipe_num_moments(int dim, int order);
 
 // binning (stencil_bins.hip)
-hipError_t launch_binning(const int64_t *row_ptr, int n_tgt, int Q, int rows_per_nbr, BinMeta *meta, int *list,
-                          hipStream_t s);
+// temporary device bytes launch_binning needs for n_tgt targets
+size_t binning_temp_bytes(int n_tgt);
+hipError_t launch_binning(const int64_t *row_ptr, const double *targets, int n_tgt, int dim, int Q,
+                          int rows_per_nbr, BinMeta *meta, int *list, void *temp, size_t temp_bytes, hipStream_t s);
 hipError_t launch_rank_deficient(const StencilArgs &a, int C, const int *list, BinMeta *meta, hipStream_t s);
 
 // apply (apply.hip)

@@ -1,7 +1,10 @@
 // mixed_unit.hip -- one instantiation of the mixed-precision stencil kernels.
 // Compiled once per (GMLS_DIM, GMLS_ORDER, GMLS_BASIS) by the build, each
-// object defining launch_mixed_d<DIM>_o<ORDER>_b<BASIS>.
+// object defining launch_mixed_d<DIM>_o<ORDER>_b<BASIS> (the per-bin fused
+// kernels) and launch_pipe_d<DIM>_o<ORDER>_b<BASIS> (the three-kernel pipeline,
+// scalar bases with at most 20 functions).
 #include "stencil_mixed64.hpp"
+#include "stencil_pipe.hpp"
 
 #if !defined(GMLS_DIM) || !defined(GMLS_ORDER) || !defined(GMLS_BASIS)
 #error "compile with -DGMLS_DIM=.. -DGMLS_ORDER=.. -DGMLS_BASIS=.."
@@ -10,14 +13,9 @@
 #define GMLS_CAT2(a, b, c, d, e, f) a##b##c##d##e##f
 #define GMLS_CAT(a, b, c, d, e, f) GMLS_CAT2(a, b, c, d, e, f)
 #define GMLS_FN GMLS_CAT(launch_mixed_d, GMLS_DIM, _o, GMLS_ORDER, _b, GMLS_BASIS)
+#define GMLS_PIPE_FN GMLS_CAT(launch_pipe_d, GMLS_DIM, _o, GMLS_ORDER, _b, GMLS_BASIS)
 
 namespace gmls {
-
-// moments that fit in registers as FP64 accumulators (3D m <= 3, 2D m <= 4)
-template <int DIM, int ORDER>
-constexpr bool has_gram64() {
-  return num_mono(DIM, 2 * ORDER) <= 96;
-}
 
 template <int DIM, int ORDER, int BASIS, int G>
 static hipError_t launch_one(const StencilArgs &a, const int *list, BinMeta *meta, int bin, int *fb, Stats *stats,
@@ -27,7 +25,7 @@ static hipError_t launch_one(const StencilArgs &a, const int *list, BinMeta *met
   if (nb > cus * 16) nb = cus * 16;
   if (nb < 1) nb = 1;
   if constexpr (has_gram64<DIM, ORDER>()) {
-    if (opt.residual == 0) {
+    if (opt.scheme == MIXED_GRAM) {
       k_mixed64<DIM, ORDER, BASIS, G><<<nb, 64, 0, s>>>(a, list, meta->count + bin, meta->offset + bin,
                                                          meta->cursor + bin, fb, meta, stats, opt);
       return hipGetLastError();
@@ -51,6 +49,17 @@ hipError_t GMLS_FN(int bin, const StencilArgs &a, const int *list, BinMeta *meta
       case 2: return launch_one<D, O, B, 16>(a, list, meta, bin, fb, stats, opt, count, cus, s);
       default: return launch_one<D, O, B, 32>(a, list, meta, bin, fb, stats, opt, count, cus, s);
     }
+  }
+}
+
+hipError_t GMLS_PIPE_FN(const StencilArgs &a, const int *list, const BinMeta &hm, BinMeta *meta, int *fb,
+                        Stats *stats, const Options &opt, double *mom, double *y, int64_t chunk, int cus,
+                        hipStream_t s) {
+  constexpr int D = GMLS_DIM, O = GMLS_ORDER, B = GMLS_BASIS;
+  if constexpr (B == 0 && has_pipe<D, O>()) {
+    return launch_pipe<D, O>(a, list, hm, meta, fb, stats, opt, mom, y, chunk, cus, s);
+  } else {
+    return hipErrorInvalidValue;
   }
 }
 

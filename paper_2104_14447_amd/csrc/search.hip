@@ -160,16 +160,19 @@ __global__ __launch_bounds__(kBBoxBlock) void k_bbox_partial(const double *pts, 
 // mode 0: kNN with neighbour count k; mode 1: radius r (cells no smaller than r)
 __global__ void k_grid_setup(const double *partial, int nb, int dim, int mode, double radius, int k, int64_t n,
                              int64_t ncell_max, GridParams *gp) {
-  if (threadIdx.x != 0) return;
-  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  for (int d = 0; d < dim; ++d) {
-    lo[d] = partial[d];
-    hi[d] = partial[3 + d];
-    for (int b = 1; b < nb; ++b) {
+  // one wave reduces the partial boxes, then lane 0 sizes the grid
+  double lo[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, hi[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+  for (int b = threadIdx.x; b < nb; b += 64)
+    for (int d = 0; d < dim; ++d) {
       lo[d] = fmin(lo[d], partial[b * 6 + d]);
       hi[d] = fmax(hi[d], partial[b * 6 + 3 + d]);
     }
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = wave_min(lo[d]);
+    hi[d] = wave_max(hi[d]);
   }
+  if (threadIdx.x != 0) return;
+  for (int d = dim; d < 3; ++d) lo[d] = hi[d] = 0.0;
   double ext_max = 0;
   for (int d = 0; d < dim; ++d) ext_max = fmax(ext_max, hi[d] - lo[d]);
   double c;

@@ -1,5 +1,6 @@
 // stencil_mixed.hip -- dispatch of the mixed-precision stencil kernels.  The
 // kernels are instantiated per (dim, order, basis) from mixed_unit.hip.
+#include "common.hpp"
 #include "gmls_internal.hpp"
 
 namespace gmls {
@@ -37,6 +38,45 @@ hipError_t launch_mixed_d3_o4_b0(int, const StencilArgs &, const int *, BinMeta 
 hipError_t launch_mixed_d3_o4_b1(int, const StencilArgs &, const int *, BinMeta *, int *, Stats *,
                                   const Options &, int, int, hipStream_t);
 
+hipError_t launch_pipe_d2_o1_b0(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d2_o1_b1(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d2_o2_b0(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d2_o2_b1(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d2_o3_b0(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d2_o3_b1(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d2_o4_b0(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d2_o4_b1(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d3_o1_b0(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d3_o1_b1(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d3_o2_b0(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d3_o2_b1(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d3_o3_b0(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d3_o3_b1(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d3_o4_b0(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+hipError_t launch_pipe_d3_o4_b1(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                                const Options &, double *, double *, int64_t, int, hipStream_t);
+
+using PipeFn = hipError_t (*)(const StencilArgs &, const int *, const BinMeta &, BinMeta *, int *, Stats *,
+                              const Options &, double *, double *, int64_t, int, hipStream_t);
+static const PipeFn kPipe[2][4][2] = {
+    {{launch_pipe_d2_o1_b0, launch_pipe_d2_o1_b1}, {launch_pipe_d2_o2_b0, launch_pipe_d2_o2_b1}, {launch_pipe_d2_o3_b0, launch_pipe_d2_o3_b1}, {launch_pipe_d2_o4_b0, launch_pipe_d2_o4_b1}},
+    {{launch_pipe_d3_o1_b0, launch_pipe_d3_o1_b1}, {launch_pipe_d3_o2_b0, launch_pipe_d3_o2_b1}, {launch_pipe_d3_o3_b0, launch_pipe_d3_o3_b1}, {launch_pipe_d3_o4_b0, launch_pipe_d3_o4_b1}}};
+
 using MixedFn = hipError_t (*)(int, const StencilArgs &, const int *, BinMeta *, int *, Stats *, const Options &, int,
                                int, hipStream_t);
 static const MixedFn kMixed[2][4][2] = {
@@ -45,6 +85,28 @@ static const MixedFn kMixed[2][4][2] = {
 
 bool mixed_supported(int dim, int order, int basis) {
   return (dim == 2 || dim == 3) && order >= 1 && order <= 4 && (basis == 0 || basis == 1);
+}
+
+int mixed_scheme(int dim, int order, int basis, int requested) {
+  if (!mixed_supported(dim, order, basis)) return -1;
+  const bool pipe = basis == 0 && num_mono(dim, order) <= 20;
+  const bool gram = num_mono(dim, 2 * order) <= 96;
+  switch (requested) {
+    case MIXED_AUTO: return pipe ? MIXED_PIPE : gram ? MIXED_GRAM : MIXED_ROWS;
+    case MIXED_ROWS: return MIXED_ROWS;
+    case MIXED_GRAM: return gram ? MIXED_GRAM : -1;
+    case MIXED_PIPE: return pipe ? MIXED_PIPE : -1;
+    default: return -1;
+  }
+}
+
+int pipe_num_moments(int dim, int order) { return num_mono(dim, 2 * order); }
+
+hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a, const int *list,
+                             const BinMeta &hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt,
+                             double *mom, double *y, int64_t chunk, int cus, hipStream_t s) {
+  if (mixed_scheme(dim, order, basis, MIXED_PIPE) != MIXED_PIPE) return hipErrorInvalidValue;
+  return kPipe[dim - 2][order - 1][basis](a, list, hm, meta, fb, stats, opt, mom, y, chunk, cus, s);
 }
 
 hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,

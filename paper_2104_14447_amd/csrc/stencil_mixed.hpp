@@ -105,6 +105,7 @@ struct MixedCfg {
 template <int DIM, int ORDER, int BASIS, int G>
 struct MixedLDS {
   using Cf = MixedCfg<DIM, ORDER, BASIS, G>;
+  double rows[Cf::NMAX][DIM + 1];  // s, w of every row (FP64)
   double y[Cf::FMAX][Cf::QA];      // current solution, shared by the group
   double u[Cf::FU][Cf::NV];        // T y (vector basis)
   double pw[Cf::NV];               // reduced P^T W P y of one functional
@@ -199,7 +200,6 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
     for (int d = 0; d < DIM; ++d) xt[d] = a.targets[(int64_t)t * DIM + d];
   }
   const double ie = 1.0 / e;
-  double rs[RPL][DIM], rw[RPL];  // this lane's rows: scaled offsets and kernel weights (FP64)
   float mu[NM];
 #pragma unroll
   for (int m = 0; m < NM; ++m) mu[m] = 0.f;
@@ -221,8 +221,8 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
       w = rad < 1.0 ? int_pow(1.0 - rad, a.p) : 0.0;
     }
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) rs[r][d] = s[d];
-    rw[r] = w;
+    for (int d = 0; d < DIM; ++d) S.rows[j][d] = s[d];
+    S.rows[j][DIM] = w;
     // weighted moments w * s^g, |g| <= 2m (FP32): prefix monomials of the
     // first DIM-1 coordinates times powers of the last one
     constexpr MomentSplit<DIM, ORDER> MS{};
@@ -413,12 +413,15 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
         for (int r = 0; r < RPL; ++r) {
           const int j = lg + G * r;
           if (j < N) {
+            double sv[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sv[d] = S.rows[j][d];
             double p[Q];
-            scaled_basis<DIM, ORDER, double>(rs[r], p);
+            scaled_basis<DIM, ORDER, double>(sv, p);
             double u = 0.0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) u += p[q] * yr[q];
-            const double tw = rw[r] * u;
+            const double tw = S.rows[j][DIM] * u;
 #pragma unroll
             for (int q = 0; q < Q; ++q) part[q] += tw * p[q];
           }
@@ -451,7 +454,8 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
           const double dy = (double)v * (double)S.dsc[i];
           const double yn = S.y[f][i] + dy;
           S.y[f][i] = yn;
-          dmax = fmax(dmax, fabs(dy));
+          // a non-finite correction must never look converged
+          dmax = (fabs(dy) <= dmax) ? dmax : (isfinite(dy) ? fabs(dy) : INFINITY);
           ymax = fmax(ymax, fabs(yn));
         }
       }
@@ -489,12 +493,15 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
         for (int r = 0; r < RPL; ++r) {
           const int j = lg + G * r;
           if (j < N) {
+            double sv[DIM];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sv[d] = S.rows[j][d];
             double p[Q];
-            scaled_basis<DIM, ORDER, double>(rs[r], p);
+            scaled_basis<DIM, ORDER, double>(sv, p);
             double u = 0.0;
 #pragma unroll
             for (int q = 0; q < Q; ++q) u += p[q] * yr[q];
-            wout[((int64_t)f * N + j) * C + c] = rw[r] * u;
+            wout[((int64_t)f * N + j) * C + c] = S.rows[j][DIM] * u;
           }
         }
       }

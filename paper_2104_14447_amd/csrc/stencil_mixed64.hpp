@@ -24,6 +24,12 @@
 
 namespace gmls {
 
+// moments that fit in registers as FP64 accumulators (3D m <= 3, 2D m <= 4)
+template <int DIM, int ORDER>
+constexpr bool has_gram64() {
+  return num_mono(DIM, 2 * ORDER) <= 96;
+}
+
 template <int DIM, int ORDER>
 struct InvFact64 {
   static constexpr int Q = num_mono(DIM, ORDER);
@@ -314,7 +320,7 @@ __device__ void mixed64_target(const StencilArgs &a, const RowKinds &rk, int t, 
           const double dy = (double)v * (double)S.dsc[i];
           const double yn = S.y[f][i] + dy;
           S.y[f][i] = yn;
-          dmax = fmax(dmax, fabs(dy));
+          dmax = (fabs(dy) <= dmax) ? dmax : (isfinite(dy) ? fabs(dy) : INFINITY);
           ymax = fmax(ymax, fabs(yn));
         }
       }

@@ -1,0 +1,471 @@
+// stencil_pipe.hpp -- mixed-precision stencils as a three-kernel pipeline for
+// small scalar bases (Q <= 20: 3D order <= 3, 2D order <= 4).
+//
+// The stencil of a functional lambda is alpha = W P y with (P^T W P) y = lambda
+// (Section 2.1, normal equations; Section 2.5, functionals on the basis).
+//
+//  A. moments (a group of G lanes per target, rows spread over the group):
+//     mu_g = sum_j w_j s_j^g for |g| <= 2m in FP64, reduce-scattered over the
+//     group and stored to HBM, moment-major [g][slot];
+//  B. solve (one thread per target, the whole system in registers):
+//     A64_ab = mu_(a+b)/(a! b!) is the Gram; its Jacobi-equilibrated FP32
+//     copy is factored by a fully unrolled packed Cholesky, its 1-norm
+//     condition number is estimated (Hager's estimator, three solves), then
+//     y = D A~^-1 D lambda is refined with FP64 residuals r = lambda - A64 y
+//     (FP32 correction, FP64 accumulation) until the predicted error
+//     rho*|dy| <= tol*|y|; y is stored to HBM, [f][a][slot];
+//  C. weights (a group of G lanes per target): alpha_j = w_j p(s_j) . y in
+//     FP64, the rows gathered again.
+// Targets that break down, exceed the condition threshold or do not converge
+// are queued for the FP64 QR fallback.  Every lane of kernel B runs the same
+// instruction stream (no row-count divergence), and no lane is idle.
+#pragma once
+
+#include <float.h>
+#include <math.h>
+
+#include "basis.hpp"
+#include "gmls_internal.hpp"
+#include "stencil_mixed64.hpp"
+
+namespace gmls {
+
+// functional rows of a scalar basis: value, dim gradient components, Laplacian
+constexpr int kPipeMaxF = 5;
+
+// ---------------------------------------------------------------------------
+// A. moments
+// ---------------------------------------------------------------------------
+// Rows j = lg + G*r (r < RPL) of a target, gathered without branches: rows
+// past N re-read row N-1 and get weight 0, so all column indices, then all
+// coordinates, are requested together (two memory round trips per target
+// instead of two per row).
+template <int DIM, int RPL, int G>
+__device__ __forceinline__ void gather_rows(const StencilArgs &a, int64_t base, int N, int lg,
+                                            double (&xs)[RPL][DIM]) {
+  int c[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int j = lg + G * r;
+    c[r] = a.col[base + (j < N ? j : N - 1)];
+  }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xs[r][d] = a.coords[(int64_t)c[r] * DIM + d];
+}
+
+// scaled offset s = (x_j - x_T)/eps and kernel weight (1 - |s|)^p (0 outside
+// the support, and 0 when `live` is false)
+template <int DIM>
+__device__ __forceinline__ double row_sw(const double *xj, const double *xt, double ie, int p, bool live,
+                                         double *s) {
+  double rr = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    s[d] = (xj[d] - xt[d]) * ie;
+    rr += s[d] * s[d];
+  }
+  const double rad = sqrt(rr);
+  return (live && rad < 1.0) ? int_pow(1.0 - rad, p) : 0.0;
+}
+
+// `t` is a target of the bin even for an invalid group (whose sums are not
+// stored), so that every gathered row exists.
+template <int DIM, int ORDER, int G, int RPL>
+__device__ void pipe_moments_target(const StencilArgs &a, int t, bool valid, int slot, int lg, double *mom) {
+  constexpr int NM = num_mono(DIM, 2 * ORDER);
+  constexpr int NMP = ((NM + G - 1) / G) * G;
+  const int64_t base = a.row_ptr[t];
+  const int N = (int)(a.row_ptr[t + 1] - base);
+  const double ie = 1.0 / a.eps[t];
+  double xt[DIM];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) xt[d] = a.targets[(int64_t)t * DIM + d];
+  double xs[RPL][DIM];
+  gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
+  double mu[NMP];
+#pragma unroll
+  for (int m = 0; m < NMP; ++m) mu[m] = 0.0;
+  constexpr MomentSplit<DIM, ORDER> MS{};
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    double s[DIM];
+    const double w = row_sw<DIM>(xs[r], xt, ie, a.p, lg + G * r < N, s);
+    double lastp[2 * ORDER + 1];
+    lastp[0] = 1.0;
+#pragma unroll
+    for (int c = 1; c <= 2 * ORDER; ++c) lastp[c] = lastp[c - 1] * s[DIM - 1];
+    double wp[MS.NP];
+    wp[0] = w;
+#pragma unroll
+    for (int pi = 1; pi < MS.NP; ++pi) wp[pi] = wp[MS.parent[pi]] * s[MS.pdim[pi]];
+#pragma unroll
+    for (int pi = 0; pi < MS.NP; ++pi)
+#pragma unroll
+      for (int c = 0; c <= 2 * ORDER - MS.deg[pi]; ++c) mu[MS.midx[pi][c]] += wp[pi] * lastp[c];
+  }
+  group_reduce_scatter<G, NMP>(mu, lg);
+  if (valid) {
+#pragma unroll
+    for (int i = 0; i < NMP / G; ++i) {
+      const int m = lg * (NMP / G) + i;
+      if (m < NM) mom[(int64_t)slot * NM + m] = mu[i];
+    }
+  }
+}
+
+// Targets list[first .. last) of one row-count bin; moment g of the target
+// in list slot i goes to mom[(i - c0) * NM + g] (target-major, so that a
+// group writes its target's moments contiguously).
+template <int DIM, int ORDER, int G, int RPL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_pipe_moments(StencilArgs a, const int *list, int first, int last, int c0,
+                                                     double *mom) {
+  constexpr int TPW = 64 / G;
+  const int lane = lane_id();
+  const int grp = lane / G, lg = lane % G;
+  for (int i0 = first + xcd_block() * TPW; i0 < last; i0 += gridDim.x * TPW) {
+    const int i = i0 + grp;
+    const bool valid = i < last;
+    const int t = list[valid ? i : first];
+    pipe_moments_target<DIM, ORDER, G, RPL>(a, t, valid, i - c0, lg, mom);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// B. solve, one thread per target
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Packed {
+  static constexpr int n = Q * (Q + 1) / 2;
+  static constexpr int at(int i, int k) { return i * (i + 1) / 2 + k; }  // k <= i
+};
+
+// x <- (L L^T)^-1 x for a packed lower-triangular L whose diagonal slots hold
+// 1/L_jj (registers, fully unrolled)
+template <int Q>
+__device__ __forceinline__ void packed_solve(const float (&L)[Q * (Q + 1) / 2], float (&x)[Q]) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    float v = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= L[Packed<Q>::at(i, k)] * x[k];
+    x[i] = v * L[Packed<Q>::at(i, i)];
+  }
+#pragma unroll
+  for (int i = Q - 1; i >= 0; --i) {
+    float v = x[i];
+#pragma unroll
+    for (int k = i + 1; k < Q; ++k) v -= L[Packed<Q>::at(k, i)] * x[k];
+    x[i] = v * L[Packed<Q>::at(i, i)];
+  }
+}
+
+// All (a, b) pairs of the Q x Q moment Gram ordered by the moment index of
+// a + b, so that the residual streams each moment once.
+template <int DIM, int ORDER>
+struct MomentPairs {
+  static constexpr int Q = num_mono(DIM, ORDER);
+  static constexpr int NM = num_mono(DIM, 2 * ORDER);
+  static constexpr int P = Q * Q;
+  int m[P], a[P], b[P];
+  constexpr MomentPairs() : m{}, a{}, b{} {
+    SumIndex<DIM, ORDER> S{};
+    int p = 0;
+    for (int g = 0; g < NM; ++g)
+      for (int i = 0; i < Q; ++i)
+        for (int k = 0; k < Q; ++k)
+          if (S.idx[i][k] == g) {
+            m[p] = g;
+            a[p] = i;
+            b[p] = k;
+            ++p;
+          }
+  }
+};
+
+template <int DIM, int ORDER>
+__global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, const int *list, int first, int last, int c0,
+                                                   const double *mom, double *yout, int *fb_list,
+                                                   BinMeta *meta, Stats *stats, Options opt) {
+  constexpr int Q = num_mono(DIM, ORDER);
+  constexpr int NP = Q * (Q + 1) / 2;
+  constexpr InvFact64<DIM, ORDER> IF{};
+  constexpr SumIndex<DIM, ORDER> SI{};
+  constexpr MomentPairs<DIM, ORDER> MP{};
+  constexpr int NM = MomentPairs<DIM, ORDER>::NM;
+  // thread-private LDS columns (lane l uses [.][l] only)
+  __shared__ double mls[NM][64];  // FP64 moments of this thread's target
+  __shared__ double ybuf[Q][64];  // this thread's solution
+  const int lane = lane_id();
+  const RowKinds rk = row_kinds(DIM, 0, a.mask);
+  const int F = a.F;
+  for (int slot = first + xcd_block() * 64 + lane; slot - lane < last; slot += gridDim.x * 64) {
+    const bool valid = slot < last;
+    const int sl = valid ? slot : first;
+    const int t = list[sl];
+    const double ie = 1.0 / a.eps[t];
+    const int64_t loc = sl - c0;
+    // stage this thread's moments into its LDS column; the wave's 84 loads
+    // walk one contiguous block of 64*NM doubles, so lines are reused from L1
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < NM; ++m) mls[m][lane] = mom[loc * NM + m];
+    }
+#define GMLS_MU(g, off) mls[(g)][lane + (off)]
+    // equilibration D_a = 1/sqrt(A64_aa) = a!/sqrt(mu_2a); equilibrated FP32
+    // Gram D A64 D, packed lower
+    float dsc[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dsc[i] = (float)(1.0 / IF.v[i]) * rsqrtf((float)GMLS_MU(SI.idx[i][i], 0));
+    float L[NP];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double di = (double)dsc[i] * IF.v[i];
+#pragma unroll
+      for (int k = 0; k <= i; ++k)
+        L[Packed<Q>::at(i, k)] = (float)(GMLS_MU(SI.idx[i][k], 0) * di * ((double)dsc[k] * IF.v[k]));
+    }
+    float anorm = 0.f;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      float sum = 0.f;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) sum += fabsf(i >= k ? L[Packed<Q>::at(i, k)] : L[Packed<Q>::at(k, i)]);
+      anorm = fmaxf(anorm, sum);
+    }
+    // Cholesky in place; the diagonal keeps 1/L_jj
+    bool ok = valid;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      float dj = L[Packed<Q>::at(j, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) dj -= L[Packed<Q>::at(j, k)] * L[Packed<Q>::at(j, k)];
+      const bool pos = dj > 1e-12f;
+      ok = ok && pos;
+      const float inv = pos ? rsqrtf(dj) : 1.0f;
+      L[Packed<Q>::at(j, j)] = inv;
+#pragma unroll
+      for (int i = j + 1; i < Q; ++i) {
+        float v = L[Packed<Q>::at(i, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) v -= L[Packed<Q>::at(i, k)] * L[Packed<Q>::at(j, k)];
+        L[Packed<Q>::at(i, j)] = v * inv;
+      }
+    }
+    // Hager's 1-norm estimate of A~^-1 (A~ symmetric)
+    float x[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) x[i] = 1.0f / Q;
+    packed_solve<Q>(L, x);
+    float est = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) est += fabsf(x[i]);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) x[i] = x[i] >= 0.f ? 1.f : -1.f;
+    packed_solve<Q>(L, x);
+    int jmax = 0;
+    float zmax = -1.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      if (fabsf(x[i]) > zmax) {
+        zmax = fabsf(x[i]);
+        jmax = i;
+      }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) x[i] = i == jmax ? 1.f : 0.f;
+    packed_solve<Q>(L, x);
+    float est2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) est2 += fabsf(x[i]);
+    const float cond = anorm * fmaxf(est, est2);
+    if (!(cond <= opt.cond_threshold)) ok = false;
+    if (opt.force_fallback) ok = false;
+    const double rho = fmin(0.5, 2.0 * Q * (double)cond * 5.960464477539063e-08);
+
+    int sweeps_max = 0;
+    bool conv_all = true;
+    for (int f = 0; f < F; ++f) {
+      const int kind = rk.kind[f];
+      // y0 = D A~^-1 D lambda
+#pragma unroll
+      for (int i = 0; i < Q; ++i) x[i] = (float)scalar_lambda<DIM, ORDER>(kind, i, ie) * dsc[i];
+      packed_solve<Q>(L, x);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) ybuf[i][lane] = (double)(x[i] * dsc[i]);
+      bool conv = false;
+      int sweeps = 0;
+      for (int it = 0; it < opt.max_sweeps && ok && !conv; ++it) {
+        // r_a = lambda_a - (1/a!) sum_b mu_(a+b) y_b / b!  (FP64), moment-major;
+        // the empty asm keeps the moment loads inside the sweep (hoisting
+        // all of them would hold NM doubles live across the loop)
+        int zoff = 0;
+        asm volatile("" : "+v"(zoff));
+        double yf[Q];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) yf[k] = ybuf[k][lane] * IF.v[k];
+        double acc[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) acc[i] = 0.0;
+#pragma unroll
+        for (int pp = 0; pp < MP.P; ++pp) {
+          const double mv = GMLS_MU(MP.m[pp], zoff);
+          acc[MP.a[pp]] += mv * yf[MP.b[pp]];
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          x[i] = (float)((scalar_lambda<DIM, ORDER>(kind, i, ie) - IF.v[i] * acc[i]) * (double)dsc[i]);
+        packed_solve<Q>(L, x);
+        double dmax = 0.0, ymax = 0.0;
+        bool finite = true;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const double dy = (double)x[i] * (double)dsc[i];
+          const double yn = ybuf[i][lane] + dy;
+          ybuf[i][lane] = yn;
+          finite = finite && isfinite(dy);
+          dmax = fmax(dmax, fabs(dy));
+          ymax = fmax(ymax, fabs(yn));
+        }
+        sweeps = it + 1;
+        if (!finite) break;
+        if (rho * dmax <= opt.refine_tol * ymax) conv = true;
+      }
+      conv_all = conv_all && conv;
+      sweeps_max = sweeps > sweeps_max ? sweeps : sweeps_max;
+      if (valid) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) yout[(loc * F + f) * Q + i] = ybuf[i][lane];
+      }
+    }
+    const bool good = valid && ok && conv_all;
+    const bool not_conv = valid && ok && !conv_all;
+    const bool fell = valid && !ok;
+    if (valid) a.status[t] = good ? GMLS_TARGET_OK : not_conv ? GMLS_TARGET_NOT_CONVERGED : GMLS_TARGET_FALLBACK;
+    if (not_conv || fell) fb_list[atomicAdd(&meta->fb_count, 1)] = t;
+    // statistics, aggregated over the wavefront (one atomic per counter)
+    const int sw = sweeps_max < 15 ? sweeps_max : 15;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const unsigned long long m = __ballot(good && sw == k);
+      if (lane == 0 && m) atomicAdd(&stats->sweep_hist[k], (unsigned long long)__popcll(m));
+    }
+    const unsigned long long mnc = __ballot(not_conv), mfb = __ballot(fell);
+    if (lane == 0 && mnc) atomicAdd(&stats->n_not_converged, (unsigned long long)__popcll(mnc));
+    if (lane == 0 && mfb) atomicAdd(&stats->n_fallback, (unsigned long long)__popcll(mfb));
+    double cd = valid && (double)cond >= 0.0 ? (double)cond : 0.0;  // NaN estimates are skipped
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cd = fmax(cd, __shfl_xor(cd, o));
+    if (lane == 0 && cd > 0.0) atomicMax(&stats->cond_max_bits, (unsigned long long)__double_as_longlong(cd));
+  }
+#undef GMLS_MU
+}
+
+// ---------------------------------------------------------------------------
+// C. weights
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER, int G, int RPL>
+__global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const int *list, int first, int last, int c0,
+                                                     const double *yin) {
+  constexpr int Q = num_mono(DIM, ORDER);
+  constexpr int TPW = 64 / G;
+  __shared__ double ys[TPW][kPipeMaxF * Q];  // the group's target solutions, [f][q]
+  const int lane = lane_id();
+  const int grp = lane / G, lg = lane % G;
+  const int F = a.F;
+  for (int i0 = first + xcd_block() * TPW; i0 < last; i0 += gridDim.x * TPW) {
+    const int i = i0 + grp;
+    const bool valid = i < last;
+    const int t = list[valid ? i : first];
+    const bool good = valid && a.status[t] == GMLS_TARGET_OK;
+    const int64_t loc = (valid ? i : first) - c0;
+    for (int k = lg; k < F * Q; k += G) ys[grp][k] = yin[loc * F * Q + k];
+    const int64_t base = a.row_ptr[t];
+    const int N = (int)(a.row_ptr[t + 1] - base);
+    const double ie = 1.0 / a.eps[t];
+    double xt[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xt[d] = a.targets[(int64_t)t * DIM + d];
+    double xs[RPL][DIM];
+    gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
+    __syncthreads();  // ys written by the group's lanes
+    double *wout = a.weights + (int64_t)F * base;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      double s[DIM];
+      const double w = row_sw<DIM>(xs[r], xt, ie, a.p, true, s);
+      double p[Q];
+      scaled_basis<DIM, ORDER, double>(s, p);
+      const int j = lg + G * r;
+      for (int f = 0; f < F; ++f) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) acc += p[q] * ys[grp][f * Q + q];
+        if (good && j < N) wout[(int64_t)f * N + j] = w * acc;
+      }
+    }
+    __syncthreads();  // ys is rewritten by the next iteration
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host: the pipeline over the bins of one call, in chunks of list slots
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER>
+constexpr bool has_pipe() {
+  return num_mono(DIM, ORDER) <= 20;
+}
+
+template <int DIM, int ORDER, int G, int RPL>
+static void pipe_bin_launch(bool weights, const StencilArgs &a, const int *list, int lo, int hi, int c0,
+                            double *buf, int cus, hipStream_t s) {
+  constexpr int TPW = 64 / G;
+  int nb = (hi - lo + TPW - 1) / TPW;
+  if (nb > cus * 32) nb = cus * 32;
+  nb = xcd_grid(nb);
+  if (weights)
+    k_pipe_weights<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, list, lo, hi, c0, buf);
+  else
+    k_pipe_moments<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, list, lo, hi, c0, buf);
+}
+
+// bins 1..4 occupy list slots [count[0], n) contiguously, in bin order;
+// lanes x rows per lane: bin 1 (<= 64 rows) 8 x 8, bin 2 (<= 128) 16 x 8,
+// bin 3 (<= 192) 32 x 6, bin 4 (<= 256) 32 x 8.
+template <int DIM, int ORDER>
+hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta &hm, BinMeta *meta, int *fb,
+                       Stats *stats, const Options &opt, double *mom, double *y, int64_t chunk, int cus,
+                       hipStream_t s) {
+  const int begin = hm.offset[1];
+  const int end = hm.offset[kNumBins - 1] + hm.count[kNumBins - 1];
+  for (int64_t c0 = begin; c0 < end; c0 += chunk) {
+    const int c1 = (int)(c0 + chunk < end ? c0 + chunk : end);
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) {
+        int nb = (int)((c1 - c0 + 63) / 64);
+        if (nb > cus * 16) nb = cus * 16;
+        nb = xcd_grid(nb);
+        k_pipe_solve<DIM, ORDER><<<nb, 64, 0, s>>>(a, list, (int)c0, c1, (int)c0, mom, y, fb, meta,
+                                                      stats, opt);
+      }
+      const bool wts = pass == 1;
+      for (int b = 1; b < kNumBins; ++b) {
+        const int lo = hm.offset[b] > c0 ? hm.offset[b] : (int)c0;
+        const int hi = hm.offset[b] + hm.count[b] < c1 ? hm.offset[b] + hm.count[b] : c1;
+        if (lo >= hi) continue;
+        double *buf = wts ? y : mom;
+        if (b == 1)
+          pipe_bin_launch<DIM, ORDER, 8, 8>(wts, a, list, lo, hi, (int)c0, buf, cus, s);
+        else if (b == 2)
+          pipe_bin_launch<DIM, ORDER, 16, 8>(wts, a, list, lo, hi, (int)c0, buf, cus, s);
+        else if (b == 3)
+          pipe_bin_launch<DIM, ORDER, 32, 6>(wts, a, list, lo, hi, (int)c0, buf, cus, s);
+        else
+          pipe_bin_launch<DIM, ORDER, 32, 8>(wts, a, list, lo, hi, (int)c0, buf, cus, s);
+      }
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gmls

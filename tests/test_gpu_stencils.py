@@ -133,34 +133,82 @@ def test_end_to_end_gpu_search_then_stencils():
     assert errs.max() <= FP64_TOL
 
 
-@pytest.mark.parametrize("residual", [0, 1], ids=["gram64", "rows"])
-@pytest.mark.parametrize("name", list(CASES))
-def test_mixed_matches_oracle(name, residual):
+def _nmono(dim, deg):
+    from math import comb
+    return comb(deg + dim, dim)
+
+
+def scheme_compiled(name, scheme):
+    """Whether a mixed scheme (1 rows, 2 moment Gram, 3 pipeline) exists for a case."""
+    _, _, basis, order, _, _ = CASES[name]
+    dim = case_data(name)[0].shape[1]
+    if scheme == 1:
+        return True
+    if scheme == 2:
+        return _nmono(dim, 2 * order) <= 96
+    return basis == "scalar" and _nmono(dim, order) <= 20
+
+
+def run_mixed(name, scheme, chunk=0):
     G = require_gpu()
-    pts, rp, col, eps, w, st, F, C = case_data(name)
     c = ctx()
-    c.set_option(G.OPT_MIXED_RESIDUAL, residual)
+    c.set_option(G.OPT_MIXED_SCHEME, scheme)
+    c.set_option(G.OPT_PIPE_CHUNK, chunk)
     try:
-        gw, gst, rep = run_gpu(name, G.PREC_MIXED)
+        return run_gpu(name, G.PREC_MIXED)
     finally:
-        c.set_option(G.OPT_MIXED_RESIDUAL, 0)
-    # fallback targets keep a fallback status; everything else is OK
+        c.set_option(G.OPT_MIXED_SCHEME, 0)
+        c.set_option(G.OPT_PIPE_CHUNK, 0)
+
+
+def check_mixed(name, gw, gst, rep):
+    pts, rp, col, eps, w, st, F, C = case_data(name)
+    # rank-deficient targets agree; everything else is OK or was recomputed
     assert np.array_equal(gst == 1, st == 1)
+    assert np.isin(gst, [0, 1, 2, 3]).all()
     zero = (F - 1,) if CASES[name][2] == "divfree" and CASES[name][4] & 8 else ()
     errs = row_errors(gw, w, rp, F, C, zero_rows=zero)
     flush(f"  mixed max rel err {errs.max():.3e}  p99 {np.percentile(errs, 99):.3e}  "
           f"fallback {rep['n_fallback']} not-conv {rep['n_not_converged']} sweeps {rep['sweep_hist'][:6]} "
           f"cond_max {rep['cond_max']:.2e}")
     assert errs.max() <= MIXED_TOL
+    # every target not rank deficient is counted once: converged, fallback or not converged
+    n_live = int((st != 1).sum())
+    assert sum(rep["sweep_hist"]) + rep["n_fallback"] + rep["n_not_converged"] == n_live
 
 
-def test_mixed_forced_fallback_is_fp64_exact():
+@pytest.mark.parametrize("scheme", [1, 2, 3], ids=["rows", "gram", "pipe"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_matches_oracle(name, scheme):
+    G = require_gpu()
+    if not scheme_compiled(name, scheme):
+        with pytest.raises(G.GmlsError) as e:
+            run_mixed(name, scheme)
+        assert e.value.status == 5
+        return
+    check_mixed(name, *run_mixed(name, scheme))
+
+
+def test_mixed_auto_scheme():
+    require_gpu()
+    check_mixed("3d_m3_radius", *run_mixed("3d_m3_radius", 0))
+
+
+@pytest.mark.parametrize("chunk", [64, 1000, 4093])
+def test_mixed_pipe_chunks(chunk):
+    """Chunked pipeline: chunk boundaries inside and across row-count bins."""
+    require_gpu()
+    check_mixed("3d_m3_radius", *run_mixed("3d_m3_radius", 3, chunk))
+
+
+@pytest.mark.parametrize("scheme", [1, 2, 3], ids=["rows", "gram", "pipe"])
+def test_mixed_forced_fallback_is_fp64_exact(scheme):
     G = require_gpu()
     c = ctx()
     c.set_option(G.OPT_FORCE_FALLBACK, 1)
     try:
         pts, rp, col, eps, w, st, F, C = case_data("3d_m3_radius")
-        gw, gst, rep = run_gpu("3d_m3_radius", G.PREC_MIXED)
+        gw, gst, rep = run_mixed("3d_m3_radius", scheme)
     finally:
         c.set_option(G.OPT_FORCE_FALLBACK, 0)
     assert (gst == 2).all() and rep["n_fallback"] == len(st)
@@ -169,9 +217,9 @@ def test_mixed_forced_fallback_is_fp64_exact():
     assert errs.max() <= FP64_TOL
 
 
-def test_mixed_near_coplanar_triggers_fallback():
+@pytest.mark.parametrize("scheme", [1, 2, 3], ids=["rows", "gram", "pipe"])
+def test_mixed_near_coplanar_triggers_fallback(scheme):
     G = require_gpu()
-    g = W.rng(31)
     n = 4000
     pts = W.jittered_grid(n, 3, 13)
     # tilted near-plane: z - 0.3x - 0.2y is tiny, so the linear monomials are
@@ -180,9 +228,14 @@ def test_mixed_near_coplanar_triggers_fallback():
     rp, col, eps = oracle.knn(pts, pts, 40, 1.5)
     w, st, F, C = oracle.stencils(pts, pts, 2, "scalar", 4, 4, eps, rp, col)
     s = dev(pts)
-    flush("near-coplanar mixed")
-    gw, gst, rep = G.gmls_stencils(ctx(), s, s, 2, G.BASIS_SCALAR, 4, 4, dev(eps), dev(rp), dev(col),
-                                   prec=G.PREC_MIXED, report=True)
+    flush(f"near-coplanar mixed scheme {scheme}")
+    c = ctx()
+    c.set_option(G.OPT_MIXED_SCHEME, scheme)
+    try:
+        gw, gst, rep = G.gmls_stencils(c, s, s, 2, G.BASIS_SCALAR, 4, 4, dev(eps), dev(rp), dev(col),
+                                       prec=G.PREC_MIXED, report=True)
+    finally:
+        c.set_option(G.OPT_MIXED_SCHEME, 0)
     gw, gst = host(gw), host(gst)
     flush(f"  fallback {rep['n_fallback']} not-conv {rep['n_not_converged']} cond_max {rep['cond_max']:.2e}")
     assert rep["n_fallback"] + rep["n_not_converged"] > 0
