@@ -32,6 +32,9 @@ import workloads as W  # noqa: E402
 # N neighbours): symmetric Gram N*Q*(Q+1), Cholesky Q^3/3, two triangular
 # solves per row 2*F*Q^2, weights 2*N*Q*F.  Bytes: the CSR row (4N), the
 # weights (8*F*N) and per-target scalars (row_ptr, eps, coordinates: 64).
+# The moment form of the Gram does N*2*NM flops (NM = monomials of degree
+# <= 2m) instead of N*Q*(Q+1); the conventional count above is the one
+# credited.
 def alg_flops(nnz, n_tgt, Q, F):
     return nnz * (Q * (Q + 1) + 2 * Q * F) + n_tgt * (Q ** 3 / 3.0 + 2 * F * Q * Q)
 
@@ -46,6 +49,52 @@ PEAK = {  # MI355X published peaks
     "fp32_TFs": 157.3,
 }
 
+# Sources of the stencil-phase kernels; a traffic figure measured with
+# hardware counters is reported only while these are unchanged.
+STENCIL_SOURCES = ["stencil_pipe.hpp", "stencil_mixed64.hpp", "stencil_mixed.hpp", "stencil_fp64.hpp",
+                   "stencil_bins.hip", "basis.hpp", "common.hpp", "api.cpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencils_c4.txt")
+
+
+def stencil_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STENCIL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2104_14447_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(prec_name):
+    """HBM bytes per step of the stencil phase from the committed counter
+    summary, if it was taken on the current kernel sources and precision."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != stencil_source_hash() or kv.get("precision") != prec_name:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_step"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe():
+    """A plain device-to-device copy of known size, for scaling HBM counters."""
+    import torch
+    n = 1 << 27  # 1 GiB of float64
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 8 * n, "copy_probe_bytes_written": 8 * n, "launches": 3}))
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -55,16 +104,20 @@ def parse():
     ap.add_argument("--prec", choices=["mixed", "fp64", "auto"], default="auto")
     ap.add_argument("--n", type=int, default=2_000_000, help="points (default: the 2M-point workload)")
     ap.add_argument("--sample", type=int, default=256, help="targets checked against the oracle")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget of the oracle timing leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle timing leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", type=int, default=0,
                     help="mixed scheme: 0 auto, 1 fused/rows residual, 2 fused/moment Gram, 3 pipeline")
     ap.add_argument("--chunk", type=int, default=0, help="pipeline chunk (targets; 0 = whole batch)")
+    ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy (counter scaling) and exit")
     return ap.parse_args()
 
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not a launched path)"}))
@@ -113,8 +166,12 @@ def main():
     wts = torch.empty(F * C * nnz, dtype=torch.float64, device=dev)
     status = torch.empty(n, dtype=torch.uint8, device=dev)
 
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
     def step(report=False):
+        ev0.record()
         rp_, col_, eps_ = G.gmls_neighbors(ctx, x, x, G.SEARCH_RADIUS, radius=r0, k_min=k_min, col=col_buf)
+        ev1.record()
         w_, st_, rep_ = G.gmls_stencils(ctx, x, x, order, G.BASIS_SCALAR, mask, p, eps_, rp_, col_, prec=prec,
                                         weights=wts, status=status, report=report)
         return rp_, col_, eps_, w_, st_, rep_
@@ -123,11 +180,12 @@ def main():
         step()
         print(f"# warmup step {i} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    stencil_ms = []
+    stencil_ms, search_ms = [], []
     t_start = time.perf_counter()
     for i in range(args.steps):
         out = step(report=True)
         stencil_ms.append(out[5]["t_stencil_ms"] + out[5]["t_fallback_ms"])
+        search_ms.append(ev0.elapsed_time(ev1))
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_per_step = 1e3 * t_total / args.steps
@@ -161,21 +219,28 @@ def main():
     print(f"# parity: search {'ok' if search_ok else 'MISMATCH'}; max rel err {max_err:.3e} (gate {tol:g})",
           file=sys.stderr, flush=True)
 
-    # ---- roofline of the dominant kernel (stencil kernels, live HIP events) ----
+    # ---- roofline of the stencil phase (its kernels timed by HIP events on
+    # the library's stream, inside the timed steps) ----
     flops = alg_flops(nnz, n, Q, F)
     t_sten = float(np.mean(stencil_ms)) * 1e-3
     achieved_tf = flops / t_sten / 1e12
     peak_tf = PEAK["fp32_TFs"] if prec_name == "mixed" else PEAK["fp64_TFs"]
+    traffic = measured_traffic(prec_name)
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": peak_tf, "unit": "TFLOP/s",
-                "frac": round(achieved_tf / peak_tf, 4), "traffic": None,
-                "kernel": "stencil (all row-count bins)", "alg_flops_per_step": flops,
-                "alg_bytes_per_step": alg_bytes(nnz, n, F), "kernel_ms": round(t_sten * 1e3, 4)}
+                "frac": round(achieved_tf / peak_tf, 4), "traffic": traffic,
+                "kernel": "stencil phase: moments, solve and weights kernels of every row-count bin + FP64 "
+                          "fallback (one launch sequence per step)",
+                "alg_flops_per_step": flops, "alg_bytes_per_step": alg_bytes(nnz, n, F),
+                "kernel_ms": round(t_sten * 1e3, 4),
+                "frac_of_fp64_peak": round(achieved_tf / PEAK["fp64_TFs"], 4),
+                "search_ms": round(float(np.mean(search_ms)), 4)}
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ----
     cpu = None
     if not args.no_cpu_baseline:
-        threads = os.cpu_count() or 1
-        m = 2000
+        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
+        # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds
+        m = max(1000, n // 64)
         t1 = time.perf_counter()
         sub = np.arange(m)
         a_rp, a_col, a_eps = oracle.radius(pts, pts[sub], r0, k_min, use_grid=True, nthreads=threads)
@@ -187,9 +252,10 @@ def main():
         a_rp, a_col, a_eps = oracle.radius(pts, pts[sub], r0, k_min, use_grid=True, nthreads=threads)
         oracle.stencils(pts, pts[sub], order, "scalar", mask, p, a_eps, a_rp, a_col, nthreads=threads)
         dt = time.perf_counter() - t1
+        what = "all" if m2 == n else f"the first {m2} of the"
         cpu = {"value": round(m2 / dt, 1), "unit": "stencils/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {m2} targets of the same 2M-point cloud: bucket-grid radius search + "
-                         f"Householder-QR stencils, {dt:.1f}s wall"}
+               "sample": f"{what} {n} targets of the same point cloud: bucket-grid radius search + "
+                         f"Householder-QR stencils in FP64, {dt:.1f} s wall on {threads} threads"}
 
     value = n / (ms_per_step * 1e-3)
     line = {
