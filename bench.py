@@ -28,19 +28,50 @@ sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
 
-# Algorithmic work per stencil (scalar basis, Q functions, F functional rows,
-# N neighbours): symmetric Gram N*Q*(Q+1), Cholesky Q^3/3, two triangular
-# solves per row 2*F*Q^2, weights 2*N*Q*F.  Bytes: the CSR row (4N), the
-# weights (8*F*N) and per-target scalars (row_ptr, eps, coordinates: 64).
-# The moment form of the Gram does N*2*NM flops (NM = monomials of degree
-# <= 2m) instead of N*Q*(Q+1); the conventional count above is the one
-# credited.
-def alg_flops(nnz, n_tgt, Q, F):
-    return nnz * (Q * (Q + 1) + 2 * Q * F) + n_tgt * (Q ** 3 / 3.0 + 2 * F * Q * Q)
+# Algorithmic work per stencil, the conventional count (scalar basis with Q
+# functions, F functional rows, N neighbours): symmetric Gram N*Q*(Q+1),
+# Cholesky Q^3/3, two triangular solves per row 2*F*Q^2, weights 2*N*Q*F.
+# Bytes: the CSR row (4N), the weights (8*F*C*N) and per-target scalars
+# (row_ptr, eps, coordinates: 64).  The moment form of the Gram does N*2*NM
+# flops (NM = monomials of degree <= 2m) instead of N*Q*(Q+1); the
+# conventional count is the one credited.
+def _binom(n, k):
+    from math import comb
+    return comb(n, k)
 
 
-def alg_bytes(nnz, n_tgt, F):
-    return nnz * (4 + 8 * F) + 64 * n_tgt
+def alg_flops_workload(nnz, n_tgt, dim, bases):
+    """Conventional count over the bases of a configuration: the scalar Gram
+    N*Qs*(Qs+1) once per target (shared by bases on one neighbour list), then
+    per basis Q^3/3 + 2FQ^2 and 2*R*Qs*F for the weights (R = N scalar, d*N
+    vector); the vector basis adds the congruence 4*Qd^2 and 2*F*Qd*d*Qs."""
+    qs_max = max(_binom(b["order"] + dim, dim) for b in bases)
+    total = nnz * qs_max * (qs_max + 1)
+    for b in bases:
+        qs = _binom(b["order"] + dim, dim)
+        Q, F = b["Q"], b["F"]
+        total += n_tgt * (Q ** 3 / 3.0 + 2 * F * Q * Q)
+        if b["name"] == "scalar":
+            total += 2 * nnz * qs * F
+        else:
+            total += 2 * dim * nnz * qs * F + n_tgt * (4 * Q * Q + 2 * F * Q * dim * qs)
+    return total
+
+
+def alg_bytes_workload(nnz, n_tgt, dim, bases):
+    return 4 * nnz + 64 * n_tgt + sum(8 * b["F"] * b["C"] * nnz for b in bases)
+
+
+DEFAULT_WORKLOAD = "c4_3d_m3_uneven"
+DESCRIBE = {
+    "c1_2d_m2": "1000 jittered-grid points in 2D, kNN 12, scalar order 2, gradient + Laplacian",
+    "c2_2d_m4": "100k jittered-grid points in 2D, kNN 40, scalar order 4, value + gradient + Laplacian",
+    "c3_3d_divfree_m2": "1M jittered-grid points in 3D, kNN 60, div-free order 2 vector Laplacian + "
+                        "scalar order 2 gradient",
+    "c4_3d_m3_uneven": "2M points, density 1+3x, radius search (k_min 30), scalar order 3, Laplacian",
+    "c5_3d_m4": "500k jittered-grid points in 3D, kNN 170, p=6, scalar order 4 gradient + Laplacian and "
+                "div-free order 4 vector Laplacian + divergence",
+}
 
 
 PEAK = {  # MI355X published peaks
@@ -102,7 +133,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", choices=["mixed", "fp64", "auto"], default="auto")
-    ap.add_argument("--n", type=int, default=2_000_000, help="points (default: the 2M-point workload)")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=list(W.WORKLOADS),
+                    help="configuration (default: the 2M-point uneven radius workload)")
+    ap.add_argument("--n", type=int, default=0, help="points (default: the configuration's size)")
     ap.add_argument("--sample", type=int, default=256, help="targets checked against the oracle")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle timing leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -135,46 +168,55 @@ def main():
     ctx.set_option(G.OPT_MIXED_SCHEME, args.scheme)
     ctx.set_option(G.OPT_PIPE_CHUNK, args.chunk)
 
-    wl = W.WORKLOADS["c4_3d_m3_uneven"]
-    n = args.n
-    order, mask, p = 3, G.F_LAPLACIAN, wl["p"]
-    r0 = W.radius_for_mean_count(n)
-    k_min = wl["search"][2]
+    name = args.workload
+    wl = W.WORKLOADS[name]
+    dim, p = wl["dim"], wl["p"]
+    n = args.n if args.n else wl["n"]
+    knn = wl["search"][0] == "knn"
+    if knn:
+        k, mult = wl["search"][1], wl["search"][2]
+        spec = dict(mode=G.SEARCH_KNN, k=k, eps_mult=mult)
+    else:
+        r0 = wl["search"][1] if n == wl["n"] else W.radius_for_mean_count(n)
+        k_min = wl["search"][2]
+        spec = dict(mode=G.SEARCH_RADIUS, radius=r0, k_min=k_min)
     t0 = time.time()
-    pts = W.density_ramp(n, wl["seed"])
+    pts = W.make_points(name, n=n)
     print(f"# generated {n} points in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     x = torch.from_numpy(pts).to(dev)
-    F, C, Q = G.gmls_stencil_shape(3, order, G.BASIS_SCALAR, mask)
+    bases = []
+    for basis, order, mask in wl["bases"]:
+        b = G.BASIS_SCALAR if basis == "scalar" else G.BASIS_DIVFREE
+        F, C, Q = G.gmls_stencil_shape(dim, order, b, mask)
+        bases.append(dict(name=basis, b=b, order=order, mask=mask, F=F, C=C, Q=Q))
 
     precs = {"mixed": G.PREC_MIXED, "fp64": G.PREC_FP64}
     if args.prec == "auto":
-        try:
-            rp, col, eps = G.gmls_neighbors(ctx, x[:4096], x[:4096], G.SEARCH_RADIUS, radius=0.1, k_min=k_min)
-            G.gmls_stencils(ctx, x[:4096], x[:4096], order, G.BASIS_SCALAR, mask, p, eps, rp, col,
-                            prec=G.PREC_MIXED)
-            prec_name = "mixed"
-        except G.GmlsError:
-            prec_name = "fp64"
+        prec_name = "mixed" if "mixed" in wl["modes"] else "fp64"
     else:
         prec_name = args.prec
     prec = precs[prec_name]
 
     # buffers reused across steps (no allocation inside the timed region)
-    rp, col, eps = G.gmls_neighbors(ctx, x, x, G.SEARCH_RADIUS, radius=r0, k_min=k_min)
+    rp, col, eps = G.gmls_neighbors(ctx, x, x, **spec)
     nnz = col.numel()
     col_buf = torch.empty(int(nnz * 1.05) + 1024, dtype=torch.int32, device=dev)
-    wts = torch.empty(F * C * nnz, dtype=torch.float64, device=dev)
-    status = torch.empty(n, dtype=torch.uint8, device=dev)
+    for bs in bases:
+        bs["w"] = torch.empty(bs["F"] * bs["C"] * nnz, dtype=torch.float64, device=dev)
+        bs["st"] = torch.empty(n, dtype=torch.uint8, device=dev)
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def step(report=False):
         ev0.record()
-        rp_, col_, eps_ = G.gmls_neighbors(ctx, x, x, G.SEARCH_RADIUS, radius=r0, k_min=k_min, col=col_buf)
+        rp_, col_, eps_ = G.gmls_neighbors(ctx, x, x, col=col_buf, **spec)
         ev1.record()
-        w_, st_, rep_ = G.gmls_stencils(ctx, x, x, order, G.BASIS_SCALAR, mask, p, eps_, rp_, col_, prec=prec,
-                                        weights=wts, status=status, report=report)
-        return rp_, col_, eps_, w_, st_, rep_
+        reps = []
+        for bs in bases:
+            _, _, r_ = G.gmls_stencils(ctx, x, x, bs["order"], bs["b"], bs["mask"], p, eps_, rp_, col_, prec=prec,
+                                       weights=bs["w"], status=bs["st"], report=report)
+            reps.append(r_)
+        return rp_, col_, eps_, reps
 
     for i in range(args.warmup):
         step()
@@ -184,53 +226,70 @@ def main():
     t_start = time.perf_counter()
     for i in range(args.steps):
         out = step(report=True)
-        stencil_ms.append(out[5]["t_stencil_ms"] + out[5]["t_fallback_ms"])
+        stencil_ms.append(sum(r["t_stencil_ms"] + r["t_fallback_ms"] for r in out[3]))
         search_ms.append(ev0.elapsed_time(ev1))
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     ms_per_step = 1e3 * t_total / args.steps
-    rp_t, col_t, eps_t, w_t, st_t, rep = out
+    rp_t, col_t, eps_t, reps = out
     print(f"# timed {args.steps} steps: {ms_per_step:.3f} ms/step; stencil kernels "
-          f"{np.mean(stencil_ms):.3f} ms; report {rep}", file=sys.stderr, flush=True)
+          f"{np.mean(stencil_ms):.3f} ms; search {np.mean(search_ms):.3f} ms; reports {reps}",
+          file=sys.stderr, flush=True)
 
     # ---- parity gate on sampled targets (same process, same outputs) ----
     import oracle
 
     rph = rp_t.cpu().numpy()
-    colh = col_t.cpu().numpy()
     epsh = eps_t.cpu().numpy()
-    wh = w_t.cpu().numpy()
-    sth = st_t.cpu().numpy()
     g = W.rng(424242)
     sample = np.sort(g.choice(n, size=min(args.sample, n), replace=False))
-    orp, ocol, oeps = oracle.radius(pts, pts[sample], r0, k_min, use_grid=False)
-    search_ok = all(np.array_equal(colh[rph[t]:rph[t + 1]], ocol[orp[q]:orp[q + 1]])
-                    for q, t in enumerate(sample)) and np.array_equal(epsh[sample], oeps)
-    srp, scol, seps = oracle.subset_csr(rph, colh, epsh, sample)
-    ow, ost, _, _ = oracle.stencils(pts, pts[sample], order, "scalar", mask, p, seps, srp, scol)
+    idx = torch.from_numpy(np.concatenate([np.arange(rph[t], rph[t + 1]) for t in sample])).cuda()
+    scol = col_t[idx].cpu().numpy()
+    srp = np.zeros(len(sample) + 1, dtype=np.int64)
+    srp[1:] = np.cumsum(np.diff(rph)[sample])
+    if knn:
+        orp, ocol, oeps = oracle.knn(pts, pts[sample], k, mult)
+    else:
+        orp, ocol, oeps = oracle.radius(pts, pts[sample], r0, k_min)
+    search_ok = np.array_equal(srp, orp) and np.array_equal(scol, ocol) and np.array_equal(epsh[sample], oeps)
+    seps = epsh[sample]
     max_err = 0.0
-    for q, t in enumerate(sample):
-        a = wh[F * C * rph[t]:F * C * rph[t + 1]].reshape(F, -1)
-        b = ow[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
-        e = np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
-        max_err = max(max_err, float(e.max()))
+    status_ok = True
+    for bs in bases:
+        F, C = bs["F"], bs["C"]
+        widx = torch.from_numpy(np.concatenate([np.arange(F * C * rph[t], F * C * rph[t + 1])
+                                                for t in sample])).cuda()
+        wh = bs["w"][widx].cpu().numpy()
+        sth = bs["st"].cpu().numpy()[sample]
+        ow, ost, _, _ = oracle.stencils(pts, pts[sample], bs["order"], bs["name"], bs["mask"], p, seps, srp, scol)
+        status_ok = status_ok and np.array_equal(sth == 1, ost == 1)
+        zero = F - 1 if bs["name"] == "divfree" and bs["mask"] & G.F_DIV else -1
+        for q in range(len(sample)):
+            if ost[q] == 1:
+                continue
+            a = wh[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
+            b_ = ow[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
+            den = np.linalg.norm(b_, axis=1)
+            if zero >= 0:
+                den[zero] = den[0]
+            max_err = max(max_err, float((np.linalg.norm(a - b_, axis=1) / den).max()))
     tol = 1e-8 if prec_name == "mixed" else 1e-10
-    gate = bool(search_ok and max_err <= tol and np.array_equal(sth[sample], ost))
+    gate = bool(search_ok and status_ok and max_err <= tol)
     print(f"# parity: search {'ok' if search_ok else 'MISMATCH'}; max rel err {max_err:.3e} (gate {tol:g})",
           file=sys.stderr, flush=True)
 
     # ---- roofline of the stencil phase (its kernels timed by HIP events on
     # the library's stream, inside the timed steps) ----
-    flops = alg_flops(nnz, n, Q, F)
+    flops = alg_flops_workload(nnz, n, dim, bases)
     t_sten = float(np.mean(stencil_ms)) * 1e-3
     achieved_tf = flops / t_sten / 1e12
     peak_tf = PEAK["fp32_TFs"] if prec_name == "mixed" else PEAK["fp64_TFs"]
-    traffic = measured_traffic(prec_name)
+    traffic = measured_traffic(prec_name) if name == DEFAULT_WORKLOAD and n == wl["n"] else None
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": peak_tf, "unit": "TFLOP/s",
                 "frac": round(achieved_tf / peak_tf, 4), "traffic": traffic,
                 "kernel": "stencil phase: moments, solve and weights kernels of every row-count bin + FP64 "
-                          "fallback (one launch sequence per step)",
-                "alg_flops_per_step": flops, "alg_bytes_per_step": alg_bytes(nnz, n, F),
+                          "fallback (one launch sequence per basis per step)",
+                "alg_flops_per_step": flops, "alg_bytes_per_step": alg_bytes_workload(nnz, n, dim, bases),
                 "kernel_ms": round(t_sten * 1e3, 4),
                 "frac_of_fp64_peak": round(achieved_tf / PEAK["fp64_TFs"], 4),
                 "search_ms": round(float(np.mean(search_ms)), 4)}
@@ -239,22 +298,29 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
+
+        def oracle_run(m):
+            sub = np.arange(m)
+            if knn:
+                a_rp, a_col, a_eps = oracle.knn(pts, pts[sub], k, mult, use_grid=True, nthreads=threads)
+            else:
+                a_rp, a_col, a_eps = oracle.radius(pts, pts[sub], r0, k_min, use_grid=True, nthreads=threads)
+            for bs in bases:
+                oracle.stencils(pts, pts[sub], bs["order"], bs["name"], bs["mask"], p, a_eps, a_rp, a_col,
+                                nthreads=threads)
+
         # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds
         m = max(1000, n // 64)
         t1 = time.perf_counter()
-        sub = np.arange(m)
-        a_rp, a_col, a_eps = oracle.radius(pts, pts[sub], r0, k_min, use_grid=True, nthreads=threads)
-        oracle.stencils(pts, pts[sub], order, "scalar", mask, p, a_eps, a_rp, a_col, nthreads=threads)
+        oracle_run(m)
         dt = time.perf_counter() - t1
         m2 = int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
-        sub = np.arange(m2)
         t1 = time.perf_counter()
-        a_rp, a_col, a_eps = oracle.radius(pts, pts[sub], r0, k_min, use_grid=True, nthreads=threads)
-        oracle.stencils(pts, pts[sub], order, "scalar", mask, p, a_eps, a_rp, a_col, nthreads=threads)
+        oracle_run(m2)
         dt = time.perf_counter() - t1
         what = "all" if m2 == n else f"the first {m2} of the"
         cpu = {"value": round(m2 / dt, 1), "unit": "stencils/s", "cores": threads, "kind": "oracle",
-               "sample": f"{what} {n} targets of the same point cloud: bucket-grid radius search + "
+               "sample": f"{what} {n} targets of the same point cloud: bucket-grid neighbour search + "
                          f"Householder-QR stencils in FP64, {dt:.1f} s wall on {threads} threads"}
 
     value = n / (ms_per_step * 1e-3)
@@ -271,13 +337,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if prec_name == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": "c4_3d_m3_uneven: 2M points, density 1+3x, radius search (k_min 30), "
-                               "scalar order 3, Laplacian",
-                   "n_points": n, "nnz": int(nnz), "precision": prec_name, "radius": r0,
+        "config": {"workload": f"{name}: {DESCRIBE[name]}",
+                   "n_points": n, "nnz": int(nnz), "precision": prec_name,
+                   "search": wl["search"][0] + (f" k={k}" if knn else f" r={r0:.6f} k_min={k_min}"),
                    "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
                                     "pipeline"][args.scheme],
                    "parity_gate": gate, "parity_max_rel_err": max_err, "parity_sample": int(len(sample)),
-                   "fallbacks": int(rep["n_fallback"]), "rank_deficient": int(rep["n_rank_deficient"])},
+                   "fallbacks": int(sum(r["n_fallback"] + r["n_not_converged"] for r in reps)),
+                   "rank_deficient": int(sum(r["n_rank_deficient"] for r in reps))},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -153,9 +153,10 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value);
  *   dim      1, 2 or 3
  *   spec     host pointer to the search rule
  *   row_ptr  out: int64 [n_tgt + 1] CSR offsets (row_ptr[0] = 0)
- *   col      out: int32 [col_capacity] source indices; each row is sorted by
- *            (squared distance, index); squared distances are evaluated as
- *            (dx*dx + dy*dy) + dz*dz in IEEE double without fused multiply-add
+ *   col      out: int32 [col_capacity] source indices.  kNN rows are sorted by
+ *            (squared distance, index); radius rows (sets) by index.  Squared
+ *            distances are evaluated as (dx*dx + dy*dy) + dz*dz in IEEE double
+ *            without fused multiply-add
  *   eps      out: [n_tgt] support radius of every target
  *   nnz_host host out: total neighbour count
  * kNN rows hold exactly k entries.  Radius rows hold between k_min and

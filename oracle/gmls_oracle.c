@@ -108,6 +108,11 @@ static int cand_cmp(const void *pa, const void *pb) {
   return 0;
 }
 
+static int index_cmp(const void *pa, const void *pb) {
+  int32_t a = *(const int32_t *)pa, b = *(const int32_t *)pb;
+  return a < b ? -1 : (a > b ? 1 : 0);
+}
+
 /* squared distance, source minus target, summed x then y then z */
 static inline double dist2(const double *src, const double *tgt, int dim) {
   double dx = src[0] - tgt[0];
@@ -385,9 +390,9 @@ int gmls_oracle_knn(const double *src, int64_t n_src, const double *tgt, int64_t
 
 /* fixed-radius search floored to k_min: the neighbours of t are every source
  * with d^2 < r0*r0 (eps = r0); if there are fewer than k_min, they are the
- * k_min nearest and eps = (d_kmin + d_{kmin+1}) / 2.  Rows are sorted by
- * (d2, j).  Pass 1 (col == NULL) writes counts[t]; pass 2 fills
- * col[row_ptr[t] ...] and eps[t]. */
+ * k_min nearest by (d2, j) and eps = (d_kmin + d_{kmin+1}) / 2.  A radius row
+ * is a set; it is written in ascending source index.  Pass 1 (col == NULL)
+ * writes counts[t]; pass 2 fills col[row_ptr[t] ...] and eps[t]. */
 typedef struct {
   cand_t *a;
   int64_t n, cap;
@@ -465,8 +470,8 @@ static int radius_impl(const double *src, int64_t n_src, const double *tgt, int6
         }
         if (l.n >= k_min) {
           if (col) {
-            qsort(lst, (size_t)l.n, sizeof(cand_t), cand_cmp);
             for (int64_t q = 0; q < l.n; ++q) col[row_ptr[t] + q] = lst[q].j;
+            qsort(col + row_ptr[t], (size_t)l.n, sizeof(int32_t), index_cmp);
             eps[t] = r0;
           } else
             counts[t] = l.n;
@@ -477,6 +482,7 @@ static int radius_impl(const double *src, int64_t n_src, const double *tgt, int6
             else
               knn_one_brute(src, n_src, dim, x, k_min + 1, buf, out);
             for (int q = 0; q < k_min; ++q) col[row_ptr[t] + q] = out[q].j;
+            qsort(col + row_ptr[t], (size_t)k_min, sizeof(int32_t), index_cmp);
             eps[t] = 0.5 * (sqrt(out[k_min - 1].d2) + sqrt(out[k_min].d2));
           } else
             counts[t] = k_min;

@@ -280,9 +280,11 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
     const int64_t chunk = std::max<int64_t>(1, opt.pipe_chunk > 0 ? std::min<int64_t>(opt.pipe_chunk, n_work) : n_work);
     double *mom = (double *)ctx->ws(WS_PIPE_MOM, sizeof(double) * (size_t)pipe_num_moments(dim, order) * chunk);
     double *yb = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)F * Q * chunk);
-    if (!mom || !yb) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+    void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * (size_t)chunk);
+    if (!mom || !yb || !rec) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
     if (n_work > 0)
-      GMLS_HIP(launch_mixed_pipe(dim, order, basis, a, list, hm, meta, fb, stats, opt, mom, yb, chunk, cus, s));
+      GMLS_HIP(
+          launch_mixed_pipe(dim, order, basis, a, list, hm, meta, fb, stats, opt, mom, yb, rec, chunk, cus, s));
   } else {
     for (int b = 1; b < kNumBins; ++b) {
       if (hm.count[b] == 0) continue;

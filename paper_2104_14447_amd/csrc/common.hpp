@@ -105,6 +105,8 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
 
 __device__ __forceinline__ int readfirstlane_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+__device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
 // Wave-uniform copies (taken from the first active lane).  Every value that
 // decides a branch or a loop exit of a whole wavefront goes through one of
 // these, so that the compiler emits scalar branches: a branch it believes to

@@ -25,6 +25,7 @@ enum Slot {
   WS_TGT_START,
   WS_TGT_ORDER,
   WS_ROW_COUNT,
+  WS_DEFER,
   WS_SCAN_TMP,
   WS_FLAGS,
   WS_BIN_META,
@@ -35,6 +36,7 @@ enum Slot {
   WS_BIN_TEMP,
   WS_PIPE_MOM,
   WS_PIPE_Y,
+  WS_PIPE_REC,
   WS_NUM_SLOTS
 };
 
@@ -131,9 +133,11 @@ hipError_t launch_qr_fallback(int dim, int order, int basis, const StencilArgs &
 hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,
                             BinMeta *meta, int *fb_list, Stats *stats, const Options &opt, int count, int cus,
                             hipStream_t s);
+// bytes of the pipeline's per-target record
+constexpr size_t kPipeRecBytes = 64;
 hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta &hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt,
-                             double *mom, double *y, int64_t chunk, int cus, hipStream_t s);
+                             double *mom, double *y, void *rec, int64_t chunk, int cus, hipStream_t s);
 bool qr_supported(int dim, int order, int basis);
 bool mixed_supported(int dim, int order, int basis);
 // the scheme a request resolves to (MIXED_AUTO picks the fastest compiled

@@ -15,11 +15,14 @@
 //    until the k-th distance is provably smaller than the distance to every
 //    unscanned cell.
 //  - radius: every source with d^2 < r^2 (count pass, scan, fill pass); a
-//    target with fewer than k_min falls back to its k_min nearest.  Rows of
-//    up to 256 entries are compacted into a small LDS buffer and sorted in
-//    registers by a wave-wide bitonic network; longer rows take a second
-//    kernel with a large LDS buffer.
-// Every output row is sorted by (squared distance, index).
+//    target with fewer than k_min falls back to its k_min nearest.  A
+//    workgroup stages the sources around one target cell in LDS and shares
+//    them among the cell's targets; rows of up to 256 entries are compacted
+//    into a small LDS buffer and sorted in registers by a wave-wide bitonic
+//    network; cells with crowded blocks, floored targets and longer rows take
+//    per-target kernels.
+// kNN rows are sorted by (squared distance, index); radius rows, which are
+// sets, by index.
 #include <float.h>
 #include <limits.h>
 
@@ -417,51 +420,24 @@ __device__ __forceinline__ int radius_blocks(const GridParams &g, double r) {
   return R < 1 ? 1 : R;
 }
 
+// Cells and rows of the (2R+1)^DIM block around the cell of x.
 template <int DIM>
-__global__ __launch_bounds__(64) void k_radius_count(const GridParams *gp, const SPoint *pts, const int *cell_start,
-                                                     const double *targets, const int *order, int64_t n_tgt,
-                                                     double r0, int k_min, int64_t *counts, int *flags) {
-  const int64_t w = blockIdx.x;
-  if (w >= n_tgt) return;
-  const GridParams g = *gp;
-  const int t = readfirstlane_i(order[w]);
-  const int lane = lane_id();
-  double x[3] = {0, 0, 0};
-  for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
-  const double r2 = r0 * r0;
-  const int R = radius_blocks(g, r0);
-  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+__device__ __forceinline__ void radius_block(const GridParams &g, const double *x, int R, int *lo, int *hi) {
+  for (int d = 0; d < 3; ++d) lo[d] = hi[d] = 0;
   for (int d = 0; d < DIM; ++d) {
     const int c = cell_coord(g, x[d], d);
     lo[d] = max(c - R, 0);
     hi[d] = min(c + R, g.nc[d] - 1);
   }
-  int count = 0;
-  for (int cz = lo[2]; cz <= hi[2]; ++cz)
-    for (int cy = lo[1]; cy <= hi[1]; ++cy) {
-      const int row = g.nc[0] * (cy + g.nc[1] * cz);
-      const int beg = readfirstlane_i(cell_start[row + lo[0]]);
-      const int end = readfirstlane_i(cell_start[row + hi[0] + 1]);
-      for (int b = beg; b < end; b += 64) {
-        const int p = b + lane;
-        bool ok = false;
-        if (p < end) ok = dist2_exact<DIM>(pts[p], x) < r2;
-        count += __popcll(__ballot(ok));
-      }
-    }
-  if (count > kCap) {
-    if (lane == 0) atomicOr(flags, 1);
-    count = kCap;
-  }
-  if (count < k_min) count = k_min;
-  if (lane == 0) counts[t] = count;
 }
 
-// Ascending bitonic sort of 64*EPL (d2, idx) keys held in registers, element
-// e = lane*EPL + r in slot r; pairs further apart than EPL are exchanged with
-// the partner lane through shuffles.
+// ---------------------------------------------------------------------------
+// radius rows: ascending bitonic sort of up to 64*EPL indices in registers
+// (element e = lane*EPL + r in slot r; partners further apart than EPL are
+// exchanged through shuffles)
+// ---------------------------------------------------------------------------
 template <int EPL>
-__device__ __forceinline__ void wave_sort(double (&kd)[EPL], int (&ki)[EPL], int lane) {
+__device__ __forceinline__ void wave_sort_int(int (&k)[EPL], int lane) {
   constexpr int E = 64 * EPL;
 #pragma unroll
   for (int size = 2; size <= E; size <<= 1) {
@@ -472,17 +448,9 @@ __device__ __forceinline__ void wave_sort(double (&kd)[EPL], int (&ki)[EPL], int
 #pragma unroll
         for (int r = 0; r < EPL; ++r) {
           const int e = lane * EPL + r;
-          const double od = __shfl_xor(kd[r], lmask, 64);
-          const int oi = __shfl_xor(ki[r], lmask, 64);
-          const bool lower = (e & stride) == 0;
-          const bool up = (e & size) == 0;
-          const bool other_less = key_less(od, oi, kd[r], ki[r]);
-          // lower element of an ascending pair keeps the smaller key, etc.
-          const bool take = (lower == up) ? other_less : !other_less;
-          if (take) {
-            kd[r] = od;
-            ki[r] = oi;
-          }
+          const int o = __shfl_xor(k[r], lmask, 64);
+          const bool keep_min = ((e & stride) == 0) == ((e & size) == 0);
+          k[r] = keep_min ? min(k[r], o) : max(k[r], o);
         }
       } else {
 #pragma unroll
@@ -490,113 +458,312 @@ __device__ __forceinline__ void wave_sort(double (&kd)[EPL], int (&ki)[EPL], int
           if (r & stride) continue;
           const int e = lane * EPL + r;
           const bool up = (e & size) == 0;
-          const int r2 = r + stride;
-          const bool sw = up ? key_less(kd[r2], ki[r2], kd[r], ki[r]) : key_less(kd[r], ki[r], kd[r2], ki[r2]);
-          if (sw) {
-            const double td = kd[r];
-            const int ti = ki[r];
-            kd[r] = kd[r2];
-            ki[r] = ki[r2];
-            kd[r2] = td;
-            ki[r2] = ti;
-          }
+          const int lo = min(k[r], k[r + stride]), hi = max(k[r], k[r + stride]);
+          k[r] = up ? lo : hi;
+          k[r + stride] = up ? hi : lo;
         }
       }
     }
   }
 }
 
-// load n <= 64*EPL candidates from LDS, sort them in registers, write the row
+// sort n <= 64*EPL indices of an LDS buffer and write them to out[0 .. n)
 template <int EPL>
-__device__ __forceinline__ void sort_and_store(const double *d2, const int *idx, int n, int32_t *out, int lane) {
-  double kd[EPL];
-  int ki[EPL];
+__device__ __forceinline__ void sort_idx_store(const int *buf, int n, int32_t *out, int lane) {
+  int k[EPL];
 #pragma unroll
   for (int r = 0; r < EPL; ++r) {
     const int e = lane * EPL + r;
-    kd[r] = e < n ? d2[e] : DBL_MAX;
-    ki[r] = e < n ? idx[e] : INT_MAX;
+    k[r] = e < n ? buf[e] : INT_MAX;
   }
-  wave_sort<EPL>(kd, ki, lane);
+  wave_sort_int<EPL>(k, lane);
 #pragma unroll
   for (int r = 0; r < EPL; ++r) {
     const int e = lane * EPL + r;
-    if (e < n) out[e] = ki[r];
+    if (e < n) out[e] = k[r];
   }
 }
 
-constexpr int kSmallCap = 256;  // candidates per target in the common-case kernel
+__device__ __forceinline__ void sort_idx_any(const int *buf, int n, int32_t *out, int lane) {
+  if (n <= 64)
+    sort_idx_store<1>(buf, n, out, lane);
+  else if (n <= 128)
+    sort_idx_store<2>(buf, n, out, lane);
+  else
+    sort_idx_store<4>(buf, n, out, lane);
+}
 
-// Common case: at most kSmallCap sources inside the radius and a floor that
-// fits the small buffer.  Other targets are appended to `overflow` for
-// k_radius_fill_big.
-template <int DIM>
-__global__ __launch_bounds__(64) void k_radius_fill(const GridParams *gp, const SPoint *pts, const int *cell_start,
-                                                    const double *targets, const int *order, int64_t n_tgt,
-                                                    double r0, int k_min, const int64_t *row_ptr, int32_t *col,
-                                                    double *eps, int *overflow, int *n_overflow) {
-  __shared__ double d2[kSmallCap];
-  __shared__ int idx[kSmallCap];
-  const int64_t w = blockIdx.x;
-  if (w >= n_tgt) return;
-  const GridParams g = *gp;
-  const int t = readfirstlane_i(order[w]);
+// ascending bitonic sort of idx[0, n) in LDS (one-wavefront blocks)
+__device__ void lds_sort_int(int *idx, int n) {
   const int lane = lane_id();
-  double x[3] = {0, 0, 0};
-  for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
+  int np = 1;
+  while (np < n) np <<= 1;
+  for (int i = n + lane; i < np; i += 64) idx[i] = INT_MAX;
+  __syncthreads();
+  for (int size = 2; size <= np; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < (np >> 1); i += 64) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const int a = idx[lo], b = idx[hi];
+        if (up ? b < a : a < b) {
+          idx[lo] = b;
+          idx[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// LDS writes of one wavefront are seen by its later LDS reads from any lane
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kSmallCap = 256;      // row entries sorted in registers
+constexpr int kCellCap = 1536;      // candidates of one cell block staged in LDS
+constexpr int kCellThreads = 256;   // four wavefronts share a cell block
+constexpr int kMaxRuns = 9;         // runs of cells along x in a 3x3(x3) block
+
+// ---------------------------------------------------------------------------
+// radius search, cell-cooperative: a workgroup takes one target cell, stages
+// the sources of its (2R+1)^DIM block of cells in LDS once, and its four
+// wavefronts share the cell's targets (one target per wavefront at a time,
+// the candidates 64 per step).  Count pass (FILL = false): row lengths.
+// Fill pass: rows of up to kSmallCap entries, floor not needed, are sorted by
+// index in registers and written at row_ptr[t].  Targets of cells whose block
+// exceeds kCellCap sources (both passes), and targets needing the k_min floor
+// or a longer row (fill pass), are appended to `defer` for the per-target
+// kernels below.
+// ---------------------------------------------------------------------------
+template <int DIM, bool FILL>
+__global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams *gp, const SPoint *pts,
+                                                               const int *cell_start, const int *tcs,
+                                                               const double *targets, const int *order, double r0,
+                                                               int k_min, int64_t *counts, const int64_t *row_ptr,
+                                                               int32_t *col, double *eps, int *defer, int *n_defer,
+                                                               int *flags) {
+  __shared__ double cxyz[3][kCellCap];
+  __shared__ int cid[kCellCap];
+  __shared__ int cbuf[kCellThreads / 64][FILL ? kSmallCap : 1];
+  const GridParams g = *gp;
+  const int tid = threadIdx.x, lane = tid & 63, wv = readfirstlane_i(tid >> 6);
   const double r2 = r0 * r0;
   const int R = radius_blocks(g, r0);
-  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-  for (int d = 0; d < DIM; ++d) {
-    const int c = cell_coord(g, x[d], d);
-    lo[d] = max(c - R, 0);
-    hi[d] = min(c + R, g.nc[d] - 1);
-  }
-  int fill = 0;
-  for (int cz = lo[2]; cz <= hi[2]; ++cz)
-    for (int cy = lo[1]; cy <= hi[1]; ++cy) {
-      const int row = g.nc[0] * (cy + g.nc[1] * cz);
-      const int beg = readfirstlane_i(cell_start[row + lo[0]]);
-      const int end = readfirstlane_i(cell_start[row + hi[0] + 1]);
-      for (int b = beg; b < end; b += 64) {
-        const int p = b + lane;
+  for (int c = xcd_block(); c < g.ncell; c += gridDim.x) {
+    const int tb = tcs[c], te = tcs[c + 1];
+    if (tb == te) continue;
+    if (R > 1) {  // cells narrower than the radius: more runs than staged here
+      for (int i = tb + tid; i < te; i += kCellThreads) defer[atomicAdd(n_defer, 1)] = order[i];
+      continue;
+    }
+    const int ic[3] = {c % g.nc[0], (c / g.nc[0]) % g.nc[1], c / (g.nc[0] * g.nc[1])};
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+      lo[d] = max(ic[d] - R, 0);
+      hi[d] = min(ic[d] + R, g.nc[d] - 1);
+    }
+    // the block's runs of cells along x: all bounds requested at once, then
+    // every source of every run (one memory round trip each)
+    const int ny = hi[1] - lo[1] + 1, nrun = ny * (hi[2] - lo[2] + 1);
+    int rb[kMaxRuns], pre[kMaxRuns + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int q = 0; q < kMaxRuns; ++q) {
+      int b = 0, e = 0;
+      if (q < nrun) {
+        const int row = g.nc[0] * ((lo[1] + q % ny) + g.nc[1] * (lo[2] + q / ny));
+        b = cell_start[row + lo[0]];
+        e = cell_start[row + hi[0] + 1];
+      }
+      rb[q] = b;
+      pre[q + 1] = pre[q] + (e - b);
+    }
+    const int total = pre[kMaxRuns];
+    if (total > kCellCap) {
+      for (int i = tb + tid; i < te; i += kCellThreads) defer[atomicAdd(n_defer, 1)] = order[i];
+      continue;
+    }
+    for (int e = tid; e < total; e += kCellThreads) {
+      int q = 0;
+#pragma unroll
+      for (int u = 1; u < kMaxRuns; ++u) q += e >= pre[u] ? 1 : 0;
+      int src = rb[0] + e;
+#pragma unroll
+      for (int u = 1; u < kMaxRuns; ++u)
+        if (q == u) src = rb[u] + (e - pre[u]);
+      const SPoint sp = pts[src];
+      cxyz[0][e] = sp.x;
+      cxyz[1][e] = sp.y;
+      cxyz[2][e] = sp.z;
+      cid[e] = sp.idx;
+    }
+    // this wavefront's targets (every fourth of the cell), fetched by its
+    // lanes together, 64 at a time, then taken one by one
+    constexpr int NW = kCellThreads / 64;
+    int my_t = 0;
+    double my_x[3] = {0, 0, 0};
+    __syncthreads();
+    for (int j = 0; tb + wv + NW * j < te; ++j) {
+      if ((j & 63) == 0) {
+        const int i = tb + wv + NW * (j + lane);
+        my_t = i < te ? order[i] : 0;
+        for (int d = 0; d < DIM; ++d) my_x[d] = i < te ? targets[(int64_t)my_t * DIM + d] : 0.0;
+      }
+      const int t = readlane_i(my_t, j & 63);
+      double x[3] = {0, 0, 0};
+      for (int d = 0; d < DIM; ++d) x[d] = readlane_d(my_x[d], j & 63);
+      int fill = 0;
+      for (int k0 = 0; k0 < total; k0 += 64) {
+        const int k = k0 + lane;
         bool ok = false;
-        double dd = 0.0;
-        int id = 0;
-        if (p < end) {
-          const SPoint sp = pts[p];
-          dd = dist2_exact<DIM>(sp, x);
-          id = sp.idx;
+        if (k < total) {
+          // (dx*dx + dy*dy) + dz*dz, unfused (the file is built without contraction)
+          const double dx = cxyz[0][k] - x[0];
+          double dd = dx * dx;
+          if (DIM > 1) {
+            const double dy = cxyz[1][k] - x[1];
+            dd = dd + dy * dy;
+          }
+          if (DIM > 2) {
+            const double dz = cxyz[2][k] - x[2];
+            dd = dd + dz * dz;
+          }
           ok = dd < r2;
         }
-        uint64_t m;
-        const int pre = ballot_prefix(ok, &m);
-        if (ok && fill + pre < kSmallCap) {
-          d2[fill + pre] = dd;
-          idx[fill + pre] = id;
+        if constexpr (FILL) {
+          uint64_t m;
+          const int pre = ballot_prefix(ok, &m);
+          if (ok && fill + pre < kSmallCap) cbuf[wv][fill + pre] = cid[k];
+          fill += __popcll(m);
+        } else {
+          fill += __popcll(__ballot(ok));
         }
-        fill += __popcll(m);
+      }
+      if constexpr (FILL) {
+        if (fill < k_min || fill > kSmallCap) {
+          if (lane == 0) defer[atomicAdd(n_defer, 1)] = t;
+        } else {
+          wave_lds_sync();
+          sort_idx_any(cbuf[wv], fill, col + row_ptr[t], lane);
+          if (lane == 0) eps[t] = r0;
+        }
+        wave_lds_sync();  // the buffer is refilled for the next target
+      } else {
+        if (lane == 0) {
+          if (fill > kCap) atomicOr(flags, 1);
+          counts[t] = fill < k_min ? k_min : (fill > kCap ? kCap : fill);
+        }
       }
     }
-  const bool big = fill > kSmallCap || (fill < k_min && k_min + 65 > kSmallCap);
-  if (big) {
-    if (lane == 0) overflow[atomicAdd(n_overflow, 1)] = t;
-    return;
+    __syncthreads();  // the next cell restages the candidates
   }
-  const int64_t base = row_ptr[t];
-  __syncthreads();
-  if (fill >= k_min) {
-    if (fill <= 64)
-      sort_and_store<1>(d2, idx, fill, col + base, lane);
-    else if (fill <= 128)
-      sort_and_store<2>(d2, idx, fill, col + base, lane);
-    else
-      sort_and_store<4>(d2, idx, fill, col + base, lane);
-    if (lane == 0) eps[t] = r0;
-  } else {
-    const int got = knn_select<DIM, kSmallCap>(g, pts, cell_start, x, k_min + 1, 1, d2, idx);
-    for (int q = lane; q < k_min; q += 64) col[base + q] = idx[q];
-    if (lane == 0) eps[t] = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
+}
+
+// ---------------------------------------------------------------------------
+// per-target radius kernels for the deferred targets (one wavefront each,
+// candidates read from the cell-ordered sources 64 at a time)
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(64) void k_radius_count_list(const GridParams *gp, const SPoint *pts,
+                                                          const int *cell_start, const double *targets,
+                                                          const int *list, const int *n_list, double r0, int k_min,
+                                                          int64_t *counts, int *flags) {
+  const GridParams g = *gp;
+  const int lane = lane_id();
+  const double r2 = r0 * r0;
+  const int R = radius_blocks(g, r0);
+  const int n = readfirstlane_i(*n_list);
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int t = readfirstlane_i(list[w]);
+    double x[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
+    int lo[3], hi[3];
+    radius_block<DIM>(g, x, R, lo, hi);
+    int count = 0;
+    for (int cz = lo[2]; cz <= hi[2]; ++cz)
+      for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+        const int row = g.nc[0] * (cy + g.nc[1] * cz);
+        const int beg = readfirstlane_i(cell_start[row + lo[0]]);
+        const int end = readfirstlane_i(cell_start[row + hi[0] + 1]);
+        for (int b = beg; b < end; b += 64) {
+          const int p = b + lane;
+          bool ok = false;
+          if (p < end) ok = dist2_exact<DIM>(pts[p], x) < r2;
+          count += __popcll(__ballot(ok));
+        }
+      }
+    if (lane == 0) {
+      if (count > kCap) atomicOr(flags, 1);
+      counts[t] = count < k_min ? k_min : (count > kCap ? kCap : count);
+    }
+  }
+}
+
+// Deferred targets of the fill pass: rows of up to kSmallCap entries, or the
+// k_min floor when it fits the small buffer; everything else goes on to
+// k_radius_fill_big through `overflow`.
+template <int DIM>
+__global__ __launch_bounds__(64) void k_radius_fill_list(const GridParams *gp, const SPoint *pts,
+                                                         const int *cell_start, const double *targets,
+                                                         const int *list, const int *n_list, double r0, int k_min,
+                                                         const int64_t *row_ptr, int32_t *col, double *eps,
+                                                         int *overflow, int *n_overflow) {
+  __shared__ double d2[kSmallCap];
+  __shared__ int idx[kSmallCap];
+  const GridParams g = *gp;
+  const int lane = lane_id();
+  const double r2 = r0 * r0;
+  const int R = radius_blocks(g, r0);
+  const int n = readfirstlane_i(*n_list);
+  for (int w = blockIdx.x; w < n; w += gridDim.x) {
+    const int t = readfirstlane_i(list[w]);
+    double x[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
+    int lo[3], hi[3];
+    radius_block<DIM>(g, x, R, lo, hi);
+    int fill = 0;
+    for (int cz = lo[2]; cz <= hi[2]; ++cz)
+      for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+        const int row = g.nc[0] * (cy + g.nc[1] * cz);
+        const int beg = readfirstlane_i(cell_start[row + lo[0]]);
+        const int end = readfirstlane_i(cell_start[row + hi[0] + 1]);
+        for (int b = beg; b < end; b += 64) {
+          const int p = b + lane;
+          bool ok = false;
+          int id = 0;
+          if (p < end) {
+            const SPoint sp = pts[p];
+            ok = dist2_exact<DIM>(sp, x) < r2;
+            id = sp.idx;
+          }
+          uint64_t m;
+          const int pre = ballot_prefix(ok, &m);
+          if (ok && fill + pre < kSmallCap) idx[fill + pre] = id;
+          fill += __popcll(m);
+        }
+      }
+    const bool big = fill > kSmallCap || (fill < k_min && k_min + 65 > kSmallCap);
+    if (big) {
+      if (lane == 0) overflow[atomicAdd(n_overflow, 1)] = t;
+      __syncthreads();
+      continue;
+    }
+    const int64_t base = row_ptr[t];
+    __syncthreads();
+    if (fill >= k_min) {
+      sort_idx_any(idx, fill, col + base, lane);
+      if (lane == 0) eps[t] = r0;
+    } else {
+      const int got = knn_select<DIM, kSmallCap>(g, pts, cell_start, x, k_min + 1, 1, d2, idx);
+      __syncthreads();
+      sort_idx_any(idx, k_min, col + base, lane);
+      if (lane == 0) eps[t] = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
+    }
+    __syncthreads();
   }
 }
 
@@ -611,19 +778,15 @@ __global__ __launch_bounds__(64) void k_radius_fill_big(const GridParams *gp, co
   __shared__ int idx[kCap];
   const GridParams g = *gp;
   const int lane = lane_id();
+  const double r2 = r0 * r0;
+  const int R = radius_blocks(g, r0);
   const int n = readfirstlane_i(*n_overflow);
   for (int w = blockIdx.x; w < n; w += gridDim.x) {
     const int t = readfirstlane_i(overflow[w]);
     double x[3] = {0, 0, 0};
     for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
-    const double r2 = r0 * r0;
-    const int R = radius_blocks(g, r0);
-    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
-    for (int d = 0; d < DIM; ++d) {
-      const int c = cell_coord(g, x[d], d);
-      lo[d] = max(c - R, 0);
-      hi[d] = min(c + R, g.nc[d] - 1);
-    }
+    int lo[3], hi[3];
+    radius_block<DIM>(g, x, R, lo, hi);
     int fill = 0;
     for (int cz = lo[2]; cz <= hi[2]; ++cz)
       for (int cy = lo[1]; cy <= hi[1]; ++cy) {
@@ -633,20 +796,15 @@ __global__ __launch_bounds__(64) void k_radius_fill_big(const GridParams *gp, co
         for (int b = beg; b < end; b += 64) {
           const int p = b + lane;
           bool ok = false;
-          double dd = 0.0;
           int id = 0;
           if (p < end) {
             const SPoint sp = pts[p];
-            dd = dist2_exact<DIM>(sp, x);
+            ok = dist2_exact<DIM>(sp, x) < r2;
             id = sp.idx;
-            ok = dd < r2;
           }
           uint64_t m;
           const int pre = ballot_prefix(ok, &m);
-          if (ok && fill + pre < kCap) {
-            d2[fill + pre] = dd;
-            idx[fill + pre] = id;
-          }
+          if (ok && fill + pre < kCap) idx[fill + pre] = id;
           fill += __popcll(m);
         }
       }
@@ -654,13 +812,17 @@ __global__ __launch_bounds__(64) void k_radius_fill_big(const GridParams *gp, co
     __syncthreads();
     if (fill >= k_min) {
       if (fill > kCap) fill = kCap;  // flagged by the count pass; the call fails
-      lds_sort(d2, idx, fill);
+      lds_sort_int(idx, fill);
       for (int q = lane; q < fill; q += 64) col[base + q] = idx[q];
       if (lane == 0) eps[t] = r0;
     } else {
       const int got = knn_select<DIM, kCap>(g, pts, cell_start, x, k_min + 1, 1, d2, idx);
+      __syncthreads();
+      const double e = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
+      __syncthreads();
+      lds_sort_int(idx, k_min);
       for (int q = lane; q < k_min; q += 64) col[base + q] = idx[q];
-      if (lane == 0) eps[t] = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
+      if (lane == 0) eps[t] = e;
     }
     __syncthreads();
   }
@@ -721,6 +883,7 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
   GMLS_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)(ncell_max + 1), s));
   k_cell_scatter<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(coords, n_src, key, start, cnt, sorted);
   GMLS_HIP(hipGetLastError());
+  const int *tcs = start;  // target ranges per cell in `order`
   if (n_tgt > 0) {
     if (targets == coords && n_tgt == n_src) {
       k_sorted_order<<<grid_for(n_tgt, 256), 256, 0, s>>>(sorted, n_tgt, order);
@@ -733,6 +896,7 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
       GMLS_HIP(exclusive_scan<int, int>(tcnt, tstart, ncell_max, (int *)tmp, s));
       GMLS_HIP(hipMemsetAsync(tcnt, 0, sizeof(int) * (size_t)(ncell_max + 1), s));
       k_index_scatter<<<grid_for(n_tgt, 256), 256, 0, s>>>(n_tgt, tkey, tstart, tcnt, order);
+      tcs = tstart;
     }
     GMLS_HIP(hipGetLastError());
   }
@@ -746,9 +910,22 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
     return GMLS_OK;
   }
   GMLS_WS(counts, int64_t, WS_ROW_COUNT, n_tgt > 0 ? n_tgt : 1);
-  if (n_tgt > 0)
-    k_radius_count<DIM><<<(unsigned)n_tgt, 64, 0, s>>>(gp, sorted, start, targets, order, n_tgt, spec.radius,
-                                                       spec.k_min, counts, flags);
+  GMLS_WS(defer, int, WS_DEFER, 2 * (n_tgt > 0 ? n_tgt : 1));
+  // flags: [0] error bits, [1] overflow count, [2] deferred (count pass), [3] deferred (fill pass)
+  int cus = 256;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
+      cus = prop.multiProcessorCount;
+  }
+  const unsigned nb_cells = (unsigned)xcd_grid(cus * 6);
+  if (n_tgt > 0) {
+    k_radius_cells<DIM, false><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order, spec.radius,
+                                                                  spec.k_min, counts, nullptr, nullptr, nullptr,
+                                                                  defer, flags + 2, flags);
+    k_radius_count_list<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, defer, flags + 2, spec.radius,
+                                                 spec.k_min, counts, flags);
+  }
   GMLS_HIP(exclusive_scan<int64_t, int64_t>(counts, row_ptr, n_tgt, tmp, s));
   int64_t nnz = 0;
   int hflags = 0;
@@ -762,11 +939,15 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
     return gmls_set_error(ctx, GMLS_ERR_CAPACITY,
                           "col_capacity " + std::to_string(col_capacity) + " < required " + std::to_string(nnz));
   if (n_tgt > 0) {
-    GMLS_HIP(hipMemsetAsync(flags + 1, 0, sizeof(int), s));
-    k_radius_fill<DIM><<<(unsigned)n_tgt, 64, 0, s>>>(gp, sorted, start, targets, order, n_tgt, spec.radius,
-                                                      spec.k_min, row_ptr, col, eps, (int *)counts, flags + 1);
+    int *defer_fill = defer + n_tgt;
+    int *overflow = (int *)counts;  // the counts are consumed by the scan
+    k_radius_cells<DIM, true><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order, spec.radius,
+                                                                 spec.k_min, nullptr, row_ptr, col, eps, defer_fill,
+                                                                 flags + 3, flags);
+    k_radius_fill_list<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, defer_fill, flags + 3, spec.radius,
+                                                spec.k_min, row_ptr, col, eps, overflow, flags + 1);
     k_radius_fill_big<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, spec.radius, spec.k_min, row_ptr, col,
-                                               eps, (int *)counts, flags + 1);
+                                               eps, overflow, flags + 1);
   }
   GMLS_HIP(hipGetLastError());
   GMLS_HIP(hipStreamSynchronize(s));

@@ -30,8 +30,36 @@
 
 namespace gmls {
 
-// functional rows of a scalar basis: value, dim gradient components, Laplacian
-constexpr int kPipeMaxF = 5;
+// Per-target record of one pipeline chunk, in list-slot order, so that the
+// three kernels read what they need about a target with one coalesced load
+// instead of a chain of scattered ones (list -> row_ptr, eps, coordinates).
+struct PipeRec {
+  int64_t base;  // row_ptr[t]
+  int n;         // row count
+  int t;         // target index
+  double ie;     // 1 / eps_t
+  double x[3];   // target coordinates
+  int ok;        // written by the solve: 1 = weights to be formed here
+  int pad;
+  double pad2;
+};
+static_assert(sizeof(PipeRec) == kPipeRecBytes, "record size");
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_pipe_prep(StencilArgs a, const int *list, int first, int last, PipeRec *rec) {
+  for (int i = first + blockIdx.x * blockDim.x + threadIdx.x; i < last; i += gridDim.x * blockDim.x) {
+    const int t = list[i];
+    PipeRec r;
+    r.base = a.row_ptr[t];
+    r.n = (int)(a.row_ptr[t + 1] - r.base);
+    r.t = t;
+    r.ie = 1.0 / a.eps[t];
+    for (int d = 0; d < 3; ++d) r.x[d] = d < DIM ? a.targets[(int64_t)t * DIM + d] : 0.0;
+    r.ok = 0;
+    r.pad = 0;
+    rec[i - first] = r;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // A. moments
@@ -73,20 +101,22 @@ __device__ __forceinline__ double row_sw(const double *xj, const double *xt, dou
 // `t` is a target of the bin even for an invalid group (whose sums are not
 // stored), so that every gathered row exists.
 template <int DIM, int ORDER, int G, int RPL>
-__device__ void pipe_moments_target(const StencilArgs &a, int t, bool valid, int slot, int lg, double *mom) {
+__device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, bool valid, int slot, int lg,
+                                    double *mom) {
   constexpr int NM = num_mono(DIM, 2 * ORDER);
-  constexpr int NMP = ((NM + G - 1) / G) * G;
-  const int64_t base = a.row_ptr[t];
-  const int N = (int)(a.row_ptr[t + 1] - base);
-  const double ie = 1.0 / a.eps[t];
+  constexpr int RS = 32;  // moments per LDS reduction round
+  __shared__ double red[64][RS + 1];
+  const int64_t base = rc.base;
+  const int N = rc.n;
+  const double ie = rc.ie;
   double xt[DIM];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) xt[d] = a.targets[(int64_t)t * DIM + d];
+  for (int d = 0; d < DIM; ++d) xt[d] = rc.x[d];
   double xs[RPL][DIM];
   gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
-  double mu[NMP];
+  double mu[NM];
 #pragma unroll
-  for (int m = 0; m < NMP; ++m) mu[m] = 0.0;
+  for (int m = 0; m < NM; ++m) mu[m] = 0.0;
   constexpr MomentSplit<DIM, ORDER> MS{};
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
@@ -105,13 +135,29 @@ __device__ void pipe_moments_target(const StencilArgs &a, int t, bool valid, int
 #pragma unroll
       for (int c = 0; c <= 2 * ORDER - MS.deg[pi]; ++c) mu[MS.midx[pi][c]] += wp[pi] * lastp[c];
   }
-  group_reduce_scatter<G, NMP>(mu, lg);
-  if (valid) {
+  // the sums are complete here: without this the compiler sinks each
+  // moment's FMA chain into the reduction round that stores it and keeps
+  // every row's products live until then
 #pragma unroll
-    for (int i = 0; i < NMP / G; ++i) {
-      const int m = lg * (NMP / G) + i;
-      if (m < NM) mom[(int64_t)slot * NM + m] = mu[i];
+  for (int m = 0; m < NM; ++m) asm volatile("" : "+v"(mu[m]));
+  // sum the G lanes' partial moments through LDS, RS moments per round:
+  // every lane writes its partials, then lane lg of the group adds column
+  // lg + G*k over the group's rows, in lane order, and stores it
+  const int lane = lane_id(), grp0 = lane - lg;
+#pragma unroll
+  for (int r0 = 0; r0 < NM; r0 += RS) {
+#pragma unroll
+    for (int q = 0; q < RS; ++q) red[lane][q] = r0 + q < NM ? mu[r0 + q] : 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RS / G; ++k) {
+      const int q = lg + G * k;
+      double acc = 0.0;
+#pragma unroll
+      for (int l = 0; l < G; ++l) acc += red[grp0 + l][q];
+      if (valid && r0 + q < NM) mom[(int64_t)slot * NM + r0 + q] = acc;
     }
+    __syncthreads();
   }
 }
 
@@ -119,16 +165,16 @@ __device__ void pipe_moments_target(const StencilArgs &a, int t, bool valid, int
 // in list slot i goes to mom[(i - c0) * NM + g] (target-major, so that a
 // group writes its target's moments contiguously).
 template <int DIM, int ORDER, int G, int RPL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_pipe_moments(StencilArgs a, const int *list, int first, int last, int c0,
-                                                     double *mom) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_pipe_moments(
+    StencilArgs a, const PipeRec *rec, int first, int last, int c0, double *mom) {
   constexpr int TPW = 64 / G;
   const int lane = lane_id();
   const int grp = lane / G, lg = lane % G;
   for (int i0 = first + xcd_block() * TPW; i0 < last; i0 += gridDim.x * TPW) {
     const int i = i0 + grp;
     const bool valid = i < last;
-    const int t = list[valid ? i : first];
-    pipe_moments_target<DIM, ORDER, G, RPL>(a, t, valid, i - c0, lg, mom);
+    const PipeRec rc = rec[(valid ? i : first) - c0];
+    pipe_moments_target<DIM, ORDER, G, RPL>(a, rc, valid, i - c0, lg, mom);
   }
 }
 
@@ -185,7 +231,7 @@ struct MomentPairs {
 };
 
 template <int DIM, int ORDER>
-__global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, const int *list, int first, int last, int c0,
+__global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, int first, int last, int c0,
                                                    const double *mom, double *yout, int *fb_list,
                                                    BinMeta *meta, Stats *stats, Options opt) {
   constexpr int Q = num_mono(DIM, ORDER);
@@ -203,8 +249,8 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, const int *lis
   for (int slot = first + xcd_block() * 64 + lane; slot - lane < last; slot += gridDim.x * 64) {
     const bool valid = slot < last;
     const int sl = valid ? slot : first;
-    const int t = list[sl];
-    const double ie = 1.0 / a.eps[t];
+    const int t = rec[sl - c0].t;
+    const double ie = rec[sl - c0].ie;
     const int64_t loc = sl - c0;
     // stage this thread's moments into its LDS column; the wave's 84 loads
     // walk one contiguous block of 64*NM doubles, so lines are reused from L1
@@ -341,7 +387,10 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, const int *lis
     const bool good = valid && ok && conv_all;
     const bool not_conv = valid && ok && !conv_all;
     const bool fell = valid && !ok;
-    if (valid) a.status[t] = good ? GMLS_TARGET_OK : not_conv ? GMLS_TARGET_NOT_CONVERGED : GMLS_TARGET_FALLBACK;
+    if (valid) {
+      a.status[t] = good ? GMLS_TARGET_OK : not_conv ? GMLS_TARGET_NOT_CONVERGED : GMLS_TARGET_FALLBACK;
+      rec[sl - c0].ok = good ? 1 : 0;
+    }
     if (not_conv || fell) fb_list[atomicAdd(&meta->fb_count, 1)] = t;
     // statistics, aggregated over the wavefront (one atomic per counter)
     const int sw = sweeps_max < 15 ? sweeps_max : 15;
@@ -364,31 +413,34 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, const int *lis
 // ---------------------------------------------------------------------------
 // C. weights
 // ---------------------------------------------------------------------------
-template <int DIM, int ORDER, int G, int RPL>
-__global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const int *list, int first, int last, int c0,
-                                                     const double *yin) {
+// F functional rows (compile time, so that the group's solutions stay in
+// registers: F*Q doubles per lane).
+template <int DIM, int ORDER, int G, int RPL, int F>
+__global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRec *rec, int first, int last,
+                                                     int c0, const double *yin) {
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int TPW = 64 / G;
-  __shared__ double ys[TPW][kPipeMaxF * Q];  // the group's target solutions, [f][q]
   const int lane = lane_id();
   const int grp = lane / G, lg = lane % G;
-  const int F = a.F;
   for (int i0 = first + xcd_block() * TPW; i0 < last; i0 += gridDim.x * TPW) {
     const int i = i0 + grp;
     const bool valid = i < last;
-    const int t = list[valid ? i : first];
-    const bool good = valid && a.status[t] == GMLS_TARGET_OK;
     const int64_t loc = (valid ? i : first) - c0;
-    for (int k = lg; k < F * Q; k += G) ys[grp][k] = yin[loc * F * Q + k];
-    const int64_t base = a.row_ptr[t];
-    const int N = (int)(a.row_ptr[t + 1] - base);
-    const double ie = 1.0 / a.eps[t];
+    const PipeRec rc = rec[loc];
+    const bool good = valid && rc.ok;
+    double y[F][Q];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) y[f][q] = yin[(loc * F + f) * Q + q];
+    const int64_t base = rc.base;
+    const int N = rc.n;
+    const double ie = rc.ie;
     double xt[DIM];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) xt[d] = a.targets[(int64_t)t * DIM + d];
+    for (int d = 0; d < DIM; ++d) xt[d] = rc.x[d];
     double xs[RPL][DIM];
     gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
-    __syncthreads();  // ys written by the group's lanes
     double *wout = a.weights + (int64_t)F * base;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
@@ -397,14 +449,14 @@ __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const int *l
       double p[Q];
       scaled_basis<DIM, ORDER, double>(s, p);
       const int j = lg + G * r;
+#pragma unroll
       for (int f = 0; f < F; ++f) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc += p[q] * ys[grp][f * Q + q];
+        for (int q = 0; q < Q; ++q) acc += p[q] * y[f][q];
         if (good && j < N) wout[(int64_t)f * N + j] = w * acc;
       }
     }
-    __syncthreads();  // ys is rewritten by the next iteration
   }
 }
 
@@ -417,16 +469,25 @@ constexpr bool has_pipe() {
 }
 
 template <int DIM, int ORDER, int G, int RPL>
-static void pipe_bin_launch(bool weights, const StencilArgs &a, const int *list, int lo, int hi, int c0,
+static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *rec, int lo, int hi, int c0,
                             double *buf, int cus, hipStream_t s) {
   constexpr int TPW = 64 / G;
   int nb = (hi - lo + TPW - 1) / TPW;
   if (nb > cus * 32) nb = cus * 32;
   nb = xcd_grid(nb);
-  if (weights)
-    k_pipe_weights<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, list, lo, hi, c0, buf);
-  else
-    k_pipe_moments<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, list, lo, hi, c0, buf);
+  if (!weights) {
+    k_pipe_moments<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf);
+    return;
+  }
+  switch (a.F) {  // scalar basis: value + up to DIM gradient rows + Laplacian
+    case 1: k_pipe_weights<DIM, ORDER, G, RPL, 1><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf); break;
+    case 2: k_pipe_weights<DIM, ORDER, G, RPL, 2><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf); break;
+    case 3: k_pipe_weights<DIM, ORDER, G, RPL, 3><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf); break;
+    case 4: k_pipe_weights<DIM, ORDER, G, RPL, 4><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf); break;
+    default:
+      if constexpr (DIM == 3) k_pipe_weights<DIM, ORDER, G, RPL, 5><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf);
+      break;
+  }
 }
 
 // bins 1..4 occupy list slots [count[0], n) contiguously, in bin order;
@@ -434,18 +495,23 @@ static void pipe_bin_launch(bool weights, const StencilArgs &a, const int *list,
 // bin 3 (<= 192) 32 x 6, bin 4 (<= 256) 32 x 8.
 template <int DIM, int ORDER>
 hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta &hm, BinMeta *meta, int *fb,
-                       Stats *stats, const Options &opt, double *mom, double *y, int64_t chunk, int cus,
-                       hipStream_t s) {
+                       Stats *stats, const Options &opt, double *mom, double *y, PipeRec *rec, int64_t chunk,
+                       int cus, hipStream_t s) {
   const int begin = hm.offset[1];
   const int end = hm.offset[kNumBins - 1] + hm.count[kNumBins - 1];
   for (int64_t c0 = begin; c0 < end; c0 += chunk) {
     const int c1 = (int)(c0 + chunk < end ? c0 + chunk : end);
+    {
+      int nbp = (int)((c1 - c0 + 255) / 256);
+      if (nbp > cus * 8) nbp = cus * 8;
+      k_pipe_prep<DIM><<<nbp, 256, 0, s>>>(a, list, (int)c0, c1, rec);
+    }
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1) {
         int nb = (int)((c1 - c0 + 63) / 64);
         if (nb > cus * 16) nb = cus * 16;
         nb = xcd_grid(nb);
-        k_pipe_solve<DIM, ORDER><<<nb, 64, 0, s>>>(a, list, (int)c0, c1, (int)c0, mom, y, fb, meta,
+        k_pipe_solve<DIM, ORDER><<<nb, 64, 0, s>>>(a, rec, (int)c0, c1, (int)c0, mom, y, fb, meta,
                                                       stats, opt);
       }
       const bool wts = pass == 1;
@@ -455,13 +521,13 @@ hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta &hm,
         if (lo >= hi) continue;
         double *buf = wts ? y : mom;
         if (b == 1)
-          pipe_bin_launch<DIM, ORDER, 8, 8>(wts, a, list, lo, hi, (int)c0, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 8, 8>(wts, a, rec, lo, hi, (int)c0, buf, cus, s);
         else if (b == 2)
-          pipe_bin_launch<DIM, ORDER, 16, 8>(wts, a, list, lo, hi, (int)c0, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 16, 8>(wts, a, rec, lo, hi, (int)c0, buf, cus, s);
         else if (b == 3)
-          pipe_bin_launch<DIM, ORDER, 32, 6>(wts, a, list, lo, hi, (int)c0, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 32, 6>(wts, a, rec, lo, hi, (int)c0, buf, cus, s);
         else
-          pipe_bin_launch<DIM, ORDER, 32, 8>(wts, a, list, lo, hi, (int)c0, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 32, 8>(wts, a, rec, lo, hi, (int)c0, buf, cus, s);
       }
     }
   }

@@ -94,10 +94,10 @@ def radius_definition(src, tgt, r0, k_min):
         order = np.lexsort((np.arange(len(src)), d2))
         inside = order[d2[order] < r0 * r0]
         if len(inside) >= k_min:
-            rows.append(inside)
+            rows.append(np.sort(inside))
             eps.append(r0)
         else:
-            rows.append(order[:k_min])
+            rows.append(np.sort(order[:k_min]))
             eps.append(0.5 * (np.sqrt(d2[order[k_min - 1]]) + np.sqrt(d2[order[k_min]])))
     return rows, np.array(eps)
 
