@@ -109,7 +109,7 @@ typedef struct {
   double t_fallback_ms;    /* GPU time of the FP64 fallback kernel                           */
 } gmls_report;
 
-/* Options for gmls_set_option (mixed path). */
+/* Options for gmls_set_option. */
 enum {
   GMLS_OPT_COND_THRESHOLD = 0, /* fallback when the Gram condition estimate exceeds it (1e6) */
   GMLS_OPT_MAX_SWEEPS = 1,     /* refinement sweeps before giving up (8)                      */
@@ -129,8 +129,11 @@ enum {
                                       <= 3, 2D order <= 4).
                                   A scheme not compiled for the shape makes gmls_stencils return
                                   GMLS_ERR_UNSUPPORTED.                                         */
-  GMLS_OPT_PIPE_CHUNK = 5      /* scheme 3: targets per pipeline chunk, 0 = all at once (0); the
+  GMLS_OPT_PIPE_CHUNK = 5,     /* scheme 3: targets per pipeline chunk, 0 = all at once (0); the
                                   workspace holds (moments + F*Q) doubles per chunk target       */
+  GMLS_OPT_RADIUS_SCRATCH_MB = 6 /* radius search: device scratch (MiB) allowed for the one-pass
+                                  search, 1 KiB per target; above it (or at 0) the search
+                                  counts and fills in two passes (8192)                          */
 };
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`

@@ -152,6 +152,11 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
       if (value != 0 && value < 64) return gmls_set_error(ctx, GMLS_ERR_ARG, "pipeline chunk must be 0 or >= 64");
       ctx->opt.pipe_chunk = (int64_t)value;
       return GMLS_OK;
+    case GMLS_OPT_RADIUS_SCRATCH_MB:
+      if (!(value >= 0 && value <= 1048576.0 && value == (double)(int64_t)value))
+        return gmls_set_error(ctx, GMLS_ERR_ARG, "radius scratch must be an integer number of MiB in [0, 2^20]");
+      ctx->opt.radius_scratch_mb = (int64_t)value;
+      return GMLS_OK;
     default:
       return gmls_set_error(ctx, GMLS_ERR_ARG, "unknown option");
   }

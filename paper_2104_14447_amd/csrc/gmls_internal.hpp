@@ -26,6 +26,8 @@ enum Slot {
   WS_TGT_ORDER,
   WS_ROW_COUNT,
   WS_DEFER,
+  WS_RADIUS_ROWS,
+  WS_TGT_FLAG,
   WS_SCAN_TMP,
   WS_FLAGS,
   WS_BIN_META,
@@ -50,6 +52,7 @@ struct Options {
   int force_fallback = 0;
   int scheme = MIXED_AUTO;  // resolved to ROWS, GRAM or PIPE before any launch
   int64_t pipe_chunk = 0;   // list slots per pipeline chunk (0: the whole call)
+  int64_t radius_scratch_mb = 8192;  // scratch rows of the one-pass radius search (MiB)
 };
 
 }  // namespace gmls

@@ -436,6 +436,20 @@ __device__ __forceinline__ void radius_block(const GridParams &g, const double *
 // (element e = lane*EPL + r in slot r; partners further apart than EPL are
 // exchanged through shuffles)
 // ---------------------------------------------------------------------------
+// v of lane (lane ^ lm) for a compile-time lm (after unrolling): DPP for
+// lm = 1, 2, 8 (quad permutes, rotation by 8 within a row of 16), swizzles
+// for lm = 4, 16, a permute through LDS only for lm = 32
+__device__ __forceinline__ int xor_lane(int v, int lm) {
+  switch (lm) {
+    case 1: return __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    case 2: return __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    case 4: return __builtin_amdgcn_ds_swizzle(v, 0x101F);                     // xor 4 within 32
+    case 8: return __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    case 16: return __builtin_amdgcn_ds_swizzle(v, 0x401F);                    // xor 16 within 32
+    default: return __shfl_xor(v, lm, 64);
+  }
+}
+
 template <int EPL>
 __device__ __forceinline__ void wave_sort_int(int (&k)[EPL], int lane) {
   constexpr int E = 64 * EPL;
@@ -448,7 +462,7 @@ __device__ __forceinline__ void wave_sort_int(int (&k)[EPL], int lane) {
 #pragma unroll
         for (int r = 0; r < EPL; ++r) {
           const int e = lane * EPL + r;
-          const int o = __shfl_xor(k[r], lmask, 64);
+          const int o = xor_lane(k[r], lmask);
           const bool keep_min = ((e & stride) == 0) == ((e & size) == 0);
           k[r] = keep_min ? min(k[r], o) : max(k[r], o);
         }
@@ -532,23 +546,30 @@ constexpr int kMaxRuns = 9;         // runs of cells along x in a 3x3(x3) block
 // radius search, cell-cooperative: a workgroup takes one target cell, stages
 // the sources of its (2R+1)^DIM block of cells in LDS once, and its four
 // wavefronts share the cell's targets (one target per wavefront at a time,
-// the candidates 64 per step).  Count pass (FILL = false): row lengths.
-// Fill pass: rows of up to kSmallCap entries, floor not needed, are sorted by
-// index in registers and written at row_ptr[t].  Targets of cells whose block
-// exceeds kCellCap sources (both passes), and targets needing the k_min floor
-// or a longer row (fill pass), are appended to `defer` for the per-target
-// kernels below.
+// the candidates 64 per step).  Modes:
+//  kCount: row lengths only;
+//  kFill:  rows of up to kSmallCap entries (floor not needed) are sorted by
+//          index in registers and written at row_ptr[t];
+//  kFused: one pass: such rows go to a scratch row of kSmallCap entries per
+//          target, every processed target's length to counts[t], and the
+//          rows are copied into place after the scan (k_rows_copy).
+// Targets of cells whose block exceeds kCellCap sources, and (fill and fused
+// modes) targets needing the k_min floor or a longer row, are appended to
+// `defer` (and flagged in dflag) for the per-target kernels below.
 // ---------------------------------------------------------------------------
-template <int DIM, bool FILL>
+enum RadiusMode { kCount = 0, kFill = 1, kFused = 2 };
+
+template <int DIM, int MODE>
 __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams *gp, const SPoint *pts,
                                                                const int *cell_start, const int *tcs,
                                                                const double *targets, const int *order, double r0,
                                                                int k_min, int64_t *counts, const int64_t *row_ptr,
                                                                int32_t *col, double *eps, int *defer, int *n_defer,
-                                                               int *flags) {
+                                                               uint8_t *dflag, int *flags) {
+  constexpr bool ROWS = MODE != kCount;
   __shared__ double cxyz[3][kCellCap];
   __shared__ int cid[kCellCap];
-  __shared__ int cbuf[kCellThreads / 64][FILL ? kSmallCap : 1];
+  __shared__ int cbuf[kCellThreads / 64][ROWS ? kSmallCap : 1];
   const GridParams g = *gp;
   const int tid = threadIdx.x, lane = tid & 63, wv = readfirstlane_i(tid >> 6);
   const double r2 = r0 * r0;
@@ -557,7 +578,10 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
     const int tb = tcs[c], te = tcs[c + 1];
     if (tb == te) continue;
     if (R > 1) {  // cells narrower than the radius: more runs than staged here
-      for (int i = tb + tid; i < te; i += kCellThreads) defer[atomicAdd(n_defer, 1)] = order[i];
+      for (int i = tb + tid; i < te; i += kCellThreads) {
+        defer[atomicAdd(n_defer, 1)] = order[i];
+        if (MODE == kFused) dflag[order[i]] = 1;
+      }
       continue;
     }
     const int ic[3] = {c % g.nc[0], (c / g.nc[0]) % g.nc[1], c / (g.nc[0] * g.nc[1])};
@@ -584,7 +608,10 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
     }
     const int total = pre[kMaxRuns];
     if (total > kCellCap) {
-      for (int i = tb + tid; i < te; i += kCellThreads) defer[atomicAdd(n_defer, 1)] = order[i];
+      for (int i = tb + tid; i < te; i += kCellThreads) {
+        defer[atomicAdd(n_defer, 1)] = order[i];
+        if (MODE == kFused) dflag[order[i]] = 1;
+      }
       continue;
     }
     for (int e = tid; e < total; e += kCellThreads) {
@@ -616,7 +643,7 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
       const int t = readlane_i(my_t, j & 63);
       double x[3] = {0, 0, 0};
       for (int d = 0; d < DIM; ++d) x[d] = readlane_d(my_x[d], j & 63);
-      int fill = 0;
+      int fill = 0, cnt = 0;
       for (int k0 = 0; k0 < total; k0 += 64) {
         const int k = k0 + lane;
         bool ok = false;
@@ -634,32 +661,61 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
           }
           ok = dd < r2;
         }
-        if constexpr (FILL) {
+        if constexpr (ROWS) {
           uint64_t m;
           const int pre = ballot_prefix(ok, &m);
           if (ok && fill + pre < kSmallCap) cbuf[wv][fill + pre] = cid[k];
           fill += __popcll(m);
         } else {
-          fill += __popcll(__ballot(ok));
+          cnt += ok ? 1 : 0;
         }
       }
-      if constexpr (FILL) {
-        if (fill < k_min || fill > kSmallCap) {
-          if (lane == 0) defer[atomicAdd(n_defer, 1)] = t;
-        } else {
-          wave_lds_sync();
-          sort_idx_any(cbuf[wv], fill, col + row_ptr[t], lane);
-          if (lane == 0) eps[t] = r0;
-        }
-        wave_lds_sync();  // the buffer is refilled for the next target
-      } else {
+      if constexpr (!ROWS) {
+        fill = wave_sum(cnt);
         if (lane == 0) {
           if (fill > kCap) atomicOr(flags, 1);
           counts[t] = fill < k_min ? k_min : (fill > kCap ? kCap : fill);
         }
+      } else {
+        if (fill < k_min || fill > kSmallCap) {
+          if (lane == 0) {
+            defer[atomicAdd(n_defer, 1)] = t;
+            if (MODE == kFused) {
+              dflag[t] = 1;
+              if (fill > kCap) atomicOr(flags, 1);
+              counts[t] = fill < k_min ? k_min : (fill > kCap ? kCap : fill);
+            }
+          }
+        } else {
+          wave_lds_sync();
+          int32_t *out = MODE == kFused ? col + (int64_t)t * kSmallCap : col + row_ptr[t];
+          sort_idx_any(cbuf[wv], fill, out, lane);
+          if (lane == 0) {
+            eps[t] = r0;
+            if (MODE == kFused) {
+              counts[t] = fill;
+              dflag[t] = 0;
+            }
+          }
+        }
+        wave_lds_sync();  // the buffer is refilled for the next target
       }
     }
     __syncthreads();  // the next cell restages the candidates
+  }
+}
+
+// Rows of the fused pass into place: 16 lanes per target.
+__global__ __launch_bounds__(256) void k_rows_copy(int64_t n_tgt, const int64_t *row_ptr, const int32_t *rows,
+                                                   const uint8_t *dflag, int32_t *col) {
+  const int sub = threadIdx.x & 15;
+  const int64_t g0 = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 4);
+  for (int64_t t = g0; t < n_tgt; t += stride) {
+    if (dflag[t]) continue;
+    const int64_t b = row_ptr[t];
+    const int n = (int)(row_ptr[t + 1] - b);
+    for (int q = sub; q < n; q += 16) col[b + q] = rows[t * kSmallCap + q];
   }
 }
 
@@ -919,11 +975,27 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
       cus = prop.multiProcessorCount;
   }
   const unsigned nb_cells = (unsigned)xcd_grid(cus * 6);
+  // one pass with a scratch row per target when that fits the budget,
+  // otherwise a count pass and a fill pass
+  const bool fused = (double)n_tgt * kSmallCap * sizeof(int32_t) <= (double)ctx->opt.radius_scratch_mb * (1 << 20);
+  int32_t *rows = nullptr;
+  uint8_t *dflag = nullptr;
+  if (fused && n_tgt > 0) {
+    rows = (int32_t *)ctx->ws(WS_RADIUS_ROWS, sizeof(int32_t) * (size_t)n_tgt * kSmallCap);
+    dflag = (uint8_t *)ctx->ws(WS_TGT_FLAG, (size_t)n_tgt);
+    if (!rows || !dflag) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed (rows)");
+  }
   if (n_tgt > 0) {
-    k_radius_cells<DIM, false><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order, spec.radius,
-                                                                  spec.k_min, counts, nullptr, nullptr, nullptr,
-                                                                  defer, flags + 2, flags);
-    k_radius_count_list<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, defer, flags + 2, spec.radius,
+    if (fused)
+      k_radius_cells<DIM, kFused><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order,
+                                                                     spec.radius, spec.k_min, counts, nullptr, rows,
+                                                                     eps, defer, flags + 2, dflag, flags);
+    else
+      k_radius_cells<DIM, kCount><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order,
+                                                                     spec.radius, spec.k_min, counts, nullptr,
+                                                                     nullptr, nullptr, defer, flags + 2, nullptr,
+                                                                     flags);
+    k_radius_count_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, defer, flags + 2, spec.radius,
                                                  spec.k_min, counts, flags);
   }
   GMLS_HIP(exclusive_scan<int64_t, int64_t>(counts, row_ptr, n_tgt, tmp, s));
@@ -939,12 +1011,19 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
     return gmls_set_error(ctx, GMLS_ERR_CAPACITY,
                           "col_capacity " + std::to_string(col_capacity) + " < required " + std::to_string(nnz));
   if (n_tgt > 0) {
-    int *defer_fill = defer + n_tgt;
+    int *defer_fill = defer;
+    int *n_defer_fill = flags + 2;
     int *overflow = (int *)counts;  // the counts are consumed by the scan
-    k_radius_cells<DIM, true><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order, spec.radius,
-                                                                 spec.k_min, nullptr, row_ptr, col, eps, defer_fill,
-                                                                 flags + 3, flags);
-    k_radius_fill_list<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, defer_fill, flags + 3, spec.radius,
+    if (fused) {
+      k_rows_copy<<<grid_for(n_tgt, 16), 256, 0, s>>>(n_tgt, row_ptr, rows, dflag, col);
+    } else {
+      defer_fill = defer + n_tgt;
+      n_defer_fill = flags + 3;
+      k_radius_cells<DIM, kFill><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order,
+                                                                    spec.radius, spec.k_min, nullptr, row_ptr, col,
+                                                                    eps, defer_fill, n_defer_fill, nullptr, flags);
+    }
+    k_radius_fill_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, defer_fill, n_defer_fill, spec.radius,
                                                 spec.k_min, row_ptr, col, eps, overflow, flags + 1);
     k_radius_fill_big<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, spec.radius, spec.k_min, row_ptr, col,
                                                eps, overflow, flags + 1);

@@ -119,3 +119,19 @@ def test_bad_arguments_raise():
         G.gmls_neighbors(ctx(), s, s, G.SEARCH_KNN, k=101)
     with pytest.raises(G.GmlsError):
         G.gmls_neighbors(ctx(), s, s, G.SEARCH_RADIUS, radius=-1.0)
+
+
+@pytest.mark.parametrize("n", [3000, 20000])
+def test_radius_two_pass_matches_oracle(n):
+    """The count-then-fill variant (no scratch rows) gives the same lists."""
+    G = require_gpu()
+    src = W.density_ramp(n, 1004)
+    r0 = W.radius_for_mean_count(n)
+    c = ctx()
+    c.set_option(G.OPT_RADIUS_SCRATCH_MB, 0)
+    try:
+        flush(f"radius two-pass n={n}")
+        g = gpu_radius(src, src, r0, 30)
+    finally:
+        c.set_option(G.OPT_RADIUS_SCRATCH_MB, 8192)
+    assert_same(g, oracle.radius(src, src, r0, 30), f"radius two-pass n={n}")
