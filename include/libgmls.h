@@ -131,9 +131,20 @@ enum {
                                   GMLS_ERR_UNSUPPORTED.                                         */
   GMLS_OPT_PIPE_CHUNK = 5,     /* scheme 3: targets per pipeline chunk, 0 = all at once (0); the
                                   workspace holds (moments + F*Q) doubles per chunk target       */
-  GMLS_OPT_RADIUS_SCRATCH_MB = 6 /* radius search: device scratch (MiB) allowed for the one-pass
+  GMLS_OPT_RADIUS_SCRATCH_MB = 6, /* radius search: device scratch (MiB) allowed for the one-pass
                                   search, 1 KiB per target; above it (or at 0) the search
                                   counts and fills in two passes (8192)                          */
+  GMLS_OPT_CAPTURE_SAFE = 7    /* nonzero: no call waits for the device or allocates, so that a
+                                  sequence of calls can be captured into a HIP graph on the
+                                  context's stream and replayed (0).  In this mode:
+                                  - workspaces are not grown: run each call once with the mode off
+                                    (same sizes) first, else GMLS_ERR_NOMEM;
+                                  - gmls_neighbors writes -1 to *nnz_host (the total is
+                                    row_ptr[n_tgt] on the device); a total over col_capacity leaves
+                                    col unwritten and is reported by gmls_check;
+                                  - gmls_stencils takes no report (GMLS_ERR_ARG otherwise); a row
+                                    longer than 256 leaves its target unwritten and is reported by
+                                    gmls_check.                                                  */
 };
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
@@ -195,6 +206,11 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
                           int64_t n_tgt, int dim, int order, int basis, unsigned functional_mask, int weight_p,
                           const double *eps, const int64_t *row_ptr, const int32_t *col, int prec,
                           double *weights, uint8_t *target_status, gmls_report *report);
+
+/* Errors of capture-safe calls found on the device since the last check
+ * (GMLS_OPT_CAPTURE_SAFE): GMLS_OK, GMLS_ERR_CAPACITY or GMLS_ERR_UNSUPPORTED
+ * with a message in gmls_last_error.  Synchronises; clears the record. */
+gmls_status gmls_check(gmls_ctx ctx);
 
 /* Apply stencils to a field (Section 3.2, the stencil sum over neighbours):
  *   out[t*F + f] = sum_j sum_c weights[F*C_in*row_ptr[t] + (f*N_t + j)*C_in + c]

@@ -22,7 +22,7 @@ __all__ = [
     "BASIS_SCALAR", "BASIS_DIVFREE", "F_VALUE", "F_GRAD", "F_LAPLACIAN", "F_DIV",
     "PREC_FP64", "PREC_MIXED", "SEARCH_KNN", "SEARCH_RADIUS",
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
-    "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE",
+    "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -33,13 +33,13 @@ F_VALUE, F_GRAD, F_LAPLACIAN, F_DIV = 1, 2, 4, 8
 PREC_FP64, PREC_MIXED = 0, 1
 SEARCH_KNN, SEARCH_RADIUS = 0, 1
 OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
-OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB = 4, 5, 6
+OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE = 4, 5, 6, 7
 SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE = 0, 1, 2, 3
 GMLS_OK, GMLS_ERR_CAPACITY, GMLS_WARN_TARGET_FLAGS = 0, 4, 6
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY", 5: "ERR_UNSUPPORTED",
            6: "WARN_TARGET_FLAGS"}
 EXPORTED_SYMBOLS = ("gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
-                    "gmls_stencil_shape", "gmls_stencils", "gmls_apply")
+                    "gmls_stencil_shape", "gmls_stencils", "gmls_apply", "gmls_check")
 
 
 class GmlsError(RuntimeError):
@@ -97,6 +97,8 @@ def load_library():
     L.gmls_stencils.restype = ctypes.c_int
     L.gmls_apply.argtypes = [_vp, _i64, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
     L.gmls_apply.restype = ctypes.c_int
+    L.gmls_check.argtypes = [_vp]
+    L.gmls_check.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -126,6 +128,7 @@ class Context:
             raise GmlsError(st, "gmls_create failed")
         self._h = h
         self._col_cap = 0
+        self.capture_safe = False
 
     def close(self):
         if getattr(self, "_h", None):
@@ -146,6 +149,14 @@ class Context:
         st = load_library().gmls_set_option(self._h, option, float(value))
         if st != GMLS_OK:
             self._raise(st)
+        if option == OPT_CAPTURE_SAFE:
+            self.capture_safe = bool(value)
+
+    def check(self):
+        """Raise for errors that capture-safe calls left on the device."""
+        st = load_library().gmls_check(self._h)
+        if st != GMLS_OK:
+            self._raise(st)
 
 
 def gmls_stencil_shape(dim: int, order: int, basis: int, mask: int):
@@ -159,7 +170,11 @@ def gmls_stencil_shape(dim: int, order: int, basis: int, mask: int):
 
 def gmls_neighbors(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, mode: int, k: int = 0,
                    eps_mult: float = 1.5, radius: float = 0.0, k_min: int = 0, col: torch.Tensor | None = None):
-    """Neighbour lists: returns (row_ptr int64 [n_tgt+1], col int32 [nnz], eps float64 [n_tgt])."""
+    """Neighbour lists: returns (row_ptr int64 [n_tgt+1], col int32 [nnz], eps float64 [n_tgt]).
+
+    In capture-safe mode the total is not known on the host: the whole `col`
+    buffer (which the caller must supply) is returned, row_ptr[-1] holds the
+    total, and capacity errors surface through Context.check()."""
     _check_dev(coords, targets)
     n_src, dim = coords.shape
     n_tgt = targets.shape[0]
@@ -168,6 +183,8 @@ def gmls_neighbors(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, mo
     row_ptr = torch.empty(n_tgt + 1, dtype=torch.int64, device=dev)
     eps = torch.empty(n_tgt, dtype=torch.float64, device=dev)
     if col is None:
+        if ctx.capture_safe:
+            raise ValueError("capture-safe mode: pass a preallocated col buffer")
         cap = n_tgt * k if mode == SEARCH_KNN else max(ctx._col_cap, n_tgt * max(k_min, 1) * 2)
         col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
     nnz = ctypes.c_int64()
@@ -175,6 +192,10 @@ def gmls_neighbors(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, mo
     args = lambda c: (ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, ctypes.byref(spec), _ptr(row_ptr),
                       _ptr(c), c.numel(), _ptr(eps), ctypes.byref(nnz))
     st = L.gmls_neighbors(*args(col))
+    if ctx.capture_safe:
+        if st != GMLS_OK:
+            ctx._raise(st)
+        return row_ptr, col, eps
     if st == GMLS_ERR_CAPACITY:
         col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
         st = L.gmls_neighbors(*args(col))

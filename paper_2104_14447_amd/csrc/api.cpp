@@ -17,6 +17,7 @@ void *gmls_ctx_s::ws(int slot, size_t bytes) {
   auto &e = slots[slot];
   if (bytes == 0) bytes = 1;
   if (e.second >= bytes) return e.first;
+  if (opt.capture_safe) return nullptr;  // no allocation while a stream may be captured
   if (e.first) {
     hipStreamSynchronize(stream);
     hipFree(e.first);
@@ -111,6 +112,16 @@ gmls_status gmls_create(gmls_ctx *out, int device, void *hip_stream) {
       delete ctx;
       return GMLS_ERR_HIP;
     }
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+      ctx->cus = prop.multiProcessorCount;
+  }
+  void *de = ctx->ws(WS_DEV_ERR, sizeof(int));
+  if (!de || fill_zero(de, sizeof(int), ctx->stream) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
+    delete ctx;
+    return GMLS_ERR_HIP;
+  }
   *out = ctx;
   return GMLS_OK;
 }
@@ -151,6 +162,9 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
         return gmls_set_error(ctx, GMLS_ERR_ARG, "pipeline chunk must be an integer in [0, 2^31)");
       if (value != 0 && value < 64) return gmls_set_error(ctx, GMLS_ERR_ARG, "pipeline chunk must be 0 or >= 64");
       ctx->opt.pipe_chunk = (int64_t)value;
+      return GMLS_OK;
+    case GMLS_OPT_CAPTURE_SAFE:
+      ctx->opt.capture_safe = value != 0;
       return GMLS_OK;
     case GMLS_OPT_RADIUS_SCRATCH_MB:
       if (!(value >= 0 && value <= 1048576.0 && value == (double)(int64_t)value))
@@ -261,43 +275,52 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
   a.n_tgt = n;
   a.ok_status = GMLS_TARGET_OK;
 
+  const bool sync = !opt.capture_safe;  // capture-safe: nothing below waits for the device
+  if (!sync && report)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "a report synchronises: pass NULL in capture-safe mode");
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[0], s));
   const size_t bin_bytes = binning_temp_bytes(n);
   void *bin_tmp = ctx->ws(WS_BIN_TEMP, bin_bytes);
   if (!bin_tmp) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
   GMLS_HIP(launch_binning(row_ptr, targets, n, dim, Q, C, meta, list, bin_tmp, bin_bytes, s));
   BinMeta hm;
-  GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
-  GMLS_HIP(hipStreamSynchronize(s));
-  if (hm.err) return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 256 neighbours");
-  GMLS_HIP(hipMemsetAsync(stats, 0, sizeof(Stats), s));
-  if (report) GMLS_HIP(hipEventRecord(ctx->ev[1], s));
-  if (hm.count[0] > 0) GMLS_HIP(launch_rank_deficient(a, C, list, meta, s));
-  int cus = 256;
-  {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
+  if (sync) {
+    GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
+    GMLS_HIP(hipStreamSynchronize(s));
+    if (hm.err) return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 256 neighbours");
+  } else {
+    // rows over the compiled maximum stay in bin 7 (never processed) and are
+    // reported by gmls_check
+    GMLS_HIP(or_error_bit((int *)ctx->ws(WS_DEV_ERR, sizeof(int)), &meta->err, 1, DEV_ERR_STENCIL_ROWS, s));
   }
+  GMLS_HIP(fill_zero(stats, sizeof(Stats), s));
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[1], s));
+  if (!sync || hm.count[0] > 0) GMLS_HIP(launch_rank_deficient(a, C, list, meta, s));
+  const int cus = ctx->cus;
   if (prec == GMLS_PREC_MIXED && opt.scheme == MIXED_PIPE) {
-    // moments [NM][chunk] and solutions [F][Q][chunk] of one chunk of targets
-    const int64_t n_work = (int64_t)n - hm.count[0];
-    const int64_t chunk = std::max<int64_t>(1, opt.pipe_chunk > 0 ? std::min<int64_t>(opt.pipe_chunk, n_work) : n_work);
-    double *mom = (double *)ctx->ws(WS_PIPE_MOM, sizeof(double) * (size_t)pipe_num_moments(dim, order) * chunk);
-    double *yb = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)F * Q * chunk);
-    void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * (size_t)chunk);
+    // moments [chunk][NM], solutions [chunk][F][Q] and records of one chunk of targets
+    // (sized for every target, so that a capture-safe call finds the
+    // workspace of an earlier call of the same size)
+    const int64_t n_work = sync ? (int64_t)n - hm.count[0] : (int64_t)n;
+    const int64_t chunk =
+        std::max<int64_t>(1, sync && opt.pipe_chunk > 0 ? std::min<int64_t>(opt.pipe_chunk, n_work) : n_work);
+    const size_t cap = (size_t)(sync && opt.pipe_chunk > 0 ? chunk : (int64_t)n);
+    double *mom = (double *)ctx->ws(WS_PIPE_MOM, sizeof(double) * (size_t)pipe_num_moments(dim, order) * cap);
+    double *yb = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)F * Q * cap);
+    void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * cap);
     if (!mom || !yb || !rec) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
     if (n_work > 0)
-      GMLS_HIP(
-          launch_mixed_pipe(dim, order, basis, a, list, hm, meta, fb, stats, opt, mom, yb, rec, chunk, cus, s));
+      GMLS_HIP(launch_mixed_pipe(dim, order, basis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, mom, yb, rec,
+                                 chunk, n, cus, s));
   } else {
     for (int b = 1; b < kNumBins; ++b) {
-      if (hm.count[b] == 0) continue;
+      if (sync && hm.count[b] == 0) continue;
+      const int cnt = sync ? hm.count[b] : n;  // sizes the grid; the kernels read the count on the device
       if (prec == GMLS_PREC_FP64) {
-        const int nb = std::min(hm.count[b], cus * 16);
+        const int nb = std::min(cnt, cus * 16);
         GMLS_HIP(launch_qr_bin(dim, order, basis, b, a, list, meta, nb, s));
       } else {
-        GMLS_HIP(launch_mixed_bin(dim, order, basis, b, a, list, meta, fb, stats, opt, hm.count[b], cus, s));
+        GMLS_HIP(launch_mixed_bin(dim, order, basis, b, a, list, meta, fb, stats, opt, cnt, cus, s));
       }
     }
   }
@@ -331,6 +354,25 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
   report->t_stencil_ms = t12;
   report->t_fallback_ms = t23;
   return hm.count[0] > 0 ? GMLS_WARN_TARGET_FLAGS : GMLS_OK;
+}
+
+gmls_status gmls_check(gmls_ctx ctx) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  DeviceGuard g(ctx->device);
+  int *de = (int *)ctx->ws(WS_DEV_ERR, sizeof(int));
+  if (!de) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device error word missing");
+  int bits = 0;
+  GMLS_HIP(hipMemcpyAsync(&bits, de, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  GMLS_HIP(hipStreamSynchronize(ctx->stream));
+  if (!bits) return GMLS_OK;
+  GMLS_HIP(fill_zero(de, sizeof(int), ctx->stream));
+  GMLS_HIP(hipStreamSynchronize(ctx->stream));
+  if (bits & DEV_ERR_CAPACITY)
+    return gmls_set_error(ctx, GMLS_ERR_CAPACITY, "a neighbour search needed more than col_capacity entries");
+  if (bits & DEV_ERR_RADIUS_ROWS)
+    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target had more than 2048 sources inside the radius");
+  return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a stencil call had a target with more than 256 neighbours");
 }
 
 gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, const int32_t *col,

@@ -28,6 +28,7 @@ enum Slot {
   WS_DEFER,
   WS_RADIUS_ROWS,
   WS_TGT_FLAG,
+  WS_DEV_ERR,
   WS_SCAN_TMP,
   WS_FLAGS,
   WS_BIN_META,
@@ -53,7 +54,11 @@ struct Options {
   int scheme = MIXED_AUTO;  // resolved to ROWS, GRAM or PIPE before any launch
   int64_t pipe_chunk = 0;   // list slots per pipeline chunk (0: the whole call)
   int64_t radius_scratch_mb = 8192;  // scratch rows of the one-pass radius search (MiB)
+  int capture_safe = 0;              // nonzero: no call waits for the device (see libgmls.h)
 };
+
+// Device error bits accumulated for gmls_check (capture-safe mode).
+enum DevErr { DEV_ERR_RADIUS_ROWS = 1, DEV_ERR_CAPACITY = 2, DEV_ERR_STENCIL_ROWS = 4 };
 
 }  // namespace gmls
 
@@ -64,8 +69,10 @@ struct gmls_ctx_s {
   std::vector<std::pair<void *, size_t>> slots;
   gmls::Options opt;
   hipEvent_t ev[8] = {};
+  int cus = 256;  // compute units of the device
 
-  // Device buffer of at least `bytes` for `slot`; nullptr on failure.
+  // Device buffer of at least `bytes` for `slot`; nullptr on failure (and,
+  // in capture-safe mode, when the slot would have to grow).
   void *ws(int slot, size_t bytes);
   ~gmls_ctx_s();
 };
@@ -138,9 +145,11 @@ hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const Stenci
                             hipStream_t s);
 // bytes of the pipeline's per-target record
 constexpr size_t kPipeRecBytes = 64;
+// hm: host copy of the bin table, or nullptr when the launches may not
+// depend on it (every bound then comes from `meta` on the device)
 hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a, const int *list,
-                             const BinMeta &hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt,
-                             double *mom, double *y, void *rec, int64_t chunk, int cus, hipStream_t s);
+                             const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt,
+                             double *mom, double *y, void *rec, int64_t chunk, int n_max, int cus, hipStream_t s);
 bool qr_supported(int dim, int order, int basis);
 bool mixed_supported(int dim, int order, int basis);
 // the scheme a request resolves to (MIXED_AUTO picks the fastest compiled
@@ -148,6 +157,15 @@ bool mixed_supported(int dim, int order, int basis);
 int mixed_scheme(int dim, int order, int basis, int requested);
 // FP64 moments of the pipeline per target (num_mono(dim, 2*order))
 int pipe_num_moments(int dim, int order);
+
+// device-side helpers (stencil_bins.hip): zero a buffer with a kernel (no
+// memset node in captured graphs); OR (src & mask) != 0 ? bit : 0 into *dst
+hipError_t fill_zero(void *p, size_t bytes, hipStream_t s);
+hipError_t or_error_bit(int *dst, const int *src, int mask, int bit, hipStream_t s);
+
+// exclusive scan of n ints (search.hip): out[0..n], tmp of scan_i32_tmp_words(n)
+int64_t scan_i32_tmp_words(int64_t n);
+hipError_t scan_i32_exclusive(const int *in, int *out, int64_t n, int *tmp, hipStream_t s);
 
 // binning (stencil_bins.hip)
 // temporary device bytes launch_binning needs for n_tgt targets

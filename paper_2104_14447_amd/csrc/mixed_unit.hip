@@ -52,12 +52,12 @@ hipError_t GMLS_FN(int bin, const StencilArgs &a, const int *list, BinMeta *meta
   }
 }
 
-hipError_t GMLS_PIPE_FN(const StencilArgs &a, const int *list, const BinMeta &hm, BinMeta *meta, int *fb,
+hipError_t GMLS_PIPE_FN(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
                         Stats *stats, const Options &opt, double *mom, double *y, void *rec, int64_t chunk,
-                        int cus, hipStream_t s) {
+                        int n_max, int cus, hipStream_t s) {
   constexpr int D = GMLS_DIM, O = GMLS_ORDER, B = GMLS_BASIS;
   if constexpr (B == 0 && has_pipe<D, O>()) {
-    return launch_pipe<D, O>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, cus, s);
+    return launch_pipe<D, O>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
   } else {
     return hipErrorInvalidValue;
   }

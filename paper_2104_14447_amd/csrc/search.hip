@@ -127,6 +127,12 @@ static int64_t scan_tmp_entries(int64_t n) {
   return (n + per - 1) / per + 2;
 }
 
+int64_t scan_i32_tmp_words(int64_t n) { return scan_tmp_entries(n); }
+
+hipError_t scan_i32_exclusive(const int *in, int *out, int64_t n, int *tmp, hipStream_t s) {
+  return exclusive_scan<int, int>(in, out, n, tmp, s);
+}
+
 // ---------------------------------------------------------------------------
 // grid construction
 // ---------------------------------------------------------------------------
@@ -567,6 +573,7 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
                                                                int32_t *col, double *eps, int *defer, int *n_defer,
                                                                uint8_t *dflag, int *flags) {
   constexpr bool ROWS = MODE != kCount;
+  if (MODE == kFill && (*flags & 2)) return;  // over capacity: nothing is written
   __shared__ double cxyz[3][kCellCap];
   __shared__ int cid[kCellCap];
   __shared__ int cbuf[kCellThreads / 64][ROWS ? kSmallCap : 1];
@@ -705,9 +712,15 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
   }
 }
 
+// Capture-safe mode: flag (bit 2) a total row count over the capacity.
+__global__ void k_check_capacity(const int64_t *nnz, int64_t capacity, int *flags) {
+  if (threadIdx.x == 0 && *nnz > capacity) atomicOr(flags, 2);
+}
+
 // Rows of the fused pass into place: 16 lanes per target.
 __global__ __launch_bounds__(256) void k_rows_copy(int64_t n_tgt, const int64_t *row_ptr, const int32_t *rows,
-                                                   const uint8_t *dflag, int32_t *col) {
+                                                   const uint8_t *dflag, int32_t *col, const int *flags) {
+  if (*flags & 2) return;  // over capacity: nothing is written
   const int sub = threadIdx.x & 15;
   const int64_t g0 = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 4);
@@ -767,7 +780,8 @@ __global__ __launch_bounds__(64) void k_radius_fill_list(const GridParams *gp, c
                                                          const int *cell_start, const double *targets,
                                                          const int *list, const int *n_list, double r0, int k_min,
                                                          const int64_t *row_ptr, int32_t *col, double *eps,
-                                                         int *overflow, int *n_overflow) {
+                                                         int *overflow, int *n_overflow, const int *flags) {
+  if (*flags & 2) return;  // over capacity: nothing is written
   __shared__ double d2[kSmallCap];
   __shared__ int idx[kSmallCap];
   const GridParams g = *gp;
@@ -829,7 +843,8 @@ template <int DIM>
 __global__ __launch_bounds__(64) void k_radius_fill_big(const GridParams *gp, const SPoint *pts,
                                                         const int *cell_start, const double *targets, double r0,
                                                         int k_min, const int64_t *row_ptr, int32_t *col, double *eps,
-                                                        const int *overflow, const int *n_overflow) {
+                                                        const int *overflow, const int *n_overflow, const int *flags) {
+  if (*flags & 2) return;  // over capacity: nothing is written
   __shared__ double d2[kCap];
   __shared__ int idx[kCap];
   const GridParams g = *gp;
@@ -911,6 +926,7 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
                                  int64_t col_capacity, double *eps, int64_t *nnz_host) {
   hipStream_t s = ctx->stream;
   const bool knn = spec.mode == GMLS_SEARCH_KNN;
+  const bool sync = !ctx->opt.capture_safe;  // capture-safe: nothing below waits for the device
   if (knn) {
     const int64_t nnz = n_tgt * (int64_t)spec.k;
     *nnz_host = nnz;
@@ -932,11 +948,11 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
 
   k_bbox_partial<<<nb_bbox, kBBoxBlock, 0, s>>>(coords, n_src, DIM, bbox);
   k_grid_setup<<<1, 64, 0, s>>>(bbox, (int)nb_bbox, DIM, knn ? 0 : 1, spec.radius, spec.k, n_src, ncell_max, gp);
-  GMLS_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)(ncell_max + 1), s));
-  GMLS_HIP(hipMemsetAsync(flags, 0, sizeof(int) * 4, s));
+  GMLS_HIP(fill_zero(cnt, sizeof(int) * (size_t)(ncell_max + 1), s));
+  GMLS_HIP(fill_zero(flags, sizeof(int) * 4, s));
   k_cell_keys<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(gp, coords, n_src, key, cnt);
   GMLS_HIP(exclusive_scan<int, int>(cnt, start, ncell_max, (int *)tmp, s));
-  GMLS_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)(ncell_max + 1), s));
+  GMLS_HIP(fill_zero(cnt, sizeof(int) * (size_t)(ncell_max + 1), s));
   k_cell_scatter<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(coords, n_src, key, start, cnt, sorted);
   GMLS_HIP(hipGetLastError());
   const int *tcs = start;  // target ranges per cell in `order`
@@ -947,10 +963,10 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
       GMLS_WS(tkey, int, WS_TGT_KEY, n_tgt);
       GMLS_WS(tcnt, int, WS_TGT_COUNT, ncell_max + 1);
       GMLS_WS(tstart, int, WS_TGT_START, ncell_max + 1);
-      GMLS_HIP(hipMemsetAsync(tcnt, 0, sizeof(int) * (size_t)(ncell_max + 1), s));
+      GMLS_HIP(fill_zero(tcnt, sizeof(int) * (size_t)(ncell_max + 1), s));
       k_cell_keys<DIM><<<grid_for(n_tgt, 256), 256, 0, s>>>(gp, targets, n_tgt, tkey, tcnt);
       GMLS_HIP(exclusive_scan<int, int>(tcnt, tstart, ncell_max, (int *)tmp, s));
-      GMLS_HIP(hipMemsetAsync(tcnt, 0, sizeof(int) * (size_t)(ncell_max + 1), s));
+      GMLS_HIP(fill_zero(tcnt, sizeof(int) * (size_t)(ncell_max + 1), s));
       k_index_scatter<<<grid_for(n_tgt, 256), 256, 0, s>>>(n_tgt, tkey, tstart, tcnt, order);
       tcs = tstart;
     }
@@ -962,18 +978,13 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
       k_knn<DIM><<<(unsigned)n_tgt, 64, 0, s>>>(gp, sorted, start, targets, order, n_tgt, spec.k, spec.eps_mult,
                                                 col, eps);
     GMLS_HIP(hipGetLastError());
-    GMLS_HIP(hipStreamSynchronize(s));
+    if (sync) GMLS_HIP(hipStreamSynchronize(s));
     return GMLS_OK;
   }
   GMLS_WS(counts, int64_t, WS_ROW_COUNT, n_tgt > 0 ? n_tgt : 1);
   GMLS_WS(defer, int, WS_DEFER, 2 * (n_tgt > 0 ? n_tgt : 1));
   // flags: [0] error bits, [1] overflow count, [2] deferred (count pass), [3] deferred (fill pass)
-  int cus = 256;
-  {
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
-      cus = prop.multiProcessorCount;
-  }
+  const int cus = ctx->cus;
   const unsigned nb_cells = (unsigned)xcd_grid(cus * 6);
   // one pass with a scratch row per target when that fits the budget,
   // otherwise a count pass and a fill pass
@@ -999,23 +1010,30 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
                                                  spec.k_min, counts, flags);
   }
   GMLS_HIP(exclusive_scan<int64_t, int64_t>(counts, row_ptr, n_tgt, tmp, s));
-  int64_t nnz = 0;
-  int hflags = 0;
-  GMLS_HIP(hipMemcpyAsync(&nnz, row_ptr + n_tgt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  GMLS_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  GMLS_HIP(hipStreamSynchronize(s));
-  *nnz_host = nnz;
-  if (hflags & 1)
-    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 2048 sources inside the radius");
-  if (nnz > col_capacity)
-    return gmls_set_error(ctx, GMLS_ERR_CAPACITY,
-                          "col_capacity " + std::to_string(col_capacity) + " < required " + std::to_string(nnz));
+  if (sync) {
+    int64_t nnz = 0;
+    int hflags = 0;
+    GMLS_HIP(hipMemcpyAsync(&nnz, row_ptr + n_tgt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    GMLS_HIP(hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    GMLS_HIP(hipStreamSynchronize(s));
+    *nnz_host = nnz;
+    if (hflags & 1)
+      return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 2048 sources inside the radius");
+    if (nnz > col_capacity)
+      return gmls_set_error(ctx, GMLS_ERR_CAPACITY,
+                            "col_capacity " + std::to_string(col_capacity) + " < required " + std::to_string(nnz));
+  } else {
+    // the size is known on the device only: the kernels that write `col`
+    // skip their writes when it exceeds the capacity (flag bit 2)
+    *nnz_host = -1;
+    k_check_capacity<<<1, 64, 0, s>>>(row_ptr + n_tgt, col_capacity, flags);
+  }
   if (n_tgt > 0) {
     int *defer_fill = defer;
     int *n_defer_fill = flags + 2;
     int *overflow = (int *)counts;  // the counts are consumed by the scan
     if (fused) {
-      k_rows_copy<<<grid_for(n_tgt, 16), 256, 0, s>>>(n_tgt, row_ptr, rows, dflag, col);
+      k_rows_copy<<<grid_for(n_tgt, 16), 256, 0, s>>>(n_tgt, row_ptr, rows, dflag, col, flags);
     } else {
       defer_fill = defer + n_tgt;
       n_defer_fill = flags + 3;
@@ -1024,12 +1042,18 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
                                                                     eps, defer_fill, n_defer_fill, nullptr, flags);
     }
     k_radius_fill_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, defer_fill, n_defer_fill, spec.radius,
-                                                spec.k_min, row_ptr, col, eps, overflow, flags + 1);
+                                                spec.k_min, row_ptr, col, eps, overflow, flags + 1, flags);
     k_radius_fill_big<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, spec.radius, spec.k_min, row_ptr, col,
-                                               eps, overflow, flags + 1);
+                                               eps, overflow, flags + 1, flags);
   }
   GMLS_HIP(hipGetLastError());
-  GMLS_HIP(hipStreamSynchronize(s));
+  if (sync) {
+    GMLS_HIP(hipStreamSynchronize(s));
+  } else {
+    int *de = (int *)ctx->ws(WS_DEV_ERR, sizeof(int));
+    GMLS_HIP(or_error_bit(de, flags, 1, DEV_ERR_RADIUS_ROWS, s));
+    GMLS_HIP(or_error_bit(de, flags, 2, DEV_ERR_CAPACITY, s));
+  }
   return GMLS_OK;
 }
 

@@ -4,14 +4,14 @@
 // fewer sample rows than basis functions (rank deficient by construction);
 // bin b >= 1 holds 64*(b-1) < N <= 64*b.  Each bin is a contiguous slice of
 // one packed index list.  Inside a bin the targets follow a Morton (Z-order)
-// curve over the targets' bounding box: consecutive targets are spatial
-// neighbours, so their neighbour rows overlap and the coordinate gathers of
-// the stencil kernels hit in cache.  The list is the value array of one
-// radix sort of (bin, Morton code) keys.
+// curve of cells over the targets' bounding box: consecutive targets are
+// spatial neighbours, so their neighbour rows overlap and the coordinate
+// gathers of the stencil kernels hit in cache.  The list comes from one
+// counting sort over (bin, Morton cell) buckets; the order inside a bucket
+// (a few targets) is that of the atomic counter and does not affect any
+// result.  No step waits for the host, and no buffer is cleared by a memset.
 #include <float.h>
 #include <math.h>
-
-#include <hipcub/hipcub.hpp>
 
 #include "common.hpp"
 #include "gmls_internal.hpp"
@@ -24,32 +24,6 @@ __device__ __forceinline__ int bin_of(int64_t n, int Q, int C) {
   if (n * C < Q) return 0;
   if (n > kMaxRows) return -1;
   return (int)((n + 63) / 64);
-}
-
-__global__ __launch_bounds__(kBinBlock) void k_bin_count(const int64_t *row_ptr, int n_tgt, int Q, int C,
-                                                         BinMeta *meta) {
-  __shared__ int cnt[kNumBins];
-  if (threadIdx.x < kNumBins) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tgt; t += gridDim.x * blockDim.x) {
-    const int b = bin_of(row_ptr[t + 1] - row_ptr[t], Q, C);
-    if (b < 0)
-      atomicOr(&meta->err, 1);
-    else
-      atomicAdd(&cnt[b], 1);
-  }
-  __syncthreads();
-  if (threadIdx.x < kNumBins && cnt[threadIdx.x]) atomicAdd(&meta->count[threadIdx.x], cnt[threadIdx.x]);
-}
-
-__global__ void k_bin_offsets(BinMeta *meta) {
-  if (threadIdx.x != 0) return;
-  int acc = 0;
-  for (int b = 0; b < kNumBins; ++b) {
-    meta->offset[b] = acc;
-    meta->cursor[b] = 0;
-    acc += meta->count[b];
-  }
 }
 
 // ---- target bounding box (two stages) ----
@@ -127,51 +101,87 @@ __device__ __forceinline__ unsigned quant(double v, double lo, double inv, int b
   return (unsigned)c;
 }
 
-// key = bin in bits 28-30 (7 for rows over the compiled maximum) | Morton
-// code in bits 0-27 (3D: 9 bits per axis, 2D: 13, 1D: 26)
-__global__ __launch_bounds__(256) void k_bin_keys(const int64_t *row_ptr, const double *x, int n_tgt, int dim,
-                                                  int Q, int C, const double *box, BinMeta *meta, unsigned *key,
-                                                  int *val) {
+constexpr int kCellBits = 18;                  // Morton cells per bin
+constexpr int64_t kBuckets = 8ll << kCellBits;  // bins 0..7 (7: rows over the maximum)
+
+// bucket = bin << 18 | Morton cell (3D: 6 bits per axis, 2D: 9, 1D: 18);
+// rank = the target's place in its bucket
+__global__ __launch_bounds__(256) void k_bucket_rank(const int64_t *row_ptr, const double *x, int n_tgt, int dim,
+                                                     int Q, int C, const double *box, int *cnt, int *bucket,
+                                                     int *rank) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tgt; t += gridDim.x * blockDim.x) {
     int b = bin_of(row_ptr[t + 1] - row_ptr[t], Q, C);
     if (b < 0) b = 7;
     unsigned m;
     if (dim == 3)
-      m = spread3(quant(x[(int64_t)t * 3], box[0], box[3], 9)) |
-          (spread3(quant(x[(int64_t)t * 3 + 1], box[1], box[4], 9)) << 1) |
-          (spread3(quant(x[(int64_t)t * 3 + 2], box[2], box[5], 9)) << 2);
+      m = spread3(quant(x[(int64_t)t * 3], box[0], box[3], 6)) |
+          (spread3(quant(x[(int64_t)t * 3 + 1], box[1], box[4], 6)) << 1) |
+          (spread3(quant(x[(int64_t)t * 3 + 2], box[2], box[5], 6)) << 2);
     else if (dim == 2)
-      m = spread2(quant(x[(int64_t)t * 2], box[0], box[3], 13)) |
-          (spread2(quant(x[(int64_t)t * 2 + 1], box[1], box[4], 13)) << 1);
+      m = spread2(quant(x[(int64_t)t * 2], box[0], box[3], 9)) |
+          (spread2(quant(x[(int64_t)t * 2 + 1], box[1], box[4], 9)) << 1);
     else
-      m = quant(x[t], box[0], box[3], 26);
-    key[t] = ((unsigned)b << 28) | m;
-    val[t] = t;
+      m = quant(x[t], box[0], box[3], kCellBits);
+    const int key = (b << kCellBits) | (int)m;
+    bucket[t] = key;
+    rank[t] = atomicAdd(&cnt[key], 1);
   }
 }
 
-__global__ void k_bin_reset(BinMeta *meta) {
+__global__ __launch_bounds__(256) void k_bucket_scatter(int n_tgt, const int *bucket, const int *rank,
+                                                        const int *start, int *list) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tgt; t += gridDim.x * blockDim.x)
+    list[start[bucket[t]] + rank[t]] = t;
+}
+
+// bin table from the bucket starts
+__global__ void k_bin_table(const int *start, BinMeta *meta) {
   if (threadIdx.x != 0) return;
-  for (int b = 0; b < kNumBins; ++b) meta->cursor[b] = 0;
+  for (int b = 0; b < kNumBins; ++b) {
+    meta->offset[b] = start[(int64_t)b << kCellBits];
+    meta->count[b] = start[(int64_t)(b + 1) << kCellBits] - meta->offset[b];
+    meta->cursor[b] = 0;
+  }
+  meta->err = start[kBuckets] - start[(int64_t)7 << kCellBits] > 0 ? 1 : 0;
   meta->fb_count = 0;
   meta->fb_cursor = 0;
 }
 
-static size_t sort_bytes(int n_tgt) {
-  size_t bytes = 0;
-  hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const unsigned *)nullptr, (unsigned *)nullptr,
-                                     (const int *)nullptr, (int *)nullptr, n_tgt, 0, 31);
-  return bytes;
+
+__global__ void k_fill_zero(uint32_t *p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
 }
 
-// layout of the temporary buffer: partial boxes, box, keys in, keys out,
-// values in, then the sort's own storage (256-byte aligned)
-static size_t sort_offset(int n_tgt) {
-  const size_t off = sizeof(double) * (6 * kBoxBlocks + 6) + (2 * sizeof(unsigned) + sizeof(int)) * (size_t)n_tgt;
-  return (off + 255) & ~(size_t)255;
+// Buffers cleared here are whole 32-bit words (counters, tables, flags).
+hipError_t fill_zero(void *p, size_t bytes, hipStream_t s) {
+  const int64_t words = (int64_t)(bytes / 4);
+  if (words == 0) return hipSuccess;
+  int64_t g = (words + 255) / 256;
+  if (g > 4096) g = 4096;
+  k_fill_zero<<<(unsigned)g, 256, 0, s>>>((uint32_t *)p, words);
+  return hipGetLastError();
 }
 
-size_t binning_temp_bytes(int n_tgt) { return sort_offset(n_tgt) + sort_bytes(n_tgt); }
+__global__ void k_or_error_bit(int *dst, const int *src, int mask, int bit) {
+  if (threadIdx.x == 0 && (*src & mask)) atomicOr(dst, bit);
+}
+
+hipError_t or_error_bit(int *dst, const int *src, int mask, int bit, hipStream_t s) {
+  k_or_error_bit<<<1, 64, 0, s>>>(dst, src, mask, bit);
+  return hipGetLastError();
+}
+
+// layout of the temporary buffer (8-byte aligned pieces): partial boxes,
+// box, bucket counters, bucket starts, per-target bucket and rank, scan
+// scratch
+static size_t scan_words(int n_tgt) { (void)n_tgt; return (size_t)scan_i32_tmp_words(kBuckets); }
+
+size_t binning_temp_bytes(int n_tgt) {
+  const size_t nb = (size_t)(n_tgt > 0 ? n_tgt : 1);
+  return sizeof(double) * (6 * kBoxBlocks + 6) + sizeof(int) * ((size_t)kBuckets + (size_t)kBuckets + 2 + 2 * nb) +
+         sizeof(int) * scan_words(n_tgt) + 64;
+}
 
 hipError_t launch_binning(const int64_t *row_ptr, const double *targets, int n_tgt, int dim, int Q, int C,
                           BinMeta *meta, int *list, void *temp, size_t temp_bytes, hipStream_t s) {
@@ -179,24 +189,23 @@ hipError_t launch_binning(const int64_t *row_ptr, const double *targets, int n_t
   if (g < 1) g = 1;
   if (g > 4096) g = 4096;
   if (temp_bytes < binning_temp_bytes(n_tgt)) return hipErrorInvalidValue;
-  char *p = (char *)temp;
-  double *partial = (double *)p;
+  double *partial = (double *)temp;
   double *box = partial + 6 * kBoxBlocks;
-  unsigned *kin = (unsigned *)(box + 6);
-  unsigned *kout = kin + n_tgt;
-  int *vin = (int *)(kout + n_tgt);
-  size_t sb = temp_bytes - sort_offset(n_tgt);
-  hipError_t e = hipMemsetAsync(meta, 0, sizeof(BinMeta), s);
+  int *cnt = (int *)(box + 6);
+  int *start = cnt + kBuckets;
+  int *bucket = start + kBuckets + 2;
+  int *rank = bucket + n_tgt;
+  int *stmp = rank + n_tgt;
+  hipError_t e = fill_zero(cnt, sizeof(int) * (size_t)kBuckets, s);
+  if (e == hipSuccess) e = fill_zero(meta, sizeof(BinMeta), s);
   if (e != hipSuccess) return e;
-  k_bin_count<<<g, kBinBlock, 0, s>>>(row_ptr, n_tgt, Q, C, meta);
-  k_bin_offsets<<<1, 64, 0, s>>>(meta);
   k_tbox_partial<<<kBoxBlocks, 256, 0, s>>>(targets, n_tgt, dim, partial);
   k_tbox_final<<<1, 64, 0, s>>>(partial, kBoxBlocks, box);
-  k_bin_keys<<<g, kBinBlock, 0, s>>>(row_ptr, targets, n_tgt, dim, Q, C, box, meta, kin, vin);
-  e = hipcub::DeviceRadixSort::SortPairs((void *)(p + sort_offset(n_tgt)), sb, kin, kout, vin, list, n_tgt, 0, 31,
-                                         s);
+  k_bucket_rank<<<g, kBinBlock, 0, s>>>(row_ptr, targets, n_tgt, dim, Q, C, box, cnt, bucket, rank);
+  e = scan_i32_exclusive(cnt, start, kBuckets, stmp, s);
   if (e != hipSuccess) return e;
-  k_bin_reset<<<1, 64, 0, s>>>(meta);
+  k_bucket_scatter<<<g, kBinBlock, 0, s>>>(n_tgt, bucket, rank, start, list);
+  k_bin_table<<<1, 64, 0, s>>>(start, meta);
   return hipGetLastError();
 }
 

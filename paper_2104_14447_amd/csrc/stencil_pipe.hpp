@@ -22,6 +22,7 @@
 #pragma once
 
 #include <float.h>
+#include <limits.h>
 #include <math.h>
 
 #include "basis.hpp"
@@ -45,8 +46,35 @@ struct PipeRec {
 };
 static_assert(sizeof(PipeRec) == kPipeRecBytes, "record size");
 
+// List slots a launch covers: bin `bin` (0: bins 1..4 together) clipped to
+// the window [win_lo, win_hi); win_lo < 0 opens the window at the first slot
+// of bin 1.  c0 is the window's first slot (records and buffers are indexed
+// from it).  The bounds come from the device bin table, so a launch needs no
+// host copy of it.
+struct SlotRange {
+  int first, last, c0;
+};
+
+__device__ __forceinline__ SlotRange slot_range(const BinMeta *meta, int bin, int win_lo, int win_hi) {
+  const int c0 = win_lo >= 0 ? win_lo : meta->offset[1];
+  int lo, hi;
+  if (bin > 0) {
+    lo = meta->offset[bin];
+    hi = lo + meta->count[bin];
+  } else {
+    lo = meta->offset[1];
+    hi = meta->offset[kNumBins - 1] + meta->count[kNumBins - 1];
+  }
+  lo = lo > c0 ? lo : c0;
+  hi = hi < win_hi ? hi : win_hi;
+  return {readfirstlane_i(lo), readfirstlane_i(hi), readfirstlane_i(c0)};
+}
+
 template <int DIM>
-__global__ __launch_bounds__(256) void k_pipe_prep(StencilArgs a, const int *list, int first, int last, PipeRec *rec) {
+__global__ __launch_bounds__(256) void k_pipe_prep(StencilArgs a, const int *list, const BinMeta *meta, int win_lo,
+                                                   int win_hi, PipeRec *rec) {
+  const SlotRange R = slot_range(meta, 0, win_lo, win_hi);
+  const int first = R.first, last = R.last;
   for (int i = first + blockIdx.x * blockDim.x + threadIdx.x; i < last; i += gridDim.x * blockDim.x) {
     const int t = list[i];
     PipeRec r;
@@ -57,7 +85,7 @@ __global__ __launch_bounds__(256) void k_pipe_prep(StencilArgs a, const int *lis
     for (int d = 0; d < 3; ++d) r.x[d] = d < DIM ? a.targets[(int64_t)t * DIM + d] : 0.0;
     r.ok = 0;
     r.pad = 0;
-    rec[i - first] = r;
+    rec[i - R.c0] = r;
   }
 }
 
@@ -166,7 +194,9 @@ __device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, boo
 // group writes its target's moments contiguously).
 template <int DIM, int ORDER, int G, int RPL>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_pipe_moments(
-    StencilArgs a, const PipeRec *rec, int first, int last, int c0, double *mom) {
+    StencilArgs a, const PipeRec *rec, const BinMeta *meta, int bin, int win_lo, int win_hi, double *mom) {
+  const SlotRange R = slot_range(meta, bin, win_lo, win_hi);
+  const int first = R.first, last = R.last, c0 = R.c0;
   constexpr int TPW = 64 / G;
   const int lane = lane_id();
   const int grp = lane / G, lg = lane % G;
@@ -231,9 +261,9 @@ struct MomentPairs {
 };
 
 template <int DIM, int ORDER>
-__global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, int first, int last, int c0,
-                                                   const double *mom, double *yout, int *fb_list,
-                                                   BinMeta *meta, Stats *stats, Options opt) {
+__global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, int win_lo, int win_hi,
+                                                   const double *mom, double *yout, int *fb_list, BinMeta *meta,
+                                                   Stats *stats, Options opt) {
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int NP = Q * (Q + 1) / 2;
   constexpr InvFact64<DIM, ORDER> IF{};
@@ -246,6 +276,8 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, 
   const int lane = lane_id();
   const RowKinds rk = row_kinds(DIM, 0, a.mask);
   const int F = a.F;
+  const SlotRange R = slot_range(meta, 0, win_lo, win_hi);
+  const int first = R.first, last = R.last, c0 = R.c0;
   for (int slot = first + xcd_block() * 64 + lane; slot - lane < last; slot += gridDim.x * 64) {
     const bool valid = slot < last;
     const int sl = valid ? slot : first;
@@ -416,8 +448,10 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, 
 // F functional rows (compile time, so that the group's solutions stay in
 // registers: F*Q doubles per lane).
 template <int DIM, int ORDER, int G, int RPL, int F>
-__global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRec *rec, int first, int last,
-                                                     int c0, const double *yin) {
+__global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRec *rec, const BinMeta *meta, int bin,
+                                                     int win_lo, int win_hi, const double *yin) {
+  const SlotRange R = slot_range(meta, bin, win_lo, win_hi);
+  const int first = R.first, last = R.last, c0 = R.c0;
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int TPW = 64 / G;
   const int lane = lane_id();
@@ -469,65 +503,81 @@ constexpr bool has_pipe() {
 }
 
 template <int DIM, int ORDER, int G, int RPL>
-static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *rec, int lo, int hi, int c0,
-                            double *buf, int cus, hipStream_t s) {
+static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *rec, const BinMeta *meta, int bin,
+                            int win_lo, int win_hi, int n_max, double *buf, int cus, hipStream_t s) {
   constexpr int TPW = 64 / G;
-  int nb = (hi - lo + TPW - 1) / TPW;
+  int nb = (n_max + TPW - 1) / TPW;
   if (nb > cus * 32) nb = cus * 32;
   nb = xcd_grid(nb);
   if (!weights) {
-    k_pipe_moments<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf);
+    k_pipe_moments<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
     return;
   }
   switch (a.F) {  // scalar basis: value + up to DIM gradient rows + Laplacian
-    case 1: k_pipe_weights<DIM, ORDER, G, RPL, 1><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf); break;
-    case 2: k_pipe_weights<DIM, ORDER, G, RPL, 2><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf); break;
-    case 3: k_pipe_weights<DIM, ORDER, G, RPL, 3><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf); break;
-    case 4: k_pipe_weights<DIM, ORDER, G, RPL, 4><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf); break;
+    case 1: k_pipe_weights<DIM, ORDER, G, RPL, 1><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 2: k_pipe_weights<DIM, ORDER, G, RPL, 2><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 3: k_pipe_weights<DIM, ORDER, G, RPL, 3><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 4: k_pipe_weights<DIM, ORDER, G, RPL, 4><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
     default:
-      if constexpr (DIM == 3) k_pipe_weights<DIM, ORDER, G, RPL, 5><<<nb, 64, 0, s>>>(a, rec, lo, hi, c0, buf);
+      if constexpr (DIM == 3)
+        k_pipe_weights<DIM, ORDER, G, RPL, 5><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
       break;
   }
 }
 
-// bins 1..4 occupy list slots [count[0], n) contiguously, in bin order;
+// The pipeline over list slots [count[0], n) (bins 1..4, contiguous, in bin
+// order).  With a host copy of the bin table (hm) it runs in chunks of
+// `chunk` slots and skips empty bins; without one (hm == nullptr: nothing
+// may wait for the device) it covers every slot in one window, all bounds
+// read from the device table, grids sized for n_max slots.
 // lanes x rows per lane: bin 1 (<= 64 rows) 8 x 8, bin 2 (<= 128) 16 x 8,
 // bin 3 (<= 192) 32 x 6, bin 4 (<= 256) 32 x 8.
 template <int DIM, int ORDER>
-hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta &hm, BinMeta *meta, int *fb,
+hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
                        Stats *stats, const Options &opt, double *mom, double *y, PipeRec *rec, int64_t chunk,
-                       int cus, hipStream_t s) {
-  const int begin = hm.offset[1];
-  const int end = hm.offset[kNumBins - 1] + hm.count[kNumBins - 1];
+                       int n_max, int cus, hipStream_t s) {
+  int begin = 0, end = 1;
+  if (hm) {
+    begin = hm->offset[1];
+    end = hm->offset[kNumBins - 1] + hm->count[kNumBins - 1];
+  } else {
+    chunk = 1;
+  }
   for (int64_t c0 = begin; c0 < end; c0 += chunk) {
-    const int c1 = (int)(c0 + chunk < end ? c0 + chunk : end);
+    const int win_lo = hm ? (int)c0 : -1;
+    const int win_hi = hm ? (int)(c0 + chunk < end ? c0 + chunk : end) : INT_MAX;
+    const int n_win = hm ? win_hi - win_lo : n_max;
     {
-      int nbp = (int)((c1 - c0 + 255) / 256);
+      int nbp = (n_win + 255) / 256;
       if (nbp > cus * 8) nbp = cus * 8;
-      k_pipe_prep<DIM><<<nbp, 256, 0, s>>>(a, list, (int)c0, c1, rec);
+      if (nbp < 1) nbp = 1;
+      k_pipe_prep<DIM><<<nbp, 256, 0, s>>>(a, list, meta, win_lo, win_hi, rec);
     }
     for (int pass = 0; pass < 2; ++pass) {
       if (pass == 1) {
-        int nb = (int)((c1 - c0 + 63) / 64);
+        int nb = (n_win + 63) / 64;
         if (nb > cus * 16) nb = cus * 16;
         nb = xcd_grid(nb);
-        k_pipe_solve<DIM, ORDER><<<nb, 64, 0, s>>>(a, rec, (int)c0, c1, (int)c0, mom, y, fb, meta,
-                                                      stats, opt);
+        k_pipe_solve<DIM, ORDER><<<nb, 64, 0, s>>>(a, rec, win_lo, win_hi, mom, y, fb, meta, stats, opt);
       }
       const bool wts = pass == 1;
       for (int b = 1; b < kNumBins; ++b) {
-        const int lo = hm.offset[b] > c0 ? hm.offset[b] : (int)c0;
-        const int hi = hm.offset[b] + hm.count[b] < c1 ? hm.offset[b] + hm.count[b] : c1;
-        if (lo >= hi) continue;
+        int nbin = n_max;
+        if (hm) {
+          const int lo = hm->offset[b] > win_lo ? hm->offset[b] : win_lo;
+          const int hi = hm->offset[b] + hm->count[b] < win_hi ? hm->offset[b] + hm->count[b] : win_hi;
+          if (lo >= hi) continue;
+          nbin = hi - lo;
+        }
         double *buf = wts ? y : mom;
         if (b == 1)
-          pipe_bin_launch<DIM, ORDER, 8, 8>(wts, a, rec, lo, hi, (int)c0, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 8, 8>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 2)
-          pipe_bin_launch<DIM, ORDER, 16, 8>(wts, a, rec, lo, hi, (int)c0, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 16, 8>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 3)
-          pipe_bin_launch<DIM, ORDER, 32, 6>(wts, a, rec, lo, hi, (int)c0, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 32, 6>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else
-          pipe_bin_launch<DIM, ORDER, 32, 8>(wts, a, rec, lo, hi, (int)c0, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 32, 8>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
       }
     }
   }

@@ -20,7 +20,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     assert names == sorted(["gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
-                            "gmls_stencil_shape", "gmls_stencils", "gmls_apply"])
+                            "gmls_stencil_shape", "gmls_stencils", "gmls_apply", "gmls_check"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -35,6 +35,15 @@ def test_library_exports_every_declared_symbol():
     L = G.load_library()
     for name in G.EXPORTED_SYMBOLS:
         assert hasattr(L, name)
+
+
+def test_library_has_no_unresolved_internal_symbols():
+    import paper_2104_14447_amd as G
+
+    if not os.path.exists(G.LIB_PATH):
+        pytest.skip("libgmls.so not built")
+    out = subprocess.run(["nm", "-D", "--undefined-only", G.LIB_PATH], capture_output=True, text=True).stdout
+    assert "gmls" not in out, out
 
 
 @pytest.mark.parametrize("dim,order,basis,mask,expect", [

@@ -1,0 +1,102 @@
+"""Capture-safe mode (GMLS_OPT_CAPTURE_SAFE): search + stencils captured into
+one HIP graph and replayed.
+
+Every replay is checked against the eager result of the normal mode, with
+eager work (the output buffers are overwritten) and synchronisations between
+the replays.  The capture-safe mode is also checked eagerly, and its
+deferred error reporting (gmls_check) is checked on a capacity overflow."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_helpers import dev, flush, host, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+N = 20000
+K_MIN = 30
+
+
+def case():
+    pts = W.density_ramp(N, 1004)
+    return pts, W.radius_for_mean_count(N)
+
+
+def run_normal(G, c, x, r0, prec, scheme=0):
+    c.set_option(G.OPT_MIXED_SCHEME, scheme)
+    rp, col, eps = G.gmls_neighbors(c, x, x, G.SEARCH_RADIUS, radius=r0, k_min=K_MIN)
+    w, st, _ = G.gmls_stencils(c, x, x, 3, G.BASIS_SCALAR, G.F_LAPLACIAN | G.F_GRAD, 4, eps, rp, col, prec=prec)
+    return [host(v) for v in (rp, col, eps, w, st)]
+
+
+@pytest.mark.parametrize("prec,scheme", [(0, 0), (1, 3), (1, 1)], ids=["fp64", "mixed-pipe", "mixed-rows"])
+def test_graph_replays_match_eager(prec, scheme):
+    G = require_gpu()
+    pts, r0 = case()
+    s = torch.cuda.Stream()
+    c = G.Context(0, stream=s)
+    with torch.cuda.stream(s):
+        x = dev(pts)
+        flush(f"graph: eager reference prec={prec} scheme={scheme}")
+        ref = run_normal(G, c, x, r0, prec, scheme)
+        nnz = len(ref[1])
+        F, C, _ = G.gmls_stencil_shape(3, 3, G.BASIS_SCALAR, G.F_LAPLACIAN | G.F_GRAD)
+        col_buf = torch.empty(nnz + 4096, dtype=torch.int32, device="cuda")
+        w_buf = torch.empty(F * C * nnz, dtype=torch.float64, device="cuda")
+        st_buf = torch.empty(N, dtype=torch.uint8, device="cuda")
+        c.set_option(G.OPT_CAPTURE_SAFE, 1)
+        outs = {}
+
+        def step():
+            rp, col, eps = G.gmls_neighbors(c, x, x, G.SEARCH_RADIUS, radius=r0, k_min=K_MIN, col=col_buf)
+            G.gmls_stencils(c, x, x, 3, G.BASIS_SCALAR, G.F_LAPLACIAN | G.F_GRAD, 4, eps, rp, col[:nnz], prec=prec,
+                            weights=w_buf, status=st_buf)
+            outs["rp"], outs["eps"] = rp, eps
+
+        def compare(tag):
+            s.synchronize()
+            got = [host(outs["rp"]), host(col_buf[:nnz]), host(outs["eps"]), host(w_buf), host(st_buf)]
+            for name, a, b in zip(("row_ptr", "col", "eps", "weights", "status"), got, ref):
+                assert np.array_equal(a, b), f"{tag}: {name} differs"
+            c.check()
+
+        flush("graph: capture-safe eager")
+        step()
+        compare("capture-safe eager")
+        g = torch.cuda.CUDAGraph()
+        flush("graph: capture")
+        with torch.cuda.graph(g, stream=s):
+            step()
+        for rep in range(3):
+            # eager work between replays: clobber every output
+            col_buf.fill_(-7)
+            w_buf.fill_(float("nan"))
+            st_buf.fill_(255)
+            outs["eps"].fill_(-1.0)
+            s.synchronize()
+            flush(f"graph: replay {rep}")
+            g.replay()
+            compare(f"replay {rep}")
+    c.close()
+
+
+def test_capture_safe_reports_capacity_through_check():
+    G = require_gpu()
+    pts, r0 = case()
+    s = torch.cuda.Stream()
+    c = G.Context(0, stream=s)
+    with torch.cuda.stream(s):
+        x = dev(pts)
+        ref = run_normal(G, c, x, r0, 0)
+        small = torch.full((len(ref[1]) // 2,), -3, dtype=torch.int32, device="cuda")
+        c.set_option(G.OPT_CAPTURE_SAFE, 1)
+        flush("capture-safe capacity overflow")
+        rp, col, eps = G.gmls_neighbors(c, x, x, G.SEARCH_RADIUS, radius=r0, k_min=K_MIN, col=small)
+        with pytest.raises(G.GmlsError) as e:
+            c.check()
+        assert e.value.status == G.GMLS_ERR_CAPACITY
+        assert (host(small) == -3).all(), "col was written despite the overflow"
+        assert host(rp)[-1] == len(ref[1])
+        c.check()  # the record is cleared
+    c.close()
