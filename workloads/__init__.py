@@ -29,6 +29,7 @@ __all__ = [
     "density_ramp",
     "radius_for_mean_count",
     "WORKLOADS",
+    "boundary_points",
     "make_points",
     "random_poly_coeffs",
     "monomial_exponents",
@@ -57,6 +58,19 @@ def jittered_grid(n_points: int, dim: int, seed: int, jitter: float = 0.25) -> n
     g = rng(seed)
     pts = pts + g.uniform(-jitter * h, jitter * h, size=pts.shape)
     return np.ascontiguousarray(pts[:n_points])
+
+
+def boundary_points(n_points: int, dim: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Points uniform on the boundary of [0,1]^dim (a face chosen uniformly,
+    then a uniform point on it) and their outward unit normals."""
+    g = rng(seed)
+    face = g.integers(0, 2 * dim, size=n_points)
+    pts = g.uniform(0.0, 1.0, size=(n_points, dim))
+    nrm = np.zeros((n_points, dim))
+    axis, side = face // 2, face % 2
+    pts[np.arange(n_points), axis] = side.astype(np.float64)
+    nrm[np.arange(n_points), axis] = np.where(side == 1, 1.0, -1.0)
+    return np.ascontiguousarray(pts), nrm
 
 
 def density_ramp(n_points: int, seed: int, batch: int = 1 << 22) -> np.ndarray:
