@@ -212,6 +212,28 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
  * with a message in gmls_last_error.  Synchronises; clears the record. */
 gmls_status gmls_check(gmls_ctx ctx);
 
+/* Neumann-constrained stencils (Section 2.3): for boundary targets the local
+ * weighted least-squares fit is solved subject to n . grad u(x_T) = h(x_T),
+ * with the outward normal n of target T, through the bordered system
+ *   [P^T W P   F] [c]   [P^T W u]
+ *   [F^T       0] [mu] = [h      ],   F = grad p(x_T)^T n.
+ * A functional lambda of the constrained fit is then
+ *   lambda^T c = sum_j alpha_j u_j + beta h(x_T),
+ * the stencil alpha (layout as in gmls_stencils) plus one boundary weight
+ * beta per target and functional row.
+ *   normals   [n_tgt][dim] FP64 (need not be unit vectors: the constraint is
+ *             on n . grad u; a zero vector leaves that target unconstrained,
+ *             beta = 0)
+ *   h_weights out: [n_tgt][F] FP64, beta of each functional row
+ * Scalar basis only; prec must be GMLS_PREC_FP64 (else
+ * GMLS_ERR_UNSUPPORTED).  Other arguments, statuses and errors as for
+ * gmls_stencils; rank-deficient targets get NaN in both outputs. */
+gmls_status gmls_stencils_constrained(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                      int64_t n_tgt, int dim, int order, unsigned functional_mask, int weight_p,
+                                      const double *eps, const int64_t *row_ptr, const int32_t *col,
+                                      const double *normals, int prec, double *weights, double *h_weights,
+                                      uint8_t *target_status, gmls_report *report);
+
 /* Apply stencils to a field (Section 3.2, the stencil sum over neighbours):
  *   out[t*F + f] = sum_j sum_c weights[F*C_in*row_ptr[t] + (f*N_t + j)*C_in + c]
  *                               * field[col[row_ptr[t] + j]*C_in + c]

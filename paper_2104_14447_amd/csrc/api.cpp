@@ -223,10 +223,14 @@ gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, co
   return run_neighbors(ctx, coords, n_src, targets, n_tgt, dim, *spec, row_ptr, col, col_capacity, eps, nnz_host);
 }
 
-gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
-                          int64_t n_tgt, int dim, int order, int basis, unsigned functional_mask, int weight_p,
-                          const double *eps, const int64_t *row_ptr, const int32_t *col, int prec,
-                          double *weights, uint8_t *target_status, gmls_report *report) {
+}  // extern "C"
+
+// plain (normals == nullptr) and Neumann-constrained stencils
+static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                int64_t n_tgt, int dim, int order, int basis, unsigned functional_mask, int weight_p,
+                                const double *eps, const int64_t *row_ptr, const int32_t *col,
+                                const double *normals, int prec, double *weights, double *hweights,
+                                uint8_t *target_status, gmls_report *report) {
   if (!ctx) return GMLS_ERR_ARG;
   ctx->err.clear();
   int F = 0, C = 0, Q = 0;
@@ -248,6 +252,13 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
     return gmls_set_error(ctx, GMLS_ERR_ARG, "n_src must be >= 1 and n_tgt in [0, 2^31)");
   if (n_tgt > 0 && (!coords || !targets || !eps || !row_ptr || !col || !weights))
     return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  if (normals) {
+    if (basis != GMLS_BASIS_SCALAR)
+      return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "the Neumann constraint is implemented for the scalar basis");
+    if (prec != GMLS_PREC_FP64)
+      return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "constrained stencils are computed in FP64 (GMLS_PREC_FP64)");
+    if (n_tgt > 0 && !hweights) return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer (h_weights)");
+  }
   if (report) memset(report, 0, sizeof(*report));
   if (n_tgt == 0) return GMLS_OK;
   DeviceGuard g(ctx->device);
@@ -274,6 +285,8 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
   a.p = weight_p;
   a.n_tgt = n;
   a.ok_status = GMLS_TARGET_OK;
+  a.normals = normals;
+  a.hweights = hweights;
 
   const bool sync = !opt.capture_safe;  // capture-safe: nothing below waits for the device
   if (!sync && report)
@@ -354,6 +367,29 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
   report->t_stencil_ms = t12;
   report->t_fallback_ms = t23;
   return hm.count[0] > 0 ? GMLS_WARN_TARGET_FLAGS : GMLS_OK;
+}
+
+extern "C" {
+
+gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                          int64_t n_tgt, int dim, int order, int basis, unsigned functional_mask, int weight_p,
+                          const double *eps, const int64_t *row_ptr, const int32_t *col, int prec,
+                          double *weights, uint8_t *target_status, gmls_report *report) {
+  return run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, basis, functional_mask, weight_p, eps, row_ptr,
+                      col, nullptr, prec, weights, nullptr, target_status, report);
+}
+
+gmls_status gmls_stencils_constrained(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                      int64_t n_tgt, int dim, int order, unsigned functional_mask, int weight_p,
+                                      const double *eps, const int64_t *row_ptr, const int32_t *col,
+                                      const double *normals, int prec, double *weights, double *h_weights,
+                                      uint8_t *target_status, gmls_report *report) {
+  if (!ctx) return GMLS_ERR_ARG;
+  if (n_tgt > 0 && !normals) return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer (normals)");
+  static const double kNoNormal = 0.0;
+  return run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, GMLS_BASIS_SCALAR, functional_mask, weight_p,
+                      eps, row_ptr, col, n_tgt > 0 ? normals : &kNoNormal, prec, weights, h_weights, target_status,
+                      report);
 }
 
 gmls_status gmls_check(gmls_ctx ctx) {

@@ -133,6 +133,11 @@ struct StencilArgs {
   int p;            // kernel power
   int n_tgt;
   int ok_status;    // status written on success (-1: leave the status as it is)
+  // Neumann-constrained stencils (scalar basis): per-target normals [n][dim]
+  // and the weight of the boundary value h per functional row [n][F];
+  // both null for plain stencils
+  const double *normals = nullptr;
+  double *hweights = nullptr;
 };
 
 // Per-bin stencil launches; `bin` selects the rows-per-lane instantiation.

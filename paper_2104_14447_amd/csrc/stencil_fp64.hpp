@@ -163,6 +163,7 @@ __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t
       if (j < r.N)
         for (int f = 0; f < F; ++f) a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = NAN;
     }
+    if (a.hweights && lane < F) a.hweights[(int64_t)t * F + lane] = NAN;
     if (lane == 0) a.status[t] = GMLS_TARGET_RANK_DEFICIENT;
     __syncthreads();
     return;
@@ -177,12 +178,37 @@ __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t
   }
   __syncthreads();
   const double ie = 1.0 / uniform_d(a.eps[t]);
+  // Neumann constraint (Section 2.3): minimise the weighted residual subject
+  // to F^T c = h, F = n . grad p(x_T) (only the linear monomials, index
+  // 1 + d, carry 1/eps).  With y = A^-1 lambda and z = A^-1 F the solution of
+  // the bordered system gives lambda^T c = (W P (y - g z))^T u + g h with
+  // g = F^T y / F^T z; lane q holds component q of every vector.
+  double Fq = 0.0, zc = 0.0, sF = 0.0;
+  bool con = false;
+  if (a.normals) {
+    for (int d = 0; d < DIM; ++d) {
+      const double nd = uniform_d(a.normals[(int64_t)t * DIM + d]);
+      if (lane == 1 + d) Fq = nd * ie;
+      con = con || nd != 0.0;
+    }
+    if (con) {
+      zc = tri_solve_rtr<Q>(Rm, Rt, Fq, rdiag, lane);
+      sF = uniform_d(wave_sum(lane < Q ? Fq * zc : 0.0));
+    }
+  }
   for (int f = 0; f < F; ++f) {
     double b = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q)
       if (lane == q) b = scalar_lambda<DIM, ORDER>(rk.kind[f], q, ie);
-    const double y = tri_solve_rtr<Q>(Rm, Rt, b, rdiag, lane);
+    double y = tri_solve_rtr<Q>(Rm, Rt, b, rdiag, lane);
+    if (con) {
+      const double g = uniform_d(wave_sum(lane < Q ? Fq * y : 0.0)) / sF;
+      y -= g * zc;
+      if (lane == 0) a.hweights[(int64_t)t * F + f] = g;
+    } else if (a.hweights && lane == 0) {
+      a.hweights[(int64_t)t * F + f] = 0.0;
+    }
     if (lane < Q) Y[f * Q + lane] = y;
   }
   __syncthreads();
