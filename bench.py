@@ -301,7 +301,12 @@ def main():
         orp, ocol, oeps = oracle.knn(pts, pts[sample], k, mult)
     else:
         orp, ocol, oeps = oracle.radius(pts, pts[sample], r0, k_min)
-    search_ok = np.array_equal(srp, orp) and np.array_equal(scol, ocol) and np.array_equal(epsh[sample], oeps)
+    if knn:
+        same_rows = np.array_equal(scol, ocol)
+    else:  # radius rows are sets: cell order on the GPU, index order in the oracle
+        rows = np.repeat(np.arange(len(srp) - 1), np.diff(srp))
+        same_rows = np.array_equal(srp, orp) and np.array_equal(scol[np.lexsort((scol, rows))], ocol)
+    search_ok = np.array_equal(srp, orp) and same_rows and np.array_equal(epsh[sample], oeps)
     seps = epsh[sample]
     max_err = 0.0
     status_ok = True

@@ -134,7 +134,7 @@ enum {
   GMLS_OPT_RADIUS_SCRATCH_MB = 6, /* radius search: device scratch (MiB) allowed for the one-pass
                                   search, 1 KiB per target; above it (or at 0) the search
                                   counts and fills in two passes (8192)                          */
-  GMLS_OPT_CAPTURE_SAFE = 7    /* nonzero: no call waits for the device or allocates, so that a
+  GMLS_OPT_CAPTURE_SAFE = 7,   /* nonzero: no call waits for the device or allocates, so that a
                                   sequence of calls can be captured into a HIP graph on the
                                   context's stream and replayed (0).  In this mode:
                                   - workspaces are not grown: run each call once with the mode off
@@ -145,6 +145,10 @@ enum {
                                   - gmls_stencils takes no report (GMLS_ERR_ARG otherwise); a row
                                     longer than 256 leaves its target unwritten and is reported by
                                     gmls_check.                                                  */
+  GMLS_OPT_ROW_ORDER = 8       /* order of the entries of a radius row (a set) (0):
+                                  0 = cell order: by (cell of the source in the search's uniform
+                                      grid, source index); deterministic for given inputs, no sort;
+                                  1 = ascending source index (a sort per row).                   */
 };
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
@@ -168,7 +172,9 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value);
  *   spec     host pointer to the search rule
  *   row_ptr  out: int64 [n_tgt + 1] CSR offsets (row_ptr[0] = 0)
  *   col      out: int32 [col_capacity] source indices.  kNN rows are sorted by
- *            (squared distance, index); radius rows (sets) by index.  Squared
+ *            (squared distance, index).  Radius rows are sets; their order is
+ *            set by GMLS_OPT_ROW_ORDER (cell order by default, or ascending
+ *            index), the same for every call with the same inputs.  Squared
  *            distances are evaluated as (dx*dx + dy*dy) + dz*dz in IEEE double
  *            without fused multiply-add
  *   eps      out: [n_tgt] support radius of every target

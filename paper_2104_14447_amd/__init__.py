@@ -22,7 +22,8 @@ __all__ = [
     "BASIS_SCALAR", "BASIS_DIVFREE", "F_VALUE", "F_GRAD", "F_LAPLACIAN", "F_DIV",
     "PREC_FP64", "PREC_MIXED", "SEARCH_KNN", "SEARCH_RADIUS",
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
-    "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE",
+    "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "OPT_ROW_ORDER", "ROW_ORDER_CELL",
+    "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -33,7 +34,8 @@ F_VALUE, F_GRAD, F_LAPLACIAN, F_DIV = 1, 2, 4, 8
 PREC_FP64, PREC_MIXED = 0, 1
 SEARCH_KNN, SEARCH_RADIUS = 0, 1
 OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
-OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE = 4, 5, 6, 7
+OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE, OPT_ROW_ORDER = 4, 5, 6, 7, 8
+ROW_ORDER_CELL, ROW_ORDER_INDEX = 0, 1
 SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE = 0, 1, 2, 3
 GMLS_OK, GMLS_ERR_CAPACITY, GMLS_ERR_UNSUPPORTED, GMLS_WARN_TARGET_FLAGS = 0, 4, 5, 6
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY", 5: "ERR_UNSUPPORTED",

@@ -166,6 +166,10 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
     case GMLS_OPT_CAPTURE_SAFE:
       ctx->opt.capture_safe = value != 0;
       return GMLS_OK;
+    case GMLS_OPT_ROW_ORDER:
+      if (value != 0 && value != 1) return gmls_set_error(ctx, GMLS_ERR_ARG, "row order must be 0 (cell) or 1 (index)");
+      ctx->opt.row_order = (int)value;
+      return GMLS_OK;
     case GMLS_OPT_RADIUS_SCRATCH_MB:
       if (!(value >= 0 && value <= 1048576.0 && value == (double)(int64_t)value))
         return gmls_set_error(ctx, GMLS_ERR_ARG, "radius scratch must be an integer number of MiB in [0, 2^20]");

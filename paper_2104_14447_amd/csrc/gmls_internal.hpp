@@ -20,6 +20,7 @@ enum Slot {
   WS_CELL_COUNT,
   WS_CELL_START,
   WS_SORTED,
+  WS_SORTED_TMP,
   WS_TGT_KEY,
   WS_TGT_COUNT,
   WS_TGT_START,
@@ -55,6 +56,7 @@ struct Options {
   int64_t pipe_chunk = 0;   // list slots per pipeline chunk (0: the whole call)
   int64_t radius_scratch_mb = 8192;  // scratch rows of the one-pass radius search (MiB)
   int capture_safe = 0;              // nonzero: no call waits for the device (see libgmls.h)
+  int row_order = 0;                 // radius rows: 0 cell order, 1 ascending source index
 };
 
 // Device error bits accumulated for gmls_check (capture-safe mode).

@@ -258,6 +258,38 @@ __global__ void k_cell_scatter(const double *pts, int64_t n, const int *key, con
   }
 }
 
+// Sources of each cell in ascending index (the scatter above places them in
+// atomic order): one wavefront per cell, from `in` to `out`.  The rank of an
+// entry is the number of smaller indices in its cell, taken from an LDS copy
+// of the cell's indices (from `in` directly for cells over kSortCellCap).
+constexpr int kSortCellCap = 1024;
+__global__ __launch_bounds__(64) void k_cell_sort(const GridParams *gp, const int *start,
+                                                  const SPoint *__restrict__ in, SPoint *__restrict__ out) {
+  __shared__ int ids[kSortCellCap];
+  const int lane = lane_id();
+  const int ncell = gp->ncell;
+  for (int c = blockIdx.x; c < ncell; c += gridDim.x) {
+    const int b = start[c], n = start[c + 1] - b;
+    if (n == 0) continue;
+    const bool staged = n <= kSortCellCap;
+    if (staged) {
+      for (int q = lane; q < n; q += 64) ids[q] = in[b + q].idx;
+      __syncthreads();
+    }
+    for (int q0 = 0; q0 < n; q0 += 64) {
+      const int q = q0 + lane;
+      SPoint p{};
+      int rank = 0;
+      if (q < n) {
+        p = in[b + q];
+        for (int j = 0; j < n; ++j) rank += (staged ? ids[j] : in[b + j].idx) < p.idx ? 1 : 0;
+        out[b + rank] = p;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_index_scatter(int64_t n, const int *key, const int *start, int *cursor, int *order) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     int id = key[j];
@@ -487,6 +519,44 @@ __device__ __forceinline__ void wave_sort_int(int (&k)[EPL], int lane) {
   }
 }
 
+// NT_ independent bitonic networks, stage by stage (same network as above)
+template <int EPL, int NT_>
+__device__ __forceinline__ void wave_sort_multi(int (&k)[NT_][EPL], int lane) {
+  constexpr int E = 64 * EPL;
+#pragma unroll
+  for (int size = 2; size <= E; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= EPL) {
+        const int lmask = stride / EPL;
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          const int e = lane * EPL + r;
+          const bool keep_min = ((e & stride) == 0) == ((e & size) == 0);
+          int o[NT_];
+#pragma unroll
+          for (int u = 0; u < NT_; ++u) o[u] = xor_lane(k[u][r], lmask);
+#pragma unroll
+          for (int u = 0; u < NT_; ++u) k[u][r] = keep_min ? min(k[u][r], o[u]) : max(k[u][r], o[u]);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          if (r & stride) continue;
+          const int e = lane * EPL + r;
+          const bool up = (e & size) == 0;
+#pragma unroll
+          for (int u = 0; u < NT_; ++u) {
+            const int lo = min(k[u][r], k[u][r + stride]), hi = max(k[u][r], k[u][r + stride]);
+            k[u][r] = up ? lo : hi;
+            k[u][r + stride] = up ? hi : lo;
+          }
+        }
+      }
+    }
+  }
+}
+
 // sort n <= 64*EPL indices of an LDS buffer and write them to out[0 .. n)
 template <int EPL>
 __device__ __forceinline__ void sort_idx_store(const int *buf, int n, int32_t *out, int lane) {
@@ -511,6 +581,29 @@ __device__ __forceinline__ void sort_idx_any(const int *buf, int n, int32_t *out
     sort_idx_store<2>(buf, n, out, lane);
   else
     sort_idx_store<4>(buf, n, out, lane);
+}
+
+// NT independent rows sorted together (interleaved networks): row u has
+// n[u] <= 64*EPL entries in buf[u] and goes to out[u]; n[u] = 0 is skipped
+template <int EPL, int NT_, int ROWLEN>
+__device__ __forceinline__ void sort_idx_multi(const int (*buf)[ROWLEN], const int *n, int32_t *const *out,
+                                               int lane) {
+  int k[NT_][EPL];
+#pragma unroll
+  for (int u = 0; u < NT_; ++u)
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) {
+      const int e = lane * EPL + r;
+      k[u][r] = e < n[u] ? buf[u][e] : INT_MAX;
+    }
+  wave_sort_multi<EPL, NT_>(k, lane);
+#pragma unroll
+  for (int u = 0; u < NT_; ++u)
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) {
+      const int e = lane * EPL + r;
+      if (e < n[u]) out[u][e] = k[u][r];
+    }
 }
 
 // ascending bitonic sort of idx[0, n) in LDS (one-wavefront blocks)
@@ -547,6 +640,7 @@ constexpr int kSmallCap = 256;      // row entries sorted in registers
 constexpr int kCellCap = 1536;      // candidates of one cell block staged in LDS
 constexpr int kCellThreads = 256;   // four wavefronts share a cell block
 constexpr int kMaxRuns = 9;         // runs of cells along x in a 3x3(x3) block
+constexpr int NT = 2;               // targets a wavefront tests together
 
 // ---------------------------------------------------------------------------
 // radius search, cell-cooperative: a workgroup takes one target cell, stages
@@ -565,7 +659,7 @@ constexpr int kMaxRuns = 9;         // runs of cells along x in a 3x3(x3) block
 // ---------------------------------------------------------------------------
 enum RadiusMode { kCount = 0, kFill = 1, kFused = 2 };
 
-template <int DIM, int MODE>
+template <int DIM, int MODE, bool SORTED>
 __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams *gp, const SPoint *pts,
                                                                const int *cell_start, const int *tcs,
                                                                const double *targets, const int *order, double r0,
@@ -576,7 +670,7 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
   if (MODE == kFill && (*flags & 2)) return;  // over capacity: nothing is written
   __shared__ double cxyz[3][kCellCap];
   __shared__ int cid[kCellCap];
-  __shared__ int cbuf[kCellThreads / 64][ROWS ? kSmallCap : 1];
+  __shared__ int cbuf[kCellThreads / 64][NT][ROWS && SORTED ? kSmallCap : 1];
   const GridParams g = *gp;
   const int tid = threadIdx.x, lane = tid & 63, wv = readfirstlane_i(tid >> 6);
   const double r2 = r0 * r0;
@@ -636,76 +730,123 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
       cid[e] = sp.idx;
     }
     // this wavefront's targets (every fourth of the cell), fetched by its
-    // lanes together, 64 at a time, then taken one by one
+    // lanes together, 64 at a time, then taken NT at a time: each staged
+    // candidate is read from LDS once for the NT targets, and their NT row
+    // sorts run interleaved (independent exchange chains)
     constexpr int NW = kCellThreads / 64;
     int my_t = 0;
     double my_x[3] = {0, 0, 0};
     __syncthreads();
-    for (int j = 0; tb + wv + NW * j < te; ++j) {
+    for (int j = 0; tb + wv + NW * j < te; j += NT) {
       if ((j & 63) == 0) {
         const int i = tb + wv + NW * (j + lane);
         my_t = i < te ? order[i] : 0;
         for (int d = 0; d < DIM; ++d) my_x[d] = i < te ? targets[(int64_t)my_t * DIM + d] : 0.0;
       }
-      const int t = readlane_i(my_t, j & 63);
-      double x[3] = {0, 0, 0};
-      for (int d = 0; d < DIM; ++d) x[d] = readlane_d(my_x[d], j & 63);
-      int fill = 0, cnt = 0;
+      int t[NT];
+      bool live[NT];
+      double x[NT][3];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        live[u] = tb + wv + NW * (j + u) < te;
+        t[u] = readlane_i(my_t, (j + u) & 63);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) x[u][d] = d < DIM ? readlane_d(my_x[d], (j + u) & 63) : 0.0;
+      }
+      int fill[NT], cnt[NT];
+      int32_t *out[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        fill[u] = cnt[u] = 0;
+        if constexpr (ROWS)
+          out[u] = MODE == kFused ? col + (int64_t)t[u] * kSmallCap : col + (live[u] ? row_ptr[t[u]] : 0);
+      }
       for (int k0 = 0; k0 < total; k0 += 64) {
         const int k = k0 + lane;
-        bool ok = false;
-        if (k < total) {
+        const bool in = k < total;
+        double c[3] = {0, 0, 0};
+        int id = 0;
+        if (in) {
+          for (int d = 0; d < DIM; ++d) c[d] = cxyz[d][k];
+          if constexpr (ROWS) id = cid[k];
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
           // (dx*dx + dy*dy) + dz*dz, unfused (the file is built without contraction)
-          const double dx = cxyz[0][k] - x[0];
+          const double dx = c[0] - x[u][0];
           double dd = dx * dx;
           if (DIM > 1) {
-            const double dy = cxyz[1][k] - x[1];
+            const double dy = c[1] - x[u][1];
             dd = dd + dy * dy;
           }
           if (DIM > 2) {
-            const double dz = cxyz[2][k] - x[2];
+            const double dz = c[2] - x[u][2];
             dd = dd + dz * dz;
           }
-          ok = dd < r2;
-        }
-        if constexpr (ROWS) {
-          uint64_t m;
-          const int pre = ballot_prefix(ok, &m);
-          if (ok && fill + pre < kSmallCap) cbuf[wv][fill + pre] = cid[k];
-          fill += __popcll(m);
-        } else {
-          cnt += ok ? 1 : 0;
+          const bool ok = in && live[u] && dd < r2;
+          if constexpr (ROWS) {
+            uint64_t m;
+            const int pre = ballot_prefix(ok, &m);
+            if (ok && fill[u] + pre < kSmallCap) {
+              if constexpr (SORTED)
+                cbuf[wv][u][fill[u] + pre] = id;
+              else
+                out[u][fill[u] + pre] = id;  // staging order is cell order: the row is final
+            }
+            fill[u] += __popcll(m);
+          } else {
+            cnt[u] += ok ? 1 : 0;
+          }
         }
       }
       if constexpr (!ROWS) {
-        fill = wave_sum(cnt);
-        if (lane == 0) {
-          if (fill > kCap) atomicOr(flags, 1);
-          counts[t] = fill < k_min ? k_min : (fill > kCap ? kCap : fill);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const int f = wave_sum(cnt[u]);
+          if (lane == 0 && live[u]) {
+            if (f > kCap) atomicOr(flags, 1);
+            counts[t[u]] = f < k_min ? k_min : (f > kCap ? kCap : f);
+          }
         }
       } else {
-        if (fill < k_min || fill > kSmallCap) {
-          if (lane == 0) {
-            defer[atomicAdd(n_defer, 1)] = t;
+        // rows that go to the per-target kernels; the others are sorted
+        int n_sort[NT];
+        int widest = 0;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+          const bool defer_it = live[u] && (fill[u] < k_min || fill[u] > kSmallCap);
+          n_sort[u] = live[u] && !defer_it ? fill[u] : 0;
+          widest = max(widest, n_sort[u]);
+          if (defer_it && lane == 0) {
+            defer[atomicAdd(n_defer, 1)] = t[u];
             if (MODE == kFused) {
-              dflag[t] = 1;
-              if (fill > kCap) atomicOr(flags, 1);
-              counts[t] = fill < k_min ? k_min : (fill > kCap ? kCap : fill);
-            }
-          }
-        } else {
-          wave_lds_sync();
-          int32_t *out = MODE == kFused ? col + (int64_t)t * kSmallCap : col + row_ptr[t];
-          sort_idx_any(cbuf[wv], fill, out, lane);
-          if (lane == 0) {
-            eps[t] = r0;
-            if (MODE == kFused) {
-              counts[t] = fill;
-              dflag[t] = 0;
+              dflag[t[u]] = 1;
+              if (fill[u] > kCap) atomicOr(flags, 1);
+              counts[t[u]] = fill[u] < k_min ? k_min : (fill[u] > kCap ? kCap : fill[u]);
             }
           }
         }
-        wave_lds_sync();  // the buffer is refilled for the next target
+        if constexpr (SORTED) {
+          wave_lds_sync();
+          if (widest <= 64)
+            sort_idx_multi<1, NT>(cbuf[wv], n_sort, out, lane);
+          else if (widest <= 128)
+            sort_idx_multi<2, NT>(cbuf[wv], n_sort, out, lane);
+          else
+            sort_idx_multi<4, NT>(cbuf[wv], n_sort, out, lane);
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            if (n_sort[u] == 0) continue;
+            eps[t[u]] = r0;
+            if (MODE == kFused) {
+              counts[t[u]] = n_sort[u];
+              dflag[t[u]] = 0;
+            }
+          }
+        }
+        if constexpr (SORTED) wave_lds_sync();  // the buffers are refilled for the next targets
       }
     }
     __syncthreads();  // the next cell restages the candidates
@@ -772,15 +913,27 @@ __global__ __launch_bounds__(64) void k_radius_count_list(const GridParams *gp, 
   }
 }
 
+// Cell order of a floored row (the k nearest, in idx[0, k) of a one-wavefront
+// block): sort by (cell of the source, index), the order the staged scans
+// produce for the other rows.  d2 is overwritten with the cell numbers.
+template <int DIM>
+__device__ void floor_cell_order(const GridParams &g, const double *coords, int k, double *d2, int *idx) {
+  __syncthreads();
+  for (int q = lane_id(); q < k; q += 64) d2[q] = (double)cell_id<DIM>(g, coords + (int64_t)idx[q] * DIM);
+  __syncthreads();
+  lds_sort(d2, idx, k);
+}
+
 // Deferred targets of the fill pass: rows of up to kSmallCap entries, or the
 // k_min floor when it fits the small buffer; everything else goes on to
 // k_radius_fill_big through `overflow`.
-template <int DIM>
+template <int DIM, bool SORTED>
 __global__ __launch_bounds__(64) void k_radius_fill_list(const GridParams *gp, const SPoint *pts,
-                                                         const int *cell_start, const double *targets,
-                                                         const int *list, const int *n_list, double r0, int k_min,
-                                                         const int64_t *row_ptr, int32_t *col, double *eps,
-                                                         int *overflow, int *n_overflow, const int *flags) {
+                                                         const int *cell_start, const double *coords,
+                                                         const double *targets, const int *list, const int *n_list,
+                                                         double r0, int k_min, const int64_t *row_ptr, int32_t *col,
+                                                         double *eps, int *overflow, int *n_overflow,
+                                                         const int *flags) {
   if (*flags & 2) return;  // over capacity: nothing is written
   __shared__ double d2[kSmallCap];
   __shared__ int idx[kSmallCap];
@@ -825,13 +978,22 @@ __global__ __launch_bounds__(64) void k_radius_fill_list(const GridParams *gp, c
     const int64_t base = row_ptr[t];
     __syncthreads();
     if (fill >= k_min) {
-      sort_idx_any(idx, fill, col + base, lane);
+      if constexpr (SORTED)
+        sort_idx_any(idx, fill, col + base, lane);
+      else
+        for (int q = lane; q < fill; q += 64) col[base + q] = idx[q];
       if (lane == 0) eps[t] = r0;
     } else {
       const int got = knn_select<DIM, kSmallCap>(g, pts, cell_start, x, k_min + 1, 1, d2, idx);
       __syncthreads();
-      sort_idx_any(idx, k_min, col + base, lane);
-      if (lane == 0) eps[t] = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
+      const double e = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
+      if constexpr (SORTED) {
+        sort_idx_any(idx, k_min, col + base, lane);
+      } else {
+        floor_cell_order<DIM>(g, coords, k_min, d2, idx);
+        for (int q = lane; q < k_min; q += 64) col[base + q] = idx[q];
+      }
+      if (lane == 0) eps[t] = e;
     }
     __syncthreads();
   }
@@ -839,10 +1001,11 @@ __global__ __launch_bounds__(64) void k_radius_fill_list(const GridParams *gp, c
 
 // Targets with more candidates than the small buffer (or a large floor):
 // LDS buffer of kCap entries and a bitonic sort in LDS.
-template <int DIM>
+template <int DIM, bool SORTED>
 __global__ __launch_bounds__(64) void k_radius_fill_big(const GridParams *gp, const SPoint *pts,
-                                                        const int *cell_start, const double *targets, double r0,
-                                                        int k_min, const int64_t *row_ptr, int32_t *col, double *eps,
+                                                        const int *cell_start, const double *coords,
+                                                        const double *targets, double r0, int k_min,
+                                                        const int64_t *row_ptr, int32_t *col, double *eps,
                                                         const int *overflow, const int *n_overflow, const int *flags) {
   if (*flags & 2) return;  // over capacity: nothing is written
   __shared__ double d2[kCap];
@@ -883,7 +1046,7 @@ __global__ __launch_bounds__(64) void k_radius_fill_big(const GridParams *gp, co
     __syncthreads();
     if (fill >= k_min) {
       if (fill > kCap) fill = kCap;  // flagged by the count pass; the call fails
-      lds_sort_int(idx, fill);
+      if constexpr (SORTED) lds_sort_int(idx, fill);
       for (int q = lane; q < fill; q += 64) col[base + q] = idx[q];
       if (lane == 0) eps[t] = r0;
     } else {
@@ -891,7 +1054,10 @@ __global__ __launch_bounds__(64) void k_radius_fill_big(const GridParams *gp, co
       __syncthreads();
       const double e = got > k_min ? 0.5 * (sqrt(d2[k_min - 1]) + sqrt(d2[k_min])) : r0;
       __syncthreads();
-      lds_sort_int(idx, k_min);
+      if constexpr (SORTED)
+        lds_sort_int(idx, k_min);
+      else
+        floor_cell_order<DIM>(g, coords, k_min, d2, idx);
       for (int q = lane; q < k_min; q += 64) col[base + q] = idx[q];
       if (lane == 0) eps[t] = e;
     }
@@ -919,6 +1085,32 @@ static inline unsigned grid_for(int64_t n, int block) {
 #define GMLS_WS(ptr, type, slot, count)                                                             \
   type *ptr = (type *)ctx->ws(slot, sizeof(type) * (size_t)(count));                                \
   if (!ptr) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed (" #ptr ")")
+
+// launches with the row order chosen at run time (cell order, or ascending
+// index with a sort per row)
+template <int DIM, int MODE, typename... A>
+static void launch_cells(bool by_index, unsigned nb, hipStream_t s, A... args) {
+  if (by_index)
+    k_radius_cells<DIM, MODE, true><<<nb, kCellThreads, 0, s>>>(args...);
+  else
+    k_radius_cells<DIM, MODE, false><<<nb, kCellThreads, 0, s>>>(args...);
+}
+
+template <int DIM, typename... A>
+static void launch_fill_list(bool by_index, hipStream_t s, A... args) {
+  if (by_index)
+    k_radius_fill_list<DIM, true><<<4096, 64, 0, s>>>(args...);
+  else
+    k_radius_fill_list<DIM, false><<<4096, 64, 0, s>>>(args...);
+}
+
+template <int DIM, typename... A>
+static void launch_fill_big(bool by_index, hipStream_t s, A... args) {
+  if (by_index)
+    k_radius_fill_big<DIM, true><<<1024, 64, 0, s>>>(args...);
+  else
+    k_radius_fill_big<DIM, false><<<1024, 64, 0, s>>>(args...);
+}
 
 template <int DIM>
 static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
@@ -953,7 +1145,16 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
   k_cell_keys<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(gp, coords, n_src, key, cnt);
   GMLS_HIP(exclusive_scan<int, int>(cnt, start, ncell_max, (int *)tmp, s));
   GMLS_HIP(fill_zero(cnt, sizeof(int) * (size_t)(ncell_max + 1), s));
-  k_cell_scatter<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(coords, n_src, key, start, cnt, sorted);
+  const bool by_index = ctx->opt.row_order != 0;
+  if (!knn && !by_index) {
+    // radius rows come out in staging order, which is cell order once each
+    // cell's sources are in ascending index
+    GMLS_WS(scattered, SPoint, WS_SORTED_TMP, n_src);
+    k_cell_scatter<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(coords, n_src, key, start, cnt, scattered);
+    k_cell_sort<<<(unsigned)xcd_grid(ctx->cus * 32), 64, 0, s>>>(gp, start, scattered, sorted);
+  } else {
+    k_cell_scatter<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(coords, n_src, key, start, cnt, sorted);
+  }
   GMLS_HIP(hipGetLastError());
   const int *tcs = start;  // target ranges per cell in `order`
   if (n_tgt > 0) {
@@ -998,14 +1199,14 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
   }
   if (n_tgt > 0) {
     if (fused)
-      k_radius_cells<DIM, kFused><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order,
-                                                                     spec.radius, spec.k_min, counts, nullptr, rows,
-                                                                     eps, defer, flags + 2, dflag, flags);
+      launch_cells<DIM, kFused>(by_index, nb_cells, s, (const GridParams *)gp, (const SPoint *)sorted, start, tcs,
+                                targets, (const int *)order, spec.radius, spec.k_min, counts,
+                                (const int64_t *)nullptr, rows, eps, defer, flags + 2, dflag, flags);
     else
-      k_radius_cells<DIM, kCount><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order,
-                                                                     spec.radius, spec.k_min, counts, nullptr,
-                                                                     nullptr, nullptr, defer, flags + 2, nullptr,
-                                                                     flags);
+      launch_cells<DIM, kCount>(by_index, nb_cells, s, (const GridParams *)gp, (const SPoint *)sorted, start, tcs,
+                                targets, (const int *)order, spec.radius, spec.k_min, counts,
+                                (const int64_t *)nullptr, (int32_t *)nullptr, (double *)nullptr, defer, flags + 2,
+                                (uint8_t *)nullptr, flags);
     k_radius_count_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, defer, flags + 2, spec.radius,
                                                  spec.k_min, counts, flags);
   }
@@ -1037,14 +1238,17 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
     } else {
       defer_fill = defer + n_tgt;
       n_defer_fill = flags + 3;
-      k_radius_cells<DIM, kFill><<<nb_cells, kCellThreads, 0, s>>>(gp, sorted, start, tcs, targets, order,
-                                                                    spec.radius, spec.k_min, nullptr, row_ptr, col,
-                                                                    eps, defer_fill, n_defer_fill, nullptr, flags);
+      launch_cells<DIM, kFill>(by_index, nb_cells, s, (const GridParams *)gp, (const SPoint *)sorted, start, tcs,
+                               targets, (const int *)order, spec.radius, spec.k_min, (int64_t *)nullptr,
+                               (const int64_t *)row_ptr, col, eps, defer_fill, n_defer_fill, (uint8_t *)nullptr,
+                               flags);
     }
-    k_radius_fill_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, defer_fill, n_defer_fill, spec.radius,
-                                                spec.k_min, row_ptr, col, eps, overflow, flags + 1, flags);
-    k_radius_fill_big<DIM><<<1024, 64, 0, s>>>(gp, sorted, start, targets, spec.radius, spec.k_min, row_ptr, col,
-                                               eps, overflow, flags + 1, flags);
+    launch_fill_list<DIM>(by_index, s, (const GridParams *)gp, (const SPoint *)sorted, start, coords, targets,
+                          (const int *)defer_fill, (const int *)n_defer_fill, spec.radius, spec.k_min,
+                          (const int64_t *)row_ptr, col, eps, overflow, flags + 1, (const int *)flags);
+    launch_fill_big<DIM>(by_index, s, (const GridParams *)gp, (const SPoint *)sorted, start, coords, targets,
+                         spec.radius, spec.k_min, (const int64_t *)row_ptr, col, eps, (const int *)overflow,
+                         (const int *)(flags + 1), (const int *)flags);
   }
   GMLS_HIP(hipGetLastError());
   if (sync) {

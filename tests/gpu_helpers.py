@@ -55,3 +55,9 @@ def row_errors(w_gpu, w_ref, row_ptr, F, C, zero_rows=()):
 
 def flush(msg):
     print(msg, flush=True)
+
+
+def row_sorted(rp, col):
+    """Each CSR row sorted ascending (radius rows compared as sets)."""
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    return col[np.lexsort((col, rows))]

@@ -1,11 +1,16 @@
-"""GPU neighbour search vs the oracle: bit-exact CSR (rows sorted by
-(squared distance, index)) and support radii."""
+"""GPU neighbour search vs the oracle: bit-exact CSR and support radii.
+
+kNN rows are sorted by (squared distance, index) on both sides.  Radius rows
+are sets: in the default cell order they are compared as sets (each row
+sorted on the host) and checked to be deterministic; with
+OPT_ROW_ORDER = ROW_ORDER_INDEX they must equal the oracle's index-sorted
+rows entry by entry."""
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
-from tests.gpu_helpers import ctx, dev, flush, host, require_gpu
+from tests.gpu_helpers import ctx, dev, flush, host, require_gpu, row_sorted
 
 pytestmark = pytest.mark.gpu
 
@@ -19,19 +24,26 @@ def gpu_knn(src, tgt, k, eps_mult=1.5):
     return host(rp), host(col), host(eps)
 
 
-def gpu_radius(src, tgt, r0, k_min):
+def gpu_radius(src, tgt, r0, k_min, row_order=0):
     G = require_gpu()
     same = tgt is src
     s = dev(src)
     t = s if same else dev(tgt)
-    rp, col, eps = G.gmls_neighbors(ctx(), s, t, G.SEARCH_RADIUS, radius=r0, k_min=k_min)
+    c = ctx()
+    c.set_option(G.OPT_ROW_ORDER, row_order)
+    try:
+        rp, col, eps = G.gmls_neighbors(c, s, t, G.SEARCH_RADIUS, radius=r0, k_min=k_min)
+    finally:
+        c.set_option(G.OPT_ROW_ORDER, G.ROW_ORDER_CELL)
     return host(rp), host(col), host(eps)
 
 
-def assert_same(g, o, tag):
+def assert_same(g, o, tag, sets=False):
     rp, col, eps = g
     orp, ocol, oeps = o
     assert np.array_equal(rp, orp), tag
+    if sets:
+        col, ocol = row_sorted(rp, col), row_sorted(orp, ocol)
     if not np.array_equal(col, ocol):
         bad = np.nonzero(col != ocol)[0][:5]
         t = np.searchsorted(orp, bad, side="right") - 1
@@ -82,9 +94,14 @@ def test_radius_matches_oracle(n):
     flush(f"radius n={n} r0={r0:.4f}")
     g = gpu_radius(src, src, r0, 30)
     o = oracle.radius(src, src, r0, 30)
-    assert_same(g, o, f"radius n={n}")
+    assert_same(g, o, f"radius n={n}", sets=True)
     counts = np.diff(g[0])
     assert (counts == 30).any() or n > 10000  # the floor is exercised on the small cloud
+    flush(f"radius n={n}: repeat (deterministic cell order)")
+    g2 = gpu_radius(src, src, r0, 30)
+    assert np.array_equal(g[1], g2[1]) and np.array_equal(g[2], g2[2])
+    flush(f"radius n={n}: index order")
+    assert_same(gpu_radius(src, src, r0, 30, row_order=1), o, f"radius index order n={n}")
 
 
 def test_radius_foreign_targets_and_empty():
@@ -93,7 +110,9 @@ def test_radius_foreign_targets_and_empty():
     tgt = W.rng(9).uniform(-0.1, 1.1, size=(400, 3))
     r0 = W.radius_for_mean_count(5000)
     flush("radius foreign")
-    assert_same(gpu_radius(src, tgt, r0, 20), oracle.radius(src, tgt, r0, 20), "radius foreign")
+    o = oracle.radius(src, tgt, r0, 20)
+    assert_same(gpu_radius(src, tgt, r0, 20), o, "radius foreign", sets=True)
+    assert_same(gpu_radius(src, tgt, r0, 20, row_order=1), o, "radius foreign, index order")
     flush("empty target set")
     rp, col, eps = G.gmls_neighbors(ctx(), dev(src), dev(np.zeros((0, 3))), G.SEARCH_RADIUS, radius=r0, k_min=5)
     assert host(rp).tolist() == [0] and col.numel() == 0
@@ -109,7 +128,7 @@ def test_capacity_error_reports_required_size():
     rp, col, eps = G.gmls_neighbors(ctx(), s, s, G.SEARCH_RADIUS, radius=r0, k_min=10, col=small)
     o = oracle.radius(src, src, r0, 10)
     assert col.numel() == len(o[1])
-    assert_same((host(rp), host(col), host(eps)), o, "capacity retry")
+    assert_same((host(rp), host(col), host(eps)), o, "capacity retry", sets=True)
 
 
 def test_bad_arguments_raise():
@@ -128,10 +147,35 @@ def test_radius_two_pass_matches_oracle(n):
     src = W.density_ramp(n, 1004)
     r0 = W.radius_for_mean_count(n)
     c = ctx()
+    one = gpu_radius(src, src, r0, 30)
+    one_idx = gpu_radius(src, src, r0, 30, row_order=1)
     c.set_option(G.OPT_RADIUS_SCRATCH_MB, 0)
     try:
         flush(f"radius two-pass n={n}")
         g = gpu_radius(src, src, r0, 30)
+        g_idx = gpu_radius(src, src, r0, 30, row_order=1)
     finally:
         c.set_option(G.OPT_RADIUS_SCRATCH_MB, 8192)
-    assert_same(g, oracle.radius(src, src, r0, 30), f"radius two-pass n={n}")
+    o = oracle.radius(src, src, r0, 30)
+    assert_same(g, o, f"radius two-pass n={n}", sets=True)
+    assert_same(g_idx, o, f"radius two-pass index order n={n}")
+    # the same cell order from both variants
+    assert np.array_equal(g[1], one[1]) and np.array_equal(g_idx[1], one_idx[1])
+
+
+def test_radius_cell_order_clustered_and_floored():
+    """Dense clusters (cells over the staging capacity, deferred rows) and a
+    large floor (floored rows ordered by cell in the per-target kernels)."""
+    g = W.rng(21)
+    clustered = np.concatenate([g.normal(0.5, 0.02, size=(3000, 3)), g.uniform(size=(4000, 3))])
+    sparse = g.uniform(size=(5000, 3))
+    # (up to ~800 sources per row near the cluster centre, 5000 staged
+    # candidates per cell block), then floors of 150 (small-buffer kernel) and
+    # 200 (large-buffer kernel) on a sparse cloud
+    for src, r0, k_min in ((clustered, 0.02, 10), (sparse, 0.03, 150), (sparse, 0.03, 200)):
+        flush(f"radius clustered/floored n={len(src)} r0={r0} k_min={k_min}")
+        o = oracle.radius(src, src, r0, k_min)
+        a = gpu_radius(src, src, r0, k_min)
+        assert_same(a, o, f"clustered r0={r0}", sets=True)
+        assert np.array_equal(a[1], gpu_radius(src, src, r0, k_min)[1])
+        assert_same(gpu_radius(src, src, r0, k_min, row_order=1), o, f"clustered r0={r0}, index order")

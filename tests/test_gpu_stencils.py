@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import workloads as W
-from tests.gpu_helpers import ctx, dev, flush, host, require_gpu, row_errors
+from tests.gpu_helpers import row_sorted, ctx, dev, flush, host, require_gpu, row_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -126,8 +126,11 @@ def test_end_to_end_gpu_search_then_stencils():
     rp, col, eps = G.gmls_neighbors(ctx(), s, s, G.SEARCH_RADIUS, radius=r0, k_min=30)
     gw, gst, _ = G.gmls_stencils(ctx(), s, s, 3, G.BASIS_SCALAR, 4, 4, eps, rp, col, prec=G.PREC_FP64)
     orp, ocol, oeps = oracle.radius(pts, pts, r0, 30)
-    assert np.array_equal(host(rp), orp) and np.array_equal(host(col), ocol)
-    w, st, F, C = oracle.stencils(pts, pts, 3, "scalar", 4, 4, oeps, orp, ocol)
+    gcol = host(col)
+    assert np.array_equal(host(rp), orp) and np.array_equal(row_sorted(orp, gcol), ocol)
+    assert np.array_equal(host(eps), oeps)
+    # the oracle's weights for the GPU's row order (radius rows are sets)
+    w, st, F, C = oracle.stencils(pts, pts, 3, "scalar", 4, 4, oeps, orp, gcol)
     errs = row_errors(host(gw), w, orp, F, C)
     flush(f"  e2e max rel err {errs.max():.3e}")
     assert errs.max() <= FP64_TOL
