@@ -46,14 +46,16 @@ def alg_flops_workload(nnz, n_tgt, dim, bases):
     """Conventional count over the bases of a configuration: the scalar Gram
     N*Qs*(Qs+1) once per target (shared by bases on one neighbour list), then
     per basis Q^3/3 + 2FQ^2 and 2*R*Qs*F for the weights (R = N scalar, d*N
-    vector); the vector basis adds the congruence 4*Qd^2 and 2*F*Qd*d*Qs."""
-    qs_max = max(_binom(b["order"] + dim, dim) for b in bases)
+    vector); the vector basis adds the congruence 4*Qd^2 and 2*F*Qd*d*Qs.
+    The staggered basis counts its Qs = Q columns (no constant monomial), the
+    Neumann-constrained basis the scalar ones."""
+    qs_max = max(b["Qs"] for b in bases)
     total = nnz * qs_max * (qs_max + 1)
     for b in bases:
-        qs = _binom(b["order"] + dim, dim)
+        qs = b["Qs"]
         Q, F = b["Q"], b["F"]
         total += n_tgt * (Q ** 3 / 3.0 + 2 * F * Q * Q)
-        if b["name"] == "scalar":
+        if b["name"] != "divfree":
             total += 2 * nnz * qs * F
         else:
             total += 2 * dim * nnz * qs * F + n_tgt * (4 * Q * Q + 2 * F * Q * dim * qs)
@@ -73,6 +75,10 @@ DESCRIBE = {
     "c4_3d_m3_uneven": "2M points, density 1+3x, radius search (k_min 30), scalar order 3, Laplacian",
     "c5_3d_m4": "500k jittered-grid points in 3D, kNN 170, p=6, scalar order 4 gradient + Laplacian and "
                 "div-free order 4 vector Laplacian + divergence",
+    "s4_3d_staggered_m2": "the C4 cloud and radius search, staggered gradient + Laplacian of vector order 2 "
+                          "(FP64)",
+    "n3_3d_neumann_m3": "60k points on the faces of the unit cube with outward normals, kNN 80 into 1M "
+                        "jittered-grid points, Neumann-constrained scalar order 3 Laplacian (FP64)",
 }
 
 
@@ -189,11 +195,40 @@ def main():
     pts = W.make_points(name, n=n)
     print(f"# generated {n} points in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     x = torch.from_numpy(pts).to(dev)
+    # targets: the sources themselves, or points on the domain boundary with
+    # outward normals (Neumann-constrained stencils)
+    nrm = None
+    if wl.get("targets"):
+        _, n_b, seed_b = wl["targets"]
+        tpts, nrm_h = W.boundary_points(n_b, dim, seed_b)
+        xt = torch.from_numpy(tpts).to(dev)
+        nrm = torch.from_numpy(nrm_h).to(dev)
+    else:
+        tpts, nrm_h, xt = pts, None, x
+    n_t = len(tpts)
     bases = []
     for basis, order, mask in wl["bases"]:
-        b = G.BASIS_SCALAR if basis == "scalar" else G.BASIS_DIVFREE
+        b = G.BASIS_DIVFREE if basis == "divfree" else G.BASIS_SCALAR
         F, C, Q = G.gmls_stencil_shape(dim, order, b, mask)
-        bases.append(dict(name=basis, b=b, order=order, mask=mask, F=F, C=C, Q=Q))
+        if basis == "staggered":  # scalar monomials of degree 1..order+1
+            F, C, Q = (dim if mask & G.F_GRAD else 0) + (1 if mask & G.F_LAPLACIAN else 0), 1, \
+                _binom(order + 1 + dim, dim) - 1
+        Qs = Q if basis != "divfree" else _binom(order + dim, dim)
+        bases.append(dict(name=basis, b=b, order=order, mask=mask, F=F, C=C, Q=Q, Qs=Qs))
+
+    def stencils(c, bs, eps_, rp_, col_, weights=None, status=None, aux=None, report=False):
+        """One basis of the configuration through its entry point; `aux`
+        receives the h-weights (constrained) or target weights (staggered)."""
+        if bs["name"] == "staggered":
+            return G.gmls_stencils_staggered(c, x, xt, bs["order"], bs["mask"], p, eps_, rp_, col_, prec=prec,
+                                             weights=weights, t_weights=aux, status=status, report=report)
+        if bs["name"] == "neumann":
+            return G.gmls_stencils_constrained(c, x, xt, bs["order"], bs["mask"], p, eps_, rp_, col_, nrm,
+                                               prec=prec, weights=weights, h_weights=aux, status=status,
+                                               report=report)
+        w_, st_, r_ = G.gmls_stencils(c, x, xt, bs["order"], bs["b"], bs["mask"], p, eps_, rp_, col_, prec=prec,
+                                      weights=weights, status=status, report=report)
+        return w_, None, st_, r_
 
     precs = {"mixed": G.PREC_MIXED, "fp64": G.PREC_FP64}
     if args.prec == "auto":
@@ -203,23 +238,24 @@ def main():
     prec = precs[prec_name]
 
     # buffers reused across steps (no allocation inside the timed region)
-    rp, col, eps = G.gmls_neighbors(ctx, x, x, **spec)
+    rp, col, eps = G.gmls_neighbors(ctx, x, xt, **spec)
     nnz = col.numel()
     col_buf = torch.empty(int(nnz * 1.05) + 1024, dtype=torch.int32, device=dev)
     for bs in bases:
         bs["w"] = torch.empty(bs["F"] * bs["C"] * nnz, dtype=torch.float64, device=dev)
-        bs["st"] = torch.empty(n, dtype=torch.uint8, device=dev)
+        bs["st"] = torch.empty(n_t, dtype=torch.uint8, device=dev)
+        bs["aux"] = torch.empty((n_t, bs["F"]), dtype=torch.float64, device=dev)
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def step(report=False):
         ev0.record()
-        rp_, col_, eps_ = G.gmls_neighbors(ctx, x, x, col=col_buf, **spec)
+        rp_, col_, eps_ = G.gmls_neighbors(ctx, x, xt, col=col_buf, **spec)
         ev1.record()
         reps = []
         for bs in bases:
-            _, _, r_ = G.gmls_stencils(ctx, x, x, bs["order"], bs["b"], bs["mask"], p, eps_, rp_, col_, prec=prec,
-                                       weights=bs["w"], status=bs["st"], report=report)
+            r_ = stencils(ctx, bs, eps_, rp_, col_, weights=bs["w"], status=bs["st"], aux=bs["aux"],
+                          report=report)[3]
             reps.append(r_)
         return rp_, col_, eps_, reps
 
@@ -251,21 +287,21 @@ def main():
         gctx.set_option(G.OPT_MIXED_SCHEME, args.scheme)
         with torch.cuda.stream(gs):
             # one normal call of each kind sizes the context's workspace
-            rpw, colw, epsw = G.gmls_neighbors(gctx, x, x, **spec)
+            rpw, colw, epsw = G.gmls_neighbors(gctx, x, xt, **spec)
             for bs in bases:
-                G.gmls_stencils(gctx, x, x, bs["order"], bs["b"], bs["mask"], p, epsw, rpw, colw, prec=prec)
+                stencils(gctx, bs, epsw, rpw, colw)
             gcol = torch.empty(nnz + 1024, dtype=torch.int32, device=dev)
             for bs in bases:
                 bs["gw"] = torch.empty(bs["F"] * bs["C"] * nnz, dtype=torch.float64, device=dev)
-                bs["gst"] = torch.empty(n, dtype=torch.uint8, device=dev)
+                bs["gst"] = torch.empty(n_t, dtype=torch.uint8, device=dev)
+                bs["gaux"] = torch.empty((n_t, bs["F"]), dtype=torch.float64, device=dev)
             gctx.set_option(G.OPT_CAPTURE_SAFE, 1)
             gout = {}
 
             def gstep():
-                rp_, col_, eps_ = G.gmls_neighbors(gctx, x, x, col=gcol, **spec)
+                rp_, col_, eps_ = G.gmls_neighbors(gctx, x, xt, col=gcol, **spec)
                 for bs in bases:
-                    G.gmls_stencils(gctx, x, x, bs["order"], bs["b"], bs["mask"], p, eps_, rp_, col_[:nnz],
-                                    prec=prec, weights=bs["gw"], status=bs["gst"])
+                    stencils(gctx, bs, eps_, rp_, col_[:nnz], weights=bs["gw"], status=bs["gst"], aux=bs["gaux"])
                 gout["rp"], gout["eps"] = rp_, eps_
 
             gstep()  # capture-safe eager run (no allocation happens in the capture)
@@ -285,7 +321,7 @@ def main():
         # the parity gate below checks the replayed outputs
         rp_t, col_t, eps_t = gout["rp"], gcol[:nnz], gout["eps"]
         for bs in bases:
-            bs["w"], bs["st"] = bs["gw"], bs["gst"]
+            bs["w"], bs["st"], bs["aux"] = bs["gw"], bs["gst"], bs["gaux"]
 
     # ---- parity gate on sampled targets (same process, same outputs) ----
     import oracle
@@ -293,15 +329,15 @@ def main():
     rph = rp_t.cpu().numpy()
     epsh = eps_t.cpu().numpy()
     g = W.rng(424242)
-    sample = np.sort(g.choice(n, size=min(args.sample, n), replace=False))
+    sample = np.sort(g.choice(n_t, size=min(args.sample, n_t), replace=False))
     idx = torch.from_numpy(np.concatenate([np.arange(rph[t], rph[t + 1]) for t in sample])).cuda()
     scol = col_t[idx].cpu().numpy()
     srp = np.zeros(len(sample) + 1, dtype=np.int64)
     srp[1:] = np.cumsum(np.diff(rph)[sample])
     if knn:
-        orp, ocol, oeps = oracle.knn(pts, pts[sample], k, mult)
+        orp, ocol, oeps = oracle.knn(pts, tpts[sample], k, mult)
     else:
-        orp, ocol, oeps = oracle.radius(pts, pts[sample], r0, k_min)
+        orp, ocol, oeps = oracle.radius(pts, tpts[sample], r0, k_min)
     if knn:
         same_rows = np.array_equal(scol, ocol)
     else:  # radius rows are sets: cell order on the GPU, index order in the oracle
@@ -317,8 +353,26 @@ def main():
                                                 for t in sample])).cuda()
         wh = bs["w"][widx].cpu().numpy()
         sth = bs["st"].cpu().numpy()[sample]
-        ow, ost, _, _ = oracle.stencils(pts, pts[sample], bs["order"], bs["name"], bs["mask"], p, seps, srp, scol)
+        if bs["name"] == "staggered":
+            from oracle import staggered as OS
+            ow, oaux, _ = OS.stencils_staggered(pts, tpts[sample], bs["order"], bs["mask"], p, seps, srp, scol)
+            ost = np.zeros(len(sample), dtype=np.uint8)
+        elif bs["name"] == "neumann":
+            from oracle import constrained as OC
+            ow, oaux, _ = OC.stencils_constrained(pts, tpts[sample], bs["order"], bs["mask"], p, seps, srp, scol,
+                                                  nrm_h[sample])
+            ost = np.zeros(len(sample), dtype=np.uint8)
+        else:
+            ow, ost, _, _ = oracle.stencils(pts, tpts[sample], bs["order"], bs["name"], bs["mask"], p, seps, srp,
+                                            scol)
+            oaux = None
         status_ok = status_ok and np.array_equal(sth == 1, ost == 1)
+        if oaux is not None:  # target weights / h-weights, relative to the row norms
+            gaux = bs["aux"].cpu().numpy()[sample]
+            for q in range(len(sample)):
+                b_ = ow[F * srp[q]:F * srp[q + 1]].reshape(F, -1)
+                den = np.hypot(np.linalg.norm(b_, axis=1), oaux[q])
+                max_err = max(max_err, float((np.abs(gaux[q] - oaux[q]) / np.where(den > 0, den, 1.0)).max()))
         zero = F - 1 if bs["name"] == "divfree" and bs["mask"] & G.F_DIV else -1
         for q in range(len(sample)):
             if ost[q] == 1:
@@ -336,7 +390,7 @@ def main():
 
     # ---- roofline of the stencil phase (its kernels timed by HIP events on
     # the library's stream, inside the timed steps) ----
-    flops = alg_flops_workload(nnz, n, dim, bases)
+    flops = alg_flops_workload(nnz, n_t, dim, bases)
     t_sten = float(np.mean(stencil_ms)) * 1e-3
     achieved_tf = flops / t_sten / 1e12
     peak_tf = PEAK["fp32_TFs"] if prec_name == "mixed" else PEAK["fp64_TFs"]
@@ -345,14 +399,14 @@ def main():
                 "frac": round(achieved_tf / peak_tf, 4), "traffic": traffic,
                 "kernel": "stencil phase: moments, solve and weights kernels of every row-count bin + FP64 "
                           "fallback (one launch sequence per basis per step)",
-                "alg_flops_per_step": flops, "alg_bytes_per_step": alg_bytes_workload(nnz, n, dim, bases),
+                "alg_flops_per_step": flops, "alg_bytes_per_step": alg_bytes_workload(nnz, n_t, dim, bases),
                 "kernel_ms": round(t_sten * 1e3, 4),
                 "frac_of_fp64_peak": round(achieved_tf / PEAK["fp64_TFs"], 4),
                 "search_ms": round(float(np.mean(search_ms)), 4)}
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload ----
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and all(bs["name"] in ("scalar", "divfree") for bs in bases) and n_t == n:
         threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
 
         def oracle_run(m):
@@ -379,7 +433,7 @@ def main():
                "sample": f"{what} {n} targets of the same point cloud: bucket-grid neighbour search + "
                          f"Householder-QR stencils in FP64, {dt:.1f} s wall on {threads} threads"}
 
-    value = n / (ms_per_step * 1e-3)
+    value = n_t / (ms_per_step * 1e-3)
     line = {
         "metric": "GMLS stencils/sec (3D, order 3, uneven nbrs); mixed vs FP64 at <=1e-8 rel err",
         "value": round(value, 1),
@@ -394,7 +448,7 @@ def main():
         "dtype": "f32+f64" if prec_name == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": f"{name}: {DESCRIBE[name]}",
-                   "n_points": n, "nnz": int(nnz), "precision": prec_name,
+                   "n_points": n, "n_targets": n_t, "nnz": int(nnz), "precision": prec_name,
                    "search": wl["search"][0] + (f" k={k}" if knn else f" r={r0:.6f} k_min={k_min}"),
                    "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
                                     "pipeline"][args.scheme],

@@ -213,6 +213,28 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
                           const double *eps, const int64_t *row_ptr, const int32_t *col, int prec,
                           double *weights, uint8_t *target_status, gmls_report *report);
 
+/* Staggered stencils (Section 2.4) for the pressure: grad p and Laplacian p
+ * at x_T from a vector polynomial fit of grad p of order `order` (0..3),
+ * sampled by integrals along the segments x_T -> x_j of the neighbour rows,
+ * with data p_j - p(x_T).  The result is exact for p of degree <= order + 1.
+ *   functional_mask  GMLS_F_GRAD and/or GMLS_F_LAPLACIAN (others: GMLS_ERR_ARG);
+ *                    rows in the order gradient (dim rows), Laplacian
+ *   weights          out: as for gmls_stencils with C_in = 1: the weight of
+ *                    p_j (the j-th entry of the row) in functional row f
+ *   target_weights   out: FP64 [n_tgt][F], the weight of p(x_T) in row f
+ *                    (-sum_j of the row's weights); NaN for rank-deficient
+ *                    targets.  A target listed among its own neighbours adds
+ *                    its target weight to that entry, or is given p(x_T) apart
+ *   prec             GMLS_PREC_FP64 only (GMLS_PREC_MIXED: GMLS_ERR_UNSUPPORTED)
+ * Other arguments, statuses and errors as for gmls_stencils (the Gram has
+ * (order+2 choose dim) - 1 columns: the circulating vector fields, which
+ * integrate to zero on every segment from x_T, are not fitted). */
+gmls_status gmls_stencils_staggered(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                    int64_t n_tgt, int dim, int order, unsigned functional_mask, int weight_p,
+                                    const double *eps, const int64_t *row_ptr, const int32_t *col, int prec,
+                                    double *weights, double *target_weights, uint8_t *target_status,
+                                    gmls_report *report);
+
 /* Errors of capture-safe calls found on the device since the last check
  * (GMLS_OPT_CAPTURE_SAFE): GMLS_OK, GMLS_ERR_CAPACITY or GMLS_ERR_UNSUPPORTED
  * with a message in gmls_last_error.  Synchronises; clears the record. */

@@ -18,7 +18,8 @@ import torch
 
 __all__ = [
     "LIB_PATH", "GmlsError", "Context", "SearchSpec", "Report", "load_library",
-    "gmls_neighbors", "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained", "gmls_apply",
+    "gmls_neighbors", "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained",
+    "gmls_stencils_staggered", "gmls_apply",
     "BASIS_SCALAR", "BASIS_DIVFREE", "F_VALUE", "F_GRAD", "F_LAPLACIAN", "F_DIV",
     "PREC_FP64", "PREC_MIXED", "SEARCH_KNN", "SEARCH_RADIUS",
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
@@ -41,7 +42,8 @@ GMLS_OK, GMLS_ERR_CAPACITY, GMLS_ERR_UNSUPPORTED, GMLS_WARN_TARGET_FLAGS = 0, 4,
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY", 5: "ERR_UNSUPPORTED",
            6: "WARN_TARGET_FLAGS"}
 EXPORTED_SYMBOLS = ("gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
-                    "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained", "gmls_apply", "gmls_check")
+                    "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained", "gmls_stencils_staggered",
+                    "gmls_apply", "gmls_check")
 
 
 class GmlsError(RuntimeError):
@@ -103,6 +105,12 @@ def load_library():
                                             ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
                                             ctypes.POINTER(Report)]
     L.gmls_stencils_constrained.restype = ctypes.c_int
+    # ctx, coords, n_src, targets, n_tgt, dim, order, mask, p, eps, row_ptr, col, prec, weights, t_weights,
+    # status, report
+    L.gmls_stencils_staggered.argtypes = [_vp, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                          ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
+                                          ctypes.POINTER(Report)]
+    L.gmls_stencils_staggered.restype = ctypes.c_int
     L.gmls_check.argtypes = [_vp]
     L.gmls_check.restype = ctypes.c_int
     _lib = L
@@ -263,6 +271,35 @@ def gmls_stencils_constrained(ctx: Context, coords: torch.Tensor, targets: torch
     if st not in (GMLS_OK, GMLS_WARN_TARGET_FLAGS):
         ctx._raise(st)
     return weights[: F * C * nnz], h_weights[:n_tgt], status[:n_tgt], (rep.as_dict() if report else None)
+
+
+def gmls_stencils_staggered(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, order: int, mask: int,
+                            weight_p: int, eps: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor,
+                            prec: int = PREC_FP64, weights: torch.Tensor | None = None,
+                            t_weights: torch.Tensor | None = None, status: torch.Tensor | None = None,
+                            report: bool = False):
+    """Staggered stencils (gradient and/or Laplacian of a scalar, vector order
+    `order`).  Returns (weights float64, target weights float64 [n_tgt, F],
+    status uint8, report dict or None)."""
+    _check_dev(coords, targets, eps, row_ptr, col)
+    n_src, dim = coords.shape
+    n_tgt = targets.shape[0]
+    F = (dim if mask & F_GRAD else 0) + (1 if mask & F_LAPLACIAN else 0)
+    nnz = col.numel()
+    dev = coords.device
+    if weights is None:
+        weights = torch.empty(max(F * nnz, 1), dtype=torch.float64, device=dev)
+    if t_weights is None:
+        t_weights = torch.empty((max(n_tgt, 1), max(F, 1)), dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.empty(max(n_tgt, 1), dtype=torch.uint8, device=dev)
+    rep = Report()
+    st = load_library().gmls_stencils_staggered(ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, order, mask,
+                                                weight_p, _ptr(eps), _ptr(row_ptr), _ptr(col), prec, _ptr(weights),
+                                                _ptr(t_weights), _ptr(status), ctypes.byref(rep) if report else None)
+    if st not in (GMLS_OK, GMLS_WARN_TARGET_FLAGS):
+        ctx._raise(st)
+    return weights[: F * nnz], t_weights[:n_tgt], status[:n_tgt], (rep.as_dict() if report else None)
 
 
 def gmls_apply(ctx: Context, row_ptr: torch.Tensor, col: torch.Tensor, weights: torch.Tensor, F: int, C: int,

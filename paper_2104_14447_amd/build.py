@@ -33,7 +33,8 @@ def units():
     for unit in ("mixed_unit.hip", "qr_unit.hip"):
         stem = unit.split("_")[0]
         for order in (4, 3, 2, 1):
-            for basis in (1, 0):
+            # basis 0 scalar, 1 divergence-free; 2 staggered (FP64 QR only)
+            for basis in ((1, 0) if stem == "mixed" else (1, 0, 2)):
                 for dim in (3, 2):
                     defs = [f"-DGMLS_DIM={dim}", f"-DGMLS_ORDER={order}", f"-DGMLS_BASIS={basis}"]
                     out.append((f"{stem}_d{dim}_o{order}_b{basis}", unit, defs))

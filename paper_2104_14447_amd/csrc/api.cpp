@@ -229,7 +229,8 @@ gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, co
 
 }  // extern "C"
 
-// plain (normals == nullptr) and Neumann-constrained stencils
+// plain (normals == nullptr), Neumann-constrained and staggered
+// (basis == kBasisStaggered) stencils
 static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
                                 int64_t n_tgt, int dim, int order, int basis, unsigned functional_mask, int weight_p,
                                 const double *eps, const int64_t *row_ptr, const int32_t *col,
@@ -238,8 +239,15 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
   if (!ctx) return GMLS_ERR_ARG;
   ctx->err.clear();
   int F = 0, C = 0, Q = 0;
-  gmls_status st = gmls_stencil_shape(dim, order, basis, functional_mask, &F, &C, &Q);
+  const bool stag = basis == kBasisStaggered;
+  gmls_status st = gmls_stencil_shape(dim, order, stag ? GMLS_BASIS_SCALAR : basis, functional_mask, &F, &C, &Q);
   if (st != GMLS_OK) return gmls_set_error(ctx, st, "functional/basis combination not supported or bad shape");
+  if (stag) {
+    Q -= 1;  // no constant monomial
+    if (prec != GMLS_PREC_FP64)
+      return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "staggered stencils are computed in FP64 (GMLS_PREC_FP64)");
+    if (n_tgt > 0 && !hweights) return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer (target_weights)");
+  }
   if (!qr_supported(dim, order, basis))
     return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "compiled kernels cover dim 2-3 and order 1-4");
   if (prec != GMLS_PREC_FP64 && prec != GMLS_PREC_MIXED) return gmls_set_error(ctx, GMLS_ERR_ARG, "bad precision");
@@ -394,6 +402,21 @@ gmls_status gmls_stencils_constrained(gmls_ctx ctx, const double *coords, int64_
   return run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, GMLS_BASIS_SCALAR, functional_mask, weight_p,
                       eps, row_ptr, col, n_tgt > 0 ? normals : &kNoNormal, prec, weights, h_weights, target_status,
                       report);
+}
+
+gmls_status gmls_stencils_staggered(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                    int64_t n_tgt, int dim, int order, unsigned functional_mask, int weight_p,
+                                    const double *eps, const int64_t *row_ptr, const int32_t *col, int prec,
+                                    double *weights, double *target_weights, uint8_t *target_status,
+                                    gmls_report *report) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (functional_mask == 0 || (functional_mask & ~(unsigned)(GMLS_F_GRAD | GMLS_F_LAPLACIAN)))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "staggered stencils provide GMLS_F_GRAD and GMLS_F_LAPLACIAN only");
+  if (order < 0 || order > 3)
+    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "staggered vector order must be 0..3");
+  return run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order + 1, kBasisStaggered, functional_mask, weight_p,
+                      eps, row_ptr, col, nullptr, prec, weights, target_weights, target_status, report);
 }
 
 gmls_status gmls_check(gmls_ctx ctx) {

@@ -44,6 +44,10 @@ enum Slot {
   WS_NUM_SLOTS
 };
 
+// internal basis id of the staggered scheme: scalar monomials of degree
+// 1..order without the constant, FP64 QR only (gmls_stencils_staggered)
+constexpr int kBasisStaggered = 2;
+
 // mixed-precision schemes (GMLS_OPT_MIXED_SCHEME)
 enum MixedScheme { MIXED_AUTO = 0, MIXED_ROWS = 1, MIXED_GRAM = 2, MIXED_PIPE = 3 };
 

@@ -217,6 +217,7 @@ __global__ void k_rank_deficient(StencilArgs a, int C, const int *list, const Bi
     const int64_t base = a.row_ptr[t];
     const int64_t len = (a.row_ptr[t + 1] - base) * a.F * C;
     for (int64_t q = threadIdx.x; q < len; q += blockDim.x) a.weights[(int64_t)a.F * C * base + q] = NAN;
+    if (a.hweights && (int)threadIdx.x < a.F) a.hweights[(int64_t)t * a.F + threadIdx.x] = NAN;
     if (threadIdx.x == 0) a.status[t] = GMLS_TARGET_RANK_DEFICIENT;
   }
 }

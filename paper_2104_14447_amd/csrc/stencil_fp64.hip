@@ -37,13 +37,31 @@ hipError_t launch_qr_d3_o4_b0(int, const StencilArgs &, const int *, const int *
 hipError_t launch_qr_d3_o4_b1(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
                                hipStream_t);
 
+hipError_t launch_qr_d2_o1_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d2_o2_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d2_o3_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d2_o4_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o1_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o2_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o3_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+hipError_t launch_qr_d3_o4_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
+                               hipStream_t);
+
 using QrFn = hipError_t (*)(int, const StencilArgs &, const int *, const int *, const int *, int *, int, hipStream_t);
-static const QrFn kQr[2][4][2] = {
-    {{launch_qr_d2_o1_b0, launch_qr_d2_o1_b1}, {launch_qr_d2_o2_b0, launch_qr_d2_o2_b1}, {launch_qr_d2_o3_b0, launch_qr_d2_o3_b1}, {launch_qr_d2_o4_b0, launch_qr_d2_o4_b1}},
-    {{launch_qr_d3_o1_b0, launch_qr_d3_o1_b1}, {launch_qr_d3_o2_b0, launch_qr_d3_o2_b1}, {launch_qr_d3_o3_b0, launch_qr_d3_o3_b1}, {launch_qr_d3_o4_b0, launch_qr_d3_o4_b1}}};
+// [dim - 2][order - 1][basis]: basis 0 scalar, 1 divergence-free, 2 staggered
+static const QrFn kQr[2][4][3] = {
+    {{launch_qr_d2_o1_b0, launch_qr_d2_o1_b1, launch_qr_d2_o1_b2}, {launch_qr_d2_o2_b0, launch_qr_d2_o2_b1, launch_qr_d2_o2_b2}, {launch_qr_d2_o3_b0, launch_qr_d2_o3_b1, launch_qr_d2_o3_b2}, {launch_qr_d2_o4_b0, launch_qr_d2_o4_b1, launch_qr_d2_o4_b2}},
+    {{launch_qr_d3_o1_b0, launch_qr_d3_o1_b1, launch_qr_d3_o1_b2}, {launch_qr_d3_o2_b0, launch_qr_d3_o2_b1, launch_qr_d3_o2_b2}, {launch_qr_d3_o3_b0, launch_qr_d3_o3_b1, launch_qr_d3_o3_b2}, {launch_qr_d3_o4_b0, launch_qr_d3_o4_b1, launch_qr_d3_o4_b2}}};
 
 bool qr_supported(int dim, int order, int basis) {
-  return (dim == 2 || dim == 3) && order >= 1 && order <= 4 && (basis == 0 || basis == 1);
+  return (dim == 2 || dim == 3) && order >= 1 && order <= 4 && basis >= 0 && basis <= 2;
 }
 
 static hipError_t dispatch_qr(int dim, int order, int basis, int rpl, const StencilArgs &a, const int *list,

@@ -134,21 +134,30 @@ __device__ __forceinline__ double tri_solve_rtr(const double *Rm, const double *
   return b;
 }
 
-template <int DIM, int ORDER, int RPL>
+// SKIP = 1 drops the constant monomial: the staggered scheme (Section 2.4).
+// Its sample of the vector basis phi_(a,k) = e_k p_a along the segment
+// x_T -> x_j is xi = eps s_k p_a(s) / (|a| + 1); the span of those columns is
+// that of the scalar monomials of degree 1..m+1 evaluated at s (by Euler's
+// relation every homogeneous h of degree n+1 is grad(h) . s / (n+1)), and
+// the gradient and divergence of the fit at x_T are the first and second
+// derivatives of the scalar fit there.  The data are p_j - p(x_T), so the
+// target's own value carries the weight -sum_j alpha_j (into hweights).
+template <int DIM, int ORDER, int RPL, int SKIP = 0>
 __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
   constexpr Mono<DIM, ORDER> MO{};
-  constexpr int Q = MO.N;
+  constexpr int QF = MO.N;       // monomials of degree <= ORDER
+  constexpr int Q = QF - SKIP;   // columns of the sample matrix
   const int lane = lane_id();
   Rows<DIM, RPL> r;
   load_rows<DIM, RPL>(a, t, r, lane);
   double M[RPL][Q];
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
-    double p[Q];
+    double p[QF];
     scaled_basis<DIM, ORDER, double>(r.s[i], p);
     const double sw = sqrt(r.w[i]);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q];
+    for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q + SKIP];
   }
   double rdiag;
   wave_householder<Q, RPL>(M, rdiag, lane);
@@ -185,7 +194,7 @@ __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t
   // g = F^T y / F^T z; lane q holds component q of every vector.
   double Fq = 0.0, zc = 0.0, sF = 0.0;
   bool con = false;
-  if (a.normals) {
+  if (SKIP == 0 && a.normals) {
     for (int d = 0; d < DIM; ++d) {
       const double nd = uniform_d(a.normals[(int64_t)t * DIM + d]);
       if (lane == 1 + d) Fq = nd * ie;
@@ -200,30 +209,44 @@ __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t
     double b = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q)
-      if (lane == q) b = scalar_lambda<DIM, ORDER>(rk.kind[f], q, ie);
+      if (lane == q) b = scalar_lambda<DIM, ORDER>(rk.kind[f], q + SKIP, ie);
     double y = tri_solve_rtr<Q>(Rm, Rt, b, rdiag, lane);
     if (con) {
       const double g = uniform_d(wave_sum(lane < Q ? Fq * y : 0.0)) / sF;
       y -= g * zc;
       if (lane == 0) a.hweights[(int64_t)t * F + f] = g;
-    } else if (a.hweights && lane == 0) {
+    } else if (SKIP == 0 && a.hweights && lane == 0) {
       a.hweights[(int64_t)t * F + f] = 0.0;
     }
     if (lane < Q) Y[f * Q + lane] = y;
   }
   __syncthreads();
+  double rsum[4] = {0.0, 0.0, 0.0, 0.0};  // staggered: F <= 4 (gradient, Laplacian)
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int j = lane + 64 * i;
     if (j < r.N) {
-      double p[Q];
+      double p[QF];
       scaled_basis<DIM, ORDER, double>(r.s[i], p);
       for (int f = 0; f < F; ++f) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc += p[q] * Y[f * Q + q];
-        a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = r.w[i] * acc;
+        for (int q = 0; q < Q; ++q) acc += p[q + SKIP] * Y[f * Q + q];
+        const double wv = r.w[i] * acc;
+        a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = wv;
+        if constexpr (SKIP != 0) {
+#pragma unroll
+          for (int g = 0; g < 4; ++g)
+            if (g == f) rsum[g] += wv;
+        }
       }
+    }
+  }
+  if constexpr (SKIP != 0) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const double tot = wave_sum(rsum[f]);
+      if (f < F && lane == 0) a.hweights[(int64_t)t * F + f] = -tot;
     }
   }
   if (lane == 0 && a.ok_status >= 0) a.status[t] = (uint8_t)a.ok_status;
@@ -408,7 +431,7 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
 template <int DIM, int ORDER, int BASIS>
 constexpr int qr_lds_doubles() {
   constexpr int Q = num_mono(DIM, ORDER);
-  if (BASIS == 0) return 2 * Q * Q + 8 * Q;
+  if (BASIS != 1) return 2 * Q * Q + 8 * Q;
   constexpr int QD = DivFreeTab<DIM, ORDER>::QD;
   constexpr int KR = DIM * Q;
   return Q * Q + QD * KR + 8 * QD + 8 * KR + QD;
@@ -419,7 +442,7 @@ template <int DIM, int ORDER, int BASIS, int RPL>
 __global__ __launch_bounds__(64) void k_qr(StencilArgs a, const int *list, const int *count, const int *offset,
                                            int *cursor) {
   __shared__ double lds[qr_lds_doubles<DIM, ORDER, BASIS>()];
-  const RowKinds rk = row_kinds(DIM, BASIS, a.mask);
+  const RowKinds rk = row_kinds(DIM, BASIS == 1 ? 1 : 0, a.mask);
   const int n = readfirstlane_i(*count);
   const int off = readfirstlane_i(offset ? *offset : 0);
   for (;;) {
@@ -428,8 +451,10 @@ __global__ __launch_bounds__(64) void k_qr(StencilArgs a, const int *list, const
     i = __builtin_amdgcn_readfirstlane(i);
     if (i >= n) break;
     const int t = readfirstlane_i(list[off + i]);
-    if (BASIS == 0)
+    if constexpr (BASIS == 0)
       qr_scalar_target<DIM, ORDER, RPL>(a, rk, t, lds);
+    else if constexpr (BASIS == 2)
+      qr_scalar_target<DIM, ORDER, RPL, 1>(a, rk, t, lds);
     else
       qr_divfree_target<DIM, ORDER, RPL>(a, rk, t, lds);
   }

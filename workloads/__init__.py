@@ -125,6 +125,21 @@ WORKLOADS = {
         bases=[("scalar", 4, F_GRAD | F_LAPLACIAN), ("divfree", 4, F_LAPLACIAN | F_DIV)],
         modes=("mixed", "fp64"),
     ),
+    # the two variants of the pressure side (Sections 2.3 and 2.4), FP64 QR
+    # path: staggered gradient + Laplacian of vector order 2 on the C4 cloud
+    # and search, and Neumann-constrained Laplacian stencils (scalar order 3)
+    # for 60 000 points on the faces of the unit cube (outward normals) with
+    # kNN rows into the C3 cloud
+    "s4_3d_staggered_m2": dict(
+        n=2_000_000, dim=3, seed=1004, gen="ramp",
+        search=("radius", radius_for_mean_count(2_000_000), 30), p=4,
+        bases=[("staggered", 2, F_GRAD | F_LAPLACIAN)], modes=("fp64",),
+    ),
+    "n3_3d_neumann_m3": dict(
+        n=1_000_000, dim=3, seed=1003, gen="grid", targets=("boundary", 60_000, 1103),
+        search=("knn", 80, 1.5), p=4,
+        bases=[("neumann", 3, F_LAPLACIAN)], modes=("fp64",),
+    ),
 }
 
 
