@@ -30,6 +30,7 @@ __all__ = [
     "radius_for_mean_count",
     "WORKLOADS",
     "boundary_points",
+    "stokes_cloud",
     "make_points",
     "random_poly_coeffs",
     "monomial_exponents",
@@ -71,6 +72,34 @@ def boundary_points(n_points: int, dim: int, seed: int) -> tuple[np.ndarray, np.
     pts[np.arange(n_points), axis] = side.astype(np.float64)
     nrm[np.arange(n_points), axis] = np.where(side == 1, 1.0, -1.0)
     return np.ascontiguousarray(pts), nrm
+
+
+def stokes_cloud(n_side: int, dim: int, seed: int) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Particles of [-1,1]^dim: a jittered n_side^dim grid inside (nodes
+    (i + 1/2) h - 1, h = 2/n_side, jitter U(-h/4, h/4)), then on every face
+    an n_side^(dim-1) grid of the same nodes jittered within the face.
+    Returns (points, boundary flag uint8, outward unit normals)."""
+    g = rng(seed)
+    h = 2.0 / n_side
+    ax = (np.arange(n_side) + 0.5) * h - 1.0
+    inner = np.stack(np.meshgrid(*([ax] * dim), indexing="ij"), -1).reshape(-1, dim)[:, ::-1].copy()
+    inner += g.uniform(-h / 4, h / 4, size=inner.shape)
+    faces, nrms = [], []
+    grid = np.stack(np.meshgrid(*([ax] * (dim - 1)), indexing="ij"), -1).reshape(-1, dim - 1)
+    for axis in range(dim):
+        for side in (-1.0, 1.0):
+            f = np.zeros((len(grid), dim))
+            others = [k for k in range(dim) if k != axis]
+            f[:, others] = grid + g.uniform(-h / 4, h / 4, size=grid.shape)
+            f[:, axis] = side
+            nv = np.zeros((len(grid), dim))
+            nv[:, axis] = side
+            faces.append(f)
+            nrms.append(nv)
+    pts = np.concatenate([inner] + faces)
+    nrm = np.concatenate([np.zeros_like(inner)] + nrms)
+    bnd = np.concatenate([np.zeros(len(inner), np.uint8), np.ones(len(pts) - len(inner), np.uint8)])
+    return np.ascontiguousarray(pts), bnd, np.ascontiguousarray(nrm)
 
 
 def density_ramp(n_points: int, seed: int, batch: int = 1 << 22) -> np.ndarray:
