@@ -154,13 +154,82 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy (counter scaling) and exit")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of HIP graph replays of search + stencils")
+    ap.add_argument("--stokes", type=int, default=0, metavar="N_SIDE",
+                    help="time the global Stokes operator build on a [-1,1]^3 cloud of N_SIDE^3 interior "
+                         "particles instead")
     return ap.parse_args()
+
+
+def stokes_main(args):
+    """The global Stokes operator of the paper's scheme on [-1,1]^3: search,
+    the four stencil families (FP64), assembly and operator application,
+    each timed with HIP events; the manufactured quadratic solution's
+    residual is the correctness gate."""
+    import torch
+
+    import paper_2104_14447_amd as G
+    from tests.manufactured import exact_system  # closed forms of the paper's manufactured solution
+
+    n_side, k = args.stokes, 80
+    pts, bnd, nrm = W.stokes_cloud(n_side, 3, 2024)
+    n = len(pts)
+    c = G.Context(0)
+    x, bt, nt = (torch.from_numpy(a).cuda() for a in (pts, bnd, nrm))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    times = {"search": [], "stencils": [], "assembly": [], "spmv": []}
+    for it in range(args.warmup + args.steps):
+        ev[0].record()
+        rp, col, eps = G.gmls_neighbors(c, x, x, G.SEARCH_KNN, k=k, eps_mult=1.5)
+        ev[1].record()
+        vlap, _, _ = G.gmls_stencils(c, x, x, 2, G.BASIS_DIVFREE, G.F_LAPLACIAN, 4, eps, rp, col, prec=G.PREC_FP64)
+        grad, _, _ = G.gmls_stencils(c, x, x, 3, G.BASIS_SCALAR, G.F_GRAD, 4, eps, rp, col, prec=G.PREC_FP64)
+        plap, plap_t, _, _ = G.gmls_stencils_staggered(c, x, x, 2, G.F_LAPLACIAN, 4, eps, rp, col)
+        nlap, nlap_h, _, _ = G.gmls_stencils_constrained(c, x, x, 3, G.F_LAPLACIAN, 4, eps, rp, col, nt)
+        ev[2].record()
+        arp, acol, aval = G.gmls_assemble_stokes(c, rp, col, bt, nt, vlap, grad, plap, plap_t.reshape(-1),
+                                                 nlap, nlap_h.reshape(-1))
+        ev[3].record()
+        if it == 0:
+            xs, rhs = exact_system(pts, bnd, nrm, nlap_h.reshape(-1).cpu().numpy(), 1.0)
+            xd = torch.from_numpy(xs).cuda()
+            y = torch.empty_like(xd)
+        for _ in range(10):
+            G.gmls_spmv(c, arp, acol, aval, xd, y)
+        ev[4].record()
+        torch.cuda.synchronize()
+        if it >= args.warmup:
+            for key, a_, b_ in (("search", 0, 1), ("stencils", 1, 2), ("assembly", 2, 3)):
+                times[key].append(ev[a_].elapsed_time(ev[b_]))
+            times["spmv"].append(ev[3].elapsed_time(ev[4]) / 10)
+        print(f"# stokes step {it} done", file=sys.stderr, flush=True)
+    yh = y.cpu().numpy()
+    # rounding scale of each row: |A| |x| + |rhs|, the product on the GPU
+    scale = G.gmls_spmv(c, arp, acol, aval.abs(), xd.abs()).cpu().numpy() + np.abs(rhs)
+    resid = float((np.abs(yh - rhs) / scale).max())
+    t = {k_: float(np.median(v)) for k_, v in times.items()}
+    total = t["search"] + t["stencils"] + t["assembly"]
+    nnz = int(acol.numel())
+    spmv_bytes = nnz * 12 + (len(xs) + 1) * 8 + 2 * len(xs) * 8
+    line = {"metric": "Stokes operator build (search + 4 stencil families FP64 + assembly), particles/s",
+            "value": round(n / (total * 1e-3), 1), "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": round(total, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"[-1,1]^3 cloud: {n_side}^3 jittered interior + {n - n_side ** 3} boundary "
+                                   f"particles, kNN {k}; div-free m2 vector Laplacian, scalar m3 gradient, "
+                                   f"staggered m2 Laplacian, Neumann m3 Laplacian",
+                       "n_particles": n, "rows": len(xs), "nnz": nnz, "phase_ms": t,
+                       "manufactured_residual": resid, "gate": resid <= 1e-9,
+                       "spmv_GBs": round(spmv_bytes / (t["spmv"] * 1e-3) / 1e9, 1)}}
+    print(json.dumps(line))
 
 
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.stokes:
+        stokes_main(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -323,70 +392,106 @@ def main():
         for bs in bases:
             bs["w"], bs["st"], bs["aux"] = bs["gw"], bs["gst"], bs["gaux"]
 
-    # ---- parity gate on sampled targets (same process, same outputs) ----
-    import oracle
+    # ---- the CPU-baseline leg: the only part of this file that uses the
+    # oracle.  It checks sampled outputs of the timed run against it (the
+    # parity gate) and, unless --no-cpu-baseline, times it on the host ----
+    def cpu_baseline_leg():
+        import oracle
 
-    rph = rp_t.cpu().numpy()
-    epsh = eps_t.cpu().numpy()
-    g = W.rng(424242)
-    sample = np.sort(g.choice(n_t, size=min(args.sample, n_t), replace=False))
-    idx = torch.from_numpy(np.concatenate([np.arange(rph[t], rph[t + 1]) for t in sample])).cuda()
-    scol = col_t[idx].cpu().numpy()
-    srp = np.zeros(len(sample) + 1, dtype=np.int64)
-    srp[1:] = np.cumsum(np.diff(rph)[sample])
-    if knn:
-        orp, ocol, oeps = oracle.knn(pts, tpts[sample], k, mult)
-    else:
-        orp, ocol, oeps = oracle.radius(pts, tpts[sample], r0, k_min)
-    if knn:
-        same_rows = np.array_equal(scol, ocol)
-    else:  # radius rows are sets: cell order on the GPU, index order in the oracle
-        rows = np.repeat(np.arange(len(srp) - 1), np.diff(srp))
-        same_rows = np.array_equal(srp, orp) and np.array_equal(scol[np.lexsort((scol, rows))], ocol)
-    search_ok = np.array_equal(srp, orp) and same_rows and np.array_equal(epsh[sample], oeps)
-    seps = epsh[sample]
-    max_err = 0.0
-    status_ok = True
-    for bs in bases:
-        F, C = bs["F"], bs["C"]
-        widx = torch.from_numpy(np.concatenate([np.arange(F * C * rph[t], F * C * rph[t + 1])
-                                                for t in sample])).cuda()
-        wh = bs["w"][widx].cpu().numpy()
-        sth = bs["st"].cpu().numpy()[sample]
-        if bs["name"] == "staggered":
-            from oracle import staggered as OS
-            ow, oaux, _ = OS.stencils_staggered(pts, tpts[sample], bs["order"], bs["mask"], p, seps, srp, scol)
-            ost = np.zeros(len(sample), dtype=np.uint8)
-        elif bs["name"] == "neumann":
-            from oracle import constrained as OC
-            ow, oaux, _ = OC.stencils_constrained(pts, tpts[sample], bs["order"], bs["mask"], p, seps, srp, scol,
-                                                  nrm_h[sample])
-            ost = np.zeros(len(sample), dtype=np.uint8)
+        rph = rp_t.cpu().numpy()
+        epsh = eps_t.cpu().numpy()
+        g = W.rng(424242)
+        sample = np.sort(g.choice(n_t, size=min(args.sample, n_t), replace=False))
+        idx = torch.from_numpy(np.concatenate([np.arange(rph[t], rph[t + 1]) for t in sample])).cuda()
+        scol = col_t[idx].cpu().numpy()
+        srp = np.zeros(len(sample) + 1, dtype=np.int64)
+        srp[1:] = np.cumsum(np.diff(rph)[sample])
+        if knn:
+            orp, ocol, oeps = oracle.knn(pts, tpts[sample], k, mult)
         else:
-            ow, ost, _, _ = oracle.stencils(pts, tpts[sample], bs["order"], bs["name"], bs["mask"], p, seps, srp,
-                                            scol)
-            oaux = None
-        status_ok = status_ok and np.array_equal(sth == 1, ost == 1)
-        if oaux is not None:  # target weights / h-weights, relative to the row norms
-            gaux = bs["aux"].cpu().numpy()[sample]
+            orp, ocol, oeps = oracle.radius(pts, tpts[sample], r0, k_min)
+        if knn:
+            same_rows = np.array_equal(scol, ocol)
+        else:  # radius rows are sets: cell order on the GPU, index order in the oracle
+            rows = np.repeat(np.arange(len(srp) - 1), np.diff(srp))
+            same_rows = np.array_equal(srp, orp) and np.array_equal(scol[np.lexsort((scol, rows))], ocol)
+        search_ok = np.array_equal(srp, orp) and same_rows and np.array_equal(epsh[sample], oeps)
+        seps = epsh[sample]
+        max_err = 0.0
+        status_ok = True
+        for bs in bases:
+            F, C = bs["F"], bs["C"]
+            widx = torch.from_numpy(np.concatenate([np.arange(F * C * rph[t], F * C * rph[t + 1])
+                                                    for t in sample])).cuda()
+            wh = bs["w"][widx].cpu().numpy()
+            sth = bs["st"].cpu().numpy()[sample]
+            if bs["name"] == "staggered":
+                from oracle import staggered as OS
+                ow, oaux, _ = OS.stencils_staggered(pts, tpts[sample], bs["order"], bs["mask"], p, seps, srp, scol)
+                ost = np.zeros(len(sample), dtype=np.uint8)
+            elif bs["name"] == "neumann":
+                from oracle import constrained as OC
+                ow, oaux, _ = OC.stencils_constrained(pts, tpts[sample], bs["order"], bs["mask"], p, seps, srp, scol,
+                                                      nrm_h[sample])
+                ost = np.zeros(len(sample), dtype=np.uint8)
+            else:
+                ow, ost, _, _ = oracle.stencils(pts, tpts[sample], bs["order"], bs["name"], bs["mask"], p, seps, srp,
+                                                scol)
+                oaux = None
+            status_ok = status_ok and np.array_equal(sth == 1, ost == 1)
+            if oaux is not None:  # target weights / h-weights, relative to the row norms
+                gaux = bs["aux"].cpu().numpy()[sample]
+                for q in range(len(sample)):
+                    b_ = ow[F * srp[q]:F * srp[q + 1]].reshape(F, -1)
+                    den = np.hypot(np.linalg.norm(b_, axis=1), oaux[q])
+                    max_err = max(max_err, float((np.abs(gaux[q] - oaux[q]) / np.where(den > 0, den, 1.0)).max()))
+            zero = F - 1 if bs["name"] == "divfree" and bs["mask"] & G.F_DIV else -1
             for q in range(len(sample)):
-                b_ = ow[F * srp[q]:F * srp[q + 1]].reshape(F, -1)
-                den = np.hypot(np.linalg.norm(b_, axis=1), oaux[q])
-                max_err = max(max_err, float((np.abs(gaux[q] - oaux[q]) / np.where(den > 0, den, 1.0)).max()))
-        zero = F - 1 if bs["name"] == "divfree" and bs["mask"] & G.F_DIV else -1
-        for q in range(len(sample)):
-            if ost[q] == 1:
-                continue
-            a = wh[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
-            b_ = ow[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
-            den = np.linalg.norm(b_, axis=1)
-            if zero >= 0:
-                den[zero] = den[0]
-            max_err = max(max_err, float((np.linalg.norm(a - b_, axis=1) / den).max()))
-    tol = 1e-8 if prec_name == "mixed" else 1e-10
-    gate = bool(search_ok and status_ok and max_err <= tol)
-    print(f"# parity: search {'ok' if search_ok else 'MISMATCH'}; max rel err {max_err:.3e} (gate {tol:g})",
-          file=sys.stderr, flush=True)
+                if ost[q] == 1:
+                    continue
+                a = wh[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
+                b_ = ow[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
+                den = np.linalg.norm(b_, axis=1)
+                if zero >= 0:
+                    den[zero] = den[0]
+                max_err = max(max_err, float((np.linalg.norm(a - b_, axis=1) / den).max()))
+        tol = 1e-8 if prec_name == "mixed" else 1e-10
+        gate = bool(search_ok and status_ok and max_err <= tol)
+        print(f"# parity: search {'ok' if search_ok else 'MISMATCH'}; max rel err {max_err:.3e} (gate {tol:g})",
+              file=sys.stderr, flush=True)
+
+
+        cpu = None
+        if not args.no_cpu_baseline and all(bs["name"] in ("scalar", "divfree") for bs in bases) and n_t == n:
+            threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
+
+            def oracle_run(m):
+                sub = np.arange(m)
+                if knn:
+                    a_rp, a_col, a_eps = oracle.knn(pts, pts[sub], k, mult, use_grid=True, nthreads=threads)
+                else:
+                    a_rp, a_col, a_eps = oracle.radius(pts, pts[sub], r0, k_min, use_grid=True, nthreads=threads)
+                for bs in bases:
+                    oracle.stencils(pts, pts[sub], bs["order"], bs["name"], bs["mask"], p, a_eps, a_rp, a_col,
+                                    nthreads=threads)
+
+            # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds
+            m = max(1000, n // 64)
+            t1 = time.perf_counter()
+            oracle_run(m)
+            dt = time.perf_counter() - t1
+            m2 = int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
+            t1 = time.perf_counter()
+            oracle_run(m2)
+            dt = time.perf_counter() - t1
+            what = "all" if m2 == n else f"the first {m2} of the"
+            cpu = {"value": round(m2 / dt, 1), "unit": "stencils/s", "cores": threads, "kind": "oracle",
+                   "sample": f"{what} {n} targets of the same point cloud: bucket-grid neighbour search + "
+                             f"Householder-QR stencils in FP64, {dt:.1f} s wall on {threads} threads"}
+
+        return gate, max_err, len(sample), cpu
+
+    gate, max_err, n_sample, cpu = cpu_baseline_leg()
 
     # ---- roofline of the stencil phase (its kernels timed by HIP events on
     # the library's stream, inside the timed steps) ----
@@ -403,35 +508,6 @@ def main():
                 "kernel_ms": round(t_sten * 1e3, 4),
                 "frac_of_fp64_peak": round(achieved_tf / PEAK["fp64_TFs"], 4),
                 "search_ms": round(float(np.mean(search_ms)), 4)}
-
-    # ---- CPU baseline: the oracle on a bounded sample of the same workload ----
-    cpu = None
-    if not args.no_cpu_baseline and all(bs["name"] in ("scalar", "divfree") for bs in bases) and n_t == n:
-        threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
-
-        def oracle_run(m):
-            sub = np.arange(m)
-            if knn:
-                a_rp, a_col, a_eps = oracle.knn(pts, pts[sub], k, mult, use_grid=True, nthreads=threads)
-            else:
-                a_rp, a_col, a_eps = oracle.radius(pts, pts[sub], r0, k_min, use_grid=True, nthreads=threads)
-            for bs in bases:
-                oracle.stencils(pts, pts[sub], bs["order"], bs["name"], bs["mask"], p, a_eps, a_rp, a_col,
-                                nthreads=threads)
-
-        # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds
-        m = max(1000, n // 64)
-        t1 = time.perf_counter()
-        oracle_run(m)
-        dt = time.perf_counter() - t1
-        m2 = int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
-        t1 = time.perf_counter()
-        oracle_run(m2)
-        dt = time.perf_counter() - t1
-        what = "all" if m2 == n else f"the first {m2} of the"
-        cpu = {"value": round(m2 / dt, 1), "unit": "stencils/s", "cores": threads, "kind": "oracle",
-               "sample": f"{what} {n} targets of the same point cloud: bucket-grid neighbour search + "
-                         f"Householder-QR stencils in FP64, {dt:.1f} s wall on {threads} threads"}
 
     value = n_t / (ms_per_step * 1e-3)
     line = {
@@ -452,7 +528,7 @@ def main():
                    "search": wl["search"][0] + (f" k={k}" if knn else f" r={r0:.6f} k_min={k_min}"),
                    "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
                                     "pipeline"][args.scheme],
-                   "parity_gate": gate, "parity_max_rel_err": max_err, "parity_sample": int(len(sample)),
+                   "parity_gate": gate, "parity_max_rel_err": max_err, "parity_sample": int(n_sample),
                    "timed_unit": "HIP graph replay of search + stencils" if graph else "eager calls",
                    "ms_per_step_eager": round(ms_eager, 4),
                    "fallbacks": int(sum(r["n_fallback"] + r["n_not_converged"] for r in reps)),

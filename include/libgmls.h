@@ -235,6 +235,55 @@ gmls_status gmls_stencils_staggered(gmls_ctx ctx, const double *coords, int64_t 
                                     double *weights, double *target_weights, uint8_t *target_status,
                                     gmls_report *report);
 
+/* Stencils of the Stokes system (Section 3.2) for n particles, every one
+ * computed on the same neighbour rows (row_ptr, col) for every particle, in
+ * the gmls_stencils layouts.  All pointers are device pointers. */
+typedef struct {
+  int64_t n;              /* particles */
+  int32_t dim;            /* 2 or 3 */
+  int32_t reserved;
+  const int64_t *row_ptr; /* [n + 1] neighbour rows */
+  const int32_t *col;     /* [row_ptr[n]] */
+  const uint8_t *boundary;/* [n] nonzero for a boundary particle */
+  const double *normals;  /* [n][dim] outward unit normals (read for boundary particles) */
+  const double *vlap;     /* divergence-free vector Laplacian (gmls_stencils, GMLS_F_LAPLACIAN,
+                             F = C_in = dim) */
+  const double *grad;     /* scalar gradient (GMLS_F_GRAD, F = dim); interior rows */
+  const double *plap;     /* staggered Laplacian (gmls_stencils_staggered, GMLS_F_LAPLACIAN);
+                             interior rows */
+  const double *plap_t;   /* its target weights [n] */
+  const double *nlap;     /* Neumann-constrained Laplacian (gmls_stencils_constrained,
+                             GMLS_F_LAPLACIAN); boundary rows */
+  const double *nlap_h;   /* its h-weights [n] */
+} gmls_stokes_stencils;
+
+/* Global Stokes operator of Section 3.2 (the block system [K G 0; N L 1;
+ * 0 1 0]) as one CSR matrix of R = dim*n + n + 1 rows.  Unknown and row
+ * order: velocity v_(J,c) at J*dim + c, pressure phi_J at dim*n + J, the
+ * zero-mean multiplier at dim*n + n.  Rows, nu the viscosity:
+ *   interior velocity (I, c): -nu sum_j vlap v + sum_j grad phi      (K, G)
+ *   boundary velocity (I, c): v_(I,c)                                 (K = identity)
+ *   interior pressure I:      sum_j plap phi + plap_t[I] phi_I + lambda          (L)
+ *   boundary pressure I:      nu nlap_h[I] sum_j n_I . vlap v + sum_j nlap phi + lambda
+ *                                                                    (N, L)
+ *   multiplier:               sum_J phi_J
+ * so that the right-hand side is (f or the boundary velocity w; div f, or
+ * div f - nlap_h[I] n_I . f on the boundary; 0).  Entries of a row follow
+ * the neighbour order (velocity block, then pressure, then multiplier).
+ *   a_row_ptr out: int64 [R + 1];  a_col out: int32 [capacity];
+ *   a_val out: FP64 [capacity];    nnz_host out: entries needed
+ * If they exceed capacity nothing is written to a_col/a_val and
+ * GMLS_ERR_CAPACITY is returned.  Synchronises; not available in
+ * capture-safe mode (GMLS_ERR_ARG). */
+gmls_status gmls_assemble_stokes(gmls_ctx ctx, const gmls_stokes_stencils *stencils, double nu, int64_t *a_row_ptr,
+                                 int32_t *a_col, double *a_val, int64_t capacity, int64_t *nnz_host);
+
+/* y = A x for a CSR matrix of n_rows rows (device pointers; col int32, values
+ * and vectors FP64).  Each row is summed in a fixed order, so y is the same on
+ * every call.  Does not synchronise. */
+gmls_status gmls_spmv(gmls_ctx ctx, int64_t n_rows, const int64_t *row_ptr, const int32_t *col, const double *val,
+                      const double *x, double *y);
+
 /* Errors of capture-safe calls found on the device since the last check
  * (GMLS_OPT_CAPTURE_SAFE): GMLS_OK, GMLS_ERR_CAPACITY or GMLS_ERR_UNSUPPORTED
  * with a message in gmls_last_error.  Synchronises; clears the record. */

@@ -19,7 +19,7 @@ import torch
 __all__ = [
     "LIB_PATH", "GmlsError", "Context", "SearchSpec", "Report", "load_library",
     "gmls_neighbors", "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained",
-    "gmls_stencils_staggered", "gmls_apply",
+    "gmls_stencils_staggered", "gmls_assemble_stokes", "gmls_spmv", "StokesStencils", "gmls_apply",
     "BASIS_SCALAR", "BASIS_DIVFREE", "F_VALUE", "F_GRAD", "F_LAPLACIAN", "F_DIV",
     "PREC_FP64", "PREC_MIXED", "SEARCH_KNN", "SEARCH_RADIUS",
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
@@ -43,7 +43,7 @@ _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY
            6: "WARN_TARGET_FLAGS"}
 EXPORTED_SYMBOLS = ("gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
                     "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained", "gmls_stencils_staggered",
-                    "gmls_apply", "gmls_check")
+                    "gmls_assemble_stokes", "gmls_spmv", "gmls_apply", "gmls_check")
 
 
 class GmlsError(RuntimeError):
@@ -55,6 +55,12 @@ class GmlsError(RuntimeError):
 class SearchSpec(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("k", ctypes.c_int32), ("eps_mult", ctypes.c_double),
                 ("radius", ctypes.c_double), ("k_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class StokesStencils(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("dim", ctypes.c_int32), ("reserved", ctypes.c_int32)] + \
+        [(k, ctypes.c_void_p) for k in ("row_ptr", "col", "boundary", "normals", "vlap", "grad", "plap", "plap_t",
+                                         "nlap", "nlap_h")]
 
 
 class Report(ctypes.Structure):
@@ -111,6 +117,11 @@ def load_library():
                                           ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, _vp,
                                           ctypes.POINTER(Report)]
     L.gmls_stencils_staggered.restype = ctypes.c_int
+    L.gmls_assemble_stokes.argtypes = [_vp, ctypes.POINTER(StokesStencils), _d, _vp, _vp, _vp, _i64,
+                                       ctypes.POINTER(ctypes.c_int64)]
+    L.gmls_assemble_stokes.restype = ctypes.c_int
+    L.gmls_spmv.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp]
+    L.gmls_spmv.restype = ctypes.c_int
     L.gmls_check.argtypes = [_vp]
     L.gmls_check.restype = ctypes.c_int
     _lib = L
@@ -300,6 +311,48 @@ def gmls_stencils_staggered(ctx: Context, coords: torch.Tensor, targets: torch.T
     if st not in (GMLS_OK, GMLS_WARN_TARGET_FLAGS):
         ctx._raise(st)
     return weights[: F * nnz], t_weights[:n_tgt], status[:n_tgt], (rep.as_dict() if report else None)
+
+
+def gmls_assemble_stokes(ctx: Context, row_ptr: torch.Tensor, col: torch.Tensor, boundary: torch.Tensor,
+                         normals: torch.Tensor, vlap: torch.Tensor, grad: torch.Tensor, plap: torch.Tensor,
+                         plap_t: torch.Tensor, nlap: torch.Tensor, nlap_h: torch.Tensor, nu: float = 1.0):
+    """Global Stokes operator from stencils (see gmls_assemble_stokes in
+    libgmls.h).  Returns the CSR (row_ptr int64, col int32, val float64)."""
+    _check_dev(row_ptr, col, boundary, normals, vlap, grad, plap, plap_t, nlap, nlap_h)
+    n = row_ptr.numel() - 1
+    dim = normals.shape[1]
+    dev = row_ptr.device
+    st = StokesStencils(n, dim, 0, *[_ptr(t).value for t in (row_ptr, col, boundary, normals, vlap, grad, plap,
+                                                           plap_t, nlap, nlap_h)])
+    rows = dim * n + n + 1
+    a_rp = torch.empty(rows + 1, dtype=torch.int64, device=dev)
+    cap = (dim + 1) * col.numel() + 2 * n + 1
+    nnz = ctypes.c_int64()
+    L = load_library()
+    for _ in range(2):
+        a_col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        a_val = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+        rc = L.gmls_assemble_stokes(ctx._h, ctypes.byref(st), float(nu), _ptr(a_rp), _ptr(a_col), _ptr(a_val), cap,
+                                    ctypes.byref(nnz))
+        if rc != GMLS_ERR_CAPACITY:
+            break
+        cap = nnz.value
+    if rc != GMLS_OK:
+        ctx._raise(rc)
+    return a_rp, a_col[: nnz.value], a_val[: nnz.value]
+
+
+def gmls_spmv(ctx: Context, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: torch.Tensor,
+              y: torch.Tensor | None = None):
+    """y = A x for a CSR matrix (device tensors)."""
+    _check_dev(row_ptr, col, val, x)
+    rows = row_ptr.numel() - 1
+    if y is None:
+        y = torch.empty(max(rows, 1), dtype=torch.float64, device=x.device)
+    st = load_library().gmls_spmv(ctx._h, rows, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y))
+    if st != GMLS_OK:
+        ctx._raise(st)
+    return y[:rows]
 
 
 def gmls_apply(ctx: Context, row_ptr: torch.Tensor, col: torch.Tensor, weights: torch.Tensor, F: int, C: int,

@@ -44,6 +44,7 @@ def units():
         ("stencil_fp64", "stencil_fp64.hip", []),
         ("stencil_mixed", "stencil_mixed.hip", []),
         ("apply", "apply.hip", []),
+        ("assemble", "assemble.hip", []),
         ("api", "api.cpp", ["-x", "hip"]),
     ]
     return out

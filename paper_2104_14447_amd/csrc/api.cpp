@@ -419,6 +419,65 @@ gmls_status gmls_stencils_staggered(gmls_ctx ctx, const double *coords, int64_t 
                       eps, row_ptr, col, nullptr, prec, weights, target_weights, target_status, report);
 }
 
+gmls_status gmls_assemble_stokes(gmls_ctx ctx, const gmls_stokes_stencils *st, double nu, int64_t *a_row_ptr,
+                                 int32_t *a_col, double *a_val, int64_t capacity, int64_t *nnz_host) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (!st || !nnz_host) return gmls_set_error(ctx, GMLS_ERR_ARG, "null host pointer");
+  if (ctx->opt.capture_safe) return gmls_set_error(ctx, GMLS_ERR_ARG, "the assembly synchronises (capture-safe mode)");
+  if (st->dim != 2 && st->dim != 3) return gmls_set_error(ctx, GMLS_ERR_ARG, "dim must be 2 or 3");
+  if (st->n < 1 || (int64_t)st->dim * st->n + st->n + 1 >= (1ll << 31))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "n must be >= 1 with dim*n + n + 1 < 2^31");
+  if (!st->row_ptr || !st->col || !st->boundary || !st->normals || !st->vlap || !st->grad || !st->plap ||
+      !st->plap_t || !st->nlap || !st->nlap_h || !a_row_ptr || (capacity > 0 && (!a_col || !a_val)))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  if (!(nu > 0)) return gmls_set_error(ctx, GMLS_ERR_ARG, "nu must be > 0");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+  StokesArgs a;
+  a.n = st->n;
+  a.dim = st->dim;
+  a.nu = nu;
+  a.row_ptr = st->row_ptr;
+  a.col = st->col;
+  a.boundary = st->boundary;
+  a.normals = st->normals;
+  a.vlap = st->vlap;
+  a.grad = st->grad;
+  a.plap = st->plap;
+  a.plap_t = st->plap_t;
+  a.nlap = st->nlap;
+  a.nlap_h = st->nlap_h;
+  const int64_t rows = (int64_t)st->dim * st->n + st->n + 1;
+  int64_t *rlen = (int64_t *)ctx->ws(WS_STOKES_LEN, sizeof(int64_t) * (size_t)(rows + 1));
+  int64_t *tmp = (int64_t *)ctx->ws(WS_STOKES_TMP, sizeof(int64_t) * (size_t)scan_i32_tmp_words(rows + 1));
+  int *flags = (int *)ctx->ws(WS_STOKES_FLAG, sizeof(int));
+  if (!rlen || !tmp || !flags) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+  GMLS_HIP(launch_stokes_assembly(a, rlen, a_row_ptr, tmp, a_col, a_val, capacity, flags, ctx->cus, s));
+  int64_t nnz = 0;
+  GMLS_HIP(hipMemcpyAsync(&nnz, a_row_ptr + rows, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  GMLS_HIP(hipStreamSynchronize(s));
+  *nnz_host = nnz;
+  if (nnz > capacity)
+    return gmls_set_error(ctx, GMLS_ERR_CAPACITY,
+                          "capacity " + std::to_string(capacity) + " < required " + std::to_string(nnz));
+  return GMLS_OK;
+}
+
+gmls_status gmls_spmv(gmls_ctx ctx, int64_t n_rows, const int64_t *row_ptr, const int32_t *col, const double *val,
+                      const double *x, double *y) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (n_rows < 0 || n_rows >= (1ll << 31)) return gmls_set_error(ctx, GMLS_ERR_ARG, "n_rows must be in [0, 2^31)");
+  if (n_rows == 0) return GMLS_OK;
+  if (!row_ptr || !col || !val || !x || !y) return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  DeviceGuard g(ctx->device);
+  int *lr = (int *)ctx->ws(WS_SPMV_LONG, sizeof(int) * (size_t)(n_rows + 1));
+  if (!lr) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+  GMLS_HIP(launch_spmv(n_rows, row_ptr, col, val, x, y, lr + 1, lr, ctx->cus, ctx->stream));
+  return GMLS_OK;
+}
+
 gmls_status gmls_check(gmls_ctx ctx) {
   if (!ctx) return GMLS_ERR_ARG;
   ctx->err.clear();

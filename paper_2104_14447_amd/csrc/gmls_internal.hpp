@@ -41,6 +41,10 @@ enum Slot {
   WS_PIPE_MOM,
   WS_PIPE_Y,
   WS_PIPE_REC,
+  WS_STOKES_LEN,
+  WS_STOKES_TMP,
+  WS_STOKES_FLAG,
+  WS_SPMV_LONG,
   WS_NUM_SLOTS
 };
 
@@ -177,6 +181,8 @@ hipError_t or_error_bit(int *dst, const int *src, int mask, int bit, hipStream_t
 // exclusive scan of n ints (search.hip): out[0..n], tmp of scan_i32_tmp_words(n)
 int64_t scan_i32_tmp_words(int64_t n);
 hipError_t scan_i32_exclusive(const int *in, int *out, int64_t n, int *tmp, hipStream_t s);
+// the same for int64 (tmp of scan_i32_tmp_words(n) int64 entries)
+hipError_t scan_i64_exclusive(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s);
 
 // binning (stencil_bins.hip)
 // temporary device bytes launch_binning needs for n_tgt targets
@@ -186,6 +192,23 @@ hipError_t launch_binning(const int64_t *row_ptr, const double *targets, int n_t
 hipError_t launch_rank_deficient(const StencilArgs &a, int C, const int *list, BinMeta *meta, hipStream_t s);
 
 // apply (apply.hip)
+// global Stokes operator (assemble.hip)
+struct StokesArgs {
+  int64_t n = 0;
+  int dim = 0;
+  double nu = 1.0;
+  const int64_t *row_ptr = nullptr;
+  const int32_t *col = nullptr;
+  const uint8_t *boundary = nullptr;
+  const double *normals = nullptr;
+  const double *vlap = nullptr, *grad = nullptr, *plap = nullptr, *plap_t = nullptr, *nlap = nullptr,
+               *nlap_h = nullptr;
+};
+hipError_t launch_stokes_assembly(const StokesArgs &s, int64_t *rlen, int64_t *arp, int64_t *tmp, int32_t *acol,
+                                  double *aval, int64_t capacity, int *flags, int cus, hipStream_t st);
+hipError_t launch_spmv(int64_t rows, const int64_t *rp, const int32_t *col, const double *val, const double *x,
+                       double *y, int *long_rows, int *n_long, int cus, hipStream_t s);
+
 hipError_t launch_apply(int64_t n_tgt, const int64_t *row_ptr, const int32_t *col, const double *weights, int F,
                         int C, const double *field, double *out, hipStream_t s);
 

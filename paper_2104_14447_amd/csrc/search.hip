@@ -133,6 +133,10 @@ hipError_t scan_i32_exclusive(const int *in, int *out, int64_t n, int *tmp, hipS
   return exclusive_scan<int, int>(in, out, n, tmp, s);
 }
 
+hipError_t scan_i64_exclusive(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t s) {
+  return exclusive_scan<int64_t, int64_t>(in, out, n, tmp, s);
+}
+
 // ---------------------------------------------------------------------------
 // grid construction
 // ---------------------------------------------------------------------------

@@ -9,9 +9,6 @@ f = -nu Laplacian v2 + grad phi2 and its divergence (Laplacian phi2) to
 rounding, in every row: interior and boundary velocity and pressure rows and
 the zero-mean multiplier row.  A wrong sign or a missing h-weight in the
 boundary coupling fails the boundary pressure rows."""
-import json
-import os
-
 import numpy as np
 import pytest
 
@@ -20,34 +17,9 @@ import workloads as W
 from oracle import constrained as OC
 from oracle import staggered as OS
 from oracle import stokes as OK
-from tests import polytools as PT
+from tests.manufactured import exact_system
 
-HERE = os.path.dirname(os.path.abspath(__file__))
 F_GRAD, F_LAP = 2, 4
-
-
-def fields():
-    fx = json.load(open(os.path.join(HERE, "golden", "manufactured_fields.json")))
-    v = [PT.from_terms(c) for c in fx["v2"]["components"]]
-    lap_v = [PT.from_terms(c) for c in fx["v2"]["laplacian"]]
-    phi = PT.from_terms(fx["phi2"]["field"])
-    grad_phi = [PT.from_terms(g) for g in fx["phi2"]["gradient"]]
-    lap_phi = PT.from_terms(fx["phi2"]["laplacian"])
-    return v, lap_v, phi, grad_phi, lap_phi
-
-
-def exact_system(pts, bnd, nrm, nlap_h, nu):
-    """Nodal unknowns x and the right-hand side of the block system."""
-    v, lap_v, phi, grad_phi, lap_phi = fields()
-    n, d = pts.shape
-    V = np.stack([PT.evaluate(c, pts) for c in v], axis=1)
-    f = np.stack([-nu * PT.evaluate(lap_v[c], pts) + PT.evaluate(grad_phi[c], pts) for c in range(d)], axis=1)
-    div_f = PT.evaluate(lap_phi, pts)  # div f = Laplacian phi since div v = 0
-    P = PT.evaluate(phi, pts)
-    x = np.concatenate([V.reshape(-1), P - P.mean(), [0.0]])
-    b = np.where(bnd[:, None] == 1, V, f).reshape(-1)
-    g = np.where(bnd == 1, div_f - nlap_h * np.sum(nrm * f, axis=1), div_f)
-    return x, np.concatenate([b, g, [0.0]])
 
 
 def oracle_stencils(pts, nrm, rp, col, eps):
