@@ -439,22 +439,6 @@ __device__ int knn_select(const GridParams &g, const SPoint *pts, const int *cel
   }
 }
 
-template <int DIM>
-__global__ __launch_bounds__(64) void k_knn(const GridParams *gp, const SPoint *pts, const int *cell_start,
-                                            const double *targets, const int *order, int64_t n_tgt, int k,
-                                            double eps_mult, int32_t *col, double *eps) {
-  __shared__ double d2[kCap];
-  __shared__ int idx[kCap];
-  const int64_t w = blockIdx.x;
-  if (w >= n_tgt) return;
-  const GridParams g = *gp;
-  const int t = readfirstlane_i(order[w]);
-  double x[3] = {0, 0, 0};
-  for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
-  const int got = knn_select<DIM, kCap>(g, pts, cell_start, x, k, 2, d2, idx);
-  for (int q = lane_id(); q < k; q += 64) col[(int64_t)t * k + q] = q < got ? idx[q] : -1;
-  if (lane_id() == 0) eps[t] = eps_mult * sqrt(d2[got - 1]);
-}
 
 // block radius needed for a search radius r on cells of side c >= r
 __device__ __forceinline__ int radius_blocks(const GridParams &g, double r) {
@@ -638,6 +622,269 @@ __device__ void lds_sort_int(int *idx, int n) {
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// kNN, register path: one wavefront per target scans the block of cells
+// within R = 2 of its cell (cells have side ~ d_k / 1.9, so the block covers
+// the k-th neighbour with a margin), keeps the candidates closer than the
+// block's inner margin delta (every source closer than delta lies in the
+// block), and sorts them by (d^2, index) in registers.  When fewer than k
+// candidates lie within delta, or more than 64*EPL, the target goes to the
+// per-target expanding kernel above (k_knn_list).  The k smallest of the kept
+// set are the k smallest of all sources, since the set holds every source
+// within delta and at least k of them.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double xor_lane_d(double v, int lm) {
+  int2 b = __builtin_bit_cast(int2, v);
+  b.x = xor_lane(b.x, lm);
+  b.y = xor_lane(b.y, lm);
+  return __builtin_bit_cast(double, b);
+}
+
+// ascending bitonic sort of 64*EPL (d, id) pairs by (d, id), element
+// e = lane*EPL + r in slot r (the network of wave_sort_int)
+template <int EPL>
+__device__ __forceinline__ void wave_sort_pair(double (&d)[EPL], int (&id)[EPL], int lane) {
+  constexpr int E = 64 * EPL;
+#pragma unroll
+  for (int size = 2; size <= E; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride >= EPL) {
+        const int lmask = stride / EPL;
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          const int e = lane * EPL + r;
+          const double od = xor_lane_d(d[r], lmask);
+          const int oi = xor_lane(id[r], lmask);
+          const bool keep_min = ((e & stride) == 0) == ((e & size) == 0);
+          const bool mine_less = key_less(d[r], id[r], od, oi);
+          const bool take = keep_min ? !mine_less : mine_less;
+          d[r] = take ? od : d[r];
+          id[r] = take ? oi : id[r];
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          if (r & stride) continue;
+          const int e = lane * EPL + r;
+          const bool up = (e & size) == 0;
+          const bool sw = up ? key_less(d[r + stride], id[r + stride], d[r], id[r])
+                             : key_less(d[r], id[r], d[r + stride], id[r + stride]);
+          const double td = d[r];
+          const int ti = id[r];
+          d[r] = sw ? d[r + stride] : d[r];
+          id[r] = sw ? id[r + stride] : id[r];
+          d[r + stride] = sw ? td : d[r + stride];
+          id[r + stride] = sw ? ti : id[r + stride];
+        }
+      }
+    }
+  }
+}
+
+// One wavefront per target of `list` (or of order[0, n_tgt) when n_list is
+// null): candidates of the block of cells within R of the target's cell that
+// are closer than the block's inner margin delta go to LDS (at most 64*EPLL);
+// when there are more than 64*EPLS of them, a bisection on the squared
+// distance finds a threshold T holding at least k and at most 64*EPLS of
+// them; the candidates with d^2 <= T (a superset of the k nearest: the k-th
+// smallest d^2 is <= T) are sorted by (d^2, index) in registers.
+template <int DIM, int EPLL, int EPLS>
+__global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoint *pts, const int *cell_start,
+                                                const double *targets, const int *list, const int *n_list,
+                                                int64_t n_tgt, int R, int k, double eps_mult, int32_t *col,
+                                                double *eps, int *slow, int *n_slow) {
+  constexpr int CAP = 64 * EPLL, SCAP = 64 * EPLS;
+  __shared__ double cd[CAP];
+  __shared__ int ci[CAP];
+  __shared__ double sd[SCAP];
+  __shared__ int si[SCAP];
+  const GridParams g = *gp;
+  const int lane = lane_id();
+  const int64_t n = n_list ? (int64_t)readfirstlane_i(*n_list) : n_tgt;
+  for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+    const int t = readfirstlane_i(list[w]);
+    double x[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    double delta = DBL_MAX;
+    for (int d = 0; d < DIM; ++d) {
+      const int c = cell_coord(g, x[d], d);
+      lo[d] = c - R;
+      if (lo[d] > 0)
+        delta = fmin(delta, x[d] - (g.lo[d] + (double)lo[d] * g.c));
+      else
+        lo[d] = 0;
+      hi[d] = c + R;
+      if (hi[d] < g.nc[d] - 1)
+        delta = fmin(delta, (g.lo[d] + (double)(hi[d] + 1) * g.c) - x[d]);
+      else
+        hi[d] = g.nc[d] - 1;
+    }
+    const double delta2 = delta == DBL_MAX ? DBL_MAX : delta * delta;
+    int fill = 0;
+    for (int cz = lo[2]; cz <= hi[2]; ++cz)
+      for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+        const int row = g.nc[0] * (cy + g.nc[1] * cz);
+        const int beg = readfirstlane_i(cell_start[row + lo[0]]);
+        const int end = readfirstlane_i(cell_start[row + hi[0] + 1]);
+        for (int b = beg; b < end; b += 64) {
+          const int p = b + lane;
+          bool ok = false;
+          double dd = 0.0;
+          int id = 0;
+          if (p < end) {
+            const SPoint sp = pts[p];
+            dd = dist2_exact<DIM>(sp, x);
+            id = sp.idx;
+            ok = dd < delta2;
+          }
+          uint64_t m;
+          const int pre = ballot_prefix(ok, &m);
+          if (ok && fill + pre < CAP) {
+            cd[fill + pre] = dd;
+            ci[fill + pre] = id;
+          }
+          fill += __popcll(m);
+        }
+      }
+    if (fill < k || fill > CAP) {  // not provably covered, or too many: the next pass
+      if (lane == 0) slow[atomicAdd(n_slow, 1)] = t;
+      continue;
+    }
+    wave_lds_sync();
+    double kd[EPLS];
+    int kid[EPLS];
+    if (fill <= SCAP) {
+#pragma unroll
+      for (int r = 0; r < EPLS; ++r) {
+        const int e = lane * EPLS + r;
+        kd[r] = e < fill ? cd[e] : DBL_MAX;
+        kid[r] = e < fill ? ci[e] : INT_MAX;
+      }
+    } else {
+      double dl[EPLL];
+      double hiT = 0.0;
+#pragma unroll
+      for (int r = 0; r < EPLL; ++r) {
+        const int e = lane + 64 * r;
+        dl[r] = e < fill ? cd[e] : DBL_MAX;
+        if (e < fill) hiT = fmax(hiT, dl[r]);
+      }
+      hiT = uniform_d(wave_max(hiT));
+      double loT = 0.0;
+      int cnt = fill;
+      // invariant: count(d^2 <= hiT) >= k; stop once it is <= SCAP
+      for (int it = 0; it < 64 && cnt > SCAP; ++it) {
+        const double mid = 0.5 * (loT + hiT);
+        if (!(mid > loT && mid < hiT)) break;
+        int c = 0;
+#pragma unroll
+        for (int r = 0; r < EPLL; ++r) c += __popcll(__ballot(dl[r] <= mid));
+        if (c >= k) {
+          hiT = mid;
+          cnt = c;
+        } else {
+          loT = mid;
+        }
+      }
+      if (cnt > SCAP) {  // ties beyond the sort capacity: the next pass
+        if (lane == 0) slow[atomicAdd(n_slow, 1)] = t;
+        wave_lds_sync();
+        continue;
+      }
+      // compact the candidates with d^2 <= hiT (in LDS order)
+      int sf = 0;
+#pragma unroll
+      for (int r = 0; r < EPLL; ++r) {
+        const int e = lane + 64 * r;
+        const bool keep = e < fill && dl[r] <= hiT;
+        uint64_t m;
+        const int pre = ballot_prefix(keep, &m);
+        if (keep) {
+          sd[sf + pre] = dl[r];
+          si[sf + pre] = ci[e];
+        }
+        sf += __popcll(m);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < EPLS; ++r) {
+        const int e = lane * EPLS + r;
+        kd[r] = e < sf ? sd[e] : DBL_MAX;
+        kid[r] = e < sf ? si[e] : INT_MAX;
+      }
+    }
+    wave_sort_pair<EPLS>(kd, kid, lane);
+#pragma unroll
+    for (int r = 0; r < EPLS; ++r) {
+      const int e = lane * EPLS + r;
+      if (e < k) col[(int64_t)t * k + e] = kid[r];
+      if (e == k - 1) eps[t] = eps_mult * sqrt(kd[r]);
+    }
+    wave_lds_sync();  // the buffers are refilled for the next target
+  }
+}
+
+// The two register passes for k (block radius 2, then 3 for the targets the
+// first could not settle); false when k is beyond the register path.
+template <int DIM, int L1, int L2, int S>
+static void knn_reg_passes(const GridParams *gp, const SPoint *pts, const int *start, const double *targets,
+                           const int *order, int64_t n_tgt, int k, double mult, int32_t *col, double *eps,
+                           int *lists, int64_t stride, unsigned nb, hipStream_t s) {
+  k_knn_reg<DIM, L1, S><<<nb, 64, 0, s>>>(gp, pts, start, targets, order, nullptr, n_tgt, 2, k, mult, col, eps,
+                                          lists + 1, lists);
+  k_knn_reg<DIM, L2, S><<<nb, 64, 0, s>>>(gp, pts, start, targets, lists + 1, lists, n_tgt, 3, k, mult, col, eps,
+                                          lists + stride + 1, lists + stride);
+}
+
+template <int DIM>
+static bool launch_knn_reg(const GridParams *gp, const SPoint *pts, const int *start, const double *targets,
+                           const int *order, int64_t n_tgt, int k, double mult, int32_t *col, double *eps,
+                           int *lists, int64_t stride, unsigned nb, hipStream_t s) {
+  // first pass keeps up to ~3.9k candidates, the second up to ~9.3k; the
+  // sort holds ~1.3k
+  if (k <= 16)
+    knn_reg_passes<DIM, 1, 4, 1>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+  else if (k <= 32)
+    knn_reg_passes<DIM, 2, 8, 1>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+  else if (k <= 48)
+    knn_reg_passes<DIM, 4, 8, 1>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+  else if (k <= 64)
+    knn_reg_passes<DIM, 4, 16, 2>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+  else if (k <= 128)
+    knn_reg_passes<DIM, 8, 32, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+  else if (k <= 192)
+    knn_reg_passes<DIM, 16, 32, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb,
+                                   s);
+  else if (k <= 256)
+    knn_reg_passes<DIM, 16, 32, 8>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb,
+                                   s);
+  else
+    return false;
+  return true;
+}
+
+// per-target expanding kNN for the targets of a list
+template <int DIM>
+__global__ __launch_bounds__(64) void k_knn_list(const GridParams *gp, const SPoint *pts, const int *cell_start,
+                                                 const double *targets, const int *list, const int *n_list,
+                                                 int64_t n_tgt, int k, double eps_mult, int32_t *col, double *eps) {
+  __shared__ double d2[kCap];
+  __shared__ int idx[kCap];
+  const GridParams g = *gp;
+  const int64_t n = n_list ? (int64_t)readfirstlane_i(*n_list) : n_tgt;
+  for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
+    const int t = readfirstlane_i(list[w]);
+    double x[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) x[d] = uniform_d(targets[(int64_t)t * DIM + d]);
+    const int got = knn_select<DIM, kCap>(g, pts, cell_start, x, k, 2, d2, idx);
+    for (int q = lane_id(); q < k; q += 64) col[(int64_t)t * k + q] = q < got ? idx[q] : -1;
+    if (lane_id() == 0) eps[t] = eps_mult * sqrt(d2[got - 1]);
+    __syncthreads();
+  }
 }
 
 constexpr int kSmallCap = 256;      // row entries sorted in registers
@@ -1179,9 +1426,25 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
   }
   if (knn) {
     k_knn_rowptr<<<grid_for(n_tgt + 1, 256), 256, 0, s>>>(n_tgt, spec.k, row_ptr);
-    if (n_tgt > 0)
-      k_knn<DIM><<<(unsigned)n_tgt, 64, 0, s>>>(gp, sorted, start, targets, order, n_tgt, spec.k, spec.eps_mult,
-                                                col, eps);
+    if (n_tgt > 0) {
+      // two register passes, then the expanding kernel for what is left;
+      // lists[0] and lists[stride] count the targets left by each pass
+      const int64_t stride = n_tgt + 1;
+      GMLS_WS(lists, int, WS_DEFER, 2 * stride);
+      GMLS_HIP(fill_zero(lists, sizeof(int), s));
+      GMLS_HIP(fill_zero(lists + stride, sizeof(int), s));
+      const unsigned nb = (unsigned)xcd_grid(ctx->cus * 64);
+      const int *left = lists + stride;
+      if (!launch_knn_reg<DIM>(gp, sorted, start, targets, order, n_tgt, spec.k, spec.eps_mult, col, eps, lists,
+                               stride, nb, s))
+        left = nullptr;  // k beyond the register path: every target expands
+      if (left)
+        k_knn_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, left + 1, left, n_tgt, spec.k,
+                                            spec.eps_mult, col, eps);
+      else
+        k_knn_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, order, nullptr, n_tgt, spec.k,
+                                            spec.eps_mult, col, eps);
+    }
     GMLS_HIP(hipGetLastError());
     if (sync) GMLS_HIP(hipStreamSynchronize(s));
     return GMLS_OK;
