@@ -75,8 +75,7 @@ DESCRIBE = {
     "c4_3d_m3_uneven": "2M points, density 1+3x, radius search (k_min 30), scalar order 3, Laplacian",
     "c5_3d_m4": "500k jittered-grid points in 3D, kNN 170, p=6, scalar order 4 gradient + Laplacian and "
                 "div-free order 4 vector Laplacian + divergence",
-    "s4_3d_staggered_m2": "the C4 cloud and radius search, staggered gradient + Laplacian of vector order 2 "
-                          "(FP64)",
+    "s4_3d_staggered_m2": "the C4 cloud and radius search, staggered gradient + Laplacian of vector order 2",
     "n3_3d_neumann_m3": "60k points on the faces of the unit cube with outward normals, kNN 80 into 1M "
                         "jittered-grid points, Neumann-constrained scalar order 3 Laplacian (FP64)",
 }

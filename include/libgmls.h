@@ -225,7 +225,11 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
  *                    (-sum_j of the row's weights); NaN for rank-deficient
  *                    targets.  A target listed among its own neighbours adds
  *                    its target weight to that entry, or is given p(x_T) apart
- *   prec             GMLS_PREC_FP64 only (GMLS_PREC_MIXED: GMLS_ERR_UNSUPPORTED)
+ *   prec             GMLS_PREC_FP64, or GMLS_PREC_MIXED where the degree-(order+1)
+ *                    monomials number at most 20 (3D order <= 2, 2D order <= 3):
+ *                    the mixed pipeline of gmls_stencils (FP64 moments, FP32
+ *                    factor, FP64 refinement, FP64 QR fallback); otherwise
+ *                    GMLS_ERR_UNSUPPORTED
  * Other arguments, statuses and errors as for gmls_stencils (the Gram has
  * (order+2 choose dim) - 1 columns: the circulating vector fields, which
  * integrate to zero on every segment from x_T, are not fitted). */

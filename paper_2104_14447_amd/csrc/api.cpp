@@ -242,22 +242,26 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
   const bool stag = basis == kBasisStaggered;
   gmls_status st = gmls_stencil_shape(dim, order, stag ? GMLS_BASIS_SCALAR : basis, functional_mask, &F, &C, &Q);
   if (st != GMLS_OK) return gmls_set_error(ctx, st, "functional/basis combination not supported or bad shape");
+  // the mixed kernels of a staggered call are the scalar pipeline's with
+  // the constant column dropped; its FP64 QR kernels (and fallback) are basis 2
+  const int mbasis = stag ? (int)GMLS_BASIS_SCALAR : basis;
   if (stag) {
     Q -= 1;  // no constant monomial
-    if (prec != GMLS_PREC_FP64)
-      return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "staggered stencils are computed in FP64 (GMLS_PREC_FP64)");
     if (n_tgt > 0 && !hweights) return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer (target_weights)");
   }
   if (!qr_supported(dim, order, basis))
     return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "compiled kernels cover dim 2-3 and order 1-4");
   if (prec != GMLS_PREC_FP64 && prec != GMLS_PREC_MIXED) return gmls_set_error(ctx, GMLS_ERR_ARG, "bad precision");
-  if (prec == GMLS_PREC_MIXED && !mixed_supported(dim, order, basis))
+  if (prec == GMLS_PREC_MIXED && !mixed_supported(dim, order, mbasis))
     return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "mixed precision not compiled for this basis/order");
   Options opt = ctx->opt;
   if (prec == GMLS_PREC_MIXED) {
-    opt.scheme = mixed_scheme(dim, order, basis, ctx->opt.scheme);
+    opt.scheme = mixed_scheme(dim, order, mbasis, stag ? (int)MIXED_PIPE : ctx->opt.scheme);
     if (opt.scheme < 0)
-      return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "the selected mixed scheme is not compiled for this shape");
+      return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED,
+                            stag ? "mixed staggered stencils need the pipeline (at most 20 monomials of degree "
+                                   "order + 1)"
+                                 : "the selected mixed scheme is not compiled for this shape");
   }
   if (weight_p < 1 || weight_p > 12) return gmls_set_error(ctx, GMLS_ERR_ARG, "weight power must be 1..12");
   if (n_src < 1 || n_tgt < 0 || n_tgt > (1ll << 31) - 1)
@@ -299,6 +303,7 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
   a.ok_status = GMLS_TARGET_OK;
   a.normals = normals;
   a.hweights = hweights;
+  a.skip_const = stag ? 1 : 0;
 
   const bool sync = !opt.capture_safe;  // capture-safe: nothing below waits for the device
   if (!sync && report)
@@ -335,8 +340,8 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
     void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * cap);
     if (!mom || !yb || !rec) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
     if (n_work > 0)
-      GMLS_HIP(launch_mixed_pipe(dim, order, basis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, mom, yb, rec,
-                                 chunk, n, cus, s));
+      GMLS_HIP(launch_mixed_pipe(dim, order, mbasis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, mom, yb,
+                                 rec, chunk, n, cus, s));
   } else {
     for (int b = 1; b < kNumBins; ++b) {
       if (sync && hm.count[b] == 0) continue;

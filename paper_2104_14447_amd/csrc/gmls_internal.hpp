@@ -148,6 +148,9 @@ struct StencilArgs {
   // both null for plain stencils
   const double *normals = nullptr;
   double *hweights = nullptr;
+  // staggered stencils on the mixed pipeline: the constant monomial is not a
+  // column, and hweights receives the target weight -sum_j alpha_j
+  int skip_const = 0;
 };
 
 // Per-bin stencil launches; `bin` selects the rows-per-lane instantiation.

@@ -57,6 +57,8 @@ hipError_t GMLS_PIPE_FN(const StencilArgs &a, const int *list, const BinMeta *hm
                         int n_max, int cus, hipStream_t s) {
   constexpr int D = GMLS_DIM, O = GMLS_ORDER, B = GMLS_BASIS;
   if constexpr (B == 0 && has_pipe<D, O>()) {
+    if (a.skip_const)  // staggered stencils
+      return launch_pipe<D, O, 1>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
     return launch_pipe<D, O>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
   } else {
     return hipErrorInvalidValue;

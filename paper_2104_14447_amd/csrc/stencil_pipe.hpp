@@ -260,11 +260,14 @@ struct MomentPairs {
   }
 };
 
-template <int DIM, int ORDER>
+// SKIP = 1 (staggered stencils): the constant monomial is not a column, so
+// the Gram is the trailing (Q-1) x (Q-1) block of the moment Gram and the
+// functionals act on monomials 1..Q-1.
+template <int DIM, int ORDER, int SKIP = 0>
 __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, int win_lo, int win_hi,
                                                    const double *mom, double *yout, int *fb_list, BinMeta *meta,
                                                    Stats *stats, Options opt) {
-  constexpr int Q = num_mono(DIM, ORDER);
+  constexpr int Q = num_mono(DIM, ORDER) - SKIP;
   constexpr int NP = Q * (Q + 1) / 2;
   constexpr InvFact64<DIM, ORDER> IF{};
   constexpr SumIndex<DIM, ORDER> SI{};
@@ -295,14 +298,16 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, 
     // Gram D A64 D, packed lower
     float dsc[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) dsc[i] = (float)(1.0 / IF.v[i]) * rsqrtf((float)GMLS_MU(SI.idx[i][i], 0));
+    for (int i = 0; i < Q; ++i)
+      dsc[i] = (float)(1.0 / IF.v[i + SKIP]) * rsqrtf((float)GMLS_MU(SI.idx[i + SKIP][i + SKIP], 0));
     float L[NP];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const double di = (double)dsc[i] * IF.v[i];
+      const double di = (double)dsc[i] * IF.v[i + SKIP];
 #pragma unroll
       for (int k = 0; k <= i; ++k)
-        L[Packed<Q>::at(i, k)] = (float)(GMLS_MU(SI.idx[i][k], 0) * di * ((double)dsc[k] * IF.v[k]));
+        L[Packed<Q>::at(i, k)] =
+            (float)(GMLS_MU(SI.idx[i + SKIP][k + SKIP], 0) * di * ((double)dsc[k] * IF.v[k + SKIP]));
     }
     float anorm = 0.f;
 #pragma unroll
@@ -367,7 +372,7 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, 
       const int kind = rk.kind[f];
       // y0 = D A~^-1 D lambda
 #pragma unroll
-      for (int i = 0; i < Q; ++i) x[i] = (float)scalar_lambda<DIM, ORDER>(kind, i, ie) * dsc[i];
+      for (int i = 0; i < Q; ++i) x[i] = (float)scalar_lambda<DIM, ORDER>(kind, i + SKIP, ie) * dsc[i];
       packed_solve<Q>(L, x);
 #pragma unroll
       for (int i = 0; i < Q; ++i) ybuf[i][lane] = (double)(x[i] * dsc[i]);
@@ -381,18 +386,19 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, 
         asm volatile("" : "+v"(zoff));
         double yf[Q];
 #pragma unroll
-        for (int k = 0; k < Q; ++k) yf[k] = ybuf[k][lane] * IF.v[k];
+        for (int k = 0; k < Q; ++k) yf[k] = ybuf[k][lane] * IF.v[k + SKIP];
         double acc[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) acc[i] = 0.0;
 #pragma unroll
         for (int pp = 0; pp < MP.P; ++pp) {
+          if (MP.a[pp] < SKIP || MP.b[pp] < SKIP) continue;
           const double mv = GMLS_MU(MP.m[pp], zoff);
-          acc[MP.a[pp]] += mv * yf[MP.b[pp]];
+          acc[MP.a[pp] - SKIP] += mv * yf[MP.b[pp] - SKIP];
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-          x[i] = (float)((scalar_lambda<DIM, ORDER>(kind, i, ie) - IF.v[i] * acc[i]) * (double)dsc[i]);
+          x[i] = (float)((scalar_lambda<DIM, ORDER>(kind, i + SKIP, ie) - IF.v[i + SKIP] * acc[i]) * (double)dsc[i]);
         packed_solve<Q>(L, x);
         double dmax = 0.0, ymax = 0.0;
         bool finite = true;
@@ -447,12 +453,15 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, 
 // ---------------------------------------------------------------------------
 // F functional rows (compile time, so that the group's solutions stay in
 // registers: F*Q doubles per lane).
-template <int DIM, int ORDER, int G, int RPL, int F>
+// SKIP = 1 (staggered): columns are monomials 1..Q-1, and the group also
+// writes each row's target weight -sum_j alpha_j.
+template <int DIM, int ORDER, int G, int RPL, int F, int SKIP = 0>
 __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRec *rec, const BinMeta *meta, int bin,
                                                      int win_lo, int win_hi, const double *yin) {
   const SlotRange R = slot_range(meta, bin, win_lo, win_hi);
   const int first = R.first, last = R.last, c0 = R.c0;
-  constexpr int Q = num_mono(DIM, ORDER);
+  constexpr int QF = num_mono(DIM, ORDER);
+  constexpr int Q = QF - SKIP;
   constexpr int TPW = 64 / G;
   const int lane = lane_id();
   const int grp = lane / G, lg = lane % G;
@@ -476,19 +485,32 @@ __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRe
     double xs[RPL][DIM];
     gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
     double *wout = a.weights + (int64_t)F * base;
+    double rsum[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f) rsum[f] = 0.0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       double s[DIM];
       const double w = row_sw<DIM>(xs[r], xt, ie, a.p, true, s);
-      double p[Q];
+      double p[QF];
       scaled_basis<DIM, ORDER, double>(s, p);
       const int j = lg + G * r;
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc += p[q] * y[f][q];
+        for (int q = 0; q < Q; ++q) acc += p[q + SKIP] * y[f][q];
         if (good && j < N) wout[(int64_t)f * N + j] = w * acc;
+        if constexpr (SKIP != 0) rsum[f] += j < N ? w * acc : 0.0;
+      }
+    }
+    if constexpr (SKIP != 0) {
+      // the group's row sums, its G lanes in a fixed butterfly order
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+#pragma unroll
+        for (int off = 1; off < G; off <<= 1) rsum[f] += __shfl_xor(rsum[f], off, 64);
+        if (good && lg == 0) a.hweights[(int64_t)rc.t * F + f] = -rsum[f];
       }
     }
   }
@@ -502,7 +524,7 @@ constexpr bool has_pipe() {
   return num_mono(DIM, ORDER) <= 20;
 }
 
-template <int DIM, int ORDER, int G, int RPL>
+template <int DIM, int ORDER, int G, int RPL, int SKIP>
 static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *rec, const BinMeta *meta, int bin,
                             int win_lo, int win_hi, int n_max, double *buf, int cus, hipStream_t s) {
   constexpr int TPW = 64 / G;
@@ -514,13 +536,13 @@ static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *r
     return;
   }
   switch (a.F) {  // scalar basis: value + up to DIM gradient rows + Laplacian
-    case 1: k_pipe_weights<DIM, ORDER, G, RPL, 1><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
-    case 2: k_pipe_weights<DIM, ORDER, G, RPL, 2><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
-    case 3: k_pipe_weights<DIM, ORDER, G, RPL, 3><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
-    case 4: k_pipe_weights<DIM, ORDER, G, RPL, 4><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 1: k_pipe_weights<DIM, ORDER, G, RPL, 1, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 2: k_pipe_weights<DIM, ORDER, G, RPL, 2, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 3: k_pipe_weights<DIM, ORDER, G, RPL, 3, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 4: k_pipe_weights<DIM, ORDER, G, RPL, 4, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
     default:
-      if constexpr (DIM == 3)
-        k_pipe_weights<DIM, ORDER, G, RPL, 5><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
+      if constexpr (DIM == 3 && SKIP == 0)
+        k_pipe_weights<DIM, ORDER, G, RPL, 5, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
       break;
   }
 }
@@ -532,7 +554,7 @@ static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *r
 // read from the device table, grids sized for n_max slots.
 // lanes x rows per lane: bin 1 (<= 64 rows) 8 x 8, bin 2 (<= 128) 16 x 8,
 // bin 3 (<= 192) 32 x 6, bin 4 (<= 256) 32 x 8.
-template <int DIM, int ORDER>
+template <int DIM, int ORDER, int SKIP = 0>
 hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
                        Stats *stats, const Options &opt, double *mom, double *y, PipeRec *rec, int64_t chunk,
                        int n_max, int cus, hipStream_t s) {
@@ -558,7 +580,7 @@ hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm,
         int nb = (n_win + 63) / 64;
         if (nb > cus * 16) nb = cus * 16;
         nb = xcd_grid(nb);
-        k_pipe_solve<DIM, ORDER><<<nb, 64, 0, s>>>(a, rec, win_lo, win_hi, mom, y, fb, meta, stats, opt);
+        k_pipe_solve<DIM, ORDER, SKIP><<<nb, 64, 0, s>>>(a, rec, win_lo, win_hi, mom, y, fb, meta, stats, opt);
       }
       const bool wts = pass == 1;
       for (int b = 1; b < kNumBins; ++b) {
@@ -571,13 +593,13 @@ hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm,
         }
         double *buf = wts ? y : mom;
         if (b == 1)
-          pipe_bin_launch<DIM, ORDER, 8, 8>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 8, 8, SKIP>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 2)
-          pipe_bin_launch<DIM, ORDER, 16, 8>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 16, 8, SKIP>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 3)
-          pipe_bin_launch<DIM, ORDER, 32, 6>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 32, 6, SKIP>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else
-          pipe_bin_launch<DIM, ORDER, 32, 8>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 32, 8, SKIP>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
       }
     }
   }

@@ -99,8 +99,10 @@ def test_staggered_refusals_and_empty():
         with pytest.raises(G.GmlsError) as e:
             G.gmls_stencils_staggered(ctx(), dev(src), dev(tgt), 1, mask, 4, *args)
         assert e.value.status == 1
-    with pytest.raises(G.GmlsError) as e:
-        G.gmls_stencils_staggered(ctx(), dev(src), dev(tgt), 1, GRAD_LAP, 4, *args, prec=G.PREC_MIXED)
+    src3, tgt3, rp3, col3, eps3 = case(3, 110, 10, 7)
+    with pytest.raises(G.GmlsError) as e:  # degree 4 in 3-D: 34 columns, beyond the mixed pipeline
+        G.gmls_stencils_staggered(ctx(), dev(src3), dev(tgt3), 3, GRAD_LAP, 4, dev(eps3), dev(rp3), dev(col3),
+                                  prec=G.PREC_MIXED)
     assert e.value.status == G.GMLS_ERR_UNSUPPORTED
     with pytest.raises(G.GmlsError) as e:
         G.gmls_stencils_staggered(ctx(), dev(src), dev(tgt), 4, GRAD_LAP, 4, *args)
@@ -109,3 +111,25 @@ def test_staggered_refusals_and_empty():
     w, tw, st, _ = G.gmls_stencils_staggered(ctx(), dev(src), dev(empty), 1, GRAD_LAP, 4, dev(np.zeros(0)),
                                              dev(np.zeros(1, dtype=np.int64)), dev(np.zeros(0, dtype=np.int32)))
     assert w.numel() == 0 and tw.shape[0] == 0 and st.numel() == 0
+
+
+@pytest.mark.parametrize("dim,m,k,n_tgt", [(2, 1, 16, 300), (2, 2, 30, 300), (2, 3, 45, 257), (3, 1, 30, 300),
+                                           (3, 2, 60, 300)])
+def test_staggered_mixed_parity(dim, m, k, n_tgt):
+    """The mixed pipeline with the constant column dropped: gate 1e-8
+    (targets it hands to the FP64 fallback meet the FP64 gate anyway)."""
+    G = require_gpu()
+    src, tgt, rp, col, eps = case(dim, k, n_tgt, 70 + m)
+    flush(f"staggered mixed dim={dim} m={m} k={k}")
+    w, tw, st, rep = G.gmls_stencils_staggered(ctx(), dev(src), dev(tgt), m, GRAD_LAP, 4, dev(eps), dev(rp),
+                                               dev(col), prec=G.PREC_MIXED, report=True)
+    w, tw, st = host(w), host(tw), host(st)
+    ow, ob, F = S.stencils_staggered(src, tgt, m, GRAD_LAP, 4, eps, rp, col)
+    assert not (st == 1).any()
+    errs = row_errors(w, ow, rp, F, 1)
+    scale = np.array([[np.hypot(np.linalg.norm(ow[F * rp[t] + f * (rp[t + 1] - rp[t]):
+                                                   F * rp[t] + (f + 1) * (rp[t + 1] - rp[t])]), ob[t, f])
+                       for f in range(F)] for t in range(len(tgt))])
+    berr = np.abs(tw - ob) / np.where(scale > 0, scale, 1.0)
+    flush(f"  max rel err weights {errs.max():.3e} target weights {berr.max():.3e} fallback {rep['n_fallback']}")
+    assert errs.max() <= 1e-8 and berr.max() <= 1e-8

@@ -162,7 +162,7 @@ WORKLOADS = {
     "s4_3d_staggered_m2": dict(
         n=2_000_000, dim=3, seed=1004, gen="ramp",
         search=("radius", radius_for_mean_count(2_000_000), 30), p=4,
-        bases=[("staggered", 2, F_GRAD | F_LAPLACIAN)], modes=("fp64",),
+        bases=[("staggered", 2, F_GRAD | F_LAPLACIAN)], modes=("mixed", "fp64"),
     ),
     "n3_3d_neumann_m3": dict(
         n=1_000_000, dim=3, seed=1003, gen="grid", targets=("boundary", 60_000, 1103),
