@@ -23,6 +23,50 @@ __device__ __forceinline__ void scaled_basis(const T *s, T *p) {
   for (int a = 1; a < M.N; ++a) p[a] = p[M.parent[a]] * sd[M.pdim[a]][M.pexp[a]];
 }
 
+// Index of the monomial x^i y^j z^k in the graded order of Mono<DIM, DEG>.
+template <int DIM, int DEG>
+struct MonoIndex {
+  int idx[DEG + 1][DEG + 1][DEG + 1];
+  constexpr MonoIndex() : idx{} {
+    Mono<DIM, DEG> M{};
+    for (int i = 0; i <= DEG; ++i)
+      for (int j = 0; j <= DEG; ++j)
+        for (int k = 0; k <= DEG; ++k) idx[i][j][k] = -1;
+    for (int a = 0; a < M.N; ++a) idx[M.e[a][0]][M.e[a][1]][M.e[a][2]] = a;
+  }
+};
+
+// sum_a c[a] s^a (plain monomials, total degree <= DEG) by nested Horner
+// steps in z, then y, then x: one multiply-add per coefficient after the
+// first of each innermost sum.
+template <int DIM, int DEG>
+__device__ __forceinline__ double horner(const double *c, const double *s) {
+  constexpr MonoIndex<DIM, DEG> H{};
+  double ax = 0.0;
+#pragma unroll
+  for (int i = DEG; i >= 0; --i) {
+    double ay = 0.0;
+    if constexpr (DIM == 1) {
+      ay = c[H.idx[i][0][0]];
+    } else {
+#pragma unroll
+      for (int j = DEG - i; j >= 0; --j) {
+        double az;
+        if constexpr (DIM == 3) {
+          az = c[H.idx[i][j][DEG - i - j]];
+#pragma unroll
+          for (int k = DEG - i - j - 1; k >= 0; --k) az = az * s[2] + c[H.idx[i][j][k]];
+        } else {
+          az = c[H.idx[i][j][0]];
+        }
+        ay = j == DEG - i ? az : ay * s[1] + az;
+      }
+    }
+    ax = i == DEG ? ay : ax * s[0] + ay;
+  }
+  return ax;
+}
+
 // plain monomials s^g (no factorials), total degree <= DEG
 template <int DIM, int DEG, typename T>
 __device__ __forceinline__ void plain_monomials(const T *s, T *p) {

@@ -484,6 +484,16 @@ __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRe
     for (int d = 0; d < DIM; ++d) xt[d] = rc.x[d];
     double xs[RPL][DIM];
     gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
+    // p(s) . y = sum_a (y_a / a!) s^a: the factorials go into the
+    // coefficients once per target, the rows take a Horner evaluation
+    constexpr InvFact64<DIM, ORDER> IFW{};
+    double cf[F][QF];
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      if constexpr (SKIP != 0) cf[f][0] = 0.0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) cf[f][q + SKIP] = y[f][q] * IFW.v[q + SKIP];
+    }
     double *wout = a.weights + (int64_t)F * base;
     double rsum[F];
 #pragma unroll
@@ -492,14 +502,10 @@ __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRe
     for (int r = 0; r < RPL; ++r) {
       double s[DIM];
       const double w = row_sw<DIM>(xs[r], xt, ie, a.p, true, s);
-      double p[QF];
-      scaled_basis<DIM, ORDER, double>(s, p);
       const int j = lg + G * r;
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) acc += p[q + SKIP] * y[f][q];
+        const double acc = horner<DIM, ORDER>(cf[f], s);
         if (good && j < N) wout[(int64_t)f * N + j] = w * acc;
         if constexpr (SKIP != 0) rsum[f] += j < N ? w * acc : 0.0;
       }
