@@ -888,10 +888,13 @@ __global__ __launch_bounds__(64) void k_knn_list(const GridParams *gp, const SPo
 }
 
 constexpr int kSmallCap = 256;      // row entries sorted in registers
-constexpr int kCellCap = 1536;      // candidates of one cell block staged in LDS
+constexpr int kCellCap = 1280;      // candidates of one cell block staged in LDS
 constexpr int kCellThreads = 256;   // four wavefronts share a cell block
 constexpr int kMaxRuns = 9;         // runs of cells along x in a 3x3(x3) block
-constexpr int NT = 2;               // targets a wavefront tests together
+// targets a wavefront tests together: 4 in cell order; 2 when the rows are
+// sorted (their LDS buffers, 1 KiB per target, limit the occupancy)
+template <bool SORTED>
+constexpr int cell_targets() { return SORTED ? 2 : 4; }
 
 // ---------------------------------------------------------------------------
 // radius search, cell-cooperative: a workgroup takes one target cell, stages
@@ -918,6 +921,7 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
                                                                int32_t *col, double *eps, int *defer, int *n_defer,
                                                                uint8_t *dflag, int *flags) {
   constexpr bool ROWS = MODE != kCount;
+  constexpr int NT = cell_targets<SORTED>();
   if (MODE == kFill && (*flags & 2)) return;  // over capacity: nothing is written
   __shared__ double cxyz[3][kCellCap];
   __shared__ int cid[kCellCap];
