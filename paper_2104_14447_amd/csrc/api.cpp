@@ -336,7 +336,9 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
         std::max<int64_t>(1, sync && opt.pipe_chunk > 0 ? std::min<int64_t>(opt.pipe_chunk, n_work) : n_work);
     const size_t cap = (size_t)(sync && opt.pipe_chunk > 0 ? chunk : (int64_t)n);
     double *mom = (double *)ctx->ws(WS_PIPE_MOM, sizeof(double) * (size_t)pipe_num_moments(dim, order) * cap);
-    double *yb = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)F * Q * cap);
+    // per target: F*Q solution values (scalar), F*C*Q_s coefficients (divergence-free)
+    const int qy = basis == GMLS_BASIS_DIVFREE ? C * (int)binom_l(order + dim, dim) : Q;
+    double *yb = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)F * qy * cap);
     void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * cap);
     if (!mom || !yb || !rec) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
     if (n_work > 0)

@@ -60,6 +60,8 @@ hipError_t GMLS_PIPE_FN(const StencilArgs &a, const int *list, const BinMeta *hm
     if (a.skip_const)  // staggered stencils
       return launch_pipe<D, O, 1>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
     return launch_pipe<D, O>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
+  } else if constexpr (B == 1 && has_pipe_div<D, O>()) {
+    return launch_pipe<D, O, 0, 1>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
   } else {
     return hipErrorInvalidValue;
   }

@@ -89,7 +89,7 @@ bool mixed_supported(int dim, int order, int basis) {
 
 int mixed_scheme(int dim, int order, int basis, int requested) {
   if (!mixed_supported(dim, order, basis)) return -1;
-  const bool pipe = basis == 0 && num_mono(dim, order) <= 20;
+  const bool pipe = (basis == 0 && num_mono(dim, order) <= 20) || (basis == 1 && num_mono(dim, order) <= 10);
   const bool gram = num_mono(dim, 2 * order) <= 96;
   switch (requested) {
     case MIXED_AUTO: return pipe ? MIXED_PIPE : gram ? MIXED_GRAM : MIXED_ROWS;

@@ -523,6 +523,297 @@ __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRe
 }
 
 // ---------------------------------------------------------------------------
+// Divergence-free basis (Section 2.2) on the pipeline, for scalar bases of
+// at most 10 monomials.  The divergence-free span is the kernel of the
+// divergence map D on the full vector polynomial space (coefficients c_(a,k)
+// of p_a e_k): with the eps-scaled Taylor monomials, d/ds_k p_a = p_(a-e_k),
+// so (D c)_b = sum_k c_(b+e_k, k) for every monomial b of degree < m.  The
+// weighted least squares over that span is the vector fit with Gram
+// I (x) G_s (G_s the scalar moment Gram, Section 2.1) under D c = 0; for a
+// functional l its value is g^T (P^T W u) with
+//     g = G^-1 (l - D^T t),   S t = D G^-1 l,   S = D G^-1 D^T
+// (G = I (x) G_s), which takes only solves with the scalar Gram and a small
+// Schur complement.  Solve kernel: one thread per target, G_s equilibrated
+// and factored by Cholesky in FP64 (the moment Gram has at most 10 columns
+// here), Hager's estimate of its condition number against the threshold;
+// g for every (functional, component) goes to HBM, and the weights kernel
+// forms alpha_(j,c) = w_j p(s_j) . g_c.  The divergence functional of a
+// divergence-free fit is identically zero: its g is 0.
+// ---------------------------------------------------------------------------
+template <int DIM, int ORDER>
+struct DivUp {
+  static constexpr int QS = num_mono(DIM, ORDER);
+  static constexpr int QM = ORDER >= 1 ? num_mono(DIM, ORDER - 1) : 1;
+  int up[QM][3];  // index of the monomial b + e_k
+  constexpr DivUp() : up{} {
+    Mono<DIM, ORDER> M{};
+    for (int b = 0; b < QM; ++b)
+      for (int k = 0; k < 3; ++k) {
+        up[b][k] = -1;
+        if (k >= DIM) continue;
+        int e[3] = {M.e[b][0], M.e[b][1], M.e[b][2]};
+        e[k] += 1;
+        for (int a = 0; a < QS; ++a)
+          if (M.e[a][0] == e[0] && M.e[a][1] == e[1] && M.e[a][2] == e[2]) up[b][k] = a;
+      }
+  }
+};
+
+// x <- (L L^T)^-1 x for a packed lower-triangular FP64 L with 1/L_jj on the
+// diagonal
+template <int Q>
+__device__ __forceinline__ void packed_solve64(const double *L, double *x) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    double v = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) v -= L[Packed<Q>::at(i, k)] * x[k];
+    x[i] = v * L[Packed<Q>::at(i, i)];
+  }
+#pragma unroll
+  for (int i = Q - 1; i >= 0; --i) {
+    double v = x[i];
+#pragma unroll
+    for (int k = i + 1; k < Q; ++k) v -= L[Packed<Q>::at(k, i)] * x[k];
+    x[i] = v * L[Packed<Q>::at(i, i)];
+  }
+}
+
+// in-place packed Cholesky (diagonal keeps 1/L_jj); false on a pivot <= tol
+template <int Q>
+__device__ __forceinline__ bool packed_cholesky64(double *L, double tol) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    double dj = L[Packed<Q>::at(j, j)];
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= L[Packed<Q>::at(j, k)] * L[Packed<Q>::at(j, k)];
+    const bool pos = dj > tol;
+    ok = ok && pos;
+    const double inv = pos ? 1.0 / sqrt(dj) : 1.0;
+    L[Packed<Q>::at(j, j)] = inv;
+#pragma unroll
+    for (int i = j + 1; i < Q; ++i) {
+      double v = L[Packed<Q>::at(i, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) v -= L[Packed<Q>::at(i, k)] * L[Packed<Q>::at(j, k)];
+      L[Packed<Q>::at(i, j)] = v * inv;
+    }
+  }
+  return ok;
+}
+
+template <int DIM, int ORDER>
+__global__ __launch_bounds__(64) void k_pipe_solve_div(StencilArgs a, PipeRec *rec, int win_lo, int win_hi,
+                                                       const double *mom, double *gout, int *fb_list, BinMeta *meta,
+                                                       Stats *stats, Options opt) {
+  constexpr int QS = num_mono(DIM, ORDER);
+  constexpr int QM = DivUp<DIM, ORDER>::QM;
+  constexpr int NP = QS * (QS + 1) / 2;
+  constexpr InvFact64<DIM, ORDER> IF{};
+  constexpr SumIndex<DIM, ORDER> SI{};
+  constexpr DivUp<DIM, ORDER> DU{};
+  constexpr int NM = num_mono(DIM, 2 * ORDER);
+  __shared__ double mls[NM][64];  // thread-private columns: lane l uses [.][l]
+  const int lane = lane_id();
+  const RowKinds rk = row_kinds(DIM, 1, a.mask);
+  const int F = a.F;
+  const SlotRange R = slot_range(meta, 0, win_lo, win_hi);
+  const int first = R.first, last = R.last, c0 = R.c0;
+  for (int slot = first + xcd_block() * 64 + lane; slot - lane < last; slot += gridDim.x * 64) {
+    const bool valid = slot < last;
+    const int sl = valid ? slot : first;
+    const int t = rec[sl - c0].t;
+    const double ie = rec[sl - c0].ie;
+    const int64_t loc = sl - c0;
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < NM; ++m) mls[m][lane] = mom[loc * NM + m];
+    }
+    // G_s_ab = mu_(a+b)/(a! b!); its equilibration sc G_s sc (sc_a =
+    // 1/sqrt(G_s_aa)) is the moment matrix scaled by dsc_a = 1/sqrt(mu_2a)
+    double dsc[QS], sc[QS];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) {
+      dsc[i] = 1.0 / sqrt(mls[SI.idx[i][i]][lane]);
+      sc[i] = dsc[i] / IF.v[i];
+    }
+    double L[NP];
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+#pragma unroll
+      for (int k = 0; k <= i; ++k) L[Packed<QS>::at(i, k)] = mls[SI.idx[i][k]][lane] * dsc[i] * dsc[k];
+    double anorm = 0.0;
+#pragma unroll
+    for (int k = 0; k < QS; ++k) {
+      double sum = 0.0;
+#pragma unroll
+      for (int i = 0; i < QS; ++i) sum += fabs(i >= k ? L[Packed<QS>::at(i, k)] : L[Packed<QS>::at(k, i)]);
+      anorm = fmax(anorm, sum);
+    }
+    bool ok = valid && packed_cholesky64<QS>(L, 1e-12);
+    // Hager's 1-norm estimate of the inverse
+    double x[QS];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) x[i] = 1.0 / QS;
+    packed_solve64<QS>(L, x);
+    double est = 0.0;
+#pragma unroll
+    for (int i = 0; i < QS; ++i) est += fabs(x[i]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) x[i] = x[i] >= 0.0 ? 1.0 : -1.0;
+    packed_solve64<QS>(L, x);
+    int jmax = 0;
+    double zmax = -1.0;
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (fabs(x[i]) > zmax) {
+        zmax = fabs(x[i]);
+        jmax = i;
+      }
+#pragma unroll
+    for (int i = 0; i < QS; ++i) x[i] = i == jmax ? 1.0 : 0.0;
+    packed_solve64<QS>(L, x);
+    double est2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < QS; ++i) est2 += fabs(x[i]);
+    const double cond = anorm * fmax(est, est2);
+    if (!(cond <= opt.cond_threshold)) ok = false;
+    if (opt.force_fallback) ok = false;
+    // solves with the Gram: G_s^-1 v = sc . (L L^T)^-1 (sc . v)
+    // S = D G^-1 D^T, column b2: component k contributes G_s^-1 e_(b2+e_k)
+    // at rows b+e_k
+    double S[QM * (QM + 1) / 2];
+#pragma unroll
+    for (int q = 0; q < QM * (QM + 1) / 2; ++q) S[q] = 0.0;
+#pragma unroll
+    for (int b2 = 0; b2 < QM; ++b2)
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+        for (int i = 0; i < QS; ++i) x[i] = i == DU.up[b2][k] ? sc[i] : 0.0;
+        packed_solve64<QS>(L, x);
+#pragma unroll
+        for (int b = b2; b < QM; ++b) S[Packed<QM>::at(b, b2)] += x[DU.up[b][k]] * sc[DU.up[b][k]];
+      }
+    ok = ok && packed_cholesky64<QM>(S, 1e-300);
+    for (int f = 0; f < F; ++f) {
+      const int kind = rk.kind[f], comp = rk.comp[f];
+      double g[DIM][QS];
+      if (kind == FK_DIV) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+          for (int i = 0; i < QS; ++i) g[k][i] = 0.0;
+      } else {
+        // v = G_s^-1 l (component comp), r_b = v_(b + e_comp), t = S^-1 r
+        double lam[QS];
+#pragma unroll
+        for (int i = 0; i < QS; ++i) lam[i] = scalar_lambda<DIM, ORDER>(kind, i, ie);
+#pragma unroll
+        for (int i = 0; i < QS; ++i) x[i] = lam[i] * sc[i];
+        packed_solve64<QS>(L, x);
+        double tv[QM];
+#pragma unroll
+        for (int b = 0; b < QM; ++b) {
+          tv[b] = 0.0;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k)
+            if (k == comp) tv[b] = x[DU.up[b][k]] * sc[DU.up[b][k]];
+        }
+        packed_solve64<QM>(S, tv);
+        // g_k = G_s^-1 (delta_(k,comp) l - sum_b t_b e_(b+e_k))
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+#pragma unroll
+          for (int i = 0; i < QS; ++i) {
+            double v = k == comp ? lam[i] : 0.0;
+#pragma unroll
+            for (int b = 0; b < QM; ++b)
+              if (DU.up[b][k] == i) v -= tv[b];
+            g[k][i] = v * sc[i];
+          }
+          packed_solve64<QS>(L, g[k]);
+#pragma unroll
+          for (int i = 0; i < QS; ++i) g[k][i] *= sc[i];
+        }
+      }
+      if (valid) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+#pragma unroll
+          for (int i = 0; i < QS; ++i) gout[((loc * F + f) * DIM + k) * QS + i] = g[k][i];
+      }
+    }
+    const bool good = valid && ok;
+    const bool fell = valid && !ok;
+    if (valid) {
+      a.status[t] = good ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
+      rec[sl - c0].ok = good ? 1 : 0;
+    }
+    if (fell) fb_list[atomicAdd(&meta->fb_count, 1)] = t;
+    const unsigned long long mg = __ballot(good), mfb = __ballot(fell);
+    if (lane == 0 && mg) atomicAdd(&stats->sweep_hist[0], (unsigned long long)__popcll(mg));
+    if (lane == 0 && mfb) atomicAdd(&stats->n_fallback, (unsigned long long)__popcll(mfb));
+    double cd = valid && cond >= 0.0 ? cond : 0.0;  // NaN estimates are skipped
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cd = fmax(cd, __shfl_xor(cd, o));
+    if (lane == 0 && cd > 0.0) atomicMax(&stats->cond_max_bits, (unsigned long long)__double_as_longlong(cd));
+  }
+}
+
+// alpha_(j, f, c) = w_j p(s_j) . g_(f,c), three (f, c) outputs per pass over
+// the rows (their coefficients in registers, Horner evaluation)
+template <int DIM, int ORDER, int G, int RPL>
+__global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const PipeRec *rec, const BinMeta *meta,
+                                                         int bin, int win_lo, int win_hi, const double *gin) {
+  const SlotRange R = slot_range(meta, bin, win_lo, win_hi);
+  const int first = R.first, last = R.last, c0 = R.c0;
+  constexpr int QS = num_mono(DIM, ORDER);
+  constexpr int TPW = 64 / G;
+  constexpr InvFact64<DIM, ORDER> IFW{};
+  const int lane = lane_id();
+  const int grp = lane / G, lg = lane % G;
+  const int FC = a.F * DIM;
+  for (int i0 = first + xcd_block() * TPW; i0 < last; i0 += gridDim.x * TPW) {
+    const int i = i0 + grp;
+    const bool valid = i < last;
+    const int64_t loc = (valid ? i : first) - c0;
+    const PipeRec rc = rec[loc];
+    const bool good = valid && rc.ok;
+    const int64_t base = rc.base;
+    const int N = rc.n;
+    double xt[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xt[d] = rc.x[d];
+    double xs[RPL][DIM];
+    gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
+    double s[RPL][DIM], w[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) w[r] = row_sw<DIM>(xs[r], xt, rc.ie, a.p, true, s[r]);
+    double *wout = a.weights + (int64_t)FC * base;
+    for (int q0 = 0; q0 < FC; q0 += 3) {
+      double cf[3][QS];
+#pragma unroll
+      for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int q = 0; q < QS; ++q)
+          cf[u][q] = q0 + u < FC ? gin[(loc * FC + q0 + u) * QS + q] * IFW.v[q] : 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int j = lg + G * r;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int fc = q0 + u;
+          const int f = fc / DIM, c = fc - f * DIM;
+          if (good && j < N && fc < FC) wout[((int64_t)f * N + j) * DIM + c] = w[r] * horner<DIM, ORDER>(cf[u], s[r]);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host: the pipeline over the bins of one call, in chunks of list slots
 // ---------------------------------------------------------------------------
 template <int DIM, int ORDER>
@@ -530,7 +821,13 @@ constexpr bool has_pipe() {
   return num_mono(DIM, ORDER) <= 20;
 }
 
-template <int DIM, int ORDER, int G, int RPL, int SKIP>
+// the divergence-free pipeline factors the scalar Gram in FP64 registers
+template <int DIM, int ORDER>
+constexpr bool has_pipe_div() {
+  return ORDER >= 1 && num_mono(DIM, ORDER) <= 10;
+}
+
+template <int DIM, int ORDER, int G, int RPL, int SKIP, int BASIS = 0>
 static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *rec, const BinMeta *meta, int bin,
                             int win_lo, int win_hi, int n_max, double *buf, int cus, hipStream_t s) {
   constexpr int TPW = 64 / G;
@@ -539,6 +836,10 @@ static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *r
   nb = xcd_grid(nb);
   if (!weights) {
     k_pipe_moments<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
+    return;
+  }
+  if constexpr (BASIS == 1) {
+    k_pipe_weights_div<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
     return;
   }
   switch (a.F) {  // scalar basis: value + up to DIM gradient rows + Laplacian
@@ -560,7 +861,7 @@ static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *r
 // read from the device table, grids sized for n_max slots.
 // lanes x rows per lane: bin 1 (<= 64 rows) 8 x 8, bin 2 (<= 128) 16 x 8,
 // bin 3 (<= 192) 32 x 6, bin 4 (<= 256) 32 x 8.
-template <int DIM, int ORDER, int SKIP = 0>
+template <int DIM, int ORDER, int SKIP = 0, int BASIS = 0>
 hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
                        Stats *stats, const Options &opt, double *mom, double *y, PipeRec *rec, int64_t chunk,
                        int n_max, int cus, hipStream_t s) {
@@ -586,7 +887,10 @@ hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm,
         int nb = (n_win + 63) / 64;
         if (nb > cus * 16) nb = cus * 16;
         nb = xcd_grid(nb);
-        k_pipe_solve<DIM, ORDER, SKIP><<<nb, 64, 0, s>>>(a, rec, win_lo, win_hi, mom, y, fb, meta, stats, opt);
+        if constexpr (BASIS == 1)
+          k_pipe_solve_div<DIM, ORDER><<<nb, 64, 0, s>>>(a, rec, win_lo, win_hi, mom, y, fb, meta, stats, opt);
+        else
+          k_pipe_solve<DIM, ORDER, SKIP><<<nb, 64, 0, s>>>(a, rec, win_lo, win_hi, mom, y, fb, meta, stats, opt);
       }
       const bool wts = pass == 1;
       for (int b = 1; b < kNumBins; ++b) {
@@ -599,13 +903,13 @@ hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm,
         }
         double *buf = wts ? y : mom;
         if (b == 1)
-          pipe_bin_launch<DIM, ORDER, 8, 8, SKIP>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 8, 8, SKIP, BASIS>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 2)
-          pipe_bin_launch<DIM, ORDER, 16, 8, SKIP>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 16, 8, SKIP, BASIS>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 3)
-          pipe_bin_launch<DIM, ORDER, 32, 6, SKIP>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 32, 6, SKIP, BASIS>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
         else
-          pipe_bin_launch<DIM, ORDER, 32, 8, SKIP>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_launch<DIM, ORDER, 32, 8, SKIP, BASIS>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
       }
     }
   }

@@ -149,7 +149,9 @@ def scheme_compiled(name, scheme):
         return True
     if scheme == 2:
         return _nmono(dim, 2 * order) <= 96
-    return basis == "scalar" and _nmono(dim, order) <= 20
+    # the pipeline: scalar bases of <= 20 monomials, divergence-free bases
+    # whose scalar basis has <= 10
+    return _nmono(dim, order) <= (20 if basis == "scalar" else 10)
 
 
 def run_mixed(name, scheme, chunk=0):
@@ -217,6 +219,22 @@ def test_mixed_forced_fallback_is_fp64_exact(scheme):
     assert (gst == 2).all() and rep["n_fallback"] == len(st)
     errs = row_errors(gw, w, rp, F, C)
     flush(f"  forced fallback max rel err {errs.max():.3e}")
+    assert errs.max() <= FP64_TOL
+
+
+def test_divfree_pipe_forced_fallback_is_fp64_exact():
+    """The divergence-free pipeline hands every target to the FP64 QR kernel."""
+    G = require_gpu()
+    c = ctx()
+    c.set_option(G.OPT_FORCE_FALLBACK, 1)
+    try:
+        pts, rp, col, eps, w, st, F, C = case_data("3d_divfree_m2")
+        gw, gst, rep = run_mixed("3d_divfree_m2", 3)
+    finally:
+        c.set_option(G.OPT_FORCE_FALLBACK, 0)
+    assert (gst == 2).all() and rep["n_fallback"] == len(st)
+    errs = row_errors(gw, w, rp, F, C, zero_rows=(F - 1,))
+    flush(f"  divergence-free forced fallback max rel err {errs.max():.3e}")
     assert errs.max() <= FP64_TOL
 
 
