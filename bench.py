@@ -148,7 +148,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle timing leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", type=int, default=0,
-                    help="mixed scheme: 0 auto, 1 fused/rows residual, 2 fused/moment Gram, 3 pipeline")
+                    help="mixed scheme: 0 auto, 1 fused/rows residual, 2 fused/moment Gram, 3 pipeline, 4 wavefront per target")
     ap.add_argument("--chunk", type=int, default=0, help="pipeline chunk (targets; 0 = whole batch)")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy (counter scaling) and exit")
     ap.add_argument("--no-graph", action="store_true",
@@ -531,7 +531,7 @@ def main():
                    "n_points": n, "n_targets": n_t, "nnz": int(nnz), "precision": prec_name,
                    "search": wl["search"][0] + (f" k={k}" if knn else f" r={r0:.6f} k_min={k_min}"),
                    "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
-                                    "pipeline"][args.scheme],
+                                    "pipeline", "wavefront per target"][args.scheme],
                    "parity_gate": gate, "parity_max_rel_err": max_err, "parity_sample": int(n_sample),
                    "timed_unit": "HIP graph replay of search + stencils" if graph else "eager calls",
                    "ms_per_step_eager": round(ms_eager, 4),

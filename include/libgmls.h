@@ -64,8 +64,10 @@ enum { GMLS_F_VALUE = 1, GMLS_F_GRAD = 2, GMLS_F_LAPLACIAN = 4, GMLS_F_DIV = 8 }
 /* arithmetic of the local solve */
 enum {
   GMLS_PREC_FP64 = 0, /* Householder QR of sqrt(W) P in FP64                                 */
-  GMLS_PREC_MIXED = 1 /* FP32 Gram + FP32 Cholesky, FP64 residual refinement, FP64 weights,
-                         FP64 QR fallback for ill-conditioned targets                        */
+  GMLS_PREC_MIXED = 1 /* normal equations of the moment Gram (GMLS_OPT_MIXED_SCHEME): FP32
+                         Cholesky with FP64 residual refinement for small scalar bases, an
+                         FP64 factorisation or inverse of the equilibrated moment Gram
+                         otherwise; FP64 weights; FP64 QR fallback for ill-conditioned targets */
 };
 
 /* neighbour search rule */
@@ -117,7 +119,7 @@ enum {
                                   rho*|dy|/|y| with rho = 2 n cond 2^-24, is <= tol (1e-11)   */
   GMLS_OPT_FORCE_FALLBACK = 3, /* nonzero: every mixed target takes the FP64 fallback (0)      */
   GMLS_OPT_MIXED_SCHEME = 4,   /* organisation of the mixed path (0):
-                                  0 = automatic: 3 where compiled, else 2 where compiled, else 1;
+                                  0 = automatic: 3 where compiled, else 4;
                                   1 = one fused kernel per row-count bin, FP64 residual recomputed
                                       over the rows every sweep (corrected semi-normal equations);
                                   2 = one fused kernel per bin, FP64 weighted moments formed once
@@ -126,7 +128,13 @@ enum {
                                   3 = three-kernel pipeline: FP64 moments to device memory, one
                                       thread per target for factorisation and refinement, then the
                                       weights (scalar basis with at most 20 functions: 3D order
-                                      <= 3, 2D order <= 4).
+                                      <= 3, 2D order <= 4; divergence-free basis whose scalar
+                                      basis has at most 10: order <= 2);
+                                  4 = one wavefront per target, fused: FP64 moments summed over
+                                      the wavefront, the equilibrated moment Gram inverted in FP64
+                                      by symmetric sweeps, then the weights (every compiled shape:
+                                      scalar bases of up to 35 functions, divergence-free bases
+                                      whose scalar basis has up to 35).
                                   A scheme not compiled for the shape makes gmls_stencils return
                                   GMLS_ERR_UNSUPPORTED.                                         */
   GMLS_OPT_PIPE_CHUNK = 5,     /* scheme 3: targets per pipeline chunk, 0 = all at once (0); the

@@ -24,7 +24,7 @@ __all__ = [
     "PREC_FP64", "PREC_MIXED", "SEARCH_KNN", "SEARCH_RADIUS",
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
     "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "OPT_ROW_ORDER", "ROW_ORDER_CELL",
-    "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE",
+    "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE", "SCHEME_WAVE",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -37,7 +37,7 @@ SEARCH_KNN, SEARCH_RADIUS = 0, 1
 OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
 OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE, OPT_ROW_ORDER = 4, 5, 6, 7, 8
 ROW_ORDER_CELL, ROW_ORDER_INDEX = 0, 1
-SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE = 0, 1, 2, 3
+SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE, SCHEME_WAVE = 0, 1, 2, 3, 4
 GMLS_OK, GMLS_ERR_CAPACITY, GMLS_ERR_UNSUPPORTED, GMLS_WARN_TARGET_FLAGS = 0, 4, 5, 6
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY", 5: "ERR_UNSUPPORTED",
            6: "WARN_TARGET_FLAGS"}

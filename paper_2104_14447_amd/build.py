@@ -30,11 +30,11 @@ COMMON = [
 def units():
     """(object name, source, extra flags), heaviest first."""
     out = []
-    for unit in ("mixed_unit.hip", "qr_unit.hip"):
+    for unit in ("mixed_unit.hip", "wave_unit.hip", "qr_unit.hip"):
         stem = unit.split("_")[0]
         for order in (4, 3, 2, 1):
             # basis 0 scalar, 1 divergence-free; 2 staggered (FP64 QR only)
-            for basis in ((1, 0) if stem == "mixed" else (1, 0, 2)):
+            for basis in ((1, 0, 2) if stem == "qr" else (1, 0)):
                 for dim in (3, 2):
                     defs = [f"-DGMLS_DIM={dim}", f"-DGMLS_ORDER={order}", f"-DGMLS_BASIS={basis}"]
                     out.append((f"{stem}_d{dim}_o{order}_b{basis}", unit, defs))

@@ -153,8 +153,8 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
       ctx->opt.force_fallback = value != 0;
       return GMLS_OK;
     case GMLS_OPT_MIXED_SCHEME:
-      if (value != 0 && value != 1 && value != 2 && value != 3)
-        return gmls_set_error(ctx, GMLS_ERR_ARG, "mixed scheme must be 0 (auto), 1, 2 or 3");
+      if (value != 0 && value != 1 && value != 2 && value != 3 && value != 4)
+        return gmls_set_error(ctx, GMLS_ERR_ARG, "mixed scheme must be 0 (auto), 1, 2, 3 or 4");
       ctx->opt.scheme = (int)value;
       return GMLS_OK;
     case GMLS_OPT_PIPE_CHUNK:
@@ -344,6 +344,9 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
     if (n_work > 0)
       GMLS_HIP(launch_mixed_pipe(dim, order, mbasis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, mom, yb,
                                  rec, chunk, n, cus, s));
+  } else if (prec == GMLS_PREC_MIXED && opt.scheme == MIXED_WAVE) {
+    if (!sync || hm.count[0] < n)
+      GMLS_HIP(launch_mixed_wave(dim, order, mbasis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, n, cus, s));
   } else {
     for (int b = 1; b < kNumBins; ++b) {
       if (sync && hm.count[b] == 0) continue;

@@ -53,14 +53,14 @@ enum Slot {
 constexpr int kBasisStaggered = 2;
 
 // mixed-precision schemes (GMLS_OPT_MIXED_SCHEME)
-enum MixedScheme { MIXED_AUTO = 0, MIXED_ROWS = 1, MIXED_GRAM = 2, MIXED_PIPE = 3 };
+enum MixedScheme { MIXED_AUTO = 0, MIXED_ROWS = 1, MIXED_GRAM = 2, MIXED_PIPE = 3, MIXED_WAVE = 4 };
 
 struct Options {
   double cond_threshold = 1e6;
   int max_sweeps = 8;
   double refine_tol = 1e-11;
   int force_fallback = 0;
-  int scheme = MIXED_AUTO;  // resolved to ROWS, GRAM or PIPE before any launch
+  int scheme = MIXED_AUTO;  // resolved to ROWS, GRAM, PIPE or WAVE before any launch
   int64_t pipe_chunk = 0;   // list slots per pipeline chunk (0: the whole call)
   int64_t radius_scratch_mb = 8192;  // scratch rows of the one-pass radius search (MiB)
   int capture_safe = 0;              // nonzero: no call waits for the device (see libgmls.h)
@@ -168,6 +168,10 @@ constexpr size_t kPipeRecBytes = 64;
 hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt,
                              double *mom, double *y, void *rec, int64_t chunk, int n_max, int cus, hipStream_t s);
+// one wavefront per target (bins launched as in launch_mixed_pipe)
+hipError_t launch_mixed_wave(int dim, int order, int basis, const StencilArgs &a, const int *list,
+                             const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt, int n_max,
+                             int cus, hipStream_t s);
 bool qr_supported(int dim, int order, int basis);
 bool mixed_supported(int dim, int order, int basis);
 // the scheme a request resolves to (MIXED_AUTO picks the fastest compiled

@@ -77,6 +77,45 @@ static const PipeFn kPipe[2][4][2] = {
     {{launch_pipe_d2_o1_b0, launch_pipe_d2_o1_b1}, {launch_pipe_d2_o2_b0, launch_pipe_d2_o2_b1}, {launch_pipe_d2_o3_b0, launch_pipe_d2_o3_b1}, {launch_pipe_d2_o4_b0, launch_pipe_d2_o4_b1}},
     {{launch_pipe_d3_o1_b0, launch_pipe_d3_o1_b1}, {launch_pipe_d3_o2_b0, launch_pipe_d3_o2_b1}, {launch_pipe_d3_o3_b0, launch_pipe_d3_o3_b1}, {launch_pipe_d3_o4_b0, launch_pipe_d3_o4_b1}}};
 
+hipError_t launch_wave_d2_o1_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d2_o1_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d2_o2_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d2_o2_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d2_o3_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d2_o3_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d2_o4_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d2_o4_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d3_o1_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d3_o1_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d3_o2_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d3_o2_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d3_o3_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d3_o3_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d3_o4_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+hipError_t launch_wave_d3_o4_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                                const Options &, int, int, hipStream_t);
+
+using WaveFn = hipError_t (*)(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
+                              const Options &, int, int, hipStream_t);
+static const WaveFn kWave[2][4][2] = {
+    {{launch_wave_d2_o1_b0, launch_wave_d2_o1_b1}, {launch_wave_d2_o2_b0, launch_wave_d2_o2_b1}, {launch_wave_d2_o3_b0, launch_wave_d2_o3_b1}, {launch_wave_d2_o4_b0, launch_wave_d2_o4_b1}},
+    {{launch_wave_d3_o1_b0, launch_wave_d3_o1_b1}, {launch_wave_d3_o2_b0, launch_wave_d3_o2_b1}, {launch_wave_d3_o3_b0, launch_wave_d3_o3_b1}, {launch_wave_d3_o4_b0, launch_wave_d3_o4_b1}}};
+
 using MixedFn = hipError_t (*)(int, const StencilArgs &, const int *, BinMeta *, int *, Stats *, const Options &, int,
                                int, hipStream_t);
 static const MixedFn kMixed[2][4][2] = {
@@ -91,11 +130,13 @@ int mixed_scheme(int dim, int order, int basis, int requested) {
   if (!mixed_supported(dim, order, basis)) return -1;
   const bool pipe = (basis == 0 && num_mono(dim, order) <= 20) || (basis == 1 && num_mono(dim, order) <= 10);
   const bool gram = num_mono(dim, 2 * order) <= 96;
+  const bool wave = num_mono(dim, order) <= 35;
   switch (requested) {
-    case MIXED_AUTO: return pipe ? MIXED_PIPE : gram ? MIXED_GRAM : MIXED_ROWS;
+    case MIXED_AUTO: return pipe ? MIXED_PIPE : wave ? MIXED_WAVE : gram ? MIXED_GRAM : MIXED_ROWS;
     case MIXED_ROWS: return MIXED_ROWS;
     case MIXED_GRAM: return gram ? MIXED_GRAM : -1;
     case MIXED_PIPE: return pipe ? MIXED_PIPE : -1;
+    case MIXED_WAVE: return wave ? MIXED_WAVE : -1;
     default: return -1;
   }
 }
@@ -107,6 +148,13 @@ hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a
                              double *mom, double *y, void *rec, int64_t chunk, int n_max, int cus, hipStream_t s) {
   if (mixed_scheme(dim, order, basis, MIXED_PIPE) != MIXED_PIPE) return hipErrorInvalidValue;
   return kPipe[dim - 2][order - 1][basis](a, list, hm, meta, fb, stats, opt, mom, y, rec, chunk, n_max, cus, s);
+}
+
+hipError_t launch_mixed_wave(int dim, int order, int basis, const StencilArgs &a, const int *list,
+                             const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt, int n_max,
+                             int cus, hipStream_t s) {
+  if (mixed_scheme(dim, order, basis, MIXED_WAVE) != MIXED_WAVE) return hipErrorInvalidValue;
+  return kWave[dim - 2][order - 1][basis](a, list, hm, meta, fb, stats, opt, n_max, cus, s);
 }
 
 hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,

@@ -1,0 +1,430 @@
+// stencil_wave.hpp -- mixed-path stencils with one wavefront per target, for
+// bases too large for the one-thread solve of the pipeline (scalar bases of
+// up to 35 monomials, divergence-free bases whose scalar part has up to 35).
+//
+// The stencil of a functional lambda is alpha = W P y with (P^T W P) y =
+// lambda (Section 2.1, normal equations; Section 2.5, functionals).  For one
+// target the wavefront
+//  1. gathers its rows j = lane + 64 r once (eps-scaled offsets s_j, kernel
+//     weights w_j, kept in registers);
+//  2. forms the FP64 moments mu_g = sum_j w_j s_j^g, |g| <= 2m: per-lane
+//     partial sums in lexicographic order of g, summed over the wavefront
+//     through LDS in rounds of 16 moments (fixed order: reproducible);
+//  3. builds the Jacobi-equilibrated moment Gram E_ik = mu_(i+k) / sqrt(
+//     mu_2i mu_2k) (the factorials of the scaled basis cancel), lane i
+//     holding row i, and inverts it in FP64 by symmetric sweeps (Gauss-Jordan
+//     on a symmetric positive definite matrix, no pivoting: every pivot is a
+//     Schur-complement diagonal in (0, 1]); the 1-norm condition number is
+//     exact here, ||E||_1 ||E^-1||_1, and is held against the threshold;
+//  4. scalar basis: y = G^-1 lambda with G^-1 = Dg E^-1 Dg (Dg_i = i! /
+//     sqrt(mu_2i)); divergence-free basis (Section 2.2): the fit over the
+//     kernel of the divergence map, as in the pipeline (g = G^-1 (l - D^T t),
+//     S t = D G^-1 l, S = D G^-1 D^T), with S equilibrated and swept too;
+//  5. alpha_j = w_j p(s_j) . y by Horner steps, the coefficients broadcast
+//     through LDS, stores coalesced over the rows.
+// Targets whose sweep meets a non-positive pivot or whose condition number
+// exceeds the threshold are queued for the FP64 QR fallback.
+#pragma once
+
+#include <float.h>
+#include <limits.h>
+#include <math.h>
+
+#include "basis.hpp"
+#include "gmls_internal.hpp"
+#include "stencil_mixed64.hpp"
+#include "stencil_pipe.hpp"
+
+namespace gmls {
+
+// index of the moment s^(x,y,z), |g| <= D2, in lexicographic order (x
+// slowest): the order in which the wavefront accumulates them
+template <int DIM, int D2>
+struct LexMoments {
+  static constexpr int N = num_mono(DIM, D2);
+  int id[D2 + 1][D2 + 1][D2 + 1];
+  int e[N][3];
+  constexpr LexMoments() : id{}, e{} {
+    int n = 0;
+    for (int x = 0; x <= D2; ++x)
+      for (int y = 0; y <= (DIM >= 2 ? D2 - x : 0); ++y)
+        for (int z = 0; z <= (DIM == 3 ? D2 - x - y : 0); ++z) {
+          id[x][y][z] = n;
+          e[n][0] = x;
+          e[n][1] = y;
+          e[n][2] = z;
+          ++n;
+        }
+  }
+};
+
+// lexicographic moment index of basis monomials i + k (row-major Q x Q)
+template <int DIM, int ORDER>
+struct WavePairs {
+  static constexpr int Q = num_mono(DIM, ORDER);
+  unsigned char p[Q * Q];
+  constexpr WavePairs() : p{} {
+    Mono<DIM, ORDER> M{};
+    LexMoments<DIM, 2 * ORDER> L{};
+    for (int i = 0; i < Q; ++i)
+      for (int k = 0; k < Q; ++k)
+        p[i * Q + k] =
+            (unsigned char)L.id[M.e[i][0] + M.e[k][0]][M.e[i][1] + M.e[k][1]][M.e[i][2] + M.e[k][2]];
+  }
+};
+static_assert(num_mono(3, 8) < 256, "moment indices fit a byte");
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Symmetric sweep of every pivot of the Q x Q symmetric matrix whose row
+// `lane` is a[] (lanes >= Q hold zeros): on return a[] is row `lane` of
+// -A^-1.  Pivot k: a_kk <- -1/a_kk, a_ik <- a_ik / a_kk, a_kj <- a_kj / a_kk,
+// a_ij <- a_ij - a_ik a_kj / a_kk; the matrix stays symmetric, so column k
+// (one LDS store per lane) is also row k.  Returns false when a pivot is
+// not above tol (wave-uniform).
+template <int Q>
+__device__ __forceinline__ bool sweep_inverse(double (&a)[Q], double *col, double tol) {
+  const int lane = lane_id();
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    if (lane < Q) col[lane] = a[k];
+    __syncthreads();
+    double rk[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) rk[j] = col[j];
+    __syncthreads();
+    const double piv = rk[k];
+    ok = ok && piv > tol;
+    const double d = 1.0 / piv;
+    const double f = a[k] * d;
+    // row k itself becomes a_kj / a_kk: a_kj + (d - a_kk d) a_kj, exact up
+    // to rounding because the equilibrated pivots are at most 1 (d >= 1)
+    const double ef = (lane == k ? d : 0.0) - f;
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      if (j != k) a[j] = fma(ef, rk[j], a[j]);
+    a[k] = lane == k ? -d : f;
+    // finish this pivot's updates here: left alone, the compiler defers each
+    // a[j] update to the pivot that first reads it, which keeps every
+    // earlier pivot row live (quadratic register use)
+#pragma unroll
+    for (int j = 0; j < Q; ++j) asm volatile("" : "+v"(a[j]));
+  }
+  return ok;
+}
+
+// Moments mu_g (lexicographic order) of the rows held by the wavefront into
+// mu[]; red is the LDS reduction buffer (64 x 17 doubles).  One step per
+// moment, unrolled by template recursion so that every exponent, register
+// index and round boundary is a compile-time constant.
+constexpr int kWaveRound = 16;  // moments per LDS reduction round
+
+// sum one round over the wavefront: every lane stores its partials, then
+// lanes q + 16 p add rows 16p..16p+15 of column q and two butterfly steps
+// combine the four quarters (fixed order)
+template <int NM>
+__device__ __forceinline__ void wave_round(const double (&acc)[kWaveRound], int g0, double *red, double *mu) {
+  constexpr int RS = kWaveRound;
+  const int lane = lane_id();
+#pragma unroll
+  for (int q = 0; q < RS; ++q) red[lane * (RS + 1) + q] = acc[q];
+  __syncthreads();
+  const int q = lane & (RS - 1), part = lane >> 4;
+  double t = 0.0;
+#pragma unroll
+  for (int l = 0; l < 16; ++l) t += red[(part * 16 + l) * (RS + 1) + q];
+  t += __shfl_xor(t, 16);
+  t += __shfl_xor(t, 32);
+  if (lane < RS && g0 + lane < NM) mu[g0 + lane] = t;
+  __syncthreads();
+}
+
+template <int DIM, int ORDER, int RPL, int G>
+struct WaveMoment {
+  static constexpr int D2 = 2 * ORDER;
+  static constexpr int NM = num_mono(DIM, D2);
+  // wab = w s_x^a [s_y^b] of the current prefix, pl = powers of the last coordinate
+  static __device__ __forceinline__ void run(const double (&s)[RPL][DIM], const double (&pl)[RPL][D2 + 1],
+                                             double (&wa)[RPL], double (&wab)[RPL], double (&acc)[kWaveRound],
+                                             double *red, double *mu) {
+    constexpr LexMoments<DIM, D2> LM{};
+    constexpr int ey = LM.e[G][1];
+    constexpr int el = DIM == 3 ? LM.e[G][2] : LM.e[G][1];
+    // a new (x[, y]) prefix starts where the last exponent is 0
+    if constexpr (G > 0 && el == 0) {
+      if constexpr (DIM == 3 && ey == 0) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          wa[r] *= s[r][0];
+          wab[r] = wa[r];
+        }
+      } else if constexpr (DIM == 3) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) wab[r] *= s[r][1];
+      } else {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) wab[r] *= s[r][0];
+      }
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) v = fma(wab[r], pl[r][el], v);
+    acc[G % kWaveRound] = v;
+    if constexpr (G % kWaveRound == kWaveRound - 1 || G == NM - 1) wave_round<NM>(acc, G - G % kWaveRound, red, mu);
+    if constexpr (G + 1 < NM) WaveMoment<DIM, ORDER, RPL, G + 1>::run(s, pl, wa, wab, acc, red, mu);
+  }
+};
+
+template <int DIM, int ORDER, int RPL>
+__device__ __forceinline__ void wave_moments(const double (&s)[RPL][DIM], const double (&w)[RPL], double *red,
+                                             double *mu) {
+  constexpr int D2 = 2 * ORDER;
+  double pl[RPL][D2 + 1], wa[RPL], wab[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    pl[r][0] = 1.0;
+#pragma unroll
+    for (int c = 1; c <= D2; ++c) pl[r][c] = pl[r][c - 1] * s[r][DIM - 1];
+    wa[r] = w[r];
+    wab[r] = w[r];
+  }
+  double acc[kWaveRound];
+  WaveMoment<DIM, ORDER, RPL, 0>::run(s, pl, wa, wab, acc, red, mu);
+}
+
+// Per-block counters, added to the call's statistics once per block.
+struct WaveCounts {
+  unsigned long long good = 0, fell = 0;
+  double cond = 0.0;
+};
+
+template <int DIM, int ORDER, int BASIS, int RPL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_wave(StencilArgs a, const int *list, BinMeta *meta, int bin, int *fb_list,
+                                             Stats *stats, Options opt) {
+  constexpr int QS = num_mono(DIM, ORDER);
+  constexpr int NM = num_mono(DIM, 2 * ORDER);
+  constexpr int QM = ORDER >= 1 ? num_mono(DIM, ORDER - 1) : 1;
+  constexpr int RED = 64 * 17;
+  constexpr int BIG = (BASIS == 1 && QS * QS > RED) ? QS * QS : RED;
+  static_assert(QS <= 64, "one basis function per lane");
+  __shared__ double big[BIG];    // moment reduction, then (divergence-free) -E^-1
+  __shared__ double mu[NM];      // moments, lexicographic order
+  __shared__ double vb[4][64];   // broadcast vectors
+  __shared__ double ubuf[BASIS == 1 ? DIM : 1][QS];
+  __shared__ unsigned char pidx[QS * QS];
+  constexpr WavePairs<DIM, ORDER> WP{};
+  constexpr InvFact64<DIM, ORDER> IF{};
+  const int lane = lane_id();
+  for (int q = lane; q < QS * QS; q += 64) pidx[q] = WP.p[q];
+  const double ifac = IF.v[lane < QS ? lane : 0];  // 1 / i!
+  int ubl[3] = {0, 0, 0};                             // divergence-free: index of b + e_k, b = lane
+  if constexpr (BASIS == 1) {
+    constexpr DivUp<DIM, ORDER> DU{};
+    if (lane < QM)
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) ubl[k] = DU.up[lane][k];
+  }
+  __syncthreads();
+  const RowKinds rk = row_kinds(DIM, BASIS, a.mask);
+  const int F = a.F;
+  WaveCounts cnt;
+  const SlotRange R = slot_range(meta, bin, -1, INT_MAX);
+  for (int i = R.first + xcd_block(); i < R.last; i += gridDim.x) {
+    const int t = list[i];
+    const int64_t base = a.row_ptr[t];
+    const int N = (int)(a.row_ptr[t + 1] - base);
+    const double ie = 1.0 / a.eps[t];
+    double xt[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xt[d] = a.targets[(int64_t)t * DIM + d];
+    double s[RPL][DIM], w[RPL];
+    {
+      double xs[RPL][DIM];
+      gather_rows<DIM, RPL, 64>(a, base, N, lane, xs);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) w[r] = row_sw<DIM>(xs[r], xt, ie, a.p, lane + 64 * r < N, s[r]);
+    }
+    wave_moments<DIM, ORDER, RPL>(s, w, big, mu);
+
+    // equilibrated Gram, row `lane` (lanes >= QS hold zeros; li keeps their
+    // table reads in bounds)
+    const int li = lane < QS ? lane : 0;
+    const double dsc = lane < QS ? 1.0 / sqrt(mu[pidx[li * QS + li]]) : 0.0;
+    vb[0][lane] = dsc;
+    __syncthreads();
+    double e[QS];
+#pragma unroll
+    for (int k = 0; k < QS; ++k) e[k] = lane < QS ? mu[pidx[li * QS + k]] * dsc * vb[0][k] : 0.0;
+    double rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < QS; ++k) rs += fabs(e[k]);
+    const double anorm = wave_max(rs);
+    bool ok = sweep_inverse<QS>(e, vb[1], 1e-14);  // e = row `lane` of -E^-1
+    rs = 0.0;
+#pragma unroll
+    for (int k = 0; k < QS; ++k) rs += fabs(e[k]);
+    const double cond = anorm * wave_max(rs);
+    if (!(cond <= opt.cond_threshold)) ok = false;
+    if (opt.force_fallback) ok = false;
+    const double dg = dsc / ifac;  // Dg_lane: G^-1 = Dg E^-1 Dg
+
+    if constexpr (BASIS == 0) {
+      if (ok) {
+        double *wout = a.weights + (int64_t)F * base;
+        for (int f = 0; f < F; ++f) {
+          // cf_i = y_i / i! = dsc_i (E^-1 Dg lambda)_i
+          vb[2][lane] = lane < QS ? scalar_lambda<DIM, ORDER>(rk.kind[f], lane, ie) * dg : 0.0;
+          __syncthreads();
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < QS; ++k) acc = fma(e[k], vb[2][k], acc);
+          vb[3][lane] = -dsc * acc;
+          __syncthreads();
+          double cf[QS];
+#pragma unroll
+          for (int k = 0; k < QS; ++k) cf[k] = vb[3][k];
+          __syncthreads();
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) {
+            const int j = lane + 64 * r;
+            const double val = w[r] * horner<DIM, ORDER>(cf, s[r]);
+            if (j < N) wout[(int64_t)f * N + j] = val;
+          }
+        }
+      }
+    } else {
+      // S = D G^-1 D^T: S_(b,b2) = sum_k G^-1_(up[b][k], up[b2][k]); lane b holds row b
+      constexpr DivUp<DIM, ORDER> DU{};
+      if (lane < QS)
+#pragma unroll
+        for (int k = 0; k < QS; ++k) big[lane * QS + k] = e[k];
+      vb[2][lane] = dg;
+      __syncthreads();
+      double sr[QM];
+      double sdiag = 1.0;
+#pragma unroll
+      for (int b2 = 0; b2 < QM; ++b2) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+          v -= vb[2][ubl[k]] * big[ubl[k] * QS + DU.up[b2][k]] * vb[2][DU.up[b2][k]];
+        sr[b2] = lane < QM ? v : 0.0;
+        if (lane == b2) sdiag = v;
+      }
+      // equilibrate S (ds_b = 1/sqrt(S_bb)) and sweep it: se = -(ds S ds)^-1
+      const double ds = lane < QM ? 1.0 / sqrt(sdiag) : 0.0;
+      vb[3][lane] = ds;
+      __syncthreads();
+#pragma unroll
+      for (int b2 = 0; b2 < QM; ++b2) sr[b2] *= ds * vb[3][b2];
+      __syncthreads();
+      ok = sweep_inverse<QM>(sr, vb[1], 1e-14) && ok;
+      if (ok) {
+        double *wout = a.weights + (int64_t)F * DIM * base;
+        for (int f = 0; f < F; ++f) {
+          const int kind = rk.kind[f], comp = rk.comp[f];
+          if (kind == FK_DIV) {  // identically zero on a divergence-free fit
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+              const int j = lane + 64 * r;
+#pragma unroll
+              for (int k = 0; k < DIM; ++k)
+                if (j < N) wout[((int64_t)f * N + j) * DIM + k] = 0.0;
+            }
+            continue;
+          }
+          // v = G^-1 l (component comp): v_i = Dg_i (E^-1 Dg lambda)_i
+          const double lam = lane < QS ? scalar_lambda<DIM, ORDER>(kind, lane, ie) : 0.0;
+          vb[0][lane] = lam * dg;
+          __syncthreads();
+          double acc = 0.0;
+#pragma unroll
+          for (int k = 0; k < QS; ++k) acc = fma(e[k], vb[0][k], acc);
+          const double v = -dg * acc;
+          vb[3][lane] = v;
+          __syncthreads();
+          // t = S^-1 r, r_b = v_(b + e_comp): t_b = ds_b ((ds S ds)^-1 (ds r))_b
+          const double rsc = lane < QM ? vb[3][ubl[comp]] * ds : 0.0;
+          vb[0][lane] = rsc;
+          if (lane < QS)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) ubuf[k][lane] = 0.0;
+          __syncthreads();
+          double tt = 0.0;
+#pragma unroll
+          for (int b2 = 0; b2 < QM; ++b2) tt = fma(sr[b2], vb[0][b2], tt);
+          tt = -ds * tt;
+          // Dg (sum_b t_b e_(b + e_k)), one vector per component k
+          if (lane < QM)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) ubuf[k][ubl[k]] = tt * vb[2][ubl[k]];
+          __syncthreads();
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            // g_k = delta_(k,comp) v + Dg E^-1 ... : g_i = d v_i - Dg_i (E^-1 u_k)_i
+            double uacc = 0.0;
+#pragma unroll
+            for (int q = 0; q < QS; ++q) uacc = fma(e[q], ubuf[k][q], uacc);
+            const double g = (k == comp ? v : 0.0) + dg * uacc;
+            vb[0][lane] = g * ifac;
+            __syncthreads();
+            double cf[QS];
+#pragma unroll
+            for (int q = 0; q < QS; ++q) cf[q] = vb[0][q];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+              const int j = lane + 64 * r;
+              const double val = w[r] * horner<DIM, ORDER>(cf, s[r]);
+              if (j < N) wout[((int64_t)f * N + j) * DIM + k] = val;
+            }
+          }
+        }
+      }
+    }
+    if (lane == 0) {
+      a.status[t] = ok ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
+      if (!ok) fb_list[atomicAdd(&meta->fb_count, 1)] = t;
+    }
+    cnt.good += ok ? 1 : 0;
+    cnt.fell += ok ? 0 : 1;
+    if (cond >= 0.0) cnt.cond = fmax(cnt.cond, cond);  // NaN estimates are skipped
+  }
+  if (lane == 0) {
+    if (cnt.good) atomicAdd(&stats->sweep_hist[0], cnt.good);
+    if (cnt.fell) atomicAdd(&stats->n_fallback, cnt.fell);
+    if (cnt.cond > 0.0) atomicMax(&stats->cond_max_bits, (unsigned long long)__double_as_longlong(cnt.cond));
+  }
+}
+
+// One launch per non-empty row-count bin (bin b: rows <= 64 b, b rows per
+// lane).  With a host copy of the bin table (hm) empty bins are skipped and
+// grids sized to the bin; without one every bin is launched, sized for n_max
+// targets, its bounds read on the device.
+template <int DIM, int ORDER, int BASIS>
+hipError_t launch_wave(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
+                       Stats *stats, const Options &opt, int n_max, int cus, hipStream_t s) {
+  for (int b = 1; b < kNumBins; ++b) {
+    int cnt = n_max;
+    if (hm) {
+      cnt = hm->count[b];
+      if (cnt == 0) continue;
+    }
+    int nb = cnt < cus * 16 ? cnt : cus * 16;
+    nb = xcd_grid(nb);
+    switch (b) {
+      case 1: k_wave<DIM, ORDER, BASIS, 1><<<nb, 64, 0, s>>>(a, list, meta, b, fb, stats, opt); break;
+      case 2: k_wave<DIM, ORDER, BASIS, 2><<<nb, 64, 0, s>>>(a, list, meta, b, fb, stats, opt); break;
+      case 3: k_wave<DIM, ORDER, BASIS, 3><<<nb, 64, 0, s>>>(a, list, meta, b, fb, stats, opt); break;
+      default: k_wave<DIM, ORDER, BASIS, 4><<<nb, 64, 0, s>>>(a, list, meta, b, fb, stats, opt); break;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gmls

@@ -30,7 +30,8 @@ def run_normal(G, c, x, r0, prec, scheme=0):
     return [host(v) for v in (rp, col, eps, w, st)]
 
 
-@pytest.mark.parametrize("prec,scheme", [(0, 0), (1, 3), (1, 1)], ids=["fp64", "mixed-pipe", "mixed-rows"])
+@pytest.mark.parametrize("prec,scheme", [(0, 0), (1, 3), (1, 1), (1, 4)],
+                         ids=["fp64", "mixed-pipe", "mixed-rows", "mixed-wave"])
 def test_graph_replays_match_eager(prec, scheme):
     G = require_gpu()
     pts, r0 = case()

@@ -142,11 +142,14 @@ def _nmono(dim, deg):
 
 
 def scheme_compiled(name, scheme):
-    """Whether a mixed scheme (1 rows, 2 moment Gram, 3 pipeline) exists for a case."""
+    """Whether a mixed scheme (1 rows, 2 moment Gram, 3 pipeline, 4 wavefront
+    per target) exists for a case."""
     _, _, basis, order, _, _ = CASES[name]
     dim = case_data(name)[0].shape[1]
     if scheme == 1:
         return True
+    if scheme == 4:
+        return _nmono(dim, order) <= 35
     if scheme == 2:
         return _nmono(dim, 2 * order) <= 96
     # the pipeline: scalar bases of <= 20 monomials, divergence-free bases
@@ -182,7 +185,7 @@ def check_mixed(name, gw, gst, rep):
     assert sum(rep["sweep_hist"]) + rep["n_fallback"] + rep["n_not_converged"] == n_live
 
 
-@pytest.mark.parametrize("scheme", [1, 2, 3], ids=["rows", "gram", "pipe"])
+@pytest.mark.parametrize("scheme", [1, 2, 3, 4], ids=["rows", "gram", "pipe", "wave"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_mixed_matches_oracle(name, scheme):
     G = require_gpu()
@@ -206,7 +209,7 @@ def test_mixed_pipe_chunks(chunk):
     check_mixed("3d_m3_radius", *run_mixed("3d_m3_radius", 3, chunk))
 
 
-@pytest.mark.parametrize("scheme", [1, 2, 3], ids=["rows", "gram", "pipe"])
+@pytest.mark.parametrize("scheme", [1, 2, 3, 4], ids=["rows", "gram", "pipe", "wave"])
 def test_mixed_forced_fallback_is_fp64_exact(scheme):
     G = require_gpu()
     c = ctx()
@@ -238,7 +241,33 @@ def test_divfree_pipe_forced_fallback_is_fp64_exact():
     assert errs.max() <= FP64_TOL
 
 
-@pytest.mark.parametrize("scheme", [1, 2, 3], ids=["rows", "gram", "pipe"])
+def test_divfree_wave_forced_fallback_is_fp64_exact():
+    """The wavefront kernel hands every divergence-free target to the FP64 QR kernel."""
+    G = require_gpu()
+    c = ctx()
+    c.set_option(G.OPT_FORCE_FALLBACK, 1)
+    try:
+        pts, rp, col, eps, w, st, F, C = case_data("2d_divfree_m2")
+        gw, gst, rep = run_mixed("2d_divfree_m2", 4)
+    finally:
+        c.set_option(G.OPT_FORCE_FALLBACK, 0)
+    assert (gst == 2).all() and rep["n_fallback"] == len(st)
+    errs = row_errors(gw, w, rp, F, C, zero_rows=(F - 1,))
+    flush(f"  divergence-free wave forced fallback max rel err {errs.max():.3e}")
+    assert errs.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["3d_m4_k170", "3d_divfree_m4", "3d_m3_radius"])
+def test_wave_reproducible(name):
+    """Two calls of the wavefront kernel give identical bits (fixed reduction order)."""
+    require_gpu()
+    a = run_mixed(name, 4)
+    b = run_mixed(name, 4)
+    assert np.array_equal(a[0].view(np.uint64), b[0].view(np.uint64))
+    assert np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("scheme", [1, 2, 3, 4], ids=["rows", "gram", "pipe", "wave"])
 def test_mixed_near_coplanar_triggers_fallback(scheme):
     G = require_gpu()
     n = 4000
