@@ -82,39 +82,65 @@ __device__ __forceinline__ double wave_max(double v) {
 
 // Symmetric sweep of every pivot of the Q x Q symmetric matrix whose row
 // `lane` is a[] (lanes >= Q hold zeros): on return a[] is row `lane` of
-// -A^-1.  Pivot k: a_kk <- -1/a_kk, a_ik <- a_ik / a_kk, a_kj <- a_kj / a_kk,
-// a_ij <- a_ij - a_ik a_kj / a_kk; the matrix stays symmetric, so column k
-// (one LDS store per lane) is also row k.  Returns false when a pivot is
-// not above tol (wave-uniform).
+// -A^-1.  Sweeping the pivot set P: A_PP <- -A_PP^-1, A_iP <- A_iP A_PP^-1,
+// A_Pj <- A_PP^-1 A_Pj, A_ij <- A_ij - A_iP A_PP^-1 A_Pj (i, j not in P);
+// sweeps of disjoint sets commute, so the pivots are taken two at a time
+// (2 x 2 blocks, one reciprocal of the determinant each) and a trailing
+// single pivot for odd Q.  The matrix stays symmetric, so columns k, k+1
+// (one LDS store each per lane) are also rows k, k+1; the column buffers
+// alternate between steps (col: 4 x 64 doubles), one barrier per step.
+// Returns false when a leading pivot of a block is not above tol
+// (wave-uniform).
 template <int Q>
 __device__ __forceinline__ bool sweep_inverse(double (&a)[Q], double *col, double tol) {
   const int lane = lane_id();
   bool ok = true;
 #pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    if (lane < Q) col[lane] = a[k];
+  for (int k = 0; k + 1 < Q; k += 2) {
+    double *c0 = col + ((k >> 1) & 1) * 128, *c1 = c0 + 64;
+    if (lane < Q) {
+      c0[lane] = a[k];
+      c1[lane] = a[k + 1];
+    }
     __syncthreads();
-    double rk[Q];
-#pragma unroll
-    for (int j = 0; j < Q; ++j) rk[j] = col[j];
-    __syncthreads();
-    const double piv = rk[k];
-    ok = ok && piv > tol;
-    const double d = 1.0 / piv;
-    const double f = a[k] * d;
-    // row k itself becomes a_kj / a_kk: a_kj + (d - a_kk d) a_kj, exact up
-    // to rounding because the equilibrated pivots are at most 1 (d >= 1)
-    const double ef = (lane == k ? d : 0.0) - f;
+    const double p00 = c0[k], p01 = c0[k + 1], p11 = c1[k + 1];
+    const double det = p00 * p11 - p01 * p01;
+    ok = ok && p00 > tol && det > tol * p00;
+    const double id = 1.0 / det;
+    const double i00 = p11 * id, i01 = -p01 * id, i11 = p00 * id;
+    const double ak = a[k], ak1 = a[k + 1];
+    const double f0 = ak * i00 + ak1 * i01, f1 = ak * i01 + ak1 * i11;
+    // rows k, k+1 themselves become A_PP^-1 A_Pj: their f is the unit
+    // vector up to rounding, so the same update with e = A_PP^-1 applies
+    const bool l0 = lane == k, l1 = lane == k + 1;
+    const double e0 = (l0 ? i00 : l1 ? i01 : 0.0) - f0;
+    const double e1 = (l0 ? i01 : l1 ? i11 : 0.0) - f1;
 #pragma unroll
     for (int j = 0; j < Q; ++j)
-      if (j != k) a[j] = fma(ef, rk[j], a[j]);
-    a[k] = lane == k ? -d : f;
-    // finish this pivot's updates here: left alone, the compiler defers each
-    // a[j] update to the pivot that first reads it, which keeps every
-    // earlier pivot row live (quadratic register use)
+      if (j != k && j != k + 1) a[j] = fma(e0, c0[j], fma(e1, c1[j], a[j]));
+    a[k] = l0 ? -i00 : l1 ? -i01 : f0;
+    a[k + 1] = l0 ? -i01 : l1 ? -i11 : f1;
+    // finish this step's updates here: left alone, the compiler defers each
+    // a[j] update to the step that first reads it, which keeps every
+    // earlier pivot column live (quadratic register use)
 #pragma unroll
     for (int j = 0; j < Q; ++j) asm volatile("" : "+v"(a[j]));
   }
+  if constexpr (Q % 2 == 1) {
+    constexpr int k = Q - 1;
+    double *c0 = col + (((Q / 2) & 1) * 128);
+    if (lane < Q) c0[lane] = a[k];
+    __syncthreads();
+    const double piv = c0[k];
+    ok = ok && piv > tol;
+    const double d = 1.0 / piv;
+    const double f = a[k] * d;
+    const double ef = (lane == k ? d : 0.0) - f;
+#pragma unroll
+    for (int j = 0; j < Q - 1; ++j) a[j] = fma(ef, c0[j], a[j]);
+    a[k] = lane == k ? -d : f;
+  }
+  __syncthreads();  // the buffers may be rewritten after this
   return ok;
 }
 
@@ -197,6 +223,37 @@ __device__ __forceinline__ void wave_moments(const double (&s)[RPL][DIM], const 
   WaveMoment<DIM, ORDER, RPL, 0>::run(s, pl, wa, wab, acc, red, mu);
 }
 
+// sum_q e[q] Dg_q lambda_q over the nonzero entries lambda_q of a functional
+// on the scaled basis (Section 2.5), Dg_q = q! dsc_q: the value reads monomial
+// 0; a gradient component the linear monomial s_d (1/eps); the Laplacian the
+// three pure squares s_d^2 (1/eps^2 each, their 1/2! cancelled by q!).  The
+// monomial indices are compile-time, so e[] stays in registers.
+template <int DIM, int ORDER, int QS, int I>
+__device__ __forceinline__ double lam_term(const double (&e)[QS], const double *dsc) {
+  constexpr InvFact64<DIM, ORDER> IF{};
+  return e[I] * (dsc[I] * (1.0 / IF.v[I]));
+}
+
+template <int DIM, int ORDER, int QS>
+__device__ __forceinline__ double lambda_dot(int kind, const double (&e)[QS], const double *dsc, double ie) {
+  constexpr MonoIndex<DIM, ORDER> MI{};
+  if (kind == FK_VALUE) return lam_term<DIM, ORDER, QS, 0>(e, dsc);
+  if constexpr (ORDER >= 1) {
+    if (kind == FK_GRAD0) return ie * lam_term<DIM, ORDER, QS, MI.idx[1][0][0]>(e, dsc);
+    if (kind == FK_GRAD1) return ie * lam_term<DIM, ORDER, QS, MI.idx[0][1][0]>(e, dsc);
+    if constexpr (DIM == 3)
+      if (kind == FK_GRAD2) return ie * lam_term<DIM, ORDER, QS, MI.idx[0][0][1]>(e, dsc);
+  }
+  if constexpr (ORDER >= 2) {
+    if (kind == FK_LAP) {
+      double t = lam_term<DIM, ORDER, QS, MI.idx[2][0][0]>(e, dsc) + lam_term<DIM, ORDER, QS, MI.idx[0][2][0]>(e, dsc);
+      if constexpr (DIM == 3) t += lam_term<DIM, ORDER, QS, MI.idx[0][0][2]>(e, dsc);
+      return ie * ie * t;
+    }
+  }
+  return 0.0;
+}
+
 // Per-block counters, added to the call's statistics once per block.
 struct WaveCounts {
   unsigned long long good = 0, fell = 0;
@@ -215,7 +272,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   __shared__ double big[BIG];    // moment reduction, then (divergence-free) -E^-1
   __shared__ double mu[NM];      // moments, lexicographic order
   __shared__ double vb[4][64];   // broadcast vectors
-  __shared__ double ubuf[BASIS == 1 ? DIM : 1][QS];
+  __shared__ double colb[4 * 64];  // pivot columns of the sweeps
   __shared__ unsigned char pidx[QS * QS];
   constexpr WavePairs<DIM, ORDER> WP{};
   constexpr InvFact64<DIM, ORDER> IF{};
@@ -264,7 +321,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
     for (int k = 0; k < QS; ++k) rs += fabs(e[k]);
     const double anorm = wave_max(rs);
-    bool ok = sweep_inverse<QS>(e, vb[1], 1e-14);  // e = row `lane` of -E^-1
+    bool ok = sweep_inverse<QS>(e, colb, 1e-14);  // e = row `lane` of -E^-1
     rs = 0.0;
 #pragma unroll
     for (int k = 0; k < QS; ++k) rs += fabs(e[k]);
@@ -275,20 +332,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 
     if constexpr (BASIS == 0) {
       if (ok) {
+        // coefficients y_i / i! = dsc_i (E^-1 Dg lambda)_i of every row,
+        // broadcast through LDS (big is free after the moments)
+        double *cfb = big;  // [F][64]
+        for (int f = 0; f < F; ++f) cfb[f * 64 + lane] = -dsc * lambda_dot<DIM, ORDER, QS>(rk.kind[f], e, vb[0], ie);
+        __syncthreads();
         double *wout = a.weights + (int64_t)F * base;
         for (int f = 0; f < F; ++f) {
-          // cf_i = y_i / i! = dsc_i (E^-1 Dg lambda)_i
-          vb[2][lane] = lane < QS ? scalar_lambda<DIM, ORDER>(rk.kind[f], lane, ie) * dg : 0.0;
-          __syncthreads();
-          double acc = 0.0;
-#pragma unroll
-          for (int k = 0; k < QS; ++k) acc = fma(e[k], vb[2][k], acc);
-          vb[3][lane] = -dsc * acc;
-          __syncthreads();
           double cf[QS];
 #pragma unroll
-          for (int k = 0; k < QS; ++k) cf[k] = vb[3][k];
-          __syncthreads();
+          for (int k = 0; k < QS; ++k) cf[k] = cfb[f * 64 + k];
 #pragma unroll
           for (int r = 0; r < RPL; ++r) {
             const int j = lane + 64 * r;
@@ -316,77 +369,87 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
         sr[b2] = lane < QM ? v : 0.0;
         if (lane == b2) sdiag = v;
       }
-      // equilibrate S (ds_b = 1/sqrt(S_bb)) and sweep it: se = -(ds S ds)^-1
+      // equilibrate S (ds_b = 1/sqrt(S_bb)) and sweep it: sr = -(ds S ds)^-1
       const double ds = lane < QM ? 1.0 / sqrt(sdiag) : 0.0;
       vb[3][lane] = ds;
       __syncthreads();
 #pragma unroll
       for (int b2 = 0; b2 < QM; ++b2) sr[b2] *= ds * vb[3][b2];
-      __syncthreads();
-      ok = sweep_inverse<QM>(sr, vb[1], 1e-14) && ok;
+      ok = sweep_inverse<QM>(sr, colb, 1e-14) && ok;  // ends with a barrier: big is free
       if (ok) {
         double *wout = a.weights + (int64_t)F * DIM * base;
-        for (int f = 0; f < F; ++f) {
-          const int kind = rk.kind[f], comp = rk.comp[f];
+        // rows come in groups of DIM (one kind, components 0..DIM-1), then
+        // the divergence row; per group, for component c of the functional:
+        //   v = G^-1 l (the same for every c), r_b = v_(b + e_c),
+        //   t = S^-1 r = ds (ds S ds)^-1 ds r,
+        //   g_(c,k) = delta_(k,c) v - G^-1 D_k^T t, D_k^T t = sum_b t_b e_(b+e_k),
+        // whose columns of E^-1 are this lane's registers
+        double *rb = big;                              // [c][QM]     ds_b r_b
+        double *tdg = big + DIM * QM;                  // [c][k][QM]  t_b Dg_(b+e_k)
+        double *cfb = big + DIM * QM + DIM * DIM * QM; // [c][k][QS]  g / q!
+        for (int f0 = 0; f0 < F; f0 += DIM) {
+          const int kind = rk.kind[f0];
           if (kind == FK_DIV) {  // identically zero on a divergence-free fit
 #pragma unroll
             for (int r = 0; r < RPL; ++r) {
               const int j = lane + 64 * r;
 #pragma unroll
               for (int k = 0; k < DIM; ++k)
-                if (j < N) wout[((int64_t)f * N + j) * DIM + k] = 0.0;
+                if (j < N) wout[((int64_t)f0 * N + j) * DIM + k] = 0.0;
             }
-            continue;
+            break;  // the last row
           }
-          // v = G^-1 l (component comp): v_i = Dg_i (E^-1 Dg lambda)_i
-          const double lam = lane < QS ? scalar_lambda<DIM, ORDER>(kind, lane, ie) : 0.0;
-          vb[0][lane] = lam * dg;
+          const double v = -dg * lambda_dot<DIM, ORDER, QS>(kind, e, vb[0], ie);
+          vb[1][lane] = v;
           __syncthreads();
-          double acc = 0.0;
-#pragma unroll
-          for (int k = 0; k < QS; ++k) acc = fma(e[k], vb[0][k], acc);
-          const double v = -dg * acc;
-          vb[3][lane] = v;
-          __syncthreads();
-          // t = S^-1 r, r_b = v_(b + e_comp): t_b = ds_b ((ds S ds)^-1 (ds r))_b
-          const double rsc = lane < QM ? vb[3][ubl[comp]] * ds : 0.0;
-          vb[0][lane] = rsc;
-          if (lane < QS)
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) ubuf[k][lane] = 0.0;
-          __syncthreads();
-          double tt = 0.0;
-#pragma unroll
-          for (int b2 = 0; b2 < QM; ++b2) tt = fma(sr[b2], vb[0][b2], tt);
-          tt = -ds * tt;
-          // Dg (sum_b t_b e_(b + e_k)), one vector per component k
           if (lane < QM)
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) ubuf[k][ubl[k]] = tt * vb[2][ubl[k]];
+            for (int c = 0; c < DIM; ++c) rb[c * QM + lane] = vb[1][ubl[c]] * ds;
           __syncthreads();
+          if (lane < QM) {
 #pragma unroll
-          for (int k = 0; k < DIM; ++k) {
-            // g_k = delta_(k,comp) v + Dg E^-1 ... : g_i = d v_i - Dg_i (E^-1 u_k)_i
-            double uacc = 0.0;
+            for (int c = 0; c < DIM; ++c) {
+              double tt = 0.0;
 #pragma unroll
-            for (int q = 0; q < QS; ++q) uacc = fma(e[q], ubuf[k][q], uacc);
-            const double g = (k == comp ? v : 0.0) + dg * uacc;
-            vb[0][lane] = g * ifac;
-            __syncthreads();
-            double cf[QS];
+              for (int b2 = 0; b2 < QM; ++b2) tt = fma(sr[b2], rb[c * QM + b2], tt);
+              tt = -ds * tt;
 #pragma unroll
-            for (int q = 0; q < QS; ++q) cf[q] = vb[0][q];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-              const int j = lane + 64 * r;
-              const double val = w[r] * horner<DIM, ORDER>(cf, s[r]);
-              if (j < N) wout[((int64_t)f * N + j) * DIM + k] = val;
+              for (int k = 0; k < DIM; ++k) tdg[(c * DIM + k) * QM + lane] = tt * vb[2][ubl[k]];
             }
           }
+          __syncthreads();
+          if (lane < QS) {
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+#pragma unroll
+              for (int k = 0; k < DIM; ++k) {
+                double u = 0.0;
+#pragma unroll
+                for (int b = 0; b < QM; ++b) u = fma(e[DU.up[b][k]], tdg[(c * DIM + k) * QM + b], u);
+                const double g = (k == c ? v : 0.0) + dg * u;
+                cfb[(c * DIM + k) * QS + lane] = g * ifac;
+              }
+          }
+          __syncthreads();
+#pragma unroll
+          for (int c = 0; c < DIM; ++c)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+              double cf[QS];
+#pragma unroll
+              for (int q = 0; q < QS; ++q) cf[q] = cfb[(c * DIM + k) * QS + q];
+#pragma unroll
+              for (int r = 0; r < RPL; ++r) {
+                const int j = lane + 64 * r;
+                const double val = w[r] * horner<DIM, ORDER>(cf, s[r]);
+                if (j < N) wout[((int64_t)(f0 + c) * N + j) * DIM + k] = val;
+              }
+            }
+          __syncthreads();
         }
       }
     }
+    __syncthreads();
     if (lane == 0) {
       a.status[t] = ok ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
       if (!ok) fb_list[atomicAdd(&meta->fb_count, 1)] = t;
