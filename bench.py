@@ -21,6 +21,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -150,6 +151,10 @@ def parse():
     ap.add_argument("--scheme", type=int, default=0,
                     help="mixed scheme: 0 auto, 1 fused/rows residual, 2 fused/moment Gram, 3 pipeline, 4 wavefront per target")
     ap.add_argument("--chunk", type=int, default=0, help="pipeline chunk (targets; 0 = whole batch)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="mixed pipeline: keep the default row shapes instead of autotuning them first")
+    ap.add_argument("--tune-cache", default="",
+                    help="autotune table (JSON): loaded if the file exists, else written after tuning")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy (counter scaling) and exit")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of HIP graph replays of search + stencils")
@@ -319,6 +324,42 @@ def main():
         bs["st"] = torch.empty(n_t, dtype=torch.uint8, device=dev)
         bs["aux"] = torch.empty((n_t, bs["F"]), dtype=torch.float64, device=dev)
 
+    # ---- autotune the mixed pipeline's row shapes (before any timing) ----
+    tune_summary = "off"
+    tune_path = None
+    if prec == G.PREC_MIXED and not args.no_autotune:
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            G.gmls_autotune_load(ctx, args.tune_cache)
+            tune_summary = {"loaded": args.tune_cache}
+            tune_path = args.tune_cache
+        else:
+            tune_summary = {}
+            t0 = time.time()
+            for bs in bases:
+                if bs["name"] == "neumann":
+                    continue
+                # staggered stencils run the scalar pipeline of order + 1
+                order_t, b_t = (bs["order"] + 1, G.BASIS_SCALAR) if bs["name"] == "staggered" \
+                    else (bs["order"], bs["b"])
+                try:
+                    res = G.gmls_autotune(ctx, x, xt, order_t, b_t, bs["mask"], p, eps, rp, col, reps=3)
+                except G.GmlsError as e:
+                    if e.status != G.GMLS_ERR_UNSUPPORTED:  # not the pipeline: nothing to tune
+                        raise
+                    continue
+                tune_summary[bs["name"]] = {k: {b: "%dx%d" % v["chosen"] for b, v in d.items()}
+                                            for k, d in res.items()}
+            print(f"# autotune: {tune_summary} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
+            if tune_summary:
+                if args.tune_cache:
+                    tune_path = args.tune_cache
+                else:
+                    fd, tune_path = tempfile.mkstemp(suffix=".json")
+                    os.close(fd)
+                G.gmls_autotune_save(ctx, tune_path)
+            else:
+                tune_summary = "no pipeline in this configuration"
+
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def step(report=False):
@@ -358,6 +399,8 @@ def main():
         gs = torch.cuda.Stream()
         gctx = G.Context(0, stream=gs)
         gctx.set_option(G.OPT_MIXED_SCHEME, args.scheme)
+        if tune_path:
+            G.gmls_autotune_load(gctx, tune_path)  # the same row shapes as the eager steps
         with torch.cuda.stream(gs):
             # one normal call of each kind sizes the context's workspace
             rpw, colw, epsw = G.gmls_neighbors(gctx, x, xt, **spec)
@@ -395,6 +438,9 @@ def main():
         rp_t, col_t, eps_t = gout["rp"], gcol[:nnz], gout["eps"]
         for bs in bases:
             bs["w"], bs["st"], bs["aux"] = bs["gw"], bs["gst"], bs["gaux"]
+
+    if tune_path and not args.tune_cache:
+        os.remove(tune_path)
 
     # ---- the CPU-baseline leg: the only part of this file that uses the
     # oracle.  It checks sampled outputs of the timed run against it (the
@@ -532,6 +578,7 @@ def main():
                    "search": wl["search"][0] + (f" k={k}" if knn else f" r={r0:.6f} k_min={k_min}"),
                    "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
                                     "pipeline", "wavefront per target"][args.scheme],
+                   "autotune": tune_summary,
                    "parity_gate": gate, "parity_max_rel_err": max_err, "parity_sample": int(n_sample),
                    "timed_unit": "HIP graph replay of search + stencils" if graph else "eager calls",
                    "ms_per_step_eager": round(ms_eager, 4),

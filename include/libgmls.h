@@ -153,10 +153,16 @@ enum {
                                   - gmls_stencils takes no report (GMLS_ERR_ARG otherwise); a row
                                     longer than 256 leaves its target unwritten and is reported by
                                     gmls_check.                                                  */
-  GMLS_OPT_ROW_ORDER = 8       /* order of the entries of a radius row (a set) (0):
+  GMLS_OPT_ROW_ORDER = 8,      /* order of the entries of a radius row (a set) (0):
                                   0 = cell order: by (cell of the source in the search's uniform
                                       grid, source index); deterministic for given inputs, no sort;
                                   1 = ascending source index (a sort per row).                   */
+  GMLS_OPT_PIPE_SHAPE = 9      /* row shape of the pipeline's moment and weight kernels (-1):
+                                  -1 = the autotuned choice (gmls_autotune) for the call's
+                                       (dim, order, basis), kernel and row-count bin; candidate 0
+                                       where nothing was tuned;
+                                  0, 1, 2 = this candidate in every bin (gmls_tune_result lists
+                                       the lanes per target and rows per lane of each).          */
 };
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
@@ -329,6 +335,53 @@ gmls_status gmls_stencils_constrained(gmls_ctx ctx, const double *coords, int64_
  * field [n_src][C_in], out [n_tgt][F]. */
 gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, const int32_t *col,
                        const double *weights, int F, int C_in, const double *field, double *out);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner of the mixed pipeline (GMLS_OPT_MIXED_SCHEME 3, or the automatic
+ * choice where it resolves to 3).  The pipeline's two row-parallel kernels,
+ * the moments (kernel 0) and the weights (kernel 1), are compiled in
+ * GMLS_TUNE_CANDIDATES row shapes for each row-count bin b (targets with
+ * 64(b-1) < N <= 64b neighbours): G lanes per target and R rows per lane,
+ * G*R >= 64b, listed in gmls_tune_result.  How fast a shape runs depends on
+ * the neighbour counts, the cloud's order in memory and the functional count,
+ * so it is measured rather than modelled.
+ *
+ * gmls_autotune runs the stencil computation of gmls_stencils (prec =
+ * GMLS_PREC_MIXED) on the given problem `reps` times per candidate (every bin
+ * in the same candidate), brackets every per-bin launch of the two kernels
+ * with HIP events, and keeps for each (kernel, bin) the candidate with the
+ * smallest time (minimum over the repetitions) in the context's table, keyed
+ * by (dim, order, basis); later calls with that key and GMLS_OPT_PIPE_SHAPE
+ * -1 use it.  Bins without targets keep their previous entry.  Arguments are
+ * those of gmls_stencils; `weights` (F*C_in*nnz doubles) and `target_status`
+ * (uint8[n_tgt], nullable) receive the last run's result.  Synchronises the
+ * context's stream.  Errors: GMLS_ERR_ARG for reps outside 1..100 or in
+ * capture-safe mode; GMLS_ERR_UNSUPPORTED when the shape or the selected
+ * scheme does not run the pipeline; otherwise those of gmls_stencils.  `out`
+ * (host, nullable) receives the candidates, their times and the choice.
+ * -------------------------------------------------------------------------*/
+enum { GMLS_TUNE_BINS = 5, GMLS_TUNE_CANDIDATES = 3 };
+typedef struct {
+  int32_t lanes[2][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES]; /* [kernel][bin][candidate]: G (bin 0 unused) */
+  int32_t rows[2][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];  /* R, rows per lane                         */
+  float ms[2][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];      /* best time per launch; 0 for an empty bin */
+  int32_t chosen[2][GMLS_TUNE_BINS];                      /* candidate kept; -1 for an empty bin      */
+} gmls_tune_result;
+
+gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets, int64_t n_tgt,
+                          int dim, int order, int basis, unsigned functional_mask, int weight_p, const double *eps,
+                          const int64_t *row_ptr, const int32_t *col, int reps, double *weights,
+                          uint8_t *target_status, gmls_tune_result *out);
+
+/* The context's autotune table as a JSON file: {"libgmls_autotune": 1,
+ * "entries": [...]}, one object per tuned (dim, order, basis, kernel, bin)
+ * with its "lanes" and "rows_per_lane", one object per line.  Load merges the
+ * entries it names into the table; a file not in this format, or naming a
+ * shape that is not compiled, returns GMLS_ERR_ARG and changes nothing.
+ * Host only (no device work).  GMLS_ERR_ARG also when the file cannot be
+ * opened. */
+gmls_status gmls_autotune_save(gmls_ctx ctx, const char *path);
+gmls_status gmls_autotune_load(gmls_ctx ctx, const char *path);
 
 #ifdef __cplusplus
 }

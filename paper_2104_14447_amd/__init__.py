@@ -25,6 +25,7 @@ __all__ = [
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
     "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "OPT_ROW_ORDER", "ROW_ORDER_CELL",
     "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE", "SCHEME_WAVE",
+    "OPT_PIPE_SHAPE", "TuneResult", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -36,6 +37,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 SEARCH_KNN, SEARCH_RADIUS = 0, 1
 OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
 OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE, OPT_ROW_ORDER = 4, 5, 6, 7, 8
+OPT_PIPE_SHAPE = 9
 ROW_ORDER_CELL, ROW_ORDER_INDEX = 0, 1
 SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE, SCHEME_WAVE = 0, 1, 2, 3, 4
 GMLS_OK, GMLS_ERR_CAPACITY, GMLS_ERR_UNSUPPORTED, GMLS_WARN_TARGET_FLAGS = 0, 4, 5, 6
@@ -43,7 +45,8 @@ _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY
            6: "WARN_TARGET_FLAGS"}
 EXPORTED_SYMBOLS = ("gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
                     "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained", "gmls_stencils_staggered",
-                    "gmls_assemble_stokes", "gmls_spmv", "gmls_apply", "gmls_check")
+                    "gmls_assemble_stokes", "gmls_spmv", "gmls_apply", "gmls_check", "gmls_autotune",
+                    "gmls_autotune_save", "gmls_autotune_load")
 
 
 class GmlsError(RuntimeError):
@@ -55,6 +58,26 @@ class GmlsError(RuntimeError):
 class SearchSpec(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("k", ctypes.c_int32), ("eps_mult", ctypes.c_double),
                 ("radius", ctypes.c_double), ("k_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    """gmls_tune_result: [kernel 0 moments, 1 weights][bin][candidate]."""
+    _fields_ = [("lanes", ctypes.c_int32 * 3 * 5 * 2), ("rows", ctypes.c_int32 * 3 * 5 * 2),
+                ("ms", ctypes.c_float * 3 * 5 * 2), ("chosen", ctypes.c_int32 * 5 * 2)]
+
+    def as_dict(self):
+        out = {}
+        for k, kname in enumerate(("moments", "weights")):
+            bins = {}
+            for b in range(1, 5):
+                c = self.chosen[k][b]
+                if c < 0:
+                    continue
+                bins[b] = {"chosen": (self.lanes[k][b][c], self.rows[k][b][c]),
+                           "ms": {(self.lanes[k][b][q], self.rows[k][b][q]): round(self.ms[k][b][q], 4)
+                                  for q in range(3)}}
+            out[kname] = bins
+        return out
 
 
 class StokesStencils(ctypes.Structure):
@@ -124,6 +147,13 @@ def load_library():
     L.gmls_spmv.restype = ctypes.c_int
     L.gmls_check.argtypes = [_vp]
     L.gmls_check.restype = ctypes.c_int
+    L.gmls_autotune.argtypes = [_vp, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.POINTER(TuneResult)]
+    L.gmls_autotune.restype = ctypes.c_int
+    L.gmls_autotune_save.argtypes = [_vp, ctypes.c_char_p]
+    L.gmls_autotune_save.restype = ctypes.c_int
+    L.gmls_autotune_load.argtypes = [_vp, ctypes.c_char_p]
+    L.gmls_autotune_load.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -251,6 +281,36 @@ def gmls_stencils(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, ord
     if st not in (GMLS_OK, GMLS_WARN_TARGET_FLAGS):
         ctx._raise(st)
     return weights[: F * C * nnz], status[:n_tgt], (rep.as_dict() if report else None)
+
+
+def gmls_autotune(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, order: int, basis: int, mask: int,
+                  weight_p: int, eps: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor, reps: int = 3):
+    """Autotune the mixed pipeline's row shapes on this problem (the choice is
+    kept in the context).  Returns the tuning result as a dict."""
+    _check_dev(coords, targets, eps, row_ptr, col)
+    n_src, dim = coords.shape
+    n_tgt = targets.shape[0]
+    F, C, _ = gmls_stencil_shape(dim, order, basis, mask)
+    weights = torch.empty(max(F * C * col.numel(), 1), dtype=torch.float64, device=coords.device)
+    res = TuneResult()
+    st = load_library().gmls_autotune(ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, order, basis, mask,
+                                      weight_p, _ptr(eps), _ptr(row_ptr), _ptr(col), reps, _ptr(weights), None,
+                                      ctypes.byref(res))
+    if st != GMLS_OK:
+        ctx._raise(st)
+    return res.as_dict()
+
+
+def gmls_autotune_save(ctx: Context, path: str):
+    st = load_library().gmls_autotune_save(ctx._h, os.fsencode(path))
+    if st != GMLS_OK:
+        ctx._raise(st)
+
+
+def gmls_autotune_load(ctx: Context, path: str):
+    st = load_library().gmls_autotune_load(ctx._h, os.fsencode(path))
+    if st != GMLS_OK:
+        ctx._raise(st)
 
 
 def gmls_stencils_constrained(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, order: int, mask: int,

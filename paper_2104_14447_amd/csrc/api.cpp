@@ -1,6 +1,7 @@
 // api.cpp -- the C ABI of libgmls (include/libgmls.h): argument validation,
 // workspace management and the launch sequence of each call.
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
@@ -170,6 +171,11 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
       if (value != 0 && value != 1) return gmls_set_error(ctx, GMLS_ERR_ARG, "row order must be 0 (cell) or 1 (index)");
       ctx->opt.row_order = (int)value;
       return GMLS_OK;
+    case GMLS_OPT_PIPE_SHAPE:
+      if (!(value == (double)(int)value && value >= -1 && value < kPipeCands))
+        return gmls_set_error(ctx, GMLS_ERR_ARG, "pipeline shape must be -1 (tuned) or a candidate 0..2");
+      ctx->opt.pipe_force = (int)value;
+      return GMLS_OK;
     case GMLS_OPT_RADIUS_SCRATCH_MB:
       if (!(value >= 0 && value <= 1048576.0 && value == (double)(int64_t)value))
         return gmls_set_error(ctx, GMLS_ERR_ARG, "radius scratch must be an integer number of MiB in [0, 2^20]");
@@ -228,6 +234,9 @@ gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, co
 }
 
 }  // extern "C"
+
+// key of the autotune table
+static int tune_key(int dim, int order, int basis) { return (dim * 8 + order) * 4 + basis; }
 
 // plain (normals == nullptr), Neumann-constrained and staggered
 // (basis == kBasisStaggered) stencils
@@ -341,9 +350,20 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
     double *yb = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)F * qy * cap);
     void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * cap);
     if (!mom || !yb || !rec) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+    // row shapes of the moment and weight kernels: forced, tuned or default
+    const auto tuned = ctx->tune.find(tune_key(dim, order, mbasis));
+    for (int k = 0; k < 2; ++k)
+      for (int b = 0; b < 8; ++b) {
+        int c = 0;
+        if (opt.pipe_force >= 0)
+          c = opt.pipe_force;
+        else if (tuned != ctx->tune.end() && tuned->second[k * 8 + b] >= 0)
+          c = tuned->second[k * 8 + b];
+        opt.pipe_shape[k][b] = (signed char)c;
+      }
     if (n_work > 0)
       GMLS_HIP(launch_mixed_pipe(dim, order, mbasis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, mom, yb,
-                                 rec, chunk, n, cus, s));
+                                 rec, chunk, n, cus, ctx->timer, s));
   } else if (prec == GMLS_PREC_MIXED && opt.scheme == MIXED_WAVE) {
     if (!sync || hm.count[0] < n)
       GMLS_HIP(launch_mixed_wave(dim, order, mbasis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, n, cus, s));
@@ -517,6 +537,180 @@ gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, cons
     return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
   DeviceGuard g(ctx->device);
   GMLS_HIP(launch_apply(n_tgt, row_ptr, col, weights, F, C_in, field, out, ctx->stream));
+  return GMLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner of the pipeline's row shapes
+// ---------------------------------------------------------------------------
+gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets, int64_t n_tgt,
+                          int dim, int order, int basis, unsigned functional_mask, int weight_p, const double *eps,
+                          const int64_t *row_ptr, const int32_t *col, int reps, double *weights,
+                          uint8_t *target_status, gmls_tune_result *out) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (reps < 1 || reps > 100) return gmls_set_error(ctx, GMLS_ERR_ARG, "reps must be in 1..100");
+  if (ctx->opt.capture_safe)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "the autotuner times its runs: not available in capture-safe mode");
+  if (basis != GMLS_BASIS_SCALAR && basis != GMLS_BASIS_DIVFREE)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "basis must be GMLS_BASIS_SCALAR or GMLS_BASIS_DIVFREE");
+  if (mixed_scheme(dim, order, basis, ctx->opt.scheme) != MIXED_PIPE)
+    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED,
+                          "the autotuner tunes the mixed pipeline (scheme 3), which this shape or the selected "
+                          "scheme does not run");
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    for (int k = 0; k < 2; ++k)
+      for (int b = 0; b < kNumBins; ++b) {
+        out->chosen[k][b] = -1;
+        for (int c = 0; c < kPipeCands; ++c) {
+          out->lanes[k][b][c] = kPipeShapes[b][c].g;
+          out->rows[k][b][c] = kPipeShapes[b][c].rpl;
+        }
+      }
+  }
+  DeviceGuard g(ctx->device);
+  PipeTimer tm;
+  hipError_t he = hipSuccess;
+  for (int k = 0; k < 2 && he == hipSuccess; ++k)
+    for (int b = 0; b < 8 && he == hipSuccess; ++b)
+      for (int e = 0; e < 2 && he == hipSuccess; ++e) {
+        he = hipEventCreate(&tm.ev[k][b][e]);
+      }
+  auto destroy = [&]() {
+    for (int k = 0; k < 2; ++k)
+      for (int b = 0; b < 8; ++b)
+        for (int e = 0; e < 2; ++e)
+          if (tm.ev[k][b][e]) hipEventDestroy(tm.ev[k][b][e]);
+  };
+  if (he != hipSuccess) {
+    destroy();
+    return gmls_set_error(ctx, GMLS_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(he));
+  }
+  const Options saved = ctx->opt;
+  ctx->opt.pipe_chunk = 0;  // one launch per bin
+  float best[2][8][kPipeCands];
+  bool seen[2][8] = {};
+  for (auto &x : best)
+    for (auto &y : x)
+      for (auto &z : y) z = INFINITY;
+  gmls_status st = GMLS_OK;
+  for (int c = 0; c < kPipeCands && st == GMLS_OK; ++c) {
+    ctx->opt.pipe_force = c;
+    for (int r = 0; r < reps && st == GMLS_OK; ++r) {
+      memset(tm.used, 0, sizeof(tm.used));
+      ctx->timer = &tm;
+      st = run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, basis, functional_mask, weight_p, eps,
+                        row_ptr, col, nullptr, GMLS_PREC_MIXED, weights, nullptr, target_status, nullptr);
+      ctx->timer = nullptr;
+      if (st != GMLS_OK) break;
+      he = hipStreamSynchronize(ctx->stream);
+      if (he != hipSuccess) {
+        st = gmls_set_error(ctx, GMLS_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(he));
+        break;
+      }
+      for (int k = 0; k < 2; ++k)
+        for (int b = 1; b < kNumBins; ++b) {
+          if (!tm.used[k][b]) continue;
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, tm.ev[k][b][0], tm.ev[k][b][1]) != hipSuccess) continue;
+          best[k][b][c] = std::min(best[k][b][c], ms);
+          seen[k][b] = true;
+        }
+    }
+  }
+  ctx->opt = saved;
+  destroy();
+  if (st != GMLS_OK) return st;
+  auto ins = ctx->tune.emplace(tune_key(dim, order, basis), std::array<signed char, 16>{});
+  if (ins.second) ins.first->second.fill(-1);
+  auto &ent = ins.first->second;
+  for (int k = 0; k < 2; ++k)
+    for (int b = 1; b < kNumBins; ++b) {
+      if (!seen[k][b]) continue;
+      int arg = 0;
+      for (int c = 1; c < kPipeCands; ++c)
+        if (best[k][b][c] < best[k][b][arg]) arg = c;
+      ent[k * 8 + b] = (signed char)arg;
+      if (out) {
+        out->chosen[k][b] = arg;
+        for (int c = 0; c < kPipeCands; ++c) out->ms[k][b][c] = isfinite(best[k][b][c]) ? best[k][b][c] : 0.f;
+      }
+    }
+  return GMLS_OK;
+}
+
+gmls_status gmls_autotune_save(gmls_ctx ctx, const char *path) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (!path) return gmls_set_error(ctx, GMLS_ERR_ARG, "null path");
+  FILE *f = fopen(path, "w");
+  if (!f) return gmls_set_error(ctx, GMLS_ERR_ARG, std::string("cannot open ") + path + " for writing");
+  static const char *kKernel[2] = {"moments", "weights"};
+  fprintf(f, "{\"libgmls_autotune\": 1,\n \"entries\": [");
+  bool first = true;
+  for (const auto &kv : ctx->tune) {
+    const int basis = kv.first % 4, order = (kv.first / 4) % 8, dim = kv.first / 32;
+    for (int k = 0; k < 2; ++k)
+      for (int b = 1; b < kNumBins; ++b) {
+        const int c = kv.second[k * 8 + b];
+        if (c < 0) continue;
+        fprintf(f,
+                "%s\n  {\"dim\": %d, \"order\": %d, \"basis\": %d, \"kernel\": \"%s\", \"bin\": %d, \"lanes\": %d, "
+                "\"rows_per_lane\": %d}",
+                first ? "" : ",", dim, order, basis, kKernel[k], b, kPipeShapes[b][c].g, kPipeShapes[b][c].rpl);
+        first = false;
+      }
+  }
+  fprintf(f, "\n ]}\n");
+  const bool bad = ferror(f) != 0;
+  if (fclose(f) != 0 || bad) return gmls_set_error(ctx, GMLS_ERR_ARG, std::string("write error on ") + path);
+  return GMLS_OK;
+}
+
+gmls_status gmls_autotune_load(gmls_ctx ctx, const char *path) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (!path) return gmls_set_error(ctx, GMLS_ERR_ARG, "null path");
+  FILE *f = fopen(path, "r");
+  if (!f) return gmls_set_error(ctx, GMLS_ERR_ARG, std::string("cannot open ") + path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0 && text.size() < (1u << 20)) text.append(buf, got);
+  fclose(f);
+  if (text.find("\"libgmls_autotune\": 1") == std::string::npos)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "not a libgmls autotune file (version 1)");
+  std::map<int, std::array<signed char, 16>> add;
+  size_t pos = 0;
+  const std::string tag = "{\"dim\":";
+  while ((pos = text.find(tag, pos)) != std::string::npos) {
+    int dim = 0, order = 0, basis = 0, bin = 0, lanes = 0, rows = 0, used = 0;
+    char kernel[16] = {0};
+    const int n = sscanf(text.c_str() + pos,
+                         "{\"dim\": %d, \"order\": %d, \"basis\": %d, \"kernel\": \"%15[a-z]\", \"bin\": %d, "
+                         "\"lanes\": %d, \"rows_per_lane\": %d}%n",
+                         &dim, &order, &basis, kernel, &bin, &lanes, &rows, &used);
+    if (n != 7 || used == 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "malformed autotune entry");
+    const int k = strcmp(kernel, "moments") == 0 ? 0 : strcmp(kernel, "weights") == 0 ? 1 : -1;
+    if (dim < 2 || dim > 3 || order < 1 || order > 4 || basis < 0 || basis > 1 || k < 0 || bin < 1 ||
+        bin >= kNumBins)
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "autotune entry out of range");
+    int cand = -1;
+    for (int c = 0; c < kPipeCands; ++c)
+      if (kPipeShapes[bin][c].g == lanes && kPipeShapes[bin][c].rpl == rows) cand = c;
+    if (cand < 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "autotune entry names a row shape that is not compiled");
+    auto ins = add.emplace(tune_key(dim, order, basis), std::array<signed char, 16>{});
+    if (ins.second) ins.first->second.fill(-1);
+    ins.first->second[k * 8 + bin] = (signed char)cand;
+    pos += (size_t)used;
+  }
+  for (const auto &kv : add) {
+    auto ins = ctx->tune.emplace(kv.first, kv.second);
+    if (!ins.second)
+      for (int q = 0; q < 16; ++q)
+        if (kv.second[q] >= 0) ins.first->second[q] = kv.second[q];
+  }
   return GMLS_OK;
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -65,6 +67,17 @@ struct Options {
   int64_t radius_scratch_mb = 8192;  // scratch rows of the one-pass radius search (MiB)
   int capture_safe = 0;              // nonzero: no call waits for the device (see libgmls.h)
   int row_order = 0;                 // radius rows: 0 cell order, 1 ascending source index
+  int pipe_force = -1;               // pipeline row shape: -1 the tuned table, else this candidate
+  // per call: pipeline row-shape candidate of [kernel: 0 moments, 1 weights][bin]
+  signed char pipe_shape[2][8] = {};
+};
+
+// HIP events around every per-bin launch of the pipeline's moment and weight
+// kernels (the autotuner's measurement); used[k][b] is set for each launch
+// recorded
+struct PipeTimer {
+  hipEvent_t ev[2][8][2] = {};
+  int used[2][8] = {};
 };
 
 // Device error bits accumulated for gmls_check (capture-safe mode).
@@ -80,6 +93,10 @@ struct gmls_ctx_s {
   gmls::Options opt;
   hipEvent_t ev[8] = {};
   int cus = 256;  // compute units of the device
+  // autotuned pipeline row shapes: key (dim * 8 + order) * 4 + basis ->
+  // candidate of [kernel * 8 + bin], -1 where not tuned
+  std::map<int, std::array<signed char, 16>> tune;
+  gmls::PipeTimer *timer = nullptr;  // set by the autotuner around its runs
 
   // Device buffer of at least `bytes` for `slot`; nullptr on failure (and,
   // in capture-safe mode, when the slot would have to grow).
@@ -165,9 +182,11 @@ hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const Stenci
 constexpr size_t kPipeRecBytes = 64;
 // hm: host copy of the bin table, or nullptr when the launches may not
 // depend on it (every bound then comes from `meta` on the device)
+// timer: nullptr, or events to record around each per-bin launch
 hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt,
-                             double *mom, double *y, void *rec, int64_t chunk, int n_max, int cus, hipStream_t s);
+                             double *mom, double *y, void *rec, int64_t chunk, int n_max, int cus,
+                             PipeTimer *timer, hipStream_t s);
 // one wavefront per target (bins launched as in launch_mixed_pipe)
 hipError_t launch_mixed_wave(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt, int n_max,
@@ -222,6 +241,21 @@ hipError_t launch_apply(int64_t n_tgt, const int64_t *row_ptr, const int32_t *co
 // number of bins: 0 = rank deficient (N*C < Q), b >= 1: N <= 64*b
 constexpr int kNumBins = 5;
 constexpr int kMaxRows = 256;
+
+// Row shapes of the pipeline's row-parallel kernels (moments, weights):
+// G lanes per target, RPL rows per lane, G * RPL >= 64 b for bin b.  All
+// three are compiled for every bin; candidate 0 is the untuned default and
+// the autotuner keeps the fastest per (dimension, order, basis, kernel, bin).
+constexpr int kPipeCands = 3;
+struct PipeShape {
+  int g, rpl;
+};
+constexpr PipeShape kPipeShapes[kNumBins][kPipeCands] = {
+    {{0, 0}, {0, 0}, {0, 0}},  // bin 0: rank deficient, never launched
+    {{8, 8}, {16, 4}, {4, 16}},
+    {{16, 8}, {32, 4}, {8, 16}},
+    {{32, 6}, {16, 12}, {64, 3}},
+    {{32, 8}, {64, 4}, {16, 16}}};
 
 }  // namespace gmls
 

@@ -54,14 +54,15 @@ hipError_t GMLS_FN(int bin, const StencilArgs &a, const int *list, BinMeta *meta
 
 hipError_t GMLS_PIPE_FN(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
                         Stats *stats, const Options &opt, double *mom, double *y, void *rec, int64_t chunk,
-                        int n_max, int cus, hipStream_t s) {
+                        int n_max, int cus, PipeTimer *timer, hipStream_t s) {
   constexpr int D = GMLS_DIM, O = GMLS_ORDER, B = GMLS_BASIS;
+  PipeRec *r = (PipeRec *)rec;
   if constexpr (B == 0 && has_pipe<D, O>()) {
     if (a.skip_const)  // staggered stencils
-      return launch_pipe<D, O, 1>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
-    return launch_pipe<D, O>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
+      return launch_pipe<D, O, 1>(a, list, hm, meta, fb, stats, opt, mom, y, r, chunk, n_max, cus, timer, s);
+    return launch_pipe<D, O>(a, list, hm, meta, fb, stats, opt, mom, y, r, chunk, n_max, cus, timer, s);
   } else if constexpr (B == 1 && has_pipe_div<D, O>()) {
-    return launch_pipe<D, O, 0, 1>(a, list, hm, meta, fb, stats, opt, mom, y, (PipeRec *)rec, chunk, n_max, cus, s);
+    return launch_pipe<D, O, 0, 1>(a, list, hm, meta, fb, stats, opt, mom, y, r, chunk, n_max, cus, timer, s);
   } else {
     return hipErrorInvalidValue;
   }

@@ -1,5 +1,6 @@
 // stencil_mixed.hip -- dispatch of the mixed-precision stencil kernels.  The
-// kernels are instantiated per (dim, order, basis) from mixed_unit.hip.
+// kernels are instantiated per (dim, order, basis) from mixed_unit.hip (fused
+// kernels and pipeline) and wave_unit.hip (one wavefront per target).
 #include "common.hpp"
 #include "gmls_internal.hpp"
 
@@ -39,40 +40,41 @@ hipError_t launch_mixed_d3_o4_b1(int, const StencilArgs &, const int *, BinMeta 
                                   const Options &, int, int, hipStream_t);
 
 hipError_t launch_pipe_d2_o1_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d2_o1_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d2_o2_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d2_o2_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d2_o3_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d2_o3_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d2_o4_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d2_o4_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d3_o1_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d3_o1_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d3_o2_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d3_o2_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d3_o3_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d3_o3_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d3_o4_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_pipe_d3_o4_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                                const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *, hipStream_t);
 
 using PipeFn = hipError_t (*)(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                              const Options &, double *, double *, void *, int64_t, int, int, hipStream_t);
+                              const Options &, double *, double *, void *, int64_t, int, int, PipeTimer *,
+                              hipStream_t);
 static const PipeFn kPipe[2][4][2] = {
     {{launch_pipe_d2_o1_b0, launch_pipe_d2_o1_b1}, {launch_pipe_d2_o2_b0, launch_pipe_d2_o2_b1}, {launch_pipe_d2_o3_b0, launch_pipe_d2_o3_b1}, {launch_pipe_d2_o4_b0, launch_pipe_d2_o4_b1}},
     {{launch_pipe_d3_o1_b0, launch_pipe_d3_o1_b1}, {launch_pipe_d3_o2_b0, launch_pipe_d3_o2_b1}, {launch_pipe_d3_o3_b0, launch_pipe_d3_o3_b1}, {launch_pipe_d3_o4_b0, launch_pipe_d3_o4_b1}}};
@@ -145,9 +147,11 @@ int pipe_num_moments(int dim, int order) { return num_mono(dim, 2 * order); }
 
 hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt,
-                             double *mom, double *y, void *rec, int64_t chunk, int n_max, int cus, hipStream_t s) {
+                             double *mom, double *y, void *rec, int64_t chunk, int n_max, int cus,
+                             PipeTimer *timer, hipStream_t s) {
   if (mixed_scheme(dim, order, basis, MIXED_PIPE) != MIXED_PIPE) return hipErrorInvalidValue;
-  return kPipe[dim - 2][order - 1][basis](a, list, hm, meta, fb, stats, opt, mom, y, rec, chunk, n_max, cus, s);
+  return kPipe[dim - 2][order - 1][basis](a, list, hm, meta, fb, stats, opt, mom, y, rec, chunk, n_max, cus, timer,
+                                          s);
 }
 
 hipError_t launch_mixed_wave(int dim, int order, int basis, const StencilArgs &a, const int *list,

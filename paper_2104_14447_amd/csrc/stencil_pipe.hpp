@@ -170,7 +170,7 @@ __device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, boo
   for (int m = 0; m < NM; ++m) asm volatile("" : "+v"(mu[m]));
   // sum the G lanes' partial moments through LDS, RS moments per round:
   // every lane writes its partials, then lane lg of the group adds column
-  // lg + G*k over the group's rows, in lane order, and stores it
+  // lg + G*k (< RS) over the group's rows, in lane order, and stores it
   const int lane = lane_id(), grp0 = lane - lg;
 #pragma unroll
   for (int r0 = 0; r0 < NM; r0 += RS) {
@@ -178,12 +178,14 @@ __device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, boo
     for (int q = 0; q < RS; ++q) red[lane][q] = r0 + q < NM ? mu[r0 + q] : 0.0;
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < RS / G; ++k) {
+    for (int k = 0; k < (RS + G - 1) / G; ++k) {
       const int q = lg + G * k;
-      double acc = 0.0;
+      if (q < RS) {
+        double acc = 0.0;
 #pragma unroll
-      for (int l = 0; l < G; ++l) acc += red[grp0 + l][q];
-      if (valid && r0 + q < NM) mom[(int64_t)slot * NM + r0 + q] = acc;
+        for (int l = 0; l < G; ++l) acc += red[grp0 + l][q];
+        if (valid && r0 + q < NM) mom[(int64_t)slot * NM + r0 + q] = acc;
+      }
     }
     __syncthreads();
   }
@@ -854,17 +856,35 @@ static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *r
   }
 }
 
+// the bin's launch in row shape `cand` (kPipeShapes)
+template <int DIM, int ORDER, int SKIP, int BASIS, int BIN>
+static void pipe_bin_shape(int cand, bool weights, const StencilArgs &a, const PipeRec *rec, const BinMeta *meta,
+                           int win_lo, int win_hi, int n_max, double *buf, int cus, hipStream_t s) {
+  constexpr PipeShape S0 = kPipeShapes[BIN][0], S1 = kPipeShapes[BIN][1], S2 = kPipeShapes[BIN][2];
+  if (cand == 1)
+    pipe_bin_launch<DIM, ORDER, S1.g, S1.rpl, SKIP, BASIS>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max, buf,
+                                                           cus, s);
+  else if (cand == 2)
+    pipe_bin_launch<DIM, ORDER, S2.g, S2.rpl, SKIP, BASIS>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max, buf,
+                                                           cus, s);
+  else
+    pipe_bin_launch<DIM, ORDER, S0.g, S0.rpl, SKIP, BASIS>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max, buf,
+                                                           cus, s);
+}
+
 // The pipeline over list slots [count[0], n) (bins 1..4, contiguous, in bin
 // order).  With a host copy of the bin table (hm) it runs in chunks of
 // `chunk` slots and skips empty bins; without one (hm == nullptr: nothing
 // may wait for the device) it covers every slot in one window, all bounds
 // read from the device table, grids sized for n_max slots.
-// lanes x rows per lane: bin 1 (<= 64 rows) 8 x 8, bin 2 (<= 128) 16 x 8,
-// bin 3 (<= 192) 32 x 6, bin 4 (<= 256) 32 x 8.
+// Lanes x rows per lane of the moment and weight kernels: the candidate
+// opt.pipe_shape[kernel][bin] of kPipeShapes (default, candidate 0: bin 1
+// (<= 64 rows) 8 x 8, bin 2 (<= 128) 16 x 8, bin 3 (<= 192) 32 x 6, bin 4
+// (<= 256) 32 x 8).  With a timer, events bracket every per-bin launch.
 template <int DIM, int ORDER, int SKIP = 0, int BASIS = 0>
 hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
                        Stats *stats, const Options &opt, double *mom, double *y, PipeRec *rec, int64_t chunk,
-                       int n_max, int cus, hipStream_t s) {
+                       int n_max, int cus, PipeTimer *timer, hipStream_t s) {
   int begin = 0, end = 1;
   if (hm) {
     begin = hm->offset[1];
@@ -902,14 +922,24 @@ hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm,
           nbin = hi - lo;
         }
         double *buf = wts ? y : mom;
+        const int cand = opt.pipe_shape[pass][b];
+        if (timer) {
+          hipError_t e = hipEventRecord(timer->ev[pass][b][0], s);
+          if (e != hipSuccess) return e;
+        }
         if (b == 1)
-          pipe_bin_launch<DIM, ORDER, 8, 8, SKIP, BASIS>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_shape<DIM, ORDER, SKIP, BASIS, 1>(cand, wts, a, rec, meta, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 2)
-          pipe_bin_launch<DIM, ORDER, 16, 8, SKIP, BASIS>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_shape<DIM, ORDER, SKIP, BASIS, 2>(cand, wts, a, rec, meta, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 3)
-          pipe_bin_launch<DIM, ORDER, 32, 6, SKIP, BASIS>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_shape<DIM, ORDER, SKIP, BASIS, 3>(cand, wts, a, rec, meta, win_lo, win_hi, nbin, buf, cus, s);
         else
-          pipe_bin_launch<DIM, ORDER, 32, 8, SKIP, BASIS>(wts, a, rec, meta, b, win_lo, win_hi, nbin, buf, cus, s);
+          pipe_bin_shape<DIM, ORDER, SKIP, BASIS, 4>(cand, wts, a, rec, meta, win_lo, win_hi, nbin, buf, cus, s);
+        if (timer) {
+          hipError_t e = hipEventRecord(timer->ev[pass][b][1], s);
+          if (e != hipSuccess) return e;
+          timer->used[pass][b] = 1;
+        }
       }
     }
   }

@@ -22,7 +22,7 @@ def test_header_declares_the_boundary():
     assert names == sorted(["gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
                             "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained",
                             "gmls_stencils_staggered", "gmls_assemble_stokes", "gmls_spmv", "gmls_apply",
-                            "gmls_check"])
+                            "gmls_check", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load"])
 
 
 def test_library_exports_every_declared_symbol():
@@ -84,6 +84,8 @@ def test_null_context_is_rejected():
     L = G.load_library()
     assert L.gmls_set_option(None, 0, 1.0) == 1
     assert L.gmls_last_error(None) == b"null context"
+    assert L.gmls_autotune_save(None, b"/nonexistent") == 1
+    assert L.gmls_autotune_load(None, b"/nonexistent") == 1
 
 
 def test_product_package_has_no_oracle_dependency():
