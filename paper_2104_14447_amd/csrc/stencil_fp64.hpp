@@ -110,6 +110,13 @@ __device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rd
       M[0][k] = 0.0;
     }
     if (lane == k) rdiag = M[0][k];
+    // finish this column's updates here: left alone, the compiler defers the
+    // updates of later columns to where they are next read, keeping every
+    // reflector live (registers grow with the column count)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+#pragma unroll
+      for (int l = k + 1; l < Q; ++l) asm volatile("" : "+v"(M[i][l]));
   }
 }
 
