@@ -128,6 +128,27 @@ __device__ __forceinline__ int64_t uniform_i64(int64_t v) {
   return __builtin_bit_cast(int64_t, b);
 }
 
+// v from the lane selected by a DPP control word (both halves of a double)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  int2 b = __builtin_bit_cast(int2, v);
+  b.x = __builtin_amdgcn_update_dpp(0, b.x, CTRL, 0xF, 0xF, false);
+  b.y = __builtin_amdgcn_update_dpp(0, b.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, b);
+}
+
+// Sum of v over all 64 lanes, the same value in every lane, without LDS
+// traffic: within each 16-lane row by DPP (swap neighbours, swap pairs,
+// rotate by 4, rotate by 8), then the four row sums read into scalar
+// registers and added in a fixed order.  Every lane must be active.
+__device__ __forceinline__ double wave_sum_uniform(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x128>(v);  // row_ror:8
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -68,7 +68,9 @@ __device__ __forceinline__ void load_rows(const StencilArgs &a, int t, Rows<DIM,
 }
 
 // Householder QR of the register-resident M (rows across lanes).  On return
-// lane k (k < Q) holds row k of R in M[0][k..Q-1] and rdiag = R_kk.
+// lane k (k < Q) holds row k of R in M[0][k..Q-1] and rdiag = R_kk.  The
+// column dot products are summed over the wavefront by DPP and scalar reads
+// (no LDS traffic); all 64 lanes take part.
 template <int Q, int RPL>
 __device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rdiag, int lane) {
   rdiag = 0.0;
@@ -84,11 +86,7 @@ __device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rd
       dots[l] = v;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int l = k; l < Q; ++l) dots[l] += __shfl_xor(dots[l], off, 64);
-#pragma unroll
-    for (int l = k; l < Q; ++l) dots[l] = uniform_d(dots[l]);
+    for (int l = k; l < Q; ++l) dots[l] = wave_sum_uniform(dots[l]);
     const double sigma = dots[k];
     const double xk = readlane_d(M[0][k], k);
     if (sigma > 0.0) {
