@@ -305,10 +305,14 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
     K[e] = v;
   }
   __syncthreads();
-  // Householder QR of K (KR x QD, column-major) in LDS, rows across lanes
+  // Householder QR of K (KR x QD, column-major) in LDS, rows across lanes:
+  // lane l owns rows l + 64 q of every column, so a column update touches
+  // only the lane's own entries; the dot products of the reflector with the
+  // later columns are taken CH at a time and summed over the wavefront by
+  // DPP (independent chains, no LDS traffic)
   constexpr int KRL = (KR + 63) / 64;
-  double kdiag = 0.0;  // R_K[i][i] on lane i % 64, slot i / 64 -> kept in LDS instead
-  double *Kd = U + 8 * KR;  // QD diagonal entries
+  constexpr int CH = 8;
+  double *Kd = U + 8 * KR;  // QD diagonal entries of R_K
   for (int k = 0; k < QD; ++k) {
     double xs[KRL];
     double part = 0.0;
@@ -318,7 +322,7 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
       xs[q] = (row >= k && row < KR) ? K[k * KR + row] : 0.0;
       part += xs[q] * xs[q];
     }
-    const double sigma = uniform_d(wave_sum(part));
+    const double sigma = wave_sum_uniform(part);
     const double xk = uniform_d(K[k * KR + k]);
     double beta = 0.0;
     if (sigma > 0.0) {
@@ -331,19 +335,28 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
         const int row = lane + 64 * q;
         v[q] = row == k ? xk - beta : xs[q];
       }
-      for (int l = k + 1; l < QD; ++l) {
-        double dp = 0.0;
+      for (int l0 = k + 1; l0 < QD; l0 += CH) {
+        double kv[CH][KRL], dp[CH];
 #pragma unroll
-        for (int q = 0; q < KRL; ++q) {
-          const int row = lane + 64 * q;
-          if (row >= k && row < KR) dp += v[q] * K[l * KR + row];
+        for (int u = 0; u < CH; ++u) {
+          dp[u] = 0.0;
+#pragma unroll
+          for (int q = 0; q < KRL; ++q) {
+            const int row = lane + 64 * q;
+            kv[u][q] = (l0 + u < QD && row >= k && row < KR) ? K[(l0 + u) * KR + row] : 0.0;
+            dp[u] += v[q] * kv[u][q];
+          }
         }
-        dp = uniform_d(wave_sum(dp));
-        const double coef = 2.0 * dp * inv_vtv;
 #pragma unroll
-        for (int q = 0; q < KRL; ++q) {
-          const int row = lane + 64 * q;
-          if (row >= k && row < KR) K[l * KR + row] -= coef * v[q];
+        for (int u = 0; u < CH; ++u) dp[u] = wave_sum_uniform(dp[u]);
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const double coef = 2.0 * dp[u] * inv_vtv;
+#pragma unroll
+          for (int q = 0; q < KRL; ++q) {
+            const int row = lane + 64 * q;
+            if (l0 + u < QD && row >= k && row < KR) K[(l0 + u) * KR + row] = kv[u][q] - coef * v[q];
+          }
         }
       }
     }
@@ -354,7 +367,6 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
     }
     __syncthreads();
   }
-  (void)kdiag;
   // rank test on both factors
   double dmax = 0.0, dmin = DBL_MAX;
   for (int k = lane; k < QD; k += 64) {
@@ -376,42 +388,65 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
     return;
   }
   const double ie = 1.0 / uniform_d(a.eps[t]);
-  // y = R_K^{-1} R_K^{-T} lambda for every row; R_K[k][l] = K[l*KR + k]
+  // y = R_K^{-1} R_K^{-T} lambda for every row at once; R_K[k][l] = K[l*KR + k].
+  // lambda_i = functional on psi_i: value c -> T[(0,c),i]; Laplacian c ->
+  // eps^-2 sum_d T[(2e_d,c),i]; divergence -> 0 (a divergence-free fit)
   for (int f = 0; f < F; ++f) {
     const int kind = rk.kind[f], comp = rk.comp[f];
-    // lambda_i = functional on psi_i: value c -> T[(0,c),i];
-    // Laplacian c -> eps^-2 sum_d T[(2e_d,c),i]; divergence -> 0
-    for (int i = lane; i < QD; i += 64) Y[f * QD + i] = divfree_lambda<DIM, ORDER>(i, kind, comp, ie);
+    for (int i = lane; i < QD; i += 64)
+      Y[f * QD + i] = kind == FK_DIV ? 0.0 : divfree_lambda<DIM, ORDER>(i, kind, comp, ie);
+  }
+  // forward R_K^T z = lambda, then back R_K y = z: one pivot per step for all
+  // rows, one barrier per step (the pivot's entry was last written by the
+  // lane that owns it in the step before)
+  for (int k = 0; k < QD; ++k) {
     __syncthreads();
-    if (kind != FK_DIV) {
-      // forward: R_K^T z = lambda (one lane walks the columns; QD <= 85)
-      for (int k = 0; k < QD; ++k) {
-        const double zk = uniform_d(Y[f * QD + k] / Kd[k]);
-        __syncthreads();
-        if (lane == 0) Y[f * QD + k] = zk;
-        for (int l = k + 1 + lane; l < QD; l += 64) Y[f * QD + l] -= K[l * KR + k] * zk;
-        __syncthreads();
-      }
-      for (int k = QD - 1; k >= 0; --k) {
-        const double yk = uniform_d(Y[f * QD + k] / Kd[k]);
-        __syncthreads();
-        if (lane == 0) Y[f * QD + k] = yk;
-        for (int l = lane; l < k; l += 64) Y[f * QD + l] -= K[k * KR + l] * yk;
-        __syncthreads();
-      }
-    } else {
-      for (int i = lane; i < QD; i += 64) Y[f * QD + i] = 0.0;
-    }
-    __syncthreads();
-    // u = T y  (KR entries)
-    for (int row = lane; row < KR; row += 64) U[f * KR + row] = 0.0;
-    __syncthreads();
+    const double id = 1.0 / uniform_d(Kd[k]);
+    double zk[8];
+#pragma unroll
+    for (int f = 0; f < 8; ++f) zk[f] = f < F ? uniform_d(Y[f * QD + k]) * id : 0.0;
     if (lane == 0)
-      for (int i = 0; i < QD; ++i) {
-        const double yi = Y[f * QD + i];
-        U[f * KR + DF.ia[i] * DIM + DF.ca[i]] += DF.va[i] * yi;
-        if (DF.ib[i] >= 0) U[f * KR + DF.ib[i] * DIM + DF.cb[i]] += DF.vb[i] * yi;
-      }
+#pragma unroll
+      for (int f = 0; f < 8; ++f)
+        if (f < F) Y[f * QD + k] = zk[f];
+    for (int l = k + 1 + lane; l < QD; l += 64) {
+      const double rkl = K[l * KR + k];
+#pragma unroll
+      for (int f = 0; f < 8; ++f)
+        if (f < F) Y[f * QD + l] -= rkl * zk[f];
+    }
+  }
+  for (int k = QD - 1; k >= 0; --k) {
+    __syncthreads();
+    const double id = 1.0 / uniform_d(Kd[k]);
+    double yk[8];
+#pragma unroll
+    for (int f = 0; f < 8; ++f) yk[f] = f < F ? uniform_d(Y[f * QD + k]) * id : 0.0;
+    if (lane == 0)
+#pragma unroll
+      for (int f = 0; f < 8; ++f)
+        if (f < F) Y[f * QD + k] = yk[f];
+    for (int l = lane; l < k; l += 64) {
+      const double rlk = K[k * KR + l];
+#pragma unroll
+      for (int f = 0; f < 8; ++f)
+        if (f < F) Y[f * QD + l] -= rlk * yk[f];
+    }
+  }
+  __syncthreads();
+  // u = T y (KR entries per row): the first entries (ia, ca) of the columns
+  // are distinct, so they are stored in parallel; the second entries
+  // (ib, 0) of columns with the same ca are distinct too, so they are added
+  // one component ca at a time (a fixed order: reproducible)
+  for (int e = lane; e < F * KR; e += 64) U[e] = 0.0;
+  __syncthreads();
+  for (int i = lane; i < QD; i += 64)
+    for (int f = 0; f < F; ++f) U[f * KR + DF.ia[i] * DIM + DF.ca[i]] = DF.va[i] * Y[f * QD + i];
+  __syncthreads();
+  for (int c = 1; c < DIM; ++c) {
+    for (int i = lane; i < QD; i += 64)
+      if (DF.ca[i] == c && DF.ib[i] >= 0)
+        for (int f = 0; f < F; ++f) U[f * KR + DF.ib[i] * DIM + DF.cb[i]] += DF.vb[i] * Y[f * QD + i];
     __syncthreads();
   }
 #pragma unroll
