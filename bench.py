@@ -92,7 +92,7 @@ PEAK = {  # MI355X published peaks
 # hardware counters is reported only while these are unchanged.
 # device code of the stencil-phase kernels (and their launch shapes)
 STENCIL_SOURCES = ["stencil_pipe.hpp", "stencil_mixed64.hpp", "stencil_mixed.hpp", "stencil_fp64.hpp",
-                   "stencil_bins.hip", "basis.hpp", "common.hpp"]
+                   "qr_kernel.hpp", "stencil_bins.hip", "basis.hpp", "common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stencils_c4.txt")
 
 

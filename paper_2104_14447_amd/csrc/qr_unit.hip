@@ -1,7 +1,7 @@
 // qr_unit.hip -- one instantiation of the FP64 QR stencil kernels.
 // Compiled once per (GMLS_DIM, GMLS_ORDER, GMLS_BASIS) by the build, each
 // object defining launch_qr_d<DIM>_o<ORDER>_b<BASIS>.
-#include "stencil_fp64.hpp"
+#include "qr_kernel.hpp"
 
 #if !defined(GMLS_DIM) || !defined(GMLS_ORDER) || !defined(GMLS_BASIS)
 #error "compile with -DGMLS_DIM=.. -DGMLS_ORDER=.. -DGMLS_BASIS=.."
