@@ -11,9 +11,7 @@ template <int DIM, int ORDER, int BASIS>
 constexpr int qr_lds_doubles() {
   constexpr int Q = num_mono(DIM, ORDER);
   if (BASIS != 1) return 2 * Q * Q + 8 * Q;
-  constexpr int QD = DivFreeTab<DIM, ORDER>::QD;
-  constexpr int KR = DIM * Q;
-  return Q * Q + QD * KR + 8 * QD + 8 * KR + QD;
+  return qr_divfree_lds_doubles<DIM, ORDER>();
 }
 
 // Persistent kernel: waves take targets from list[0 .. *count) in turn.

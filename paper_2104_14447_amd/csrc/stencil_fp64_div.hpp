@@ -2,12 +2,24 @@
 // stencil_fp64_div.hpp -- FP64 stencils of the divergence-free basis
 // (Section 2.2), one wavefront per target.
 //
-// With psi = (p (x) I_d) T the vector sample matrix is
-// (sqrt(W) P (x) I_d) T = (Q1 (x) I)(R (x) I) T, so its R factor is the R
-// factor of the small matrix K = (R (x) I_d) T (d*Q x Q_d), R from the
-// Householder QR of the scalar sample matrix; K is factored by Householder QR
-// in LDS and
-//   y = R_K^{-1} R_K^{-T} lambda,  u = T y,  alpha_{j,c} = w_j p(s_j) . u_c.
+// The divergence-free span is the kernel of the divergence map D on the
+// vector polynomials of degree <= m (coefficients c_(a,k) of p_a e_k; with
+// the eps-scaled Taylor monomials d/ds_k p_a = p_(a - e_k), so (D c)_b =
+// sum_k c_(b + e_k, k) for every monomial b of degree < m).  The weighted
+// least squares over that span is the vector fit with Gram I (x) G, G = P^T W P
+// (Section 2.1), under D c = 0, and for a functional l (scalar part lambda on
+// component comp)
+//     g_k = G^-1 (delta_(k,comp) lambda - D_k^T t),   S t = D G^-1 l,
+//     S = D (I (x) G^-1) D^T = sum_k D_k G^-1 D_k^T,
+// D_k the part of D acting on component k.  Everything is taken through the
+// Householder factor R of the scalar sample matrix sqrt(W) P (G = R^T R,
+// G^-1 = R^-1 R^-T):
+//   * R^-1 by back substitution, one column per lane;
+//   * S = B^T B with B = [R^-T D_0^T; ...; R^-T D_(d-1)^T] (d*Q x Q_m; column
+//     b of block k is column b + e_k of R^-T), factored by a second
+//     Householder QR, S = R_B^T R_B, so that neither G nor S is formed;
+//   * alpha_(j,k) = w_j p(s_j) . g_k.
+// The divergence functional of a divergence-free fit is identically zero.
 #include <float.h>
 #include <math.h>
 
@@ -16,124 +28,173 @@
 
 namespace gmls {
 
-// ---------------------------------------------------------------------------
-// divergence-free basis
-// ---------------------------------------------------------------------------
+// index of the monomial b + e_k (b of degree < ORDER), in the graded order of
+// Mono<DIM, ORDER> whose first num_mono(DIM, ORDER - 1) entries are the
+// monomials of degree < ORDER
+template <int DIM, int ORDER>
+struct DivUpIndex {
+  static constexpr int QM = num_mono(DIM, ORDER - 1);
+  int up[QM > 0 ? QM : 1][3];
+  constexpr DivUpIndex() : up{} {
+    Mono<DIM, ORDER> M{};
+    MonoIndex<DIM, ORDER> MI{};
+    for (int b = 0; b < QM; ++b)
+      for (int k = 0; k < 3; ++k)
+        up[b][k] = k < DIM ? MI.idx[M.e[b][0] + (k == 0)][M.e[b][1] + (k == 1)][M.e[b][2] + (k == 2)] : 0;
+  }
+};
+
+template <int DIM, int ORDER>
+constexpr int qr_divfree_lds_doubles() {
+  constexpr int Q = num_mono(DIM, ORDER);
+  constexpr int QM = num_mono(DIM, ORDER - 1);
+  // R, R^-1; R_B row- and column-major; three broadcast vectors; u per row
+  return 2 * Q * Q + 2 * QM * QM + 3 * 64 + 8 * DIM * Q;
+}
+
 template <int DIM, int ORDER, int RPL>
 __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
-  constexpr Mono<DIM, ORDER> MO{};
-  constexpr int Q = MO.N;
-  const DivFreeTab<DIM, ORDER> &DF = kDivFree<DIM, ORDER>;
-  constexpr int QD = DivFreeTab<DIM, ORDER>::QD;
-  constexpr int KR = DIM * Q;  // rows of K
+  constexpr int Q = num_mono(DIM, ORDER);
+  constexpr int QM = num_mono(DIM, ORDER - 1);
+  constexpr int KB = DIM * Q;            // rows of B
+  constexpr int KBL = (KB + 63) / 64;    // rows of B per lane
+  constexpr DivUpIndex<DIM, ORDER> DU{};
+  constexpr MonoIndex<DIM, ORDER> MI{};
   const int lane = lane_id();
   Rows<DIM, RPL> r;
   load_rows<DIM, RPL>(a, t, r, lane);
-  double M[RPL][Q];
-#pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    double p[Q];
-    scaled_basis<DIM, ORDER, double>(r.s[i], p);
-    const double sw = sqrt(r.w[i]);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q];
-  }
   double rdiag;
-  wave_householder<Q, RPL>(M, rdiag, lane);
+  {
+    double M[RPL][Q];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      double p[Q];
+      scaled_basis<DIM, ORDER, double>(r.s[i], p);
+      const double sw = sqrt(r.w[i]);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q];
+    }
+    wave_householder<Q, RPL>(M, rdiag, lane);
+    if (lane < Q) {
+#pragma unroll
+      for (int l = 0; l < Q; ++l) lds[lane * Q + l] = l >= lane ? M[0][l] : 0.0;
+    }
+  }
   const int F = a.F;
-  // scalar R in LDS (row-major), then K = (R (x) I) T column-major [QD][KR]
-  double *Rs = lds;              // Q*Q
-  double *K = lds + Q * Q;       // QD*KR
-  double *Y = K + QD * KR;       // F*QD (y), then F*KR (u = T y)
-  double *U = Y + 8 * QD;
-  if (lane < Q) {
-#pragma unroll
-    for (int l = 0; l < Q; ++l) Rs[lane * Q + l] = l >= lane ? M[0][l] : 0.0;
-  }
+  double *Rs = lds;                 // R, row-major
+  double *Ri = Rs + Q * Q;          // R^-1, row-major (upper triangular)
+  double *RBm = Ri + Q * Q;         // R_B, row-major
+  double *RBt = RBm + QM * QM;      // R_B, column-major
+  double *V0 = RBt + QM * QM;       // broadcast vectors
+  double *V1 = V0 + 64, *V2 = V1 + 64;
+  double *U = V2 + 64;              // [f][q * DIM + k]: g_k of row f
+  const double rmax = uniform_d(wave_max(lane < Q ? fabs(rdiag) : 0.0));
+  const double rmin = uniform_d(wave_min(lane < Q ? fabs(rdiag) : DBL_MAX));
+  bool deficient = !(rmin > kRankTol * rmax);
   __syncthreads();
-  // K[(alpha, c), i] = sum_beta R[alpha][beta] T[(beta, c), i]; T has at most
-  // two nonzeros per column: (ia, ca, va) and (ib, cb, vb)
-  for (int e = lane; e < QD * KR; e += 64) {
-    const int i = e / KR, row = e - i * KR;
-    const int al = row / DIM, c = row - al * DIM;
-    double v = 0.0;
-    const int ia = DF.ia[i], ib = DF.ib[i];
-    if (DF.ca[i] == c) v += DF.va[i] * Rs[al * Q + ia];
-    if (ib >= 0 && DF.cb[i] == c) v += DF.vb[i] * Rs[al * Q + ib];
-    K[e] = v;
-  }
-  __syncthreads();
-  // Householder QR of K (KR x QD, column-major) in LDS, rows across lanes:
-  // lane l owns rows l + 64 q of every column, so a column update touches
-  // only the lane's own entries; the dot products of the reflector with the
-  // later columns are taken CH at a time and summed over the wavefront by
-  // DPP (independent chains, no LDS traffic)
-  constexpr int KRL = (KR + 63) / 64;
-  constexpr int CH = 8;
-  double *Kd = U + 8 * KR;  // QD diagonal entries of R_K
-  for (int k = 0; k < QD; ++k) {
-    double xs[KRL];
-    double part = 0.0;
+  // R^-1, column `lane`: R x = e_lane by back substitution (rows above the
+  // diagonal only); every lane walks the same rows, so the reads of R are
+  // broadcasts
+  if (!readfirstlane_i(deficient ? 1 : 0)) {
+    double x[Q];
 #pragma unroll
-    for (int q = 0; q < KRL; ++q) {
-      const int row = lane + 64 * q;
-      xs[q] = (row >= k && row < KR) ? K[k * KR + row] : 0.0;
-      part += xs[q] * xs[q];
+    for (int i = Q - 1; i >= 0; --i) {
+      double acc = i == lane ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = i + 1; l < Q; ++l) acc -= Rs[i * Q + l] * x[l];
+      x[i] = i <= lane ? acc / Rs[i * Q + i] : 0.0;
     }
-    const double sigma = wave_sum_uniform(part);
-    const double xk = uniform_d(K[k * KR + k]);
-    double beta = 0.0;
-    if (sigma > 0.0) {
-      const double norm = sqrt(sigma);
-      beta = xk >= 0.0 ? -norm : norm;
-      const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
-      double v[KRL];
+    if (lane < Q)
 #pragma unroll
-      for (int q = 0; q < KRL; ++q) {
-        const int row = lane + 64 * q;
-        v[q] = row == k ? xk - beta : xs[q];
+      for (int i = 0; i < Q; ++i) Ri[i * Q + lane] = x[i];
+    __syncthreads();
+    // B, rows rho = k Q + a on lane rho % 64: B[rho][b] = R^-T[a][b + e_k] = R^-1[b + e_k][a]
+    double MB[KBL][QM];
+#pragma unroll
+    for (int s = 0; s < KBL; ++s) {
+      const int rho = lane + 64 * s;
+      const int k = rho / Q, ar = rho - k * Q;
+#pragma unroll
+      for (int b = 0; b < QM; ++b) {
+        const int u = k == 0 ? DU.up[b][0] : k == 1 ? DU.up[b][1] : DU.up[b][2];
+        MB[s][b] = rho < KB ? Ri[u * Q + ar] : 0.0;
       }
-      for (int l0 = k + 1; l0 < QD; l0 += CH) {
-        double kv[CH][KRL], dp[CH];
+    }
+    double rdb;
+    wave_householder<QM, KBL>(MB, rdb, lane);
+    const double bmax = uniform_d(wave_max(lane < QM ? fabs(rdb) : 0.0));
+    const double bmin = uniform_d(wave_min(lane < QM ? fabs(rdb) : DBL_MAX));
+    deficient = !(bmin > kRankTol * bmax);
+    if (lane < QM) {
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          dp[u] = 0.0;
-#pragma unroll
-          for (int q = 0; q < KRL; ++q) {
-            const int row = lane + 64 * q;
-            kv[u][q] = (l0 + u < QD && row >= k && row < KR) ? K[(l0 + u) * KR + row] : 0.0;
-            dp[u] += v[q] * kv[u][q];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < CH; ++u) dp[u] = wave_sum_uniform(dp[u]);
-#pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const double coef = 2.0 * dp[u] * inv_vtv;
-#pragma unroll
-          for (int q = 0; q < KRL; ++q) {
-            const int row = lane + 64 * q;
-            if (l0 + u < QD && row >= k && row < KR) K[(l0 + u) * KR + row] = kv[u][q] - coef * v[q];
-          }
-        }
+      for (int l = 0; l < QM; ++l) {
+        const double v = l >= lane ? MB[0][l] : 0.0;
+        RBm[lane * QM + l] = v;
+        RBt[l * QM + lane] = v;
       }
     }
     __syncthreads();
-    if (lane == 0) {
-      K[k * KR + k] = beta;
-      Kd[k] = beta;
+    if (!readfirstlane_i(deficient ? 1 : 0)) {
+      const double ie = 1.0 / uniform_d(a.eps[t]);
+      const int li = lane < Q ? lane : 0;  // keeps the lane's row reads in bounds
+      for (int f = 0; f < F; ++f) {
+        const int kind = rk.kind[f], comp = rk.comp[f];
+        if (kind == FK_DIV) {
+          if (lane < Q)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) U[f * KB + lane * DIM + k] = 0.0;
+          continue;
+        }
+        // w1 = R^-T lambda over the nonzeros of lambda (value: monomial 0;
+        // Laplacian: the pure squares, 1/eps^2 each)
+        double w1 = 0.0;
+        if (kind == FK_VALUE) {
+          w1 = Ri[0 * Q + li];
+        } else if constexpr (ORDER >= 2) {
+          w1 = Ri[MI.idx[2][0][0] * Q + li] + Ri[MI.idx[0][2][0] * Q + li];
+          if constexpr (DIM == 3) w1 += Ri[MI.idx[0][0][2] * Q + li];
+          w1 *= ie * ie;
+        }
+        V0[lane] = lane < Q ? w1 : 0.0;
+        __syncthreads();
+        // v = R^-1 w1 = G^-1 lambda
+        double v = 0.0;
+#pragma unroll
+        for (int l = 0; l < Q; ++l) v += Ri[li * Q + l] * V0[l];
+        if (lane >= Q) v = 0.0;
+        V1[lane] = v;
+        __syncthreads();
+        // r_b = v_(b + e_comp); t = S^-1 r = R_B^-1 R_B^-T r
+        double rb = 0.0;
+        if (lane < QM) {
+          int u = 0;
+#pragma unroll
+          for (int b = 0; b < QM; ++b)
+            if (lane == b) u = comp == 0 ? DU.up[b][0] : comp == 1 ? DU.up[b][1] : DU.up[b][2];
+          rb = V1[u];
+        }
+        const double tb = tri_solve_rtr<QM>(RBm, RBt, rb, rdb, lane);
+        V2[lane] = lane < QM ? tb : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          // y = G^-1 D_k^T t = R^-1 (R^-T D_k^T t); (R^-T D_k^T t)_i = sum_b R^-1[b + e_k][i] t_b
+          double w2 = 0.0;
+#pragma unroll
+          for (int b = 0; b < QM; ++b) w2 += Ri[DU.up[b][k] * Q + li] * V2[b];
+          V0[lane] = lane < Q ? w2 : 0.0;
+          __syncthreads();
+          double y = 0.0;
+#pragma unroll
+          for (int l = 0; l < Q; ++l) y += Ri[li * Q + l] * V0[l];
+          if (lane < Q) U[f * KB + lane * DIM + k] = (k == comp ? v : 0.0) - y;
+          __syncthreads();
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // rank test on both factors
-  double dmax = 0.0, dmin = DBL_MAX;
-  for (int k = lane; k < QD; k += 64) {
-    dmax = fmax(dmax, fabs(Kd[k]));
-    dmin = fmin(dmin, fabs(Kd[k]));
-  }
-  dmax = uniform_d(wave_max(dmax));
-  dmin = uniform_d(wave_min(dmin));
-  if (readfirstlane_i(!(dmin > kRankTol * dmax) ? 1 : 0)) {
+  if (readfirstlane_i(deficient ? 1 : 0)) {
     for (int i = 0; i < RPL; ++i) {
       const int j = lane + 64 * i;
       if (j < r.N)
@@ -145,68 +206,6 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
     __syncthreads();
     return;
   }
-  const double ie = 1.0 / uniform_d(a.eps[t]);
-  // y = R_K^{-1} R_K^{-T} lambda for every row at once; R_K[k][l] = K[l*KR + k].
-  // lambda_i = functional on psi_i: value c -> T[(0,c),i]; Laplacian c ->
-  // eps^-2 sum_d T[(2e_d,c),i]; divergence -> 0 (a divergence-free fit)
-  for (int f = 0; f < F; ++f) {
-    const int kind = rk.kind[f], comp = rk.comp[f];
-    for (int i = lane; i < QD; i += 64)
-      Y[f * QD + i] = kind == FK_DIV ? 0.0 : divfree_lambda<DIM, ORDER>(i, kind, comp, ie);
-  }
-  // forward R_K^T z = lambda, then back R_K y = z: one pivot per step for all
-  // rows, one barrier per step (the pivot's entry was last written by the
-  // lane that owns it in the step before)
-  for (int k = 0; k < QD; ++k) {
-    __syncthreads();
-    const double id = 1.0 / uniform_d(Kd[k]);
-    double zk[8];
-#pragma unroll
-    for (int f = 0; f < 8; ++f) zk[f] = f < F ? uniform_d(Y[f * QD + k]) * id : 0.0;
-    if (lane == 0)
-#pragma unroll
-      for (int f = 0; f < 8; ++f)
-        if (f < F) Y[f * QD + k] = zk[f];
-    for (int l = k + 1 + lane; l < QD; l += 64) {
-      const double rkl = K[l * KR + k];
-#pragma unroll
-      for (int f = 0; f < 8; ++f)
-        if (f < F) Y[f * QD + l] -= rkl * zk[f];
-    }
-  }
-  for (int k = QD - 1; k >= 0; --k) {
-    __syncthreads();
-    const double id = 1.0 / uniform_d(Kd[k]);
-    double yk[8];
-#pragma unroll
-    for (int f = 0; f < 8; ++f) yk[f] = f < F ? uniform_d(Y[f * QD + k]) * id : 0.0;
-    if (lane == 0)
-#pragma unroll
-      for (int f = 0; f < 8; ++f)
-        if (f < F) Y[f * QD + k] = yk[f];
-    for (int l = lane; l < k; l += 64) {
-      const double rlk = K[k * KR + l];
-#pragma unroll
-      for (int f = 0; f < 8; ++f)
-        if (f < F) Y[f * QD + l] -= rlk * yk[f];
-    }
-  }
-  __syncthreads();
-  // u = T y (KR entries per row): the first entries (ia, ca) of the columns
-  // are distinct, so they are stored in parallel; the second entries
-  // (ib, 0) of columns with the same ca are distinct too, so they are added
-  // one component ca at a time (a fixed order: reproducible)
-  for (int e = lane; e < F * KR; e += 64) U[e] = 0.0;
-  __syncthreads();
-  for (int i = lane; i < QD; i += 64)
-    for (int f = 0; f < F; ++f) U[f * KR + DF.ia[i] * DIM + DF.ca[i]] = DF.va[i] * Y[f * QD + i];
-  __syncthreads();
-  for (int c = 1; c < DIM; ++c) {
-    for (int i = lane; i < QD; i += 64)
-      if (DF.ca[i] == c && DF.ib[i] >= 0)
-        for (int f = 0; f < F; ++f) U[f * KR + DF.ib[i] * DIM + DF.cb[i]] += DF.vb[i] * Y[f * QD + i];
-    __syncthreads();
-  }
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int j = lane + 64 * i;
@@ -217,7 +216,7 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
         for (int c = 0; c < DIM; ++c) {
           double acc = 0.0;
 #pragma unroll
-          for (int q = 0; q < Q; ++q) acc += p[q] * U[f * KR + q * DIM + c];
+          for (int q = 0; q < Q; ++q) acc += p[q] * U[f * KB + q * DIM + c];
           a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = r.w[i] * acc;
         }
     }
