@@ -23,7 +23,6 @@
 #include <float.h>
 #include <math.h>
 
-#include "divfree.hpp"
 #include "stencil_fp64.hpp"
 
 namespace gmls {
