@@ -313,6 +313,11 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
   a.normals = normals;
   a.hweights = hweights;
   a.skip_const = stag ? 1 : 0;
+  if (basis == GMLS_BASIS_DIVFREE) {  // queue of targets whose scalar basis is not unisolvent
+    a.aux_list = (int *)ctx->ws(WS_AUX_LIST, sizeof(int) * (size_t)n);
+    if (!a.aux_list) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+    a.aux_count = &meta->aux_count;  // cleared with the bin table
+  }
 
   const bool sync = !opt.capture_safe;  // capture-safe: nothing below waits for the device
   if (!sync && report)
@@ -380,11 +385,13 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
     }
   }
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
+  StencilArgs af = a;
   if (prec == GMLS_PREC_MIXED) {
-    StencilArgs af = a;
     af.ok_status = -1;  // keep the fallback/not-converged status set by the mixed kernel
     GMLS_HIP(launch_qr_fallback(dim, order, basis, af, fb, meta, 4, cus * 8, s));
   }
+  if (basis == GMLS_BASIS_DIVFREE)  // the queue is usually empty: a small persistent grid
+    GMLS_HIP(launch_qr_kmat(dim, order, af, a.aux_list, &meta->aux_count, &meta->aux_cursor, 64, s));
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[3], s));
   if (!report) return GMLS_OK;
 

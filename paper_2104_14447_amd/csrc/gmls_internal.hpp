@@ -47,6 +47,7 @@ enum Slot {
   WS_STOKES_TMP,
   WS_STOKES_FLAG,
   WS_SPMV_LONG,
+  WS_AUX_LIST,
   WS_NUM_SLOTS
 };
 
@@ -130,6 +131,8 @@ struct BinMeta {
   int fb_cursor;   // fallback work counter
   int err;         // nonzero: a row longer than the compiled maximum
   int pad;
+  int aux_count;   // divergence-free targets queued for the factorisation of
+  int aux_cursor;  // their own sample matrix (scalar basis not unisolvent)
 };
 
 // Per-call statistics accumulated on the device (mixed path).
@@ -168,6 +171,10 @@ struct StencilArgs {
   // staggered stencils on the mixed pipeline: the constant monomial is not a
   // column, and hweights receives the target weight -sum_j alpha_j
   int skip_const = 0;
+  // divergence-free FP64 kernel: targets whose scalar basis is not unisolvent
+  // go to aux_list[atomicAdd(aux_count, 1)] (null: they are rank deficient)
+  int *aux_list = nullptr;
+  int *aux_count = nullptr;
 };
 
 // Per-bin stencil launches; `bin` selects the rows-per-lane instantiation.
@@ -191,6 +198,9 @@ hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a
 hipError_t launch_mixed_wave(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt, int n_max,
                              int cus, hipStream_t s);
+// the queued divergence-free targets of aux_list[0 .. *count)
+hipError_t launch_qr_kmat(int dim, int order, const StencilArgs &a, const int *list, const int *count,
+                          int *cursor, int n_blocks, hipStream_t s);
 bool qr_supported(int dim, int order, int basis);
 bool mixed_supported(int dim, int order, int basis);
 // the scheme a request resolves to (MIXED_AUTO picks the fastest compiled

@@ -2,6 +2,7 @@
 // Compiled once per (GMLS_DIM, GMLS_ORDER, GMLS_BASIS) by the build, each
 // object defining launch_qr_d<DIM>_o<ORDER>_b<BASIS>.
 #include "qr_kernel.hpp"
+#include "stencil_fp64_kmat.hpp"
 
 #if !defined(GMLS_DIM) || !defined(GMLS_ORDER) || !defined(GMLS_BASIS)
 #error "compile with -DGMLS_DIM=.. -DGMLS_ORDER=.. -DGMLS_BASIS=.."
@@ -10,6 +11,7 @@
 #define GMLS_CAT2(a, b, c, d, e, f) a##b##c##d##e##f
 #define GMLS_CAT(a, b, c, d, e, f) GMLS_CAT2(a, b, c, d, e, f)
 #define GMLS_FN GMLS_CAT(launch_qr_d, GMLS_DIM, _o, GMLS_ORDER, _b, GMLS_BASIS)
+#define GMLS_KMAT_FN GMLS_CAT(launch_qr_kmat_d, GMLS_DIM, _o, GMLS_ORDER, , )
 
 namespace gmls {
 
@@ -25,5 +27,14 @@ hipError_t GMLS_FN(int rpl, const StencilArgs &a, const int *list, const int *co
   }
   return hipGetLastError();
 }
+
+#if GMLS_BASIS == 1
+// queued divergence-free targets (any row count up to 256: four rows per lane)
+hipError_t GMLS_KMAT_FN(const StencilArgs &a, const int *list, const int *count, int *cursor, int n_blocks,
+                        hipStream_t s) {
+  k_qr_kmat<GMLS_DIM, GMLS_ORDER, 4><<<n_blocks, 64, 0, s>>>(a, list, count, cursor);
+  return hipGetLastError();
+}
+#endif
 
 }  // namespace gmls

@@ -54,6 +54,26 @@ hipError_t launch_qr_d3_o3_b2(int, const StencilArgs &, const int *, const int *
 hipError_t launch_qr_d3_o4_b2(int, const StencilArgs &, const int *, const int *, const int *, int *, int,
                                hipStream_t);
 
+hipError_t launch_qr_kmat_d2_o1(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+hipError_t launch_qr_kmat_d2_o2(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+hipError_t launch_qr_kmat_d2_o3(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+hipError_t launch_qr_kmat_d2_o4(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+hipError_t launch_qr_kmat_d3_o1(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+hipError_t launch_qr_kmat_d3_o2(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+hipError_t launch_qr_kmat_d3_o3(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+hipError_t launch_qr_kmat_d3_o4(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+
+using KmatFn = hipError_t (*)(const StencilArgs &, const int *, const int *, int *, int, hipStream_t);
+static const KmatFn kKmat[2][4] = {
+    {launch_qr_kmat_d2_o1, launch_qr_kmat_d2_o2, launch_qr_kmat_d2_o3, launch_qr_kmat_d2_o4},
+    {launch_qr_kmat_d3_o1, launch_qr_kmat_d3_o2, launch_qr_kmat_d3_o3, launch_qr_kmat_d3_o4}};
+
+hipError_t launch_qr_kmat(int dim, int order, const StencilArgs &a, const int *list, const int *count, int *cursor,
+                          int n_blocks, hipStream_t s) {
+  if (!qr_supported(dim, order, 1)) return hipErrorInvalidValue;
+  return kKmat[dim - 2][order - 1](a, list, count, cursor, n_blocks, s);
+}
+
 using QrFn = hipError_t (*)(int, const StencilArgs &, const int *, const int *, const int *, int *, int, hipStream_t);
 // [dim - 2][order - 1][basis]: basis 0 scalar, 1 divergence-free, 2 staggered
 static const QrFn kQr[2][4][3] = {

@@ -20,6 +20,7 @@
 //     Householder QR, S = R_B^T R_B, so that neither G nor S is formed;
 //   * alpha_(j,k) = w_j p(s_j) . g_k.
 // The divergence functional of a divergence-free fit is identically zero.
+// Targets whose R is rank deficient are queued for stencil_fp64_kmat.hpp.
 #include <float.h>
 #include <math.h>
 
@@ -90,6 +91,14 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
   const double rmax = uniform_d(wave_max(lane < Q ? fabs(rdiag) : 0.0));
   const double rmin = uniform_d(wave_min(lane < Q ? fabs(rdiag) : DBL_MAX));
   bool deficient = !(rmin > kRankTol * rmax);
+  if (readfirstlane_i(deficient ? 1 : 0) && a.aux_list) {
+    // the scalar basis is not unisolvent on these neighbours, which does not
+    // make the divergence-free fit singular: queue the target for the kernel
+    // that factors the divergence-free sample matrix itself
+    if (lane == 0) a.aux_list[atomicAdd(a.aux_count, 1)] = t;
+    __syncthreads();
+    return;
+  }
   __syncthreads();
   // R^-1, column `lane`: R x = e_lane by back substitution (rows above the
   // diagonal only); every lane walks the same rows, so the reads of R are

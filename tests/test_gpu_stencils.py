@@ -25,6 +25,11 @@ CASES = {
     "3d_divfree_m2": (lambda: W.jittered_grid(8000, 3, 1003), ("knn", 60), "divfree", 2, 1 | 4 | 8, 4),
     "2d_divfree_m2": (lambda: W.jittered_grid(3000, 2, 7), ("knn", 20), "divfree", 2, 1 | 4 | 8, 4),
     "3d_divfree_m4": (lambda: W.jittered_grid(8000, 3, 1005), ("knn", 170), "divfree", 4, 4 | 8, 6),
+    # fewer neighbours than scalar monomials (9 < 10, 30 < 35) but enough
+    # rows for the divergence-free functions (27 >= 26, 90 >= 85): the
+    # divergence-free sample matrix is factored itself
+    "3d_divfree_m2_k9": (lambda: W.jittered_grid(3000, 3, 11), ("knn", 9), "divfree", 2, 1 | 4 | 8, 4),
+    "3d_divfree_m4_k30": (lambda: W.jittered_grid(3000, 3, 12), ("knn", 30), "divfree", 4, 4 | 8, 6),
 }
 
 _cache = {}
