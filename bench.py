@@ -362,15 +362,26 @@ def main():
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
+    # a scalar and a divergence-free basis of one order on the same neighbour
+    # lists go through one gmls_stencils_multi call (the library shares their
+    # Gram where the scheme allows)
+    shared = len(bases) == 2 and sorted(b["name"] for b in bases) == ["divfree", "scalar"] and \
+        bases[0]["order"] == bases[1]["order"]
+
+    def all_stencils(c, eps_, rp_, col_, wkey, stkey, auxkey, report=False):
+        if shared:
+            outs = [(bs[wkey], bs[stkey]) for bs in bases]
+            return [G.gmls_stencils_multi(c, x, xt, bases[0]["order"], p, eps_, rp_, col_,
+                                          [(bs["b"], bs["mask"]) for bs in bases], prec=prec, outputs=outs,
+                                          report=report)[1]]
+        return [stencils(c, bs, eps_, rp_, col_, weights=bs[wkey], status=bs[stkey], aux=bs[auxkey],
+                         report=report)[3] for bs in bases]
+
     def step(report=False):
         ev0.record()
         rp_, col_, eps_ = G.gmls_neighbors(ctx, x, xt, col=col_buf, **spec)
         ev1.record()
-        reps = []
-        for bs in bases:
-            r_ = stencils(ctx, bs, eps_, rp_, col_, weights=bs["w"], status=bs["st"], aux=bs["aux"],
-                          report=report)[3]
-            reps.append(r_)
+        reps = all_stencils(ctx, eps_, rp_, col_, "w", "st", "aux", report=report)
         return rp_, col_, eps_, reps
 
     # ---- eager steps: per-phase GPU times (HIP events on the library's stream) ----
@@ -406,6 +417,9 @@ def main():
             rpw, colw, epsw = G.gmls_neighbors(gctx, x, xt, **spec)
             for bs in bases:
                 stencils(gctx, bs, epsw, rpw, colw)
+            if shared:
+                G.gmls_stencils_multi(gctx, x, xt, bases[0]["order"], p, epsw, rpw, colw,
+                                      [(bs["b"], bs["mask"]) for bs in bases], prec=prec)
             gcol = torch.empty(nnz + 1024, dtype=torch.int32, device=dev)
             for bs in bases:
                 bs["gw"] = torch.empty(bs["F"] * bs["C"] * nnz, dtype=torch.float64, device=dev)
@@ -416,8 +430,7 @@ def main():
 
             def gstep():
                 rp_, col_, eps_ = G.gmls_neighbors(gctx, x, xt, col=gcol, **spec)
-                for bs in bases:
-                    stencils(gctx, bs, eps_, rp_, col_[:nnz], weights=bs["gw"], status=bs["gst"], aux=bs["gaux"])
+                all_stencils(gctx, eps_, rp_, col_[:nnz], "gw", "gst", "gaux")
                 gout["rp"], gout["eps"] = rp_, eps_
 
             gstep()  # capture-safe eager run (no allocation happens in the capture)
@@ -579,6 +592,7 @@ def main():
                    "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
                                     "pipeline", "wavefront per target"][args.scheme],
                    "autotune": tune_summary,
+                   "bases_call": "gmls_stencils_multi (one call for both bases)" if shared else "gmls_stencils per basis",
                    "parity_gate": gate, "parity_max_rel_err": max_err, "parity_sample": int(n_sample),
                    "timed_unit": "HIP graph replay of search + stencils" if graph else "eager calls",
                    "ms_per_step_eager": round(ms_eager, 4),

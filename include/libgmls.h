@@ -336,6 +336,39 @@ gmls_status gmls_stencils_constrained(gmls_ctx ctx, const double *coords, int64_
 gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, const int32_t *col,
                        const double *weights, int F, int C_in, const double *field, double *out);
 
+/* Several stencil sets on the same neighbour lists and order: the scalar
+ * Gram G = P^T W P of the weighted Taylor basis (Section 2.1) depends only on
+ * the neighbours, eps and the weight, and the divergence-free fit of
+ * Section 2.2 is the vector fit with Gram I (x) G under the constraint
+ * D c = 0, so a scalar set and a divergence-free set can share it.  The
+ * result of each set is that of gmls_stencils with the same arguments (bit
+ * for bit where nothing is shared, within the precision's gate otherwise).
+ * Shared: with prec = GMLS_PREC_MIXED, exactly one scalar and one
+ * divergence-free set, and the wavefront scheme (GMLS_OPT_MIXED_SCHEME 4, or
+ * automatic where it resolves to 4 for both: order 4 in 3D), one kernel forms
+ * the moments and the swept Gram of a target once for both sets.  Other
+ * combinations run the sets in turn.
+ *   sets, n_sets  host array of 1..8 sets: basis (GMLS_BASIS_SCALAR or
+ *                 GMLS_BASIS_DIVFREE), functional_mask, weights (device,
+ *                 F*C_in*nnz doubles, layout of gmls_stencils) and
+ *                 target_status (device uint8[n_tgt], nullable)
+ *   report        host, nullable: the times of the whole call and the counts
+ *                 of one set (the scalar set where the Gram is shared, else
+ *                 sets[0]); synchronises
+ * Errors: those of gmls_stencils for any set; GMLS_ERR_ARG for n_sets outside
+ * 1..8 or a null sets array. */
+typedef struct {
+  int32_t basis;
+  uint32_t functional_mask;
+  double *weights;
+  uint8_t *target_status;
+} gmls_stencil_set;
+
+gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                int64_t n_tgt, int dim, int order, int weight_p, const double *eps,
+                                const int64_t *row_ptr, const int32_t *col, int prec, int n_sets,
+                                const gmls_stencil_set *sets, gmls_report *report);
+
 /* ---------------------------------------------------------------------------
  * Autotuner of the mixed pipeline (GMLS_OPT_MIXED_SCHEME 3, or the automatic
  * choice where it resolves to 3).  The pipeline's two row-parallel kernels,

@@ -26,6 +26,7 @@ __all__ = [
     "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "OPT_ROW_ORDER", "ROW_ORDER_CELL",
     "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE", "SCHEME_WAVE",
     "OPT_PIPE_SHAPE", "TuneResult", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
+    "StencilSet", "gmls_stencils_multi",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -46,7 +47,7 @@ _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY
 EXPORTED_SYMBOLS = ("gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
                     "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained", "gmls_stencils_staggered",
                     "gmls_assemble_stokes", "gmls_spmv", "gmls_apply", "gmls_check", "gmls_autotune",
-                    "gmls_autotune_save", "gmls_autotune_load")
+                    "gmls_autotune_save", "gmls_autotune_load", "gmls_stencils_multi")
 
 
 class GmlsError(RuntimeError):
@@ -58,6 +59,11 @@ class GmlsError(RuntimeError):
 class SearchSpec(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("k", ctypes.c_int32), ("eps_mult", ctypes.c_double),
                 ("radius", ctypes.c_double), ("k_min", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class StencilSet(ctypes.Structure):
+    _fields_ = [("basis", ctypes.c_int32), ("functional_mask", ctypes.c_uint32), ("weights", ctypes.c_void_p),
+                ("target_status", ctypes.c_void_p)]
 
 
 class TuneResult(ctypes.Structure):
@@ -150,6 +156,10 @@ def load_library():
     L.gmls_autotune.argtypes = [_vp, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
                                 ctypes.c_int, _vp, _vp, _vp, ctypes.c_int, _vp, _vp, ctypes.POINTER(TuneResult)]
     L.gmls_autotune.restype = ctypes.c_int
+    L.gmls_stencils_multi.argtypes = [_vp, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, _vp,
+                                      _vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(StencilSet),
+                                      ctypes.POINTER(Report)]
+    L.gmls_stencils_multi.restype = ctypes.c_int
     L.gmls_autotune_save.argtypes = [_vp, ctypes.c_char_p]
     L.gmls_autotune_save.restype = ctypes.c_int
     L.gmls_autotune_load.argtypes = [_vp, ctypes.c_char_p]
@@ -281,6 +291,36 @@ def gmls_stencils(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, ord
     if st not in (GMLS_OK, GMLS_WARN_TARGET_FLAGS):
         ctx._raise(st)
     return weights[: F * C * nnz], status[:n_tgt], (rep.as_dict() if report else None)
+
+
+def gmls_stencils_multi(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, order: int, weight_p: int,
+                        eps: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor, sets, prec: int = PREC_FP64,
+                        outputs=None, report: bool = False):
+    """Several (basis, functional mask) sets on the same neighbour lists.
+    `sets` is a list of (basis, mask); `outputs` an optional list of
+    (weights, status) tensors.  Returns ([(weights, status), ...], report)."""
+    _check_dev(coords, targets, eps, row_ptr, col)
+    n_src, dim = coords.shape
+    n_tgt = targets.shape[0]
+    nnz = col.numel()
+    arr = (StencilSet * len(sets))()
+    outs = []
+    for k, (basis, mask) in enumerate(sets):
+        F, C, _ = gmls_stencil_shape(dim, order, basis, mask)
+        if outputs is not None:
+            w, stt = outputs[k]
+        else:
+            w = torch.empty(max(F * C * nnz, 1), dtype=torch.float64, device=coords.device)
+            stt = torch.empty(max(n_tgt, 1), dtype=torch.uint8, device=coords.device)
+        arr[k] = StencilSet(basis, mask, _ptr(w).value, _ptr(stt).value)
+        outs.append((w[: F * C * nnz], stt[:n_tgt]))
+    rep = Report()
+    st = load_library().gmls_stencils_multi(ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, order,
+                                            weight_p, _ptr(eps), _ptr(row_ptr), _ptr(col), prec, len(sets), arr,
+                                            ctypes.byref(rep) if report else None)
+    if st not in (GMLS_OK, GMLS_WARN_TARGET_FLAGS):
+        ctx._raise(st)
+    return outs, (rep.as_dict() if report else None)
 
 
 def gmls_autotune(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, order: int, basis: int, mask: int,

@@ -418,6 +418,124 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
   return hm.count[0] > 0 ? GMLS_WARN_TARGET_FLAGS : GMLS_OK;
 }
 
+// A scalar set (ss) and a divergence-free set (sv) on the same neighbour
+// lists, mixed precision, wavefront scheme: one kernel forms the moments and
+// the swept Gram of each target once for both.  Bins follow the scalar basis
+// (bin 0: N < Q_s); the divergence-free set's bin-0 targets, which its own
+// call would have handled through the FP64 kernel's queue, go to that kernel
+// directly.
+static gmls_status run_shared_wave(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                   int64_t n_tgt, int dim, int order, int weight_p, const double *eps,
+                                   const int64_t *row_ptr, const int32_t *col, const gmls_stencil_set &ss,
+                                   const gmls_stencil_set &sv, gmls_report *report) {
+  int Fs = 0, Cs = 0, Qs = 0, Fv = 0, Cv = 0, Qv = 0;
+  gmls_status st = gmls_stencil_shape(dim, order, GMLS_BASIS_SCALAR, ss.functional_mask, &Fs, &Cs, &Qs);
+  if (st == GMLS_OK) st = gmls_stencil_shape(dim, order, GMLS_BASIS_DIVFREE, sv.functional_mask, &Fv, &Cv, &Qv);
+  if (st != GMLS_OK) return gmls_set_error(ctx, st, "functional/basis combination not supported or bad shape");
+  if (weight_p < 1 || weight_p > 12) return gmls_set_error(ctx, GMLS_ERR_ARG, "weight power must be 1..12");
+  if (n_src < 1 || n_tgt < 0 || n_tgt > (1ll << 31) - 1)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "n_src must be >= 1 and n_tgt in [0, 2^31)");
+  if (n_tgt > 0 && (!coords || !targets || !eps || !row_ptr || !col || !ss.weights || !sv.weights))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  if (report) memset(report, 0, sizeof(*report));
+  if (n_tgt == 0) return GMLS_OK;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = ctx->stream;
+  const int n = (int)n_tgt;
+  Options opt = ctx->opt;
+  opt.scheme = MIXED_WAVE;
+  BinMeta *meta = (BinMeta *)ctx->ws(WS_BIN_META, sizeof(BinMeta));
+  int *list = (int *)ctx->ws(WS_BIN_LIST, sizeof(int) * (size_t)n);
+  int *fbs = (int *)ctx->ws(WS_FALLBACK, sizeof(int) * (size_t)n);
+  int *fbv = (int *)ctx->ws(WS_FALLBACK2, sizeof(int) * (size_t)n);
+  int *aux = (int *)ctx->ws(WS_AUX_LIST, sizeof(int) * (size_t)n);
+  Stats *stats = (Stats *)ctx->ws(WS_STATS, sizeof(Stats));
+  uint8_t *sts = ss.target_status ? ss.target_status : (uint8_t *)ctx->ws(WS_STATUS_TMP, (size_t)n);
+  uint8_t *stv = sv.target_status ? sv.target_status : (uint8_t *)ctx->ws(WS_STATUS_TMP2, (size_t)n);
+  if (!meta || !list || !fbs || !fbv || !aux || !stats || !sts || !stv)
+    return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+  StencilArgs as;
+  as.coords = coords;
+  as.targets = targets;
+  as.eps = eps;
+  as.row_ptr = row_ptr;
+  as.col = col;
+  as.weights = ss.weights;
+  as.status = sts;
+  as.mask = ss.functional_mask;
+  as.F = Fs;
+  as.p = weight_p;
+  as.n_tgt = n;
+  as.ok_status = GMLS_TARGET_OK;
+  StencilArgs av = as;
+  av.weights = sv.weights;
+  av.status = stv;
+  av.mask = sv.functional_mask;
+  av.F = Fv;
+  av.aux_list = aux;
+  av.aux_count = &meta->aux_count;
+
+  const bool sync = !opt.capture_safe;
+  if (!sync && report)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "a report synchronises: pass NULL in capture-safe mode");
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[0], s));
+  const size_t bin_bytes = binning_temp_bytes(n);
+  void *bin_tmp = ctx->ws(WS_BIN_TEMP, bin_bytes);
+  if (!bin_tmp) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+  GMLS_HIP(launch_binning(row_ptr, targets, n, dim, Qs, 1, meta, list, bin_tmp, bin_bytes, s));
+  BinMeta hm;
+  if (sync) {
+    GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
+    GMLS_HIP(hipStreamSynchronize(s));
+    if (hm.err) return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 256 neighbours");
+  } else {
+    GMLS_HIP(or_error_bit((int *)ctx->ws(WS_DEV_ERR, sizeof(int)), &meta->err, 1, DEV_ERR_STENCIL_ROWS, s));
+  }
+  GMLS_HIP(fill_zero(stats, sizeof(Stats), s));
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[1], s));
+  // the FP64 kernels' targets were computed outside the mixed path: status 2
+  StencilArgs afv = av;
+  afv.ok_status = GMLS_TARGET_FALLBACK;
+  if (!sync || hm.count[0] > 0) {
+    GMLS_HIP(launch_rank_deficient(as, 1, list, meta, s));
+    GMLS_HIP(launch_qr_bin(dim, order, GMLS_BASIS_DIVFREE, 0, afv, list, meta, ctx->cus * 8, s));
+  }
+  GMLS_HIP(launch_mixed_wave_shared(dim, order, as, fbs, &meta->fb_count, av, fbv, &meta->fb2_count, list,
+                                    sync ? &hm : nullptr, meta, stats, opt, n, ctx->cus, s));
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
+  StencilArgs afs = as;
+  afs.ok_status = -1;  // keep the fallback status set by the mixed kernel
+  GMLS_HIP(launch_qr_fallback(dim, order, GMLS_BASIS_SCALAR, afs, fbs, meta, 4, ctx->cus * 8, s));
+  StencilArgs afv2 = av;
+  afv2.ok_status = -1;
+  GMLS_HIP(launch_qr_queue(dim, order, GMLS_BASIS_DIVFREE, afv2, fbv, &meta->fb2_count, &meta->fb2_cursor,
+                           ctx->cus * 8, s));
+  GMLS_HIP(launch_qr_kmat(dim, order, afv, aux, &meta->aux_count, &meta->aux_cursor, 64, s));
+  if (report) GMLS_HIP(hipEventRecord(ctx->ev[3], s));
+  if (!report) return GMLS_OK;
+  Stats hs;
+  GMLS_HIP(hipMemcpyAsync(&hs, stats, sizeof(Stats), hipMemcpyDeviceToHost, s));
+  GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
+  GMLS_HIP(hipStreamSynchronize(s));
+  float t01 = 0, t12 = 0, t23 = 0;
+  hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
+  hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
+  hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
+  report->n_targets = n_tgt;
+  report->n_rank_deficient = hm.count[0];
+  report->n_fallback = (int64_t)hs.n_fallback;
+  report->n_not_converged = (int64_t)hs.n_not_converged;
+  report->n_ok = n_tgt - hm.count[0];
+  for (int i = 0; i < 16; ++i) report->sweep_hist[i] = (int32_t)hs.sweep_hist[i];
+  double cmax;
+  memcpy(&cmax, &hs.cond_max_bits, sizeof(double));
+  report->cond_max = cmax;
+  report->t_bin_ms = t01;
+  report->t_stencil_ms = t12;
+  report->t_fallback_ms = t23;
+  return hm.count[0] > 0 ? GMLS_WARN_TARGET_FLAGS : GMLS_OK;
+}
+
 extern "C" {
 
 gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
@@ -426,6 +544,48 @@ gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, con
                           double *weights, uint8_t *target_status, gmls_report *report) {
   return run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, basis, functional_mask, weight_p, eps, row_ptr,
                       col, nullptr, prec, weights, nullptr, target_status, report);
+}
+
+gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                int64_t n_tgt, int dim, int order, int weight_p, const double *eps,
+                                const int64_t *row_ptr, const int32_t *col, int prec, int n_sets,
+                                const gmls_stencil_set *sets, gmls_report *report) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (!sets || n_sets < 1 || n_sets > 8)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "n_sets must be in 1..8, with a host array of sets");
+  int is = -1, iv = -1;
+  for (int k = 0; k < n_sets; ++k) {
+    if (sets[k].basis != GMLS_BASIS_SCALAR && sets[k].basis != GMLS_BASIS_DIVFREE)
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "a set's basis must be GMLS_BASIS_SCALAR or GMLS_BASIS_DIVFREE");
+    (sets[k].basis == GMLS_BASIS_SCALAR ? is : iv) = k;
+  }
+  const bool shared = n_sets == 2 && is >= 0 && iv >= 0 && prec == GMLS_PREC_MIXED &&
+                      (dim == 2 || dim == 3) && order >= 1 && order <= 4 &&
+                      mixed_scheme(dim, order, GMLS_BASIS_SCALAR, ctx->opt.scheme) == MIXED_WAVE &&
+                      mixed_scheme(dim, order, GMLS_BASIS_DIVFREE, ctx->opt.scheme) == MIXED_WAVE;
+  if (shared)
+    return run_shared_wave(ctx, coords, n_src, targets, n_tgt, dim, order, weight_p, eps, row_ptr, col, sets[is],
+                           sets[iv], report);
+  gmls_status ret = GMLS_OK;
+  gmls_report acc;
+  for (int k = 0; k < n_sets; ++k) {
+    gmls_report r;
+    const gmls_status st = run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, sets[k].basis,
+                                        sets[k].functional_mask, weight_p, eps, row_ptr, col, nullptr, prec,
+                                        sets[k].weights, nullptr, sets[k].target_status, report ? &r : nullptr);
+    if (st != GMLS_OK && st != GMLS_WARN_TARGET_FLAGS) return st;
+    if (k == 0) {
+      ret = st;
+      if (report) acc = r;
+    } else if (report) {
+      acc.t_bin_ms += r.t_bin_ms;
+      acc.t_stencil_ms += r.t_stencil_ms;
+      acc.t_fallback_ms += r.t_fallback_ms;
+    }
+  }
+  if (report) *report = acc;
+  return ret;
 }
 
 gmls_status gmls_stencils_constrained(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,

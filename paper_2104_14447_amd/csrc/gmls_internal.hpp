@@ -48,6 +48,8 @@ enum Slot {
   WS_STOKES_FLAG,
   WS_SPMV_LONG,
   WS_AUX_LIST,
+  WS_FALLBACK2,
+  WS_STATUS_TMP2,
   WS_NUM_SLOTS
 };
 
@@ -133,6 +135,8 @@ struct BinMeta {
   int pad;
   int aux_count;   // divergence-free targets queued for the factorisation of
   int aux_cursor;  // their own sample matrix (scalar basis not unisolvent)
+  int fb2_count;   // second set of a shared call (gmls_stencils_multi):
+  int fb2_cursor;  // its FP64 fallback queue
 };
 
 // Per-call statistics accumulated on the device (mixed path).
@@ -198,6 +202,15 @@ hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a
 hipError_t launch_mixed_wave(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt, int n_max,
                              int cus, hipStream_t s);
+// FP64 QR of the targets list[0 .. *count) (work counter *cursor), any row count
+hipError_t launch_qr_queue(int dim, int order, int basis, const StencilArgs &a, const int *list, const int *count,
+                           int *cursor, int n_blocks, hipStream_t s);
+// one wavefront per target for a scalar set (as) and a divergence-free set
+// (av) on the same neighbour lists: moments and swept Gram formed once
+hipError_t launch_mixed_wave_shared(int dim, int order, const StencilArgs &as, int *fbs, int *fbs_count,
+                                    const StencilArgs &av, int *fbv, int *fbv_count, const int *list,
+                                    const BinMeta *hm, BinMeta *meta, Stats *stats, const Options &opt, int n_max,
+                                    int cus, hipStream_t s);
 // the queued divergence-free targets of aux_list[0 .. *count)
 hipError_t launch_qr_kmat(int dim, int order, const StencilArgs &a, const int *list, const int *count,
                           int *cursor, int n_blocks, hipStream_t s);

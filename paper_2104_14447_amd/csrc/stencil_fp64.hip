@@ -96,6 +96,11 @@ hipError_t launch_qr_bin(int dim, int order, int basis, int bin, const StencilAr
                      n_blocks, s);
 }
 
+hipError_t launch_qr_queue(int dim, int order, int basis, const StencilArgs &a, const int *list, const int *count,
+                           int *cursor, int n_blocks, hipStream_t s) {
+  return dispatch_qr(dim, order, basis, 4, a, list, count, nullptr, cursor, n_blocks, s);
+}
+
 hipError_t launch_qr_fallback(int dim, int order, int basis, const StencilArgs &a, const int *list, BinMeta *meta,
                               int max_bin, int n_blocks, hipStream_t s) {
   return dispatch_qr(dim, order, basis, max_bin, a, list, &meta->fb_count, nullptr, &meta->fb_cursor, n_blocks, s);

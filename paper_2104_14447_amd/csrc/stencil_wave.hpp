@@ -260,35 +260,186 @@ struct WaveCounts {
   double cond = 0.0;
 };
 
+// Queue of one stencil set: its arguments, fallback list and counter.
+struct WaveSet {
+  StencilArgs a;
+  int *fb_list;
+  int *fb_count;
+};
+
+// Scalar basis: the weights of every row of `as` from e = row `lane` of
+// -E^-1 (the coefficients y_i / i! = dsc_i (E^-1 Dg lambda)_i broadcast
+// through LDS; `big` is free here).
+template <int DIM, int ORDER, int RPL>
+__device__ __forceinline__ void wave_scalar_rows(const StencilArgs &as, const RowKinds &rk,
+                                                 const double (&e)[num_mono(DIM, ORDER)], double dsc,
+                                                 const double *dscv, double ie, int64_t base, int N,
+                                                 const double (&s)[RPL][DIM], const double (&w)[RPL], double *big) {
+  constexpr int QS = num_mono(DIM, ORDER);
+  const int lane = lane_id();
+  const int F = as.F;
+  double *cfb = big;  // [F][64]
+  for (int f = 0; f < F; ++f) cfb[f * 64 + lane] = -dsc * lambda_dot<DIM, ORDER, QS>(rk.kind[f], e, dscv, ie);
+  __syncthreads();
+  double *wout = as.weights + (int64_t)F * base;
+  for (int f = 0; f < F; ++f) {
+    double cf[QS];
+#pragma unroll
+    for (int k = 0; k < QS; ++k) cf[k] = cfb[f * 64 + k];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int j = lane + 64 * r;
+      const double val = w[r] * horner<DIM, ORDER>(cf, s[r]);
+      if (j < N) wout[(int64_t)f * N + j] = val;
+    }
+  }
+  __syncthreads();
+}
+
+// Divergence-free basis: S = D G^-1 D^T from E^-1, its sweep, and the weights
+// of every row of `av`.  Returns false when S breaks down (the target then
+// goes to the FP64 kernel); `big`, vb and colb are free on entry.
+template <int DIM, int ORDER, int RPL>
+__device__ __forceinline__ bool wave_divfree_rows(const StencilArgs &av, const RowKinds &rk,
+                                                  const double (&e)[num_mono(DIM, ORDER)], double dg, double ifac,
+                                                  const int (&ubl)[3], const double *dscv, double ie, int64_t base,
+                                                  int N, const double (&s)[RPL][DIM], const double (&w)[RPL],
+                                                  double *big, double (*vb)[64], double *colb) {
+  constexpr int QS = num_mono(DIM, ORDER);
+  constexpr int QM = ORDER >= 1 ? num_mono(DIM, ORDER - 1) : 1;
+  constexpr DivUp<DIM, ORDER> DU{};
+  const int lane = lane_id();
+  const int F = av.F;
+  // S = D G^-1 D^T: S_(b,b2) = sum_k G^-1_(up[b][k], up[b2][k]); lane b holds row b
+  if (lane < QS)
+#pragma unroll
+    for (int k = 0; k < QS; ++k) big[lane * QS + k] = e[k];
+  vb[2][lane] = dg;
+  __syncthreads();
+  double sr[QM];
+  double sdiag = 1.0;
+#pragma unroll
+  for (int b2 = 0; b2 < QM; ++b2) {
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) v -= vb[2][ubl[k]] * big[ubl[k] * QS + DU.up[b2][k]] * vb[2][DU.up[b2][k]];
+    sr[b2] = lane < QM ? v : 0.0;
+    if (lane == b2) sdiag = v;
+  }
+  // equilibrate S (ds_b = 1/sqrt(S_bb)) and sweep it: sr = -(ds S ds)^-1
+  const double ds = lane < QM ? 1.0 / sqrt(sdiag) : 0.0;
+  vb[3][lane] = ds;
+  __syncthreads();
+#pragma unroll
+  for (int b2 = 0; b2 < QM; ++b2) sr[b2] *= ds * vb[3][b2];
+  if (!sweep_inverse<QM>(sr, colb, 1e-14)) return false;  // ends with a barrier: big is free
+  double *wout = av.weights + (int64_t)F * DIM * base;
+  // rows come in groups of DIM (one kind, components 0..DIM-1), then the
+  // divergence row; per group, for component c of the functional:
+  //   v = G^-1 l (the same for every c), r_b = v_(b + e_c),
+  //   t = S^-1 r = ds (ds S ds)^-1 ds r,
+  //   g_(c,k) = delta_(k,c) v - G^-1 D_k^T t, D_k^T t = sum_b t_b e_(b+e_k),
+  // whose columns of E^-1 are this lane's registers
+  double *rb = big;                               // [c][QM]     ds_b r_b
+  double *tdg = big + DIM * QM;                   // [c][k][QM]  t_b Dg_(b+e_k)
+  double *cfb = big + DIM * QM + DIM * DIM * QM;  // [c][k][QS]  g / q!
+  for (int f0 = 0; f0 < F; f0 += DIM) {
+    const int kind = rk.kind[f0];
+    if (kind == FK_DIV) {  // identically zero on a divergence-free fit
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int j = lane + 64 * r;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+          if (j < N) wout[((int64_t)f0 * N + j) * DIM + k] = 0.0;
+      }
+      break;  // the last row
+    }
+    const double v = -dg * lambda_dot<DIM, ORDER, QS>(kind, e, dscv, ie);
+    vb[1][lane] = v;
+    __syncthreads();
+    if (lane < QM)
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) rb[c * QM + lane] = vb[1][ubl[c]] * ds;
+    __syncthreads();
+    if (lane < QM) {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) {
+        double tt = 0.0;
+#pragma unroll
+        for (int b2 = 0; b2 < QM; ++b2) tt = fma(sr[b2], rb[c * QM + b2], tt);
+        tt = -ds * tt;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) tdg[(c * DIM + k) * QM + lane] = tt * vb[2][ubl[k]];
+      }
+    }
+    __syncthreads();
+    if (lane < QS) {
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          double u = 0.0;
+#pragma unroll
+          for (int b = 0; b < QM; ++b) u = fma(e[DU.up[b][k]], tdg[(c * DIM + k) * QM + b], u);
+          const double g = (k == c ? v : 0.0) + dg * u;
+          cfb[(c * DIM + k) * QS + lane] = g * ifac;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        double cf[QS];
+#pragma unroll
+        for (int q = 0; q < QS; ++q) cf[q] = cfb[(c * DIM + k) * QS + q];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+          const int j = lane + 64 * r;
+          const double val = w[r] * horner<DIM, ORDER>(cf, s[r]);
+          if (j < N) wout[((int64_t)(f0 + c) * N + j) * DIM + k] = val;
+        }
+      }
+    __syncthreads();
+  }
+  return true;
+}
+
+// BASIS 0 scalar set (ss), 1 divergence-free set (sv), 3 both on the same
+// neighbour lists: the moments and the swept Gram are formed once per target
+// for both sets (Section 2.2: the divergence-free fit is the scalar fit under
+// D c = 0, so both take the same G).
 template <int DIM, int ORDER, int BASIS, int RPL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_wave(StencilArgs a, const int *list, BinMeta *meta, int bin, int *fb_list,
-                                             Stats *stats, Options opt) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_wave(
+    WaveSet ss, WaveSet sv, const int *list, BinMeta *meta, int bin, Stats *stats, Options opt) {
+  constexpr bool SCAL = BASIS == 0 || BASIS == 3, DIVF = BASIS == 1 || BASIS == 3;
   constexpr int QS = num_mono(DIM, ORDER);
   constexpr int NM = num_mono(DIM, 2 * ORDER);
   constexpr int QM = ORDER >= 1 ? num_mono(DIM, ORDER - 1) : 1;
   constexpr int RED = 64 * 17;
-  constexpr int BIG = (BASIS == 1 && QS * QS > RED) ? QS * QS : RED;
+  constexpr int BIG = (DIVF && QS * QS > RED) ? QS * QS : RED;
   static_assert(QS <= 64, "one basis function per lane");
-  __shared__ double big[BIG];    // moment reduction, then (divergence-free) -E^-1
-  __shared__ double mu[NM];      // moments, lexicographic order
-  __shared__ double vb[4][64];   // broadcast vectors
+  __shared__ double big[BIG];      // moment reduction, then (divergence-free) -E^-1
+  __shared__ double mu[NM];        // moments, lexicographic order
+  __shared__ double vb[4][64];     // broadcast vectors
   __shared__ double colb[4 * 64];  // pivot columns of the sweeps
   __shared__ unsigned char pidx[QS * QS];
   constexpr WavePairs<DIM, ORDER> WP{};
   constexpr InvFact64<DIM, ORDER> IF{};
+  const StencilArgs &a = SCAL ? ss.a : sv.a;  // the common inputs
   const int lane = lane_id();
   for (int q = lane; q < QS * QS; q += 64) pidx[q] = WP.p[q];
   const double ifac = IF.v[lane < QS ? lane : 0];  // 1 / i!
   int ubl[3] = {0, 0, 0};                             // divergence-free: index of b + e_k, b = lane
-  if constexpr (BASIS == 1) {
+  if constexpr (DIVF) {
     constexpr DivUp<DIM, ORDER> DU{};
     if (lane < QM)
 #pragma unroll
       for (int k = 0; k < DIM; ++k) ubl[k] = DU.up[lane][k];
   }
   __syncthreads();
-  const RowKinds rk = row_kinds(DIM, BASIS, a.mask);
-  const int F = a.F;
+  const RowKinds rks = row_kinds(DIM, 0, ss.a.mask), rkv = row_kinds(DIM, 1, sv.a.mask);
   WaveCounts cnt;
   const SlotRange R = slot_range(meta, bin, -1, INT_MAX);
   for (int i = R.first + xcd_block(); i < R.last; i += gridDim.x) {
@@ -330,132 +481,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     if (opt.force_fallback) ok = false;
     const double dg = dsc / ifac;  // Dg_lane: G^-1 = Dg E^-1 Dg
 
-    if constexpr (BASIS == 0) {
-      if (ok) {
-        // coefficients y_i / i! = dsc_i (E^-1 Dg lambda)_i of every row,
-        // broadcast through LDS (big is free after the moments)
-        double *cfb = big;  // [F][64]
-        for (int f = 0; f < F; ++f) cfb[f * 64 + lane] = -dsc * lambda_dot<DIM, ORDER, QS>(rk.kind[f], e, vb[0], ie);
-        __syncthreads();
-        double *wout = a.weights + (int64_t)F * base;
-        for (int f = 0; f < F; ++f) {
-          double cf[QS];
-#pragma unroll
-          for (int k = 0; k < QS; ++k) cf[k] = cfb[f * 64 + k];
-#pragma unroll
-          for (int r = 0; r < RPL; ++r) {
-            const int j = lane + 64 * r;
-            const double val = w[r] * horner<DIM, ORDER>(cf, s[r]);
-            if (j < N) wout[(int64_t)f * N + j] = val;
-          }
-        }
+    if constexpr (SCAL) {
+      if (ok) wave_scalar_rows<DIM, ORDER, RPL>(ss.a, rks, e, dsc, vb[0], ie, base, N, s, w, big);
+      if (lane == 0) {
+        ss.a.status[t] = ok ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
+        if (!ok) ss.fb_list[atomicAdd(ss.fb_count, 1)] = t;
       }
-    } else {
-      // S = D G^-1 D^T: S_(b,b2) = sum_k G^-1_(up[b][k], up[b2][k]); lane b holds row b
-      constexpr DivUp<DIM, ORDER> DU{};
-      if (lane < QS)
-#pragma unroll
-        for (int k = 0; k < QS; ++k) big[lane * QS + k] = e[k];
-      vb[2][lane] = dg;
-      __syncthreads();
-      double sr[QM];
-      double sdiag = 1.0;
-#pragma unroll
-      for (int b2 = 0; b2 < QM; ++b2) {
-        double v = 0.0;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k)
-          v -= vb[2][ubl[k]] * big[ubl[k] * QS + DU.up[b2][k]] * vb[2][DU.up[b2][k]];
-        sr[b2] = lane < QM ? v : 0.0;
-        if (lane == b2) sdiag = v;
-      }
-      // equilibrate S (ds_b = 1/sqrt(S_bb)) and sweep it: sr = -(ds S ds)^-1
-      const double ds = lane < QM ? 1.0 / sqrt(sdiag) : 0.0;
-      vb[3][lane] = ds;
-      __syncthreads();
-#pragma unroll
-      for (int b2 = 0; b2 < QM; ++b2) sr[b2] *= ds * vb[3][b2];
-      ok = sweep_inverse<QM>(sr, colb, 1e-14) && ok;  // ends with a barrier: big is free
-      if (ok) {
-        double *wout = a.weights + (int64_t)F * DIM * base;
-        // rows come in groups of DIM (one kind, components 0..DIM-1), then
-        // the divergence row; per group, for component c of the functional:
-        //   v = G^-1 l (the same for every c), r_b = v_(b + e_c),
-        //   t = S^-1 r = ds (ds S ds)^-1 ds r,
-        //   g_(c,k) = delta_(k,c) v - G^-1 D_k^T t, D_k^T t = sum_b t_b e_(b+e_k),
-        // whose columns of E^-1 are this lane's registers
-        double *rb = big;                              // [c][QM]     ds_b r_b
-        double *tdg = big + DIM * QM;                  // [c][k][QM]  t_b Dg_(b+e_k)
-        double *cfb = big + DIM * QM + DIM * DIM * QM; // [c][k][QS]  g / q!
-        for (int f0 = 0; f0 < F; f0 += DIM) {
-          const int kind = rk.kind[f0];
-          if (kind == FK_DIV) {  // identically zero on a divergence-free fit
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-              const int j = lane + 64 * r;
-#pragma unroll
-              for (int k = 0; k < DIM; ++k)
-                if (j < N) wout[((int64_t)f0 * N + j) * DIM + k] = 0.0;
-            }
-            break;  // the last row
-          }
-          const double v = -dg * lambda_dot<DIM, ORDER, QS>(kind, e, vb[0], ie);
-          vb[1][lane] = v;
-          __syncthreads();
-          if (lane < QM)
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) rb[c * QM + lane] = vb[1][ubl[c]] * ds;
-          __syncthreads();
-          if (lane < QM) {
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) {
-              double tt = 0.0;
-#pragma unroll
-              for (int b2 = 0; b2 < QM; ++b2) tt = fma(sr[b2], rb[c * QM + b2], tt);
-              tt = -ds * tt;
-#pragma unroll
-              for (int k = 0; k < DIM; ++k) tdg[(c * DIM + k) * QM + lane] = tt * vb[2][ubl[k]];
-            }
-          }
-          __syncthreads();
-          if (lane < QS) {
-#pragma unroll
-            for (int c = 0; c < DIM; ++c)
-#pragma unroll
-              for (int k = 0; k < DIM; ++k) {
-                double u = 0.0;
-#pragma unroll
-                for (int b = 0; b < QM; ++b) u = fma(e[DU.up[b][k]], tdg[(c * DIM + k) * QM + b], u);
-                const double g = (k == c ? v : 0.0) + dg * u;
-                cfb[(c * DIM + k) * QS + lane] = g * ifac;
-              }
-          }
-          __syncthreads();
-#pragma unroll
-          for (int c = 0; c < DIM; ++c)
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-              double cf[QS];
-#pragma unroll
-              for (int q = 0; q < QS; ++q) cf[q] = cfb[(c * DIM + k) * QS + q];
-#pragma unroll
-              for (int r = 0; r < RPL; ++r) {
-                const int j = lane + 64 * r;
-                const double val = w[r] * horner<DIM, ORDER>(cf, s[r]);
-                if (j < N) wout[((int64_t)(f0 + c) * N + j) * DIM + k] = val;
-              }
-            }
-          __syncthreads();
-        }
+    }
+    bool okv = ok;
+    if constexpr (DIVF) {
+      if (ok) okv = wave_divfree_rows<DIM, ORDER, RPL>(sv.a, rkv, e, dg, ifac, ubl, vb[0], ie, base, N, s, w, big,
+                                                       vb, colb);
+      if (lane == 0) {
+        sv.a.status[t] = okv ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
+        if (!okv) sv.fb_list[atomicAdd(sv.fb_count, 1)] = t;
       }
     }
     __syncthreads();
-    if (lane == 0) {
-      a.status[t] = ok ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
-      if (!ok) fb_list[atomicAdd(&meta->fb_count, 1)] = t;
-    }
-    cnt.good += ok ? 1 : 0;
-    cnt.fell += ok ? 0 : 1;
+    const bool good = SCAL ? ok : okv;  // statistics of the (first) set
+    cnt.good += good ? 1 : 0;
+    cnt.fell += good ? 0 : 1;
     if (cond >= 0.0) cnt.cond = fmax(cnt.cond, cond);  // NaN estimates are skipped
   }
   if (lane == 0) {
@@ -470,7 +515,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // grids sized to the bin; without one every bin is launched, sized for n_max
 // targets, its bounds read on the device.
 template <int DIM, int ORDER, int BASIS>
-hipError_t launch_wave(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
+hipError_t launch_wave(const WaveSet &ss, const WaveSet &sv, const int *list, const BinMeta *hm, BinMeta *meta,
                        Stats *stats, const Options &opt, int n_max, int cus, hipStream_t s) {
   for (int b = 1; b < kNumBins; ++b) {
     int cnt = n_max;
@@ -481,10 +526,10 @@ hipError_t launch_wave(const StencilArgs &a, const int *list, const BinMeta *hm,
     int nb = cnt < cus * 16 ? cnt : cus * 16;
     nb = xcd_grid(nb);
     switch (b) {
-      case 1: k_wave<DIM, ORDER, BASIS, 1><<<nb, 64, 0, s>>>(a, list, meta, b, fb, stats, opt); break;
-      case 2: k_wave<DIM, ORDER, BASIS, 2><<<nb, 64, 0, s>>>(a, list, meta, b, fb, stats, opt); break;
-      case 3: k_wave<DIM, ORDER, BASIS, 3><<<nb, 64, 0, s>>>(a, list, meta, b, fb, stats, opt); break;
-      default: k_wave<DIM, ORDER, BASIS, 4><<<nb, 64, 0, s>>>(a, list, meta, b, fb, stats, opt); break;
+      case 1: k_wave<DIM, ORDER, BASIS, 1><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt); break;
+      case 2: k_wave<DIM, ORDER, BASIS, 2><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt); break;
+      case 3: k_wave<DIM, ORDER, BASIS, 3><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt); break;
+      default: k_wave<DIM, ORDER, BASIS, 4><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt); break;
     }
   }
   return hipGetLastError();

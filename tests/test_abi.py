@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
     assert names == sorted(["gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
                             "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained",
                             "gmls_stencils_staggered", "gmls_assemble_stokes", "gmls_spmv", "gmls_apply",
-                            "gmls_check", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load"])
+                            "gmls_check", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
+                            "gmls_stencils_multi"])
 
 
 def test_library_exports_every_declared_symbol():

@@ -1,0 +1,82 @@
+"""Several stencil sets on one neighbour list (gmls_stencils_multi).
+
+A scalar and a divergence-free set of the same order share the moments and
+the swept Gram in the wavefront scheme; each set's result must be the one
+gmls_stencils gives for it alone (bit for bit: the shared kernel runs the
+same arithmetic in the same order), and therefore within the gates of the
+oracle.  Other combinations run the sets in turn."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import ctx, dev, flush, host, require_gpu, row_errors
+from tests.test_gpu_stencils import FP64_TOL, MIXED_TOL, case_data
+
+pytestmark = pytest.mark.gpu
+
+
+def separate(G, pts, rp, col, eps, order, p, sets, prec):
+    s = dev(pts)
+    out = []
+    for basis, mask in sets:
+        w, st, _ = G.gmls_stencils(ctx(), s, s, order, basis, mask, p, dev(eps), dev(rp), dev(col), prec=prec)
+        out.append((host(w), host(st)))
+    return out
+
+
+def multi(G, pts, rp, col, eps, order, p, sets, prec):
+    s = dev(pts)
+    outs, rep = G.gmls_stencils_multi(ctx(), s, s, order, p, dev(eps), dev(rp), dev(col), sets, prec=prec,
+                                      report=True)
+    return [(host(w), host(st)) for w, st in outs], rep
+
+
+@pytest.mark.parametrize("names", [("3d_m4_k170", "3d_divfree_m4"), ("3d_divfree_m4_k30", "3d_divfree_m4_k30")])
+def test_shared_gram_equals_separate_calls(names):
+    G = require_gpu()
+    pts, rp, col, eps, _, _, _, _ = case_data(names[0])
+    order, p = 4, 6
+    sets = [(G.BASIS_SCALAR, G.F_GRAD | G.F_LAPLACIAN), (G.BASIS_DIVFREE, G.F_LAPLACIAN | G.F_DIV)]
+    flush(f"shared Gram {names}")
+    got, rep = multi(G, pts, rp, col, eps, order, p, sets, G.PREC_MIXED)
+    ref = separate(G, pts, rp, col, eps, order, p, sets, G.PREC_MIXED)
+    flush(f"  report {rep}")
+    for (gw, gs), (rw, rs) in zip(got, ref):
+        assert np.array_equal(gs, rs)
+        assert np.array_equal(gw.view(np.uint64), rw.view(np.uint64))
+    # and against the oracle, where it defines the stencils
+    if names[0] == "3d_m4_k170":
+        for (gw, gs), name, tol in zip(got, names, (MIXED_TOL, MIXED_TOL)):
+            _, _, _, _, w, st, F, C = case_data(name)
+            assert np.array_equal(gs == 1, st == 1)
+            zero = (F - 1,) if C > 1 else ()
+            assert row_errors(gw, w, rp, F, C, zero_rows=zero).max() <= tol
+    else:  # 30 neighbours: the scalar basis (35) is rank deficient, the divergence-free one (85 of 90 rows) is not
+        assert (got[0][1] == 1).all() and np.isnan(got[0][0]).all()
+        _, _, _, _, w, st, F, C = case_data(names[1])
+        assert (st == 0).all() and (got[1][1] == 2).all()
+        assert row_errors(got[1][0], w, rp, F, C, zero_rows=(F - 1,)).max() <= FP64_TOL
+
+
+def test_sets_in_turn_equal_separate_calls():
+    """FP64, or a scheme without sharing: the sets run one after the other."""
+    G = require_gpu()
+    pts, rp, col, eps, _, _, _, _ = case_data("3d_divfree_m2")
+    sets = [(G.BASIS_DIVFREE, G.F_VALUE | G.F_LAPLACIAN), (G.BASIS_SCALAR, G.F_GRAD)]
+    for prec in (G.PREC_FP64, G.PREC_MIXED):
+        flush(f"sets in turn prec={prec}")
+        got, _ = multi(G, pts, rp, col, eps, 2, 4, sets, prec)
+        ref = separate(G, pts, rp, col, eps, 2, 4, sets, prec)
+        for (gw, gs), (rw, rs) in zip(got, ref):
+            assert np.array_equal(gs, rs)
+            assert np.array_equal(gw.view(np.uint64), rw.view(np.uint64))
+
+
+def test_multi_rejects_bad_sets():
+    G = require_gpu()
+    pts, rp, col, eps, _, _, _, _ = case_data("3d_divfree_m2")
+    with pytest.raises(G.GmlsError):
+        multi(G, pts, rp, col, eps, 2, 4, [], G.PREC_MIXED)
+    with pytest.raises(G.GmlsError):
+        multi(G, pts, rp, col, eps, 2, 4, [(7, G.F_GRAD)], G.PREC_MIXED)
+    with pytest.raises(G.GmlsError):
+        multi(G, pts, rp, col, eps, 2, 4, [(G.BASIS_DIVFREE, G.F_GRAD)], G.PREC_MIXED)
