@@ -764,8 +764,12 @@ __global__ __launch_bounds__(64) void k_pipe_solve_div(StencilArgs a, PipeRec *r
   }
 }
 
-// alpha_(j, f, c) = w_j p(s_j) . g_(f,c), three (f, c) outputs per pass over
-// the rows (their coefficients in registers, Horner evaluation)
+// alpha_(j, f, c) = w_j p(s_j) . g_(f,c), one functional row f (its DIM
+// components' coefficients in registers, Horner evaluation) per pass over
+// the rows.  The G lanes of a group hold G consecutive rows, whose DIM
+// components form one contiguous run of G*DIM doubles: the values are staged
+// in LDS and stored as DIM fully coalesced runs instead of DIM stores with a
+// DIM-double stride (which split every cache line between instructions).
 template <int DIM, int ORDER, int G, int RPL>
 __global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const PipeRec *rec, const BinMeta *meta,
                                                          int bin, int win_lo, int win_hi, const double *gin) {
@@ -774,9 +778,11 @@ __global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const Pi
   constexpr int QS = num_mono(DIM, ORDER);
   constexpr int TPW = 64 / G;
   constexpr InvFact64<DIM, ORDER> IFW{};
+  __shared__ double stage[64 * DIM];  // group g: [g * G * DIM, (g + 1) * G * DIM)
   const int lane = lane_id();
   const int grp = lane / G, lg = lane % G;
-  const int FC = a.F * DIM;
+  const int F = a.F, FC = F * DIM;
+  double *gst = stage + grp * G * DIM;
   for (int i0 = first + xcd_block() * TPW; i0 < last; i0 += gridDim.x * TPW) {
     const int i = i0 + grp;
     const bool valid = i < last;
@@ -794,22 +800,25 @@ __global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const Pi
 #pragma unroll
     for (int r = 0; r < RPL; ++r) w[r] = row_sw<DIM>(xs[r], xt, rc.ie, a.p, true, s[r]);
     double *wout = a.weights + (int64_t)FC * base;
-    for (int q0 = 0; q0 < FC; q0 += 3) {
-      double cf[3][QS];
+    for (int f = 0; f < F; ++f) {
+      double cf[DIM][QS];
 #pragma unroll
-      for (int u = 0; u < 3; ++u)
+      for (int c = 0; c < DIM; ++c)
 #pragma unroll
-        for (int q = 0; q < QS; ++q)
-          cf[u][q] = q0 + u < FC ? gin[(loc * FC + q0 + u) * QS + q] * IFW.v[q] : 0.0;
+        for (int q = 0; q < QS; ++q) cf[c][q] = gin[(loc * FC + f * DIM + c) * QS + q] * IFW.v[q];
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
-        const int j = lg + G * r;
 #pragma unroll
-        for (int u = 0; u < 3; ++u) {
-          const int fc = q0 + u;
-          const int f = fc / DIM, c = fc - f * DIM;
-          if (good && j < N && fc < FC) wout[((int64_t)f * N + j) * DIM + c] = w[r] * horner<DIM, ORDER>(cf[u], s[r]);
+        for (int c = 0; c < DIM; ++c) gst[lg * DIM + c] = w[r] * horner<DIM, ORDER>(cf[c], s[r]);
+        __syncthreads();
+        // the group's rows G r .. G r + G - 1: doubles (f N + G r) DIM + m, m < G DIM
+        double *run = wout + ((int64_t)f * N + G * r) * DIM;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+          const int m = k * G + lg;
+          if (good && G * r + m / DIM < N) run[m] = gst[m];
         }
+        __syncthreads();
       }
     }
   }
