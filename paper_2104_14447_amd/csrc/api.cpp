@@ -419,15 +419,17 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
 }
 
 // A scalar set (ss) and a divergence-free set (sv) on the same neighbour
-// lists, mixed precision, wavefront scheme: one kernel forms the moments and
-// the swept Gram of each target once for both.  Bins follow the scalar basis
-// (bin 0: N < Q_s); the divergence-free set's bin-0 targets, which its own
-// call would have handled through the FP64 kernel's queue, go to that kernel
-// directly.
-static gmls_status run_shared_wave(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
-                                   int64_t n_tgt, int dim, int order, int weight_p, const double *eps,
-                                   const int64_t *row_ptr, const int32_t *col, const gmls_stencil_set &ss,
-                                   const gmls_stencil_set &sv, gmls_report *report) {
+// lists, mixed precision, the same scheme for both: with the wavefront scheme
+// one kernel forms the moments and the swept Gram of each target once for
+// both; with the pipeline the moments (and per-target records) of the scalar
+// set's run are taken by the divergence-free set's solve and weights.  Bins
+// follow the scalar basis (bin 0: N < Q_s); the divergence-free set's bin-0
+// targets, which its own call would have handled through the FP64 kernel's
+// queue, go to that kernel directly.
+static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                              int64_t n_tgt, int dim, int order, int weight_p, const double *eps,
+                              const int64_t *row_ptr, const int32_t *col, const gmls_stencil_set &ss,
+                              const gmls_stencil_set &sv, int scheme, gmls_report *report) {
   int Fs = 0, Cs = 0, Qs = 0, Fv = 0, Cv = 0, Qv = 0;
   gmls_status st = gmls_stencil_shape(dim, order, GMLS_BASIS_SCALAR, ss.functional_mask, &Fs, &Cs, &Qs);
   if (st == GMLS_OK) st = gmls_stencil_shape(dim, order, GMLS_BASIS_DIVFREE, sv.functional_mask, &Fv, &Cv, &Qv);
@@ -443,13 +445,13 @@ static gmls_status run_shared_wave(gmls_ctx ctx, const double *coords, int64_t n
   hipStream_t s = ctx->stream;
   const int n = (int)n_tgt;
   Options opt = ctx->opt;
-  opt.scheme = MIXED_WAVE;
+  opt.scheme = scheme;
   BinMeta *meta = (BinMeta *)ctx->ws(WS_BIN_META, sizeof(BinMeta));
   int *list = (int *)ctx->ws(WS_BIN_LIST, sizeof(int) * (size_t)n);
   int *fbs = (int *)ctx->ws(WS_FALLBACK, sizeof(int) * (size_t)n);
   int *fbv = (int *)ctx->ws(WS_FALLBACK2, sizeof(int) * (size_t)n);
   int *aux = (int *)ctx->ws(WS_AUX_LIST, sizeof(int) * (size_t)n);
-  Stats *stats = (Stats *)ctx->ws(WS_STATS, sizeof(Stats));
+  Stats *stats = (Stats *)ctx->ws(WS_STATS, 2 * sizeof(Stats));  // [0] scalar set (reported), [1] the other
   uint8_t *sts = ss.target_status ? ss.target_status : (uint8_t *)ctx->ws(WS_STATUS_TMP, (size_t)n);
   uint8_t *stv = sv.target_status ? sv.target_status : (uint8_t *)ctx->ws(WS_STATUS_TMP2, (size_t)n);
   if (!meta || !list || !fbs || !fbv || !aux || !stats || !sts || !stv)
@@ -491,7 +493,7 @@ static gmls_status run_shared_wave(gmls_ctx ctx, const double *coords, int64_t n
   } else {
     GMLS_HIP(or_error_bit((int *)ctx->ws(WS_DEV_ERR, sizeof(int)), &meta->err, 1, DEV_ERR_STENCIL_ROWS, s));
   }
-  GMLS_HIP(fill_zero(stats, sizeof(Stats), s));
+  GMLS_HIP(fill_zero(stats, 2 * sizeof(Stats), s));
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[1], s));
   // the FP64 kernels' targets were computed outside the mixed path: status 2
   StencilArgs afv = av;
@@ -500,16 +502,53 @@ static gmls_status run_shared_wave(gmls_ctx ctx, const double *coords, int64_t n
     GMLS_HIP(launch_rank_deficient(as, 1, list, meta, s));
     GMLS_HIP(launch_qr_bin(dim, order, GMLS_BASIS_DIVFREE, 0, afv, list, meta, ctx->cus * 8, s));
   }
-  GMLS_HIP(launch_mixed_wave_shared(dim, order, as, fbs, &meta->fb_count, av, fbv, &meta->fb2_count, list,
-                                    sync ? &hm : nullptr, meta, stats, opt, n, ctx->cus, s));
-  if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
   StencilArgs afs = as;
   afs.ok_status = -1;  // keep the fallback status set by the mixed kernel
-  GMLS_HIP(launch_qr_fallback(dim, order, GMLS_BASIS_SCALAR, afs, fbs, meta, 4, ctx->cus * 8, s));
   StencilArgs afv2 = av;
   afv2.ok_status = -1;
-  GMLS_HIP(launch_qr_queue(dim, order, GMLS_BASIS_DIVFREE, afv2, fbv, &meta->fb2_count, &meta->fb2_cursor,
-                           ctx->cus * 8, s));
+  if (scheme == MIXED_WAVE) {
+    GMLS_HIP(launch_mixed_wave_shared(dim, order, as, fbs, &meta->fb_count, av, fbv, &meta->fb2_count, list,
+                                      sync ? &hm : nullptr, meta, stats, opt, n, ctx->cus, s));
+    if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
+    GMLS_HIP(launch_qr_fallback(dim, order, GMLS_BASIS_SCALAR, afs, fbs, meta, 4, ctx->cus * 8, s));
+  } else {
+    // pipeline: the whole list in one window; the scalar set (prep, moments,
+    // solve, weights) and its fallback, then the divergence-free set's solve
+    // and weights on the same records and moments, with the fallback queue
+    // cleared in between
+    const int qs = (int)binom_l(order + dim, dim);
+    double *mom = (double *)ctx->ws(WS_PIPE_MOM, sizeof(double) * (size_t)pipe_num_moments(dim, order) * n);
+    double *ys = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)as.F * qs * n);
+    double *yv = (double *)ctx->ws(WS_PIPE_Y2, sizeof(double) * (size_t)av.F * dim * qs * n);
+    void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * (size_t)n);
+    if (!mom || !ys || !yv || !rec) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+    Options os = opt, ov = opt;
+    for (int b = 0; b < 2; ++b) {
+      Options &o = b == 0 ? os : ov;
+      const auto tuned = ctx->tune.find(tune_key(dim, order, b));
+      for (int k = 0; k < 2; ++k)
+        for (int q = 0; q < 8; ++q) {
+          int c = 0;
+          if (o.pipe_force >= 0)
+            c = o.pipe_force;
+          else if (tuned != ctx->tune.end() && tuned->second[k * 8 + q] >= 0)
+            c = tuned->second[k * 8 + q];
+          o.pipe_shape[k][q] = (signed char)c;
+        }
+    }
+    ov.reuse_moments = 1;
+    GMLS_HIP(launch_mixed_pipe(dim, order, GMLS_BASIS_SCALAR, as, list, sync ? &hm : nullptr, meta, fbs, stats, os,
+                               mom, ys, rec, n, n, ctx->cus, nullptr, s));
+    GMLS_HIP(launch_qr_fallback(dim, order, GMLS_BASIS_SCALAR, afs, fbs, meta, 4, ctx->cus * 8, s));
+    GMLS_HIP(fill_zero(&meta->fb_count, 2 * sizeof(int), s));  // fb_count, fb_cursor
+    GMLS_HIP(launch_mixed_pipe(dim, order, GMLS_BASIS_DIVFREE, av, list, sync ? &hm : nullptr, meta, fbv, stats + 1, ov,
+                               mom, yv, rec, n, n, ctx->cus, nullptr, s));
+    if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
+    GMLS_HIP(launch_qr_fallback(dim, order, GMLS_BASIS_DIVFREE, afv2, fbv, meta, 4, ctx->cus * 8, s));
+  }
+  if (scheme == MIXED_WAVE)
+    GMLS_HIP(launch_qr_queue(dim, order, GMLS_BASIS_DIVFREE, afv2, fbv, &meta->fb2_count, &meta->fb2_cursor,
+                             ctx->cus * 8, s));
   GMLS_HIP(launch_qr_kmat(dim, order, afv, aux, &meta->aux_count, &meta->aux_cursor, 64, s));
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[3], s));
   if (!report) return GMLS_OK;
@@ -560,13 +599,16 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
       return gmls_set_error(ctx, GMLS_ERR_ARG, "a set's basis must be GMLS_BASIS_SCALAR or GMLS_BASIS_DIVFREE");
     (sets[k].basis == GMLS_BASIS_SCALAR ? is : iv) = k;
   }
-  const bool shared = n_sets == 2 && is >= 0 && iv >= 0 && prec == GMLS_PREC_MIXED &&
-                      (dim == 2 || dim == 3) && order >= 1 && order <= 4 &&
-                      mixed_scheme(dim, order, GMLS_BASIS_SCALAR, ctx->opt.scheme) == MIXED_WAVE &&
-                      mixed_scheme(dim, order, GMLS_BASIS_DIVFREE, ctx->opt.scheme) == MIXED_WAVE;
-  if (shared)
-    return run_shared_wave(ctx, coords, n_src, targets, n_tgt, dim, order, weight_p, eps, row_ptr, col, sets[is],
-                           sets[iv], report);
+  int scheme = -1;
+  if (n_sets == 2 && is >= 0 && iv >= 0 && prec == GMLS_PREC_MIXED && (dim == 2 || dim == 3) && order >= 1 &&
+      order <= 4) {
+    const int s0 = mixed_scheme(dim, order, GMLS_BASIS_SCALAR, ctx->opt.scheme);
+    const int s1 = mixed_scheme(dim, order, GMLS_BASIS_DIVFREE, ctx->opt.scheme);
+    if (s0 == s1 && (s0 == MIXED_WAVE || s0 == MIXED_PIPE)) scheme = s0;
+  }
+  if (scheme >= 0)
+    return run_shared(ctx, coords, n_src, targets, n_tgt, dim, order, weight_p, eps, row_ptr, col, sets[is],
+                      sets[iv], scheme, report);
   gmls_status ret = GMLS_OK;
   gmls_report acc;
   for (int k = 0; k < n_sets; ++k) {

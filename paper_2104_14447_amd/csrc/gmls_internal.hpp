@@ -50,6 +50,7 @@ enum Slot {
   WS_AUX_LIST,
   WS_FALLBACK2,
   WS_STATUS_TMP2,
+  WS_PIPE_Y2,
   WS_NUM_SLOTS
 };
 
@@ -71,6 +72,7 @@ struct Options {
   int capture_safe = 0;              // nonzero: no call waits for the device (see libgmls.h)
   int row_order = 0;                 // radius rows: 0 cell order, 1 ascending source index
   int pipe_force = -1;               // pipeline row shape: -1 the tuned table, else this candidate
+  int reuse_moments = 0;             // per call: the pipeline's moments and records are already in place
   // per call: pipeline row-shape candidate of [kernel: 0 moments, 1 weights][bin]
   signed char pipe_shape[2][8] = {};
 };

@@ -905,13 +905,15 @@ hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm,
     const int win_lo = hm ? (int)c0 : -1;
     const int win_hi = hm ? (int)(c0 + chunk < end ? c0 + chunk : end) : INT_MAX;
     const int n_win = hm ? win_hi - win_lo : n_max;
-    {
+    if (!opt.reuse_moments) {
       int nbp = (n_win + 255) / 256;
       if (nbp > cus * 8) nbp = cus * 8;
       if (nbp < 1) nbp = 1;
       k_pipe_prep<DIM><<<nbp, 256, 0, s>>>(a, list, meta, win_lo, win_hi, rec);
     }
-    for (int pass = 0; pass < 2; ++pass) {
+    // a second stencil set on the same neighbour lists (one window) takes
+    // the records and moments of the first
+    for (int pass = opt.reuse_moments ? 1 : 0; pass < 2; ++pass) {
       if (pass == 1) {
         int nb = (n_win + 63) / 64;
         if (nb > cus * 16) nb = cus * 16;
