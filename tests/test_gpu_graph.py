@@ -101,3 +101,56 @@ def test_capture_safe_reports_capacity_through_check():
         assert host(rp)[-1] == len(ref[1])
         c.check()  # the record is cleared
     c.close()
+
+
+@pytest.mark.parametrize("order,k,p", [(4, 170, 6), (2, 60, 4)], ids=["wave", "pipeline"])
+def test_graph_replays_shared_multi(order, k, p):
+    """A kNN search and one gmls_stencils_multi call (scalar + divergence-free
+    sets sharing the Gram) captured together and replayed, against eager."""
+    G = require_gpu()
+    pts = W.jittered_grid(6000, 3, 1005)
+    sets = [(G.BASIS_SCALAR, G.F_GRAD | G.F_LAPLACIAN), (G.BASIS_DIVFREE, G.F_LAPLACIAN | G.F_DIV)]
+    s = torch.cuda.Stream()
+    c = G.Context(0, stream=s)
+    with torch.cuda.stream(s):
+        x = dev(pts)
+        flush(f"graph multi order={order}: eager reference")
+        rp, col, eps = G.gmls_neighbors(c, x, x, G.SEARCH_KNN, k=k, eps_mult=1.5)
+        ref = [(host(w), host(st)) for w, st in
+               G.gmls_stencils_multi(c, x, x, order, p, eps, rp, col, sets, prec=G.PREC_MIXED)[0]]
+        nnz = col.numel()
+        col_buf = torch.empty(nnz, dtype=torch.int32, device="cuda")
+        outs = []
+        for basis, mask in sets:
+            F, C, _ = G.gmls_stencil_shape(3, order, basis, mask)
+            outs.append((torch.empty(F * C * nnz, dtype=torch.float64, device="cuda"),
+                         torch.empty(len(pts), dtype=torch.uint8, device="cuda")))
+        c.set_option(G.OPT_CAPTURE_SAFE, 1)
+        gout = {}
+
+        def step():
+            rp_, col_, eps_ = G.gmls_neighbors(c, x, x, G.SEARCH_KNN, k=k, eps_mult=1.5, col=col_buf)
+            G.gmls_stencils_multi(c, x, x, order, p, eps_, rp_, col_, sets, prec=G.PREC_MIXED, outputs=outs)
+            gout["rp"] = rp_
+
+        def compare(tag):
+            s.synchronize()
+            for (w, st), (rw, rst) in zip(outs, ref):
+                assert np.array_equal(host(st), rst), tag
+                assert np.array_equal(host(w).view(np.uint64), rw.view(np.uint64)), tag
+            c.check()
+
+        step()
+        compare("capture-safe eager")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            step()
+        for rep in range(3):
+            for w, st in outs:
+                w.fill_(float("nan"))
+                st.fill_(255)
+            s.synchronize()
+            flush(f"graph multi: replay {rep}")
+            g.replay()
+            compare(f"replay {rep}")
+    c.close()
