@@ -699,8 +699,10 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
   constexpr int CAP = 64 * EPLL, SCAP = 64 * EPLS;
   __shared__ double cd[CAP];
   __shared__ int ci[CAP];
+  constexpr int KU = 4;  // chunks of 64 candidates loaded together
   __shared__ double sd[SCAP];
   __shared__ int si[SCAP];
+  __shared__ int rpre[64], roff[64];  // per run: first candidate number, source offset
   const GridParams g = *gp;
   const int lane = lane_id();
   const int64_t n = n_list ? (int64_t)readfirstlane_i(*n_list) : n_tgt;
@@ -724,32 +726,67 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
         hi[d] = g.nc[d] - 1;
     }
     const double delta2 = delta == DBL_MAX ? DBL_MAX : delta * delta;
+    // the block's runs of cells along x, one per lane: their bounds are
+    // fetched together, and the candidates of all runs are numbered by an
+    // exclusive prefix over the runs, so that a lane finds the source of
+    // candidate e by a binary search and the loads of KU chunks of 64
+    // candidates are in flight at once
+    const int ny = hi[1] - lo[1] + 1;
+    const int nrun = readfirstlane_i(ny * (hi[2] - lo[2] + 1));
+    if (nrun > 64) {  // blocks wider than the wavefront: the next pass
+      if (lane == 0) slow[atomicAdd(n_slow, 1)] = t;
+      continue;
+    }
+    int rb = 0, rl = 0;
+    if (lane < nrun) {
+      const int row = g.nc[0] * ((lo[1] + lane % ny) + g.nc[1] * (lo[2] + lane / ny));
+      rb = cell_start[row + lo[0]];
+      rl = cell_start[row + hi[0] + 1] - rb;
+    }
+    int incl = rl;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const int total = readlane_i(incl, 63);
+    wave_lds_sync();  // the previous target's reads of the run tables are done
+    rpre[lane] = lane < nrun ? incl - rl : INT_MAX;
+    roff[lane] = rb - (incl - rl);
+    wave_lds_sync();
     int fill = 0;
-    for (int cz = lo[2]; cz <= hi[2]; ++cz)
-      for (int cy = lo[1]; cy <= hi[1]; ++cy) {
-        const int row = g.nc[0] * (cy + g.nc[1] * cz);
-        const int beg = readfirstlane_i(cell_start[row + lo[0]]);
-        const int end = readfirstlane_i(cell_start[row + hi[0] + 1]);
-        for (int b = beg; b < end; b += 64) {
-          const int p = b + lane;
-          bool ok = false;
-          double dd = 0.0;
-          int id = 0;
-          if (p < end) {
-            const SPoint sp = pts[p];
-            dd = dist2_exact<DIM>(sp, x);
-            id = sp.idx;
-            ok = dd < delta2;
-          }
-          uint64_t m;
-          const int pre = ballot_prefix(ok, &m);
-          if (ok && fill + pre < CAP) {
-            cd[fill + pre] = dd;
-            ci[fill + pre] = id;
-          }
-          fill += __popcll(m);
-        }
+    for (int base = 0; base < total; base += 64 * KU) {
+      SPoint sp[KU];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int e = base + 64 * u + lane;
+        // the last run starting at or before e (rpre[0] = 0; rpre is
+        // non-decreasing and INT_MAX past the last run)
+        int q = 0;
+#pragma unroll
+        for (int st = 32; st >= 1; st >>= 1) q = rpre[q + st] <= e ? q + st : q;
+        if (e < total) sp[u] = pts[roff[q] + e];
       }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int e = base + 64 * u + lane;
+        bool ok = false;
+        double dd = 0.0;
+        int id = 0;
+        if (e < total) {
+          dd = dist2_exact<DIM>(sp[u], x);
+          id = sp[u].idx;
+          ok = dd < delta2;
+        }
+        uint64_t m;
+        const int pre = ballot_prefix(ok, &m);
+        if (ok && fill + pre < CAP) {
+          cd[fill + pre] = dd;
+          ci[fill + pre] = id;
+        }
+        fill += __popcll(m);
+      }
+    }
     if (fill < k || fill > CAP) {  // not provably covered, or too many: the next pass
       if (lane == 0) slow[atomicAdd(n_slow, 1)] = t;
       continue;
