@@ -419,13 +419,15 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
 }
 
 // A scalar set (ss) and a divergence-free set (sv) on the same neighbour
-// lists, mixed precision, the same scheme for both: with the wavefront scheme
-// one kernel forms the moments and the swept Gram of each target once for
-// both; with the pipeline the moments (and per-target records) of the scalar
-// set's run are taken by the divergence-free set's solve and weights.  Bins
-// follow the scalar basis (bin 0: N < Q_s); the divergence-free set's bin-0
-// targets, which its own call would have handled through the FP64 kernel's
-// queue, go to that kernel directly.
+// lists.  FP64 (scheme < 0): one QR kernel takes the Householder factor of
+// each target once for both sets.  Mixed precision, the same scheme for both:
+// with the wavefront scheme one kernel forms the moments and the swept Gram
+// of each target once for both; with the pipeline the moments (and
+// per-target records) of the scalar set's run are taken by the
+// divergence-free set's solve and weights.  Bins follow the scalar basis
+// (bin 0: N < Q_s); the divergence-free set's bin-0 targets, which its own
+// call would have handled through the FP64 kernel's queue, go to that kernel
+// directly.
 static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
                               int64_t n_tgt, int dim, int order, int weight_p, const double *eps,
                               const int64_t *row_ptr, const int32_t *col, const gmls_stencil_set &ss,
@@ -497,7 +499,7 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[1], s));
   // the FP64 kernels' targets were computed outside the mixed path: status 2
   StencilArgs afv = av;
-  afv.ok_status = GMLS_TARGET_FALLBACK;
+  afv.ok_status = scheme < 0 ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
   if (!sync || hm.count[0] > 0) {
     GMLS_HIP(launch_rank_deficient(as, 1, list, meta, s));
     GMLS_HIP(launch_qr_bin(dim, order, GMLS_BASIS_DIVFREE, 0, afv, list, meta, ctx->cus * 8, s));
@@ -506,7 +508,14 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
   afs.ok_status = -1;  // keep the fallback status set by the mixed kernel
   StencilArgs afv2 = av;
   afv2.ok_status = -1;
-  if (scheme == MIXED_WAVE) {
+  if (scheme < 0) {
+    for (int b = 1; b < kNumBins; ++b) {
+      if (sync && hm.count[b] == 0) continue;
+      const int cnt = sync ? hm.count[b] : n;  // sizes the grid; the kernel reads the count on the device
+      GMLS_HIP(launch_qr_shared_bin(dim, order, b, as, av, list, meta, std::min(cnt, ctx->cus * 16), s));
+    }
+    if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
+  } else if (scheme == MIXED_WAVE) {
     GMLS_HIP(launch_mixed_wave_shared(dim, order, as, fbs, &meta->fb_count, av, fbv, &meta->fb2_count, list,
                                       sync ? &hm : nullptr, meta, stats, opt, n, ctx->cus, s));
     if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
@@ -599,14 +608,16 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
       return gmls_set_error(ctx, GMLS_ERR_ARG, "a set's basis must be GMLS_BASIS_SCALAR or GMLS_BASIS_DIVFREE");
     (sets[k].basis == GMLS_BASIS_SCALAR ? is : iv) = k;
   }
-  int scheme = -1;
-  if (n_sets == 2 && is >= 0 && iv >= 0 && prec == GMLS_PREC_MIXED && (dim == 2 || dim == 3) && order >= 1 &&
-      order <= 4) {
+  const bool pair = n_sets == 2 && is >= 0 && iv >= 0 && (dim == 2 || dim == 3) && order >= 1 && order <= 4;
+  int scheme = -2;  // -1: FP64, shared factor
+  if (pair && prec == GMLS_PREC_FP64) {
+    scheme = -1;
+  } else if (pair && prec == GMLS_PREC_MIXED) {
     const int s0 = mixed_scheme(dim, order, GMLS_BASIS_SCALAR, ctx->opt.scheme);
     const int s1 = mixed_scheme(dim, order, GMLS_BASIS_DIVFREE, ctx->opt.scheme);
     if (s0 == s1 && (s0 == MIXED_WAVE || s0 == MIXED_PIPE)) scheme = s0;
   }
-  if (scheme >= 0)
+  if (scheme >= -1)
     return run_shared(ctx, coords, n_src, targets, n_tgt, dim, order, weight_p, eps, row_ptr, col, sets[is],
                       sets[iv], scheme, report);
   gmls_status ret = GMLS_OK;

@@ -213,6 +213,10 @@ hipError_t launch_mixed_wave_shared(int dim, int order, const StencilArgs &as, i
                                     const StencilArgs &av, int *fbv, int *fbv_count, const int *list,
                                     const BinMeta *hm, BinMeta *meta, Stats *stats, const Options &opt, int n_max,
                                     int cus, hipStream_t s);
+// FP64 QR of bin `bin` for a scalar set (as) and a divergence-free set (av)
+// on the same neighbour lists: one Householder factor per target for both
+hipError_t launch_qr_shared_bin(int dim, int order, int bin, const StencilArgs &as, const StencilArgs &av,
+                                const int *list, BinMeta *meta, int n_blocks, hipStream_t s);
 // the queued divergence-free targets of aux_list[0 .. *count)
 hipError_t launch_qr_kmat(int dim, int order, const StencilArgs &a, const int *list, const int *count,
                           int *cursor, int n_blocks, hipStream_t s);

@@ -12,6 +12,7 @@
 #define GMLS_CAT(a, b, c, d, e, f) GMLS_CAT2(a, b, c, d, e, f)
 #define GMLS_FN GMLS_CAT(launch_qr_d, GMLS_DIM, _o, GMLS_ORDER, _b, GMLS_BASIS)
 #define GMLS_KMAT_FN GMLS_CAT(launch_qr_kmat_d, GMLS_DIM, _o, GMLS_ORDER, , )
+#define GMLS_SHARED_FN GMLS_CAT(launch_qr_shared_d, GMLS_DIM, _o, GMLS_ORDER, , )
 
 namespace gmls {
 
@@ -33,6 +34,19 @@ hipError_t GMLS_FN(int rpl, const StencilArgs &a, const int *list, const int *co
 hipError_t GMLS_KMAT_FN(const StencilArgs &a, const int *list, const int *count, int *cursor, int n_blocks,
                         hipStream_t s) {
   k_qr_kmat<GMLS_DIM, GMLS_ORDER, 4><<<n_blocks, 64, 0, s>>>(a, list, count, cursor);
+  return hipGetLastError();
+}
+
+// a scalar and a divergence-free set from one factor per target
+hipError_t GMLS_SHARED_FN(int rpl, const StencilArgs &as, const StencilArgs &av, const int *list, const int *count,
+                          const int *offset, int *cursor, int n_blocks, hipStream_t s) {
+  constexpr int D = GMLS_DIM, O = GMLS_ORDER;
+  switch (rpl) {
+    case 1: k_qr_shared<D, O, 1><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
+    case 2: k_qr_shared<D, O, 2><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
+    case 3: k_qr_shared<D, O, 3><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
+    default: k_qr_shared<D, O, 4><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
+  }
   return hipGetLastError();
 }
 #endif

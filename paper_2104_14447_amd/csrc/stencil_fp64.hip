@@ -74,6 +74,36 @@ hipError_t launch_qr_kmat(int dim, int order, const StencilArgs &a, const int *l
   return kKmat[dim - 2][order - 1](a, list, count, cursor, n_blocks, s);
 }
 
+hipError_t launch_qr_shared_d2_o1(int, const StencilArgs &, const StencilArgs &, const int *, const int *,
+                                   const int *, int *, int, hipStream_t);
+hipError_t launch_qr_shared_d2_o2(int, const StencilArgs &, const StencilArgs &, const int *, const int *,
+                                   const int *, int *, int, hipStream_t);
+hipError_t launch_qr_shared_d2_o3(int, const StencilArgs &, const StencilArgs &, const int *, const int *,
+                                   const int *, int *, int, hipStream_t);
+hipError_t launch_qr_shared_d2_o4(int, const StencilArgs &, const StencilArgs &, const int *, const int *,
+                                   const int *, int *, int, hipStream_t);
+hipError_t launch_qr_shared_d3_o1(int, const StencilArgs &, const StencilArgs &, const int *, const int *,
+                                   const int *, int *, int, hipStream_t);
+hipError_t launch_qr_shared_d3_o2(int, const StencilArgs &, const StencilArgs &, const int *, const int *,
+                                   const int *, int *, int, hipStream_t);
+hipError_t launch_qr_shared_d3_o3(int, const StencilArgs &, const StencilArgs &, const int *, const int *,
+                                   const int *, int *, int, hipStream_t);
+hipError_t launch_qr_shared_d3_o4(int, const StencilArgs &, const StencilArgs &, const int *, const int *,
+                                   const int *, int *, int, hipStream_t);
+
+using SharedFn = hipError_t (*)(int, const StencilArgs &, const StencilArgs &, const int *, const int *, const int *,
+                                int *, int, hipStream_t);
+static const SharedFn kShared[2][4] = {
+    {launch_qr_shared_d2_o1, launch_qr_shared_d2_o2, launch_qr_shared_d2_o3, launch_qr_shared_d2_o4},
+    {launch_qr_shared_d3_o1, launch_qr_shared_d3_o2, launch_qr_shared_d3_o3, launch_qr_shared_d3_o4}};
+
+hipError_t launch_qr_shared_bin(int dim, int order, int bin, const StencilArgs &as, const StencilArgs &av,
+                                const int *list, BinMeta *meta, int n_blocks, hipStream_t s) {
+  if (!qr_supported(dim, order, 1)) return hipErrorInvalidValue;
+  return kShared[dim - 2][order - 1](bin, as, av, list, meta->count + bin, meta->offset + bin, meta->cursor + bin,
+                                     n_blocks, s);
+}
+
 using QrFn = hipError_t (*)(int, const StencilArgs &, const int *, const int *, const int *, int *, int, hipStream_t);
 // [dim - 2][order - 1][basis]: basis 0 scalar, 1 divergence-free, 2 staggered
 static const QrFn kQr[2][4][3] = {

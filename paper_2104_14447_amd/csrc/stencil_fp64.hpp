@@ -134,23 +134,15 @@ __device__ __forceinline__ double tri_solve_rtr(const double *Rm, const double *
   return b;
 }
 
-// SKIP = 1 drops the constant monomial: the staggered scheme (Section 2.4).
-// Its sample of the vector basis phi_(a,k) = e_k p_a along the segment
-// x_T -> x_j is xi = eps s_k p_a(s) / (|a| + 1); the span of those columns is
-// that of the scalar monomials of degree 1..m+1 evaluated at s (by Euler's
-// relation every homogeneous h of degree n+1 is grad(h) . s / (n+1)), and
-// the gradient and divergence of the fit at x_T are the first and second
-// derivatives of the scalar fit there.  The data are p_j - p(x_T), so the
-// target's own value carries the weight -sum_j alpha_j (into hweights).
+// The target's rows, its weighted sample matrix and the Householder factor:
+// on return lane k < Q holds row k of R in M[0][k..Q-1] and rdiag = R_kk.
 template <int DIM, int ORDER, int RPL, int SKIP = 0>
-__device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
-  constexpr Mono<DIM, ORDER> MO{};
-  constexpr int QF = MO.N;       // monomials of degree <= ORDER
-  constexpr int Q = QF - SKIP;   // columns of the sample matrix
-  const int lane = lane_id();
-  Rows<DIM, RPL> r;
+__device__ __forceinline__ void qr_factor(const StencilArgs &a, int t, Rows<DIM, RPL> &r,
+                                          double (&M)[RPL][num_mono(DIM, ORDER) - SKIP], double &rdiag,
+                                          int lane) {
+  constexpr int QF = num_mono(DIM, ORDER);
+  constexpr int Q = QF - SKIP;
   load_rows<DIM, RPL>(a, t, r, lane);
-  double M[RPL][Q];
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     double p[QF];
@@ -159,8 +151,28 @@ __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t
 #pragma unroll
     for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q + SKIP];
   }
-  double rdiag;
   wave_householder<Q, RPL>(M, rdiag, lane);
+}
+
+// SKIP = 1 drops the constant monomial: the staggered scheme (Section 2.4).
+// Its sample of the vector basis phi_(a,k) = e_k p_a along the segment
+// x_T -> x_j is xi = eps s_k p_a(s) / (|a| + 1); the span of those columns is
+// that of the scalar monomials of degree 1..m+1 evaluated at s (by Euler's
+// relation every homogeneous h of degree n+1 is grad(h) . s / (n+1)), and
+// the gradient and divergence of the fit at x_T are the first and second
+// derivatives of the scalar fit there.  The data are p_j - p(x_T), so the
+// target's own value carries the weight -sum_j alpha_j (into hweights).
+//
+// The weights from the factor (lane k < Q holds row k of R in Rrow[k..Q-1],
+// rdiag = R_kk): rank test, R to LDS, the functionals' solves and the rows.
+template <int DIM, int ORDER, int RPL, int SKIP = 0>
+__device__ __forceinline__ void qr_scalar_solve(const StencilArgs &a, const RowKinds &rk, int t,
+                                                const Rows<DIM, RPL> &r, const double (&Rrow)[num_mono(DIM, ORDER) - SKIP],
+                                                double rdiag, double *lds) {
+  constexpr Mono<DIM, ORDER> MO{};
+  constexpr int QF = MO.N;       // monomials of degree <= ORDER
+  constexpr int Q = QF - SKIP;   // columns of the sample matrix
+  const int lane = lane_id();
   const double amax = uniform_d(wave_max(lane < Q ? fabs(rdiag) : 0.0));
   const double amin = uniform_d(wave_min(lane < Q ? fabs(rdiag) : DBL_MAX));
   double *Rm = lds, *Rt = lds + Q * Q, *Y = lds + 2 * Q * Q;
@@ -180,7 +192,7 @@ __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t
   if (lane < Q) {
 #pragma unroll
     for (int l = 0; l < Q; ++l) {
-      const double v = l >= lane ? M[0][l] : 0.0;
+      const double v = l >= lane ? Rrow[l] : 0.0;
       Rm[lane * Q + l] = v;
       Rt[l * Q + lane] = v;
     }
@@ -251,6 +263,16 @@ __device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t
   }
   if (lane == 0 && a.ok_status >= 0) a.status[t] = (uint8_t)a.ok_status;
   __syncthreads();
+}
+
+template <int DIM, int ORDER, int RPL, int SKIP = 0>
+__device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
+  constexpr int Q = num_mono(DIM, ORDER) - SKIP;
+  Rows<DIM, RPL> r;
+  double M[RPL][Q];
+  double rdiag;
+  qr_factor<DIM, ORDER, RPL, SKIP>(a, t, r, M, rdiag, lane_id());
+  qr_scalar_solve<DIM, ORDER, RPL, SKIP>(a, rk, t, r, M[0], rdiag, lds);
 }
 
 }  // namespace gmls

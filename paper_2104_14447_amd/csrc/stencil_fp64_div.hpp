@@ -52,8 +52,14 @@ constexpr int qr_divfree_lds_doubles() {
   return 2 * Q * Q + 2 * QM * QM + 3 * 64 + 8 * DIM * Q;
 }
 
-template <int DIM, int ORDER, int RPL>
-__device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
+// The divergence-free weights from the scalar factor (qr_factor: lane k < Q
+// holds row k of R in Rrow[k..Q-1], rdiag = R_kk).  R_IN_LDS: R is already
+// in lds[0 .. Q*Q) row-major (qr_scalar_solve leaves it there whenever it
+// passes the same rank test), and Rrow is not read.
+template <int DIM, int ORDER, int RPL, bool R_IN_LDS = false>
+__device__ __forceinline__ void qr_divfree_solve(const StencilArgs &a, const RowKinds &rk, int t,
+                                                 const Rows<DIM, RPL> &r, const double (&Rrow)[num_mono(DIM, ORDER)],
+                                                 double rdiag, double *lds) {
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int QM = num_mono(DIM, ORDER - 1);
   constexpr int KB = DIM * Q;            // rows of B
@@ -61,24 +67,9 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
   constexpr DivUpIndex<DIM, ORDER> DU{};
   constexpr MonoIndex<DIM, ORDER> MI{};
   const int lane = lane_id();
-  Rows<DIM, RPL> r;
-  load_rows<DIM, RPL>(a, t, r, lane);
-  double rdiag;
-  {
-    double M[RPL][Q];
+  if (!R_IN_LDS && lane < Q) {
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      double p[Q];
-      scaled_basis<DIM, ORDER, double>(r.s[i], p);
-      const double sw = sqrt(r.w[i]);
-#pragma unroll
-      for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q];
-    }
-    wave_householder<Q, RPL>(M, rdiag, lane);
-    if (lane < Q) {
-#pragma unroll
-      for (int l = 0; l < Q; ++l) lds[lane * Q + l] = l >= lane ? M[0][l] : 0.0;
-    }
+    for (int l = 0; l < Q; ++l) lds[lane * Q + l] = l >= lane ? Rrow[l] : 0.0;
   }
   const int F = a.F;
   double *Rs = lds;                 // R, row-major
@@ -231,6 +222,16 @@ __device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int 
   }
   if (lane == 0 && a.ok_status >= 0) a.status[t] = (uint8_t)a.ok_status;
   __syncthreads();
+}
+
+template <int DIM, int ORDER, int RPL>
+__device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
+  constexpr int Q = num_mono(DIM, ORDER);
+  Rows<DIM, RPL> r;
+  double M[RPL][Q];
+  double rdiag;
+  qr_factor<DIM, ORDER, RPL>(a, t, r, M, rdiag, lane_id());
+  qr_divfree_solve<DIM, ORDER, RPL>(a, rk, t, r, M[0], rdiag, lds);
 }
 
 }  // namespace gmls

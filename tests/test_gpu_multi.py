@@ -1,10 +1,11 @@
 """Several stencil sets on one neighbour list (gmls_stencils_multi).
 
 A scalar and a divergence-free set of the same order share the moments and
-the swept Gram in the wavefront scheme; each set's result must be the one
-gmls_stencils gives for it alone (bit for bit: the shared kernel runs the
-same arithmetic in the same order), and therefore within the gates of the
-oracle.  Other combinations run the sets in turn."""
+the swept Gram in the wavefront scheme, the moments on the pipeline, and the
+Householder factor in FP64; each set's result must be the one gmls_stencils
+gives for it alone (bit for bit: the shared kernels run the same arithmetic
+in the same order), and therefore within the gates of the oracle.  Other
+combinations run the sets in turn."""
 import numpy as np
 import pytest
 
@@ -78,12 +79,37 @@ def test_shared_pipeline_moments_equal_separate_calls(name):
     assert errs[st != 1].max() <= MIXED_TOL
 
 
+@pytest.mark.parametrize("name,order,p", [("3d_divfree_m2", 2, 4), ("2d_divfree_m2", 2, 4),
+                                          ("3d_divfree_m2_k9", 2, 4), ("3d_divfree_m4", 4, 6),
+                                          ("3d_divfree_m4_k30", 4, 6)])
+def test_fp64_shared_factor_equals_separate_calls(name, order, p):
+    """FP64: one Householder factor per target serves the scalar and the
+    divergence-free set; each set's weights and statuses are those of its own
+    call bit for bit (the same steps in the same order), and the
+    divergence-free set is within the FP64 gate of the oracle."""
+    G = require_gpu()
+    pts, rp, col, eps, w, st, F, C = case_data(name)
+    dmask = G.F_VALUE | G.F_LAPLACIAN | G.F_DIV if order == 2 else G.F_LAPLACIAN | G.F_DIV
+    sets = [(G.BASIS_SCALAR, G.F_GRAD | G.F_LAPLACIAN), (G.BASIS_DIVFREE, dmask)]
+    flush(f"FP64 shared factor {name}")
+    got, rep = multi(G, pts, rp, col, eps, order, p, sets, G.PREC_FP64)
+    ref = separate(G, pts, rp, col, eps, order, p, sets, G.PREC_FP64)
+    flush(f"  report {rep}")
+    for (gw, gs), (rw, rs) in zip(got, ref):
+        assert np.array_equal(gs, rs)
+        assert np.array_equal(gw.view(np.uint64), rw.view(np.uint64))
+    gw, gs = got[1]
+    assert np.array_equal(gs == 1, st == 1)
+    errs = row_errors(gw, w, rp, F, C, zero_rows=(F - 1,))
+    assert errs[st != 1].max() <= FP64_TOL
+
+
 def test_sets_in_turn_equal_separate_calls():
-    """FP64, or a scheme without sharing: the sets run one after the other."""
+    """Two sets of one basis are not shared: they run one after the other."""
     G = require_gpu()
     pts, rp, col, eps, _, _, _, _ = case_data("3d_divfree_m2")
-    sets = [(G.BASIS_DIVFREE, G.F_VALUE | G.F_LAPLACIAN), (G.BASIS_SCALAR, G.F_GRAD)]
-    for prec in (G.PREC_FP64,):
+    sets = [(G.BASIS_SCALAR, G.F_VALUE | G.F_LAPLACIAN), (G.BASIS_SCALAR, G.F_GRAD)]
+    for prec in (G.PREC_FP64, G.PREC_MIXED):
         flush(f"sets in turn prec={prec}")
         got, _ = multi(G, pts, rp, col, eps, 2, 4, sets, prec)
         ref = separate(G, pts, rp, col, eps, 2, 4, sets, prec)
