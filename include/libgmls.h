@@ -343,13 +343,15 @@ gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, cons
  * D c = 0, so a scalar set and a divergence-free set can share it.  The
  * result of each set is that of gmls_stencils with the same arguments (bit
  * for bit where nothing is shared, within the precision's gate otherwise).
- * Shared: with prec = GMLS_PREC_MIXED, exactly one scalar and one
- * divergence-free set, and the same scheme for both: the wavefront scheme
- * (GMLS_OPT_MIXED_SCHEME 4, automatic for order 4 in 3D), where one kernel
- * forms the moments and the swept Gram of a target once for both sets, or
- * the pipeline (scheme 3, automatic for order 2 in 3D), where the
- * divergence-free set's solve takes the scalar set's moments.  Other
- * combinations run the sets in turn.
+ * Shared, for exactly one scalar and one divergence-free set: with
+ * prec = GMLS_PREC_FP64 one QR kernel takes the Householder factor R of a
+ * target's weighted sample matrix once for both sets (G = R^T R; the weights
+ * equal those of separate calls bit for bit); with prec = GMLS_PREC_MIXED and
+ * the same scheme for both, the wavefront scheme (GMLS_OPT_MIXED_SCHEME 4,
+ * automatic for order 4 in 3D), where one kernel forms the moments and the
+ * swept Gram of a target once for both sets, or the pipeline (scheme 3,
+ * automatic for order 2 in 3D), where the divergence-free set's solve takes
+ * the scalar set's moments.  Other combinations run the sets in turn.
  *   sets, n_sets  host array of 1..8 sets: basis (GMLS_BASIS_SCALAR or
  *                 GMLS_BASIS_DIVFREE), functional_mask, weights (device,
  *                 F*C_in*nnz doubles, layout of gmls_stencils) and
