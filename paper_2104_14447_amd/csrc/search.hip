@@ -684,6 +684,28 @@ __device__ __forceinline__ void wave_sort_pair(double (&d)[EPL], int (&id)[EPL],
   }
 }
 
+// the n <= 64*EPL pairs of bd/bi sorted by (d^2, index); the first k are the
+// target's row, the k-th distance defines eps
+template <int EPL>
+__device__ __forceinline__ void knn_sort_write(const double *bd, const int *bi, int n, int k, int t,
+                                               double eps_mult, int32_t *col, double *eps, int lane) {
+  double kd[EPL];
+  int kid[EPL];
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    const int e = lane * EPL + r;
+    kd[r] = e < n ? bd[e] : DBL_MAX;
+    kid[r] = e < n ? bi[e] : INT_MAX;
+  }
+  wave_sort_pair<EPL>(kd, kid, lane);
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    const int e = lane * EPL + r;
+    if (e < k) col[(int64_t)t * k + e] = kid[r];
+    if (e == k - 1) eps[t] = eps_mult * sqrt(kd[r]);
+  }
+}
+
 // One wavefront per target of `list` (or of order[0, n_tgt) when n_list is
 // null): candidates of the block of cells within R of the target's cell that
 // are closer than the block's inner margin delta go to LDS (at most 64*EPLL);
@@ -792,16 +814,15 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
       continue;
     }
     wave_lds_sync();
-    double kd[EPLS];
-    int kid[EPLS];
-    if (fill <= SCAP) {
-#pragma unroll
-      for (int r = 0; r < EPLS; ++r) {
-        const int e = lane * EPLS + r;
-        kd[r] = e < fill ? cd[e] : DBL_MAX;
-        kid[r] = e < fill ? ci[e] : INT_MAX;
-      }
-    } else {
+    // the sort takes 64*EPLS pairs, or half as many when k fits in half: the
+    // bisection then aims at the half (a narrower network), and keeps the
+    // full width when ties leave more than half
+    constexpr int EH = EPLS >= 2 ? EPLS / 2 : EPLS;
+    const int cap = EPLS >= 2 && k <= 64 * EH ? 64 * EH : SCAP;
+    const double *bd = cd;
+    const int *bi = ci;
+    int nb = fill;
+    if (fill > cap) {
       double dl[EPLL];
       double hiT = 0.0;
 #pragma unroll
@@ -813,8 +834,8 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
       hiT = uniform_d(wave_max(hiT));
       double loT = 0.0;
       int cnt = fill;
-      // invariant: count(d^2 <= hiT) >= k; stop once it is <= SCAP
-      for (int it = 0; it < 64 && cnt > SCAP; ++it) {
+      // invariant: count(d^2 <= hiT) >= k; stop once it is <= cap
+      for (int it = 0; it < 64 && cnt > cap; ++it) {
         const double mid = 0.5 * (loT + hiT);
         if (!(mid > loT && mid < hiT)) break;
         int c = 0;
@@ -847,20 +868,14 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
         sf += __popcll(m);
       }
       wave_lds_sync();
-#pragma unroll
-      for (int r = 0; r < EPLS; ++r) {
-        const int e = lane * EPLS + r;
-        kd[r] = e < sf ? sd[e] : DBL_MAX;
-        kid[r] = e < sf ? si[e] : INT_MAX;
-      }
+      bd = sd;
+      bi = si;
+      nb = sf;
     }
-    wave_sort_pair<EPLS>(kd, kid, lane);
-#pragma unroll
-    for (int r = 0; r < EPLS; ++r) {
-      const int e = lane * EPLS + r;
-      if (e < k) col[(int64_t)t * k + e] = kid[r];
-      if (e == k - 1) eps[t] = eps_mult * sqrt(kd[r]);
-    }
+    if (nb <= 64 * EH)
+      knn_sort_write<EH>(bd, bi, nb, k, t, eps_mult, col, eps, lane);
+    else
+      knn_sort_write<EPLS>(bd, bi, nb, k, t, eps_mult, col, eps, lane);
     wave_lds_sync();  // the buffers are refilled for the next target
   }
 }
