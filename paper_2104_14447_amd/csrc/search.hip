@@ -834,8 +834,11 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
       hiT = uniform_d(wave_max(hiT));
       double loT = 0.0;
       int cnt = fill;
-      // invariant: count(d^2 <= hiT) >= k; stop once it is <= cap
+      // invariant: count(d^2 <= hiT) >= k; stop once it is <= cap, or after
+      // 16 steps aimed at the half once the full width holds the count
+      // (ties at the k-th distance can keep the count above the half)
       for (int it = 0; it < 64 && cnt > cap; ++it) {
+        if (it >= 16 && cnt <= SCAP) break;
         const double mid = 0.5 * (loT + hiT);
         if (!(mid > loT && mid < hiT)) break;
         int c = 0;

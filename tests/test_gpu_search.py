@@ -51,14 +51,20 @@ def assert_same(g, o, tag, sets=False):
     np.testing.assert_allclose(eps, oeps, rtol=2e-16 * 4, atol=0, err_msg=tag)
 
 
-@pytest.mark.parametrize("case", ["c1_2d_k12", "2d_k40", "3d_k60", "3d_k170", "1d_k7"])
+@pytest.mark.parametrize("case", ["c1_2d_k12", "2d_k40", "3d_k60", "3d_k64", "3d_k100", "3d_k170", "1d_k7"])
 def test_knn_matches_oracle(case):
+    # k = 60, 64 and 100 take the half-width sort (64 of 128 and 128 of 256
+    # pairs), 170 the full width
     if case == "c1_2d_k12":
         src, k = W.make_points("c1_2d_m2"), 12
     elif case == "2d_k40":
         src, k = W.jittered_grid(20000, 2, 1002), 40
     elif case == "3d_k60":
         src, k = W.jittered_grid(27000, 3, 1003), 60
+    elif case == "3d_k64":
+        src, k = W.jittered_grid(27000, 3, 1004), 64
+    elif case == "3d_k100":
+        src, k = W.jittered_grid(27000, 3, 1006), 100
     elif case == "3d_k170":
         src, k = W.jittered_grid(27000, 3, 1005), 170
     else:
@@ -71,7 +77,7 @@ def test_knn_exact_grid_ties_and_foreign_targets():
     n = 24
     ax = (np.arange(n) + 0.5) / n
     src = np.stack(np.meshgrid(ax, ax, indexing="ij"), -1).reshape(-1, 2)[:, ::-1].copy()
-    for k in (1, 5, 9, 21, 50):
+    for k in (1, 5, 9, 21, 50, 60, 64, 100):  # 60..100: ties against the half-width sort
         flush(f"grid ties k={k}")
         assert_same(gpu_knn(src, src, k), oracle.knn(src, src, k, 1.5), f"ties k={k}")
     tgt = W.rng(8).uniform(-0.5, 1.5, size=(300, 2))
