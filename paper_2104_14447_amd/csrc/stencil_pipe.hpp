@@ -777,13 +777,27 @@ __global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const Pi
   const int first = R.first, last = R.last, c0 = R.c0;
   constexpr int QS = num_mono(DIM, ORDER);
   constexpr int TPW = 64 / G;
+  constexpr int CW = DIM * QS;                 // coefficients of one target and row
+  constexpr int NL = (TPW * CW + 63) / 64;     // of the wavefront's targets, per lane
   constexpr InvFact64<DIM, ORDER> IFW{};
   __shared__ double stage[64 * DIM];  // group g: [g * G * DIM, (g + 1) * G * DIM)
+  __shared__ double cfs[2][TPW * CW];  // row f's coefficients of the wavefront's targets, by f % 2
   const int lane = lane_id();
   const int grp = lane / G, lg = lane % G;
   const int F = a.F, FC = F * DIM;
   double *gst = stage + grp * G * DIM;
   for (int i0 = first + xcd_block() * TPW; i0 < last; i0 += gridDim.x * TPW) {
+    // the coefficients of row f of the wavefront's TPW targets, fetched by
+    // all lanes together one row ahead (row 0 with the neighbour gathers)
+    double pre[NL];
+    auto fetch = [&](int f) {
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int e = lane + 64 * u, tt = e / CW;
+        pre[u] = e < TPW * CW && i0 + tt < last ? gin[((int64_t)(i0 + tt - c0) * FC * QS) + f * CW + (e - tt * CW)] : 0.0;
+      }
+    };
+    fetch(0);
     const int i = i0 + grp;
     const bool valid = i < last;
     const int64_t loc = (valid ? i : first) - c0;
@@ -801,11 +815,19 @@ __global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const Pi
     for (int r = 0; r < RPL; ++r) w[r] = row_sw<DIM>(xs[r], xt, rc.ie, a.p, true, s[r]);
     double *wout = a.weights + (int64_t)FC * base;
     for (int f = 0; f < F; ++f) {
+      double *cb = cfs[f & 1];
+#pragma unroll
+      for (int u = 0; u < NL; ++u) {
+        const int e = lane + 64 * u;
+        if (e < TPW * CW) cb[e] = pre[u];
+      }
+      __syncthreads();
+      if (f + 1 < F) fetch(f + 1);
       double cf[DIM][QS];
 #pragma unroll
       for (int c = 0; c < DIM; ++c)
 #pragma unroll
-        for (int q = 0; q < QS; ++q) cf[c][q] = gin[(loc * FC + f * DIM + c) * QS + q] * IFW.v[q];
+        for (int q = 0; q < QS; ++q) cf[c][q] = cb[grp * CW + c * QS + q] * IFW.v[q];
 #pragma unroll
       for (int r = 0; r < RPL; ++r) {
 #pragma unroll
