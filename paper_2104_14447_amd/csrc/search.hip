@@ -899,8 +899,9 @@ template <int DIM>
 static bool launch_knn_reg(const GridParams *gp, const SPoint *pts, const int *start, const double *targets,
                            const int *order, int64_t n_tgt, int k, double mult, int32_t *col, double *eps,
                            int *lists, int64_t stride, unsigned nb, hipStream_t s) {
-  // first pass keeps up to ~3.9k candidates, the second up to ~9.3k; the
-  // sort holds ~1.3k
+  // <L1, L2, S>: the first pass keeps up to 64*L1 candidates within the
+  // block's margin, the second up to 64*L2; the register sort holds 64*S
+  // pairs (k <= 64*S; half of it when k fits there)
   if (k <= 16)
     knn_reg_passes<DIM, 1, 4, 1>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 32)
