@@ -103,11 +103,14 @@ def test_capture_safe_reports_capacity_through_check():
     c.close()
 
 
-@pytest.mark.parametrize("order,k,p", [(4, 170, 6), (2, 60, 4)], ids=["wave", "pipeline"])
-def test_graph_replays_shared_multi(order, k, p):
+@pytest.mark.parametrize("order,k,p,fp64", [(4, 170, 6, False), (2, 60, 4, False), (4, 170, 6, True)],
+                         ids=["wave", "pipeline", "fp64"])
+def test_graph_replays_shared_multi(order, k, p, fp64):
     """A kNN search and one gmls_stencils_multi call (scalar + divergence-free
-    sets sharing the Gram) captured together and replayed, against eager."""
+    sets sharing the Gram, or in FP64 the QR factor) captured together and
+    replayed, against eager."""
     G = require_gpu()
+    prec = G.PREC_FP64 if fp64 else G.PREC_MIXED
     pts = W.jittered_grid(6000, 3, 1005)
     sets = [(G.BASIS_SCALAR, G.F_GRAD | G.F_LAPLACIAN), (G.BASIS_DIVFREE, G.F_LAPLACIAN | G.F_DIV)]
     s = torch.cuda.Stream()
@@ -117,7 +120,7 @@ def test_graph_replays_shared_multi(order, k, p):
         flush(f"graph multi order={order}: eager reference")
         rp, col, eps = G.gmls_neighbors(c, x, x, G.SEARCH_KNN, k=k, eps_mult=1.5)
         ref = [(host(w), host(st)) for w, st in
-               G.gmls_stencils_multi(c, x, x, order, p, eps, rp, col, sets, prec=G.PREC_MIXED)[0]]
+               G.gmls_stencils_multi(c, x, x, order, p, eps, rp, col, sets, prec=prec)[0]]
         nnz = col.numel()
         col_buf = torch.empty(nnz, dtype=torch.int32, device="cuda")
         outs = []
@@ -130,7 +133,7 @@ def test_graph_replays_shared_multi(order, k, p):
 
         def step():
             rp_, col_, eps_ = G.gmls_neighbors(c, x, x, G.SEARCH_KNN, k=k, eps_mult=1.5, col=col_buf)
-            G.gmls_stencils_multi(c, x, x, order, p, eps_, rp_, col_, sets, prec=G.PREC_MIXED, outputs=outs)
+            G.gmls_stencils_multi(c, x, x, order, p, eps_, rp_, col_, sets, prec=prec, outputs=outs)
             gout["rp"] = rp_
 
         def compare(tag):
