@@ -1169,9 +1169,11 @@ __global__ void k_check_capacity(const int64_t *nnz, int64_t capacity, int *flag
   if (threadIdx.x == 0 && *nnz > capacity) atomicOr(flags, 2);
 }
 
-// Rows of the fused pass into place: 16 lanes per target, 64 entries per
-// step (four loads in flight per lane before the stores; consecutive lanes
-// take consecutive entries, so loads and stores stay contiguous).
+// Rows of the fused pass into place: 16 lanes per target, 16*kCopyLoads
+// entries per step (that many loads in flight per lane before the stores, so
+// that most rows take one memory round trip; consecutive lanes take
+// consecutive entries, so loads and stores stay contiguous).
+constexpr int kCopyLoads = 8;
 __global__ __launch_bounds__(256) void k_rows_copy(int64_t n_tgt, const int64_t *row_ptr, const int32_t *rows,
                                                    const uint8_t *dflag, int32_t *col, const int *flags) {
   if (*flags & 2) return;  // over capacity: nothing is written
@@ -1183,15 +1185,15 @@ __global__ __launch_bounds__(256) void k_rows_copy(int64_t n_tgt, const int64_t 
     const int64_t b = row_ptr[t];
     const int n = (int)(row_ptr[t + 1] - b);
     const int32_t *src = rows + t * kSmallCap;
-    for (int q0 = 0; q0 < n; q0 += 64) {
-      int32_t v[4];
+    for (int q0 = 0; q0 < n; q0 += 16 * kCopyLoads) {
+      int32_t v[kCopyLoads];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kCopyLoads; ++u) {
         const int q = q0 + 16 * u + sub;
         v[u] = q < n ? src[q] : 0;
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kCopyLoads; ++u) {
         const int q = q0 + 16 * u + sub;
         if (q < n) col[b + q] = v[u];
       }
