@@ -910,11 +910,10 @@ static bool launch_knn_reg(const GridParams *gp, const SPoint *pts, const int *s
     knn_reg_passes<DIM, 4, 8, 1>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 64)
     knn_reg_passes<DIM, 4, 16, 2>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
-  else if (k <= 128)
-    knn_reg_passes<DIM, 8, 32, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+  else if (k <= 96)
+    knn_reg_passes<DIM, 4, 32, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 192)
-    knn_reg_passes<DIM, 16, 32, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb,
-                                   s);
+    knn_reg_passes<DIM, 8, 32, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 256)
     knn_reg_passes<DIM, 16, 32, 8>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb,
                                    s);

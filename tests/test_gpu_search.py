@@ -51,10 +51,12 @@ def assert_same(g, o, tag, sets=False):
     np.testing.assert_allclose(eps, oeps, rtol=2e-16 * 4, atol=0, err_msg=tag)
 
 
-@pytest.mark.parametrize("case", ["c1_2d_k12", "2d_k40", "3d_k60", "3d_k64", "3d_k100", "3d_k170", "1d_k7"])
+@pytest.mark.parametrize("case", ["c1_2d_k12", "2d_k40", "3d_k60", "3d_k64", "3d_k80", "3d_k100", "3d_k170",
+                                  "1d_k7"])
 def test_knn_matches_oracle(case):
-    # k = 60, 64 and 100 take the half-width sort (64 of 128 and 128 of 256
-    # pairs), 170 the full width
+    # k = 60, 64, 80 and 100 take the half-width sort (64 of 128 and 128 of
+    # 256 pairs), 170 the full width; 80 keeps up to 256 candidates in the
+    # first pass, 100 and 170 up to 512
     if case == "c1_2d_k12":
         src, k = W.make_points("c1_2d_m2"), 12
     elif case == "2d_k40":
@@ -63,6 +65,8 @@ def test_knn_matches_oracle(case):
         src, k = W.jittered_grid(27000, 3, 1003), 60
     elif case == "3d_k64":
         src, k = W.jittered_grid(27000, 3, 1004), 64
+    elif case == "3d_k80":
+        src, k = W.jittered_grid(27000, 3, 1007), 80
     elif case == "3d_k100":
         src, k = W.jittered_grid(27000, 3, 1006), 100
     elif case == "3d_k170":
