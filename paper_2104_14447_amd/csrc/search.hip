@@ -725,8 +725,27 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
   __shared__ double sd[SCAP];
   __shared__ int si[SCAP];
   __shared__ int rpre[64], roff[64];  // per run: first candidate number, source offset
+  // targets left to the next pass, gathered per wavefront and appended to
+  // `slow` 64 at a time (one atomic per 64 rather than one per target: when
+  // most targets are left, as for targets on the boundary of the cloud, a
+  // per-target atomic on the one counter serialises the wavefronts)
+  __shared__ int pend[64];
   const GridParams g = *gp;
   const int lane = lane_id();
+  int npend = 0;  // uniform
+  auto flush_slow = [&]() {
+    wave_lds_sync();
+    int b = 0;
+    if (lane == 0) b = atomicAdd(n_slow, npend);
+    b = readfirstlane_i(b);
+    if (lane < npend) slow[b + lane] = pend[lane];
+    npend = 0;
+    wave_lds_sync();
+  };
+  auto push_slow = [&](int tt) {
+    if (lane == 0) pend[npend] = tt;
+    if (++npend == 64) flush_slow();
+  };
   const int64_t n = n_list ? (int64_t)readfirstlane_i(*n_list) : n_tgt;
   for (int64_t w = blockIdx.x; w < n; w += gridDim.x) {
     const int t = readfirstlane_i(list[w]);
@@ -756,7 +775,7 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
     const int ny = hi[1] - lo[1] + 1;
     const int nrun = readfirstlane_i(ny * (hi[2] - lo[2] + 1));
     if (nrun > 64) {  // blocks wider than the wavefront: the next pass
-      if (lane == 0) slow[atomicAdd(n_slow, 1)] = t;
+      push_slow(t);
       continue;
     }
     int rb = 0, rl = 0;
@@ -810,7 +829,7 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
       }
     }
     if (fill < k || fill > CAP) {  // not provably covered, or too many: the next pass
-      if (lane == 0) slow[atomicAdd(n_slow, 1)] = t;
+      push_slow(t);
       continue;
     }
     wave_lds_sync();
@@ -852,7 +871,7 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
         }
       }
       if (cnt > SCAP) {  // ties beyond the sort capacity: the next pass
-        if (lane == 0) slow[atomicAdd(n_slow, 1)] = t;
+        push_slow(t);
         wave_lds_sync();
         continue;
       }
@@ -881,6 +900,7 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
       knn_sort_write<EPLS>(bd, bi, nb, k, t, eps_mult, col, eps, lane);
     wave_lds_sync();  // the buffers are refilled for the next target
   }
+  if (npend > 0) flush_slow();
 }
 
 // The two register passes for k (block radius 2, then 3 for the targets the
