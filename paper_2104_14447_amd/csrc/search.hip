@@ -921,7 +921,10 @@ static bool launch_knn_reg(const GridParams *gp, const SPoint *pts, const int *s
                            int *lists, int64_t stride, unsigned nb, hipStream_t s) {
   // <L1, L2, S>: the first pass keeps up to 64*L1 candidates within the
   // block's margin, the second up to 64*L2; the register sort holds 64*S
-  // pairs (k <= 64*S; half of it when k fits there)
+  // pairs (k <= 64*S; half of it when k fits there).  The capacities are the
+  // smallest that settle nearly every target of a cloud (interior or on its
+  // boundary) in the two passes: larger ones cost registers and bisection
+  // work on every target
   if (k <= 16)
     knn_reg_passes<DIM, 1, 4, 1>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 32)
@@ -929,11 +932,11 @@ static bool launch_knn_reg(const GridParams *gp, const SPoint *pts, const int *s
   else if (k <= 48)
     knn_reg_passes<DIM, 4, 8, 1>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 64)
-    knn_reg_passes<DIM, 4, 16, 2>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+    knn_reg_passes<DIM, 4, 8, 2>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 96)
-    knn_reg_passes<DIM, 4, 32, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+    knn_reg_passes<DIM, 4, 8, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 192)
-    knn_reg_passes<DIM, 8, 32, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
+    knn_reg_passes<DIM, 8, 16, 4>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb, s);
   else if (k <= 256)
     knn_reg_passes<DIM, 16, 32, 8>(gp, pts, start, targets, order, n_tgt, k, mult, col, eps, lists, stride, nb,
                                    s);
