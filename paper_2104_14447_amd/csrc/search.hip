@@ -721,7 +721,9 @@ __global__ __launch_bounds__(64) void k_knn_reg(const GridParams *gp, const SPoi
   constexpr int CAP = 64 * EPLL, SCAP = 64 * EPLS;
   __shared__ double cd[CAP];
   __shared__ int ci[CAP];
-  constexpr int KU = 4;  // chunks of 64 candidates loaded together
+  // chunks of 64 candidates loaded together: more loads in flight cost
+  // registers and occupancy, which pay only for the larger blocks
+  constexpr int KU = EPLL >= 8 ? 2 : 1;
   __shared__ double sd[SCAP];
   __shared__ int si[SCAP];
   __shared__ int rpre[64], roff[64];  // per run: first candidate number, source offset
