@@ -158,6 +158,10 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB device copy (counter scaling) and exit")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of HIP graph replays of search + stencils")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="mixed workloads: skip the FP64 leg (timed and checked after the mixed one by default)")
+    ap.add_argument("--cpu-seconds-1", type=float, default=6.0,
+                    help="target duration of the one-core oracle timing")
     ap.add_argument("--stokes", type=int, default=0, metavar="N_SIDE",
                     help="time the global Stokes operator build on a [-1,1]^3 cloud of N_SIDE^3 interior "
                          "particles instead")
@@ -232,6 +236,42 @@ def stokes_main(args):
     print(json.dumps(line))
 
 
+def host_info():
+    """Host cores available to this job and the CPU model.  The oracle's
+    timing uses every core of the job's CPU share: the affinity mask, capped
+    by OMP_NUM_THREADS where the launcher sets it (one GPU's share of the
+    host)."""
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    threads = min(avail, int(omp)) if omp.isdigit() and int(omp) > 0 else avail
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": nproc, "affinity": avail, "omp_num_threads": omp or None, "threads": threads,
+            "cpu_model": model}
+
+
+def executed_flops_workload(nnz, n_tgt, dim, bases):
+    """The count of the arithmetic the mixed and FP64-moment kernels do for
+    the Gram: the weighted moments of degree <= 2m, 2*NM flops per
+    neighbour row (NM monomials), in place of the conventional N*Q*(Q+1);
+    the other terms as in alg_flops_workload."""
+    qs_max = max(b["Qs"] for b in bases)
+    order = max(b["order"] + (1 if b["name"] == "staggered" else 0) for b in bases)
+    nm = _binom(2 * order + dim, dim)
+    return alg_flops_workload(nnz, n_tgt, dim, bases) - nnz * qs_max * (qs_max + 1) + nnz * 2 * nm
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -294,7 +334,16 @@ def main():
         Qs = Q if basis != "divfree" else _binom(order + dim, dim)
         bases.append(dict(name=basis, b=b, order=order, mask=mask, F=F, C=C, Q=Q, Qs=Qs))
 
-    def stencils(c, bs, eps_, rp_, col_, weights=None, status=None, aux=None, report=False):
+    precs = {"mixed": G.PREC_MIXED, "fp64": G.PREC_FP64}
+    if args.prec == "auto":
+        prec_name = "mixed" if "mixed" in wl["modes"] else "fp64"
+    else:
+        prec_name = args.prec
+    legs = [prec_name]
+    if prec_name == "mixed" and "fp64" in wl["modes"] and not args.no_fp64:
+        legs.append("fp64")
+
+    def stencils(c, prec, bs, eps_, rp_, col_, weights=None, status=None, aux=None, report=False):
         """One basis of the configuration through its entry point; `aux`
         receives the h-weights (constrained) or target weights (staggered)."""
         if bs["name"] == "staggered":
@@ -308,26 +357,34 @@ def main():
                                       weights=weights, status=status, report=report)
         return w_, None, st_, r_
 
-    precs = {"mixed": G.PREC_MIXED, "fp64": G.PREC_FP64}
-    if args.prec == "auto":
-        prec_name = "mixed" if "mixed" in wl["modes"] else "fp64"
-    else:
-        prec_name = args.prec
-    prec = precs[prec_name]
+    # a scalar and a divergence-free basis of one order on the same neighbour
+    # lists go through one gmls_stencils_multi call (the library shares their
+    # Gram where the scheme allows)
+    shared = len(bases) == 2 and sorted(b["name"] for b in bases) == ["divfree", "scalar"] and \
+        bases[0]["order"] == bases[1]["order"]
 
-    # buffers reused across steps (no allocation inside the timed region)
-    rp, col, eps = G.gmls_neighbors(ctx, x, xt, **spec)
-    nnz = col.numel()
+    def all_stencils(c, prec, eps_, rp_, col_, bufs, report=False):
+        if shared:
+            outs = [(bufs[i]["w"], bufs[i]["st"]) for i in range(len(bases))]
+            return [G.gmls_stencils_multi(c, x, xt, bases[0]["order"], p, eps_, rp_, col_,
+                                          [(bs["b"], bs["mask"]) for bs in bases], prec=prec, outputs=outs,
+                                          report=report)[1]]
+        return [stencils(c, prec, bs, eps_, rp_, col_, weights=bufs[i]["w"], status=bufs[i]["st"],
+                         aux=bufs[i]["aux"], report=report)[3] for i, bs in enumerate(bases)]
+
+    rp0, col0, eps0 = G.gmls_neighbors(ctx, x, xt, **spec)
+    nnz = col0.numel()
     col_buf = torch.empty(int(nnz * 1.05) + 1024, dtype=torch.int32, device=dev)
-    for bs in bases:
-        bs["w"] = torch.empty(bs["F"] * bs["C"] * nnz, dtype=torch.float64, device=dev)
-        bs["st"] = torch.empty(n_t, dtype=torch.uint8, device=dev)
-        bs["aux"] = torch.empty((n_t, bs["F"]), dtype=torch.float64, device=dev)
+
+    def new_bufs():
+        return [dict(w=torch.empty(bs["F"] * bs["C"] * nnz, dtype=torch.float64, device=dev),
+                     st=torch.empty(n_t, dtype=torch.uint8, device=dev),
+                     aux=torch.empty((n_t, bs["F"]), dtype=torch.float64, device=dev)) for bs in bases]
 
     # ---- autotune the mixed pipeline's row shapes (before any timing) ----
     tune_summary = "off"
     tune_path = None
-    if prec == G.PREC_MIXED and not args.no_autotune:
+    if "mixed" in legs and not args.no_autotune:
         if args.tune_cache and os.path.exists(args.tune_cache):
             G.gmls_autotune_load(ctx, args.tune_cache)
             tune_summary = {"loaded": args.tune_cache}
@@ -342,13 +399,13 @@ def main():
                 order_t, b_t = (bs["order"] + 1, G.BASIS_SCALAR) if bs["name"] == "staggered" \
                     else (bs["order"], bs["b"])
                 try:
-                    res = G.gmls_autotune(ctx, x, xt, order_t, b_t, bs["mask"], p, eps, rp, col, reps=3)
+                    res = G.gmls_autotune(ctx, x, xt, order_t, b_t, bs["mask"], p, eps0, rp0, col0, reps=3)
                 except G.GmlsError as e:
                     if e.status != G.GMLS_ERR_UNSUPPORTED:  # not the pipeline: nothing to tune
                         raise
                     continue
-                tune_summary[bs["name"]] = {k: {b: "%dx%d" % v["chosen"] for b, v in d.items()}
-                                            for k, d in res.items()}
+                tune_summary[bs["name"]] = {k_: {b: "%dx%d" % v["chosen"] for b, v in d.items()}
+                                            for k_, d in res.items()}
             print(f"# autotune: {tune_summary} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
             if tune_summary:
                 if args.tune_cache:
@@ -362,217 +419,318 @@ def main():
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    # a scalar and a divergence-free basis of one order on the same neighbour
-    # lists go through one gmls_stencils_multi call (the library shares their
-    # Gram where the scheme allows)
-    shared = len(bases) == 2 and sorted(b["name"] for b in bases) == ["divfree", "scalar"] and \
-        bases[0]["order"] == bases[1]["order"]
+    def run_leg(leg):
+        """Eager steps (per-phase HIP event times, reports), then the timed
+        unit: HIP graph replays of search + stencils.  Returns the figures and
+        the outputs of the last replay."""
+        prec = precs[leg]
+        bufs = new_bufs()
 
-    def all_stencils(c, eps_, rp_, col_, wkey, stkey, auxkey, report=False):
-        if shared:
-            outs = [(bs[wkey], bs[stkey]) for bs in bases]
-            return [G.gmls_stencils_multi(c, x, xt, bases[0]["order"], p, eps_, rp_, col_,
-                                          [(bs["b"], bs["mask"]) for bs in bases], prec=prec, outputs=outs,
-                                          report=report)[1]]
-        return [stencils(c, bs, eps_, rp_, col_, weights=bs[wkey], status=bs[stkey], aux=bs[auxkey],
-                         report=report)[3] for bs in bases]
+        def step(report=False):
+            ev0.record()
+            rp_, col_, eps_ = G.gmls_neighbors(ctx, x, xt, col=col_buf, **spec)
+            ev1.record()
+            reps_ = all_stencils(ctx, prec, eps_, rp_, col_, bufs, report=report)
+            return rp_, col_, eps_, reps_
 
-    def step(report=False):
-        ev0.record()
-        rp_, col_, eps_ = G.gmls_neighbors(ctx, x, xt, col=col_buf, **spec)
-        ev1.record()
-        reps = all_stencils(ctx, eps_, rp_, col_, "w", "st", "aux", report=report)
-        return rp_, col_, eps_, reps
-
-    # ---- eager steps: per-phase GPU times (HIP events on the library's stream) ----
-    for i in range(args.warmup):
-        step()
-        print(f"# warmup step {i} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    stencil_ms, search_ms = [], []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        out = step(report=True)
-        stencil_ms.append(sum(r["t_stencil_ms"] + r["t_fallback_ms"] for r in out[3]))
-        search_ms.append(ev0.elapsed_time(ev1))
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    ms_eager = 1e3 * t_total / args.steps
-    rp_t, col_t, eps_t, reps = out
-    print(f"# eager: {args.steps} steps: {ms_eager:.3f} ms/step; stencil kernels "
-          f"{np.mean(stencil_ms):.3f} ms; search {np.mean(search_ms):.3f} ms; reports {reps}",
-          file=sys.stderr, flush=True)
-    ms_per_step = ms_eager
-
-    # ---- the timed unit: one HIP graph replay of search + stencils ----
-    graph = not args.no_graph
-    if graph:
-        gs = torch.cuda.Stream()
-        gctx = G.Context(0, stream=gs)
-        gctx.set_option(G.OPT_MIXED_SCHEME, args.scheme)
-        if tune_path:
-            G.gmls_autotune_load(gctx, tune_path)  # the same row shapes as the eager steps
-        with torch.cuda.stream(gs):
-            # one normal call of each kind sizes the context's workspace
-            rpw, colw, epsw = G.gmls_neighbors(gctx, x, xt, **spec)
-            for bs in bases:
-                stencils(gctx, bs, epsw, rpw, colw)
-            if shared:
-                G.gmls_stencils_multi(gctx, x, xt, bases[0]["order"], p, epsw, rpw, colw,
-                                      [(bs["b"], bs["mask"]) for bs in bases], prec=prec)
-            gcol = torch.empty(nnz + 1024, dtype=torch.int32, device=dev)
-            for bs in bases:
-                bs["gw"] = torch.empty(bs["F"] * bs["C"] * nnz, dtype=torch.float64, device=dev)
-                bs["gst"] = torch.empty(n_t, dtype=torch.uint8, device=dev)
-                bs["gaux"] = torch.empty((n_t, bs["F"]), dtype=torch.float64, device=dev)
-            gctx.set_option(G.OPT_CAPTURE_SAFE, 1)
-            gout = {}
-
-            def gstep():
-                rp_, col_, eps_ = G.gmls_neighbors(gctx, x, xt, col=gcol, **spec)
-                all_stencils(gctx, eps_, rp_, col_[:nnz], "gw", "gst", "gaux")
-                gout["rp"], gout["eps"] = rp_, eps_
-
-            gstep()  # capture-safe eager run (no allocation happens in the capture)
-            hg = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(hg, stream=gs):
-                gstep()
         for i in range(args.warmup):
-            hg.replay()
+            step()
+            print(f"# {leg}: warmup step {i} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
+        stencil_ms, search_ms = [], []
         t_start = time.perf_counter()
         for i in range(args.steps):
-            hg.replay()
+            out_ = step(report=True)
+            stencil_ms.append(sum(r["t_stencil_ms"] + r["t_fallback_ms"] for r in out_[3]))
+            search_ms.append(ev0.elapsed_time(ev1))
         torch.cuda.synchronize()
-        ms_per_step = 1e3 * (time.perf_counter() - t_start) / args.steps
-        gctx.check()
-        print(f"# graph: {args.steps} replays: {ms_per_step:.3f} ms/step", file=sys.stderr, flush=True)
-        # the parity gate below checks the replayed outputs
-        rp_t, col_t, eps_t = gout["rp"], gcol[:nnz], gout["eps"]
-        for bs in bases:
-            bs["w"], bs["st"], bs["aux"] = bs["gw"], bs["gst"], bs["gaux"]
+        ms_eager = 1e3 * (time.perf_counter() - t_start) / args.steps
+        rp_t, col_t, eps_t, reps_ = out_
+        print(f"# {leg} eager: {args.steps} steps: {ms_eager:.3f} ms/step; stencil kernels "
+              f"{np.mean(stencil_ms):.3f} ms; search {np.mean(search_ms):.3f} ms; reports {reps_}",
+              file=sys.stderr, flush=True)
+        res = {"prec": leg, "ms_eager": ms_eager, "stencil_ms": float(np.mean(stencil_ms)),
+               "search_ms": float(np.mean(search_ms)), "reports": reps_, "ms_per_step": ms_eager,
+               "graph": False}
+        out = {"rp": rp_t, "col": col_t, "eps": eps_t, "bufs": bufs}
+        if not args.no_graph:
+            gs = torch.cuda.Stream()
+            gctx = G.Context(0, stream=gs)
+            gctx.set_option(G.OPT_MIXED_SCHEME, args.scheme)
+            if tune_path and leg == "mixed":
+                G.gmls_autotune_load(gctx, tune_path)  # the same row shapes as the eager steps
+            gbufs = new_bufs()
+            gcol = torch.empty(nnz + 1024, dtype=torch.int32, device=dev)
+            with torch.cuda.stream(gs):
+                # one normal call of each kind sizes the context's workspace
+                rpw, colw, epsw = G.gmls_neighbors(gctx, x, xt, **spec)
+                all_stencils(gctx, prec, epsw, rpw, colw, gbufs)
+                gctx.set_option(G.OPT_CAPTURE_SAFE, 1)
+                gout = {}
 
+                def gstep():
+                    rp_, col_, eps_ = G.gmls_neighbors(gctx, x, xt, col=gcol, **spec)
+                    all_stencils(gctx, prec, eps_, rp_, col_[:nnz], gbufs)
+                    gout["rp"], gout["eps"] = rp_, eps_
+
+                gstep()  # capture-safe eager run (no allocation happens in the capture)
+                hg = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(hg, stream=gs):
+                    gstep()
+            for i in range(args.warmup):
+                hg.replay()
+            torch.cuda.synchronize()
+            t_start = time.perf_counter()
+            for i in range(args.steps):
+                hg.replay()
+            torch.cuda.synchronize()
+            res["ms_per_step"] = 1e3 * (time.perf_counter() - t_start) / args.steps
+            res["graph"] = True
+            gctx.check()
+            print(f"# {leg} graph: {args.steps} replays: {res['ms_per_step']:.3f} ms/step", file=sys.stderr,
+                  flush=True)
+            # the parity gate checks the replayed outputs
+            out = {"rp": gout["rp"], "col": gcol[:nnz], "eps": gout["eps"], "bufs": gbufs}
+        return res, out
+
+    results, outputs = {}, {}
+    for leg in legs:
+        results[leg], outputs[leg] = run_leg(leg)
     if tune_path and not args.tune_cache:
         os.remove(tune_path)
 
     # ---- the CPU-baseline leg: the only part of this file that uses the
-    # oracle.  It checks sampled outputs of the timed run against it (the
-    # parity gate) and, unless --no-cpu-baseline, times it on the host ----
-    def cpu_baseline_leg():
-        import oracle
+    # oracle.  It times the oracle on the host cores (all of the job's share,
+    # then one core), and checks the timed runs' outputs against the oracle's:
+    # every target the timed oracle run covered, plus a random sample ----
+    import oracle
 
-        rph = rp_t.cpu().numpy()
-        epsh = eps_t.cpu().numpy()
-        g = W.rng(424242)
-        sample = np.sort(g.choice(n_t, size=min(args.sample, n_t), replace=False))
-        idx = torch.from_numpy(np.concatenate([np.arange(rph[t], rph[t + 1]) for t in sample])).cuda()
-        scol = col_t[idx].cpu().numpy()
-        srp = np.zeros(len(sample) + 1, dtype=np.int64)
-        srp[1:] = np.cumsum(np.diff(rph)[sample])
-        if knn:
-            orp, ocol, oeps = oracle.knn(pts, tpts[sample], k, mult)
-        else:
-            orp, ocol, oeps = oracle.radius(pts, tpts[sample], r0, k_min)
-        if knn:
-            same_rows = np.array_equal(scol, ocol)
-        else:  # radius rows are sets: cell order on the GPU, index order in the oracle
-            rows = np.repeat(np.arange(len(srp) - 1), np.diff(srp))
-            same_rows = np.array_equal(srp, orp) and np.array_equal(scol[np.lexsort((scol, rows))], ocol)
-        search_ok = np.array_equal(srp, orp) and same_rows and np.array_equal(epsh[sample], oeps)
-        seps = epsh[sample]
-        max_err = 0.0
-        status_ok = True
+    tol_of = {"mixed": 1e-8, "fp64": 1e-10}
+
+    def oracle_stencils(sub_pts, o_rp, o_col, o_eps, nthreads=0):
+        outs = []
         for bs in bases:
-            F, C = bs["F"], bs["C"]
-            widx = torch.from_numpy(np.concatenate([np.arange(F * C * rph[t], F * C * rph[t + 1])
-                                                    for t in sample])).cuda()
-            wh = bs["w"][widx].cpu().numpy()
-            sth = bs["st"].cpu().numpy()[sample]
             if bs["name"] == "staggered":
                 from oracle import staggered as OS
-                ow, oaux, _ = OS.stencils_staggered(pts, tpts[sample], bs["order"], bs["mask"], p, seps, srp, scol)
-                ost = np.zeros(len(sample), dtype=np.uint8)
+                ow, oaux, _ = OS.stencils_staggered(pts, sub_pts, bs["order"], bs["mask"], p, o_eps, o_rp, o_col)
+                ost = np.zeros(len(sub_pts), dtype=np.uint8)
             elif bs["name"] == "neumann":
                 from oracle import constrained as OC
-                ow, oaux, _ = OC.stencils_constrained(pts, tpts[sample], bs["order"], bs["mask"], p, seps, srp, scol,
-                                                      nrm_h[sample])
-                ost = np.zeros(len(sample), dtype=np.uint8)
+                ow, oaux, _ = OC.stencils_constrained(pts, sub_pts, bs["order"], bs["mask"], p, o_eps, o_rp, o_col,
+                                                      nrm_h[:len(sub_pts)] if sub_pts is tpts else nrm_h[o_sel])
+                ost = np.zeros(len(sub_pts), dtype=np.uint8)
             else:
-                ow, ost, _, _ = oracle.stencils(pts, tpts[sample], bs["order"], bs["name"], bs["mask"], p, seps, srp,
-                                                scol)
+                ow, ost, _, _ = oracle.stencils(pts, sub_pts, bs["order"], bs["name"], bs["mask"], p, o_eps, o_rp,
+                                                o_col, nthreads=nthreads)
                 oaux = None
-            status_ok = status_ok and np.array_equal(sth == 1, ost == 1)
+            outs.append((ow, ost, oaux))
+        return outs
+
+    def oracle_search(sub_pts, nthreads=0, use_grid=None):
+        if knn:
+            return oracle.knn(pts, sub_pts, k, mult, use_grid=use_grid, nthreads=nthreads)
+        return oracle.radius(pts, sub_pts, r0, k_min, use_grid=use_grid, nthreads=nthreads)
+
+    def compare(leg, m, o_rp, o_col, o_eps, o_out, sel=None):
+        """GPU outputs of `leg` for targets sel (default: 0..m-1) against the
+        oracle's: search bit for bit (radius rows as sets), statuses, and the
+        weights per (target, functional row) relative error.  Radius rows are
+        matched by sorting each GPU row by source index on the GPU (torch,
+        as test plumbing); the weights follow the same permutation."""
+        o = outputs[leg]
+        if sel is None:
+            rph = o["rp"][: m + 1].cpu().numpy()
+            g_idx = torch.arange(int(rph[-1]), device=dev)
+            cols = o["col"][: int(rph[-1])]
+            wsel = None
+        else:
+            rp_all = o["rp"].cpu().numpy()
+            lens = np.diff(rp_all)[sel]
+            rph = np.zeros(len(sel) + 1, dtype=np.int64)
+            rph[1:] = np.cumsum(lens)
+            g_idx = torch.from_numpy(np.concatenate([np.arange(rp_all[t], rp_all[t + 1]) for t in sel])).to(dev)
+            cols = o["col"][g_idx]
+            wsel = rp_all[sel]
+        search_ok = np.array_equal(rph, o_rp)
+        nn = int(rph[-1])
+        cnt = torch.from_numpy(np.diff(rph)).to(dev)
+        rows = torch.repeat_interleave(torch.arange(len(rph) - 1, device=dev), cnt)
+        if search_ok:
+            if knn:
+                perm = torch.arange(nn, device=dev)
+                search_ok = np.array_equal(cols.cpu().numpy(), o_col)
+            else:
+                keys = (rows << 32) | cols.to(torch.int64)
+                skeys, perm = torch.sort(keys)
+                okeys = (torch.from_numpy(np.repeat(np.arange(len(rph) - 1), np.diff(o_rp))).to(dev) << 32) | \
+                    torch.from_numpy(o_col.astype(np.int64)).to(dev)
+                search_ok = bool(torch.equal(skeys, okeys))
+            eps_g = o["eps"].cpu().numpy()[sel] if sel is not None else o["eps"][:m].cpu().numpy()
+            search_ok = search_ok and np.array_equal(eps_g, o_eps)
+        if not search_ok:
+            return {"search_ok": False, "status_ok": False, "max": float("inf"), "p99": float("inf"),
+                    "p50": float("inf"), "targets": len(rph) - 1}
+        rp_d = torch.from_numpy(rph[:-1]).to(dev)
+        jd = torch.arange(nn, device=dev) - rp_d[rows]       # position in the oracle's row
+        js = perm - rp_d[rows]                                # the GPU's position of that entry
+        nrow = cnt[rows]
+        errs_all, status_ok = [], True
+        for i, bs in enumerate(bases):
+            F, C = bs["F"], bs["C"]
+            ow, ost, oaux = o_out[i]
+            gst = o["bufs"][i]["st"].cpu().numpy()
+            gst = gst[sel] if sel is not None else gst[:m]
+            status_ok = status_ok and np.array_equal(gst == 1, ost == 1)
+            gw = o["bufs"][i]["w"]
+            if wsel is not None:
+                gbase = torch.from_numpy(F * C * wsel).to(dev)[rows]
+            else:
+                gbase = F * C * rp_d[rows]
+            obase = F * C * rp_d[rows]
+            wo = torch.from_numpy(ow).to(dev)
+            d2 = torch.zeros(len(rph) - 1, F, dtype=torch.float64, device=dev)
+            r2 = torch.zeros_like(d2)
+            for f in range(F):
+                for c in range(C):
+                    a = gw[gbase + (f * nrow + js) * C + c]
+                    b = wo[obase + (f * nrow + jd) * C + c]
+                    d2[:, f].index_add_(0, rows, (a - b) ** 2)
+                    r2[:, f].index_add_(0, rows, b * b)
+            if bs["name"] == "divfree" and bs["mask"] & G.F_DIV:
+                r2[:, F - 1] = r2[:, 0]  # identically zero row: the same target's scale
             if oaux is not None:  # target weights / h-weights, relative to the row norms
-                gaux = bs["aux"].cpu().numpy()[sample]
-                for q in range(len(sample)):
-                    b_ = ow[F * srp[q]:F * srp[q + 1]].reshape(F, -1)
-                    den = np.hypot(np.linalg.norm(b_, axis=1), oaux[q])
-                    max_err = max(max_err, float((np.abs(gaux[q] - oaux[q]) / np.where(den > 0, den, 1.0)).max()))
-            zero = F - 1 if bs["name"] == "divfree" and bs["mask"] & G.F_DIV else -1
-            for q in range(len(sample)):
-                if ost[q] == 1:
-                    continue
-                a = wh[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
-                b_ = ow[F * C * srp[q]:F * C * srp[q + 1]].reshape(F, -1)
-                den = np.linalg.norm(b_, axis=1)
-                if zero >= 0:
-                    den[zero] = den[0]
-                max_err = max(max_err, float((np.linalg.norm(a - b_, axis=1) / den).max()))
-        tol = 1e-8 if prec_name == "mixed" else 1e-10
-        gate = bool(search_ok and status_ok and max_err <= tol)
-        print(f"# parity: search {'ok' if search_ok else 'MISMATCH'}; max rel err {max_err:.3e} (gate {tol:g})",
-              file=sys.stderr, flush=True)
+                ga = o["bufs"][i]["aux"][:m] if sel is None else o["bufs"][i]["aux"][torch.from_numpy(sel).to(dev)]
+                oa = torch.from_numpy(np.asarray(oaux).reshape(len(rph) - 1, F)).to(dev)
+                d2 = d2 + (ga - oa) ** 2
+                r2 = r2 + oa * oa
+            e = torch.sqrt(d2 / r2)
+            live = torch.from_numpy(ost != 1).to(dev)
+            errs_all.append(e[live].reshape(-1))
+        errs = torch.cat(errs_all).cpu().numpy() if errs_all else np.zeros(1)
+        return {"search_ok": True, "status_ok": bool(status_ok), "max": float(errs.max()),
+                "p99": float(np.percentile(errs, 99)), "p50": float(np.percentile(errs, 50)),
+                "targets": len(rph) - 1, "tol": tol_of[leg],
+                "gate": bool(status_ok and errs.max() <= tol_of[leg])}
 
+    info = host_info()
+    threads = info["threads"]
+    full_ok = all(bs["name"] in ("scalar", "divfree") for bs in bases) and n_t == n
+    cpu = None
+    parity = {}
+    o_sel = None
+    # a random sample over the whole cloud (every workload)
+    g = W.rng(424242)
+    o_sel = np.sort(g.choice(n_t, size=min(args.sample, n_t), replace=False))
+    s_rp, s_col, s_eps = oracle_search(tpts[o_sel])
+    s_out = oracle_stencils(tpts[o_sel], s_rp, s_col, s_eps)
+    for leg in legs:
+        parity[leg] = {"random_sample": compare(leg, 0, s_rp, s_col, s_eps, s_out, sel=o_sel)}
+        print(f"# {leg} parity on {len(o_sel)} random targets: {parity[leg]['random_sample']}", file=sys.stderr,
+              flush=True)
+    if full_ok and not args.no_cpu_baseline:
+        def oracle_run(m_, nthreads):
+            sub = tpts[:m_]
+            a_rp, a_col, a_eps = oracle_search(sub, nthreads=nthreads, use_grid=True)
+            outs_ = [oracle.stencils(pts, sub, bs["order"], bs["name"], bs["mask"], p, a_eps, a_rp, a_col,
+                                     nthreads=nthreads)[:2] + (None,) for bs in bases]
+            return a_rp, a_col, a_eps, outs_
 
-        cpu = None
-        if not args.no_cpu_baseline and all(bs["name"] in ("scalar", "divfree") for bs in bases) and n_t == n:
-            threads = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
+        # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds
+        m = max(1000, n // 64)
+        t1 = time.perf_counter()
+        oracle_run(m, threads)
+        dt = time.perf_counter() - t1
+        m2 = int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
+        t1 = time.perf_counter()
+        a_rp, a_col, a_eps, a_out = oracle_run(m2, threads)
+        dt2 = time.perf_counter() - t1
+        what = "all" if m2 == n else f"the first {m2} of the"
+        # one core: a sample sized from the all-core rate for ~cpu_seconds_1
+        m1 = int(min(m2, max(200, (m2 / dt2) / threads * args.cpu_seconds_1)))
+        t1 = time.perf_counter()
+        oracle_run(m1, 1)
+        dt1 = time.perf_counter() - t1
+        cpu = {"value": round(m2 / dt2, 1), "unit": "stencils/s", "cores": threads, "kind": "oracle",
+               "sample": f"{what} {n} targets of the same point cloud: bucket-grid neighbour search + "
+                         f"Householder-QR stencils in FP64, {dt2:.1f} s wall on {threads} threads",
+               "value_1core": round(m1 / dt1, 1),
+               "sample_1core": f"the first {m1} targets, {dt1:.1f} s wall on 1 thread",
+               "host": info}
+        print(f"# oracle: {cpu}", file=sys.stderr, flush=True)
+        for leg in legs:
+            parity[leg]["oracle_run"] = compare(leg, m2, a_rp, a_col, a_eps, a_out)
+            print(f"# {leg} parity on the first {m2} targets: {parity[leg]['oracle_run']}", file=sys.stderr,
+                  flush=True)
+        del a_rp, a_col, a_eps, a_out
 
-            def oracle_run(m):
-                sub = np.arange(m)
-                if knn:
-                    a_rp, a_col, a_eps = oracle.knn(pts, pts[sub], k, mult, use_grid=True, nthreads=threads)
-                else:
-                    a_rp, a_col, a_eps = oracle.radius(pts, pts[sub], r0, k_min, use_grid=True, nthreads=threads)
-                for bs in bases:
-                    oracle.stencils(pts, pts[sub], bs["order"], bs["name"], bs["mask"], p, a_eps, a_rp, a_col,
-                                    nthreads=threads)
+    def summary(leg):
+        pr = parity[leg]
+        parts = [v for v in pr.values()]
+        full = pr.get("oracle_run")
+        return {"gate": bool(all(v["search_ok"] and v["status_ok"] and v["max"] <= tol_of[leg] for v in parts)),
+                "max_rel_err": max(v["max"] for v in parts),
+                "p99_rel_err": (full or pr["random_sample"])["p99"],
+                "p50_rel_err": (full or pr["random_sample"])["p50"],
+                "targets_compared": (full["targets"] if full else 0) + pr["random_sample"]["targets"],
+                "all_targets": bool(full and full["targets"] == n_t)}
 
-            # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds
-            m = max(1000, n // 64)
-            t1 = time.perf_counter()
-            oracle_run(m)
-            dt = time.perf_counter() - t1
-            m2 = int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
-            t1 = time.perf_counter()
-            oracle_run(m2)
-            dt = time.perf_counter() - t1
-            what = "all" if m2 == n else f"the first {m2} of the"
-            cpu = {"value": round(m2 / dt, 1), "unit": "stencils/s", "cores": threads, "kind": "oracle",
-                   "sample": f"{what} {n} targets of the same point cloud: bucket-grid neighbour search + "
-                             f"Householder-QR stencils in FP64, {dt:.1f} s wall on {threads} threads"}
-
-        return gate, max_err, len(sample), cpu
-
-    gate, max_err, n_sample, cpu = cpu_baseline_leg()
-
+    head = results[legs[0]]
+    sum_head = summary(legs[0])
     # ---- roofline of the stencil phase (its kernels timed by HIP events on
-    # the library's stream, inside the timed steps) ----
+    # the library's stream, inside the timed steps).  No MFMA and no packed
+    # FP32 instruction executes (packed FP32 is disabled at build time), so
+    # FP32 and FP64 vector arithmetic run at the same rate: the peak of the
+    # arithmetic that executes is the FP64 vector peak in both precisions ----
     flops = alg_flops_workload(nnz, n_t, dim, bases)
-    t_sten = float(np.mean(stencil_ms)) * 1e-3
+    flops_exec = executed_flops_workload(nnz, n_t, dim, bases)
+    t_sten = head["stencil_ms"] * 1e-3
     achieved_tf = flops / t_sten / 1e12
-    peak_tf = PEAK["fp32_TFs"] if prec_name == "mixed" else PEAK["fp64_TFs"]
-    traffic = measured_traffic(prec_name) if name == DEFAULT_WORKLOAD and n == wl["n"] else None
+    peak_tf = PEAK["fp64_TFs"]
+    traffic = measured_traffic(legs[0]) if name == DEFAULT_WORKLOAD and n == wl["n"] else None
+    alg_bytes = alg_bytes_workload(nnz, n_t, dim, bases)
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": peak_tf, "unit": "TFLOP/s",
                 "frac": round(achieved_tf / peak_tf, 4), "traffic": traffic,
                 "kernel": "stencil phase: moments, solve and weights kernels of every row-count bin + FP64 "
                           "fallback (one launch sequence per basis per step)",
-                "alg_flops_per_step": flops, "alg_bytes_per_step": alg_bytes_workload(nnz, n_t, dim, bases),
+                "peak_basis": "FP64 vector (78.6 TF): no MFMA and no packed FP32 executes, so FP32 runs at the "
+                              "FP64 rate",
+                "alg_flops_per_step": flops, "alg_bytes_per_step": alg_bytes,
+                "executed_flops_per_step": flops_exec,
+                "achieved_executed": round(flops_exec / t_sten / 1e12, 3),
+                "frac_executed": round(flops_exec / t_sten / 1e12 / peak_tf, 4),
+                "alg_hbm_GBs": round(alg_bytes / t_sten / 1e9, 1),
+                "alg_hbm_frac": round(alg_bytes / t_sten / 1e9 / PEAK["hbm_GBs"], 4),
                 "kernel_ms": round(t_sten * 1e3, 4),
-                "frac_of_fp64_peak": round(achieved_tf / PEAK["fp64_TFs"], 4),
-                "search_ms": round(float(np.mean(search_ms)), 4)}
+                "search_ms": round(head["search_ms"], 4)}
+    if traffic:
+        roofline["traffic_GBs"] = round(traffic / t_sten / 1e9, 1)
+        roofline["traffic_hbm_frac"] = round(traffic / t_sten / 1e9 / PEAK["hbm_GBs"], 4)
+        roofline["traffic_over_alg_bytes"] = round(traffic / alg_bytes, 2)
 
-    value = n_t / (ms_per_step * 1e-3)
+    def leg_fields(leg):
+        r = results[leg]
+        sm = summary(leg)
+        reps_ = r["reports"]
+        return {"ms_per_step": round(r["ms_per_step"], 4), "value": round(n_t / (r["ms_per_step"] * 1e-3), 1),
+                "timed_unit": "HIP graph replay of search + stencils" if r["graph"] else "eager calls",
+                "ms_per_step_eager": round(r["ms_eager"], 4), "stencil_ms": round(r["stencil_ms"], 4),
+                "search_ms": round(r["search_ms"], 4),
+                "stencils_only_per_s": round(n_t / (r["stencil_ms"] * 1e-3), 1),
+                "parity_gate": sm["gate"], "parity_max_rel_err": sm["max_rel_err"],
+                "parity_p99_rel_err": sm["p99_rel_err"], "parity_p50_rel_err": sm["p50_rel_err"],
+                "parity_sample": sm["targets_compared"], "parity_all_targets": sm["all_targets"],
+                "fallbacks": int(sum(x_["n_fallback"] + x_["n_not_converged"] for x_ in reps_)),
+                "rank_deficient": int(sum(x_["n_rank_deficient"] for x_ in reps_)),
+                "cond": {"min": min(x_["cond_min"] for x_ in reps_), "med": reps_[0]["cond_med"],
+                         "max": max(x_["cond_max"] for x_ in reps_)}}
+
+    hf = leg_fields(legs[0])
+    value = n_t / (head["ms_per_step"] * 1e-3)
+    # FP32 executes only in the Cholesky factor of the pipeline's scalar
+    # solve (scalar bases of at most 20 functions): elsewhere the mixed
+    # path's arithmetic is FP64
+    fp32_used = legs[0] == "mixed" and any(
+        bs["name"] in ("scalar", "staggered") and bs["Q"] <= 20 for bs in bases)
     line = {
         "metric": "GMLS stencils/sec (3D, order 3, uneven nbrs); mixed vs FP64 at <=1e-8 rel err",
         "value": round(value, 1),
@@ -580,27 +738,34 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step": round(head["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if prec_name == "mixed" else "f64",
+        "dtype": "f32+f64" if fp32_used else "f64",
         "data": "synthetic",
         "config": {"workload": f"{name}: {DESCRIBE[name]}",
-                   "n_points": n, "n_targets": n_t, "nnz": int(nnz), "precision": prec_name,
+                   "n_points": n, "n_targets": n_t, "nnz": int(nnz), "precision": legs[0],
                    "search": wl["search"][0] + (f" k={k}" if knn else f" r={r0:.6f} k_min={k_min}"),
                    "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
                                     "pipeline", "wavefront per target"][args.scheme],
                    "autotune": tune_summary,
                    "bases_call": "gmls_stencils_multi (one call for both bases)" if shared else "gmls_stencils per basis",
-                   "parity_gate": gate, "parity_max_rel_err": max_err, "parity_sample": int(n_sample),
-                   "timed_unit": "HIP graph replay of search + stencils" if graph else "eager calls",
-                   "ms_per_step_eager": round(ms_eager, 4),
-                   "fallbacks": int(sum(r["n_fallback"] + r["n_not_converged"] for r in reps)),
-                   "rank_deficient": int(sum(r["n_rank_deficient"] for r in reps))},
+                   "timed_unit": hf["timed_unit"],
+                   "ms_per_step_eager": hf["ms_per_step_eager"],
+                   "stencils_only_per_s": hf["stencils_only_per_s"],
+                   "parity_gate": hf["parity_gate"], "parity_max_rel_err": hf["parity_max_rel_err"],
+                   "parity_p99_rel_err": hf["parity_p99_rel_err"], "parity_p50_rel_err": hf["parity_p50_rel_err"],
+                   "parity_sample": hf["parity_sample"], "parity_all_targets": hf["parity_all_targets"],
+                   "fallbacks": hf["fallbacks"], "rank_deficient": hf["rank_deficient"], "cond": hf["cond"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if "fp64" in legs and legs[0] != "fp64":
+        ff = leg_fields("fp64")
+        ff["mixed_speedup"] = round(results["fp64"]["ms_per_step"] / head["ms_per_step"], 3)
+        ff["dtype"] = "f64"
+        line["fp64"] = ff
     print(json.dumps(line))
     ctx.close()
 

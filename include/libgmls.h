@@ -96,19 +96,29 @@ typedef struct {
   int32_t reserved;
 } gmls_search;
 
-/* filled (host memory) when a non-NULL report is passed to gmls_stencils;
- * that call then synchronises the stream */
+/* filled (host memory) when a non-NULL report is passed to a stencil call;
+ * that call then synchronises the stream.  The target counts are those of
+ * the statuses written (GMLS_TARGET_*); gmls_stencils_multi sums them over
+ * its sets, counting (target, set) pairs. */
 typedef struct {
-  int64_t n_targets;
-  int64_t n_ok;
-  int64_t n_rank_deficient;
-  int64_t n_fallback;      /* mixed: targets recomputed by FP64 QR (condition or breakdown) */
-  int64_t n_not_converged; /* mixed: refinement budget exhausted (also recomputed by QR)    */
+  int64_t n_targets;       /* targets (times the number of sets of a multi call)           */
+  int64_t n_ok;            /* targets with weights: n_targets - n_rank_deficient            */
+  int64_t n_rank_deficient;/* status GMLS_TARGET_RANK_DEFICIENT                            */
+  int64_t n_fallback;      /* status GMLS_TARGET_FALLBACK: the mixed path handed the target
+                              to the FP64 QR path (condition or breakdown)                  */
+  int64_t n_not_converged; /* status GMLS_TARGET_NOT_CONVERGED (also recomputed by QR)      */
   int32_t sweep_hist[16];  /* mixed: targets by number of refinement sweeps used            */
-  double cond_max;         /* mixed: largest 1-norm condition number of the equilibrated Gram */
+  double cond_max;         /* mixed: largest 1-norm condition number (estimate) of the
+                              equilibrated Gram over the targets the mixed kernels factored */
   double t_bin_ms;         /* GPU time of the binning kernels                                */
   double t_stencil_ms;     /* GPU time of the stencil kernels (all bins)                     */
   double t_fallback_ms;    /* GPU time of the FP64 fallback kernel                           */
+  double cond_min;         /* mixed: smallest of those condition numbers (0 when none)       */
+  double cond_med;         /* mixed: their median, to within a factor 2^(1/32) (the centre of
+                              a log2 histogram bin of width 2^(1/16)); 0 when none.  A multi
+                              call reports the scalar Gram's (sets in turn: sets[0]'s)       */
+  double t_search_ms;      /* GPU time of the context's last gmls_neighbors call that
+                              synchronised (0 if none, or if it failed)                      */
 } gmls_report;
 
 /* Options for gmls_set_option. */

@@ -96,7 +96,8 @@ class Report(ctypes.Structure):
     _fields_ = [("n_targets", ctypes.c_int64), ("n_ok", ctypes.c_int64), ("n_rank_deficient", ctypes.c_int64),
                 ("n_fallback", ctypes.c_int64), ("n_not_converged", ctypes.c_int64),
                 ("sweep_hist", ctypes.c_int32 * 16), ("cond_max", ctypes.c_double), ("t_bin_ms", ctypes.c_double),
-                ("t_stencil_ms", ctypes.c_double), ("t_fallback_ms", ctypes.c_double)]
+                ("t_stencil_ms", ctypes.c_double), ("t_fallback_ms", ctypes.c_double),
+                ("cond_min", ctypes.c_double), ("cond_med", ctypes.c_double), ("t_search_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "sweep_hist"}

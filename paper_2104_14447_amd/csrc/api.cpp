@@ -238,6 +238,73 @@ gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, co
 // key of the autotune table
 static int tune_key(int dim, int order, int basis) { return (dim * 8 + order) * 4 + basis; }
 
+// Device buffers of a report: the per-target condition numbers of the mixed
+// kernels (NaN where none was computed) and the counters, both cleared.
+static gmls_status report_begin(gmls_ctx ctx, int n, float **cond, ReportCounts **rc) {
+  *cond = (float *)ctx->ws(WS_COND, sizeof(float) * (size_t)n);
+  *rc = (ReportCounts *)ctx->ws(WS_REPORT, sizeof(ReportCounts));
+  if (!*cond || !*rc) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed (report)");
+  GMLS_HIP(fill_f32(*cond, NAN, n, ctx->stream));
+  GMLS_HIP(fill_zero(*rc, sizeof(ReportCounts), ctx->stream));
+  return GMLS_OK;
+}
+
+// The report of a stencil call (synchronises): target counts by status over
+// the call's status arrays (one per stencil set), the refinement histogram
+// and largest condition number from the mixed kernels' statistics (n_stats
+// records), the smallest and median condition number over the targets whose
+// Gram the mixed kernels factored, the phase times between events 0..3, and
+// the time of the context's last search.
+static gmls_status report_end(gmls_ctx ctx, gmls_report *report, int n, const uint8_t *const *status, int n_sets,
+                              const Stats *stats, int n_stats, const float *cond, ReportCounts *rc) {
+  hipStream_t s = ctx->stream;
+  for (int k = 0; k < n_sets; ++k) GMLS_HIP(launch_status_count(status[k], n, rc, s));
+  GMLS_HIP(launch_cond_stats(cond, n, rc, s));
+  Stats hs[2];
+  ReportCounts hr;
+  GMLS_HIP(hipMemcpyAsync(hs, stats, sizeof(Stats) * (size_t)n_stats, hipMemcpyDeviceToHost, s));
+  GMLS_HIP(hipMemcpyAsync(&hr, rc, sizeof(ReportCounts), hipMemcpyDeviceToHost, s));
+  GMLS_HIP(hipStreamSynchronize(s));
+  float t01 = 0, t12 = 0, t23 = 0;
+  hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
+  hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
+  hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
+  memset(report, 0, sizeof(*report));
+  report->n_targets = (int64_t)n * n_sets;
+  report->n_rank_deficient = (int64_t)hr.status[GMLS_TARGET_RANK_DEFICIENT];
+  report->n_fallback = (int64_t)hr.status[GMLS_TARGET_FALLBACK];
+  report->n_not_converged = (int64_t)hr.status[GMLS_TARGET_NOT_CONVERGED];
+  report->n_ok = report->n_targets - report->n_rank_deficient;
+  double cmax = 0.0;
+  for (int k = 0; k < n_stats; ++k) {
+    for (int i = 0; i < 16; ++i) report->sweep_hist[i] += (int32_t)hs[k].sweep_hist[i];
+    double c;
+    memcpy(&c, &hs[k].cond_max_bits, sizeof(double));
+    cmax = std::max(cmax, c);
+  }
+  report->cond_max = cmax;
+  if (hr.n_cond > 0) {
+    const unsigned int bits = ~hr.cond_min_inv;
+    float cmin;
+    memcpy(&cmin, &bits, sizeof(float));
+    report->cond_min = cmin;
+    const unsigned long long half = (hr.n_cond + 1) / 2;
+    unsigned long long cum = 0;
+    for (int b = 0; b < kCondBins; ++b) {
+      cum += hr.cond_hist[b];
+      if (cum >= half) {
+        report->cond_med = exp2((b + 0.5) / kCondBinsPerOctave);
+        break;
+      }
+    }
+  }
+  report->t_bin_ms = t01;
+  report->t_stencil_ms = t12;
+  report->t_fallback_ms = t23;
+  report->t_search_ms = ctx->t_search_ms;
+  return report->n_rank_deficient > 0 ? GMLS_WARN_TARGET_FLAGS : GMLS_OK;
+}
+
 // plain (normals == nullptr), Neumann-constrained and staggered
 // (basis == kBasisStaggered) stencils
 static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
@@ -322,6 +389,13 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
   const bool sync = !opt.capture_safe;  // capture-safe: nothing below waits for the device
   if (!sync && report)
     return gmls_set_error(ctx, GMLS_ERR_ARG, "a report synchronises: pass NULL in capture-safe mode");
+  float *cond = nullptr;
+  ReportCounts *rc = nullptr;
+  if (report) {
+    st = report_begin(ctx, n, &cond, &rc);
+    if (st != GMLS_OK) return st;
+    a.cond_out = cond;
+  }
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[0], s));
   const size_t bin_bytes = binning_temp_bytes(n);
   void *bin_tmp = ctx->ws(WS_BIN_TEMP, bin_bytes);
@@ -394,28 +468,8 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
     GMLS_HIP(launch_qr_kmat(dim, order, af, a.aux_list, &meta->aux_count, &meta->aux_cursor, 64, s));
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[3], s));
   if (!report) return GMLS_OK;
-
-  Stats hs;
-  GMLS_HIP(hipMemcpyAsync(&hs, stats, sizeof(Stats), hipMemcpyDeviceToHost, s));
-  GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
-  GMLS_HIP(hipStreamSynchronize(s));
-  float t01 = 0, t12 = 0, t23 = 0;
-  hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
-  hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
-  hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
-  report->n_targets = n_tgt;
-  report->n_rank_deficient = hm.count[0];
-  report->n_fallback = (int64_t)hs.n_fallback;
-  report->n_not_converged = (int64_t)hs.n_not_converged;
-  report->n_ok = n_tgt - hm.count[0];
-  for (int i = 0; i < 16; ++i) report->sweep_hist[i] = (int32_t)hs.sweep_hist[i];
-  double cmax;
-  memcpy(&cmax, &hs.cond_max_bits, sizeof(double));
-  report->cond_max = cmax;
-  report->t_bin_ms = t01;
-  report->t_stencil_ms = t12;
-  report->t_fallback_ms = t23;
-  return hm.count[0] > 0 ? GMLS_WARN_TARGET_FLAGS : GMLS_OK;
+  const uint8_t *sts[1] = {status};
+  return report_end(ctx, report, n, sts, 1, stats, 1, cond, rc);
 }
 
 // A scalar set (ss) and a divergence-free set (sv) on the same neighbour
@@ -482,6 +536,13 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
   const bool sync = !opt.capture_safe;
   if (!sync && report)
     return gmls_set_error(ctx, GMLS_ERR_ARG, "a report synchronises: pass NULL in capture-safe mode");
+  float *cond = nullptr;
+  ReportCounts *rc = nullptr;
+  if (report) {  // the condition numbers of the shared scalar Gram
+    st = report_begin(ctx, n, &cond, &rc);
+    if (st != GMLS_OK) return st;
+    as.cond_out = cond;
+  }
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[0], s));
   const size_t bin_bytes = binning_temp_bytes(n);
   void *bin_tmp = ctx->ws(WS_BIN_TEMP, bin_bytes);
@@ -561,27 +622,8 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
   GMLS_HIP(launch_qr_kmat(dim, order, afv, aux, &meta->aux_count, &meta->aux_cursor, 64, s));
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[3], s));
   if (!report) return GMLS_OK;
-  Stats hs;
-  GMLS_HIP(hipMemcpyAsync(&hs, stats, sizeof(Stats), hipMemcpyDeviceToHost, s));
-  GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
-  GMLS_HIP(hipStreamSynchronize(s));
-  float t01 = 0, t12 = 0, t23 = 0;
-  hipEventElapsedTime(&t01, ctx->ev[0], ctx->ev[1]);
-  hipEventElapsedTime(&t12, ctx->ev[1], ctx->ev[2]);
-  hipEventElapsedTime(&t23, ctx->ev[2], ctx->ev[3]);
-  report->n_targets = n_tgt;
-  report->n_rank_deficient = hm.count[0];
-  report->n_fallback = (int64_t)hs.n_fallback;
-  report->n_not_converged = (int64_t)hs.n_not_converged;
-  report->n_ok = n_tgt - hm.count[0];
-  for (int i = 0; i < 16; ++i) report->sweep_hist[i] = (int32_t)hs.sweep_hist[i];
-  double cmax;
-  memcpy(&cmax, &hs.cond_max_bits, sizeof(double));
-  report->cond_max = cmax;
-  report->t_bin_ms = t01;
-  report->t_stencil_ms = t12;
-  report->t_fallback_ms = t23;
-  return hm.count[0] > 0 ? GMLS_WARN_TARGET_FLAGS : GMLS_OK;
+  const uint8_t *stl[2] = {sts, stv};
+  return report_end(ctx, report, n, stl, 2, stats, scheme < 0 ? 1 : 2, cond, rc);
 }
 
 extern "C" {
@@ -628,10 +670,18 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
                                         sets[k].functional_mask, weight_p, eps, row_ptr, col, nullptr, prec,
                                         sets[k].weights, nullptr, sets[k].target_status, report ? &r : nullptr);
     if (st != GMLS_OK && st != GMLS_WARN_TARGET_FLAGS) return st;
+    if (st == GMLS_WARN_TARGET_FLAGS) ret = st;
     if (k == 0) {
-      ret = st;
       if (report) acc = r;
-    } else if (report) {
+    } else if (report) {  // counts summed over the sets; condition figures: min, max, sets[0]'s median
+      acc.n_targets += r.n_targets;
+      acc.n_ok += r.n_ok;
+      acc.n_rank_deficient += r.n_rank_deficient;
+      acc.n_fallback += r.n_fallback;
+      acc.n_not_converged += r.n_not_converged;
+      for (int i = 0; i < 16; ++i) acc.sweep_hist[i] += r.sweep_hist[i];
+      acc.cond_max = std::max(acc.cond_max, r.cond_max);
+      if (r.cond_min > 0 && (acc.cond_min == 0 || r.cond_min < acc.cond_min)) acc.cond_min = r.cond_min;
       acc.t_bin_ms += r.t_bin_ms;
       acc.t_stencil_ms += r.t_stencil_ms;
       acc.t_fallback_ms += r.t_fallback_ms;

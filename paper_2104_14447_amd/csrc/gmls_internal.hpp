@@ -51,6 +51,8 @@ enum Slot {
   WS_FALLBACK2,
   WS_STATUS_TMP2,
   WS_PIPE_Y2,
+  WS_COND,
+  WS_REPORT,
   WS_NUM_SLOTS
 };
 
@@ -102,6 +104,7 @@ struct gmls_ctx_s {
   // candidate of [kernel * 8 + bin], -1 where not tuned
   std::map<int, std::array<signed char, 16>> tune;
   gmls::PipeTimer *timer = nullptr;  // set by the autotuner around its runs
+  double t_search_ms = 0.0;           // GPU time of the last synchronising gmls_neighbors call
 
   // Device buffer of at least `bytes` for `slot`; nullptr on failure (and,
   // in capture-safe mode, when the slot would have to grow).
@@ -181,6 +184,9 @@ struct StencilArgs {
   // go to aux_list[atomicAdd(aux_count, 1)] (null: they are rank deficient)
   int *aux_list = nullptr;
   int *aux_count = nullptr;
+  // when non-null (a report was requested): the mixed kernels write the
+  // condition number (estimate) of each target's equilibrated Gram here
+  float *cond_out = nullptr;
 };
 
 // Per-bin stencil launches; `bin` selects the rows-per-lane instantiation.
@@ -232,6 +238,24 @@ int pipe_num_moments(int dim, int order);
 // memset node in captured graphs); OR (src & mask) != 0 ? bit : 0 into *dst
 hipError_t fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t or_error_bit(int *dst, const int *src, int mask, int bit, hipStream_t s);
+
+// Report counters (stencil_bins.hip): per-status target counts of a status
+// array, and the smallest value and a log2 histogram (kCondBinsPerOctave
+// bins per factor of 2 over [1, 2^64)) of per-target condition numbers
+// (non-finite entries are skipped).
+constexpr int kCondBinsPerOctave = 16;
+constexpr int kCondBins = 64 * kCondBinsPerOctave;
+struct ReportCounts {
+  unsigned long long status[4];      // targets with status 0..3 (summed over the arrays counted)
+  unsigned long long n_cond;         // finite condition numbers seen
+  unsigned int cond_min_inv;         // ~(float bits) of the smallest one (non-negative floats order as
+                                     // their bits, so the largest complement is the smallest value)
+  unsigned int pad;
+  unsigned int cond_hist[kCondBins];
+};
+hipError_t fill_f32(float *p, float v, int64_t n, hipStream_t s);
+hipError_t launch_status_count(const uint8_t *status, int n, ReportCounts *rc, hipStream_t s);
+hipError_t launch_cond_stats(const float *cond, int n, ReportCounts *rc, hipStream_t s);
 
 // exclusive scan of n ints (search.hip): out[0..n], tmp of scan_i32_tmp_words(n)
 int64_t scan_i32_tmp_words(int64_t n);

@@ -7,22 +7,34 @@
 // is one contiguous range of memory.  Targets are processed in cell order so
 // that neighbouring waves read the same cells.
 //
-// Query: one wavefront per target.  Candidates from a block of cells are
-// streamed through LDS 64 at a time; squared distances use the fixed
-// evaluation order (dx*dx + dy*dy) + dz*dz without fused multiply-add.
-//  - kNN: the k best (squared distance, index) pairs are kept by sorting the
-//    LDS buffer (bitonic network) whenever it fills; the search block grows
-//    until the k-th distance is provably smaller than the distance to every
-//    unscanned cell.
-//  - radius: every source with d^2 < r^2 (count pass, scan, fill pass); a
-//    target with fewer than k_min falls back to its k_min nearest.  A
-//    workgroup stages the sources around one target cell in LDS and shares
-//    them among the cell's targets; rows of up to 256 entries are compacted
-//    into a small LDS buffer and sorted in registers by a wave-wide bitonic
-//    network; cells with crowded blocks, floored targets and longer rows take
-//    per-target kernels.
-// kNN rows are sorted by (squared distance, index); radius rows, which are
-// sets, by index.
+// kNN query (cells of side about d_k/1.9): one wavefront per target.  The
+// block of cells within 2 (then 3) of the target's cell is read as runs of
+// cells along x, whose bounds are fetched together so that a chunk of 64
+// candidate loads goes out at once; exact squared distances (fixed order
+// (dx*dx + dy*dy) + dz*dz, no fused multiply-add) closer than the block's
+// inner margin are kept, a bisection on d^2 (ballot counts over registers)
+// trims them to the capacity of a register bitonic sort of (d^2, index)
+// pairs, and the k smallest are the row.  Targets with fewer than k inside
+// the margin go to a second register pass with a wider block, then to a
+// per-target kernel that expands the block until the k-th distance is
+// provably below the distance to every unscanned cell.
+//
+// Radius query (cells of side >= r): a workgroup stages the sources of the
+// 3^dim block around one target cell in LDS and its four wavefronts share
+// them among the cell's targets, several targets per wavefront reading each
+// staged candidate once.  Accepted sources are compacted by ballot prefix
+// sums into a scratch row of up to 256 entries per target (one-pass mode) or
+// straight into `col` after a count pass and a scan (two-pass mode, when the
+// scratch does not fit its budget); the scratch rows are copied into place
+// after the scan of the counts (k_rows_copy).  Targets that need the k_min
+// floor, rows over 256 entries and crowded blocks are finished by
+// per-target kernels.
+//
+// kNN rows are sorted by (squared distance, index).  Radius rows, which are
+// sets, come out in cell order, by (cell of the source, index): each cell's
+// sources are put in ascending index once per search, and the staged scan
+// emits them in that order with no sort.  GMLS_OPT_ROW_ORDER = 1 sorts each
+// row by index instead (a register bitonic network per row).
 #include <float.h>
 #include <limits.h>
 
@@ -1146,11 +1158,13 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
       } else {
         // rows that go to the per-target kernels; the others are sorted
         int n_sort[NT];
+        bool here[NT];  // finished by this kernel (an empty row included, when k_min is 0)
         int widest = 0;
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
           const bool defer_it = live[u] && (fill[u] < k_min || fill[u] > kSmallCap);
-          n_sort[u] = live[u] && !defer_it ? fill[u] : 0;
+          here[u] = live[u] && !defer_it;
+          n_sort[u] = here[u] ? fill[u] : 0;
           widest = max(widest, n_sort[u]);
           if (defer_it && lane == 0) {
             defer[atomicAdd(n_defer, 1)] = t[u];
@@ -1173,7 +1187,7 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
         if (lane == 0) {
 #pragma unroll
           for (int u = 0; u < NT; ++u) {
-            if (n_sort[u] == 0) continue;
+            if (!here[u]) continue;
             eps[t[u]] = r0;
             if (MODE == kFused) {
               counts[t[u]] = n_sort[u];
@@ -1464,6 +1478,13 @@ static void launch_fill_big(bool by_index, hipStream_t s, A... args) {
     k_radius_fill_big<DIM, false><<<1024, 64, 0, s>>>(args...);
 }
 
+// GPU time of the search just finished (events 4 and 5 of the context)
+static void search_time(gmls_ctx ctx) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, ctx->ev[4], ctx->ev[5]) == hipSuccess) ctx->t_search_ms = ms;
+  (void)hipGetLastError();
+}
+
 template <int DIM>
 static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
                                  int64_t n_tgt, const gmls_search &spec, int64_t *row_ptr, int32_t *col,
@@ -1490,6 +1511,8 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
   GMLS_WS(tmp, int64_t, WS_SCAN_TMP, scan_tmp_entries(ncell_max + 1 > n_tgt + 1 ? ncell_max + 1 : n_tgt + 1));
   GMLS_WS(flags, int, WS_FLAGS, 4);
 
+  ctx->t_search_ms = 0.0;
+  if (sync) GMLS_HIP(hipEventRecord(ctx->ev[4], s));
   k_bbox_partial<<<nb_bbox, kBBoxBlock, 0, s>>>(coords, n_src, DIM, bbox);
   k_grid_setup<<<1, 64, 0, s>>>(bbox, (int)nb_bbox, DIM, knn ? 0 : 1, spec.radius, spec.k, n_src, ncell_max, gp);
   GMLS_HIP(fill_zero(cnt, sizeof(int) * (size_t)(ncell_max + 1), s));
@@ -1547,7 +1570,11 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
                                             spec.eps_mult, col, eps);
     }
     GMLS_HIP(hipGetLastError());
-    if (sync) GMLS_HIP(hipStreamSynchronize(s));
+    if (sync) {
+      GMLS_HIP(hipEventRecord(ctx->ev[5], s));
+      GMLS_HIP(hipStreamSynchronize(s));
+      search_time(ctx);
+    }
     return GMLS_OK;
   }
   GMLS_WS(counts, int64_t, WS_ROW_COUNT, n_tgt > 0 ? n_tgt : 1);
@@ -1620,7 +1647,9 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
   }
   GMLS_HIP(hipGetLastError());
   if (sync) {
+    GMLS_HIP(hipEventRecord(ctx->ev[5], s));
     GMLS_HIP(hipStreamSynchronize(s));
+    search_time(ctx);
   } else {
     int *de = (int *)ctx->ws(WS_DEV_ERR, sizeof(int));
     GMLS_HIP(or_error_bit(de, flags, 1, DEV_ERR_RADIUS_ROWS, s));

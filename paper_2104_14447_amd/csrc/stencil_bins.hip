@@ -172,6 +172,87 @@ hipError_t or_error_bit(int *dst, const int *src, int mask, int bit, hipStream_t
   return hipGetLastError();
 }
 
+__global__ void k_fill_f32(float *p, float v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t fill_f32(float *p, float v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > 4096) g = 4096;
+  k_fill_f32<<<(unsigned)g, 256, 0, s>>>(p, v, n);
+  return hipGetLastError();
+}
+
+// ---- report counters ----
+// per-status counts: block-local counts, then one atomic per status and block
+__global__ __launch_bounds__(256) void k_status_count(const uint8_t *st, int n, ReportCounts *rc) {
+  __shared__ unsigned int c[4];
+  if (threadIdx.x < 4) c[threadIdx.x] = 0u;
+  __syncthreads();
+  unsigned int mine[4] = {0u, 0u, 0u, 0u};
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int v = st[i];
+    if (v < 4) mine[v] += 1u;
+  }
+  for (int k = 0; k < 4; ++k) {
+    const unsigned int w = (unsigned int)wave_sum((int)mine[k]);
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd(&c[k], w);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 && c[threadIdx.x]) atomicAdd(&rc->status[threadIdx.x], (unsigned long long)c[threadIdx.x]);
+}
+
+hipError_t launch_status_count(const uint8_t *status, int n, ReportCounts *rc, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int g = (n + 255) / 256;
+  if (g > 1024) g = 1024;
+  k_status_count<<<g, 256, 0, s>>>(status, n, rc);
+  return hipGetLastError();
+}
+
+// condition numbers: a block-local histogram in LDS over log2 bins, merged
+// into the call's histogram with one atomic per non-empty bin and block
+__global__ __launch_bounds__(256) void k_cond_stats(const float *cond, int n, ReportCounts *rc) {
+  __shared__ unsigned int h[kCondBins];
+  __shared__ unsigned int cmin_inv, cnt;  // ~bits of the smallest value (0: none)
+  for (int b = threadIdx.x; b < kCondBins; b += blockDim.x) h[b] = 0u;
+  if (threadIdx.x == 0) {
+    cmin_inv = 0u;
+    cnt = 0u;
+  }
+  __syncthreads();
+  unsigned int mymin_inv = 0u, mycnt = 0u;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float c = cond[i];
+    if (!(c >= 0.f) || !isfinite(c)) continue;  // NaN: not computed by the mixed kernels
+    const unsigned int inv = ~__float_as_uint(c);
+    mymin_inv = inv > mymin_inv ? inv : mymin_inv;
+    mycnt += 1u;
+    int b = c >= 1.f ? (int)floorf(log2f(c) * (float)kCondBinsPerOctave) : 0;
+    b = b < 0 ? 0 : (b >= kCondBins ? kCondBins - 1 : b);
+    atomicAdd(&h[b], 1u);
+  }
+  atomicMax(&cmin_inv, mymin_inv);
+  atomicAdd(&cnt, mycnt);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kCondBins; b += blockDim.x)
+    if (h[b]) atomicAdd(&rc->cond_hist[b], h[b]);
+  if (threadIdx.x == 0) {
+    if (cnt) atomicAdd(&rc->n_cond, (unsigned long long)cnt);
+    atomicMax(&rc->cond_min_inv, cmin_inv);
+  }
+}
+
+hipError_t launch_cond_stats(const float *cond, int n, ReportCounts *rc, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int g = (n + 255) / 256;
+  if (g > 512) g = 512;
+  k_cond_stats<<<g, 256, 0, s>>>(cond, n, rc);
+  return hipGetLastError();
+}
+
 // layout of the temporary buffer (8-byte aligned pieces): partial boxes,
 // box, bucket counters, bucket starts, per-target bucket and rank, scan
 // scratch

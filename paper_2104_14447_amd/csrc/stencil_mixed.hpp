@@ -507,6 +507,7 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
       }
   }
   if (valid && lg == 0) {
+    if (a.cond_out) a.cond_out[t] = (float)cond;
     if (good) {
       a.status[t] = GMLS_TARGET_OK;
       atomicAdd(&stats->sweep_hist[sweeps < 15 ? sweeps : 15], 1ull);

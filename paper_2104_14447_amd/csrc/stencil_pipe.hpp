@@ -364,6 +364,7 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, 
 #pragma unroll
     for (int i = 0; i < Q; ++i) est2 += fabsf(x[i]);
     const float cond = anorm * fmaxf(est, est2);
+    if (valid && a.cond_out) a.cond_out[t] = cond;
     if (!(cond <= opt.cond_threshold)) ok = false;
     if (opt.force_fallback) ok = false;
     const double rho = fmin(0.5, 2.0 * Q * (double)cond * 5.960464477539063e-08);
@@ -680,6 +681,7 @@ __global__ __launch_bounds__(64) void k_pipe_solve_div(StencilArgs a, PipeRec *r
 #pragma unroll
     for (int i = 0; i < QS; ++i) est2 += fabs(x[i]);
     const double cond = anorm * fmax(est, est2);
+    if (valid && a.cond_out) a.cond_out[t] = (float)cond;
     if (!(cond <= opt.cond_threshold)) ok = false;
     if (opt.force_fallback) ok = false;
     // solves with the Gram: G_s^-1 v = sc . (L L^T)^-1 (sc . v)

@@ -440,7 +440,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
   }
   __syncthreads();
   const RowKinds rks = row_kinds(DIM, 0, ss.a.mask), rkv = row_kinds(DIM, 1, sv.a.mask);
-  WaveCounts cnt;
+  WaveCounts cnt, cntv;
   const SlotRange R = slot_range(meta, bin, -1, INT_MAX);
   for (int i = R.first + xcd_block(); i < R.last; i += gridDim.x) {
     const int t = list[i];
@@ -477,6 +477,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
     for (int k = 0; k < QS; ++k) rs += fabs(e[k]);
     const double cond = anorm * wave_max(rs);
+    if (lane == 0 && a.cond_out) a.cond_out[t] = (float)cond;
     if (!(cond <= opt.cond_threshold)) ok = false;
     if (opt.force_fallback) ok = false;
     const double dg = dsc / ifac;  // Dg_lane: G^-1 = Dg E^-1 Dg
@@ -498,15 +499,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
       }
     }
     __syncthreads();
-    const bool good = SCAL ? ok : okv;  // statistics of the (first) set
+    const bool good = SCAL ? ok : okv;  // statistics of the first set
     cnt.good += good ? 1 : 0;
     cnt.fell += good ? 0 : 1;
     if (cond >= 0.0) cnt.cond = fmax(cnt.cond, cond);  // NaN estimates are skipped
+    if constexpr (BASIS == 3) {  // the divergence-free set of a shared call: its own counters
+      cntv.good += okv ? 1 : 0;
+      cntv.fell += okv ? 0 : 1;
+    }
   }
   if (lane == 0) {
     if (cnt.good) atomicAdd(&stats->sweep_hist[0], cnt.good);
     if (cnt.fell) atomicAdd(&stats->n_fallback, cnt.fell);
     if (cnt.cond > 0.0) atomicMax(&stats->cond_max_bits, (unsigned long long)__double_as_longlong(cnt.cond));
+    if constexpr (BASIS == 3) {  // stats[1]: the second set (shared calls pass two records)
+      if (cntv.good) atomicAdd(&stats[1].sweep_hist[0], cntv.good);
+      if (cntv.fell) atomicAdd(&stats[1].n_fallback, cntv.fell);
+      if (cnt.cond > 0.0)
+        atomicMax(&stats[1].cond_max_bits, (unsigned long long)__double_as_longlong(cnt.cond));
+    }
   }
 }
 

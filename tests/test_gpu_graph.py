@@ -3,14 +3,19 @@ one HIP graph and replayed.
 
 Every replay is checked against the eager result of the normal mode, with
 eager work (the output buffers are overwritten) and synchronisations between
-the replays.  The capture-safe mode is also checked eagerly, and its
-deferred error reporting (gmls_check) is checked on a capacity overflow."""
+the replays, and the last replay against the FP64 oracle (neighbour sets,
+support radii, statuses and weights within the precision's gate).  The
+capture-safe mode is also checked eagerly, and its deferred error reporting
+(gmls_check) is checked on a capacity overflow."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import workloads as W
-from tests.gpu_helpers import dev, flush, host, require_gpu
+from tests.gpu_helpers import dev, flush, host, require_gpu, row_errors, row_sorted
+
+FP64_TOL, MIXED_TOL = 1e-10, 1e-8
 
 pytestmark = pytest.mark.gpu
 
@@ -79,7 +84,19 @@ def test_graph_replays_match_eager(prec, scheme):
             flush(f"graph: replay {rep}")
             g.replay()
             compare(f"replay {rep}")
+        flush("graph: last replay against the oracle")
+        rp, col, eps = host(outs["rp"]), host(col_buf[:nnz]), host(outs["eps"])
+        w, st = host(w_buf), host(st_buf)
     c.close()
+    orp, ocol, oeps = oracle.radius(pts, pts, r0, K_MIN)
+    assert np.array_equal(rp, orp) and np.array_equal(row_sorted(rp, col), ocol) and np.array_equal(eps, oeps)
+    # the oracle's stencils on the replay's rows (radius rows are sets; the
+    # weights follow the row order they are given)
+    ow, ost, _, _ = oracle.stencils(pts, pts, 3, "scalar", G.F_LAPLACIAN | G.F_GRAD, 4, oeps, orp, col)
+    assert np.array_equal(st == 1, ost == 1)
+    errs = row_errors(w, ow, rp, F, C)[ost != 1]
+    flush(f"  max rel err {errs.max():.3e}")
+    assert errs.max() <= (FP64_TOL if prec == G.PREC_FP64 else MIXED_TOL)
 
 
 def test_capture_safe_reports_capacity_through_check():
@@ -156,4 +173,17 @@ def test_graph_replays_shared_multi(order, k, p, fp64):
             flush(f"graph multi: replay {rep}")
             g.replay()
             compare(f"replay {rep}")
+        flush("graph multi: last replay against the oracle")
+        rp, col = host(gout["rp"]), host(col_buf)
+        got = [(host(w), host(st)) for w, st in outs]
     c.close()
+    orp, ocol, oeps = oracle.knn(pts, pts, k, 1.5)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol)
+    for (basis, mask), (w, st) in zip(sets, got):
+        name = "scalar" if basis == G.BASIS_SCALAR else "divfree"
+        ow, ost, F, C = oracle.stencils(pts, pts, order, name, mask, p, oeps, orp, ocol)
+        assert np.array_equal(st == 1, ost == 1)
+        zero = (F - 1,) if name == "divfree" and mask & G.F_DIV else ()
+        errs = row_errors(w, ow, rp, F, C, zero_rows=zero)[ost != 1]
+        flush(f"  {name}: max rel err {errs.max():.3e}")
+        assert errs.max() <= (FP64_TOL if fp64 else MIXED_TOL)

@@ -28,7 +28,20 @@ def multi(G, pts, rp, col, eps, order, p, sets, prec):
     s = dev(pts)
     outs, rep = G.gmls_stencils_multi(ctx(), s, s, order, p, dev(eps), dev(rp), dev(col), sets, prec=prec,
                                       report=True)
-    return [(host(w), host(st)) for w, st in outs], rep
+    got = [(host(w), host(st)) for w, st in outs]
+    check_report(rep, [st for _, st in got])
+    return got, rep
+
+
+def check_report(rep, statuses):
+    """The report counts (target, set) pairs by the statuses written, over
+    every set of the call."""
+    allst = np.concatenate(statuses)
+    assert rep["n_targets"] == allst.size
+    assert rep["n_rank_deficient"] == int((allst == 1).sum())
+    assert rep["n_fallback"] == int((allst == 2).sum())
+    assert rep["n_not_converged"] == int((allst == 3).sum())
+    assert rep["n_ok"] == allst.size - rep["n_rank_deficient"]
 
 
 @pytest.mark.parametrize("names", [("3d_m4_k170", "3d_divfree_m4"), ("3d_divfree_m4_k30", "3d_divfree_m4_k30")])

@@ -189,3 +189,42 @@ def test_radius_cell_order_clustered_and_floored():
         assert_same(a, o, f"clustered r0={r0}", sets=True)
         assert np.array_equal(a[1], gpu_radius(src, src, r0, k_min)[1])
         assert_same(gpu_radius(src, src, r0, k_min, row_order=1), o, f"clustered r0={r0}, index order")
+
+
+def test_radius_empty_rows_without_floor():
+    """k_min = 0: a target with no source inside the radius gets an empty row
+    and eps = r0, in the one-pass (scratch rows) and the two-pass variants.
+    A search with full rows runs first on the same context, so that a row
+    count or flag left in the workspace would show."""
+    G = require_gpu()
+    src = W.density_ramp(5000, 78)
+    g = W.rng(10)
+    tgt = np.concatenate([g.uniform(-0.4, 1.4, size=(400, 3)), src[:100]])
+    r0 = W.radius_for_mean_count(5000)
+    o = oracle.radius(src, tgt, r0, 0)
+    assert (np.diff(o[0]) == 0).sum() >= 50 and (np.diff(o[0]) > 0).sum() >= 100
+    c = ctx()
+    for mb in (8192, 0):
+        c.set_option(G.OPT_RADIUS_SCRATCH_MB, mb)
+        try:
+            flush(f"radius empty rows, scratch {mb} MiB")
+            gpu_radius(src, src, r0, 30)  # leaves full rows in the workspace
+            assert_same(gpu_radius(src, tgt, r0, 0), o, f"empty rows, scratch {mb}", sets=True)
+            assert_same(gpu_radius(src, tgt, r0, 0, row_order=1), o, f"empty rows, index order, scratch {mb}")
+        finally:
+            c.set_option(G.OPT_RADIUS_SCRATCH_MB, 8192)
+
+
+def test_search_time_in_report():
+    """The stencil report carries the GPU time of the context's last search."""
+    G = require_gpu()
+    src = W.density_ramp(20000, 1004)
+    s = dev(src)
+    c = ctx()
+    rp, col, eps = G.gmls_neighbors(c, s, s, G.SEARCH_RADIUS, radius=W.radius_for_mean_count(20000), k_min=30)
+    _, _, rep = G.gmls_stencils(c, s, s, 2, G.BASIS_SCALAR, G.F_LAPLACIAN, 4, eps, rp, col, prec=G.PREC_MIXED,
+                                report=True)
+    flush(f"report {rep}")
+    assert 0.0 < rep["t_search_ms"] < 1e4
+    assert 0.0 < rep["cond_min"] <= rep["cond_max"]
+    assert rep["cond_min"] / 1.03 <= rep["cond_med"] <= rep["cond_max"] * 1.03

@@ -188,6 +188,12 @@ def check_mixed(name, gw, gst, rep):
     # every target not rank deficient is counted once: converged, fallback or not converged
     n_live = int((st != 1).sum())
     assert sum(rep["sweep_hist"]) + rep["n_fallback"] + rep["n_not_converged"] == n_live
+    # the report's counts are those of the statuses written
+    assert rep["n_fallback"] == int((gst == 2).sum()) and rep["n_not_converged"] == int((gst == 3).sum())
+    assert rep["n_rank_deficient"] == int((gst == 1).sum())
+    if sum(rep["sweep_hist"]) > 0:  # condition numbers of the Grams the mixed kernels factored
+        assert 0.0 < rep["cond_min"] <= rep["cond_max"] * (1 + 1e-6)
+        assert rep["cond_min"] / 1.03 <= rep["cond_med"] <= rep["cond_max"] * 1.03
 
 
 @pytest.mark.parametrize("scheme", [1, 2, 3, 4], ids=["rows", "gram", "pipe", "wave"])
@@ -298,3 +304,32 @@ def test_mixed_near_coplanar_triggers_fallback(scheme):
     assert np.array_equal(gst == 1, st == 1)
     errs = row_errors(gw, w, rp, F, C)
     assert errs[ok].max() <= MIXED_TOL
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_duplicate_points(prec):
+    """Every point of the cloud three times over: with 12 neighbours a target
+    sees 4 distinct points (fewer than the 6 functions of order 2 in 2D), so
+    its weighted sample matrix is rank deficient although N >= Q; with 30 it
+    sees 10 and the duplicated rows only weight them.  Statuses must equal the
+    oracle's and the weights must be within the gate where defined."""
+    G = require_gpu()
+    base = W.jittered_grid(400, 2, 31)
+    pts = np.repeat(base, 3, axis=0)
+    p = G.PREC_FP64 if prec == "fp64" else G.PREC_MIXED
+    s = dev(pts)
+    for k in (12, 30):
+        rp, col, eps = oracle.knn(pts, pts, k, 1.5)
+        w, st, F, C = oracle.stencils(pts, pts, 2, "scalar", 2 | 4, 4, eps, rp, col)
+        assert (st == 1).all() if k == 12 else (st == 0).all()
+        flush(f"duplicate points k={k} prec={prec}")
+        gw, gst, rep = G.gmls_stencils(ctx(), s, s, 2, G.BASIS_SCALAR, 2 | 4, 4, dev(eps), dev(rp), dev(col),
+                                       prec=p, report=True)
+        gw, gst = host(gw), host(gst)
+        assert np.array_equal(gst == 1, st == 1)
+        assert rep["n_rank_deficient"] == int((st == 1).sum())
+        if k == 12:
+            assert np.isnan(gw).all()
+        else:
+            errs = row_errors(gw, w, rp, F, C)
+            assert errs.max() <= (FP64_TOL if prec == "fp64" else MIXED_TOL)

@@ -375,3 +375,40 @@ def test_rank_deficient_flags():
     rp, col, eps = oracle.knn(flat, flat, 30, 1.5)
     w, st, F, C = oracle.stencils(flat, flat, 2, "scalar", F_LAP, 4, eps, rp, col)
     assert st.all()
+
+
+# --------------------------------------------------------------------------
+# Duplicate points: repeated rows of the weighted sample matrix
+# --------------------------------------------------------------------------
+def test_duplicate_points():
+    """Each point three times over.  Twelve neighbours are four distinct
+    points, fewer than the six functions of order 2 in 2D: every target is
+    rank deficient although N >= Q.  Thirty neighbours are the ten nearest
+    distinct points three times; tripling every row triples the Gram, so each
+    copy's weight is one third of the weight on the distinct cloud with ten
+    neighbours (the same support radius), and the copies of a point sum to it."""
+    base = W.jittered_grid(400, 2, 31)
+    pts = np.repeat(base, 3, axis=0)
+    mask = F_GRAD | F_LAP
+    rp, col, eps = oracle.knn(pts, pts, 12, 1.5)
+    w, st, F, C = oracle.stencils(pts, pts, 2, "scalar", mask, 4, eps, rp, col)
+    assert (st == 1).all() and np.isnan(w).all()
+    rp, col, eps = oracle.knn(pts, pts, 30, 1.5)
+    w, st, F, C = oracle.stencils(pts, pts, 2, "scalar", mask, 4, eps, rp, col)
+    brp, bcol, beps = oracle.knn(base, base, 10, 1.5)
+    bw, bst, _, _ = oracle.stencils(base, base, 2, "scalar", mask, 4, beps, brp, bcol)
+    assert not st.any() and not bst.any()
+    for t in range(0, len(pts), 7):
+        b = t // 3
+        assert eps[t] == beps[b]
+        a = rows_of(w, rp, t, F, C)[:, :, 0]
+        src = col[rp[t]:rp[t + 1]] // 3
+        summed = np.zeros((F, len(base)))
+        np.add.at(summed.T, src, a.T)
+        ref = rows_of(bw, brp, b, F, C)[:, :, 0]
+        got = summed[:, bcol[brp[b]:brp[b + 1]]]
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        # the three copies of a point (adjacent: equal distances, ties by index) carry equal weights
+        trip = a.reshape(F, -1, 3)
+        assert np.array_equal(src.reshape(-1, 3), np.repeat(src[::3, None], 3, axis=1))
+        assert np.abs(trip - trip[:, :, :1]).max() <= 1e-12 * np.abs(a).max()
