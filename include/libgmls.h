@@ -312,6 +312,22 @@ gmls_status gmls_assemble_stokes(gmls_ctx ctx, const gmls_stokes_stencils *stenc
 gmls_status gmls_spmv(gmls_ctx ctx, int64_t n_rows, const int64_t *row_ptr, const int32_t *col, const double *val,
                       const double *x, double *y);
 
+/* gmls_spmv without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  The same kernels and summation order as gmls_spmv, so
+ * y is bit for bit the one gmls_spmv gives.  Its scratch (the list of rows
+ * longer than 8192 entries) is a file-scope device array of the library of
+ * 4 * (64 + 2^23) bytes (32 MiB), one per GPU, held until the process ends;
+ * its address on a device is looked up when a context is created there.
+ *   n_rows  0 .. 8388608 (2^23); more returns GMLS_ERR_ARG and enqueues nothing
+ * Other arguments as for gmls_spmv.  Every call on one GPU uses that GPU's
+ * scratch: calls that overlap in time on one GPU (different streams or
+ * contexts) race and must not be made; calls in one stream order are safe.
+ * Does not synchronise; no allocation, no memset (the counter is cleared by
+ * a kernel). */
+gmls_status gmls_spmv_noalloc(gmls_ctx ctx, int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                              const double *val, const double *x, double *y);
+
 /* Errors of capture-safe calls found on the device since the last check
  * (GMLS_OPT_CAPTURE_SAFE): GMLS_OK, GMLS_ERR_CAPACITY or GMLS_ERR_UNSUPPORTED
  * with a message in gmls_last_error.  Synchronises; clears the record. */

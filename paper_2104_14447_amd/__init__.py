@@ -26,7 +26,7 @@ __all__ = [
     "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "OPT_ROW_ORDER", "ROW_ORDER_CELL",
     "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE", "SCHEME_WAVE",
     "OPT_PIPE_SHAPE", "TuneResult", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
-    "StencilSet", "gmls_stencils_multi",
+    "StencilSet", "gmls_stencils_multi", "gmls_spmv_noalloc", "NOALLOC_SPMV_MAX_ROWS",
     "EXPORTED_SYMBOLS",
 ]
 
@@ -40,6 +40,7 @@ OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2
 OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE, OPT_ROW_ORDER = 4, 5, 6, 7, 8
 OPT_PIPE_SHAPE = 9
 ROW_ORDER_CELL, ROW_ORDER_INDEX = 0, 1
+NOALLOC_SPMV_MAX_ROWS = 1 << 23  # rows gmls_spmv_noalloc takes (its static scratch)
 SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE, SCHEME_WAVE = 0, 1, 2, 3, 4
 GMLS_OK, GMLS_ERR_CAPACITY, GMLS_ERR_UNSUPPORTED, GMLS_WARN_TARGET_FLAGS = 0, 4, 5, 6
 _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY", 5: "ERR_UNSUPPORTED",
@@ -47,7 +48,7 @@ _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY
 EXPORTED_SYMBOLS = ("gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
                     "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained", "gmls_stencils_staggered",
                     "gmls_assemble_stokes", "gmls_spmv", "gmls_apply", "gmls_check", "gmls_autotune",
-                    "gmls_autotune_save", "gmls_autotune_load", "gmls_stencils_multi")
+                    "gmls_autotune_save", "gmls_autotune_load", "gmls_stencils_multi", "gmls_spmv_noalloc")
 
 
 class GmlsError(RuntimeError):
@@ -152,6 +153,8 @@ def load_library():
     L.gmls_assemble_stokes.restype = ctypes.c_int
     L.gmls_spmv.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp]
     L.gmls_spmv.restype = ctypes.c_int
+    L.gmls_spmv_noalloc.argtypes = [_vp, _i64, _vp, _vp, _vp, _vp, _vp]
+    L.gmls_spmv_noalloc.restype = ctypes.c_int
     L.gmls_check.argtypes = [_vp]
     L.gmls_check.restype = ctypes.c_int
     L.gmls_autotune.argtypes = [_vp, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
@@ -468,3 +471,15 @@ def gmls_apply(ctx: Context, row_ptr: torch.Tensor, col: torch.Tensor, weights: 
     if st != GMLS_OK:
         ctx._raise(st)
     return out[:n_tgt]
+
+
+def gmls_spmv_noalloc(ctx: Context, row_ptr: torch.Tensor, col: torch.Tensor, val: torch.Tensor, x: torch.Tensor,
+                      y: torch.Tensor):
+    """y = A x like gmls_spmv, with no device allocation in the library (the
+    caller passes y; the long-row list lives in the library's static scratch)."""
+    _check_dev(row_ptr, col, val, x, y)
+    rows = row_ptr.numel() - 1
+    st = load_library().gmls_spmv_noalloc(ctx._h, rows, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(x), _ptr(y))
+    if st != GMLS_OK:
+        ctx._raise(st)
+    return y[:rows]

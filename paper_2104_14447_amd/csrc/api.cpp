@@ -123,6 +123,12 @@ gmls_status gmls_create(gmls_ctx *out, int device, void *hip_stream) {
     delete ctx;
     return GMLS_ERR_HIP;
   }
+  // the allocation-free product's scratch address on this device (current here)
+  if (spmv_scratch_setup(device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ctx;
+    return GMLS_ERR_HIP;
+  }
   *out = ctx;
   return GMLS_OK;
 }
@@ -775,6 +781,24 @@ gmls_status gmls_spmv(gmls_ctx ctx, int64_t n_rows, const int64_t *row_ptr, cons
   int *lr = (int *)ctx->ws(WS_SPMV_LONG, sizeof(int) * (size_t)(n_rows + 1));
   if (!lr) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
   GMLS_HIP(launch_spmv(n_rows, row_ptr, col, val, x, y, lr + 1, lr, ctx->cus, ctx->stream));
+  return GMLS_OK;
+}
+
+gmls_status gmls_spmv_noalloc(gmls_ctx ctx, int64_t n_rows, const int64_t *row_ptr, const int32_t *col,
+                              const double *val, const double *x, double *y) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (n_rows < 0 || n_rows > kNoAllocSpmvRows)
+    return gmls_set_error(ctx, GMLS_ERR_ARG,
+                          "gmls_spmv_noalloc takes 0 .. " + std::to_string(kNoAllocSpmvRows) + " rows");
+  if (n_rows == 0) return GMLS_OK;
+  if (!row_ptr || !col || !val || !x || !y) return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  int *sp = spmv_scratch(ctx->device);
+  if (!sp) return gmls_set_error(ctx, GMLS_ERR_HIP, "the scratch of gmls_spmv_noalloc was not set up on this device");
+  DeviceGuard g(ctx->device);
+  // the counter at word 0 is cleared by a kernel of launch_spmv; the list
+  // starts at word 64
+  GMLS_HIP(launch_spmv(n_rows, row_ptr, col, val, x, y, sp + 64, sp, ctx->cus, ctx->stream));
   return GMLS_OK;
 }
 

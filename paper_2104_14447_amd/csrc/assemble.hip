@@ -17,6 +17,9 @@
 // A velocity row holds the K block then the G block, a pressure row the N
 // block (boundary), then the L block, then the multiplier; entries follow the
 // neighbour order.  One wavefront writes all rows of a particle.
+#include <atomic>
+#include <mutex>
+
 #include "common.hpp"
 #include "gmls_internal.hpp"
 
@@ -217,6 +220,37 @@ hipError_t launch_spmv(int64_t rows, const int64_t *rp, const int32_t *col, cons
   k_spmv<<<(unsigned)g, 256, 0, s>>>(rows, rp, col, val, x, y, long_rows, n_long);
   k_spmv_long<<<64, 1024, 0, s>>>(rp, col, val, x, y, long_rows, n_long);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free product (gmls_spmv_noalloc): the long-row
+// counter at word 0 and the long-row list from word 64 (256-byte aligned),
+// room for every row of a matrix of up to kNoAllocSpmvRows rows.  Each device
+// holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) int scratch[64 + kNoAllocSpmvRows];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mutex;
+static std::atomic<int *> g_scratch_ptr[kMaxScratchDevices];
+
+hipError_t spmv_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device].load(std::memory_order_acquire)) return hipSuccess;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[device].load(std::memory_order_relaxed)) return hipSuccess;
+  int *p = nullptr;  // the caller has made `device` current
+  hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device].store(p, std::memory_order_release);
+  return hipSuccess;
+}
+
+int *spmv_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  return g_scratch_ptr[device].load(std::memory_order_acquire);
 }
 
 }  // namespace gmls

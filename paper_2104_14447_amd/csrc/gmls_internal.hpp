@@ -287,6 +287,13 @@ hipError_t launch_stokes_assembly(const StokesArgs &s, int64_t *rlen, int64_t *a
                                   double *aval, int64_t capacity, int *flags, int cus, hipStream_t st);
 hipError_t launch_spmv(int64_t rows, const int64_t *rp, const int32_t *col, const double *val, const double *x,
                        double *y, int *long_rows, int *n_long, int cus, hipStream_t s);
+// allocation-free product: rows of at most kNoAllocSpmvRows, the long-row
+// list in the file-scope device array of assemble.hip, whose address on a
+// device spmv_scratch_setup (called with that device current, once per
+// device) looks up and spmv_scratch returns (nullptr before the set-up)
+constexpr int64_t kNoAllocSpmvRows = (int64_t)1 << 23;
+hipError_t spmv_scratch_setup(int device);
+int *spmv_scratch(int device);
 
 hipError_t launch_apply(int64_t n_tgt, const int64_t *row_ptr, const int32_t *col, const double *weights, int F,
                         int C, const double *field, double *out, hipStream_t s);
