@@ -19,7 +19,9 @@ import numpy as np
 from . import divfree  # noqa: F401  (re-exported helper module)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# GMLS_ORACLE_LIB selects another build of the same source (the sanitizer
+# build of oracle/build.py, loaded by the sanitizer test in a subprocess)
+_LIB_PATH = os.environ.get("GMLS_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 F_VALUE, F_GRAD, F_LAPLACIAN, F_DIV = 1, 2, 4, 8

@@ -80,5 +80,38 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB
 
 
+SAN_DIR = os.path.join(BUILD, "san")
+SAN_LIB = os.path.join(SAN_DIR, "libgmls_san.so")
+
+
+def build_sanitized(verbose: bool = False) -> str:
+    """The library with its ABI layer (api.cpp: argument validation, reports,
+    workspace, the autotune table and its JSON files) built with
+    AddressSanitizer and UndefinedBehaviorSanitizer on the host side only,
+    linked with the objects of build() (call that first) into
+    _build/san/libgmls_san.so for tests/test_sanitizers.py.  Device code is
+    not instrumented (no GPU sanitizer here)."""
+    os.makedirs(SAN_DIR, exist_ok=True)
+    obj = os.path.join(SAN_DIR, "api.o")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+    cmd = [hipcc()] + COMMON + san + ["-x", "hip", "-c", os.path.join(CSRC, "api.cpp"), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the sanitized api.cpp:\n{r.stdout}\n{r.stderr}")
+    objs = [os.path.join(BUILD, n + ".o") for n, _, _ in units() if n != "api"]
+    tmp = SAN_LIB + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-fsanitize=undefined", "-shared-libsan", "-o", tmp, obj] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    print(build_sanitized(verbose="-v" in sys.argv))

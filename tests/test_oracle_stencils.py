@@ -412,3 +412,44 @@ def test_duplicate_points():
         trip = a.reshape(F, -1, 3)
         assert np.array_equal(src.reshape(-1, 3), np.repeat(src[::3, None], 3, axis=1))
         assert np.abs(trip - trip[:, :, :1]).max() <= 1e-12 * np.abs(a).max()
+
+
+# --------------------------------------------------------------------------
+# P10: convergence of the stencils on refining clouds (Section 2.5: a
+# derivative D^beta of an order-m fit converges as h^(m+1-|beta|))
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim,order,k,sides", [(2, 2, 12, (20, 40, 80)), (2, 4, 30, (20, 40, 80)),
+                                                (3, 2, 30, (10, 16, 24)), (3, 3, 50, (10, 16, 24))])
+def test_convergence_order(dim, order, k, sides):
+    """u = prod_d sin(pi x_d) (the paper's manufactured field of Section 4.2
+    scaled to the unit box) on jittered grids of spacing h = 1/n: the RMS
+    error of the x-derivative and Laplacian stencils over the targets in the
+    middle of the box falls at least as h^(m+1-|beta|), with 0.3 of slack on
+    the fitted log-log slope.  (The Laplacian of an even order can converge
+    faster on these quasi-uniform clouds, so only the lower bound is held.)
+    A wrong power of eps, a dropped term or a wrong functional changes the
+    slope by a whole order or stops the convergence."""
+    hs, eg, el = [], [], []
+    for n in sides:
+        pts = W.jittered_grid(n ** dim, dim, 7)
+        rp, col, eps = knn_case(pts, k)
+        w, st, F, C = oracle.stencils(pts, pts, order, "scalar", F_GRAD | F_LAP, 4, eps, rp, col)
+        assert not st.any()
+        u = np.prod(np.sin(np.pi * pts), axis=1)
+        gx = np.pi * np.cos(np.pi * pts[:, 0]) * np.prod(np.sin(np.pi * pts[:, 1:]), axis=1)
+        lap = -dim * np.pi ** 2 * u
+        inner = np.where(np.all((pts > 0.3) & (pts < 0.7), axis=1))[0]
+        g, lp = [], []
+        for t in inner:
+            a = rows_of(w, rp, t, F, C)[:, :, 0]
+            v = u[col[rp[t]:rp[t + 1]]]
+            g.append(a[0] @ v - gx[t])
+            lp.append(a[F - 1] @ v - lap[t])
+        hs.append(1.0 / n)
+        eg.append(np.sqrt(np.mean(np.square(g))))
+        el.append(np.sqrt(np.mean(np.square(lp))))
+    slope_g = np.polyfit(np.log(hs), np.log(eg), 1)[0]
+    slope_l = np.polyfit(np.log(hs), np.log(el), 1)[0]
+    assert slope_g >= order - 0.3, (slope_g, eg)
+    assert slope_l >= order - 1 - 0.3, (slope_l, el)
+    assert eg[-1] < eg[0] and el[-1] < el[0]
