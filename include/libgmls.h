@@ -161,7 +161,7 @@ enum {
                                     row_ptr[n_tgt] on the device); a total over col_capacity leaves
                                     col unwritten and is reported by gmls_check;
                                   - gmls_stencils takes no report (GMLS_ERR_ARG otherwise); a row
-                                    longer than 256 leaves its target unwritten and is reported by
+                                    longer than 2^24 leaves its target unwritten and is reported by
                                     gmls_check.                                                  */
   GMLS_OPT_ROW_ORDER = 8,      /* order of the entries of a radius row (a set) (0):
                                   0 = cell order: by (cell of the source in the search's uniform
@@ -229,7 +229,12 @@ gmls_status gmls_stencil_shape(int dim, int order, int basis, unsigned functiona
  *             neighbour j (the j-th entry of the row) in functional row f
  *   target_status  out (nullable): uint8 [n_tgt], GMLS_TARGET_*
  *   report    host out (nullable): summary; a non-NULL report synchronises
- * Rows must satisfy 1 <= N_t <= 256 (N_t < Q gives a rank-deficient target).
+ * Rows must satisfy 0 <= N_t <= 2^24 (N_t * C_in < Q gives a rank-deficient
+ * target).  Rows of more than 256 neighbours are taken in chunks: the FP64
+ * QR factors them by a tall-skinny QR (the factor of 64 RPL rows stacked
+ * with the next rows), the mixed pipeline loops its moment and weight
+ * kernels over them, and the other mixed schemes hand them to the FP64 QR
+ * path (status GMLS_TARGET_FALLBACK).
  * Returns GMLS_WARN_TARGET_FLAGS when a report is requested and some targets
  * are rank deficient. */
 gmls_status gmls_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
@@ -407,7 +412,8 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
  * 64(b-1) < N <= 64b neighbours): G lanes per target and R rows per lane,
  * G*R >= 64b, listed in gmls_tune_result.  How fast a shape runs depends on
  * the neighbour counts, the cloud's order in memory and the functional count,
- * so it is measured rather than modelled.
+ * so it is measured rather than modelled.  Bin 5 holds the rows of more than
+ * 256 neighbours, which the kernels take in chunks of G*R rows.
  *
  * gmls_autotune runs the stencil computation of gmls_stencils (prec =
  * GMLS_PREC_MIXED) on the given problem `reps` times per candidate (every bin
@@ -423,7 +429,7 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
  * scheme does not run the pipeline; otherwise those of gmls_stencils.  `out`
  * (host, nullable) receives the candidates, their times and the choice.
  * -------------------------------------------------------------------------*/
-enum { GMLS_TUNE_BINS = 5, GMLS_TUNE_CANDIDATES = 3 };
+enum { GMLS_TUNE_BINS = 6, GMLS_TUNE_CANDIDATES = 3 };
 typedef struct {
   int32_t lanes[2][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES]; /* [kernel][bin][candidate]: G (bin 0 unused) */
   int32_t rows[2][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];  /* R, rows per lane                         */

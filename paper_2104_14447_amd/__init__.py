@@ -69,14 +69,14 @@ class StencilSet(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     """gmls_tune_result: [kernel 0 moments, 1 weights][bin][candidate]."""
-    _fields_ = [("lanes", ctypes.c_int32 * 3 * 5 * 2), ("rows", ctypes.c_int32 * 3 * 5 * 2),
-                ("ms", ctypes.c_float * 3 * 5 * 2), ("chosen", ctypes.c_int32 * 5 * 2)]
+    _fields_ = [("lanes", ctypes.c_int32 * 3 * 6 * 2), ("rows", ctypes.c_int32 * 3 * 6 * 2),
+                ("ms", ctypes.c_float * 3 * 6 * 2), ("chosen", ctypes.c_int32 * 6 * 2)]
 
     def as_dict(self):
         out = {}
         for k, kname in enumerate(("moments", "weights")):
             bins = {}
-            for b in range(1, 5):
+            for b in range(1, 6):
                 c = self.chosen[k][b]
                 if c < 0:
                     continue

@@ -411,7 +411,7 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
   if (sync) {
     GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
     GMLS_HIP(hipStreamSynchronize(s));
-    if (hm.err) return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 256 neighbours");
+    if (hm.err) return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 2^24 neighbours");
   } else {
     // rows over the compiled maximum stay in bin 7 (never processed) and are
     // reported by gmls_check
@@ -459,6 +459,8 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
       if (prec == GMLS_PREC_FP64) {
         const int nb = std::min(cnt, cus * 16);
         GMLS_HIP(launch_qr_bin(dim, order, basis, b, a, list, meta, nb, s));
+      } else if (b == kLongBin) {  // the fused kernels hold at most 256 rows: FP64 QR in chunks
+        GMLS_HIP(launch_defer_bin(a.status, list, meta, b, fb, &meta->fb_count, stats, s));
       } else {
         GMLS_HIP(launch_mixed_bin(dim, order, basis, b, a, list, meta, fb, stats, opt, cnt, cus, s));
       }
@@ -558,7 +560,7 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
   if (sync) {
     GMLS_HIP(hipMemcpyAsync(&hm, meta, sizeof(BinMeta), hipMemcpyDeviceToHost, s));
     GMLS_HIP(hipStreamSynchronize(s));
-    if (hm.err) return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 256 neighbours");
+    if (hm.err) return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target has more than 2^24 neighbours");
   } else {
     GMLS_HIP(or_error_bit((int *)ctx->ws(WS_DEV_ERR, sizeof(int)), &meta->err, 1, DEV_ERR_STENCIL_ROWS, s));
   }
@@ -818,7 +820,7 @@ gmls_status gmls_check(gmls_ctx ctx) {
     return gmls_set_error(ctx, GMLS_ERR_CAPACITY, "a neighbour search needed more than col_capacity entries");
   if (bits & DEV_ERR_RADIUS_ROWS)
     return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a target had more than 2048 sources inside the radius");
-  return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a stencil call had a target with more than 256 neighbours");
+  return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "a stencil call had a target with more than 2^24 neighbours");
 }
 
 gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, const int32_t *col,

@@ -269,6 +269,10 @@ size_t binning_temp_bytes(int n_tgt);
 hipError_t launch_binning(const int64_t *row_ptr, const double *targets, int n_tgt, int dim, int Q,
                           int rows_per_nbr, BinMeta *meta, int *list, void *temp, size_t temp_bytes, hipStream_t s);
 hipError_t launch_rank_deficient(const StencilArgs &a, int C, const int *list, BinMeta *meta, hipStream_t s);
+// every target of `bin` to the FP64 fallback queue fb_list / *fb_count with
+// status FALLBACK (stats: counted there unless null)
+hipError_t launch_defer_bin(uint8_t *status, const int *list, const BinMeta *meta, int bin, int *fb_list,
+                            int *fb_count, Stats *stats, hipStream_t s);
 
 // apply (apply.hip)
 // global Stokes operator (assemble.hip)
@@ -298,14 +302,18 @@ int *spmv_scratch(int device);
 hipError_t launch_apply(int64_t n_tgt, const int64_t *row_ptr, const int32_t *col, const double *weights, int F,
                         int C, const double *field, double *out, hipStream_t s);
 
-// number of bins: 0 = rank deficient (N*C < Q), b >= 1: N <= 64*b
-constexpr int kNumBins = 5;
-constexpr int kMaxRows = 256;
+// number of bins: 0 = rank deficient (N*C < Q), b = 1..4: 64(b-1) < N <=
+// 64b, b = 5 (kLongBin): 256 < N <= kMaxRows, rows taken in chunks; a longer
+// row (bin 7 of the binning) fails the call
+constexpr int kNumBins = 6;
+constexpr int kLongBin = 5;
+constexpr int kMaxRows = 1 << 24;
 
 // Row shapes of the pipeline's row-parallel kernels (moments, weights):
-// G lanes per target, RPL rows per lane, G * RPL >= 64 b for bin b.  All
-// three are compiled for every bin; candidate 0 is the untuned default and
-// the autotuner keeps the fastest per (dimension, order, basis, kernel, bin).
+// G lanes per target, RPL rows per lane, G * RPL >= 64 b for bin b (the long
+// bin loops over chunks of G * RPL rows).  All three are compiled for every
+// bin; candidate 0 is the untuned default and the autotuner keeps the
+// fastest per (dimension, order, basis, kernel, bin).
 constexpr int kPipeCands = 3;
 struct PipeShape {
   int g, rpl;
@@ -315,7 +323,8 @@ constexpr PipeShape kPipeShapes[kNumBins][kPipeCands] = {
     {{8, 8}, {16, 4}, {4, 16}},
     {{16, 8}, {32, 4}, {8, 16}},
     {{32, 6}, {16, 12}, {64, 3}},
-    {{32, 8}, {64, 4}, {16, 16}}};
+    {{32, 8}, {64, 4}, {16, 16}},
+    {{64, 4}, {64, 2}, {32, 8}}};
 
 }  // namespace gmls
 

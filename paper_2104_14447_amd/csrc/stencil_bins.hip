@@ -2,7 +2,8 @@
 //
 // Targets are split by neighbour count N into bins: bin 0 holds targets with
 // fewer sample rows than basis functions (rank deficient by construction);
-// bin b >= 1 holds 64*(b-1) < N <= 64*b.  Each bin is a contiguous slice of
+// bin b = 1..4 holds 64*(b-1) < N <= 64*b, bin 5 the longer rows (the
+// kernels take those in chunks).  Each bin is a contiguous slice of
 // one packed index list.  Inside a bin the targets follow a Morton (Z-order)
 // curve of cells over the targets' bounding box: consecutive targets are
 // spatial neighbours, so their neighbour rows overlap and the coordinate
@@ -23,6 +24,7 @@ constexpr int kBinBlock = 256;
 __device__ __forceinline__ int bin_of(int64_t n, int Q, int C) {
   if (n * C < Q) return 0;
   if (n > kMaxRows) return -1;
+  if (n > 256) return kLongBin;
   return (int)((n + 63) / 64);
 }
 
@@ -103,6 +105,7 @@ __device__ __forceinline__ unsigned quant(double v, double lo, double inv, int b
 
 constexpr int kCellBits = 18;                  // Morton cells per bin
 constexpr int64_t kBuckets = 8ll << kCellBits;  // bins 0..7 (7: rows over the maximum)
+static_assert(kNumBins <= 7, "bin 7 holds the rows over the maximum");
 
 // bucket = bin << 18 | Morton cell (3D: 6 bits per axis, 2D: 9, 1D: 18);
 // rank = the target's place in its bucket
@@ -301,6 +304,27 @@ __global__ void k_rank_deficient(StencilArgs a, int C, const int *list, const Bi
     if (a.hweights && (int)threadIdx.x < a.F) a.hweights[(int64_t)t * a.F + threadIdx.x] = NAN;
     if (threadIdx.x == 0) a.status[t] = GMLS_TARGET_RANK_DEFICIENT;
   }
+}
+
+// The targets of bin `bin` handed to the FP64 QR kernels: status FALLBACK,
+// queued on fb_list (counter *fb_count), counted in stats (may be null).
+// The wavefront and fused mixed kernels hold a row's sample in registers and
+// take the long bin this way; the QR kernels factor long rows in chunks.
+__global__ void k_defer_bin(uint8_t *status, const int *list, const BinMeta *meta, int bin, int *fb_list,
+                            int *fb_count, Stats *stats) {
+  const int n = meta->count[bin], off = meta->offset[bin];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int t = list[off + i];
+    status[t] = GMLS_TARGET_FALLBACK;
+    fb_list[atomicAdd(fb_count, 1)] = t;
+  }
+  if (stats && blockIdx.x == 0 && threadIdx.x == 0 && n > 0) atomicAdd(&stats->n_fallback, (unsigned long long)n);
+}
+
+hipError_t launch_defer_bin(uint8_t *status, const int *list, const BinMeta *meta, int bin, int *fb_list,
+                            int *fb_count, Stats *stats, hipStream_t s) {
+  k_defer_bin<<<64, 256, 0, s>>>(status, list, meta, bin, fb_list, fb_count, stats);
+  return hipGetLastError();
 }
 
 hipError_t launch_rank_deficient(const StencilArgs &a, int C, const int *list, BinMeta *meta, hipStream_t s) {

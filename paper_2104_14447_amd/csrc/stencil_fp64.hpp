@@ -23,43 +23,52 @@ namespace gmls {
 
 constexpr double kRankTol = 1e-12;  // QR rank test: min|R_kk| <= tol * max|R_kk|
 
-// Rows of one target held by a wavefront; loads coordinates and weights.
+// Rows of one target held by a wavefront: rows first + lane + 64 i of the
+// target's neighbour row (a chunk of 64 RPL rows; rows with more neighbours
+// are taken chunk by chunk).
 template <int DIM, int RPL>
 struct Rows {
   double s[RPL][DIM];
   double w[RPL];
   int N;
+  int first;  // the chunk held (-1: none)
   int64_t base;
 };
 
+// scaled offset and kernel weight of row j of target t (zero for j >= N)
+template <int DIM>
+__device__ __forceinline__ void row_s_w(const StencilArgs &a, int64_t base, int j, int N, const double *xt,
+                                        double ie, double *s, double &w) {
+  double rr = 0.0;
+  if (j < N) {
+    const int c = a.col[base + j];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      s[d] = (a.coords[(int64_t)c * DIM + d] - xt[d]) * ie;
+      rr += s[d] * s[d];
+    }
+    const double rad = sqrt(rr);
+    w = rad < 1.0 ? int_pow(1.0 - rad, a.p) : 0.0;
+  } else {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) s[d] = 0.0;
+    w = 0.0;
+  }
+}
+
 template <int DIM, int RPL>
-__device__ __forceinline__ void load_rows(const StencilArgs &a, int t, Rows<DIM, RPL> &r, int lane) {
+__device__ __forceinline__ void load_rows(const StencilArgs &a, int t, Rows<DIM, RPL> &r, int lane,
+                                          int first = 0) {
   r.base = uniform_i64(a.row_ptr[t]);
   r.N = readfirstlane_i((int)(a.row_ptr[t + 1] - r.base));
+  r.first = first;
   const double e = uniform_d(a.eps[t]);
   const double ie = 1.0 / e;
   double xt[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) xt[d] = uniform_d(a.targets[(int64_t)t * DIM + d]);
 #pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int j = lane + 64 * i;
-    double rr = 0.0;
-    if (j < r.N) {
-      const int c = a.col[r.base + j];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        r.s[i][d] = (a.coords[(int64_t)c * DIM + d] - xt[d]) * ie;
-        rr += r.s[i][d] * r.s[i][d];
-      }
-      const double rad = sqrt(rr);
-      r.w[i] = rad < 1.0 ? int_pow(1.0 - rad, a.p) : 0.0;
-    } else {
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) r.s[i][d] = 0.0;
-      r.w[i] = 0.0;
-    }
-  }
+  for (int i = 0; i < RPL; ++i) row_s_w<DIM>(a, r.base, first + lane + 64 * i, r.N, xt, ie, r.s[i], r.w[i]);
 }
 
 // Householder QR of the register-resident M (rows across lanes).  On return
@@ -136,6 +145,12 @@ __device__ __forceinline__ double tri_solve_rtr(const double *Rm, const double *
 
 // The target's rows, its weighted sample matrix and the Householder factor:
 // on return lane k < Q holds row k of R in M[0][k..Q-1] and rdiag = R_kk.
+// A row of more than 64 RPL neighbours is factored chunk by chunk (tall-skinny
+// QR): R of the rows so far stays on lanes 0..Q-1 of slot 0, with its
+// strictly lower part cleared, and the next 64 RPL - Q rows fill the other
+// positions; the Householder QR of that stack is R of all the rows so far
+// (the same R up to the signs of its rows, which y = R^-1 R^-T lambda does not
+// see).  r then holds no chunk (first = -1): the solves reload the rows.
 template <int DIM, int ORDER, int RPL, int SKIP = 0>
 __device__ __forceinline__ void qr_factor(const StencilArgs &a, int t, Rows<DIM, RPL> &r,
                                           double (&M)[RPL][num_mono(DIM, ORDER) - SKIP], double &rdiag,
@@ -152,6 +167,34 @@ __device__ __forceinline__ void qr_factor(const StencilArgs &a, int t, Rows<DIM,
     for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q + SKIP];
   }
   wave_householder<Q, RPL>(M, rdiag, lane);
+  if (r.N > 64 * RPL) {
+    static_assert(Q < 64, "R and the next rows share the wavefront");
+    constexpr int CAP = 64 * RPL - Q;  // rows added per step
+    const double ie = 1.0 / uniform_d(a.eps[t]);
+    double xt[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xt[d] = uniform_d(a.targets[(int64_t)t * DIM + d]);
+    for (int c = 64 * RPL; c < r.N; c += CAP) {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        if (i == 0 && lane < Q) {  // row `lane` of R: clear the reflector left below its diagonal
+#pragma unroll
+          for (int l = 0; l < Q; ++l) M[0][l] = l < lane ? 0.0 : M[0][l];
+          continue;
+        }
+        const int q = i == 0 ? lane - Q : (64 - Q) + 64 * (i - 1) + lane;
+        double s[DIM], w;
+        row_s_w<DIM>(a, r.base, c + q, r.N, xt, ie, s, w);
+        double p[QF];
+        scaled_basis<DIM, ORDER, double>(s, p);
+        const double sw = sqrt(w);
+#pragma unroll
+        for (int l = 0; l < Q; ++l) M[i][l] = sw * p[l + SKIP];
+      }
+      wave_householder<Q, RPL>(M, rdiag, lane);
+    }
+    r.first = -1;
+  }
 }
 
 // SKIP = 1 drops the constant monomial: the staggered scheme (Section 2.4).
@@ -167,7 +210,7 @@ __device__ __forceinline__ void qr_factor(const StencilArgs &a, int t, Rows<DIM,
 // rdiag = R_kk): rank test, R to LDS, the functionals' solves and the rows.
 template <int DIM, int ORDER, int RPL, int SKIP = 0>
 __device__ __forceinline__ void qr_scalar_solve(const StencilArgs &a, const RowKinds &rk, int t,
-                                                const Rows<DIM, RPL> &r, const double (&Rrow)[num_mono(DIM, ORDER) - SKIP],
+                                                Rows<DIM, RPL> &r, const double (&Rrow)[num_mono(DIM, ORDER) - SKIP],
                                                 double rdiag, double *lds) {
   constexpr Mono<DIM, ORDER> MO{};
   constexpr int QF = MO.N;       // monomials of degree <= ORDER
@@ -179,11 +222,8 @@ __device__ __forceinline__ void qr_scalar_solve(const StencilArgs &a, const RowK
   const int F = a.F;
   const int rank_def = readfirstlane_i(!(amin > kRankTol * amax) ? 1 : 0);
   if (rank_def) {
-    for (int i = 0; i < RPL; ++i) {
-      const int j = lane + 64 * i;
-      if (j < r.N)
-        for (int f = 0; f < F; ++f) a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = NAN;
-    }
+    for (int j = lane; j < r.N; j += 64)
+      for (int f = 0; f < F; ++f) a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = NAN;
     if (a.hweights && lane < F) a.hweights[(int64_t)t * F + lane] = NAN;
     if (lane == 0) a.status[t] = GMLS_TARGET_RANK_DEFICIENT;
     __syncthreads();
@@ -234,22 +274,25 @@ __device__ __forceinline__ void qr_scalar_solve(const StencilArgs &a, const RowK
   }
   __syncthreads();
   double rsum[4] = {0.0, 0.0, 0.0, 0.0};  // staggered: F <= 4 (gradient, Laplacian)
+  for (int c = 0; c < r.N; c += 64 * RPL) {  // one pass unless the row is longer than 64 RPL
+    if (r.first != c) load_rows<DIM, RPL>(a, t, r, lane, c);
 #pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int j = lane + 64 * i;
-    if (j < r.N) {
-      double p[QF];
-      scaled_basis<DIM, ORDER, double>(r.s[i], p);
-      for (int f = 0; f < F; ++f) {
-        double acc = 0.0;
+    for (int i = 0; i < RPL; ++i) {
+      const int j = c + lane + 64 * i;
+      if (j < r.N) {
+        double p[QF];
+        scaled_basis<DIM, ORDER, double>(r.s[i], p);
+        for (int f = 0; f < F; ++f) {
+          double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) acc += p[q + SKIP] * Y[f * Q + q];
-        const double wv = r.w[i] * acc;
-        a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = wv;
-        if constexpr (SKIP != 0) {
+          for (int q = 0; q < Q; ++q) acc += p[q + SKIP] * Y[f * Q + q];
+          const double wv = r.w[i] * acc;
+          a.weights[(int64_t)F * r.base + (int64_t)f * r.N + j] = wv;
+          if constexpr (SKIP != 0) {
 #pragma unroll
-          for (int g = 0; g < 4; ++g)
-            if (g == f) rsum[g] += wv;
+            for (int g = 0; g < 4; ++g)
+              if (g == f) rsum[g] += wv;
+          }
         }
       }
     }

@@ -58,7 +58,7 @@ constexpr int qr_divfree_lds_doubles() {
 // passes the same rank test), and Rrow is not read.
 template <int DIM, int ORDER, int RPL, bool R_IN_LDS = false>
 __device__ __forceinline__ void qr_divfree_solve(const StencilArgs &a, const RowKinds &rk, int t,
-                                                 const Rows<DIM, RPL> &r, const double (&Rrow)[num_mono(DIM, ORDER)],
+                                                 Rows<DIM, RPL> &r, const double (&Rrow)[num_mono(DIM, ORDER)],
                                                  double rdiag, double *lds) {
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int QM = num_mono(DIM, ORDER - 1);
@@ -194,30 +194,29 @@ __device__ __forceinline__ void qr_divfree_solve(const StencilArgs &a, const Row
     }
   }
   if (readfirstlane_i(deficient ? 1 : 0)) {
-    for (int i = 0; i < RPL; ++i) {
-      const int j = lane + 64 * i;
-      if (j < r.N)
-        for (int f = 0; f < F; ++f)
-          for (int c = 0; c < DIM; ++c)
-            a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = NAN;
-    }
+    for (int j = lane; j < r.N; j += 64)
+      for (int f = 0; f < F; ++f)
+        for (int c = 0; c < DIM; ++c) a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = NAN;
     if (lane == 0) a.status[t] = GMLS_TARGET_RANK_DEFICIENT;
     __syncthreads();
     return;
   }
+  for (int c0 = 0; c0 < r.N; c0 += 64 * RPL) {  // one pass unless the row is longer than 64 RPL
+    if (r.first != c0) load_rows<DIM, RPL>(a, t, r, lane, c0);
 #pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int j = lane + 64 * i;
-    if (j < r.N) {
-      double p[Q];
-      scaled_basis<DIM, ORDER, double>(r.s[i], p);
-      for (int f = 0; f < F; ++f)
-        for (int c = 0; c < DIM; ++c) {
-          double acc = 0.0;
+    for (int i = 0; i < RPL; ++i) {
+      const int j = c0 + lane + 64 * i;
+      if (j < r.N) {
+        double p[Q];
+        scaled_basis<DIM, ORDER, double>(r.s[i], p);
+        for (int f = 0; f < F; ++f)
+          for (int c = 0; c < DIM; ++c) {
+            double acc = 0.0;
 #pragma unroll
-          for (int q = 0; q < Q; ++q) acc += p[q] * U[f * KB + q * DIM + c];
-          a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = r.w[i] * acc;
-        }
+            for (int q = 0; q < Q; ++q) acc += p[q] * U[f * KB + q * DIM + c];
+            a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = r.w[i] * acc;
+          }
+      }
     }
   }
   if (lane == 0 && a.ok_status >= 0) a.status[t] = (uint8_t)a.ok_status;

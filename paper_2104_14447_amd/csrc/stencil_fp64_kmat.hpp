@@ -35,18 +35,9 @@ __device__ void qr_divfree_kmat_target(const StencilArgs &a, const RowKinds &rk,
   constexpr int KR = DIM * Q;  // rows of K
   const int lane = lane_id();
   Rows<DIM, RPL> r;
-  load_rows<DIM, RPL>(a, t, r, lane);
   double M[RPL][Q];
-#pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    double p[Q];
-    scaled_basis<DIM, ORDER, double>(r.s[i], p);
-    const double sw = sqrt(r.w[i]);
-#pragma unroll
-    for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q];
-  }
   double rdiag;
-  wave_householder<Q, RPL>(M, rdiag, lane);
+  qr_factor<DIM, ORDER, RPL>(a, t, r, M, rdiag, lane);  // any row count (chunked when long)
   const int F = a.F;
   // scalar R in LDS (row-major), then K = (R (x) I) T column-major [QD][KR]
   double *Rs = lds;              // Q*Q
@@ -141,13 +132,9 @@ __device__ void qr_divfree_kmat_target(const StencilArgs &a, const RowKinds &rk,
   dmax = uniform_d(wave_max(dmax));
   dmin = uniform_d(wave_min(dmin));
   if (readfirstlane_i(!(dmin > kRankTol * dmax) ? 1 : 0)) {
-    for (int i = 0; i < RPL; ++i) {
-      const int j = lane + 64 * i;
-      if (j < r.N)
-        for (int f = 0; f < F; ++f)
-          for (int c = 0; c < DIM; ++c)
-            a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = NAN;
-    }
+    for (int j = lane; j < r.N; j += 64)
+      for (int f = 0; f < F; ++f)
+        for (int c = 0; c < DIM; ++c) a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = NAN;
     if (lane == 0) a.status[t] = GMLS_TARGET_RANK_DEFICIENT;
     __syncthreads();
     return;
@@ -214,19 +201,22 @@ __device__ void qr_divfree_kmat_target(const StencilArgs &a, const RowKinds &rk,
         for (int f = 0; f < F; ++f) U[f * KR + DF.ib[i] * DIM + DF.cb[i]] += DF.vb[i] * Y[f * QD + i];
     __syncthreads();
   }
+  for (int c0 = 0; c0 < r.N; c0 += 64 * RPL) {  // one pass unless the row is longer than 64 RPL
+    if (r.first != c0) load_rows<DIM, RPL>(a, t, r, lane, c0);
 #pragma unroll
-  for (int i = 0; i < RPL; ++i) {
-    const int j = lane + 64 * i;
-    if (j < r.N) {
-      double p[Q];
-      scaled_basis<DIM, ORDER, double>(r.s[i], p);
-      for (int f = 0; f < F; ++f)
-        for (int c = 0; c < DIM; ++c) {
-          double acc = 0.0;
+    for (int i = 0; i < RPL; ++i) {
+      const int j = c0 + lane + 64 * i;
+      if (j < r.N) {
+        double p[Q];
+        scaled_basis<DIM, ORDER, double>(r.s[i], p);
+        for (int f = 0; f < F; ++f)
+          for (int c = 0; c < DIM; ++c) {
+            double acc = 0.0;
 #pragma unroll
-          for (int q = 0; q < Q; ++q) acc += p[q] * U[f * KR + q * DIM + c];
-          a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = r.w[i] * acc;
-        }
+            for (int q = 0; q < Q; ++q) acc += p[q] * U[f * KR + q * DIM + c];
+            a.weights[(int64_t)F * DIM * r.base + ((int64_t)f * r.N + j) * DIM + c] = r.w[i] * acc;
+          }
+      }
     }
   }
   if (lane == 0 && a.ok_status >= 0) a.status[t] = (uint8_t)a.ok_status;
@@ -234,7 +224,7 @@ __device__ void qr_divfree_kmat_target(const StencilArgs &a, const RowKinds &rk,
 }
 
 
-// Persistent kernel over the queue aux_list[0 .. *count) (rows <= 64 RPL).
+// Persistent kernel over the queue aux_list[0 .. *count) (any row count).
 template <int DIM, int ORDER, int RPL>
 __global__ __launch_bounds__(64) void k_qr_kmat(StencilArgs a, const int *list, const int *count, int *cursor) {
   __shared__ double lds[qr_kmat_lds_doubles<DIM, ORDER>()];

@@ -126,9 +126,25 @@ __device__ __forceinline__ double row_sw(const double *xj, const double *xt, dou
   return (live && rad < 1.0) ? int_pow(1.0 - rad, p) : 0.0;
 }
 
+// Trip count of the chunk loop over a row: one pass of G * RPL rows, or for
+// the long bin (LOOP) enough passes for the longest row of the wavefront's
+// targets (the same for every lane: the loop holds no divergent barrier).
+template <bool LOOP, int CH>
+__device__ __forceinline__ int chunk_end(int N) {
+  if constexpr (!LOOP) {
+    return 1;
+  } else {
+    int m = N;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o));
+    return readfirstlane_i(m);
+  }
+}
+
 // `t` is a target of the bin even for an invalid group (whose sums are not
-// stored), so that every gathered row exists.
-template <int DIM, int ORDER, int G, int RPL>
+// stored), so that every gathered row exists.  LOOP: rows in chunks of
+// G * RPL (the long bin), the partial sums carried over the chunks.
+template <int DIM, int ORDER, int G, int RPL, bool LOOP = false>
 __device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, bool valid, int slot, int lg,
                                     double *mom) {
   constexpr int NM = num_mono(DIM, 2 * ORDER);
@@ -140,28 +156,32 @@ __device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, boo
   double xt[DIM];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) xt[d] = rc.x[d];
-  double xs[RPL][DIM];
-  gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
   double mu[NM];
 #pragma unroll
   for (int m = 0; m < NM; ++m) mu[m] = 0.0;
   constexpr MomentSplit<DIM, ORDER> MS{};
+  const int cend = chunk_end<LOOP, G * RPL>(N);
+  for (int c0 = 0; c0 < cend; c0 += G * RPL) {
+    const int nrem = N - c0;  // rows of this chunk and after (may be <= 0 in a long loop)
+    double xs[RPL][DIM];
+    gather_rows<DIM, RPL, G>(a, base + (nrem > 0 ? c0 : 0), nrem > 0 ? nrem : N, lg, xs);
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    double s[DIM];
-    const double w = row_sw<DIM>(xs[r], xt, ie, a.p, lg + G * r < N, s);
-    double lastp[2 * ORDER + 1];
-    lastp[0] = 1.0;
+    for (int r = 0; r < RPL; ++r) {
+      double s[DIM];
+      const double w = row_sw<DIM>(xs[r], xt, ie, a.p, lg + G * r < nrem, s);
+      double lastp[2 * ORDER + 1];
+      lastp[0] = 1.0;
 #pragma unroll
-    for (int c = 1; c <= 2 * ORDER; ++c) lastp[c] = lastp[c - 1] * s[DIM - 1];
-    double wp[MS.NP];
-    wp[0] = w;
+      for (int c = 1; c <= 2 * ORDER; ++c) lastp[c] = lastp[c - 1] * s[DIM - 1];
+      double wp[MS.NP];
+      wp[0] = w;
 #pragma unroll
-    for (int pi = 1; pi < MS.NP; ++pi) wp[pi] = wp[MS.parent[pi]] * s[MS.pdim[pi]];
+      for (int pi = 1; pi < MS.NP; ++pi) wp[pi] = wp[MS.parent[pi]] * s[MS.pdim[pi]];
 #pragma unroll
-    for (int pi = 0; pi < MS.NP; ++pi)
+      for (int pi = 0; pi < MS.NP; ++pi)
 #pragma unroll
-      for (int c = 0; c <= 2 * ORDER - MS.deg[pi]; ++c) mu[MS.midx[pi][c]] += wp[pi] * lastp[c];
+        for (int c = 0; c <= 2 * ORDER - MS.deg[pi]; ++c) mu[MS.midx[pi][c]] += wp[pi] * lastp[c];
+    }
   }
   // the sums are complete here: without this the compiler sinks each
   // moment's FMA chain into the reduction round that stores it and keeps
@@ -194,7 +214,7 @@ __device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, boo
 // Targets list[first .. last) of one row-count bin; moment g of the target
 // in list slot i goes to mom[(i - c0) * NM + g] (target-major, so that a
 // group writes its target's moments contiguously).
-template <int DIM, int ORDER, int G, int RPL>
+template <int DIM, int ORDER, int G, int RPL, bool LOOP = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_pipe_moments(
     StencilArgs a, const PipeRec *rec, const BinMeta *meta, int bin, int win_lo, int win_hi, double *mom) {
   const SlotRange R = slot_range(meta, bin, win_lo, win_hi);
@@ -206,7 +226,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
     const int i = i0 + grp;
     const bool valid = i < last;
     const PipeRec rc = rec[(valid ? i : first) - c0];
-    pipe_moments_target<DIM, ORDER, G, RPL>(a, rc, valid, i - c0, lg, mom);
+    pipe_moments_target<DIM, ORDER, G, RPL, LOOP>(a, rc, valid, i - c0, lg, mom);
   }
 }
 
@@ -458,7 +478,7 @@ __global__ __launch_bounds__(64) void k_pipe_solve(StencilArgs a, PipeRec *rec, 
 // registers: F*Q doubles per lane).
 // SKIP = 1 (staggered): columns are monomials 1..Q-1, and the group also
 // writes each row's target weight -sum_j alpha_j.
-template <int DIM, int ORDER, int G, int RPL, int F, int SKIP = 0>
+template <int DIM, int ORDER, int G, int RPL, int F, int SKIP = 0, bool LOOP = false>
 __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRec *rec, const BinMeta *meta, int bin,
                                                      int win_lo, int win_hi, const double *yin) {
   const SlotRange R = slot_range(meta, bin, win_lo, win_hi);
@@ -485,8 +505,6 @@ __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRe
     double xt[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xt[d] = rc.x[d];
-    double xs[RPL][DIM];
-    gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
     // p(s) . y = sum_a (y_a / a!) s^a: the factorials go into the
     // coefficients once per target, the rows take a Horner evaluation
     constexpr InvFact64<DIM, ORDER> IFW{};
@@ -501,16 +519,22 @@ __global__ __launch_bounds__(64) void k_pipe_weights(StencilArgs a, const PipeRe
     double rsum[F];
 #pragma unroll
     for (int f = 0; f < F; ++f) rsum[f] = 0.0;
+    const int cend = chunk_end<LOOP, G * RPL>(N);
+    for (int q0 = 0; q0 < cend; q0 += G * RPL) {  // one pass unless LOOP (the long bin)
+      const int nrem = N - q0;
+      double xs[RPL][DIM];
+      gather_rows<DIM, RPL, G>(a, base + (nrem > 0 ? q0 : 0), nrem > 0 ? nrem : N, lg, xs);
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      double s[DIM];
-      const double w = row_sw<DIM>(xs[r], xt, ie, a.p, true, s);
-      const int j = lg + G * r;
+      for (int r = 0; r < RPL; ++r) {
+        double s[DIM];
+        const double w = row_sw<DIM>(xs[r], xt, ie, a.p, true, s);
+        const int j = lg + G * r;
 #pragma unroll
-      for (int f = 0; f < F; ++f) {
-        const double acc = horner<DIM, ORDER>(cf[f], s);
-        if (good && j < N) wout[(int64_t)f * N + j] = w * acc;
-        if constexpr (SKIP != 0) rsum[f] += j < N ? w * acc : 0.0;
+        for (int f = 0; f < F; ++f) {
+          const double acc = horner<DIM, ORDER>(cf[f], s);
+          if (good && j < nrem) wout[(int64_t)f * N + q0 + j] = w * acc;
+          if constexpr (SKIP != 0) rsum[f] += j < nrem ? w * acc : 0.0;
+        }
       }
     }
     if constexpr (SKIP != 0) {
@@ -772,7 +796,7 @@ __global__ __launch_bounds__(64) void k_pipe_solve_div(StencilArgs a, PipeRec *r
 // components form one contiguous run of G*DIM doubles: the values are staged
 // in LDS and stored as DIM fully coalesced runs instead of DIM stores with a
 // DIM-double stride (which split every cache line between instructions).
-template <int DIM, int ORDER, int G, int RPL>
+template <int DIM, int ORDER, int G, int RPL, bool LOOP = false>
 __global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const PipeRec *rec, const BinMeta *meta,
                                                          int bin, int win_lo, int win_hi, const double *gin) {
   const SlotRange R = slot_range(meta, bin, win_lo, win_hi);
@@ -810,12 +834,15 @@ __global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const Pi
     double xt[DIM];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) xt[d] = rc.x[d];
+    double *wout = a.weights + (int64_t)FC * base;
+    // one pass unless LOOP (the long bin): then every chunk of G * RPL rows
+    // is gathered again for each functional row
+    const int cend = chunk_end<LOOP, G * RPL>(N);
     double xs[RPL][DIM];
     gather_rows<DIM, RPL, G>(a, base, N, lg, xs);
     double s[RPL][DIM], w[RPL];
 #pragma unroll
     for (int r = 0; r < RPL; ++r) w[r] = row_sw<DIM>(xs[r], xt, rc.ie, a.p, true, s[r]);
-    double *wout = a.weights + (int64_t)FC * base;
     for (int f = 0; f < F; ++f) {
       double *cb = cfs[f & 1];
 #pragma unroll
@@ -830,19 +857,27 @@ __global__ __launch_bounds__(64) void k_pipe_weights_div(StencilArgs a, const Pi
       for (int c = 0; c < DIM; ++c)
 #pragma unroll
         for (int q = 0; q < QS; ++q) cf[c][q] = cb[grp * CW + c * QS + q] * IFW.v[q];
+      for (int q0 = 0; q0 < cend; q0 += G * RPL) {
+        const int nrem = N - q0;
+        if (LOOP && (q0 > 0 || f > 0)) {  // the rows of this chunk (chunk 0 of row 0 is loaded above)
+          gather_rows<DIM, RPL, G>(a, base + (nrem > 0 ? q0 : 0), nrem > 0 ? nrem : N, lg, xs);
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) gst[lg * DIM + c] = w[r] * horner<DIM, ORDER>(cf[c], s[r]);
-        __syncthreads();
-        // the group's rows G r .. G r + G - 1: doubles (f N + G r) DIM + m, m < G DIM
-        double *run = wout + ((int64_t)f * N + G * r) * DIM;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-          const int m = k * G + lg;
-          if (good && G * r + m / DIM < N) run[m] = gst[m];
+          for (int r = 0; r < RPL; ++r) w[r] = row_sw<DIM>(xs[r], xt, rc.ie, a.p, true, s[r]);
         }
-        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+#pragma unroll
+          for (int c = 0; c < DIM; ++c) gst[lg * DIM + c] = w[r] * horner<DIM, ORDER>(cf[c], s[r]);
+          __syncthreads();
+          // the group's rows q0 + G r .. q0 + G r + G - 1: doubles (f N + q0 + G r) DIM + m, m < G DIM
+          double *run = wout + ((int64_t)f * N + q0 + G * r) * DIM;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            const int m = k * G + lg;
+            if (good && G * r + m / DIM < nrem) run[m] = gst[m];
+          }
+          __syncthreads();
+        }
       }
     }
   }
@@ -862,7 +897,7 @@ constexpr bool has_pipe_div() {
   return ORDER >= 1 && num_mono(DIM, ORDER) <= 10;
 }
 
-template <int DIM, int ORDER, int G, int RPL, int SKIP, int BASIS = 0>
+template <int DIM, int ORDER, int G, int RPL, int SKIP, int BASIS = 0, bool LOOP = false>
 static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *rec, const BinMeta *meta, int bin,
                             int win_lo, int win_hi, int n_max, double *buf, int cus, hipStream_t s) {
   constexpr int TPW = 64 / G;
@@ -870,21 +905,21 @@ static void pipe_bin_launch(bool weights, const StencilArgs &a, const PipeRec *r
   if (nb > cus * 32) nb = cus * 32;
   nb = xcd_grid(nb);
   if (!weights) {
-    k_pipe_moments<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
+    k_pipe_moments<DIM, ORDER, G, RPL, LOOP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
     return;
   }
   if constexpr (BASIS == 1) {
-    k_pipe_weights_div<DIM, ORDER, G, RPL><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
+    k_pipe_weights_div<DIM, ORDER, G, RPL, LOOP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
     return;
   }
   switch (a.F) {  // scalar basis: value + up to DIM gradient rows + Laplacian
-    case 1: k_pipe_weights<DIM, ORDER, G, RPL, 1, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
-    case 2: k_pipe_weights<DIM, ORDER, G, RPL, 2, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
-    case 3: k_pipe_weights<DIM, ORDER, G, RPL, 3, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
-    case 4: k_pipe_weights<DIM, ORDER, G, RPL, 4, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 1: k_pipe_weights<DIM, ORDER, G, RPL, 1, SKIP, LOOP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 2: k_pipe_weights<DIM, ORDER, G, RPL, 2, SKIP, LOOP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 3: k_pipe_weights<DIM, ORDER, G, RPL, 3, SKIP, LOOP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
+    case 4: k_pipe_weights<DIM, ORDER, G, RPL, 4, SKIP, LOOP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf); break;
     default:
       if constexpr (DIM == 3 && SKIP == 0)
-        k_pipe_weights<DIM, ORDER, G, RPL, 5, SKIP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
+        k_pipe_weights<DIM, ORDER, G, RPL, 5, SKIP, LOOP><<<nb, 64, 0, s>>>(a, rec, meta, bin, win_lo, win_hi, buf);
       break;
   }
 }
@@ -894,15 +929,16 @@ template <int DIM, int ORDER, int SKIP, int BASIS, int BIN>
 static void pipe_bin_shape(int cand, bool weights, const StencilArgs &a, const PipeRec *rec, const BinMeta *meta,
                            int win_lo, int win_hi, int n_max, double *buf, int cus, hipStream_t s) {
   constexpr PipeShape S0 = kPipeShapes[BIN][0], S1 = kPipeShapes[BIN][1], S2 = kPipeShapes[BIN][2];
+  constexpr bool L = BIN == kLongBin;
   if (cand == 1)
-    pipe_bin_launch<DIM, ORDER, S1.g, S1.rpl, SKIP, BASIS>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max, buf,
-                                                           cus, s);
+    pipe_bin_launch<DIM, ORDER, S1.g, S1.rpl, SKIP, BASIS, L>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max,
+                                                              buf, cus, s);
   else if (cand == 2)
-    pipe_bin_launch<DIM, ORDER, S2.g, S2.rpl, SKIP, BASIS>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max, buf,
-                                                           cus, s);
+    pipe_bin_launch<DIM, ORDER, S2.g, S2.rpl, SKIP, BASIS, L>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max,
+                                                              buf, cus, s);
   else
-    pipe_bin_launch<DIM, ORDER, S0.g, S0.rpl, SKIP, BASIS>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max, buf,
-                                                           cus, s);
+    pipe_bin_launch<DIM, ORDER, S0.g, S0.rpl, SKIP, BASIS, L>(weights, a, rec, meta, BIN, win_lo, win_hi, n_max,
+                                                              buf, cus, s);
 }
 
 // The pipeline over list slots [count[0], n) (bins 1..4, contiguous, in bin
@@ -968,8 +1004,11 @@ hipError_t launch_pipe(const StencilArgs &a, const int *list, const BinMeta *hm,
           pipe_bin_shape<DIM, ORDER, SKIP, BASIS, 2>(cand, wts, a, rec, meta, win_lo, win_hi, nbin, buf, cus, s);
         else if (b == 3)
           pipe_bin_shape<DIM, ORDER, SKIP, BASIS, 3>(cand, wts, a, rec, meta, win_lo, win_hi, nbin, buf, cus, s);
-        else
+        else if (b == 4)
           pipe_bin_shape<DIM, ORDER, SKIP, BASIS, 4>(cand, wts, a, rec, meta, win_lo, win_hi, nbin, buf, cus, s);
+        else
+          pipe_bin_shape<DIM, ORDER, SKIP, BASIS, kLongBin>(cand, wts, a, rec, meta, win_lo, win_hi, nbin, buf, cus,
+                                                            s);
         if (timer) {
           hipError_t e = hipEventRecord(timer->ev[pass][b][1], s);
           if (e != hipSuccess) return e;

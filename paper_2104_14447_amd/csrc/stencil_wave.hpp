@@ -534,6 +534,17 @@ hipError_t launch_wave(const WaveSet &ss, const WaveSet &sv, const int *list, co
       cnt = hm->count[b];
       if (cnt == 0) continue;
     }
+    if (b == kLongBin) {  // rows over 256: the FP64 QR kernels take them in chunks
+      hipError_t e = hipSuccess;
+      if constexpr (BASIS == 0 || BASIS == 3)
+        e = launch_defer_bin(ss.a.status, list, meta, b, ss.fb_list, ss.fb_count, stats, s);
+      if constexpr (BASIS == 1 || BASIS == 3)
+        if (e == hipSuccess)
+          e = launch_defer_bin(sv.a.status, list, meta, b, sv.fb_list, sv.fb_count, BASIS == 3 ? stats + 1 : stats,
+                               s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
     int nb = cnt < cus * 16 ? cnt : cus * 16;
     nb = xcd_grid(nb);
     switch (b) {
