@@ -151,6 +151,9 @@ def parse():
     ap.add_argument("--scheme", type=int, default=0,
                     help="mixed scheme: 0 auto, 1 fused/rows residual, 2 fused/moment Gram, 3 pipeline, 4 wavefront per target")
     ap.add_argument("--chunk", type=int, default=0, help="pipeline chunk (targets; 0 = whole batch)")
+    ap.add_argument("--layout", choices=["sorted", "index"], default="index",
+                    help="stencil sources: the search's cell-ordered records (gmls_neighbors_sorted) or the "
+                         "points in their own order")
     ap.add_argument("--no-autotune", action="store_true",
                     help="mixed pipeline: keep the default row shapes instead of autotuning them first")
     ap.add_argument("--tune-cache", default="",
@@ -343,17 +346,17 @@ def main():
     if prec_name == "mixed" and "fp64" in wl["modes"] and not args.no_fp64:
         legs.append("fp64")
 
-    def stencils(c, prec, bs, eps_, rp_, col_, weights=None, status=None, aux=None, report=False):
+    def stencils(c, prec, bs, src, eps_, rp_, col_, weights=None, status=None, aux=None, report=False):
         """One basis of the configuration through its entry point; `aux`
         receives the h-weights (constrained) or target weights (staggered)."""
         if bs["name"] == "staggered":
-            return G.gmls_stencils_staggered(c, x, xt, bs["order"], bs["mask"], p, eps_, rp_, col_, prec=prec,
+            return G.gmls_stencils_staggered(c, src, xt, bs["order"], bs["mask"], p, eps_, rp_, col_, prec=prec,
                                              weights=weights, t_weights=aux, status=status, report=report)
         if bs["name"] == "neumann":
-            return G.gmls_stencils_constrained(c, x, xt, bs["order"], bs["mask"], p, eps_, rp_, col_, nrm,
+            return G.gmls_stencils_constrained(c, src, xt, bs["order"], bs["mask"], p, eps_, rp_, col_, nrm,
                                                prec=prec, weights=weights, h_weights=aux, status=status,
                                                report=report)
-        w_, st_, r_ = G.gmls_stencils(c, x, xt, bs["order"], bs["b"], bs["mask"], p, eps_, rp_, col_, prec=prec,
+        w_, st_, r_ = G.gmls_stencils(c, src, xt, bs["order"], bs["b"], bs["mask"], p, eps_, rp_, col_, prec=prec,
                                       weights=weights, status=status, report=report)
         return w_, None, st_, r_
 
@@ -363,18 +366,36 @@ def main():
     shared = len(bases) == 2 and sorted(b["name"] for b in bases) == ["divfree", "scalar"] and \
         bases[0]["order"] == bases[1]["order"]
 
-    def all_stencils(c, prec, eps_, rp_, col_, bufs, report=False):
+    def all_stencils(c, prec, src, eps_, rp_, col_, bufs, report=False):
         if shared:
             outs = [(bufs[i]["w"], bufs[i]["st"]) for i in range(len(bases))]
-            return [G.gmls_stencils_multi(c, x, xt, bases[0]["order"], p, eps_, rp_, col_,
+            return [G.gmls_stencils_multi(c, src, xt, bases[0]["order"], p, eps_, rp_, col_,
                                           [(bs["b"], bs["mask"]) for bs in bases], prec=prec, outputs=outs,
                                           report=report)[1]]
-        return [stencils(c, prec, bs, eps_, rp_, col_, weights=bufs[i]["w"], status=bufs[i]["st"],
+        return [stencils(c, prec, bs, src, eps_, rp_, col_, weights=bufs[i]["w"], status=bufs[i]["st"],
                          aux=bufs[i]["aux"], report=report)[3] for i, bs in enumerate(bases)]
 
-    rp0, col0, eps0 = G.gmls_neighbors(ctx, x, xt, **spec)
+    # source layout of the stencil calls: the search's cell-ordered records
+    # and the rows as positions in them (gmls_neighbors_sorted, source stride
+    # 4), or the points in their own order
+    sorted_layout = args.layout == "sorted"
+
+    def search(c, col=None, pcol=None, rec=None):
+        """(row_ptr, col, eps, stencil sources, stencil rows)"""
+        if sorted_layout:
+            rp_, col_, eps_, rec_, pcol_ = G.gmls_neighbors_sorted(c, x, xt, col=col, col_sorted=pcol, records=rec,
+                                                                   **spec)
+            return rp_, col_, eps_, rec_, pcol_
+        rp_, col_, eps_ = G.gmls_neighbors(c, x, xt, col=col, **spec)
+        return rp_, col_, eps_, x, col_
+
+    if sorted_layout:
+        ctx.set_option(G.OPT_SOURCE_STRIDE, 4)
+    rp0, col0, eps0, src0, scol0 = search(ctx)
     nnz = col0.numel()
     col_buf = torch.empty(int(nnz * 1.05) + 1024, dtype=torch.int32, device=dev)
+    pcol_buf = torch.empty_like(col_buf) if sorted_layout else None
+    rec_buf = torch.empty((n, 4), dtype=torch.float64, device=dev) if sorted_layout else None
 
     def new_bufs():
         return [dict(w=torch.empty(bs["F"] * bs["C"] * nnz, dtype=torch.float64, device=dev),
@@ -399,7 +420,7 @@ def main():
                 order_t, b_t = (bs["order"] + 1, G.BASIS_SCALAR) if bs["name"] == "staggered" \
                     else (bs["order"], bs["b"])
                 try:
-                    res = G.gmls_autotune(ctx, x, xt, order_t, b_t, bs["mask"], p, eps0, rp0, col0, reps=3)
+                    res = G.gmls_autotune(ctx, src0, xt, order_t, b_t, bs["mask"], p, eps0, rp0, scol0, reps=3)
                 except G.GmlsError as e:
                     if e.status != G.GMLS_ERR_UNSUPPORTED:  # not the pipeline: nothing to tune
                         raise
@@ -428,9 +449,9 @@ def main():
 
         def step(report=False):
             ev0.record()
-            rp_, col_, eps_ = G.gmls_neighbors(ctx, x, xt, col=col_buf, **spec)
+            rp_, col_, eps_, src_, scol_ = search(ctx, col_buf, pcol_buf, rec_buf)
             ev1.record()
-            reps_ = all_stencils(ctx, prec, eps_, rp_, col_, bufs, report=report)
+            reps_ = all_stencils(ctx, prec, src_, eps_, rp_, scol_, bufs, report=report)
             return rp_, col_, eps_, reps_
 
         for i in range(args.warmup):
@@ -457,20 +478,24 @@ def main():
             gs = torch.cuda.Stream()
             gctx = G.Context(0, stream=gs)
             gctx.set_option(G.OPT_MIXED_SCHEME, args.scheme)
+            if sorted_layout:
+                gctx.set_option(G.OPT_SOURCE_STRIDE, 4)
             if tune_path and leg == "mixed":
                 G.gmls_autotune_load(gctx, tune_path)  # the same row shapes as the eager steps
             gbufs = new_bufs()
             gcol = torch.empty(nnz + 1024, dtype=torch.int32, device=dev)
+            gpcol = torch.empty_like(gcol) if sorted_layout else None
+            grec = torch.empty((n, 4), dtype=torch.float64, device=dev) if sorted_layout else None
             with torch.cuda.stream(gs):
                 # one normal call of each kind sizes the context's workspace
-                rpw, colw, epsw = G.gmls_neighbors(gctx, x, xt, **spec)
-                all_stencils(gctx, prec, epsw, rpw, colw, gbufs)
+                rpw, colw, epsw, srcw, scolw = search(gctx)
+                all_stencils(gctx, prec, srcw, epsw, rpw, scolw, gbufs)
                 gctx.set_option(G.OPT_CAPTURE_SAFE, 1)
                 gout = {}
 
                 def gstep():
-                    rp_, col_, eps_ = G.gmls_neighbors(gctx, x, xt, col=gcol, **spec)
-                    all_stencils(gctx, prec, eps_, rp_, col_[:nnz], gbufs)
+                    rp_, col_, eps_, src_, scol_ = search(gctx, gcol, gpcol, grec)
+                    all_stencils(gctx, prec, src_, eps_, rp_, scol_[:nnz], gbufs)
                     gout["rp"], gout["eps"] = rp_, eps_
 
                 gstep()  # capture-safe eager run (no allocation happens in the capture)
@@ -747,6 +772,8 @@ def main():
         "config": {"workload": f"{name}: {DESCRIBE[name]}",
                    "n_points": n, "n_targets": n_t, "nnz": int(nnz), "precision": legs[0],
                    "search": wl["search"][0] + (f" k={k}" if knn else f" r={r0:.6f} k_min={k_min}"),
+                   "source_layout": ("cell-ordered records (gmls_neighbors_sorted, source stride 4)"
+                                     if sorted_layout else "points in their own order"),
                    "mixed_scheme": ["auto", "fused, rows residual", "fused, moment Gram",
                                     "pipeline", "wavefront per target"][args.scheme],
                    "autotune": tune_summary,

@@ -167,12 +167,17 @@ enum {
                                   0 = cell order: by (cell of the source in the search's uniform
                                       grid, source index); deterministic for given inputs, no sort;
                                   1 = ascending source index (a sort per row).                   */
-  GMLS_OPT_PIPE_SHAPE = 9      /* row shape of the pipeline's moment and weight kernels (-1):
+  GMLS_OPT_PIPE_SHAPE = 9,     /* row shape of the pipeline's moment and weight kernels (-1):
                                   -1 = the autotuned choice (gmls_autotune) for the call's
                                        (dim, order, basis), kernel and row-count bin; candidate 0
                                        where nothing was tuned;
                                   0, 1, 2 = this candidate in every bin (gmls_tune_result lists
                                        the lanes per target and rows per lane of each).          */
+  GMLS_OPT_SOURCE_STRIDE = 10  /* layout of `coords` in the stencil calls (gmls_stencils, _multi,
+                                  _constrained, _staggered) (0): source j is at coords[j*stride ..
+                                  j*stride + dim); 0 means stride = dim; otherwise an integer in
+                                  [dim, 64].  Use 4 with the records of gmls_neighbors_sorted.
+                                  The search calls always read [n][dim].                         */
 };
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
@@ -210,6 +215,31 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value);
 gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
                            int64_t n_tgt, int dim, const gmls_search *spec, int64_t *row_ptr, int32_t *col,
                            int64_t col_capacity, double *eps, int64_t *nnz_host);
+
+/* gmls_neighbors, also handing out the search's cell-ordered copy of the
+ * sources and every row as positions in that copy (Section 2.1: a target's
+ * neighbours lie in the few cells around it, so in this copy a row is a few
+ * runs of nearby records).  A stencil depends only on the coordinates of its
+ * row entries, in row order, so gmls_stencils on (sources_sorted, col_sorted)
+ * with GMLS_OPT_SOURCE_STRIDE = 4 gives the weights of (coords, col) bit for
+ * bit, gathering each row from nearby memory instead of from the sources'
+ * own order.
+ *   sources_sorted  out: FP64 [n_src][4] records (x, y, z, source index): the
+ *                   coordinates (0 beyond dim) and the index as a double, by
+ *                   cell of the search's uniform grid, then by source index;
+ *                   the same on every call with the same inputs
+ *   col_sorted      out: int32 [col_capacity], must not alias col: entry j of
+ *                   a row is the position of the record of source col[j]
+ *                   (sources_sorted[4*col_sorted[j] + 3] == col[j])
+ * Other arguments, errors and capacity rules as for gmls_neighbors; col and
+ * col_sorted are both written, or (over capacity) neither.  The one-pass
+ * radius search in cell order (GMLS_OPT_ROW_ORDER 0, scratch within
+ * GMLS_OPT_RADIUS_SCRATCH_MB) writes the positions as it finds the rows;
+ * the other paths translate the finished rows, one more pass over them. */
+gmls_status gmls_neighbors_sorted(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                  int64_t n_tgt, int dim, const gmls_search *spec, int64_t *row_ptr, int32_t *col,
+                                  int64_t col_capacity, double *eps, int64_t *nnz_host, double *sources_sorted,
+                                  int32_t *col_sorted);
 
 /* Output shape (host only): number of functional rows F, input components
  * C_in (1 scalar, dim vector) and basis size Q for a basis/order/mask. */

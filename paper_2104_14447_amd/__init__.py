@@ -25,7 +25,7 @@ __all__ = [
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
     "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "OPT_ROW_ORDER", "ROW_ORDER_CELL",
     "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE", "SCHEME_WAVE",
-    "OPT_PIPE_SHAPE", "TuneResult", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
+    "OPT_PIPE_SHAPE", "OPT_SOURCE_STRIDE", "gmls_neighbors_sorted", "TuneResult", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
     "StencilSet", "gmls_stencils_multi", "gmls_spmv_noalloc", "NOALLOC_SPMV_MAX_ROWS",
     "EXPORTED_SYMBOLS",
 ]
@@ -38,7 +38,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 SEARCH_KNN, SEARCH_RADIUS = 0, 1
 OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
 OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE, OPT_ROW_ORDER = 4, 5, 6, 7, 8
-OPT_PIPE_SHAPE = 9
+OPT_PIPE_SHAPE, OPT_SOURCE_STRIDE = 9, 10
 ROW_ORDER_CELL, ROW_ORDER_INDEX = 0, 1
 NOALLOC_SPMV_MAX_ROWS = 1 << 23  # rows gmls_spmv_noalloc takes (its static scratch)
 SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE, SCHEME_WAVE = 0, 1, 2, 3, 4
@@ -48,7 +48,8 @@ _STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_HIP", 3: "ERR_NOMEM", 4: "ERR_CAPACITY
 EXPORTED_SYMBOLS = ("gmls_create", "gmls_destroy", "gmls_last_error", "gmls_set_option", "gmls_neighbors",
                     "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained", "gmls_stencils_staggered",
                     "gmls_assemble_stokes", "gmls_spmv", "gmls_apply", "gmls_check", "gmls_autotune",
-                    "gmls_autotune_save", "gmls_autotune_load", "gmls_stencils_multi", "gmls_spmv_noalloc")
+                    "gmls_autotune_save", "gmls_autotune_load", "gmls_stencils_multi", "gmls_spmv_noalloc",
+                    "gmls_neighbors_sorted")
 
 
 class GmlsError(RuntimeError):
@@ -129,6 +130,8 @@ def load_library():
     L.gmls_neighbors.argtypes = [_vp, _vp, _i64, _vp, _i64, ctypes.c_int, ctypes.POINTER(SearchSpec), _vp, _vp, _i64,
                                  _vp, ctypes.POINTER(_i64)]
     L.gmls_neighbors.restype = ctypes.c_int
+    L.gmls_neighbors_sorted.argtypes = list(L.gmls_neighbors.argtypes) + [_vp, _vp]
+    L.gmls_neighbors_sorted.restype = ctypes.c_int
     L.gmls_stencil_shape.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint,
                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                      ctypes.POINTER(ctypes.c_int)]
@@ -198,6 +201,7 @@ class Context:
         self._h = h
         self._col_cap = 0
         self.capture_safe = False
+        self.source_stride = 0
 
     def close(self):
         if getattr(self, "_h", None):
@@ -220,6 +224,8 @@ class Context:
             self._raise(st)
         if option == OPT_CAPTURE_SAFE:
             self.capture_safe = bool(value)
+        if option == OPT_SOURCE_STRIDE:
+            self.source_stride = int(value)
 
     def check(self):
         """Raise for errors that capture-safe calls left on the device."""
@@ -237,13 +243,7 @@ def gmls_stencil_shape(dim: int, order: int, basis: int, mask: int):
     return F.value, C.value, Q.value
 
 
-def gmls_neighbors(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, mode: int, k: int = 0,
-                   eps_mult: float = 1.5, radius: float = 0.0, k_min: int = 0, col: torch.Tensor | None = None):
-    """Neighbour lists: returns (row_ptr int64 [n_tgt+1], col int32 [nnz], eps float64 [n_tgt]).
-
-    In capture-safe mode the total is not known on the host: the whole `col`
-    buffer (which the caller must supply) is returned, row_ptr[-1] holds the
-    total, and capacity errors surface through Context.check()."""
+def _neighbors(ctx, coords, targets, mode, k, eps_mult, radius, k_min, col, col_sorted, sorted_out, records=None):
     _check_dev(coords, targets)
     n_src, dim = coords.shape
     n_tgt = targets.shape[0]
@@ -251,27 +251,74 @@ def gmls_neighbors(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, mo
     spec = SearchSpec(mode, k, eps_mult, radius, k_min, 0)
     row_ptr = torch.empty(n_tgt + 1, dtype=torch.int64, device=dev)
     eps = torch.empty(n_tgt, dtype=torch.float64, device=dev)
-    if col is None:
+    if sorted_out and records is None:
+        records = torch.empty((n_src, 4), dtype=torch.float64, device=dev)
+    if sorted_out and (records.shape != (n_src, 4) or records.dtype != torch.float64 or not records.is_contiguous()):
+        raise ValueError("records must be a contiguous float64 tensor [n_src, 4]")
+    if col is None or (sorted_out and col_sorted is None):
         if ctx.capture_safe:
-            raise ValueError("capture-safe mode: pass a preallocated col buffer")
+            raise ValueError("capture-safe mode: pass preallocated col (and col_sorted) buffers")
         cap = n_tgt * k if mode == SEARCH_KNN else max(ctx._col_cap, n_tgt * max(k_min, 1) * 2)
-        col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        if col is None:
+            col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        if sorted_out and col_sorted is None:
+            col_sorted = torch.empty(col.numel(), dtype=torch.int32, device=dev)
+    if sorted_out and col_sorted.numel() < col.numel():
+        raise ValueError("col_sorted must hold as many entries as col")
     nnz = ctypes.c_int64()
     L = load_library()
-    args = lambda c: (ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, ctypes.byref(spec), _ptr(row_ptr),
-                      _ptr(c), c.numel(), _ptr(eps), ctypes.byref(nnz))
-    st = L.gmls_neighbors(*args(col))
+
+    def call(c, cs):
+        a = (ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, ctypes.byref(spec), _ptr(row_ptr), _ptr(c),
+             c.numel(), _ptr(eps), ctypes.byref(nnz))
+        return L.gmls_neighbors_sorted(*a, _ptr(records), _ptr(cs)) if sorted_out else L.gmls_neighbors(*a)
+
+    st = call(col, col_sorted)
     if ctx.capture_safe:
         if st != GMLS_OK:
             ctx._raise(st)
-        return row_ptr, col, eps
+        return row_ptr, col, eps, records, col_sorted
     if st == GMLS_ERR_CAPACITY:
         col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
-        st = L.gmls_neighbors(*args(col))
+        if sorted_out:
+            col_sorted = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+        st = call(col, col_sorted)
     if st != GMLS_OK:
         ctx._raise(st)
     ctx._col_cap = max(ctx._col_cap, nnz.value)
-    return row_ptr, col[: nnz.value], eps
+    return row_ptr, col[: nnz.value], eps, records, (col_sorted[: nnz.value] if sorted_out else None)
+
+
+def gmls_neighbors(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, mode: int, k: int = 0,
+                   eps_mult: float = 1.5, radius: float = 0.0, k_min: int = 0, col: torch.Tensor | None = None):
+    """Neighbour lists: returns (row_ptr int64 [n_tgt+1], col int32 [nnz], eps float64 [n_tgt]).
+
+    In capture-safe mode the total is not known on the host: the whole `col`
+    buffer (which the caller must supply) is returned, row_ptr[-1] holds the
+    total, and capacity errors surface through Context.check()."""
+    return _neighbors(ctx, coords, targets, mode, k, eps_mult, radius, k_min, col, None, False)[:3]
+
+
+def gmls_neighbors_sorted(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, mode: int, k: int = 0,
+                          eps_mult: float = 1.5, radius: float = 0.0, k_min: int = 0,
+                          col: torch.Tensor | None = None, col_sorted: torch.Tensor | None = None,
+                          records: torch.Tensor | None = None):
+    """gmls_neighbors plus the search's cell-ordered source records and the
+    rows as positions in them.  Returns (row_ptr, col, eps, records float64
+    [n_src, 4] (x, y, z, index), col_sorted int32 [nnz]).  Stencil calls on
+    (records, col_sorted) with OPT_SOURCE_STRIDE = 4 give the weights of
+    (coords, col)."""
+    return _neighbors(ctx, coords, targets, mode, k, eps_mult, radius, k_min, col, col_sorted, True, records)
+
+
+def _source_shape(ctx: Context, coords: torch.Tensor, targets: torch.Tensor):
+    """(n_src, dim) of a stencil call: dim from the targets, the coords'
+    width checked against the context's source stride."""
+    dim = targets.shape[1]
+    stride = ctx.source_stride or dim
+    if coords.dim() != 2 or coords.shape[1] != stride:
+        raise ValueError(f"coords must be [n_src, {stride}] (dim {dim}, source stride option {ctx.source_stride})")
+    return coords.shape[0], dim
 
 
 def gmls_stencils(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, order: int, basis: int, mask: int,
@@ -280,7 +327,7 @@ def gmls_stencils(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, ord
                   report: bool = False):
     """Stencil weights.  Returns (weights float64, status uint8, report dict or None)."""
     _check_dev(coords, targets, eps, row_ptr, col)
-    n_src, dim = coords.shape
+    n_src, dim = _source_shape(ctx, coords, targets)
     n_tgt = targets.shape[0]
     F, C, _ = gmls_stencil_shape(dim, order, basis, mask)
     nnz = col.numel()
@@ -304,7 +351,7 @@ def gmls_stencils_multi(ctx: Context, coords: torch.Tensor, targets: torch.Tenso
     `sets` is a list of (basis, mask); `outputs` an optional list of
     (weights, status) tensors.  Returns ([(weights, status), ...], report)."""
     _check_dev(coords, targets, eps, row_ptr, col)
-    n_src, dim = coords.shape
+    n_src, dim = _source_shape(ctx, coords, targets)
     n_tgt = targets.shape[0]
     nnz = col.numel()
     arr = (StencilSet * len(sets))()
@@ -332,7 +379,7 @@ def gmls_autotune(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, ord
     """Autotune the mixed pipeline's row shapes on this problem (the choice is
     kept in the context).  Returns the tuning result as a dict."""
     _check_dev(coords, targets, eps, row_ptr, col)
-    n_src, dim = coords.shape
+    n_src, dim = _source_shape(ctx, coords, targets)
     n_tgt = targets.shape[0]
     F, C, _ = gmls_stencil_shape(dim, order, basis, mask)
     weights = torch.empty(max(F * C * col.numel(), 1), dtype=torch.float64, device=coords.device)
@@ -367,7 +414,7 @@ def gmls_stencils_constrained(ctx: Context, coords: torch.Tensor, targets: torch
     _check_dev(coords, targets, eps, row_ptr, col, normals)
     if normals.shape != targets.shape or normals.dtype != torch.float64 or not normals.is_contiguous():
         raise ValueError("normals must be a contiguous float64 tensor shaped like targets [n_tgt, dim]")
-    n_src, dim = coords.shape
+    n_src, dim = _source_shape(ctx, coords, targets)
     n_tgt = targets.shape[0]
     F, C, _ = gmls_stencil_shape(dim, order, BASIS_SCALAR, mask)
     nnz = col.numel()
@@ -397,7 +444,7 @@ def gmls_stencils_staggered(ctx: Context, coords: torch.Tensor, targets: torch.T
     `order`).  Returns (weights float64, target weights float64 [n_tgt, F],
     status uint8, report dict or None)."""
     _check_dev(coords, targets, eps, row_ptr, col)
-    n_src, dim = coords.shape
+    n_src, dim = _source_shape(ctx, coords, targets)
     n_tgt = targets.shape[0]
     F = (dim if mask & F_GRAD else 0) + (1 if mask & F_LAPLACIAN else 0)
     nnz = col.numel()

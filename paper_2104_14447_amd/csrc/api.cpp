@@ -182,6 +182,11 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
         return gmls_set_error(ctx, GMLS_ERR_ARG, "pipeline shape must be -1 (tuned) or a candidate 0..2");
       ctx->opt.pipe_force = (int)value;
       return GMLS_OK;
+    case GMLS_OPT_SOURCE_STRIDE:
+      if (!(value == (double)(int)value && value >= 0 && value <= 64))
+        return gmls_set_error(ctx, GMLS_ERR_ARG, "source stride must be an integer in [0, 64]");
+      ctx->opt.source_stride = (int)value;
+      return GMLS_OK;
     case GMLS_OPT_RADIUS_SCRATCH_MB:
       if (!(value >= 0 && value <= 1048576.0 && value == (double)(int64_t)value))
         return gmls_set_error(ctx, GMLS_ERR_ARG, "radius scratch must be an integer number of MiB in [0, 2^20]");
@@ -207,9 +212,10 @@ gmls_status gmls_stencil_shape(int dim, int order, int basis, unsigned functiona
   return GMLS_OK;
 }
 
-gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
-                           int64_t n_tgt, int dim, const gmls_search *spec, int64_t *row_ptr, int32_t *col,
-                           int64_t col_capacity, double *eps, int64_t *nnz_host) {
+static gmls_status neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                             int64_t n_tgt, int dim, const gmls_search *spec, int64_t *row_ptr, int32_t *col,
+                             int64_t col_capacity, double *eps, int64_t *nnz_host, double *records,
+                             int32_t *pcol) {
   if (!ctx) return GMLS_ERR_ARG;
   ctx->err.clear();
   if (!spec || !nnz_host) return gmls_set_error(ctx, GMLS_ERR_ARG, "spec and nnz_host must be non-null");
@@ -236,7 +242,28 @@ gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, co
     return gmls_set_error(ctx, GMLS_ERR_ARG, "unknown search mode");
   }
   DeviceGuard g(ctx->device);
-  return run_neighbors(ctx, coords, n_src, targets, n_tgt, dim, *spec, row_ptr, col, col_capacity, eps, nnz_host);
+  return run_neighbors(ctx, coords, n_src, targets, n_tgt, dim, *spec, row_ptr, col, col_capacity, eps, nnz_host,
+                       records, pcol);
+}
+
+gmls_status gmls_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                           int64_t n_tgt, int dim, const gmls_search *spec, int64_t *row_ptr, int32_t *col,
+                           int64_t col_capacity, double *eps, int64_t *nnz_host) {
+  return neighbors(ctx, coords, n_src, targets, n_tgt, dim, spec, row_ptr, col, col_capacity, eps, nnz_host, nullptr,
+                   nullptr);
+}
+
+gmls_status gmls_neighbors_sorted(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
+                                  int64_t n_tgt, int dim, const gmls_search *spec, int64_t *row_ptr, int32_t *col,
+                                  int64_t col_capacity, double *eps, int64_t *nnz_host, double *sources_sorted,
+                                  int32_t *col_sorted) {
+  if (!ctx) return GMLS_ERR_ARG;
+  ctx->err.clear();
+  if (!sources_sorted || (col_capacity > 0 && !col_sorted))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer (sources_sorted, col_sorted)");
+  if (col_sorted && col_sorted == col) return gmls_set_error(ctx, GMLS_ERR_ARG, "col_sorted must not alias col");
+  return neighbors(ctx, coords, n_src, targets, n_tgt, dim, spec, row_ptr, col, col_capacity, eps, nnz_host,
+                   sources_sorted, col_sorted);
 }
 
 }  // extern "C"
@@ -350,6 +377,8 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
     return gmls_set_error(ctx, GMLS_ERR_ARG, "n_src must be >= 1 and n_tgt in [0, 2^31)");
   if (n_tgt > 0 && (!coords || !targets || !eps || !row_ptr || !col || !weights))
     return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  const int cstride = ctx->opt.source_stride ? ctx->opt.source_stride : dim;
+  if (cstride < dim) return gmls_set_error(ctx, GMLS_ERR_ARG, "source stride is smaller than dim");
   if (normals) {
     if (basis != GMLS_BASIS_SCALAR)
       return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "the Neumann constraint is implemented for the scalar basis");
@@ -372,6 +401,7 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
 
   StencilArgs a;
   a.coords = coords;
+  a.cstride = cstride;
   a.targets = targets;
   a.eps = eps;
   a.row_ptr = row_ptr;
@@ -503,6 +533,8 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
     return gmls_set_error(ctx, GMLS_ERR_ARG, "n_src must be >= 1 and n_tgt in [0, 2^31)");
   if (n_tgt > 0 && (!coords || !targets || !eps || !row_ptr || !col || !ss.weights || !sv.weights))
     return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+  const int cstride = ctx->opt.source_stride ? ctx->opt.source_stride : dim;
+  if (cstride < dim) return gmls_set_error(ctx, GMLS_ERR_ARG, "source stride is smaller than dim");
   if (report) memset(report, 0, sizeof(*report));
   if (n_tgt == 0) return GMLS_OK;
   DeviceGuard g(ctx->device);
@@ -522,6 +554,7 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
     return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
   StencilArgs as;
   as.coords = coords;
+  as.cstride = cstride;
   as.targets = targets;
   as.eps = eps;
   as.row_ptr = row_ptr;

@@ -53,6 +53,7 @@ enum Slot {
   WS_PIPE_Y2,
   WS_COND,
   WS_REPORT,
+  WS_SRC_POS,
   WS_NUM_SLOTS
 };
 
@@ -74,6 +75,7 @@ struct Options {
   int capture_safe = 0;              // nonzero: no call waits for the device (see libgmls.h)
   int row_order = 0;                 // radius rows: 0 cell order, 1 ascending source index
   int pipe_force = -1;               // pipeline row shape: -1 the tuned table, else this candidate
+  int source_stride = 0;             // doubles per source record of the stencil calls (0: dim)
   int reuse_moments = 0;             // per call: the pipeline's moments and records are already in place
   // per call: pipeline row-shape candidate of [kernel: 0 moments, 1 weights][bin]
   signed char pipe_shape[2][8] = {};
@@ -156,11 +158,12 @@ struct Stats {
 // ---- search (search.hip) ----
 gmls_status run_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
                           int64_t n_tgt, int dim, const gmls_search &spec, int64_t *row_ptr, int32_t *col,
-                          int64_t col_capacity, double *eps, int64_t *nnz_host);
+                          int64_t col_capacity, double *eps, int64_t *nnz_host, double *records, int32_t *pcol);
 
 // ---- stencils (stencil_*.hip) ----
 struct StencilArgs {
-  const double *coords;
+  const double *coords;  // source j at coords[j * cstride .. + dim)
+  int cstride;
   const double *targets;
   const double *eps;
   const int64_t *row_ptr;

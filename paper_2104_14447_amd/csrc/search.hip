@@ -1011,7 +1011,7 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
                                                                const double *targets, const int *order, double r0,
                                                                int k_min, int64_t *counts, const int64_t *row_ptr,
                                                                int32_t *col, double *eps, int *defer, int *n_defer,
-                                                               uint8_t *dflag, int *flags) {
+                                                               uint8_t *dflag, int *flags, int pos_rows) {
   constexpr bool ROWS = MODE != kCount;
   constexpr int NT = cell_targets<SORTED>();
   if (MODE == kFill && (*flags & 2)) return;  // over capacity: nothing is written
@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
       cxyz[0][e] = sp.x;
       cxyz[1][e] = sp.y;
       cxyz[2][e] = sp.z;
-      cid[e] = sp.idx;
+      cid[e] = pos_rows ? src : sp.idx;  // the record's position, or the source index
     }
     // this wavefront's targets (every fourth of the cell), fetched by its
     // lanes together, 64 at a time, then taken NT at a time: each staged
@@ -1213,12 +1213,16 @@ __global__ void k_check_capacity(const int64_t *nnz, int64_t capacity, int *flag
 // consecutive entries, so loads and stores stay contiguous).
 constexpr int kCopyLoads = 8;
 __global__ __launch_bounds__(256) void k_rows_copy(int64_t n_tgt, const int64_t *row_ptr, const int32_t *rows,
-                                                   const uint8_t *dflag, int32_t *col, const int *flags) {
+                                                   const uint8_t *dflag, int32_t *col, const int *flags,
+                                                   const SPoint *sorted, int32_t *pcol, const int *order) {
   if (*flags & 2) return;  // over capacity: nothing is written
   const int sub = threadIdx.x & 15;
   const int64_t g0 = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
   const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 4);
-  for (int64_t t = g0; t < n_tgt; t += stride) {
+  for (int64_t i = g0; i < n_tgt; i += stride) {
+    // with record positions, targets in cell order, so that neighbouring
+    // groups read the same records
+    const int64_t t = pcol ? order[i] : i;
     if (dflag[t]) continue;
     const int64_t b = row_ptr[t];
     const int n = (int)(row_ptr[t + 1] - b);
@@ -1230,11 +1234,62 @@ __global__ __launch_bounds__(256) void k_rows_copy(int64_t n_tgt, const int64_t 
         const int q = q0 + 16 * u + sub;
         v[u] = q < n ? src[q] : 0;
       }
+      if (pcol) {
+        // the scratch rows hold record positions: the source index is the
+        // record's (the positions of a row are a few runs of nearby records)
+        int32_t id[kCopyLoads];
 #pragma unroll
-      for (int u = 0; u < kCopyLoads; ++u) {
-        const int q = q0 + 16 * u + sub;
-        if (q < n) col[b + q] = v[u];
+        for (int u = 0; u < kCopyLoads; ++u) id[u] = q0 + 16 * u + sub < n ? sorted[v[u]].idx : 0;
+#pragma unroll
+        for (int u = 0; u < kCopyLoads; ++u) {
+          const int q = q0 + 16 * u + sub;
+          if (q < n) {
+            pcol[b + q] = v[u];
+            col[b + q] = id[u];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < kCopyLoads; ++u) {
+          const int q = q0 + 16 * u + sub;
+          if (q < n) col[b + q] = v[u];
+        }
       }
+    }
+  }
+}
+
+// Record positions of the rows written with source indices (every row, or
+// those flagged in dflag): pcol[j] = pos[col[j]], pos the inverse of the
+// record order.  16 lanes per target, as k_rows_copy.
+__global__ __launch_bounds__(256) void k_rows_pos(int64_t n_tgt, const int64_t *row_ptr, const int32_t *col,
+                                                  const uint8_t *dflag, const int *pos, int32_t *pcol,
+                                                  const int *flags) {
+  if (*flags & 2) return;  // over capacity: nothing was written
+  const int sub = threadIdx.x & 15;
+  const int64_t g0 = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
+  const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 4);
+  for (int64_t t = g0; t < n_tgt; t += stride) {
+    if (dflag && !dflag[t]) continue;
+    const int64_t b = row_ptr[t];
+    const int n = (int)(row_ptr[t + 1] - b);
+    for (int q = sub; q < n; q += 16) pcol[b + q] = pos[col[b + q]];
+  }
+}
+
+// pos[idx] = position of the source's record; the records handed out as
+// (x, y, z, index) doubles
+__global__ void k_source_records(const SPoint *sorted, int64_t n, int *pos, double *rec) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const SPoint p = sorted[j];
+    pos[p.idx] = (int)j;
+    if (rec) {
+      double4 r;
+      r.x = p.x;
+      r.y = p.y;
+      r.z = p.z;
+      r.w = (double)p.idx;
+      *(double4 *)(rec + 4 * j) = r;
     }
   }
 }
@@ -1488,7 +1543,8 @@ static void search_time(gmls_ctx ctx) {
 template <int DIM>
 static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
                                  int64_t n_tgt, const gmls_search &spec, int64_t *row_ptr, int32_t *col,
-                                 int64_t col_capacity, double *eps, int64_t *nnz_host) {
+                                 int64_t col_capacity, double *eps, int64_t *nnz_host, double *records,
+                                 int32_t *pcol) {
   hipStream_t s = ctx->stream;
   const bool knn = spec.mode == GMLS_SEARCH_KNN;
   const bool sync = !ctx->opt.capture_safe;  // capture-safe: nothing below waits for the device
@@ -1521,9 +1577,10 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
   GMLS_HIP(exclusive_scan<int, int>(cnt, start, ncell_max, (int *)tmp, s));
   GMLS_HIP(fill_zero(cnt, sizeof(int) * (size_t)(ncell_max + 1), s));
   const bool by_index = ctx->opt.row_order != 0;
-  if (!knn && !by_index) {
+  if ((!knn && !by_index) || records) {
     // radius rows come out in staging order, which is cell order once each
-    // cell's sources are in ascending index
+    // cell's sources are in ascending index (and the records handed out are
+    // then the same on every call)
     GMLS_WS(scattered, SPoint, WS_SORTED_TMP, n_src);
     k_cell_scatter<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(coords, n_src, key, start, cnt, scattered);
     k_cell_sort<<<(unsigned)xcd_grid(ctx->cus * 32), 64, 0, s>>>(gp, start, scattered, sorted);
@@ -1531,6 +1588,12 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
     k_cell_scatter<DIM><<<grid_for(n_src, 256), 256, 0, s>>>(coords, n_src, key, start, cnt, sorted);
   }
   GMLS_HIP(hipGetLastError());
+  int *pos = nullptr;  // source index -> record position
+  if (records) {
+    pos = (int *)ctx->ws(WS_SRC_POS, sizeof(int) * (size_t)n_src);
+    if (!pos) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed (positions)");
+    k_source_records<<<grid_for(n_src, 256), 256, 0, s>>>(sorted, n_src, pos, records);
+  }
   const int *tcs = start;  // target ranges per cell in `order`
   if (n_tgt > 0) {
     if (targets == coords && n_tgt == n_src) {
@@ -1568,6 +1631,7 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
       else
         k_knn_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, order, nullptr, n_tgt, spec.k,
                                             spec.eps_mult, col, eps);
+      if (pcol) k_rows_pos<<<grid_for(n_tgt, 16), 256, 0, s>>>(n_tgt, row_ptr, col, nullptr, pos, pcol, flags);
     }
     GMLS_HIP(hipGetLastError());
     if (sync) {
@@ -1592,16 +1656,19 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
     dflag = (uint8_t *)ctx->ws(WS_TGT_FLAG, (size_t)n_tgt);
     if (!rows || !dflag) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed (rows)");
   }
+  // the one-pass search in cell order writes record positions to its scratch
+  // rows when they are asked for; the other paths translate finished rows
+  const int pos_rows = (pcol && fused && !by_index) ? 1 : 0;
   if (n_tgt > 0) {
     if (fused)
       launch_cells<DIM, kFused>(by_index, nb_cells, s, (const GridParams *)gp, (const SPoint *)sorted, start, tcs,
                                 targets, (const int *)order, spec.radius, spec.k_min, counts,
-                                (const int64_t *)nullptr, rows, eps, defer, flags + 2, dflag, flags);
+                                (const int64_t *)nullptr, rows, eps, defer, flags + 2, dflag, flags, pos_rows);
     else
       launch_cells<DIM, kCount>(by_index, nb_cells, s, (const GridParams *)gp, (const SPoint *)sorted, start, tcs,
                                 targets, (const int *)order, spec.radius, spec.k_min, counts,
                                 (const int64_t *)nullptr, (int32_t *)nullptr, (double *)nullptr, defer, flags + 2,
-                                (uint8_t *)nullptr, flags);
+                                (uint8_t *)nullptr, flags, 0);
     k_radius_count_list<DIM><<<4096, 64, 0, s>>>(gp, sorted, start, targets, defer, flags + 2, spec.radius,
                                                  spec.k_min, counts, flags);
   }
@@ -1629,14 +1696,16 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
     int *n_defer_fill = flags + 2;
     int *overflow = (int *)counts;  // the counts are consumed by the scan
     if (fused) {
-      k_rows_copy<<<grid_for(n_tgt, 16), 256, 0, s>>>(n_tgt, row_ptr, rows, dflag, col, flags);
+      k_rows_copy<<<grid_for(n_tgt, 16), 256, 0, s>>>(n_tgt, row_ptr, rows, dflag, col, flags,
+                                                       (const SPoint *)sorted, pos_rows ? pcol : nullptr,
+                                                       (const int *)order);
     } else {
       defer_fill = defer + n_tgt;
       n_defer_fill = flags + 3;
       launch_cells<DIM, kFill>(by_index, nb_cells, s, (const GridParams *)gp, (const SPoint *)sorted, start, tcs,
                                targets, (const int *)order, spec.radius, spec.k_min, (int64_t *)nullptr,
                                (const int64_t *)row_ptr, col, eps, defer_fill, n_defer_fill, (uint8_t *)nullptr,
-                               flags);
+                               flags, 0);
     }
     launch_fill_list<DIM>(by_index, s, (const GridParams *)gp, (const SPoint *)sorted, start, coords, targets,
                           (const int *)defer_fill, (const int *)n_defer_fill, spec.radius, spec.k_min,
@@ -1644,6 +1713,9 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
     launch_fill_big<DIM>(by_index, s, (const GridParams *)gp, (const SPoint *)sorted, start, coords, targets,
                          spec.radius, spec.k_min, (const int64_t *)row_ptr, col, eps, (const int *)overflow,
                          (const int *)(flags + 1), (const int *)flags);
+    if (pcol)  // rows written with source indices: the deferred ones, or all
+      k_rows_pos<<<grid_for(n_tgt, 16), 256, 0, s>>>(n_tgt, row_ptr, col, pos_rows ? dflag : nullptr, pos, pcol,
+                                                      flags);
   }
   GMLS_HIP(hipGetLastError());
   if (sync) {
@@ -1660,14 +1732,17 @@ static gmls_status neighbors_dim(gmls_ctx ctx, const double *coords, int64_t n_s
 
 gmls_status run_neighbors(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
                           int64_t n_tgt, int dim, const gmls_search &spec, int64_t *row_ptr, int32_t *col,
-                          int64_t col_capacity, double *eps, int64_t *nnz_host) {
+                          int64_t col_capacity, double *eps, int64_t *nnz_host, double *records, int32_t *pcol) {
   switch (dim) {
     case 1:
-      return neighbors_dim<1>(ctx, coords, n_src, targets, n_tgt, spec, row_ptr, col, col_capacity, eps, nnz_host);
+      return neighbors_dim<1>(ctx, coords, n_src, targets, n_tgt, spec, row_ptr, col, col_capacity, eps, nnz_host,
+                              records, pcol);
     case 2:
-      return neighbors_dim<2>(ctx, coords, n_src, targets, n_tgt, spec, row_ptr, col, col_capacity, eps, nnz_host);
+      return neighbors_dim<2>(ctx, coords, n_src, targets, n_tgt, spec, row_ptr, col, col_capacity, eps, nnz_host,
+                              records, pcol);
     case 3:
-      return neighbors_dim<3>(ctx, coords, n_src, targets, n_tgt, spec, row_ptr, col, col_capacity, eps, nnz_host);
+      return neighbors_dim<3>(ctx, coords, n_src, targets, n_tgt, spec, row_ptr, col, col_capacity, eps, nnz_host,
+                              records, pcol);
     default:
       return gmls_set_error(ctx, GMLS_ERR_ARG, "dim must be 1, 2 or 3");
   }

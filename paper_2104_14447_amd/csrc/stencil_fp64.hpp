@@ -44,7 +44,7 @@ __device__ __forceinline__ void row_s_w(const StencilArgs &a, int64_t base, int 
     const int c = a.col[base + j];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      s[d] = (a.coords[(int64_t)c * DIM + d] - xt[d]) * ie;
+      s[d] = (a.coords[(int64_t)c * a.cstride + d] - xt[d]) * ie;
       rr += s[d] * s[d];
     }
     const double rad = sqrt(rr);

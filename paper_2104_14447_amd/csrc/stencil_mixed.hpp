@@ -214,7 +214,7 @@ __device__ void mixed_target(const StencilArgs &a, const RowKinds &rk, int t, bo
       double rr = 0.0;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) {
-        s[d] = (a.coords[(int64_t)c * DIM + d] - xt[d]) * ie;
+        s[d] = (a.coords[(int64_t)c * a.cstride + d] - xt[d]) * ie;
         rr += s[d] * s[d];
       }
       const double rad = sqrt(rr);

@@ -94,7 +94,7 @@ __device__ __forceinline__ void load_row(const StencilArgs &a, int64_t base, int
   double rr = 0.0;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
-    s[d] = (a.coords[(int64_t)c * DIM + d] - xt[d]) * ie;
+    s[d] = (a.coords[(int64_t)c * a.cstride + d] - xt[d]) * ie;
     rr += s[d] * s[d];
   }
   const double rad = sqrt(rr);

@@ -108,7 +108,7 @@ __device__ __forceinline__ void gather_rows(const StencilArgs &a, int64_t base, 
 #pragma unroll
   for (int r = 0; r < RPL; ++r)
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) xs[r][d] = a.coords[(int64_t)c[r] * DIM + d];
+    for (int d = 0; d < DIM; ++d) xs[r][d] = a.coords[(int64_t)c[r] * a.cstride + d];
 }
 
 // scaled offset s = (x_j - x_T)/eps and kernel weight (1 - |s|)^p (0 outside

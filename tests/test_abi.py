@@ -23,7 +23,7 @@ def test_header_declares_the_boundary():
                             "gmls_stencil_shape", "gmls_stencils", "gmls_stencils_constrained",
                             "gmls_stencils_staggered", "gmls_assemble_stokes", "gmls_spmv", "gmls_apply",
                             "gmls_check", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
-                            "gmls_stencils_multi", "gmls_spmv_noalloc"])
+                            "gmls_stencils_multi", "gmls_spmv_noalloc", "gmls_neighbors_sorted"])
 
 
 def test_library_exports_every_declared_symbol():
