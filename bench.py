@@ -403,9 +403,12 @@ def main():
                      aux=torch.empty((n_t, bs["F"]), dtype=torch.float64, device=dev)) for bs in bases]
 
     # ---- autotune the mixed pipeline's row shapes (before any timing) ----
+    # ---- autotune the per-bin kernel shapes (before any timing): the mixed
+    # scheme's kernels and the FP64 QR kernel, per basis and, for a scalar and
+    # a divergence-free basis on one call, the shared kernels ----
     tune_summary = "off"
     tune_path = None
-    if "mixed" in legs and not args.no_autotune:
+    if not args.no_autotune:
         if args.tune_cache and os.path.exists(args.tune_cache):
             G.gmls_autotune_load(ctx, args.tune_cache)
             tune_summary = {"loaded": args.tune_cache}
@@ -413,20 +416,27 @@ def main():
         else:
             tune_summary = {}
             t0 = time.time()
+            jobs = []
             for bs in bases:
                 if bs["name"] == "neumann":
                     continue
                 # staggered stencils run the scalar pipeline of order + 1
                 order_t, b_t = (bs["order"] + 1, G.BASIS_SCALAR) if bs["name"] == "staggered" \
                     else (bs["order"], bs["b"])
+                jobs.append((bs["name"], order_t, b_t, bs["mask"]))
+            if shared:
+                ms_ = [bs["mask"] for bs in bases if bs["name"] == "scalar"][0]
+                mv_ = [bs["mask"] for bs in bases if bs["name"] == "divfree"][0]
+                jobs.append(("shared", bases[0]["order"], G.TUNE_SHARED, ms_ | (mv_ << 4)))
+            for name_t, order_t, b_t, mask_t in jobs:
                 try:
-                    res = G.gmls_autotune(ctx, src0, xt, order_t, b_t, bs["mask"], p, eps0, rp0, scol0, reps=3)
+                    res = G.gmls_autotune(ctx, src0, xt, order_t, b_t, mask_t, p, eps0, rp0, scol0, reps=3)
                 except G.GmlsError as e:
-                    if e.status != G.GMLS_ERR_UNSUPPORTED:  # not the pipeline: nothing to tune
+                    if e.status != G.GMLS_ERR_UNSUPPORTED:  # no tunable kernel compiled for the shape
                         raise
                     continue
-                tune_summary[bs["name"]] = {k_: {b: "%dx%d" % v["chosen"] for b, v in d.items()}
-                                            for k_, d in res.items()}
+                tune_summary[name_t] = {k_: {b: "%dx%d" % v["chosen"] for b, v in d.items()}
+                                        for k_, d in res.items()}
             print(f"# autotune: {tune_summary} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
             if tune_summary:
                 if args.tune_cache:
@@ -436,7 +446,7 @@ def main():
                     os.close(fd)
                 G.gmls_autotune_save(ctx, tune_path)
             else:
-                tune_summary = "no pipeline in this configuration"
+                tune_summary = "nothing tunable in this configuration"
 
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
@@ -480,8 +490,8 @@ def main():
             gctx.set_option(G.OPT_MIXED_SCHEME, args.scheme)
             if sorted_layout:
                 gctx.set_option(G.OPT_SOURCE_STRIDE, 4)
-            if tune_path and leg == "mixed":
-                G.gmls_autotune_load(gctx, tune_path)  # the same row shapes as the eager steps
+            if tune_path:
+                G.gmls_autotune_load(gctx, tune_path)  # the same shapes as the eager steps
             gbufs = new_bufs()
             gcol = torch.empty(nnz + 1024, dtype=torch.int32, device=dev)
             gpcol = torch.empty_like(gcol) if sorted_layout else None

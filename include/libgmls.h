@@ -173,11 +173,15 @@ enum {
                                        where nothing was tuned;
                                   0, 1, 2 = this candidate in every bin (gmls_tune_result lists
                                        the lanes per target and rows per lane of each).          */
-  GMLS_OPT_SOURCE_STRIDE = 10  /* layout of `coords` in the stencil calls (gmls_stencils, _multi,
+  GMLS_OPT_SOURCE_STRIDE = 10, /* layout of `coords` in the stencil calls (gmls_stencils, _multi,
                                   _constrained, _staggered) (0): source j is at coords[j*stride ..
                                   j*stride + dim); 0 means stride = dim; otherwise an integer in
                                   [dim, 64].  Use 4 with the records of gmls_neighbors_sorted.
                                   The search calls always read [n][dim].                         */
+  GMLS_OPT_WAVE_SHAPE = 11,    /* variant of the wavefront kernel (mixed scheme 4) (-1): -1 the
+                                  autotuned choice per bin, else this candidate in every bin      */
+  GMLS_OPT_QR_SHAPE = 12       /* shape of the FP64 QR kernel per bin (-1): -1 the autotuned
+                                  choice, else this candidate in every bin (gmls_tune_result)    */
 };
 
 /* Create a context on HIP device `device`, enqueuing on `hip_stream`
@@ -435,36 +439,60 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
                                 const gmls_stencil_set *sets, gmls_report *report);
 
 /* ---------------------------------------------------------------------------
- * Autotuner of the mixed pipeline (GMLS_OPT_MIXED_SCHEME 3, or the automatic
- * choice where it resolves to 3).  The pipeline's two row-parallel kernels,
- * the moments (kernel 0) and the weights (kernel 1), are compiled in
- * GMLS_TUNE_CANDIDATES row shapes for each row-count bin b (targets with
- * 64(b-1) < N <= 64b neighbours): G lanes per target and R rows per lane,
- * G*R >= 64b, listed in gmls_tune_result.  How fast a shape runs depends on
- * the neighbour counts, the cloud's order in memory and the functional count,
- * so it is measured rather than modelled.  Bin 5 holds the rows of more than
- * 256 neighbours, which the kernels take in chunks of G*R rows.
+ * Autotuner of the per-bin kernel shapes.  Targets are binned by row count
+ * (bin b: 64(b-1) < N <= 64b neighbours; bin 5: N > 256), and each tunable
+ * kernel is compiled in GMLS_TUNE_CANDIDATES shapes per bin, listed in
+ * gmls_tune_result.  How fast a shape runs depends on the neighbour counts,
+ * the cloud's order in memory and the functional count, so it is measured
+ * rather than modelled.  The kernels (index k of the result):
+ *   0 pipeline moments, 1 pipeline weights (mixed scheme 3): G lanes per
+ *     target and R rows per lane, G*R >= 64b (bin 5: chunks of G*R rows);
+ *   2 wavefront kernel (mixed scheme 4, one wavefront per target, b rows per
+ *     lane): the occupancy it is compiled for (waves per SIMD; 1 lifts the
+ *     register cap that 2 imposes) and the moments per LDS reduction round;
+ *   3 FP64 Householder QR (one persistent wavefront per target): rows per lane
+ *     R (a row of N > 64R is factored in chunks of 64R rows by the tall-skinny
+ *     QR) and persistent wavefronts per compute unit.
  *
- * gmls_autotune runs the stencil computation of gmls_stencils (prec =
- * GMLS_PREC_MIXED) on the given problem `reps` times per candidate (every bin
- * in the same candidate), brackets every per-bin launch of the two kernels
- * with HIP events, and keeps for each (kernel, bin) the candidate with the
- * smallest time (minimum over the repetitions) in the context's table, keyed
- * by (dim, order, basis); later calls with that key and GMLS_OPT_PIPE_SHAPE
- * -1 use it.  Bins without targets keep their previous entry.  Arguments are
- * those of gmls_stencils; `weights` (F*C_in*nnz doubles) and `target_status`
- * (uint8[n_tgt], nullable) receive the last run's result.  Synchronises the
- * context's stream.  Errors: GMLS_ERR_ARG for reps outside 1..100 or in
- * capture-safe mode; GMLS_ERR_UNSUPPORTED when the shape or the selected
- * scheme does not run the pipeline; otherwise those of gmls_stencils.  `out`
- * (host, nullable) receives the candidates, their times and the choice.
+ * gmls_autotune runs the call's stencil computation `reps` times per
+ * candidate (every bin in the same candidate) for each kernel the shape runs:
+ * the mixed scheme's (0 and 1, or 2, where it resolves to scheme 3 or 4) in
+ * GMLS_PREC_MIXED, and kernel 3 in GMLS_PREC_FP64.  It brackets every per-bin
+ * launch with HIP events and keeps for each (kernel, bin) the candidate with
+ * the smallest time (minimum over the repetitions) in the context's table,
+ * keyed by (dim, order, basis); later calls with that key use it unless
+ * GMLS_OPT_PIPE_SHAPE, GMLS_OPT_WAVE_SHAPE or GMLS_OPT_QR_SHAPE force a
+ * candidate.  Bins without targets keep their previous entry.
+ *   basis     GMLS_BASIS_SCALAR, GMLS_BASIS_DIVFREE, or GMLS_TUNE_SHARED: the
+ *             kernels that gmls_stencils_multi runs for a scalar and a
+ *             divergence-free set of one order on the same rows (kernels 2
+ *             and 3; each set's pipeline is tuned under its own basis);
+ *             functional_mask then holds the scalar set's mask in bits 0-3
+ *             and the divergence-free set's in bits 4-7
+ *   weights   F*C_in*nnz doubles (shared: the scalar set's F_s*nnz, then the
+ *             divergence-free set's F_v*dim*nnz); target_status uint8[n_tgt]
+ *             (shared: 2*n_tgt), nullable: the last run's result
+ * Other arguments are those of gmls_stencils.  Synchronises the context's
+ * stream.  Errors: GMLS_ERR_ARG for reps outside 1..100, a bad basis or mask,
+ * or capture-safe mode; GMLS_ERR_UNSUPPORTED when no kernel is compiled for
+ * the shape; otherwise those of gmls_stencils.  `out` (host, nullable)
+ * receives the candidates, their times and the choice.
  * -------------------------------------------------------------------------*/
-enum { GMLS_TUNE_BINS = 6, GMLS_TUNE_CANDIDATES = 3 };
+enum { GMLS_TUNE_BINS = 6, GMLS_TUNE_CANDIDATES = 3, GMLS_TUNE_KERNELS = 4, GMLS_TUNE_SHARED = 3 };
 typedef struct {
-  int32_t lanes[2][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES]; /* [kernel][bin][candidate]: G (bin 0 unused) */
-  int32_t rows[2][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];  /* R, rows per lane                         */
-  float ms[2][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];      /* best time per launch; 0 for an empty bin */
-  int32_t chosen[2][GMLS_TUNE_BINS];                      /* candidate kept; -1 for an empty bin      */
+  /* [kernel][bin][candidate]; bin 0 unused */
+  int32_t lanes[GMLS_TUNE_KERNELS][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];          /* per target         */
+  int32_t rows[GMLS_TUNE_KERNELS][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];           /* rows per lane      */
+  int32_t waves_per_simd[GMLS_TUNE_KERNELS][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES]; /* compiled-for
+                                                                                       occupancy (0: the
+                                                                                       compiler's)      */
+  int32_t lds_round[GMLS_TUNE_KERNELS][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];      /* moments per LDS
+                                                                                       round (0: none)  */
+  int32_t waves_per_cu[GMLS_TUNE_KERNELS][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];   /* persistent grid
+                                                                                       (0: not
+                                                                                       persistent)      */
+  float ms[GMLS_TUNE_KERNELS][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES]; /* best time per launch; 0 if not run */
+  int32_t chosen[GMLS_TUNE_KERNELS][GMLS_TUNE_BINS];                  /* candidate kept; -1 if not run     */
 } gmls_tune_result;
 
 gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets, int64_t n_tgt,
@@ -473,8 +501,11 @@ gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, con
                           uint8_t *target_status, gmls_tune_result *out);
 
 /* The context's autotune table as a JSON file: {"libgmls_autotune": 1,
- * "entries": [...]}, one object per tuned (dim, order, basis, kernel, bin)
- * with its "lanes" and "rows_per_lane", one object per line.  Load merges the
+ * "entries": [...]}, one object per tuned (dim, order, basis, kernel, bin),
+ * one per line, with the fields of the chosen shape in this order: "lanes"
+ * and "rows_per_lane"; then for kernel "wave" "waves_per_simd" and
+ * "lds_round", for kernel "qr" "waves_per_cu" (kernels "moments", "weights",
+ * "wave", "qr"; basis 2 is the staggered QR, 3 the shared kernels).  Load merges the
  * entries it names into the table; a file not in this format, or naming a
  * shape that is not compiled, returns GMLS_ERR_ARG and changes nothing.
  * Host only (no device work).  GMLS_ERR_ARG also when the file cannot be

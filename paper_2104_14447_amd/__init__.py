@@ -25,7 +25,8 @@ __all__ = [
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
     "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "OPT_ROW_ORDER", "ROW_ORDER_CELL",
     "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE", "SCHEME_WAVE",
-    "OPT_PIPE_SHAPE", "OPT_SOURCE_STRIDE", "gmls_neighbors_sorted", "TuneResult", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
+    "OPT_PIPE_SHAPE", "OPT_SOURCE_STRIDE", "OPT_WAVE_SHAPE", "OPT_QR_SHAPE", "TUNE_SHARED",
+    "gmls_neighbors_sorted", "TuneResult", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
     "StencilSet", "gmls_stencils_multi", "gmls_spmv_noalloc", "NOALLOC_SPMV_MAX_ROWS",
     "EXPORTED_SYMBOLS",
 ]
@@ -38,7 +39,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 SEARCH_KNN, SEARCH_RADIUS = 0, 1
 OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
 OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE, OPT_ROW_ORDER = 4, 5, 6, 7, 8
-OPT_PIPE_SHAPE, OPT_SOURCE_STRIDE = 9, 10
+OPT_PIPE_SHAPE, OPT_SOURCE_STRIDE, OPT_WAVE_SHAPE, OPT_QR_SHAPE = 9, 10, 11, 12
+TUNE_SHARED = 3  # gmls_autotune's basis for gmls_stencils_multi's shared kernels
 ROW_ORDER_CELL, ROW_ORDER_INDEX = 0, 1
 NOALLOC_SPMV_MAX_ROWS = 1 << 23  # rows gmls_spmv_noalloc takes (its static scratch)
 SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE, SCHEME_WAVE = 0, 1, 2, 3, 4
@@ -69,22 +71,34 @@ class StencilSet(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    """gmls_tune_result: [kernel 0 moments, 1 weights][bin][candidate]."""
-    _fields_ = [("lanes", ctypes.c_int32 * 3 * 6 * 2), ("rows", ctypes.c_int32 * 3 * 6 * 2),
-                ("ms", ctypes.c_float * 3 * 6 * 2), ("chosen", ctypes.c_int32 * 6 * 2)]
+    """gmls_tune_result: [kernel 0 moments, 1 weights, 2 wave, 3 qr][bin][candidate]."""
+    _fields_ = [(f, ctypes.c_int32 * 3 * 6 * 4) for f in ("lanes", "rows", "waves_per_simd", "lds_round",
+                                                           "waves_per_cu")] + \
+        [("ms", ctypes.c_float * 3 * 6 * 4), ("chosen", ctypes.c_int32 * 6 * 4)]
+    KERNELS = ("moments", "weights", "wave", "qr")
+
+    def shape(self, k, b, q):
+        """The candidate's distinguishing shape: (lanes, rows per lane) for the
+        pipeline, (waves per SIMD, moments per LDS round) for the wavefront
+        kernel, (rows per lane, waves per CU) for the QR kernel."""
+        if k < 2:
+            return (self.lanes[k][b][q], self.rows[k][b][q])
+        if k == 2:
+            return (self.waves_per_simd[k][b][q], self.lds_round[k][b][q])
+        return (self.rows[k][b][q], self.waves_per_cu[k][b][q])
 
     def as_dict(self):
         out = {}
-        for k, kname in enumerate(("moments", "weights")):
+        for k, kname in enumerate(self.KERNELS):
             bins = {}
             for b in range(1, 6):
                 c = self.chosen[k][b]
                 if c < 0:
                     continue
-                bins[b] = {"chosen": (self.lanes[k][b][c], self.rows[k][b][c]),
-                           "ms": {(self.lanes[k][b][q], self.rows[k][b][q]): round(self.ms[k][b][q], 4)
-                                  for q in range(3)}}
-            out[kname] = bins
+                bins[b] = {"chosen": self.shape(k, b, c), "candidate": c,
+                           "ms": {self.shape(k, b, q): round(self.ms[k][b][q], 4) for q in range(3)}}
+            if bins:
+                out[kname] = bins
         return out
 
 
@@ -376,17 +390,27 @@ def gmls_stencils_multi(ctx: Context, coords: torch.Tensor, targets: torch.Tenso
 
 def gmls_autotune(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, order: int, basis: int, mask: int,
                   weight_p: int, eps: torch.Tensor, row_ptr: torch.Tensor, col: torch.Tensor, reps: int = 3):
-    """Autotune the mixed pipeline's row shapes on this problem (the choice is
-    kept in the context).  Returns the tuning result as a dict."""
+    """Autotune the per-bin shapes of the kernels this problem runs (the
+    choice is kept in the context).  basis TUNE_SHARED tunes the shared
+    kernels of gmls_stencils_multi; mask then holds the scalar set's mask in
+    bits 0-3 and the divergence-free set's in bits 4-7.  Returns the tuning
+    result as a dict {kernel: {bin: {...}}}."""
     _check_dev(coords, targets, eps, row_ptr, col)
     n_src, dim = _source_shape(ctx, coords, targets)
     n_tgt = targets.shape[0]
-    F, C, _ = gmls_stencil_shape(dim, order, basis, mask)
-    weights = torch.empty(max(F * C * col.numel(), 1), dtype=torch.float64, device=coords.device)
+    if basis == TUNE_SHARED:
+        Fs, _, _ = gmls_stencil_shape(dim, order, BASIS_SCALAR, mask & 15)
+        Fv, Cv, _ = gmls_stencil_shape(dim, order, BASIS_DIVFREE, (mask >> 4) & 15)
+        nw, ns = (Fs + Fv * Cv) * col.numel(), 2 * n_tgt
+    else:
+        F, C, _ = gmls_stencil_shape(dim, order, basis, mask)
+        nw, ns = F * C * col.numel(), n_tgt
+    weights = torch.empty(max(nw, 1), dtype=torch.float64, device=coords.device)
+    status = torch.empty(max(ns, 1), dtype=torch.uint8, device=coords.device)
     res = TuneResult()
     st = load_library().gmls_autotune(ctx._h, _ptr(coords), n_src, _ptr(targets), n_tgt, dim, order, basis, mask,
-                                      weight_p, _ptr(eps), _ptr(row_ptr), _ptr(col), reps, _ptr(weights), None,
-                                      ctypes.byref(res))
+                                      weight_p, _ptr(eps), _ptr(row_ptr), _ptr(col), reps, _ptr(weights),
+                                      _ptr(status), ctypes.byref(res))
     if st != GMLS_OK:
         ctx._raise(st)
     return res.as_dict()

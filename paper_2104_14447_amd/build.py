@@ -37,7 +37,12 @@ def units():
             for basis in ((1, 0, 2) if stem == "qr" else (1, 0)):
                 for dim in (3, 2):
                     defs = [f"-DGMLS_DIM={dim}", f"-DGMLS_ORDER={order}", f"-DGMLS_BASIS={basis}"]
-                    out.append((f"{stem}_d{dim}_o{order}_b{basis}", unit, defs))
+                    name = f"{stem}_d{dim}_o{order}_b{basis}"
+                    if basis == 1 and stem in ("qr", "wave"):  # the shared kernels in an object of their own
+                        out.append((name + "_p0", unit, defs + ["-DGMLS_PART=0"]))
+                        out.append((name + "_p1", unit, defs + ["-DGMLS_PART=1"]))
+                    else:
+                        out.append((name, unit, defs))
     out += [
         ("search", "search.hip", ["-ffp-contract=off"]),
         ("stencil_bins", "stencil_bins.hip", []),

@@ -182,6 +182,12 @@ gmls_status gmls_set_option(gmls_ctx ctx, int option, double value) {
         return gmls_set_error(ctx, GMLS_ERR_ARG, "pipeline shape must be -1 (tuned) or a candidate 0..2");
       ctx->opt.pipe_force = (int)value;
       return GMLS_OK;
+    case GMLS_OPT_WAVE_SHAPE:
+    case GMLS_OPT_QR_SHAPE:
+      if (!(value == (double)(int)value && value >= -1 && value < kPipeCands))
+        return gmls_set_error(ctx, GMLS_ERR_ARG, "shape must be -1 (tuned) or a candidate 0..2");
+      (option == GMLS_OPT_WAVE_SHAPE ? ctx->opt.wave_force : ctx->opt.qr_force) = (int)value;
+      return GMLS_OK;
     case GMLS_OPT_SOURCE_STRIDE:
       if (!(value == (double)(int)value && value >= 0 && value <= 64))
         return gmls_set_error(ctx, GMLS_ERR_ARG, "source stride must be an integer in [0, 64]");
@@ -268,8 +274,6 @@ gmls_status gmls_neighbors_sorted(gmls_ctx ctx, const double *coords, int64_t n_
 
 }  // extern "C"
 
-// key of the autotune table
-static int tune_key(int dim, int order, int basis) { return (dim * 8 + order) * 4 + basis; }
 
 // Device buffers of a report: the per-target condition numbers of the mixed
 // kernels (NaN where none was computed) and the counters, both cleared.
@@ -340,6 +344,47 @@ static gmls_status report_end(gmls_ctx ctx, gmls_report *report, int n, const ui
 
 // plain (normals == nullptr), Neumann-constrained and staggered
 // (basis == kBasisStaggered) stencils
+// key of the autotune table
+static int tune_key(int dim, int order, int basis) { return (dim * 8 + order) * 4 + basis; }
+
+// The per-bin candidates of one call: forced by an option, else the tuned
+// table's entry under `key`, else candidate 0.  pipe_key: the key of the
+// pipeline's shapes (a shared call runs each set's own pipeline).
+static void resolve_shapes(gmls_ctx ctx, int key, int pipe_key, Options &o) {
+  const auto it = ctx->tune.find(key), ip = ctx->tune.find(pipe_key);
+  auto pick = [&](decltype(it) e, int k, int b, int force) -> signed char {
+    if (force >= 0) return (signed char)force;
+    if (e != ctx->tune.end() && e->second[k * 8 + b] >= 0) return e->second[k * 8 + b];
+    return 0;
+  };
+  for (int b = 0; b < 8; ++b) {
+    o.pipe_shape[0][b] = pick(ip, 0, b, o.pipe_force);
+    o.pipe_shape[1][b] = pick(ip, 1, b, o.pipe_force);
+    o.wave_shape[b] = pick(it, 2, b, o.wave_force);
+    o.qr_shape[b] = pick(it, 3, b, o.qr_force);
+  }
+}
+
+// The FP64 QR kernel on row-count bin b (scalar, divergence-free or
+// staggered; or, with av, both sets of a shared call) in the bin's shape,
+// bracketed by the autotuner's events when it is timing.
+static hipError_t qr_bin(gmls_ctx ctx, const Options &o, int dim, int order, int basis, int b, int cnt,
+                         const StencilArgs &a, const StencilArgs *av, const int *list, BinMeta *meta,
+                         hipStream_t s) {
+  const QrShape q = kQrShapes[b][o.qr_shape[b]];
+  const int nb = std::min(cnt, ctx->cus * q.per_cu);
+  PipeTimer *tm = ctx->timer;
+  hipError_t e = tm ? hipEventRecord(tm->ev[3][b][0], s) : hipSuccess;
+  if (e == hipSuccess)
+    e = av ? launch_qr_shared_bin(dim, order, b, q.rpl, a, *av, list, meta, nb, s)
+           : launch_qr_bin(dim, order, basis, b, q.rpl, a, list, meta, nb, s);
+  if (e == hipSuccess && tm) {
+    e = hipEventRecord(tm->ev[3][b][1], s);
+    tm->used[3][b] = 1;
+  }
+  return e;
+}
+
 static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets,
                                 int64_t n_tgt, int dim, int order, int basis, unsigned functional_mask, int weight_p,
                                 const double *eps, const int64_t *row_ptr, const int32_t *col,
@@ -451,6 +496,8 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
   if (report) GMLS_HIP(hipEventRecord(ctx->ev[1], s));
   if (!sync || hm.count[0] > 0) GMLS_HIP(launch_rank_deficient(a, C, list, meta, s));
   const int cus = ctx->cus;
+  // shapes of the pipeline, wavefront and QR kernels: forced, tuned or default
+  resolve_shapes(ctx, tune_key(dim, order, basis), tune_key(dim, order, mbasis), opt);
   if (prec == GMLS_PREC_MIXED && opt.scheme == MIXED_PIPE) {
     // moments [chunk][NM], solutions [chunk][F][Q] and records of one chunk of targets
     // (sized for every target, so that a capture-safe call finds the
@@ -465,30 +512,19 @@ static gmls_status run_stencils(gmls_ctx ctx, const double *coords, int64_t n_sr
     double *yb = (double *)ctx->ws(WS_PIPE_Y, sizeof(double) * (size_t)F * qy * cap);
     void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * cap);
     if (!mom || !yb || !rec) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
-    // row shapes of the moment and weight kernels: forced, tuned or default
-    const auto tuned = ctx->tune.find(tune_key(dim, order, mbasis));
-    for (int k = 0; k < 2; ++k)
-      for (int b = 0; b < 8; ++b) {
-        int c = 0;
-        if (opt.pipe_force >= 0)
-          c = opt.pipe_force;
-        else if (tuned != ctx->tune.end() && tuned->second[k * 8 + b] >= 0)
-          c = tuned->second[k * 8 + b];
-        opt.pipe_shape[k][b] = (signed char)c;
-      }
     if (n_work > 0)
       GMLS_HIP(launch_mixed_pipe(dim, order, mbasis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, mom, yb,
                                  rec, chunk, n, cus, ctx->timer, s));
   } else if (prec == GMLS_PREC_MIXED && opt.scheme == MIXED_WAVE) {
     if (!sync || hm.count[0] < n)
-      GMLS_HIP(launch_mixed_wave(dim, order, mbasis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, n, cus, s));
+      GMLS_HIP(launch_mixed_wave(dim, order, mbasis, a, list, sync ? &hm : nullptr, meta, fb, stats, opt, n, cus,
+                                 ctx->timer, s));
   } else {
     for (int b = 1; b < kNumBins; ++b) {
       if (sync && hm.count[b] == 0) continue;
       const int cnt = sync ? hm.count[b] : n;  // sizes the grid; the kernels read the count on the device
       if (prec == GMLS_PREC_FP64) {
-        const int nb = std::min(cnt, cus * 16);
-        GMLS_HIP(launch_qr_bin(dim, order, basis, b, a, list, meta, nb, s));
+        GMLS_HIP(qr_bin(ctx, opt, dim, order, basis, b, cnt, a, nullptr, list, meta, s));
       } else if (b == kLongBin) {  // the fused kernels hold at most 256 rows: FP64 QR in chunks
         GMLS_HIP(launch_defer_bin(a.status, list, meta, b, fb, &meta->fb_count, stats, s));
       } else {
@@ -542,6 +578,8 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
   const int n = (int)n_tgt;
   Options opt = ctx->opt;
   opt.scheme = scheme;
+  // the shared kernels' shapes (wavefront, QR) are tuned under their own key
+  resolve_shapes(ctx, tune_key(dim, order, kTuneShared), tune_key(dim, order, 0), opt);
   BinMeta *meta = (BinMeta *)ctx->ws(WS_BIN_META, sizeof(BinMeta));
   int *list = (int *)ctx->ws(WS_BIN_LIST, sizeof(int) * (size_t)n);
   int *fbs = (int *)ctx->ws(WS_FALLBACK, sizeof(int) * (size_t)n);
@@ -604,7 +642,7 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
   afv.ok_status = scheme < 0 ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
   if (!sync || hm.count[0] > 0) {
     GMLS_HIP(launch_rank_deficient(as, 1, list, meta, s));
-    GMLS_HIP(launch_qr_bin(dim, order, GMLS_BASIS_DIVFREE, 0, afv, list, meta, ctx->cus * 8, s));
+    GMLS_HIP(launch_qr_bin(dim, order, GMLS_BASIS_DIVFREE, 0, 4, afv, list, meta, ctx->cus * 8, s));
   }
   StencilArgs afs = as;
   afs.ok_status = -1;  // keep the fallback status set by the mixed kernel
@@ -614,12 +652,12 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
     for (int b = 1; b < kNumBins; ++b) {
       if (sync && hm.count[b] == 0) continue;
       const int cnt = sync ? hm.count[b] : n;  // sizes the grid; the kernel reads the count on the device
-      GMLS_HIP(launch_qr_shared_bin(dim, order, b, as, av, list, meta, std::min(cnt, ctx->cus * 16), s));
+      GMLS_HIP(qr_bin(ctx, opt, dim, order, 0, b, cnt, as, &av, list, meta, s));
     }
     if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
   } else if (scheme == MIXED_WAVE) {
     GMLS_HIP(launch_mixed_wave_shared(dim, order, as, fbs, &meta->fb_count, av, fbv, &meta->fb2_count, list,
-                                      sync ? &hm : nullptr, meta, stats, opt, n, ctx->cus, s));
+                                      sync ? &hm : nullptr, meta, stats, opt, n, ctx->cus, ctx->timer, s));
     if (report) GMLS_HIP(hipEventRecord(ctx->ev[2], s));
     GMLS_HIP(launch_qr_fallback(dim, order, GMLS_BASIS_SCALAR, afs, fbs, meta, 4, ctx->cus * 8, s));
   } else {
@@ -633,20 +671,9 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
     double *yv = (double *)ctx->ws(WS_PIPE_Y2, sizeof(double) * (size_t)av.F * dim * qs * n);
     void *rec = ctx->ws(WS_PIPE_REC, kPipeRecBytes * (size_t)n);
     if (!mom || !ys || !yv || !rec) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
-    Options os = opt, ov = opt;
-    for (int b = 0; b < 2; ++b) {
-      Options &o = b == 0 ? os : ov;
-      const auto tuned = ctx->tune.find(tune_key(dim, order, b));
-      for (int k = 0; k < 2; ++k)
-        for (int q = 0; q < 8; ++q) {
-          int c = 0;
-          if (o.pipe_force >= 0)
-            c = o.pipe_force;
-          else if (tuned != ctx->tune.end() && tuned->second[k * 8 + q] >= 0)
-            c = tuned->second[k * 8 + q];
-          o.pipe_shape[k][q] = (signed char)c;
-        }
-    }
+    Options os = opt, ov = opt;  // each set's own pipeline shapes
+    resolve_shapes(ctx, tune_key(dim, order, kTuneShared), tune_key(dim, order, 0), os);
+    resolve_shapes(ctx, tune_key(dim, order, kTuneShared), tune_key(dim, order, 1), ov);
     ov.reuse_moments = 1;
     GMLS_HIP(launch_mixed_pipe(dim, order, GMLS_BASIS_SCALAR, as, list, sync ? &hm : nullptr, meta, fbs, stats, os,
                                mom, ys, rec, n, n, ctx->cus, nullptr, s));
@@ -872,6 +899,37 @@ gmls_status gmls_apply(gmls_ctx ctx, int64_t n_tgt, const int64_t *row_ptr, cons
 // ---------------------------------------------------------------------------
 // autotuner of the pipeline's row shapes
 // ---------------------------------------------------------------------------
+// Candidates of every tunable kernel, as reported in gmls_tune_result.
+static void tune_candidates(gmls_tune_result *out) {
+  memset(out, 0, sizeof(*out));
+  for (int k = 0; k < GMLS_TUNE_KERNELS; ++k)
+    for (int b = 0; b < kNumBins; ++b) {
+      out->chosen[k][b] = -1;
+      if (b == 0) continue;
+      for (int c = 0; c < kPipeCands; ++c) {
+        int lanes = 64, rows = b, wps = 0, round = 0, per_cu = 0;
+        if (k < 2) {
+          lanes = kPipeShapes[b][c].g;
+          rows = kPipeShapes[b][c].rpl;
+          wps = k == 0 ? 2 : 0;
+          round = k == 0 ? 32 : 0;
+        } else if (k == 2) {
+          rows = b == kLongBin ? 0 : b;  // the long bin goes to the FP64 QR
+          wps = kWaveCand[c].wpe;
+          round = kWaveCand[c].rs;
+        } else {
+          rows = kQrShapes[b][c].rpl;
+          per_cu = kQrShapes[b][c].per_cu;
+        }
+        out->lanes[k][b][c] = lanes;
+        out->rows[k][b][c] = rows;
+        out->waves_per_simd[k][b][c] = wps;
+        out->lds_round[k][b][c] = round;
+        out->waves_per_cu[k][b][c] = per_cu;
+      }
+    }
+}
+
 gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, const double *targets, int64_t n_tgt,
                           int dim, int order, int basis, unsigned functional_mask, int weight_p, const double *eps,
                           const int64_t *row_ptr, const int32_t *col, int reps, double *weights,
@@ -881,33 +939,50 @@ gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, con
   if (reps < 1 || reps > 100) return gmls_set_error(ctx, GMLS_ERR_ARG, "reps must be in 1..100");
   if (ctx->opt.capture_safe)
     return gmls_set_error(ctx, GMLS_ERR_ARG, "the autotuner times its runs: not available in capture-safe mode");
-  if (basis != GMLS_BASIS_SCALAR && basis != GMLS_BASIS_DIVFREE)
-    return gmls_set_error(ctx, GMLS_ERR_ARG, "basis must be GMLS_BASIS_SCALAR or GMLS_BASIS_DIVFREE");
-  if (mixed_scheme(dim, order, basis, ctx->opt.scheme) != MIXED_PIPE)
-    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED,
-                          "the autotuner tunes the mixed pipeline (scheme 3), which this shape or the selected "
-                          "scheme does not run");
-  if (out) {
-    memset(out, 0, sizeof(*out));
-    for (int k = 0; k < 2; ++k)
-      for (int b = 0; b < kNumBins; ++b) {
-        out->chosen[k][b] = -1;
-        for (int c = 0; c < kPipeCands; ++c) {
-          out->lanes[k][b][c] = kPipeShapes[b][c].g;
-          out->rows[k][b][c] = kPipeShapes[b][c].rpl;
-        }
-      }
+  const bool shared = basis == GMLS_TUNE_SHARED;
+  if (basis != GMLS_BASIS_SCALAR && basis != GMLS_BASIS_DIVFREE && !shared)
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "basis must be GMLS_BASIS_SCALAR, GMLS_BASIS_DIVFREE or GMLS_TUNE_SHARED");
+  if (!qr_supported(dim, order, shared ? 1 : basis))
+    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "compiled kernels cover dim 2-3 and order 1-4");
+  // what each precision runs for this shape
+  int mixed = -1;  // the mixed scheme, when it is a tuned one
+  if (shared) {
+    const int s0 = mixed_scheme(dim, order, 0, ctx->opt.scheme), s1 = mixed_scheme(dim, order, 1, ctx->opt.scheme);
+    if (s0 == s1 && s0 == MIXED_WAVE) mixed = MIXED_WAVE;  // the shared pipeline runs each set's own shapes
+  } else {
+    const int sc = mixed_scheme(dim, order, basis, ctx->opt.scheme);
+    if (sc == MIXED_PIPE || sc == MIXED_WAVE) mixed = sc;
   }
+  gmls_stencil_set sets[2] = {};
+  if (shared) {
+    int Fs = 0, Fv = 0, Cv = 0;
+    const unsigned ms = functional_mask & 15u, mv = (functional_mask >> 4) & 15u;
+    if (gmls_stencil_shape(dim, order, GMLS_BASIS_SCALAR, ms, &Fs, nullptr, nullptr) != GMLS_OK ||
+        gmls_stencil_shape(dim, order, GMLS_BASIS_DIVFREE, mv, &Fv, &Cv, nullptr) != GMLS_OK ||
+        (functional_mask >> 8) != 0)
+      return gmls_set_error(ctx, GMLS_ERR_ARG, "shared tuning: scalar mask in bits 0-3, divergence-free in 4-7");
+    // the divergence-free set's weights follow the scalar set's F_s * nnz
+    int64_t tot = 0;
+    if (n_tgt > 0) {
+      if (!row_ptr) return gmls_set_error(ctx, GMLS_ERR_ARG, "null device pointer");
+      DeviceGuard g(ctx->device);
+      if (hipMemcpyAsync(&tot, row_ptr + n_tgt, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return gmls_set_error(ctx, GMLS_ERR_HIP, "reading row_ptr[n_tgt]");
+    }
+    sets[0] = {GMLS_BASIS_SCALAR, ms, weights, target_status};
+    sets[1] = {GMLS_BASIS_DIVFREE, mv, weights ? weights + (int64_t)Fs * tot : nullptr,
+               target_status ? target_status + n_tgt : nullptr};
+  }
+  if (out) tune_candidates(out);
   DeviceGuard g(ctx->device);
   PipeTimer tm;
   hipError_t he = hipSuccess;
-  for (int k = 0; k < 2 && he == hipSuccess; ++k)
+  for (int k = 0; k < 4 && he == hipSuccess; ++k)
     for (int b = 0; b < 8 && he == hipSuccess; ++b)
-      for (int e = 0; e < 2 && he == hipSuccess; ++e) {
-        he = hipEventCreate(&tm.ev[k][b][e]);
-      }
+      for (int e = 0; e < 2 && he == hipSuccess; ++e) he = hipEventCreate(&tm.ev[k][b][e]);
   auto destroy = [&]() {
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 4; ++k)
       for (int b = 0; b < 8; ++b)
         for (int e = 0; e < 2; ++e)
           if (tm.ev[k][b][e]) hipEventDestroy(tm.ev[k][b][e]);
@@ -918,43 +993,63 @@ gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, con
   }
   const Options saved = ctx->opt;
   ctx->opt.pipe_chunk = 0;  // one launch per bin
-  float best[2][8][kPipeCands];
-  bool seen[2][8] = {};
+  float best[4][8][kPipeCands];
+  bool seen[4][8] = {};
   for (auto &x : best)
     for (auto &y : x)
       for (auto &z : y) z = INFINITY;
+  // groups of kernels timed together: the pipeline's two (mixed), the
+  // wavefront kernel (mixed), the QR kernel (FP64)
+  struct Group {
+    int k0, k1, prec;
+  };
+  Group groups[2];
+  int ng = 0;
+  if (mixed == MIXED_PIPE) groups[ng++] = {0, 1, GMLS_PREC_MIXED};
+  if (mixed == MIXED_WAVE) groups[ng++] = {2, 2, GMLS_PREC_MIXED};
+  groups[ng++] = {3, 3, GMLS_PREC_FP64};
   gmls_status st = GMLS_OK;
-  for (int c = 0; c < kPipeCands && st == GMLS_OK; ++c) {
-    ctx->opt.pipe_force = c;
-    for (int r = 0; r < reps && st == GMLS_OK; ++r) {
-      memset(tm.used, 0, sizeof(tm.used));
-      ctx->timer = &tm;
-      st = run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, basis, functional_mask, weight_p, eps,
-                        row_ptr, col, nullptr, GMLS_PREC_MIXED, weights, nullptr, target_status, nullptr);
-      ctx->timer = nullptr;
-      if (st != GMLS_OK) break;
-      he = hipStreamSynchronize(ctx->stream);
-      if (he != hipSuccess) {
-        st = gmls_set_error(ctx, GMLS_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(he));
-        break;
-      }
-      for (int k = 0; k < 2; ++k)
-        for (int b = 1; b < kNumBins; ++b) {
-          if (!tm.used[k][b]) continue;
-          float ms = 0.f;
-          if (hipEventElapsedTime(&ms, tm.ev[k][b][0], tm.ev[k][b][1]) != hipSuccess) continue;
-          best[k][b][c] = std::min(best[k][b][c], ms);
-          seen[k][b] = true;
+  for (int gi = 0; gi < ng && st == GMLS_OK; ++gi) {
+    const Group &gr = groups[gi];
+    for (int c = 0; c < kPipeCands && st == GMLS_OK; ++c) {
+      ctx->opt.pipe_force = gr.k0 == 0 ? c : -1;
+      ctx->opt.wave_force = gr.k0 == 2 ? c : -1;
+      ctx->opt.qr_force = gr.k0 == 3 ? c : -1;
+      for (int r = 0; r < reps && st == GMLS_OK; ++r) {
+        memset(tm.used, 0, sizeof(tm.used));
+        ctx->timer = &tm;
+        if (shared)
+          st = run_shared(ctx, coords, n_src, targets, n_tgt, dim, order, weight_p, eps, row_ptr, col, sets[0],
+                          sets[1], gr.prec == GMLS_PREC_FP64 ? -1 : mixed, nullptr);
+        else
+          st = run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, basis, functional_mask, weight_p, eps,
+                            row_ptr, col, nullptr, gr.prec, weights, nullptr, target_status, nullptr);
+        ctx->timer = nullptr;
+        if (st == GMLS_WARN_TARGET_FLAGS) st = GMLS_OK;
+        if (st != GMLS_OK) break;
+        he = hipStreamSynchronize(ctx->stream);
+        if (he != hipSuccess) {
+          st = gmls_set_error(ctx, GMLS_ERR_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(he));
+          break;
         }
+        for (int k = gr.k0; k <= gr.k1; ++k)
+          for (int b = 1; b < kNumBins; ++b) {
+            if (!tm.used[k][b]) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, tm.ev[k][b][0], tm.ev[k][b][1]) != hipSuccess) continue;
+            best[k][b][c] = std::min(best[k][b][c], ms);
+            seen[k][b] = true;
+          }
+      }
     }
   }
   ctx->opt = saved;
   destroy();
   if (st != GMLS_OK) return st;
-  auto ins = ctx->tune.emplace(tune_key(dim, order, basis), std::array<signed char, 16>{});
+  auto ins = ctx->tune.emplace(tune_key(dim, order, shared ? kTuneShared : basis), std::array<signed char, 32>{});
   if (ins.second) ins.first->second.fill(-1);
   auto &ent = ins.first->second;
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 4; ++k)
     for (int b = 1; b < kNumBins; ++b) {
       if (!seen[k][b]) continue;
       int arg = 0;
@@ -969,25 +1064,31 @@ gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, con
   return GMLS_OK;
 }
 
+static const char *kTuneKernel[4] = {"moments", "weights", "wave", "qr"};
+
 gmls_status gmls_autotune_save(gmls_ctx ctx, const char *path) {
   if (!ctx) return GMLS_ERR_ARG;
   ctx->err.clear();
   if (!path) return gmls_set_error(ctx, GMLS_ERR_ARG, "null path");
   FILE *f = fopen(path, "w");
   if (!f) return gmls_set_error(ctx, GMLS_ERR_ARG, std::string("cannot open ") + path + " for writing");
-  static const char *kKernel[2] = {"moments", "weights"};
   fprintf(f, "{\"libgmls_autotune\": 1,\n \"entries\": [");
   bool first = true;
   for (const auto &kv : ctx->tune) {
     const int basis = kv.first % 4, order = (kv.first / 4) % 8, dim = kv.first / 32;
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 4; ++k)
       for (int b = 1; b < kNumBins; ++b) {
         const int c = kv.second[k * 8 + b];
         if (c < 0) continue;
+        const int lanes = k < 2 ? kPipeShapes[b][c].g : 64;
+        const int rows = k < 2 ? kPipeShapes[b][c].rpl : k == 2 ? b : kQrShapes[b][c].rpl;
         fprintf(f,
                 "%s\n  {\"dim\": %d, \"order\": %d, \"basis\": %d, \"kernel\": \"%s\", \"bin\": %d, \"lanes\": %d, "
-                "\"rows_per_lane\": %d}",
-                first ? "" : ",", dim, order, basis, kKernel[k], b, kPipeShapes[b][c].g, kPipeShapes[b][c].rpl);
+                "\"rows_per_lane\": %d",
+                first ? "" : ",", dim, order, basis, kTuneKernel[k], b, lanes, rows);
+        if (k == 2) fprintf(f, ", \"waves_per_simd\": %d, \"lds_round\": %d", kWaveCand[c].wpe, kWaveCand[c].rs);
+        if (k == 3) fprintf(f, ", \"waves_per_cu\": %d", kQrShapes[b][c].per_cu);
+        fprintf(f, "}");
         first = false;
       }
   }
@@ -1010,34 +1111,51 @@ gmls_status gmls_autotune_load(gmls_ctx ctx, const char *path) {
   fclose(f);
   if (text.find("\"libgmls_autotune\": 1") == std::string::npos)
     return gmls_set_error(ctx, GMLS_ERR_ARG, "not a libgmls autotune file (version 1)");
-  std::map<int, std::array<signed char, 16>> add;
+  std::map<int, std::array<signed char, 32>> add;
   size_t pos = 0;
   const std::string tag = "{\"dim\":";
   while ((pos = text.find(tag, pos)) != std::string::npos) {
     int dim = 0, order = 0, basis = 0, bin = 0, lanes = 0, rows = 0, used = 0;
     char kernel[16] = {0};
-    const int n = sscanf(text.c_str() + pos,
+    const char *at = text.c_str() + pos;
+    const int n = sscanf(at,
                          "{\"dim\": %d, \"order\": %d, \"basis\": %d, \"kernel\": \"%15[a-z]\", \"bin\": %d, "
-                         "\"lanes\": %d, \"rows_per_lane\": %d}%n",
+                         "\"lanes\": %d, \"rows_per_lane\": %d%n",
                          &dim, &order, &basis, kernel, &bin, &lanes, &rows, &used);
     if (n != 7 || used == 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "malformed autotune entry");
-    const int k = strcmp(kernel, "moments") == 0 ? 0 : strcmp(kernel, "weights") == 0 ? 1 : -1;
-    if (dim < 2 || dim > 3 || order < 1 || order > 4 || basis < 0 || basis > 1 || k < 0 || bin < 1 ||
-        bin >= kNumBins)
+    int k = -1;
+    for (int q = 0; q < 4; ++q)
+      if (strcmp(kernel, kTuneKernel[q]) == 0) k = q;
+    int wps = 0, round = 0, per_cu = 0, more = 0;
+    int m = -1;
+    if (k == 2)
+      m = sscanf(at + used, ", \"waves_per_simd\": %d, \"lds_round\": %d}%n", &wps, &round, &more) == 2 ? 0 : -1;
+    else if (k == 3)
+      m = sscanf(at + used, ", \"waves_per_cu\": %d}%n", &per_cu, &more) == 1 ? 0 : -1;
+    else if (k >= 0)
+      m = sscanf(at + used, "}%n", &more) == 0 ? 0 : -1;
+    if (k < 0 || m < 0 || more == 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "malformed autotune entry");
+    // the bases each kernel runs for: 0 scalar, 1 divergence-free, 2 staggered (QR), 3 shared
+    const bool basis_ok = k < 2 ? basis <= 1 : k == 2 ? basis != 2 : true;
+    if (dim < 2 || dim > 3 || order < 1 || order > 4 || basis < 0 || basis > 3 || !basis_ok || bin < 1 ||
+        bin >= kNumBins || (k == 2 && bin == kLongBin))
       return gmls_set_error(ctx, GMLS_ERR_ARG, "autotune entry out of range");
     int cand = -1;
-    for (int c = 0; c < kPipeCands; ++c)
-      if (kPipeShapes[bin][c].g == lanes && kPipeShapes[bin][c].rpl == rows) cand = c;
-    if (cand < 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "autotune entry names a row shape that is not compiled");
-    auto ins = add.emplace(tune_key(dim, order, basis), std::array<signed char, 16>{});
+    for (int c = 0; c < kPipeCands; ++c) {
+      if (k < 2 && kPipeShapes[bin][c].g == lanes && kPipeShapes[bin][c].rpl == rows) cand = c;
+      if (k == 2 && lanes == 64 && rows == bin && kWaveCand[c].wpe == wps && kWaveCand[c].rs == round) cand = c;
+      if (k == 3 && lanes == 64 && kQrShapes[bin][c].rpl == rows && kQrShapes[bin][c].per_cu == per_cu) cand = c;
+    }
+    if (cand < 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "autotune entry names a shape that is not compiled");
+    auto ins = add.emplace(tune_key(dim, order, basis), std::array<signed char, 32>{});
     if (ins.second) ins.first->second.fill(-1);
     ins.first->second[k * 8 + bin] = (signed char)cand;
-    pos += (size_t)used;
+    pos += (size_t)(used + more);
   }
   for (const auto &kv : add) {
     auto ins = ctx->tune.emplace(kv.first, kv.second);
     if (!ins.second)
-      for (int q = 0; q < 16; ++q)
+      for (int q = 0; q < 32; ++q)
         if (kv.second[q] >= 0) ins.first->second[q] = kv.second[q];
   }
   return GMLS_OK;

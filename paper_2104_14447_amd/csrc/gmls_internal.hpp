@@ -75,18 +75,24 @@ struct Options {
   int capture_safe = 0;              // nonzero: no call waits for the device (see libgmls.h)
   int row_order = 0;                 // radius rows: 0 cell order, 1 ascending source index
   int pipe_force = -1;               // pipeline row shape: -1 the tuned table, else this candidate
+  int wave_force = -1;               // wavefront-kernel variant: -1 the tuned table, else this candidate
+  int qr_force = -1;                 // FP64 QR shape: -1 the tuned table, else this candidate
   int source_stride = 0;             // doubles per source record of the stencil calls (0: dim)
   int reuse_moments = 0;             // per call: the pipeline's moments and records are already in place
   // per call: pipeline row-shape candidate of [kernel: 0 moments, 1 weights][bin]
   signed char pipe_shape[2][8] = {};
+  // per call: wavefront-kernel variant and FP64 QR shape of [bin]
+  signed char wave_shape[8] = {};
+  signed char qr_shape[8] = {};
 };
 
-// HIP events around every per-bin launch of the pipeline's moment and weight
-// kernels (the autotuner's measurement); used[k][b] is set for each launch
+// HIP events around every per-bin launch of the tunable kernels (the
+// autotuner's measurement: [0 pipeline moments, 1 pipeline weights,
+// 2 wavefront kernel, 3 FP64 QR][bin]); used[k][b] is set for each launch
 // recorded
 struct PipeTimer {
-  hipEvent_t ev[2][8][2] = {};
-  int used[2][8] = {};
+  hipEvent_t ev[4][8][2] = {};
+  int used[4][8] = {};
 };
 
 // Device error bits accumulated for gmls_check (capture-safe mode).
@@ -104,7 +110,10 @@ struct gmls_ctx_s {
   int cus = 256;  // compute units of the device
   // autotuned pipeline row shapes: key (dim * 8 + order) * 4 + basis ->
   // candidate of [kernel * 8 + bin], -1 where not tuned
-  std::map<int, std::array<signed char, 16>> tune;
+  // autotune table: (dim, order, basis) -> candidate of [kernel * 8 + bin]
+  // (kernels: 0 pipeline moments, 1 pipeline weights, 2 wavefront, 3 FP64 QR;
+  // -1 where nothing was tuned)
+  std::map<int, std::array<signed char, 32>> tune;
   gmls::PipeTimer *timer = nullptr;  // set by the autotuner around its runs
   double t_search_ms = 0.0;           // GPU time of the last synchronising gmls_neighbors call
 
@@ -192,8 +201,9 @@ struct StencilArgs {
   float *cond_out = nullptr;
 };
 
-// Per-bin stencil launches; `bin` selects the rows-per-lane instantiation.
-hipError_t launch_qr_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,
+// Per-bin stencil launches.  The FP64 QR kernel of bin `bin` runs with `rpl`
+// rows per lane (a row longer than 64 * rpl is factored in chunks).
+hipError_t launch_qr_bin(int dim, int order, int basis, int bin, int rpl, const StencilArgs &a, const int *list,
                          BinMeta *meta, int n_blocks, hipStream_t s);
 hipError_t launch_qr_fallback(int dim, int order, int basis, const StencilArgs &a, const int *list,
                               BinMeta *meta, int max_bin, int n_blocks, hipStream_t s);
@@ -212,7 +222,7 @@ hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a
 // one wavefront per target (bins launched as in launch_mixed_pipe)
 hipError_t launch_mixed_wave(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt, int n_max,
-                             int cus, hipStream_t s);
+                             int cus, PipeTimer *timer, hipStream_t s);
 // FP64 QR of the targets list[0 .. *count) (work counter *cursor), any row count
 hipError_t launch_qr_queue(int dim, int order, int basis, const StencilArgs &a, const int *list, const int *count,
                            int *cursor, int n_blocks, hipStream_t s);
@@ -221,10 +231,10 @@ hipError_t launch_qr_queue(int dim, int order, int basis, const StencilArgs &a, 
 hipError_t launch_mixed_wave_shared(int dim, int order, const StencilArgs &as, int *fbs, int *fbs_count,
                                     const StencilArgs &av, int *fbv, int *fbv_count, const int *list,
                                     const BinMeta *hm, BinMeta *meta, Stats *stats, const Options &opt, int n_max,
-                                    int cus, hipStream_t s);
+                                    int cus, PipeTimer *timer, hipStream_t s);
 // FP64 QR of bin `bin` for a scalar set (as) and a divergence-free set (av)
 // on the same neighbour lists: one Householder factor per target for both
-hipError_t launch_qr_shared_bin(int dim, int order, int bin, const StencilArgs &as, const StencilArgs &av,
+hipError_t launch_qr_shared_bin(int dim, int order, int bin, int rpl, const StencilArgs &as, const StencilArgs &av,
                                 const int *list, BinMeta *meta, int n_blocks, hipStream_t s);
 // the queued divergence-free targets of aux_list[0 .. *count)
 hipError_t launch_qr_kmat(int dim, int order, const StencilArgs &a, const int *list, const int *count,
@@ -321,6 +331,29 @@ constexpr int kPipeCands = 3;
 struct PipeShape {
   int g, rpl;
 };
+// FP64 QR shapes per bin: rows per lane (a row count above 64 * rpl is
+// factored in chunks by the tall-skinny QR) and persistent wavefronts per
+// compute unit
+struct QrShape {
+  int rpl, per_cu;
+};
+constexpr QrShape kQrShapes[kNumBins][kPipeCands] = {
+    {{4, 8}, {4, 8}, {4, 8}},  // bin 0: the divergence-free targets whose scalar basis is rank deficient
+    {{1, 16}, {1, 8}, {1, 32}},
+    {{2, 16}, {1, 16}, {2, 8}},
+    {{3, 16}, {2, 16}, {3, 8}},
+    {{4, 16}, {3, 16}, {2, 16}},
+    {{4, 16}, {3, 16}, {2, 16}}};
+// Compiled variants of the wavefront kernel (mixed scheme 4), selected per
+// row-count bin: the occupancy it is compiled for (waves per SIMD) and the
+// moments per LDS reduction round.
+struct WaveCand {
+  int wpe, rs;
+};
+constexpr int kWaveCands = 3;
+constexpr WaveCand kWaveCand[kWaveCands] = {{2, 16}, {1, 16}, {2, 8}};
+// key basis of the tuned shapes of gmls_stencils_multi's shared kernels
+constexpr int kTuneShared = 3;
 constexpr PipeShape kPipeShapes[kNumBins][kPipeCands] = {
     {{0, 0}, {0, 0}, {0, 0}},  // bin 0: rank deficient, never launched
     {{8, 8}, {16, 4}, {4, 16}},

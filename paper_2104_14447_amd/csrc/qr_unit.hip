@@ -7,6 +7,11 @@
 #if !defined(GMLS_DIM) || !defined(GMLS_ORDER) || !defined(GMLS_BASIS)
 #error "compile with -DGMLS_DIM=.. -DGMLS_ORDER=.. -DGMLS_BASIS=.."
 #endif
+// GMLS_PART 0: the per-basis kernel only; 1: the divergence-free unit's
+// queued and shared kernels only; undefined: both (objects build in parallel)
+#ifndef GMLS_PART
+#define GMLS_PART -1
+#endif
 
 #define GMLS_CAT2(a, b, c, d, e, f) a##b##c##d##e##f
 #define GMLS_CAT(a, b, c, d, e, f) GMLS_CAT2(a, b, c, d, e, f)
@@ -16,7 +21,8 @@
 
 namespace gmls {
 
-// one wavefront per target; rows per lane = bin (rows <= 64 * bin)
+#if GMLS_PART != 1
+// one wavefront per target, `rpl` rows per lane (longer rows in chunks)
 hipError_t GMLS_FN(int rpl, const StencilArgs &a, const int *list, const int *count, const int *offset, int *cursor,
                    int n_blocks, hipStream_t s) {
   constexpr int D = GMLS_DIM, O = GMLS_ORDER, B = GMLS_BASIS;
@@ -28,8 +34,9 @@ hipError_t GMLS_FN(int rpl, const StencilArgs &a, const int *list, const int *co
   }
   return hipGetLastError();
 }
+#endif
 
-#if GMLS_BASIS == 1
+#if GMLS_BASIS == 1 && GMLS_PART != 0
 // queued divergence-free targets (any row count up to 256: four rows per lane)
 hipError_t GMLS_KMAT_FN(const StencilArgs &a, const int *list, const int *count, int *cursor, int n_blocks,
                         hipStream_t s) {

@@ -97,10 +97,10 @@ static const SharedFn kShared[2][4] = {
     {launch_qr_shared_d2_o1, launch_qr_shared_d2_o2, launch_qr_shared_d2_o3, launch_qr_shared_d2_o4},
     {launch_qr_shared_d3_o1, launch_qr_shared_d3_o2, launch_qr_shared_d3_o3, launch_qr_shared_d3_o4}};
 
-hipError_t launch_qr_shared_bin(int dim, int order, int bin, const StencilArgs &as, const StencilArgs &av,
+hipError_t launch_qr_shared_bin(int dim, int order, int bin, int rpl, const StencilArgs &as, const StencilArgs &av,
                                 const int *list, BinMeta *meta, int n_blocks, hipStream_t s) {
   if (!qr_supported(dim, order, 1)) return hipErrorInvalidValue;
-  return kShared[dim - 2][order - 1](bin, as, av, list, meta->count + bin, meta->offset + bin, meta->cursor + bin,
+  return kShared[dim - 2][order - 1](rpl, as, av, list, meta->count + bin, meta->offset + bin, meta->cursor + bin,
                                      n_blocks, s);
 }
 
@@ -120,9 +120,9 @@ static hipError_t dispatch_qr(int dim, int order, int basis, int rpl, const Sten
   return kQr[dim - 2][order - 1][basis](rpl, a, list, count, offset, cursor, n_blocks, s);
 }
 
-hipError_t launch_qr_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,
+hipError_t launch_qr_bin(int dim, int order, int basis, int bin, int rpl, const StencilArgs &a, const int *list,
                          BinMeta *meta, int n_blocks, hipStream_t s) {
-  return dispatch_qr(dim, order, basis, bin, a, list, meta->count + bin, meta->offset + bin, meta->cursor + bin,
+  return dispatch_qr(dim, order, basis, rpl, a, list, meta->count + bin, meta->offset + bin, meta->cursor + bin,
                      n_blocks, s);
 }
 

@@ -80,70 +80,70 @@ static const PipeFn kPipe[2][4][2] = {
     {{launch_pipe_d3_o1_b0, launch_pipe_d3_o1_b1}, {launch_pipe_d3_o2_b0, launch_pipe_d3_o2_b1}, {launch_pipe_d3_o3_b0, launch_pipe_d3_o3_b1}, {launch_pipe_d3_o4_b0, launch_pipe_d3_o4_b1}}};
 
 hipError_t launch_wave_d2_o1_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d2_o1_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d2_o2_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d2_o2_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d2_o3_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d2_o3_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d2_o4_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d2_o4_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d3_o1_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d3_o1_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d3_o2_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d3_o2_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d3_o3_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d3_o3_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d3_o4_b0(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 hipError_t launch_wave_d3_o4_b1(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                                const Options &, int, int, hipStream_t);
+                                const Options &, int, int, PipeTimer *, hipStream_t);
 
 using WaveFn = hipError_t (*)(const StencilArgs &, const int *, const BinMeta *, BinMeta *, int *, Stats *,
-                              const Options &, int, int, hipStream_t);
+                              const Options &, int, int, PipeTimer *, hipStream_t);
 static const WaveFn kWave[2][4][2] = {
     {{launch_wave_d2_o1_b0, launch_wave_d2_o1_b1}, {launch_wave_d2_o2_b0, launch_wave_d2_o2_b1}, {launch_wave_d2_o3_b0, launch_wave_d2_o3_b1}, {launch_wave_d2_o4_b0, launch_wave_d2_o4_b1}},
     {{launch_wave_d3_o1_b0, launch_wave_d3_o1_b1}, {launch_wave_d3_o2_b0, launch_wave_d3_o2_b1}, {launch_wave_d3_o3_b0, launch_wave_d3_o3_b1}, {launch_wave_d3_o4_b0, launch_wave_d3_o4_b1}}};
 
 hipError_t launch_wave_shared_d2_o1(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *,
                                  const int *, const BinMeta *, BinMeta *, Stats *, const Options &, int, int,
-                                 hipStream_t);
+                                 PipeTimer *, hipStream_t);
 hipError_t launch_wave_shared_d2_o2(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *,
                                  const int *, const BinMeta *, BinMeta *, Stats *, const Options &, int, int,
-                                 hipStream_t);
+                                 PipeTimer *, hipStream_t);
 hipError_t launch_wave_shared_d2_o3(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *,
                                  const int *, const BinMeta *, BinMeta *, Stats *, const Options &, int, int,
-                                 hipStream_t);
+                                 PipeTimer *, hipStream_t);
 hipError_t launch_wave_shared_d2_o4(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *,
                                  const int *, const BinMeta *, BinMeta *, Stats *, const Options &, int, int,
-                                 hipStream_t);
+                                 PipeTimer *, hipStream_t);
 hipError_t launch_wave_shared_d3_o1(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *,
                                  const int *, const BinMeta *, BinMeta *, Stats *, const Options &, int, int,
-                                 hipStream_t);
+                                 PipeTimer *, hipStream_t);
 hipError_t launch_wave_shared_d3_o2(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *,
                                  const int *, const BinMeta *, BinMeta *, Stats *, const Options &, int, int,
-                                 hipStream_t);
+                                 PipeTimer *, hipStream_t);
 hipError_t launch_wave_shared_d3_o3(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *,
                                  const int *, const BinMeta *, BinMeta *, Stats *, const Options &, int, int,
-                                 hipStream_t);
+                                 PipeTimer *, hipStream_t);
 hipError_t launch_wave_shared_d3_o4(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *,
                                  const int *, const BinMeta *, BinMeta *, Stats *, const Options &, int, int,
-                                 hipStream_t);
+                                 PipeTimer *, hipStream_t);
 using SharedFn = hipError_t (*)(const StencilArgs &, int *, int *, const StencilArgs &, int *, int *, const int *,
-                                const BinMeta *, BinMeta *, Stats *, const Options &, int, int, hipStream_t);
+                                const BinMeta *, BinMeta *, Stats *, const Options &, int, int, PipeTimer *, hipStream_t);
 static const SharedFn kShared[2][4] = {
     {launch_wave_shared_d2_o1, launch_wave_shared_d2_o2, launch_wave_shared_d2_o3, launch_wave_shared_d2_o4},
     {launch_wave_shared_d3_o1, launch_wave_shared_d3_o2, launch_wave_shared_d3_o3, launch_wave_shared_d3_o4}};
@@ -186,19 +186,19 @@ hipError_t launch_mixed_pipe(int dim, int order, int basis, const StencilArgs &a
 
 hipError_t launch_mixed_wave(int dim, int order, int basis, const StencilArgs &a, const int *list,
                              const BinMeta *hm, BinMeta *meta, int *fb, Stats *stats, const Options &opt, int n_max,
-                             int cus, hipStream_t s) {
+                             int cus, PipeTimer *timer, hipStream_t s) {
   if (mixed_scheme(dim, order, basis, MIXED_WAVE) != MIXED_WAVE) return hipErrorInvalidValue;
-  return kWave[dim - 2][order - 1][basis](a, list, hm, meta, fb, stats, opt, n_max, cus, s);
+  return kWave[dim - 2][order - 1][basis](a, list, hm, meta, fb, stats, opt, n_max, cus, timer, s);
 }
 
 hipError_t launch_mixed_wave_shared(int dim, int order, const StencilArgs &as, int *fbs, int *fbs_count,
                                     const StencilArgs &av, int *fbv, int *fbv_count, const int *list,
                                     const BinMeta *hm, BinMeta *meta, Stats *stats, const Options &opt, int n_max,
-                                    int cus, hipStream_t s) {
+                                    int cus, PipeTimer *timer, hipStream_t s) {
   if (mixed_scheme(dim, order, 0, MIXED_WAVE) != MIXED_WAVE || mixed_scheme(dim, order, 1, MIXED_WAVE) != MIXED_WAVE)
     return hipErrorInvalidValue;
   return kShared[dim - 2][order - 1](as, fbs, fbs_count, av, fbv, fbv_count, list, hm, meta, stats, opt, n_max, cus,
-                                     s);
+                                     timer, s);
 }
 
 hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,

@@ -145,38 +145,39 @@ __device__ __forceinline__ bool sweep_inverse(double (&a)[Q], double *col, doubl
 }
 
 // Moments mu_g (lexicographic order) of the rows held by the wavefront into
-// mu[]; red is the LDS reduction buffer (64 x 17 doubles).  One step per
+// mu[]; red is the LDS reduction buffer (64 x (RS + 1) doubles).  One step per
 // moment, unrolled by template recursion so that every exponent, register
-// index and round boundary is a compile-time constant.
-constexpr int kWaveRound = 16;  // moments per LDS reduction round
+// index and round boundary is a compile-time constant.  RS moments go
+// through LDS per round (8, 16 or 32: the autotuner's choice, a trade of
+// registers and LDS for barriers).
 
 // sum one round over the wavefront: every lane stores its partials, then
-// lanes q + 16 p add rows 16p..16p+15 of column q and two butterfly steps
-// combine the four quarters (fixed order)
-template <int NM>
-__device__ __forceinline__ void wave_round(const double (&acc)[kWaveRound], int g0, double *red, double *mu) {
-  constexpr int RS = kWaveRound;
+// lanes q + RS p add rows RS p .. RS p + RS - 1 of column q and butterfly
+// steps combine the 64 / RS parts (fixed order)
+template <int NM, int RS>
+__device__ __forceinline__ void wave_round(const double (&acc)[RS], int g0, double *red, double *mu) {
+  static_assert(RS == 8 || RS == 16 || RS == 32, "round size");
   const int lane = lane_id();
 #pragma unroll
   for (int q = 0; q < RS; ++q) red[lane * (RS + 1) + q] = acc[q];
   __syncthreads();
-  const int q = lane & (RS - 1), part = lane >> 4;
+  const int q = lane & (RS - 1), part = lane / RS;
   double t = 0.0;
 #pragma unroll
-  for (int l = 0; l < 16; ++l) t += red[(part * 16 + l) * (RS + 1) + q];
-  t += __shfl_xor(t, 16);
-  t += __shfl_xor(t, 32);
+  for (int l = 0; l < RS; ++l) t += red[(part * RS + l) * (RS + 1) + q];
+#pragma unroll
+  for (int o = RS; o < 64; o <<= 1) t += __shfl_xor(t, o);
   if (lane < RS && g0 + lane < NM) mu[g0 + lane] = t;
   __syncthreads();
 }
 
-template <int DIM, int ORDER, int RPL, int G>
+template <int DIM, int ORDER, int RPL, int RS, int G>
 struct WaveMoment {
   static constexpr int D2 = 2 * ORDER;
   static constexpr int NM = num_mono(DIM, D2);
   // wab = w s_x^a [s_y^b] of the current prefix, pl = powers of the last coordinate
   static __device__ __forceinline__ void run(const double (&s)[RPL][DIM], const double (&pl)[RPL][D2 + 1],
-                                             double (&wa)[RPL], double (&wab)[RPL], double (&acc)[kWaveRound],
+                                             double (&wa)[RPL], double (&wab)[RPL], double (&acc)[RS],
                                              double *red, double *mu) {
     constexpr LexMoments<DIM, D2> LM{};
     constexpr int ey = LM.e[G][1];
@@ -200,13 +201,13 @@ struct WaveMoment {
     double v = 0.0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) v = fma(wab[r], pl[r][el], v);
-    acc[G % kWaveRound] = v;
-    if constexpr (G % kWaveRound == kWaveRound - 1 || G == NM - 1) wave_round<NM>(acc, G - G % kWaveRound, red, mu);
-    if constexpr (G + 1 < NM) WaveMoment<DIM, ORDER, RPL, G + 1>::run(s, pl, wa, wab, acc, red, mu);
+    acc[G % RS] = v;
+    if constexpr (G % RS == RS - 1 || G == NM - 1) wave_round<NM, RS>(acc, G - G % RS, red, mu);
+    if constexpr (G + 1 < NM) WaveMoment<DIM, ORDER, RPL, RS, G + 1>::run(s, pl, wa, wab, acc, red, mu);
   }
 };
 
-template <int DIM, int ORDER, int RPL>
+template <int DIM, int ORDER, int RPL, int RS>
 __device__ __forceinline__ void wave_moments(const double (&s)[RPL][DIM], const double (&w)[RPL], double *red,
                                              double *mu) {
   constexpr int D2 = 2 * ORDER;
@@ -219,8 +220,8 @@ __device__ __forceinline__ void wave_moments(const double (&s)[RPL][DIM], const 
     wa[r] = w[r];
     wab[r] = w[r];
   }
-  double acc[kWaveRound];
-  WaveMoment<DIM, ORDER, RPL, 0>::run(s, pl, wa, wab, acc, red, mu);
+  double acc[RS];
+  WaveMoment<DIM, ORDER, RPL, RS, 0>::run(s, pl, wa, wab, acc, red, mu);
 }
 
 // sum_q e[q] Dg_q lambda_q over the nonzero entries lambda_q of a functional
@@ -410,14 +411,16 @@ __device__ __forceinline__ bool wave_divfree_rows(const StencilArgs &av, const R
 // neighbour lists: the moments and the swept Gram are formed once per target
 // for both sets (Section 2.2: the divergence-free fit is the scalar fit under
 // D c = 0, so both take the same G).
-template <int DIM, int ORDER, int BASIS, int RPL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_wave(
+// CAND: the compiled variant (kWaveCand).
+template <int DIM, int ORDER, int BASIS, int RPL, int CAND>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaveCand[CAND].wpe))) void k_wave(
     WaveSet ss, WaveSet sv, const int *list, BinMeta *meta, int bin, Stats *stats, Options opt) {
   constexpr bool SCAL = BASIS == 0 || BASIS == 3, DIVF = BASIS == 1 || BASIS == 3;
   constexpr int QS = num_mono(DIM, ORDER);
   constexpr int NM = num_mono(DIM, 2 * ORDER);
   constexpr int QM = ORDER >= 1 ? num_mono(DIM, ORDER - 1) : 1;
-  constexpr int RED = 64 * 17;
+  constexpr int RS = kWaveCand[CAND].rs;
+  constexpr int RED = 64 * (RS + 1);
   constexpr int BIG = (DIVF && QS * QS > RED) ? QS * QS : RED;
   static_assert(QS <= 64, "one basis function per lane");
   __shared__ double big[BIG];      // moment reduction, then (divergence-free) -E^-1
@@ -457,7 +460,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 #pragma unroll
       for (int r = 0; r < RPL; ++r) w[r] = row_sw<DIM>(xs[r], xt, ie, a.p, lane + 64 * r < N, s[r]);
     }
-    wave_moments<DIM, ORDER, RPL>(s, w, big, mu);
+    wave_moments<DIM, ORDER, RPL, RS>(s, w, big, mu);
 
     // equilibrated Gram, row `lane` (lanes >= QS hold zeros; li keeps their
     // table reads in bounds)
@@ -527,7 +530,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_
 // targets, its bounds read on the device.
 template <int DIM, int ORDER, int BASIS>
 hipError_t launch_wave(const WaveSet &ss, const WaveSet &sv, const int *list, const BinMeta *hm, BinMeta *meta,
-                       Stats *stats, const Options &opt, int n_max, int cus, hipStream_t s) {
+                       Stats *stats, const Options &opt, int n_max, int cus, PipeTimer *timer, hipStream_t s) {
   for (int b = 1; b < kNumBins; ++b) {
     int cnt = n_max;
     if (hm) {
@@ -547,11 +550,27 @@ hipError_t launch_wave(const WaveSet &ss, const WaveSet &sv, const int *list, co
     }
     int nb = cnt < cus * 16 ? cnt : cus * 16;
     nb = xcd_grid(nb);
-    switch (b) {
-      case 1: k_wave<DIM, ORDER, BASIS, 1><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt); break;
-      case 2: k_wave<DIM, ORDER, BASIS, 2><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt); break;
-      case 3: k_wave<DIM, ORDER, BASIS, 3><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt); break;
-      default: k_wave<DIM, ORDER, BASIS, 4><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt); break;
+    const int c = opt.wave_shape[b] >= 0 && opt.wave_shape[b] < kWaveCands ? opt.wave_shape[b] : 0;
+    if (timer) {
+      const hipError_t e = hipEventRecord(timer->ev[2][b][0], s);
+      if (e != hipSuccess) return e;
+    }
+    switch (b * 4 + c) {
+#define GMLS_WAVE_CASE(B_, C_)                                                                                  \
+  case B_ * 4 + C_:                                                                                             \
+    k_wave<DIM, ORDER, BASIS, B_, C_><<<nb, 64, 0, s>>>(ss, sv, list, meta, b, stats, opt);                     \
+    break;
+      GMLS_WAVE_CASE(1, 0) GMLS_WAVE_CASE(1, 1) GMLS_WAVE_CASE(1, 2)
+      GMLS_WAVE_CASE(2, 0) GMLS_WAVE_CASE(2, 1) GMLS_WAVE_CASE(2, 2)
+      GMLS_WAVE_CASE(3, 0) GMLS_WAVE_CASE(3, 1) GMLS_WAVE_CASE(3, 2)
+      GMLS_WAVE_CASE(4, 0) GMLS_WAVE_CASE(4, 1) GMLS_WAVE_CASE(4, 2)
+#undef GMLS_WAVE_CASE
+      default: return hipErrorInvalidValue;
+    }
+    if (timer) {
+      const hipError_t e = hipEventRecord(timer->ev[2][b][1], s);
+      if (e != hipSuccess) return e;
+      timer->used[2][b] = 1;
     }
   }
   return hipGetLastError();

@@ -8,6 +8,11 @@
 #if !defined(GMLS_DIM) || !defined(GMLS_ORDER) || !defined(GMLS_BASIS)
 #error "compile with -DGMLS_DIM=.. -DGMLS_ORDER=.. -DGMLS_BASIS=.."
 #endif
+// GMLS_PART 0: the per-basis launcher only; 1: the shared launcher only;
+// undefined: both (objects build in parallel)
+#ifndef GMLS_PART
+#define GMLS_PART -1
+#endif
 
 #define GMLS_CAT2(a, b, c, d, e, f) a##b##c##d##e##f
 #define GMLS_CAT(a, b, c, d, e, f) GMLS_CAT2(a, b, c, d, e, f)
@@ -16,19 +21,21 @@
 
 namespace gmls {
 
+#if GMLS_PART != 1
 hipError_t GMLS_WAVE_FN(const StencilArgs &a, const int *list, const BinMeta *hm, BinMeta *meta, int *fb,
-                        Stats *stats, const Options &opt, int n_max, int cus, hipStream_t s) {
+                        Stats *stats, const Options &opt, int n_max, int cus, PipeTimer *timer, hipStream_t s) {
   const WaveSet one{a, fb, &meta->fb_count};
-  return launch_wave<GMLS_DIM, GMLS_ORDER, GMLS_BASIS>(one, one, list, hm, meta, stats, opt, n_max, cus, s);
+  return launch_wave<GMLS_DIM, GMLS_ORDER, GMLS_BASIS>(one, one, list, hm, meta, stats, opt, n_max, cus, timer, s);
 }
+#endif
 
-#if GMLS_BASIS == 1
+#if GMLS_BASIS == 1 && GMLS_PART != 0
 // a scalar and a divergence-free set on the same neighbour lists, one pass
 hipError_t GMLS_SHARED_FN(const StencilArgs &as, int *fbs, int *fbs_count, const StencilArgs &av, int *fbv,
                           int *fbv_count, const int *list, const BinMeta *hm, BinMeta *meta, Stats *stats,
-                          const Options &opt, int n_max, int cus, hipStream_t s) {
+                          const Options &opt, int n_max, int cus, PipeTimer *timer, hipStream_t s) {
   const WaveSet ss{as, fbs, fbs_count}, sv{av, fbv, fbv_count};
-  return launch_wave<GMLS_DIM, GMLS_ORDER, 3>(ss, sv, list, hm, meta, stats, opt, n_max, cus, s);
+  return launch_wave<GMLS_DIM, GMLS_ORDER, 3>(ss, sv, list, hm, meta, stats, opt, n_max, cus, timer, s);
 }
 #endif
 

@@ -139,3 +139,29 @@ def test_long_rows_staggered_and_constrained():
     errs = row_errors(sub(host(gw), F), ow, srp, F, 1)
     flush(f"  max rel err {errs.max():.3e}")
     assert errs.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("cand", [1, 2])
+@pytest.mark.parametrize("basis,order,mask", [("scalar", 3, 1 | 4), ("divfree", 2, 1 | 4 | 8)],
+                         ids=["scalar3", "divfree2"])
+def test_long_rows_every_qr_shape(basis, order, mask, cand):
+    """The FP64 QR kernel's other shapes (fewer rows per lane, so that every
+    bin's rows, and the long rows, are factored in more chunks)."""
+    G = require_gpu()
+    pts, rp, col, eps = gpu_rows()
+    b = G.BASIS_SCALAR if basis == "scalar" else G.BASIS_DIVFREE
+    c = ctx()
+    c.set_option(G.OPT_QR_SHAPE, cand)
+    s = dev(pts)
+    flush(f"long rows {basis} m={order} fp64 QR shape {cand}")
+    try:
+        gw, gst, _ = G.gmls_stencils(c, s, s, order, b, mask, 4, dev(eps), dev(rp), dev(col), prec=G.PREC_FP64)
+    finally:
+        c.set_option(G.OPT_QR_SHAPE, -1)
+    gw, gst = host(gw), host(gst)
+    w, st, F, C = oracle.stencils(pts, pts, order, basis, mask, 4, eps, rp, col)
+    assert np.array_equal(gst, st)
+    zero = (F - 1,) if basis == "divfree" and mask & 8 else ()
+    errs = row_errors(gw, w, rp, F, C, zero_rows=zero)[st != 1]
+    flush(f"  max rel err {errs.max():.3e}")
+    assert errs.max() <= FP64_TOL
