@@ -424,6 +424,8 @@ def main():
                 order_t, b_t = (bs["order"] + 1, G.BASIS_SCALAR) if bs["name"] == "staggered" \
                     else (bs["order"], bs["b"])
                 jobs.append((bs["name"], order_t, b_t, bs["mask"]))
+                if bs["name"] == "staggered":  # its FP64 QR kernel has a key of its own
+                    jobs.append(("staggered-qr", bs["order"], G.TUNE_STAGGERED, bs["mask"]))
             if shared:
                 ms_ = [bs["mask"] for bs in bases if bs["name"] == "scalar"][0]
                 mv_ = [bs["mask"] for bs in bases if bs["name"] == "divfree"][0]
@@ -435,7 +437,7 @@ def main():
                     if e.status != G.GMLS_ERR_UNSUPPORTED:  # no tunable kernel compiled for the shape
                         raise
                     continue
-                tune_summary[name_t] = {k_: {b: "%dx%d" % v["chosen"] for b, v in d.items()}
+                tune_summary[name_t] = {k_: {b: "x".join(str(u) for u in v["chosen"]) for b, v in d.items()}
                                         for k_, d in res.items()}
             print(f"# autotune: {tune_summary} ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
             if tune_summary:

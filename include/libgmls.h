@@ -452,7 +452,8 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
  *     register cap that 2 imposes) and the moments per LDS reduction round;
  *   3 FP64 Householder QR (one persistent wavefront per target): rows per lane
  *     R (a row of N > 64R is factored in chunks of 64R rows by the tall-skinny
- *     QR) and persistent wavefronts per compute unit.
+ *     QR), persistent wavefronts per compute unit, and the occupancy it is
+ *     compiled for (the compiler's choice, or two waves per SIMD).
  *
  * gmls_autotune runs the call's stencil computation `reps` times per
  * candidate (every bin in the same candidate) for each kernel the shape runs:
@@ -468,9 +469,14 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
  *             divergence-free set of one order on the same rows (kernels 2
  *             and 3; each set's pipeline is tuned under its own basis);
  *             functional_mask then holds the scalar set's mask in bits 0-3
- *             and the divergence-free set's in bits 4-7
+ *             and the divergence-free set's in bits 4-7; or
+ *             GMLS_TUNE_STAGGERED: the FP64 QR kernel of
+ *             gmls_stencils_staggered (kernel 3 only; its mixed pipeline
+ *             takes the shapes tuned for the scalar basis of order + 1), with
+ *             `order` and functional_mask as that call takes them
  *   weights   F*C_in*nnz doubles (shared: the scalar set's F_s*nnz, then the
- *             divergence-free set's F_v*dim*nnz); target_status uint8[n_tgt]
+ *             divergence-free set's F_v*dim*nnz; staggered: F*nnz, the target
+ *             weights go to a workspace); target_status uint8[n_tgt]
  *             (shared: 2*n_tgt), nullable: the last run's result
  * Other arguments are those of gmls_stencils.  Synchronises the context's
  * stream.  Errors: GMLS_ERR_ARG for reps outside 1..100, a bad basis or mask,
@@ -478,7 +484,13 @@ gmls_status gmls_stencils_multi(gmls_ctx ctx, const double *coords, int64_t n_sr
  * the shape; otherwise those of gmls_stencils.  `out` (host, nullable)
  * receives the candidates, their times and the choice.
  * -------------------------------------------------------------------------*/
-enum { GMLS_TUNE_BINS = 6, GMLS_TUNE_CANDIDATES = 3, GMLS_TUNE_KERNELS = 4, GMLS_TUNE_SHARED = 3 };
+enum {
+  GMLS_TUNE_BINS = 6,
+  GMLS_TUNE_CANDIDATES = 3,
+  GMLS_TUNE_KERNELS = 4,
+  GMLS_TUNE_STAGGERED = 2,
+  GMLS_TUNE_SHARED = 3
+};
 typedef struct {
   /* [kernel][bin][candidate]; bin 0 unused */
   int32_t lanes[GMLS_TUNE_KERNELS][GMLS_TUNE_BINS][GMLS_TUNE_CANDIDATES];          /* per target         */
@@ -504,7 +516,8 @@ gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, con
  * "entries": [...]}, one object per tuned (dim, order, basis, kernel, bin),
  * one per line, with the fields of the chosen shape in this order: "lanes"
  * and "rows_per_lane"; then for kernel "wave" "waves_per_simd" and
- * "lds_round", for kernel "qr" "waves_per_cu" (kernels "moments", "weights",
+ * "lds_round", for kernel "qr" "waves_per_simd" (0: the compiler's choice)
+ * and "waves_per_cu" (kernels "moments", "weights",
  * "wave", "qr"; basis 2 is the staggered QR, 3 the shared kernels).  Load merges the
  * entries it names into the table; a file not in this format, or naming a
  * shape that is not compiled, returns GMLS_ERR_ARG and changes nothing.

@@ -25,7 +25,7 @@ __all__ = [
     "OPT_COND_THRESHOLD", "OPT_MAX_SWEEPS", "OPT_REFINE_TOL", "OPT_FORCE_FALLBACK", "OPT_MIXED_SCHEME",
     "OPT_PIPE_CHUNK", "OPT_RADIUS_SCRATCH_MB", "OPT_CAPTURE_SAFE", "OPT_ROW_ORDER", "ROW_ORDER_CELL",
     "ROW_ORDER_INDEX", "SCHEME_AUTO", "SCHEME_ROWS", "SCHEME_GRAM", "SCHEME_PIPE", "SCHEME_WAVE",
-    "OPT_PIPE_SHAPE", "OPT_SOURCE_STRIDE", "OPT_WAVE_SHAPE", "OPT_QR_SHAPE", "TUNE_SHARED",
+    "OPT_PIPE_SHAPE", "OPT_SOURCE_STRIDE", "OPT_WAVE_SHAPE", "OPT_QR_SHAPE", "TUNE_SHARED", "TUNE_STAGGERED",
     "gmls_neighbors_sorted", "TuneResult", "gmls_autotune", "gmls_autotune_save", "gmls_autotune_load",
     "StencilSet", "gmls_stencils_multi", "gmls_spmv_noalloc", "NOALLOC_SPMV_MAX_ROWS",
     "EXPORTED_SYMBOLS",
@@ -40,7 +40,8 @@ SEARCH_KNN, SEARCH_RADIUS = 0, 1
 OPT_COND_THRESHOLD, OPT_MAX_SWEEPS, OPT_REFINE_TOL, OPT_FORCE_FALLBACK = 0, 1, 2, 3
 OPT_MIXED_SCHEME, OPT_PIPE_CHUNK, OPT_RADIUS_SCRATCH_MB, OPT_CAPTURE_SAFE, OPT_ROW_ORDER = 4, 5, 6, 7, 8
 OPT_PIPE_SHAPE, OPT_SOURCE_STRIDE, OPT_WAVE_SHAPE, OPT_QR_SHAPE = 9, 10, 11, 12
-TUNE_SHARED = 3  # gmls_autotune's basis for gmls_stencils_multi's shared kernels
+TUNE_STAGGERED, TUNE_SHARED = 2, 3  # gmls_autotune's basis for gmls_stencils_staggered's QR kernel,
+# and for gmls_stencils_multi's shared kernels
 ROW_ORDER_CELL, ROW_ORDER_INDEX = 0, 1
 NOALLOC_SPMV_MAX_ROWS = 1 << 23  # rows gmls_spmv_noalloc takes (its static scratch)
 SCHEME_AUTO, SCHEME_ROWS, SCHEME_GRAM, SCHEME_PIPE, SCHEME_WAVE = 0, 1, 2, 3, 4
@@ -80,12 +81,13 @@ class TuneResult(ctypes.Structure):
     def shape(self, k, b, q):
         """The candidate's distinguishing shape: (lanes, rows per lane) for the
         pipeline, (waves per SIMD, moments per LDS round) for the wavefront
-        kernel, (rows per lane, waves per CU) for the QR kernel."""
+        kernel, (rows per lane, waves per SIMD compiled for (0: the
+        compiler's choice), waves per CU) for the QR kernel."""
         if k < 2:
             return (self.lanes[k][b][q], self.rows[k][b][q])
         if k == 2:
             return (self.waves_per_simd[k][b][q], self.lds_round[k][b][q])
-        return (self.rows[k][b][q], self.waves_per_cu[k][b][q])
+        return (self.rows[k][b][q], self.waves_per_simd[k][b][q], self.waves_per_cu[k][b][q])
 
     def as_dict(self):
         out = {}
@@ -393,7 +395,8 @@ def gmls_autotune(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, ord
     """Autotune the per-bin shapes of the kernels this problem runs (the
     choice is kept in the context).  basis TUNE_SHARED tunes the shared
     kernels of gmls_stencils_multi; mask then holds the scalar set's mask in
-    bits 0-3 and the divergence-free set's in bits 4-7.  Returns the tuning
+    bits 0-3 and the divergence-free set's in bits 4-7.  basis TUNE_STAGGERED
+    tunes the QR kernel of gmls_stencils_staggered (order: its vector order).  Returns the tuning
     result as a dict {kernel: {bin: {...}}}."""
     _check_dev(coords, targets, eps, row_ptr, col)
     n_src, dim = _source_shape(ctx, coords, targets)
@@ -402,6 +405,8 @@ def gmls_autotune(ctx: Context, coords: torch.Tensor, targets: torch.Tensor, ord
         Fs, _, _ = gmls_stencil_shape(dim, order, BASIS_SCALAR, mask & 15)
         Fv, Cv, _ = gmls_stencil_shape(dim, order, BASIS_DIVFREE, (mask >> 4) & 15)
         nw, ns = (Fs + Fv * Cv) * col.numel(), 2 * n_tgt
+    elif basis == TUNE_STAGGERED:
+        nw, ns = ((dim if mask & F_GRAD else 0) + (1 if mask & F_LAPLACIAN else 0)) * col.numel(), n_tgt
     else:
         F, C, _ = gmls_stencil_shape(dim, order, basis, mask)
         nw, ns = F * C * col.numel(), n_tgt

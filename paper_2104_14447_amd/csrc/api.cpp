@@ -376,8 +376,8 @@ static hipError_t qr_bin(gmls_ctx ctx, const Options &o, int dim, int order, int
   PipeTimer *tm = ctx->timer;
   hipError_t e = tm ? hipEventRecord(tm->ev[3][b][0], s) : hipSuccess;
   if (e == hipSuccess)
-    e = av ? launch_qr_shared_bin(dim, order, b, q.rpl, a, *av, list, meta, nb, s)
-           : launch_qr_bin(dim, order, basis, b, q.rpl, a, list, meta, nb, s);
+    e = av ? launch_qr_shared_bin(dim, order, b, q.rpl, q.wpe, a, *av, list, meta, nb, s)
+           : launch_qr_bin(dim, order, basis, b, q.rpl, q.wpe, a, list, meta, nb, s);
   if (e == hipSuccess && tm) {
     e = hipEventRecord(tm->ev[3][b][1], s);
     tm->used[3][b] = 1;
@@ -642,7 +642,7 @@ static gmls_status run_shared(gmls_ctx ctx, const double *coords, int64_t n_src,
   afv.ok_status = scheme < 0 ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
   if (!sync || hm.count[0] > 0) {
     GMLS_HIP(launch_rank_deficient(as, 1, list, meta, s));
-    GMLS_HIP(launch_qr_bin(dim, order, GMLS_BASIS_DIVFREE, 0, 4, afv, list, meta, ctx->cus * 8, s));
+    GMLS_HIP(launch_qr_bin(dim, order, GMLS_BASIS_DIVFREE, 0, 4, 0, afv, list, meta, ctx->cus * 8, s));
   }
   StencilArgs afs = as;
   afs.ok_status = -1;  // keep the fallback status set by the mixed kernel
@@ -920,6 +920,7 @@ static void tune_candidates(gmls_tune_result *out) {
         } else {
           rows = kQrShapes[b][c].rpl;
           per_cu = kQrShapes[b][c].per_cu;
+          wps = kQrShapes[b][c].wpe;
         }
         out->lanes[k][b][c] = lanes;
         out->rows[k][b][c] = rows;
@@ -939,17 +940,29 @@ gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, con
   if (reps < 1 || reps > 100) return gmls_set_error(ctx, GMLS_ERR_ARG, "reps must be in 1..100");
   if (ctx->opt.capture_safe)
     return gmls_set_error(ctx, GMLS_ERR_ARG, "the autotuner times its runs: not available in capture-safe mode");
-  const bool shared = basis == GMLS_TUNE_SHARED;
-  if (basis != GMLS_BASIS_SCALAR && basis != GMLS_BASIS_DIVFREE && !shared)
-    return gmls_set_error(ctx, GMLS_ERR_ARG, "basis must be GMLS_BASIS_SCALAR, GMLS_BASIS_DIVFREE or GMLS_TUNE_SHARED");
-  if (!qr_supported(dim, order, shared ? 1 : basis))
+  const bool shared = basis == GMLS_TUNE_SHARED, stag = basis == GMLS_TUNE_STAGGERED;
+  if (basis != GMLS_BASIS_SCALAR && basis != GMLS_BASIS_DIVFREE && !shared && !stag)
+    return gmls_set_error(ctx, GMLS_ERR_ARG,
+                          "basis must be GMLS_BASIS_SCALAR, GMLS_BASIS_DIVFREE, GMLS_TUNE_SHARED or GMLS_TUNE_STAGGERED");
+  if (stag && (functional_mask == 0 || (functional_mask & ~(unsigned)(GMLS_F_GRAD | GMLS_F_LAPLACIAN))))
+    return gmls_set_error(ctx, GMLS_ERR_ARG, "staggered tuning: GMLS_F_GRAD and/or GMLS_F_LAPLACIAN");
+  if (stag && (order < 0 || order > 3))
+    return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "staggered vector order must be 0..3");
+  if (!qr_supported(dim, stag ? order + 1 : order, shared ? 1 : stag ? kBasisStaggered : basis))
     return gmls_set_error(ctx, GMLS_ERR_UNSUPPORTED, "compiled kernels cover dim 2-3 and order 1-4");
+  // staggered: the target weights go to a workspace
+  double *hw = nullptr;
+  if (stag && n_tgt > 0) {
+    const int F = (functional_mask & GMLS_F_GRAD ? dim : 0) + (functional_mask & GMLS_F_LAPLACIAN ? 1 : 0);
+    hw = (double *)ctx->ws(WS_TUNE_AUX, sizeof(double) * (size_t)F * (size_t)n_tgt);
+    if (!hw) return gmls_set_error(ctx, GMLS_ERR_NOMEM, "device workspace allocation failed");
+  }
   // what each precision runs for this shape
   int mixed = -1;  // the mixed scheme, when it is a tuned one
   if (shared) {
     const int s0 = mixed_scheme(dim, order, 0, ctx->opt.scheme), s1 = mixed_scheme(dim, order, 1, ctx->opt.scheme);
     if (s0 == s1 && s0 == MIXED_WAVE) mixed = MIXED_WAVE;  // the shared pipeline runs each set's own shapes
-  } else {
+  } else if (!stag) {  // a staggered call's pipeline is tuned as the scalar basis of order + 1
     const int sc = mixed_scheme(dim, order, basis, ctx->opt.scheme);
     if (sc == MIXED_PIPE || sc == MIXED_WAVE) mixed = sc;
   }
@@ -1021,6 +1034,9 @@ gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, con
         if (shared)
           st = run_shared(ctx, coords, n_src, targets, n_tgt, dim, order, weight_p, eps, row_ptr, col, sets[0],
                           sets[1], gr.prec == GMLS_PREC_FP64 ? -1 : mixed, nullptr);
+        else if (stag)
+          st = run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order + 1, kBasisStaggered, functional_mask,
+                            weight_p, eps, row_ptr, col, nullptr, GMLS_PREC_FP64, weights, hw, target_status, nullptr);
         else
           st = run_stencils(ctx, coords, n_src, targets, n_tgt, dim, order, basis, functional_mask, weight_p, eps,
                             row_ptr, col, nullptr, gr.prec, weights, nullptr, target_status, nullptr);
@@ -1046,7 +1062,8 @@ gmls_status gmls_autotune(gmls_ctx ctx, const double *coords, int64_t n_src, con
   ctx->opt = saved;
   destroy();
   if (st != GMLS_OK) return st;
-  auto ins = ctx->tune.emplace(tune_key(dim, order, shared ? kTuneShared : basis), std::array<signed char, 32>{});
+  const int key = stag ? tune_key(dim, order + 1, kBasisStaggered) : tune_key(dim, order, shared ? kTuneShared : basis);
+  auto ins = ctx->tune.emplace(key, std::array<signed char, 32>{});
   if (ins.second) ins.first->second.fill(-1);
   auto &ent = ins.first->second;
   for (int k = 0; k < 4; ++k)
@@ -1087,7 +1104,8 @@ gmls_status gmls_autotune_save(gmls_ctx ctx, const char *path) {
                 "\"rows_per_lane\": %d",
                 first ? "" : ",", dim, order, basis, kTuneKernel[k], b, lanes, rows);
         if (k == 2) fprintf(f, ", \"waves_per_simd\": %d, \"lds_round\": %d", kWaveCand[c].wpe, kWaveCand[c].rs);
-        if (k == 3) fprintf(f, ", \"waves_per_cu\": %d", kQrShapes[b][c].per_cu);
+        if (k == 3)
+          fprintf(f, ", \"waves_per_simd\": %d, \"waves_per_cu\": %d", kQrShapes[b][c].wpe, kQrShapes[b][c].per_cu);
         fprintf(f, "}");
         first = false;
       }
@@ -1131,7 +1149,8 @@ gmls_status gmls_autotune_load(gmls_ctx ctx, const char *path) {
     if (k == 2)
       m = sscanf(at + used, ", \"waves_per_simd\": %d, \"lds_round\": %d}%n", &wps, &round, &more) == 2 ? 0 : -1;
     else if (k == 3)
-      m = sscanf(at + used, ", \"waves_per_cu\": %d}%n", &per_cu, &more) == 1 ? 0 : -1;
+      m = sscanf(at + used, ", \"waves_per_simd\": %d, \"waves_per_cu\": %d}%n", &wps, &per_cu, &more) == 2 ? 0
+                                                                                                         : -1;
     else if (k >= 0)
       m = sscanf(at + used, "}%n", &more) == 0 ? 0 : -1;
     if (k < 0 || m < 0 || more == 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "malformed autotune entry");
@@ -1144,7 +1163,9 @@ gmls_status gmls_autotune_load(gmls_ctx ctx, const char *path) {
     for (int c = 0; c < kPipeCands; ++c) {
       if (k < 2 && kPipeShapes[bin][c].g == lanes && kPipeShapes[bin][c].rpl == rows) cand = c;
       if (k == 2 && lanes == 64 && rows == bin && kWaveCand[c].wpe == wps && kWaveCand[c].rs == round) cand = c;
-      if (k == 3 && lanes == 64 && kQrShapes[bin][c].rpl == rows && kQrShapes[bin][c].per_cu == per_cu) cand = c;
+      if (k == 3 && lanes == 64 && kQrShapes[bin][c].rpl == rows && kQrShapes[bin][c].per_cu == per_cu &&
+          kQrShapes[bin][c].wpe == wps)
+        cand = c;
     }
     if (cand < 0) return gmls_set_error(ctx, GMLS_ERR_ARG, "autotune entry names a shape that is not compiled");
     auto ins = add.emplace(tune_key(dim, order, basis), std::array<signed char, 32>{});

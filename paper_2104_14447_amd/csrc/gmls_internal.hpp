@@ -54,6 +54,7 @@ enum Slot {
   WS_COND,
   WS_REPORT,
   WS_SRC_POS,
+  WS_TUNE_AUX,
   WS_NUM_SLOTS
 };
 
@@ -202,9 +203,10 @@ struct StencilArgs {
 };
 
 // Per-bin stencil launches.  The FP64 QR kernel of bin `bin` runs with `rpl`
-// rows per lane (a row longer than 64 * rpl is factored in chunks).
-hipError_t launch_qr_bin(int dim, int order, int basis, int bin, int rpl, const StencilArgs &a, const int *list,
-                         BinMeta *meta, int n_blocks, hipStream_t s);
+// rows per lane (a row longer than 64 * rpl is factored in chunks); wpe 2
+// selects its variant compiled for two waves per SIMD.
+hipError_t launch_qr_bin(int dim, int order, int basis, int bin, int rpl, int wpe, const StencilArgs &a,
+                         const int *list, BinMeta *meta, int n_blocks, hipStream_t s);
 hipError_t launch_qr_fallback(int dim, int order, int basis, const StencilArgs &a, const int *list,
                               BinMeta *meta, int max_bin, int n_blocks, hipStream_t s);
 hipError_t launch_mixed_bin(int dim, int order, int basis, int bin, const StencilArgs &a, const int *list,
@@ -234,8 +236,8 @@ hipError_t launch_mixed_wave_shared(int dim, int order, const StencilArgs &as, i
                                     int cus, PipeTimer *timer, hipStream_t s);
 // FP64 QR of bin `bin` for a scalar set (as) and a divergence-free set (av)
 // on the same neighbour lists: one Householder factor per target for both
-hipError_t launch_qr_shared_bin(int dim, int order, int bin, int rpl, const StencilArgs &as, const StencilArgs &av,
-                                const int *list, BinMeta *meta, int n_blocks, hipStream_t s);
+hipError_t launch_qr_shared_bin(int dim, int order, int bin, int rpl, int wpe, const StencilArgs &as,
+                                const StencilArgs &av, const int *list, BinMeta *meta, int n_blocks, hipStream_t s);
 // the queued divergence-free targets of aux_list[0 .. *count)
 hipError_t launch_qr_kmat(int dim, int order, const StencilArgs &a, const int *list, const int *count,
                           int *cursor, int n_blocks, hipStream_t s);
@@ -332,18 +334,19 @@ struct PipeShape {
   int g, rpl;
 };
 // FP64 QR shapes per bin: rows per lane (a row count above 64 * rpl is
-// factored in chunks by the tall-skinny QR) and persistent wavefronts per
-// compute unit
+// factored in chunks by the tall-skinny QR), persistent wavefronts per
+// compute unit, and the occupancy the kernel is compiled for (0: the
+// compiler's choice; 2: at most 256 registers, two waves per SIMD)
 struct QrShape {
-  int rpl, per_cu;
+  int rpl, per_cu, wpe;
 };
 constexpr QrShape kQrShapes[kNumBins][kPipeCands] = {
-    {{4, 8}, {4, 8}, {4, 8}},  // bin 0: the divergence-free targets whose scalar basis is rank deficient
-    {{1, 16}, {1, 8}, {1, 32}},
-    {{2, 16}, {1, 16}, {2, 8}},
-    {{3, 16}, {2, 16}, {3, 8}},
-    {{4, 16}, {3, 16}, {2, 16}},
-    {{4, 16}, {3, 16}, {2, 16}}};
+    {{4, 8, 0}, {4, 8, 0}, {4, 8, 0}},  // bin 0: divergence-free targets whose scalar basis is rank deficient
+    {{1, 16, 0}, {1, 8, 0}, {1, 16, 2}},
+    {{2, 16, 0}, {1, 16, 0}, {2, 16, 2}},
+    {{3, 16, 0}, {2, 16, 0}, {3, 16, 2}},
+    {{4, 16, 0}, {3, 16, 0}, {4, 16, 2}},
+    {{4, 16, 0}, {3, 16, 0}, {2, 16, 0}}};
 // Compiled variants of the wavefront kernel (mixed scheme 4), selected per
 // row-count bin: the occupancy it is compiled for (waves per SIMD) and the
 // moments per LDS reduction round.

@@ -17,8 +17,8 @@ constexpr int qr_lds_doubles() {
 
 // Persistent kernel: waves take targets from list[0 .. *count) in turn.
 template <int DIM, int ORDER, int BASIS, int RPL>
-__global__ __launch_bounds__(64) void k_qr(StencilArgs a, const int *list, const int *count, const int *offset,
-                                           int *cursor) {
+__device__ __forceinline__ void qr_loop(const StencilArgs &a, const int *list, const int *count, const int *offset,
+                                        int *cursor) {
   __shared__ double lds[qr_lds_doubles<DIM, ORDER, BASIS>()];
   const RowKinds rk = row_kinds(DIM, BASIS == 1 ? 1 : 0, a.mask);
   const int n = readfirstlane_i(*count);
@@ -38,6 +38,21 @@ __global__ __launch_bounds__(64) void k_qr(StencilArgs a, const int *list, const
   }
 }
 
+template <int DIM, int ORDER, int BASIS, int RPL>
+__global__ __launch_bounds__(64) void k_qr(StencilArgs a, const int *list, const int *count, const int *offset,
+                                           int *cursor) {
+  qr_loop<DIM, ORDER, BASIS, RPL>(a, list, count, offset, cursor);
+}
+
+// The same kernel compiled for two waves per SIMD (at most 256 registers):
+// an autotuner candidate for the instantiations that the compiler gives
+// slightly more than 256 registers, and so one wave per SIMD.
+template <int DIM, int ORDER, int BASIS, int RPL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_qr_w2(
+    StencilArgs a, const int *list, const int *count, const int *offset, int *cursor) {
+  qr_loop<DIM, ORDER, BASIS, RPL>(a, list, count, offset, cursor);
+}
+
 // A scalar set (as) and a divergence-free set (av) of the same order on the
 // same neighbour rows: both fits are taken through the Householder factor R
 // of the scalar sample matrix sqrt(W) P, which is computed once per target
@@ -45,8 +60,8 @@ __global__ __launch_bounds__(64) void k_qr(StencilArgs a, const int *list, const
 // per-set steps are those of k_qr, so the weights equal those of two k_qr
 // calls bit for bit.
 template <int DIM, int ORDER, int RPL>
-__global__ __launch_bounds__(64) void k_qr_shared(StencilArgs as, StencilArgs av, const int *list, const int *count,
-                                                  const int *offset, int *cursor) {
+__device__ __forceinline__ void qr_shared_loop(const StencilArgs &as, const StencilArgs &av, const int *list,
+                                               const int *count, const int *offset, int *cursor) {
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int LS = qr_lds_doubles<DIM, ORDER, 0>(), LV = qr_lds_doubles<DIM, ORDER, 1>();
   __shared__ double lds[LS > LV ? LS : LV];
@@ -70,6 +85,18 @@ __global__ __launch_bounds__(64) void k_qr_shared(StencilArgs as, StencilArgs av
     qr_scalar_solve<DIM, ORDER, RPL>(as, rks, t, r, M[0], rdiag, lds);
     qr_divfree_solve<DIM, ORDER, RPL, true>(av, rkv, t, r, M[0], rdiag, lds);
   }
+}
+
+template <int DIM, int ORDER, int RPL>
+__global__ __launch_bounds__(64) void k_qr_shared(StencilArgs as, StencilArgs av, const int *list, const int *count,
+                                                  const int *offset, int *cursor) {
+  qr_shared_loop<DIM, ORDER, RPL>(as, av, list, count, offset, cursor);
+}
+
+template <int DIM, int ORDER, int RPL>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void k_qr_shared_w2(
+    StencilArgs as, StencilArgs av, const int *list, const int *count, const int *offset, int *cursor) {
+  qr_shared_loop<DIM, ORDER, RPL>(as, av, list, count, offset, cursor);
 }
 
 }  // namespace gmls

@@ -22,14 +22,19 @@
 namespace gmls {
 
 #if GMLS_PART != 1
-// one wavefront per target, `rpl` rows per lane (longer rows in chunks)
-hipError_t GMLS_FN(int rpl, const StencilArgs &a, const int *list, const int *count, const int *offset, int *cursor,
-                   int n_blocks, hipStream_t s) {
+// one wavefront per target, `rpl` rows per lane (longer rows in chunks);
+// wpe 2: the variant compiled for two waves per SIMD
+hipError_t GMLS_FN(int rpl, int wpe, const StencilArgs &a, const int *list, const int *count, const int *offset,
+                   int *cursor, int n_blocks, hipStream_t s) {
   constexpr int D = GMLS_DIM, O = GMLS_ORDER, B = GMLS_BASIS;
-  switch (rpl) {
+  switch ((rpl < 1 || rpl > 4 ? 4 : rpl) + (wpe == 2 ? 4 : 0)) {
     case 1: k_qr<D, O, B, 1><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
     case 2: k_qr<D, O, B, 2><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
     case 3: k_qr<D, O, B, 3><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
+    case 5: k_qr_w2<D, O, B, 1><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
+    case 6: k_qr_w2<D, O, B, 2><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
+    case 7: k_qr_w2<D, O, B, 3><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
+    case 8: k_qr_w2<D, O, B, 4><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
     default: k_qr<D, O, B, 4><<<n_blocks, 64, 0, s>>>(a, list, count, offset, cursor); break;
   }
   return hipGetLastError();
@@ -45,13 +50,17 @@ hipError_t GMLS_KMAT_FN(const StencilArgs &a, const int *list, const int *count,
 }
 
 // a scalar and a divergence-free set from one factor per target
-hipError_t GMLS_SHARED_FN(int rpl, const StencilArgs &as, const StencilArgs &av, const int *list, const int *count,
-                          const int *offset, int *cursor, int n_blocks, hipStream_t s) {
+hipError_t GMLS_SHARED_FN(int rpl, int wpe, const StencilArgs &as, const StencilArgs &av, const int *list,
+                          const int *count, const int *offset, int *cursor, int n_blocks, hipStream_t s) {
   constexpr int D = GMLS_DIM, O = GMLS_ORDER;
-  switch (rpl) {
+  switch ((rpl < 1 || rpl > 4 ? 4 : rpl) + (wpe == 2 ? 4 : 0)) {
     case 1: k_qr_shared<D, O, 1><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
     case 2: k_qr_shared<D, O, 2><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
     case 3: k_qr_shared<D, O, 3><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
+    case 5: k_qr_shared_w2<D, O, 1><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
+    case 6: k_qr_shared_w2<D, O, 2><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
+    case 7: k_qr_shared_w2<D, O, 3><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
+    case 8: k_qr_shared_w2<D, O, 4><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
     default: k_qr_shared<D, O, 4><<<n_blocks, 64, 0, s>>>(as, av, list, count, offset, cursor); break;
   }
   return hipGetLastError();

@@ -81,7 +81,8 @@ def test_autotune_then_stencils_and_json_round_trip(tmp_path):
     assert len(doc["entries"]) == 3 * len(bins)
     for e in doc["entries"]:
         assert (e["dim"], e["order"], e["basis"]) == (3, order, 0)
-        shape = (e["rows_per_lane"], e["waves_per_cu"]) if e["kernel"] == "qr" else (e["lanes"], e["rows_per_lane"])
+        shape = (e["rows_per_lane"], e["waves_per_simd"], e["waves_per_cu"]) if e["kernel"] == "qr" else \
+            (e["lanes"], e["rows_per_lane"])
         assert shape == res[e["kernel"]][e["bin"]]["chosen"]
     c2 = G.Context(0)
     G.gmls_autotune_load(c2, str(path))
@@ -116,7 +117,10 @@ def test_autotune_arguments():
         G.gmls_autotune(c, s, s, order, G.BASIS_SCALAR, mask, p, de, drp, dcol, reps=0)
     assert e.value.status == 1
     with pytest.raises(G.GmlsError) as e:  # not a basis
-        G.gmls_autotune(c, s, s, order, 2, mask, p, de, drp, dcol)
+        G.gmls_autotune(c, s, s, order, 5, mask, p, de, drp, dcol)
+    assert e.value.status == 1
+    with pytest.raises(G.GmlsError) as e:  # staggered: gradient and Laplacian only
+        G.gmls_autotune(c, s, s, 2, G.TUNE_STAGGERED, G.F_VALUE, p, de, drp, dcol)
     assert e.value.status == 1
     with pytest.raises(G.GmlsError) as e:  # shared: a mask beyond bits 0-7
         G.gmls_autotune(c, s, s, order, G.TUNE_SHARED, 1 << 9, p, de, drp, dcol)
@@ -249,7 +253,7 @@ def test_autotune_shared_and_wave_json(tmp_path):
     for e in doc["entries"]:
         r = res if e["basis"] == 3 else res1
         shape = (e["waves_per_simd"], e["lds_round"]) if e["kernel"] == "wave" else \
-            (e["rows_per_lane"], e["waves_per_cu"])
+            (e["rows_per_lane"], e["waves_per_simd"], e["waves_per_cu"])
         assert shape == r[e["kernel"]][e["bin"]]["chosen"]
     c2 = G.Context(0)
     G.gmls_autotune_load(c2, str(path))

@@ -42,13 +42,21 @@ def cond_reduced(src, tgt, rp, col, eps, dim, m):
     return out
 
 
-@pytest.mark.parametrize("dim,m,k,n_tgt", [(2, 1, 16, 300), (2, 2, 30, 300), (2, 3, 45, 257), (3, 0, 12, 200),
-                                           (3, 1, 30, 300), (3, 2, 60, 300), (3, 3, 110, 130)])
-def test_staggered_parity(dim, m, k, n_tgt):
+@pytest.mark.parametrize("dim,m,k,n_tgt,qr", [(2, 1, 16, 300, -1), (2, 2, 30, 300, -1), (2, 3, 45, 257, -1),
+                                              (3, 0, 12, 200, -1), (3, 1, 30, 300, -1), (3, 2, 60, 300, -1),
+                                              (3, 3, 110, 130, -1), (3, 2, 60, 300, 1), (3, 2, 60, 300, 2),
+                                              (3, 3, 110, 130, 1), (3, 3, 110, 130, 2), (2, 3, 45, 257, 2)])
+def test_staggered_parity(dim, m, k, n_tgt, qr):
+    """qr: the FP64 QR kernel's shape candidate (-1: the default)."""
     G = require_gpu()
     src, tgt, rp, col, eps = case(dim, k, n_tgt, 60 + m)
-    flush(f"staggered dim={dim} m={m} k={k} n_tgt={n_tgt}")
-    w, tw, st, _ = G.gmls_stencils_staggered(ctx(), dev(src), dev(tgt), m, GRAD_LAP, 4, dev(eps), dev(rp), dev(col))
+    flush(f"staggered dim={dim} m={m} k={k} n_tgt={n_tgt} qr shape {qr}")
+    c = ctx()
+    c.set_option(G.OPT_QR_SHAPE, qr)
+    try:
+        w, tw, st, _ = G.gmls_stencils_staggered(c, dev(src), dev(tgt), m, GRAD_LAP, 4, dev(eps), dev(rp), dev(col))
+    finally:
+        c.set_option(G.OPT_QR_SHAPE, -1)
     w, tw, st = host(w), host(tw), host(st)
     ow, ob, F = S.stencils_staggered(src, tgt, m, GRAD_LAP, 4, eps, rp, col)
     assert (st == 0).all()
@@ -133,3 +141,23 @@ def test_staggered_mixed_parity(dim, m, k, n_tgt):
     berr = np.abs(tw - ob) / np.where(scale > 0, scale, 1.0)
     flush(f"  max rel err weights {errs.max():.3e} target weights {berr.max():.3e} fallback {rep['n_fallback']}")
     assert errs.max() <= 1e-8 and berr.max() <= 1e-8
+
+
+def test_staggered_autotune_then_parity():
+    """Tuning the staggered QR kernel (GMLS_TUNE_STAGGERED); the next call
+    takes the tuned shapes and stays within the gate."""
+    G = require_gpu()
+    dim, m, k, n_tgt = 3, 2, 60, 300
+    src, tgt, rp, col, eps = case(dim, k, n_tgt, 60 + m)
+    c = G.Context(0)
+    args = (dev(src), dev(tgt), m, GRAD_LAP, 4, dev(eps), dev(rp), dev(col))
+    res = G.gmls_autotune(c, args[0], args[1], m, G.TUNE_STAGGERED, GRAD_LAP, 4, args[5], args[6], args[7], reps=1)
+    flush(f"  {res}")
+    assert sorted(res) == ["qr"]
+    w, tw, st, _ = G.gmls_stencils_staggered(c, *args)
+    w, tw = host(w), host(tw)
+    ow, ob, F = S.stencils_staggered(src, tgt, m, GRAD_LAP, 4, eps, rp, col)
+    cond = cond_reduced(src, tgt, rp, col, eps, dim, m)
+    tol = np.maximum(TOL, 4 * cond * 2.0 ** -53)[:, None]
+    assert np.all(row_errors(w, ow, rp, F, 1) <= tol)
+    c.close()
