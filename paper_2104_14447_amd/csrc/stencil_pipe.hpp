@@ -122,8 +122,14 @@ __device__ __forceinline__ double row_sw(const double *xj, const double *xt, dou
     s[d] = (xj[d] - xt[d]) * ie;
     rr += s[d] * s[d];
   }
-  const double rad = sqrt(rr);
-  return (live && rad < 1.0) ? int_pow(1.0 - rad, p) : 0.0;
+  // |s| from the hardware reciprocal square root and one Newton step for the
+  // square root (relative error about the square of the estimate's, far
+  // below the mixed path's tolerance), in place of the correctly rounded
+  // sqrt sequence; the support test uses |s|^2 itself
+  const double y = __builtin_amdgcn_rsq(rr);
+  const double r0 = rr * y;
+  const double rad = rr > 0.0 ? fma(fma(-r0, r0, rr), 0.5 * y, r0) : 0.0;
+  return (live && rr < 1.0) ? int_pow(1.0 - rad, p) : 0.0;
 }
 
 // Trip count of the chunk loop over a row: one pass of G * RPL rows, or for
