@@ -764,9 +764,9 @@ def main():
     hf = leg_fields(legs[0])
     value = n_t / (head["ms_per_step"] * 1e-3)
     # FP32 executes only in the Cholesky factor of the pipeline's scalar
-    # solve (scalar bases of at most 20 functions): elsewhere the mixed
-    # path's arithmetic is FP64
-    fp32_used = legs[0] == "mixed" and any(
+    # solve (scalar bases of at most 20 functions; scheme 4, forced, is
+    # FP64 throughout): elsewhere the mixed path's arithmetic is FP64
+    fp32_used = legs[0] == "mixed" and args.scheme != 4 and any(
         bs["name"] in ("scalar", "staggered") and bs["Q"] <= 20 for bs in bases)
     line = {
         "metric": "GMLS stencils/sec (3D, order 3, uneven nbrs); mixed vs FP64 at <=1e-8 rel err",

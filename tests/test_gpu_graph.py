@@ -187,3 +187,78 @@ def test_graph_replays_shared_multi(order, k, p, fp64):
         errs = row_errors(w, ow, rp, F, C, zero_rows=zero)[ost != 1]
         flush(f"  {name}: max rel err {errs.max():.3e}")
         assert errs.max() <= (FP64_TOL if fp64 else MIXED_TOL)
+
+
+@pytest.mark.parametrize("knn", [False, True], ids=["radius", "knn"])
+def test_graph_replays_sorted_records(knn):
+    """gmls_neighbors_sorted (records and positions) and stencils gathered
+    from the records (source stride 4) captured together: every replay equals
+    the eager capture-safe run, and the stencils equal those of the index
+    layout bit for bit."""
+    G = require_gpu()
+    pts, r0 = case()
+    n = len(pts)
+    spec = dict(mode=G.SEARCH_KNN, k=40, eps_mult=1.5) if knn else dict(mode=G.SEARCH_RADIUS, radius=r0,
+                                                                         k_min=K_MIN)
+    s = torch.cuda.Stream()
+    c = G.Context(0, stream=s)
+    with torch.cuda.stream(s):
+        x = dev(pts)
+        flush(f"graph sorted knn={knn}: index-layout reference")
+        rp, col, eps = G.gmls_neighbors(c, x, x, **spec)
+        ref_w, ref_st, _ = G.gmls_stencils(c, x, x, 3, G.BASIS_SCALAR, G.F_LAPLACIAN | G.F_GRAD, 4, eps, rp, col,
+                                           prec=G.PREC_MIXED)
+        ref = [host(v) for v in (rp, col, eps, ref_w, ref_st)]
+        nnz = col.numel()
+        F, C, _ = G.gmls_stencil_shape(3, 3, G.BASIS_SCALAR, G.F_LAPLACIAN | G.F_GRAD)
+        col_buf = torch.empty(nnz + 4096, dtype=torch.int32, device="cuda")
+        pcol_buf = torch.empty_like(col_buf)
+        rec_buf = torch.empty((n, 4), dtype=torch.float64, device="cuda")
+        w_buf = torch.empty(F * C * nnz, dtype=torch.float64, device="cuda")
+        st_buf = torch.empty(n, dtype=torch.uint8, device="cuda")
+        c.set_option(G.OPT_SOURCE_STRIDE, 4)
+        # one normal call of each kind sizes the workspace
+        rp_, col_, eps_, rec_, pcol_ = G.gmls_neighbors_sorted(c, x, x, **spec)
+        G.gmls_stencils(c, rec_, x, 3, G.BASIS_SCALAR, G.F_LAPLACIAN | G.F_GRAD, 4, eps_, rp_, pcol_,
+                        prec=G.PREC_MIXED)
+        c.set_option(G.OPT_CAPTURE_SAFE, 1)
+        outs = {}
+
+        def step():
+            rp2, col2, eps2, rec2, pcol2 = G.gmls_neighbors_sorted(c, x, x, col=col_buf, col_sorted=pcol_buf,
+                                                                   records=rec_buf, **spec)
+            G.gmls_stencils(c, rec2, x, 3, G.BASIS_SCALAR, G.F_LAPLACIAN | G.F_GRAD, 4, eps2, rp2,
+                            pcol2[:nnz], prec=G.PREC_MIXED, weights=w_buf, status=st_buf)
+            outs["rp"], outs["eps"] = rp2, eps2
+
+        def snapshot():
+            s.synchronize()
+            return [host(outs["rp"]), host(col_buf[:nnz]), host(outs["eps"]), host(w_buf), host(st_buf),
+                    host(pcol_buf[:nnz]), host(rec_buf)]
+
+        flush("graph sorted: capture-safe eager")
+        step()
+        eager = snapshot()
+        c.check()
+        for name, a_, b_ in zip(("row_ptr", "col", "eps", "weights", "status"), eager, ref):
+            assert np.array_equal(a_, b_), f"records vs index layout: {name} differs"
+        idx = eager[6][:, 3].astype(np.int64)
+        assert np.array_equal(idx[eager[5]], eager[1])
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            step()
+        for rep in range(3):
+            col_buf.fill_(-7)
+            pcol_buf.fill_(-7)
+            rec_buf.fill_(float("nan"))
+            w_buf.fill_(float("nan"))
+            st_buf.fill_(255)
+            s.synchronize()
+            flush(f"graph sorted: replay {rep}")
+            g.replay()
+            got = snapshot()
+            for k_, (a_, b_) in enumerate(zip(got, eager)):
+                assert np.array_equal(np.asarray(a_).view(np.uint8), np.asarray(b_).view(np.uint8)), \
+                    f"replay {rep}: output {k_} differs"
+            c.check()
+    c.close()
