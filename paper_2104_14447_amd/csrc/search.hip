@@ -1100,25 +1100,30 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
 #pragma unroll
         for (int d = 0; d < 3; ++d) x[u][d] = d < DIM ? readlane_d(my_x[d], (j + u) & 63) : 0.0;
       }
-      int fill[NT], cnt[NT];
+      unsigned fill[NT];  // row entries found so far (wave-uniform)
+      int cnt[NT];
       int32_t *out[NT];
 #pragma unroll
       for (int u = 0; u < NT; ++u) {
-        fill[u] = cnt[u] = 0;
+        fill[u] = 0;
+        cnt[u] = 0;
         if constexpr (ROWS)
           out[u] = MODE == kFused ? col + (int64_t)t[u] * kSmallCap : col + (live[u] ? row_ptr[t[u]] : 0);
       }
       for (int k0 = 0; k0 < total; k0 += 64) {
         const int k = k0 + lane;
-        const bool in = k < total;
-        double c[3] = {0, 0, 0};
+        // a lane past the staged block tests a point at NaN, whose squared
+        // distance compares false: it is never accepted
+        const double nan = __builtin_nan("");
+        double c[3] = {nan, nan, nan};
         int id = 0;
-        if (in) {
+        if (k < total) {
           for (int d = 0; d < DIM; ++d) c[d] = cxyz[d][k];
           if constexpr (ROWS) id = cid[k];
         }
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
+          if (!live[u]) continue;
           // (dx*dx + dy*dy) + dz*dz, unfused (the file is built without contraction)
           const double dx = c[0] - x[u][0];
           double dd = dx * dx;
@@ -1130,17 +1135,22 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
             const double dz = c[2] - x[u][2];
             dd = dd + dz * dz;
           }
-          const bool ok = in && live[u] && dd < r2;
+          const bool ok = dd < r2;
           if constexpr (ROWS) {
-            uint64_t m;
-            const int pre = ballot_prefix(ok, &m);
-            if (ok && fill[u] + pre < kSmallCap) {
+            // a row of more than kSmallCap entries goes to the per-target
+            // kernels, which write it again: once a row overflows, nothing
+            // more of it is stored (a wave-uniform test, no per-lane bound)
+            const uint64_t m = __ballot(ok);
+            const unsigned nf = __builtin_amdgcn_readfirstlane(fill[u] + (unsigned)__popcll(m));
+            if (ok && nf <= (unsigned)kSmallCap) {
+              const unsigned slot = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, fill[u]));
               if constexpr (SORTED)
-                cbuf[wv][u][fill[u] + pre] = id;
+                cbuf[wv][u][slot] = id;
               else
-                out[u][fill[u] + pre] = id;  // staging order is cell order: the row is final
+                out[u][slot] = id;  // staging order is cell order: the row is final
             }
-            fill[u] += __popcll(m);
+            fill[u] = nf;
           } else {
             cnt[u] += ok ? 1 : 0;
           }
@@ -1162,7 +1172,7 @@ __global__ __launch_bounds__(kCellThreads) void k_radius_cells(const GridParams 
         int widest = 0;
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
-          const bool defer_it = live[u] && (fill[u] < k_min || fill[u] > kSmallCap);
+          const bool defer_it = live[u] && (fill[u] < (unsigned)k_min || fill[u] > (unsigned)kSmallCap);
           here[u] = live[u] && !defer_it;
           n_sort[u] = here[u] ? fill[u] : 0;
           widest = max(widest, n_sort[u]);

@@ -87,26 +87,43 @@ __device__ __forceinline__ double wave_max(double v) {
 // sweeps of disjoint sets commute, so the pivots are taken two at a time
 // (2 x 2 blocks, one reciprocal of the determinant each) and a trailing
 // single pivot for odd Q.  The matrix stays symmetric, so columns k, k+1
-// (one LDS store each per lane) are also rows k, k+1; the column buffers
-// alternate between steps (col: 4 x 64 doubles), one barrier per step.
+// (one LDS store per lane) are also rows k, k+1; the column buffers
+// alternate between steps (col: 4 x 64 doubles, 16-byte aligned), one
+// barrier per step.
+// Each step updates the next step's pivot columns first, stores them, and
+// takes the next pivot block (from the registers of its lanes) and its
+// reciprocal before the rest of its update, so that this chain overlaps
+// the step's bulk of independent multiply-adds.
 // Returns false when a leading pivot of a block is not above tol
 // (wave-uniform).
 template <int Q>
 __device__ __forceinline__ bool sweep_inverse(double (&a)[Q], double *col, double tol) {
   const int lane = lane_id();
   bool ok = true;
+  // a step's two pivot columns, interleaved: cc[j] = (A_jk, A_j,k+1), so
+  // that one 16-byte LDS read brings both operands of the update of a[j]
+  double2 *cb[2] = {(double2 *)col, (double2 *)(col + 128)};
+  // pivot block of the current step: p00, p01, p11 and 1/det (2 x 2), or
+  // p00 and 1/p00 (the trailing single pivot)
+  double p00 = 0.0, p01 = 0.0, p11 = 0.0, det = 1.0, id = 1.0;
+  if constexpr (Q >= 2) {
+    if (lane < Q) cb[0][lane] = make_double2(a[0], a[1]);
+    p00 = readlane_d(a[0], 0);
+    p01 = readlane_d(a[0], 1);
+    p11 = readlane_d(a[1], 1);
+    det = p00 * p11 - p01 * p01;
+    id = 1.0 / det;
+  } else {
+    if (lane < Q) cb[0][lane].x = a[0];
+    p00 = readlane_d(a[0], 0);
+    id = 1.0 / p00;
+  }
 #pragma unroll
   for (int k = 0; k + 1 < Q; k += 2) {
-    double *c0 = col + ((k >> 1) & 1) * 128, *c1 = c0 + 64;
-    if (lane < Q) {
-      c0[lane] = a[k];
-      c1[lane] = a[k + 1];
-    }
+    const double2 *cc = cb[(k >> 1) & 1];
+    double2 *nc = cb[((k >> 1) + 1) & 1];  // the next step's columns
     __syncthreads();
-    const double p00 = c0[k], p01 = c0[k + 1], p11 = c1[k + 1];
-    const double det = p00 * p11 - p01 * p01;
     ok = ok && p00 > tol && det > tol * p00;
-    const double id = 1.0 / det;
     const double i00 = p11 * id, i01 = -p01 * id, i11 = p00 * id;
     const double ak = a[k], ak1 = a[k + 1];
     const double f0 = ak * i00 + ak1 * i01, f1 = ak * i01 + ak1 * i11;
@@ -115,9 +132,36 @@ __device__ __forceinline__ bool sweep_inverse(double (&a)[Q], double *col, doubl
     const bool l0 = lane == k, l1 = lane == k + 1;
     const double e0 = (l0 ? i00 : l1 ? i01 : 0.0) - f0;
     const double e1 = (l0 ? i01 : l1 ? i11 : 0.0) - f1;
+    // pivots of the next step: 2, 1 (the trailing single pivot) or none
+    // (the loop is unrolled, so NX and the indices below are constants)
+    const int NX = (k + 3 < Q) ? 2 : (k + 2 < Q ? 1 : 0);
+    const int q0 = k + 2 < Q ? k + 2 : Q - 1, q1 = k + 3 < Q ? k + 3 : Q - 1;
+    if (NX >= 1) {
+      const double2 c = cc[q0];
+      a[q0] = fma(e0, c.x, fma(e1, c.y, a[q0]));
+    }
+    if (NX == 2) {
+      const double2 c = cc[q1];
+      a[q1] = fma(e0, c.x, fma(e1, c.y, a[q1]));
+    }
+    if (NX == 2) {
+      if (lane < Q) nc[lane] = make_double2(a[q0], a[q1]);
+      p00 = readlane_d(a[q0], q0);
+      p01 = readlane_d(a[q0], q1);
+      p11 = readlane_d(a[q1], q1);
+      det = p00 * p11 - p01 * p01;
+      id = 1.0 / det;
+    } else if (NX == 1) {
+      if (lane < Q) nc[lane].x = a[q0];
+      p00 = readlane_d(a[q0], q0);
+      id = 1.0 / p00;
+    }
 #pragma unroll
     for (int j = 0; j < Q; ++j)
-      if (j != k && j != k + 1) a[j] = fma(e0, c0[j], fma(e1, c1[j], a[j]));
+      if (j != k && j != k + 1 && (j < k + 2 || j >= k + 2 + NX)) {
+        const double2 c = cc[j];
+        a[j] = fma(e0, c.x, fma(e1, c.y, a[j]));
+      }
     a[k] = l0 ? -i00 : l1 ? -i01 : f0;
     a[k + 1] = l0 ? -i01 : l1 ? -i11 : f1;
     // finish this step's updates here: left alone, the compiler defers each
@@ -128,16 +172,14 @@ __device__ __forceinline__ bool sweep_inverse(double (&a)[Q], double *col, doubl
   }
   if constexpr (Q % 2 == 1) {
     constexpr int k = Q - 1;
-    double *c0 = col + (((Q / 2) & 1) * 128);
-    if (lane < Q) c0[lane] = a[k];
+    const double2 *cc = cb[(Q / 2) & 1];
     __syncthreads();
-    const double piv = c0[k];
-    ok = ok && piv > tol;
-    const double d = 1.0 / piv;
+    ok = ok && p00 > tol;
+    const double d = id;
     const double f = a[k] * d;
     const double ef = (lane == k ? d : 0.0) - f;
 #pragma unroll
-    for (int j = 0; j < Q - 1; ++j) a[j] = fma(ef, c0[j], a[j]);
+    for (int j = 0; j < Q - 1; ++j) a[j] = fma(ef, cc[j].x, a[j]);
     a[k] = lane == k ? -d : f;
   }
   __syncthreads();  // the buffers may be rewritten after this
@@ -162,9 +204,16 @@ __device__ __forceinline__ void wave_round(const double (&acc)[RS], int g0, doub
   for (int q = 0; q < RS; ++q) red[lane * (RS + 1) + q] = acc[q];
   __syncthreads();
   const int q = lane & (RS - 1), part = lane / RS;
-  double t = 0.0;
+  // pairwise sum of the RS rows (fixed order; a chain of log2 RS dependent
+  // adds instead of RS)
+  double v[RS];
 #pragma unroll
-  for (int l = 0; l < RS; ++l) t += red[(part * RS + l) * (RS + 1) + q];
+  for (int l = 0; l < RS; ++l) v[l] = red[(part * RS + l) * (RS + 1) + q];
+#pragma unroll
+  for (int h = RS / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int l = 0; l < h; ++l) v[l] = v[l] + v[l + h];
+  double t = v[0];
 #pragma unroll
   for (int o = RS; o < 64; o <<= 1) t += __shfl_xor(t, o);
   if (lane < RS && g0 + lane < NM) mu[g0 + lane] = t;
@@ -268,20 +317,32 @@ struct WaveSet {
   int *fb_count;
 };
 
-// Scalar basis: the weights of every row of `as` from e = row `lane` of
-// -E^-1 (the coefficients y_i / i! = dsc_i (E^-1 Dg lambda)_i broadcast
-// through LDS; `big` is free here).
+// The rows are written in two steps: first the polynomial coefficients of
+// every functional of every set, into LDS, while the rows of E^-1 (and of
+// S^-1) are in registers; then the weights of every row from those
+// coefficients, with the inverses dead (their registers free for the
+// coefficients of the Horner steps).
+
+// Scalar basis, coefficients: y_i / i! = dsc_i (E^-1 Dg lambda)_i of
+// functional f into cf[f * 64 + i], from e = row `lane` of -E^-1.
+template <int DIM, int ORDER>
+__device__ __forceinline__ void wave_scalar_coefs(const StencilArgs &as, const RowKinds &rk,
+                                                  const double (&e)[num_mono(DIM, ORDER)], double dsc,
+                                                  const double *dscv, double ie, double *cf) {
+  constexpr int QS = num_mono(DIM, ORDER);
+  const int lane = lane_id();
+  for (int f = 0; f < as.F; ++f) cf[f * 64 + lane] = -dsc * lambda_dot<DIM, ORDER, QS>(rk.kind[f], e, dscv, ie);
+}
+
+// Scalar basis, weights of every row of `as` (cfb: the coefficients above,
+// visible to the whole wavefront).
 template <int DIM, int ORDER, int RPL>
-__device__ __forceinline__ void wave_scalar_rows(const StencilArgs &as, const RowKinds &rk,
-                                                 const double (&e)[num_mono(DIM, ORDER)], double dsc,
-                                                 const double *dscv, double ie, int64_t base, int N,
-                                                 const double (&s)[RPL][DIM], const double (&w)[RPL], double *big) {
+__device__ __forceinline__ void wave_scalar_weights(const StencilArgs &as, int64_t base, int N,
+                                                    const double (&s)[RPL][DIM], const double (&w)[RPL],
+                                                    const double *cfb) {
   constexpr int QS = num_mono(DIM, ORDER);
   const int lane = lane_id();
   const int F = as.F;
-  double *cfb = big;  // [F][64]
-  for (int f = 0; f < F; ++f) cfb[f * 64 + lane] = -dsc * lambda_dot<DIM, ORDER, QS>(rk.kind[f], e, dscv, ie);
-  __syncthreads();
   double *wout = as.weights + (int64_t)F * base;
   for (int f = 0; f < F; ++f) {
     double cf[QS];
@@ -294,21 +355,33 @@ __device__ __forceinline__ void wave_scalar_rows(const StencilArgs &as, const Ro
       if (j < N) wout[(int64_t)f * N + j] = val;
     }
   }
-  __syncthreads();
 }
 
-// Divergence-free basis: S = D G^-1 D^T from E^-1, its sweep, and the weights
-// of every row of `av`.  Returns false when S breaks down (the target then
-// goes to the FP64 kernel); `big`, vb and colb are free on entry.
-template <int DIM, int ORDER, int RPL>
-__device__ __forceinline__ bool wave_divfree_rows(const StencilArgs &av, const RowKinds &rk,
-                                                  const double (&e)[num_mono(DIM, ORDER)], double dg, double ifac,
-                                                  const int (&ubl)[3], const double *dscv, double ie, int64_t base,
-                                                  int N, const double (&s)[RPL][DIM], const double (&w)[RPL],
-                                                  double *big, double (*vb)[64], double *colb) {
+// Divergence-free basis, offsets in `big` of the coefficient step's buffers:
+// [c][QM] ds_b r_b, [c][k][QM] t_b Dg_(b+e_k), then per row group g (at most
+// two groups precede the divergence row) [g][c][k][QS] g / q!.
+template <int DIM, int ORDER>
+struct DivBuf {
+  static constexpr int QS = num_mono(DIM, ORDER);
+  static constexpr int QM = ORDER >= 1 ? num_mono(DIM, ORDER - 1) : 1;
+  static constexpr int RB = 0, TDG = DIM * QM, CF = TDG + DIM * DIM * QM;
+  static constexpr int GROUP = DIM * DIM * QS;
+  static constexpr int SIZE = CF + 2 * GROUP;
+};
+
+// Divergence-free basis, coefficients: S = D G^-1 D^T from E^-1, its sweep,
+// and the coefficients of every row group of `av` into big (DivBuf).
+// Returns false when S breaks down (the target then goes to the FP64
+// kernel); `big`, vb and colb are free on entry.
+template <int DIM, int ORDER>
+__device__ __forceinline__ bool wave_divfree_coefs(const StencilArgs &av, const RowKinds &rk,
+                                                   const double (&e)[num_mono(DIM, ORDER)], double dg, double ifac,
+                                                   const int (&ubl)[3], const double *dscv, double ie, double *big,
+                                                   double (*vb)[64], double *colb) {
   constexpr int QS = num_mono(DIM, ORDER);
   constexpr int QM = ORDER >= 1 ? num_mono(DIM, ORDER - 1) : 1;
   constexpr DivUp<DIM, ORDER> DU{};
+  using DB = DivBuf<DIM, ORDER>;
   const int lane = lane_id();
   const int F = av.F;
   // S = D G^-1 D^T: S_(b,b2) = sum_k G^-1_(up[b][k], up[b2][k]); lane b holds row b
@@ -334,28 +407,18 @@ __device__ __forceinline__ bool wave_divfree_rows(const StencilArgs &av, const R
 #pragma unroll
   for (int b2 = 0; b2 < QM; ++b2) sr[b2] *= ds * vb[3][b2];
   if (!sweep_inverse<QM>(sr, colb, 1e-14)) return false;  // ends with a barrier: big is free
-  double *wout = av.weights + (int64_t)F * DIM * base;
   // rows come in groups of DIM (one kind, components 0..DIM-1), then the
   // divergence row; per group, for component c of the functional:
   //   v = G^-1 l (the same for every c), r_b = v_(b + e_c),
   //   t = S^-1 r = ds (ds S ds)^-1 ds r,
   //   g_(c,k) = delta_(k,c) v - G^-1 D_k^T t, D_k^T t = sum_b t_b e_(b+e_k),
   // whose columns of E^-1 are this lane's registers
-  double *rb = big;                               // [c][QM]     ds_b r_b
-  double *tdg = big + DIM * QM;                   // [c][k][QM]  t_b Dg_(b+e_k)
-  double *cfb = big + DIM * QM + DIM * DIM * QM;  // [c][k][QS]  g / q!
-  for (int f0 = 0; f0 < F; f0 += DIM) {
+  double *rb = big + DB::RB;
+  double *tdg = big + DB::TDG;
+  for (int f0 = 0, g = 0; f0 < F; f0 += DIM, ++g) {
     const int kind = rk.kind[f0];
-    if (kind == FK_DIV) {  // identically zero on a divergence-free fit
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int j = lane + 64 * r;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k)
-          if (j < N) wout[((int64_t)f0 * N + j) * DIM + k] = 0.0;
-      }
-      break;  // the last row
-    }
+    if (kind == FK_DIV) break;  // identically zero on a divergence-free fit: the last row
+    double *cfb = big + DB::CF + g * DB::GROUP;
     const double v = -dg * lambda_dot<DIM, ORDER, QS>(kind, e, dscv, ie);
     vb[1][lane] = v;
     __syncthreads();
@@ -383,11 +446,37 @@ __device__ __forceinline__ bool wave_divfree_rows(const StencilArgs &av, const R
           double u = 0.0;
 #pragma unroll
           for (int b = 0; b < QM; ++b) u = fma(e[DU.up[b][k]], tdg[(c * DIM + k) * QM + b], u);
-          const double g = (k == c ? v : 0.0) + dg * u;
-          cfb[(c * DIM + k) * QS + lane] = g * ifac;
+          const double gv = (k == c ? v : 0.0) + dg * u;
+          cfb[(c * DIM + k) * QS + lane] = gv * ifac;
         }
     }
-    __syncthreads();
+  }
+  return true;
+}
+
+// Divergence-free basis, weights of every row of `av` from the coefficients
+// in big (visible to the whole wavefront).
+template <int DIM, int ORDER, int RPL>
+__device__ __forceinline__ void wave_divfree_weights(const StencilArgs &av, const RowKinds &rk, int64_t base,
+                                                     int N, const double (&s)[RPL][DIM], const double (&w)[RPL],
+                                                     const double *big) {
+  constexpr int QS = num_mono(DIM, ORDER);
+  using DB = DivBuf<DIM, ORDER>;
+  const int lane = lane_id();
+  const int F = av.F;
+  double *wout = av.weights + (int64_t)F * DIM * base;
+  for (int f0 = 0, g = 0; f0 < F; f0 += DIM, ++g) {
+    if (rk.kind[f0] == FK_DIV) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int j = lane + 64 * r;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+          if (j < N) wout[((int64_t)f0 * N + j) * DIM + k] = 0.0;
+      }
+      break;  // the last row
+    }
+    const double *cfb = big + DB::CF + g * DB::GROUP;
 #pragma unroll
     for (int c = 0; c < DIM; ++c)
 #pragma unroll
@@ -402,9 +491,7 @@ __device__ __forceinline__ bool wave_divfree_rows(const StencilArgs &av, const R
           if (j < N) wout[((int64_t)(f0 + c) * N + j) * DIM + k] = val;
         }
       }
-    __syncthreads();
   }
-  return true;
 }
 
 // BASIS 0 scalar set (ss), 1 divergence-free set (sv), 3 both on the same
@@ -423,11 +510,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaveCand[CA
   constexpr int RED = 64 * (RS + 1);
   constexpr int BIG = (DIVF && QS * QS > RED) ? QS * QS : RED;
   static_assert(QS <= 64, "one basis function per lane");
+  static_assert(!DIVF || DivBuf<DIM, ORDER>::SIZE <= BIG, "divergence-free buffers fit");
+  static_assert(5 * 64 <= BIG, "scalar coefficients fit");
   __shared__ double big[BIG];      // moment reduction, then (divergence-free) -E^-1
   __shared__ double mu[NM];        // moments, lexicographic order
   __shared__ double vb[4][64];     // broadcast vectors
-  __shared__ double colb[4 * 64];  // pivot columns of the sweeps
+  __shared__ __align__(16) double colb[4 * 64];  // pivot columns of the sweeps
   __shared__ unsigned char pidx[QS * QS];
+  // the scalar set's coefficients [f][64]: their own buffer when the
+  // divergence-free set's coefficients take `big` (shared calls)
+  __shared__ double cfs_own[BASIS == 3 ? 5 * 64 : 1];
+  double *cfs = BASIS == 3 ? cfs_own : big;
   constexpr WavePairs<DIM, ORDER> WP{};
   constexpr InvFact64<DIM, ORDER> IF{};
   const StencilArgs &a = SCAL ? ss.a : sv.a;  // the common inputs
@@ -470,7 +563,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaveCand[CA
     __syncthreads();
     double e[QS];
 #pragma unroll
-    for (int k = 0; k < QS; ++k) e[k] = lane < QS ? mu[pidx[li * QS + k]] * dsc * vb[0][k] : 0.0;
+    for (int k = 0; k < QS; ++k) {
+      // every lane loads (li is in range), so the QS reads go out together
+      const double v = mu[pidx[li * QS + k]] * dsc * vb[0][k];
+      e[k] = lane < QS ? v : 0.0;
+    }
     double rs = 0.0;
 #pragma unroll
     for (int k = 0; k < QS; ++k) rs += fabs(e[k]);
@@ -485,17 +582,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaveCand[CA
     if (opt.force_fallback) ok = false;
     const double dg = dsc / ifac;  // Dg_lane: G^-1 = Dg E^-1 Dg
 
+    // the coefficients of both sets while the inverse rows are in
+    // registers, then the weights of every row with those registers free
+    if constexpr (SCAL)
+      if (ok) wave_scalar_coefs<DIM, ORDER>(ss.a, rks, e, dsc, vb[0], ie, cfs);
+    bool okv = ok;
+    if constexpr (DIVF)
+      if (ok) okv = wave_divfree_coefs<DIM, ORDER>(sv.a, rkv, e, dg, ifac, ubl, vb[0], ie, big, vb, colb);
+    __syncthreads();
     if constexpr (SCAL) {
-      if (ok) wave_scalar_rows<DIM, ORDER, RPL>(ss.a, rks, e, dsc, vb[0], ie, base, N, s, w, big);
+      if (ok) wave_scalar_weights<DIM, ORDER, RPL>(ss.a, base, N, s, w, cfs);
       if (lane == 0) {
         ss.a.status[t] = ok ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
         if (!ok) ss.fb_list[atomicAdd(ss.fb_count, 1)] = t;
       }
     }
-    bool okv = ok;
     if constexpr (DIVF) {
-      if (ok) okv = wave_divfree_rows<DIM, ORDER, RPL>(sv.a, rkv, e, dg, ifac, ubl, vb[0], ie, base, N, s, w, big,
-                                                       vb, colb);
+      if (okv) wave_divfree_weights<DIM, ORDER, RPL>(sv.a, rkv, base, N, s, w, big);
       if (lane == 0) {
         sv.a.status[t] = okv ? GMLS_TARGET_OK : GMLS_TARGET_FALLBACK;
         if (!okv) sv.fb_list[atomicAdd(sv.fb_count, 1)] = t;
