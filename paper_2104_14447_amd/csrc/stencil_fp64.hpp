@@ -128,15 +128,18 @@ __device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rd
 template <int Q>
 __device__ __forceinline__ double tri_solve_rtr(const double *Rm, const double *Rt, double b, double rdiag,
                                                 int lane) {
+  // 1/R_aa once per lane, so that each of the 2Q dependent steps multiplies
+  // instead of dividing
+  const double rinv = lane < Q ? 1.0 / rdiag : 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
-    const double zk = readlane_d(b, k) / readlane_d(rdiag, k);
+    const double zk = readlane_d(b, k) * readlane_d(rinv, k);
     if (lane == k) b = zk;
     if (lane > k && lane < Q) b -= Rm[k * Q + lane] * zk;
   }
 #pragma unroll
   for (int k = Q - 1; k >= 0; --k) {
-    const double yk = readlane_d(b, k) / readlane_d(rdiag, k);
+    const double yk = readlane_d(b, k) * readlane_d(rinv, k);
     if (lane == k) b = yk;
     if (lane < k) b -= Rt[k * Q + lane] * yk;
   }

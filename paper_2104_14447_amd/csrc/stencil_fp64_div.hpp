@@ -101,7 +101,7 @@ __device__ __forceinline__ void qr_divfree_solve(const StencilArgs &a, const Row
       double acc = i == lane ? 1.0 : 0.0;
 #pragma unroll
       for (int l = i + 1; l < Q; ++l) acc -= Rs[i * Q + l] * x[l];
-      x[i] = i <= lane ? acc / Rs[i * Q + i] : 0.0;
+      x[i] = i <= lane ? acc * (1.0 / Rs[i * Q + i]) : 0.0;  // the reciprocal is off the chain
     }
     if (lane < Q)
 #pragma unroll
