@@ -137,16 +137,42 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __builtin_bit_cast(double, b);
 }
 
-// Sum of v over all 64 lanes, the same value in every lane, without LDS
-// traffic: within each 16-lane row by DPP (swap neighbours, swap pairs,
-// rotate by 4, rotate by 8), then the four row sums read into scalar
-// registers and added in a fixed order.  Every lane must be active.
+// v[lane] + v[lane ^ 16] (S = 16) or v[lane] + v[lane ^ 32] (S = 32) by the
+// lane-swap instructions: swapping the odd 16-lane rows (the upper half) of
+// one copy of v with the even rows (lower half) of another leaves the lower
+// partner in the first copy and the upper one in the second, in every lane,
+// so both lanes of a pair add the same operands in the same order.
+template <int S>
+__device__ __forceinline__ double swap_pair_sum(double v) {
+  static_assert(S == 16 || S == 32, "row or half swap");
+  const int2 b = __builtin_bit_cast(int2, v);
+  int2 lo, hi;
+  if constexpr (S == 16) {
+    const auto x = __builtin_amdgcn_permlane16_swap(b.x, b.x, false, false);
+    const auto y = __builtin_amdgcn_permlane16_swap(b.y, b.y, false, false);
+    lo = make_int2(x[0], y[0]);
+    hi = make_int2(x[1], y[1]);
+  } else {
+    const auto x = __builtin_amdgcn_permlane32_swap(b.x, b.x, false, false);
+    const auto y = __builtin_amdgcn_permlane32_swap(b.y, b.y, false, false);
+    lo = make_int2(x[0], y[0]);
+    hi = make_int2(x[1], y[1]);
+  }
+  return __builtin_bit_cast(double, lo) + __builtin_bit_cast(double, hi);
+}
+
+// Sum of v over all 64 lanes, bitwise the same in every lane, with no LDS
+// traffic and no scalar reads: within each 16-lane row by DPP (swap
+// neighbours, swap pairs, mirror the row, rotate by 8: at every step the two
+// lanes that combine add the same two operands, so the row sum is identical
+// across the row), then rows 0 + 1 and 2 + 3, then the two halves, by lane
+// swaps.  Every lane must be active.
 __device__ __forceinline__ double wave_sum_uniform(double v) {
   v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x140>(v);  // row_mirror
   v += dpp_d<0x128>(v);  // row_ror:8
-  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+  return swap_pair_sum<32>(swap_pair_sum<16>(v));
 }
 
 template <typename T>

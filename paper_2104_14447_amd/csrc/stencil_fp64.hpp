@@ -91,7 +91,7 @@ __device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rd
     }
 #pragma unroll
     for (int l = k; l < Q; ++l) dots[l] = wave_sum_uniform(dots[l]);
-    const double sigma = dots[k];
+    const double sigma = uniform_d(dots[k]);  // the same in every lane; a scalar branch
     const double xk = readlane_d(M[0][k], k);
     if (sigma > 0.0) {
       const double norm = sqrt(sigma);

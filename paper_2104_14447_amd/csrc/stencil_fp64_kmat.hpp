@@ -78,7 +78,7 @@ __device__ void qr_divfree_kmat_target(const StencilArgs &a, const RowKinds &rk,
       xs[q] = (row >= k && row < KR) ? K[k * KR + row] : 0.0;
       part += xs[q] * xs[q];
     }
-    const double sigma = wave_sum_uniform(part);
+    const double sigma = uniform_d(wave_sum_uniform(part));  // a scalar branch below
     const double xk = uniform_d(K[k * KR + k]);
     double beta = 0.0;
     if (sigma > 0.0) {
