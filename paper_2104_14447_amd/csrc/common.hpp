@@ -175,6 +175,12 @@ __device__ __forceinline__ double wave_sum_uniform(double v) {
   return swap_pair_sum<32>(swap_pair_sum<16>(v));
 }
 
+// LDS writes of one wavefront are seen by its later LDS reads from any lane
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

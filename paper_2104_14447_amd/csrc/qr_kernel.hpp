@@ -11,8 +11,10 @@ namespace gmls {
 template <int DIM, int ORDER, int BASIS>
 constexpr int qr_lds_doubles() {
   constexpr int Q = num_mono(DIM, ORDER);
-  if (BASIS != 1) return 2 * Q * Q + 8 * Q;
-  return qr_divfree_lds_doubles<DIM, ORDER>();
+  // the solves' buffers, or the factor's column sums if larger (the factor
+  // runs before the solves, so they share the array)
+  constexpr int SOLVE = BASIS != 1 ? 2 * Q * Q + 8 * Q : qr_divfree_lds_doubles<DIM, ORDER>();
+  return SOLVE > kSumBufDoubles ? SOLVE : kSumBufDoubles;
 }
 
 // Persistent kernel: waves take targets from list[0 .. *count) in turn.
@@ -78,7 +80,7 @@ __device__ __forceinline__ void qr_shared_loop(const StencilArgs &as, const Sten
     Rows<DIM, RPL> r;
     double M[RPL][Q];
     double rdiag;
-    qr_factor<DIM, ORDER, RPL>(as, t, r, M, rdiag, lane_id());
+    qr_factor<DIM, ORDER, RPL>(as, t, r, M, rdiag, lane_id(), lds);  // lds is free until the solves
     // the scalar solve leaves R row-major in lds[0 .. Q*Q) (the divergence-free
     // solve's layout) unless R fails the rank test, after which the
     // divergence-free solve does not read it; it ends with a barrier

@@ -630,12 +630,6 @@ __device__ void lds_sort_int(int *idx, int n) {
   }
 }
 
-// LDS writes of one wavefront are seen by its later LDS reads from any lane
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // ---------------------------------------------------------------------------
 // kNN, register path: one wavefront per target scans the block of cells
 // within R = 2 of its cell (cells have side ~ d_k / 1.9, so the block covers

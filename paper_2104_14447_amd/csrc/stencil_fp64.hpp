@@ -71,55 +71,106 @@ __device__ __forceinline__ void load_rows(const StencilArgs &a, int t, Rows<DIM,
   for (int i = 0; i < RPL; ++i) row_s_w<DIM>(a, r.base, first + lane + 64 * i, r.N, xt, ie, r.s[i], r.w[i]);
 }
 
+// LDS the batched column sums of wave_householder take (a row of 17 doubles
+// per lane: 16 values and one of padding, so that the rows start in
+// different banks).
+constexpr int kSumBufDoubles = 64 * 17;
+
+// v[FIRST..N) summed over the wavefront, bitwise the same in every lane, 16
+// values at a time through LDS: every lane stores its partial values, lane
+// j + 16 g then adds value j over the 16 lanes 16 g .. 16 g + 15 (pairwise,
+// a fixed order), the four groups are combined by lane swaps (both lanes of
+// a pair add the same operands), and value j is read from lane j.  One pass
+// costs about 55 vector instructions for 16 values, where a full wave sum
+// per value (DPP within the rows, then across them) costs about 18 each.
+// buf: kSumBufDoubles of LDS owned by this wavefront; all 64 lanes active.
+template <int N, int FIRST>
+__device__ __forceinline__ void wave_sums_lds(double (&v)[N], double *buf, int lane) {
+  const int j = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int c0 = FIRST; c0 < N; c0 += 16) {
+    const int ch = N - c0 < 16 ? N - c0 : 16;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q < ch) buf[lane * 17 + q] = v[c0 + q];
+    wave_lds_sync();
+    double p[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) p[i] = j < ch ? buf[(16 * g + i) * 17 + j] : 0.0;
+#pragma unroll
+    for (int h = 8; h >= 1; h >>= 1)
+#pragma unroll
+      for (int i = 0; i < h; ++i) p[i] = p[i] + p[i + h];
+    const double sum = swap_pair_sum<32>(swap_pair_sum<16>(p[0]));
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q < ch) v[c0 + q] = readlane_d(sum, q);
+    wave_lds_sync();  // the next pass (or the caller) may rewrite buf
+  }
+}
+
+// One Householder step of wave_householder: column K of M is reduced and the
+// reflector applied to columns K+1..Q-1, then the next step (a template
+// recursion, so that every column index is a constant and M stays in
+// registers).
+template <int K, int Q, int RPL, bool VIA_LDS>
+__device__ __forceinline__ void householder_step(double (&M)[RPL][Q], double &rdiag, int lane, double *buf) {
+  double dots[Q];
+  const double x0 = lane >= K ? M[0][K] : 0.0;
+#pragma unroll
+  for (int l = K; l < Q; ++l) {
+    double v = x0 * (lane >= K ? M[0][l] : 0.0);
+#pragma unroll
+    for (int i = 1; i < RPL; ++i) v += M[i][K] * M[i][l];
+    dots[l] = v;
+  }
+  if constexpr (VIA_LDS) {
+    wave_sums_lds<Q, K>(dots, buf, lane);
+  } else {
+#pragma unroll
+    for (int l = K; l < Q; ++l) dots[l] = wave_sum_uniform(dots[l]);
+  }
+  const double sigma = uniform_d(dots[K]);  // the same in every lane; a scalar branch
+  const double xk = readlane_d(M[0][K], K);
+  if (sigma > 0.0) {
+    const double norm = sqrt(sigma);
+    const double beta = xk >= 0.0 ? -norm : norm;
+    const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
+    // v = x - beta e_K on rows >= K
+    const double v0 = lane > K ? M[0][K] : (lane == K ? xk - beta : 0.0);
+#pragma unroll
+    for (int l = K + 1; l < Q; ++l) {
+      const double rkl = readlane_d(M[0][l], K);
+      const double coef = 2.0 * (dots[l] - beta * rkl) * inv_vtv;
+      M[0][l] -= coef * v0;
+#pragma unroll
+      for (int i = 1; i < RPL; ++i) M[i][l] -= coef * M[i][K];
+    }
+    if (lane == K) M[0][K] = beta;
+  } else if (lane == K) {
+    M[0][K] = 0.0;
+  }
+  if (lane == K) rdiag = M[0][K];
+  // finish this column's updates here: left alone, the compiler defers the
+  // updates of later columns to where they are next read, keeping every
+  // reflector live (registers grow with the column count)
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+#pragma unroll
+    for (int l = K + 1; l < Q; ++l) asm volatile("" : "+v"(M[i][l]));
+  if constexpr (K + 1 < Q) householder_step<K + 1, Q, RPL, VIA_LDS>(M, rdiag, lane, buf);
+}
+
 // Householder QR of the register-resident M (rows across lanes).  On return
 // lane k (k < Q) holds row k of R in M[0][k..Q-1] and rdiag = R_kk.  The
-// column dot products are summed over the wavefront by DPP and scalar reads
-// (no LDS traffic); all 64 lanes take part.
-template <int Q, int RPL>
-__device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rdiag, int lane) {
+// column dot products of each step are summed over the wavefront together,
+// through `buf` (kSumBufDoubles of LDS; wave_sums_lds), or one by one by DPP
+// and lane swaps when VIA_LDS is false (no LDS; buf unused); all 64 lanes
+// take part.
+template <int Q, int RPL, bool VIA_LDS = true>
+__device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rdiag, int lane, double *buf) {
   rdiag = 0.0;
-#pragma unroll
-  for (int k = 0; k < Q; ++k) {
-    double dots[Q];
-    const double x0 = lane >= k ? M[0][k] : 0.0;
-#pragma unroll
-    for (int l = k; l < Q; ++l) {
-      double v = x0 * (lane >= k ? M[0][l] : 0.0);
-#pragma unroll
-      for (int i = 1; i < RPL; ++i) v += M[i][k] * M[i][l];
-      dots[l] = v;
-    }
-#pragma unroll
-    for (int l = k; l < Q; ++l) dots[l] = wave_sum_uniform(dots[l]);
-    const double sigma = uniform_d(dots[k]);  // the same in every lane; a scalar branch
-    const double xk = readlane_d(M[0][k], k);
-    if (sigma > 0.0) {
-      const double norm = sqrt(sigma);
-      const double beta = xk >= 0.0 ? -norm : norm;
-      const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
-      // v = x - beta e_k on rows >= k
-      const double v0 = lane > k ? M[0][k] : (lane == k ? xk - beta : 0.0);
-#pragma unroll
-      for (int l = k + 1; l < Q; ++l) {
-        const double rkl = readlane_d(M[0][l], k);
-        const double coef = 2.0 * (dots[l] - beta * rkl) * inv_vtv;
-        M[0][l] -= coef * v0;
-#pragma unroll
-        for (int i = 1; i < RPL; ++i) M[i][l] -= coef * M[i][k];
-      }
-      if (lane == k) M[0][k] = beta;
-    } else if (lane == k) {
-      M[0][k] = 0.0;
-    }
-    if (lane == k) rdiag = M[0][k];
-    // finish this column's updates here: left alone, the compiler defers the
-    // updates of later columns to where they are next read, keeping every
-    // reflector live (registers grow with the column count)
-#pragma unroll
-    for (int i = 0; i < RPL; ++i)
-#pragma unroll
-      for (int l = k + 1; l < Q; ++l) asm volatile("" : "+v"(M[i][l]));
-  }
+  householder_step<0, Q, RPL, VIA_LDS>(M, rdiag, lane, buf);
 }
 
 // Solve R^T z = b then R y = z for a Q x Q upper-triangular R stored
@@ -157,7 +208,7 @@ __device__ __forceinline__ double tri_solve_rtr(const double *Rm, const double *
 template <int DIM, int ORDER, int RPL, int SKIP = 0>
 __device__ __forceinline__ void qr_factor(const StencilArgs &a, int t, Rows<DIM, RPL> &r,
                                           double (&M)[RPL][num_mono(DIM, ORDER) - SKIP], double &rdiag,
-                                          int lane) {
+                                          int lane, double *buf) {
   constexpr int QF = num_mono(DIM, ORDER);
   constexpr int Q = QF - SKIP;
   load_rows<DIM, RPL>(a, t, r, lane);
@@ -169,7 +220,7 @@ __device__ __forceinline__ void qr_factor(const StencilArgs &a, int t, Rows<DIM,
 #pragma unroll
     for (int q = 0; q < Q; ++q) M[i][q] = sw * p[q + SKIP];
   }
-  wave_householder<Q, RPL>(M, rdiag, lane);
+  wave_householder<Q, RPL>(M, rdiag, lane, buf);
   if (r.N > 64 * RPL) {
     static_assert(Q < 64, "R and the next rows share the wavefront");
     constexpr int CAP = 64 * RPL - Q;  // rows added per step
@@ -194,7 +245,7 @@ __device__ __forceinline__ void qr_factor(const StencilArgs &a, int t, Rows<DIM,
 #pragma unroll
         for (int l = 0; l < Q; ++l) M[i][l] = sw * p[l + SKIP];
       }
-      wave_householder<Q, RPL>(M, rdiag, lane);
+      wave_householder<Q, RPL>(M, rdiag, lane, buf);
     }
     r.first = -1;
   }
@@ -312,12 +363,12 @@ __device__ __forceinline__ void qr_scalar_solve(const StencilArgs &a, const RowK
 }
 
 template <int DIM, int ORDER, int RPL, int SKIP = 0>
-__device__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
+__device__ __forceinline__ void qr_scalar_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
   constexpr int Q = num_mono(DIM, ORDER) - SKIP;
   Rows<DIM, RPL> r;
   double M[RPL][Q];
   double rdiag;
-  qr_factor<DIM, ORDER, RPL, SKIP>(a, t, r, M, rdiag, lane_id());
+  qr_factor<DIM, ORDER, RPL, SKIP>(a, t, r, M, rdiag, lane_id(), lds);  // lds is free until the solves
   qr_scalar_solve<DIM, ORDER, RPL, SKIP>(a, rk, t, r, M[0], rdiag, lds);
 }
 

@@ -120,7 +120,7 @@ __device__ __forceinline__ void qr_divfree_solve(const StencilArgs &a, const Row
       }
     }
     double rdb;
-    wave_householder<QM, KBL>(MB, rdb, lane);
+    wave_householder<QM, KBL, false>(MB, rdb, lane, nullptr);  // lds holds R^-1
     const double bmax = uniform_d(wave_max(lane < QM ? fabs(rdb) : 0.0));
     const double bmin = uniform_d(wave_min(lane < QM ? fabs(rdb) : DBL_MAX));
     deficient = !(bmin > kRankTol * bmax);
@@ -224,12 +224,12 @@ __device__ __forceinline__ void qr_divfree_solve(const StencilArgs &a, const Row
 }
 
 template <int DIM, int ORDER, int RPL>
-__device__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
+__device__ __forceinline__ void qr_divfree_target(const StencilArgs &a, const RowKinds &rk, int t, double *lds) {
   constexpr int Q = num_mono(DIM, ORDER);
   Rows<DIM, RPL> r;
   double M[RPL][Q];
   double rdiag;
-  qr_factor<DIM, ORDER, RPL>(a, t, r, M, rdiag, lane_id());
+  qr_factor<DIM, ORDER, RPL>(a, t, r, M, rdiag, lane_id(), lds);  // lds is free until the solves
   qr_divfree_solve<DIM, ORDER, RPL>(a, rk, t, r, M[0], rdiag, lds);
 }
 

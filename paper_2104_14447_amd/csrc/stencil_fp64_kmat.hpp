@@ -23,7 +23,8 @@ constexpr int qr_kmat_lds_doubles() {
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int QD = DivFreeTab<DIM, ORDER>::QD;
   constexpr int KR = DIM * Q;
-  return Q * Q + QD * KR + 8 * QD + 8 * KR + QD;
+  constexpr int SOLVE = Q * Q + QD * KR + 8 * QD + 8 * KR + QD;
+  return SOLVE > kSumBufDoubles ? SOLVE : kSumBufDoubles;  // the factor's column sums come first
 }
 
 template <int DIM, int ORDER, int RPL>
@@ -37,7 +38,7 @@ __device__ void qr_divfree_kmat_target(const StencilArgs &a, const RowKinds &rk,
   Rows<DIM, RPL> r;
   double M[RPL][Q];
   double rdiag;
-  qr_factor<DIM, ORDER, RPL>(a, t, r, M, rdiag, lane);  // any row count (chunked when long)
+  qr_factor<DIM, ORDER, RPL>(a, t, r, M, rdiag, lane, lds);  // any row count (chunked when long)
   const int F = a.F;
   // scalar R in LDS (row-major), then K = (R (x) I) T column-major [QD][KR]
   double *Rs = lds;              // Q*Q
