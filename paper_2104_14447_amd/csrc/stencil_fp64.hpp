@@ -76,16 +76,17 @@ __device__ __forceinline__ void load_rows(const StencilArgs &a, int t, Rows<DIM,
 // different banks).
 constexpr int kSumBufDoubles = 64 * 17;
 
-// v[FIRST..N) summed over the wavefront, bitwise the same in every lane, 16
-// values at a time through LDS: every lane stores its partial values, lane
-// j + 16 g then adds value j over the 16 lanes 16 g .. 16 g + 15 (pairwise,
-// a fixed order), the four groups are combined by lane swaps (both lanes of
-// a pair add the same operands), and value j is read from lane j.  One pass
-// costs about 55 vector instructions for 16 values, where a full wave sum
-// per value (DPP within the rows, then across them) costs about 18 each.
-// buf: kSumBufDoubles of LDS owned by this wavefront; all 64 lanes active.
+// v[FIRST..N) summed over the wavefront and multiplied by scale, bitwise the
+// same in every lane, 16 values at a time through LDS: every lane stores its
+// partial values, lane j + 16 g then adds value j over the 16 lanes
+// 16 g .. 16 g + 15 (pairwise, a fixed order), the four groups are combined
+// by lane swaps (both lanes of a pair add the same operands), lane j scales
+// value j, and value j is read from lane j.  One pass costs about 55 vector
+// instructions for 16 values, where a full wave sum per value (DPP within the
+// rows, then across them) costs about 18 each.  buf: kSumBufDoubles of LDS
+// owned by this wavefront; all 64 lanes active.
 template <int N, int FIRST>
-__device__ __forceinline__ void wave_sums_lds(double (&v)[N], double *buf, int lane) {
+__device__ __forceinline__ void wave_sums_lds(double (&v)[N], double *buf, int lane, double scale) {
   const int j = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int c0 = FIRST; c0 < N; c0 += 16) {
@@ -101,7 +102,7 @@ __device__ __forceinline__ void wave_sums_lds(double (&v)[N], double *buf, int l
     for (int h = 8; h >= 1; h >>= 1)
 #pragma unroll
       for (int i = 0; i < h; ++i) p[i] = p[i] + p[i + h];
-    const double sum = swap_pair_sum<32>(swap_pair_sum<16>(p[0]));
+    const double sum = swap_pair_sum<32>(swap_pair_sum<16>(p[0])) * scale;
 #pragma unroll
     for (int q = 0; q < 16; ++q)
       if (q < ch) v[c0 + q] = readlane_d(sum, q);
@@ -112,43 +113,74 @@ __device__ __forceinline__ void wave_sums_lds(double (&v)[N], double *buf, int l
 // One Householder step of wave_householder: column K of M is reduced and the
 // reflector applied to columns K+1..Q-1, then the next step (a template
 // recursion, so that every column index is a constant and M stays in
-// registers).
+// registers).  With v = x - beta e_K (x: column K on rows >= K, beta = -+|x|)
+// column l takes a_l -= (2 v.a_l / v.v) v; v.a_l equals x.a_l - beta R_Kl.
 template <int K, int Q, int RPL, bool VIA_LDS>
 __device__ __forceinline__ void householder_step(double (&M)[RPL][Q], double &rdiag, int lane, double *buf) {
-  double dots[Q];
   const double x0 = lane >= K ? M[0][K] : 0.0;
-#pragma unroll
-  for (int l = K; l < Q; ++l) {
-    double v = x0 * (lane >= K ? M[0][l] : 0.0);
-#pragma unroll
-    for (int i = 1; i < RPL; ++i) v += M[i][K] * M[i][l];
-    dots[l] = v;
-  }
   if constexpr (VIA_LDS) {
-    wave_sums_lds<Q, K>(dots, buf, lane);
-  } else {
+    // |x|^2 first (one wave sum), then the products v.a_l of all later
+    // columns with v itself, reduced together and scaled by 2 / v.v in LDS
+    double ss = x0 * x0;
 #pragma unroll
-    for (int l = K; l < Q; ++l) dots[l] = wave_sum_uniform(dots[l]);
-  }
-  const double sigma = uniform_d(dots[K]);  // the same in every lane; a scalar branch
-  const double xk = readlane_d(M[0][K], K);
-  if (sigma > 0.0) {
-    const double norm = sqrt(sigma);
-    const double beta = xk >= 0.0 ? -norm : norm;
-    const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
-    // v = x - beta e_K on rows >= K
-    const double v0 = lane > K ? M[0][K] : (lane == K ? xk - beta : 0.0);
+    for (int i = 1; i < RPL; ++i) ss = fma(M[i][K], M[i][K], ss);
+    const double sigma = uniform_d(wave_sum_uniform(ss));  // the same in every lane; a scalar branch
+    const double xk = readlane_d(M[0][K], K);
+    if (sigma > 0.0) {
+      const double norm = sqrt(sigma);
+      const double beta = xk >= 0.0 ? -norm : norm;
+      const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
+      const double v0 = lane > K ? M[0][K] : (lane == K ? xk - beta : 0.0);
+      if constexpr (K + 1 < Q) {
+        double coef[Q];
 #pragma unroll
-    for (int l = K + 1; l < Q; ++l) {
-      const double rkl = readlane_d(M[0][l], K);
-      const double coef = 2.0 * (dots[l] - beta * rkl) * inv_vtv;
-      M[0][l] -= coef * v0;
+        for (int l = K + 1; l < Q; ++l) {
+          double t = v0 * M[0][l];
 #pragma unroll
-      for (int i = 1; i < RPL; ++i) M[i][l] -= coef * M[i][K];
+          for (int i = 1; i < RPL; ++i) t = fma(M[i][K], M[i][l], t);
+          coef[l] = t;
+        }
+        wave_sums_lds<Q, K + 1>(coef, buf, lane, 2.0 * inv_vtv);
+#pragma unroll
+        for (int l = K + 1; l < Q; ++l) {
+          M[0][l] -= coef[l] * v0;
+#pragma unroll
+          for (int i = 1; i < RPL; ++i) M[i][l] -= coef[l] * M[i][K];
+        }
+      }
+      if (lane == K) M[0][K] = beta;
+    } else if (lane == K) {
+      M[0][K] = 0.0;
     }
-    if (lane == K) M[0][K] = beta;
-  } else if (lane == K) {
-    M[0][K] = 0.0;
+  } else {
+    // every x.a_l by its own wave sum (no LDS)
+    double dots[Q];
+#pragma unroll
+    for (int l = K; l < Q; ++l) {
+      double v = x0 * (lane >= K ? M[0][l] : 0.0);
+#pragma unroll
+      for (int i = 1; i < RPL; ++i) v += M[i][K] * M[i][l];
+      dots[l] = wave_sum_uniform(v);
+    }
+    const double sigma = uniform_d(dots[K]);  // the same in every lane; a scalar branch
+    const double xk = readlane_d(M[0][K], K);
+    if (sigma > 0.0) {
+      const double norm = sqrt(sigma);
+      const double beta = xk >= 0.0 ? -norm : norm;
+      const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
+      const double v0 = lane > K ? M[0][K] : (lane == K ? xk - beta : 0.0);
+#pragma unroll
+      for (int l = K + 1; l < Q; ++l) {
+        const double rkl = readlane_d(M[0][l], K);
+        const double coef = 2.0 * (dots[l] - beta * rkl) * inv_vtv;
+        M[0][l] -= coef * v0;
+#pragma unroll
+        for (int i = 1; i < RPL; ++i) M[i][l] -= coef * M[i][K];
+      }
+      if (lane == K) M[0][K] = beta;
+    } else if (lane == K) {
+      M[0][K] = 0.0;
+    }
   }
   if (lane == K) rdiag = M[0][K];
   // finish this column's updates here: left alone, the compiler defers the
@@ -163,10 +195,10 @@ __device__ __forceinline__ void householder_step(double (&M)[RPL][Q], double &rd
 
 // Householder QR of the register-resident M (rows across lanes).  On return
 // lane k (k < Q) holds row k of R in M[0][k..Q-1] and rdiag = R_kk.  The
-// column dot products of each step are summed over the wavefront together,
-// through `buf` (kSumBufDoubles of LDS; wave_sums_lds), or one by one by DPP
-// and lane swaps when VIA_LDS is false (no LDS; buf unused); all 64 lanes
-// take part.
+// reflector's products with the later columns of each step are summed over
+// the wavefront together, through `buf` (kSumBufDoubles of LDS;
+// wave_sums_lds), or one by one by DPP and lane swaps when VIA_LDS is false
+// (no LDS; buf unused); all 64 lanes take part.
 template <int Q, int RPL, bool VIA_LDS = true>
 __device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rdiag, int lane, double *buf) {
   rdiag = 0.0;
