@@ -48,8 +48,12 @@ template <int DIM, int ORDER>
 constexpr int qr_divfree_lds_doubles() {
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int QM = num_mono(DIM, ORDER - 1);
-  // R, R^-1; R_B row- and column-major; three broadcast vectors; u per row
-  return 2 * Q * Q + 2 * QM * QM + 3 * 64 + 8 * DIM * Q;
+  // R, R^-1; R_B row- and column-major; three broadcast vectors; u per row.
+  // The second factor's column sums use the space after R^-1 before R_B is
+  // written.
+  constexpr int SOLVE = 2 * Q * Q + 2 * QM * QM + 3 * 64 + 8 * DIM * Q;
+  constexpr int SUMS = 2 * Q * Q + kSumBufDoubles;
+  return SOLVE > SUMS ? SOLVE : SUMS;
 }
 
 // The divergence-free weights from the scalar factor (qr_factor: lane k < Q
@@ -120,7 +124,9 @@ __device__ __forceinline__ void qr_divfree_solve(const StencilArgs &a, const Row
       }
     }
     double rdb;
-    wave_householder<QM, KBL, false>(MB, rdb, lane, nullptr);  // lds holds R^-1
+    // the column sums through LDS past R^-1 once there are enough columns
+    // to batch (a wave sum each is cheaper for a handful)
+    wave_householder<QM, KBL, (QM >= 8)>(MB, rdb, lane, RBm);
     const double bmax = uniform_d(wave_max(lane < QM ? fabs(rdb) : 0.0));
     const double bmin = uniform_d(wave_min(lane < QM ? fabs(rdb) : DBL_MAX));
     deficient = !(bmin > kRankTol * bmax);
