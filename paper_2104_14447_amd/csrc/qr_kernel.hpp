@@ -21,7 +21,7 @@ constexpr int qr_lds_doubles() {
 template <int DIM, int ORDER, int BASIS, int RPL>
 __device__ __forceinline__ void qr_loop(const StencilArgs &a, const int *list, const int *count, const int *offset,
                                         int *cursor) {
-  __shared__ double lds[qr_lds_doubles<DIM, ORDER, BASIS>()];
+  __shared__ __align__(16) double lds[qr_lds_doubles<DIM, ORDER, BASIS>()];
   const RowKinds rk = row_kinds(DIM, BASIS == 1 ? 1 : 0, a.mask);
   const int n = readfirstlane_i(*count);
   const int off = readfirstlane_i(offset ? *offset : 0);
@@ -66,7 +66,7 @@ __device__ __forceinline__ void qr_shared_loop(const StencilArgs &as, const Sten
                                                const int *count, const int *offset, int *cursor) {
   constexpr int Q = num_mono(DIM, ORDER);
   constexpr int LS = qr_lds_doubles<DIM, ORDER, 0>(), LV = qr_lds_doubles<DIM, ORDER, 1>();
-  __shared__ double lds[LS > LV ? LS : LV];
+  __shared__ __align__(16) double lds[LS > LV ? LS : LV];
   const RowKinds rks = row_kinds(DIM, 0, as.mask);
   const RowKinds rkv = row_kinds(DIM, 1, av.mask);
   const int n = readfirstlane_i(*count);

@@ -71,43 +71,63 @@ __device__ __forceinline__ void load_rows(const StencilArgs &a, int t, Rows<DIM,
   for (int i = 0; i < RPL; ++i) row_s_w<DIM>(a, r.base, first + lane + 64 * i, r.N, xt, ie, r.s[i], r.w[i]);
 }
 
-// LDS the batched column sums of wave_householder take (a row of 17 doubles
-// per lane: 16 values and one of padding, so that the rows start in
-// different banks).
-constexpr int kSumBufDoubles = 64 * 17;
+// LDS the batched column sums of wave_householder take: a 16 x 66 tile of
+// partial values (value q of lane L at q * 66 + L; 66 keeps each lane's
+// reads 16-byte aligned) and 16 results.  The array must be 16-byte aligned.
+constexpr int kSumStride = 66;
+constexpr int kSumBufDoubles = 16 * kSumStride + 16;
 
-// v[FIRST..N) summed over the wavefront and multiplied by scale, bitwise the
-// same in every lane, 16 values at a time through LDS: every lane stores its
-// partial values, lane j + 16 g then adds value j over the 16 lanes
-// 16 g .. 16 g + 15 (pairwise, a fixed order), the four groups are combined
-// by lane swaps (both lanes of a pair add the same operands), lane j scales
-// value j, and value j is read from lane j.  One pass costs about 55 vector
-// instructions for 16 values, where a full wave sum per value (DPP within the
-// rows, then across them) costs about 18 each.  buf: kSumBufDoubles of LDS
-// owned by this wavefront; all 64 lanes active.
-template <int N, int FIRST>
-__device__ __forceinline__ void wave_sums_lds(double (&v)[N], double *buf, int lane, double scale) {
+// v[0..ch) (ch <= 16) summed over the wavefront and multiplied by scale,
+// bitwise the same in every lane, through LDS: every lane stores its partial
+// values, lane j + 16 g adds value j over the 16 lanes 16 g .. 16 g + 15
+// (contiguous, read 2 at a time; pairwise, a fixed order), the four groups
+// are combined by lane swaps (both lanes of a pair add the same operands),
+// lane j scales value j, and every lane takes the results: BCAST_LDS, from
+// LDS, 2 at a time (broadcast reads, into vector registers), else by lane
+// reads (into scalar registers, for kernels short of vector registers).
+// About 25 vector and 33 LDS instructions for 16 values (BCAST_LDS), where a
+// full wave sum per value (DPP within the rows, then across them) costs
+// about 18 vector instructions each.  buf: kSumBufDoubles of LDS owned by
+// this wavefront; all 64 lanes active.
+template <bool BCAST_LDS>
+__device__ __forceinline__ void wave_sum16_lds(double (&v)[16], int ch, double *buf, int lane, double scale) {
   const int j = lane & 15, g = lane >> 4;
+  const double2 *part = reinterpret_cast<const double2 *>(buf + j * kSumStride + 16 * g);
+  double *res = buf + 16 * kSumStride;
 #pragma unroll
-  for (int c0 = FIRST; c0 < N; c0 += 16) {
-    const int ch = N - c0 < 16 ? N - c0 : 16;
+  for (int q = 0; q < 16; ++q)
+    if (q < ch) buf[q * kSumStride + lane] = v[q];
+  wave_lds_sync();
+  // lanes j >= ch add stale values; their results are never read
+  double p[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (q < ch) buf[lane * 17 + q] = v[c0 + q];
-    wave_lds_sync();
-    double p[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) p[i] = j < ch ? buf[(16 * g + i) * 17 + j] : 0.0;
-#pragma unroll
-    for (int h = 8; h >= 1; h >>= 1)
-#pragma unroll
-      for (int i = 0; i < h; ++i) p[i] = p[i] + p[i + h];
-    const double sum = swap_pair_sum<32>(swap_pair_sum<16>(p[0])) * scale;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (q < ch) v[c0 + q] = readlane_d(sum, q);
-    wave_lds_sync();  // the next pass (or the caller) may rewrite buf
+  for (int i = 0; i < 8; ++i) {
+    const double2 t = part[i];
+    p[2 * i] = t.x;
+    p[2 * i + 1] = t.y;
   }
+#pragma unroll
+  for (int h = 8; h >= 1; h >>= 1)
+#pragma unroll
+    for (int i = 0; i < h; ++i) p[i] = p[i] + p[i + h];
+  const double sum = swap_pair_sum<32>(swap_pair_sum<16>(p[0])) * scale;
+  if constexpr (BCAST_LDS) {
+    if (lane < 16) res[lane] = sum;
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+      if (q < ch) {
+        const double2 t = reinterpret_cast<const double2 *>(res)[q / 2];
+        v[q] = t.x;
+        v[q + 1] = t.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q < ch) v[q] = readlane_d(sum, q);
+  }
+  wave_lds_sync();  // the next call (or the caller) may rewrite buf
 }
 
 // One Householder step of wave_householder: column K of M is reduced and the
@@ -131,21 +151,29 @@ __device__ __forceinline__ void householder_step(double (&M)[RPL][Q], double &rd
       const double beta = xk >= 0.0 ? -norm : norm;
       const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
       const double v0 = lane > K ? M[0][K] : (lane == K ? xk - beta : 0.0);
-      if constexpr (K + 1 < Q) {
-        double coef[Q];
+      // 16 columns at a time: their products, sums and updates (a chunk's
+      // values are all that is held beyond M)
 #pragma unroll
-        for (int l = K + 1; l < Q; ++l) {
-          double t = v0 * M[0][l];
+      for (int c0 = K + 1; c0 < Q; c0 += 16) {
+        const int ch = Q - c0 < 16 ? Q - c0 : 16;
+        double coef[16];
 #pragma unroll
-          for (int i = 1; i < RPL; ++i) t = fma(M[i][K], M[i][l], t);
-          coef[l] = t;
+        for (int q = 0; q < 16; ++q) {
+          if (q < ch) {
+            double t = v0 * M[0][c0 + q];
+#pragma unroll
+            for (int i = 1; i < RPL; ++i) t = fma(M[i][K], M[i][c0 + q], t);
+            coef[q] = t;
+          }
         }
-        wave_sums_lds<Q, K + 1>(coef, buf, lane, 2.0 * inv_vtv);
+        wave_sum16_lds<(RPL * Q <= 80)>(coef, ch, buf, lane, 2.0 * inv_vtv);
 #pragma unroll
-        for (int l = K + 1; l < Q; ++l) {
-          M[0][l] -= coef[l] * v0;
+        for (int q = 0; q < 16; ++q) {
+          if (q < ch) {
+            M[0][c0 + q] -= coef[q] * v0;
 #pragma unroll
-          for (int i = 1; i < RPL; ++i) M[i][l] -= coef[l] * M[i][K];
+            for (int i = 1; i < RPL; ++i) M[i][c0 + q] -= coef[q] * M[i][K];
+          }
         }
       }
       if (lane == K) M[0][K] = beta;
@@ -197,7 +225,7 @@ __device__ __forceinline__ void householder_step(double (&M)[RPL][Q], double &rd
 // lane k (k < Q) holds row k of R in M[0][k..Q-1] and rdiag = R_kk.  The
 // reflector's products with the later columns of each step are summed over
 // the wavefront together, through `buf` (kSumBufDoubles of LDS;
-// wave_sums_lds), or one by one by DPP and lane swaps when VIA_LDS is false
+// wave_sum16_lds), or one by one by DPP and lane swaps when VIA_LDS is false
 // (no LDS; buf unused); all 64 lanes take part.
 template <int Q, int RPL, bool VIA_LDS = true>
 __device__ __forceinline__ void wave_householder(double (&M)[RPL][Q], double &rdiag, int lane, double *buf) {

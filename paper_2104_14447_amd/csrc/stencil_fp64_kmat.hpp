@@ -228,7 +228,7 @@ __device__ void qr_divfree_kmat_target(const StencilArgs &a, const RowKinds &rk,
 // Persistent kernel over the queue aux_list[0 .. *count) (any row count).
 template <int DIM, int ORDER, int RPL>
 __global__ __launch_bounds__(64) void k_qr_kmat(StencilArgs a, const int *list, const int *count, int *cursor) {
-  __shared__ double lds[qr_kmat_lds_doubles<DIM, ORDER>()];
+  __shared__ __align__(16) double lds[qr_kmat_lds_doubles<DIM, ORDER>()];
   const RowKinds rk = row_kinds(DIM, 1, a.mask);
   const int n = readfirstlane_i(*count);
   for (;;) {
