@@ -147,9 +147,20 @@ __device__ __forceinline__ void householder_step(double (&M)[RPL][Q], double &rd
     const double sigma = uniform_d(wave_sum_uniform(ss));  // the same in every lane; a scalar branch
     const double xk = readlane_d(M[0][K], K);
     if (sigma > 0.0) {
-      const double norm = sqrt(sigma);
+      // |x| and 2 / v.v = 1 / (|x|^2 + |x_K| |x|) from the hardware
+      // reciprocal square root and reciprocal, each refined by Newton steps
+      // (quadratic convergence: two steps take an estimate good to 1e-4 to
+      // a few ulp), in place of the correctly rounded sqrt and division
+      // sequences on the step's dependent chain
+      const double y0 = __builtin_amdgcn_rsq(sigma);
+      const double y1 = fma(y0, fma(-(0.5 * sigma) * y0, y0, 0.5), y0);
+      const double n0 = sigma * y1;
+      const double norm = fma(fma(-n0, n0, sigma), 0.5 * y1, n0);
       const double beta = xk >= 0.0 ? -norm : norm;
-      const double inv_vtv = 1.0 / (2.0 * beta * (beta - xk));
+      const double d = fma(fabs(xk), norm, sigma);
+      const double r0 = __builtin_amdgcn_rcp(d);
+      const double r1 = fma(r0, fma(-d, r0, 1.0), r0);
+      const double two_inv_vtv = fma(r1, fma(-d, r1, 1.0), r1);
       const double v0 = lane > K ? M[0][K] : (lane == K ? xk - beta : 0.0);
       // 16 columns at a time: their products, sums and updates (a chunk's
       // values are all that is held beyond M)
@@ -166,7 +177,7 @@ __device__ __forceinline__ void householder_step(double (&M)[RPL][Q], double &rd
             coef[q] = t;
           }
         }
-        wave_sum16_lds<(RPL * Q <= 80)>(coef, ch, buf, lane, 2.0 * inv_vtv);
+        wave_sum16_lds<(RPL * Q <= 80)>(coef, ch, buf, lane, two_inv_vtv);
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           if (q < ch) {
