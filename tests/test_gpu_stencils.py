@@ -25,6 +25,10 @@ CASES = {
     "3d_divfree_m2": (lambda: W.jittered_grid(8000, 3, 1003), ("knn", 60), "divfree", 2, 1 | 4 | 8, 4),
     "2d_divfree_m2": (lambda: W.jittered_grid(3000, 2, 7), ("knn", 20), "divfree", 2, 1 | 4 | 8, 4),
     "3d_divfree_m4": (lambda: W.jittered_grid(8000, 3, 1005), ("knn", 170), "divfree", 4, 4 | 8, 6),
+    # the FP64 solve's second factor (of B) at 10 columns: its column sums
+    # go through LDS (3-D order 3, 2-D order 4), where order 2 takes wave sums
+    "3d_divfree_m3": (lambda: W.jittered_grid(6000, 3, 1006), ("knn", 100), "divfree", 3, 1 | 4 | 8, 4),
+    "2d_divfree_m4": (lambda: W.jittered_grid(4000, 2, 1007), ("knn", 40), "divfree", 4, 1 | 4 | 8, 4),
     # fewer neighbours than scalar monomials (9 < 10, 30 < 35) but enough
     # rows for the divergence-free functions (27 >= 26, 90 >= 85): the
     # divergence-free sample matrix is factored itself
