@@ -146,7 +146,9 @@ def parse():
                     help="configuration (default: the 2M-point uneven radius workload)")
     ap.add_argument("--n", type=int, default=0, help="points (default: the configuration's size)")
     ap.add_argument("--sample", type=int, default=256, help="targets checked against the oracle")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target duration of the oracle timing leg")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target duration of the oracle timing leg (every target when they are estimated to "
+                         "take at most twice this)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--scheme", type=int, default=0,
                     help="mixed scheme: 0 auto, 1 fused/rows residual, 2 fused/moment Gram, 3 pipeline, 4 wavefront per target")
@@ -672,12 +674,15 @@ def main():
                                      nthreads=nthreads)[:2] + (None,) for bs in bases]
             return a_rp, a_col, a_eps, outs_
 
-        # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds
+        # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds;
+        # every target when they are estimated to take at most twice that, so
+        # that the all-target parity does not hinge on the host's speed
         m = max(1000, n // 64)
         t1 = time.perf_counter()
         oracle_run(m, threads)
         dt = time.perf_counter() - t1
-        m2 = int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
+        est_all = dt * n / m
+        m2 = n if est_all <= 2 * args.cpu_seconds else int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
         t1 = time.perf_counter()
         a_rp, a_col, a_eps, a_out = oracle_run(m2, threads)
         dt2 = time.perf_counter() - t1
