@@ -85,10 +85,11 @@ constexpr int kSumBufDoubles = 16 * kSumStride + 16;
 // lane j scales value j, and every lane takes the results: BCAST_LDS, from
 // LDS, 2 at a time (broadcast reads, into vector registers), else by lane
 // reads (into scalar registers, for kernels short of vector registers).
-// About 25 vector and 33 LDS instructions for 16 values (BCAST_LDS), where a
-// full wave sum per value (DPP within the rows, then across them) costs
-// about 18 vector instructions each.  buf: kSumBufDoubles of LDS owned by
-// this wavefront; all 64 lanes active.
+// Up to 8 values take half the reads (below).  About 25 vector and 33 LDS
+// instructions for 16 values (BCAST_LDS), where a full wave sum per value
+// (DPP within the rows, then across them) costs about 18 vector
+// instructions each.  buf: kSumBufDoubles of LDS owned by this wavefront;
+// all 64 lanes active.
 template <bool BCAST_LDS>
 __device__ __forceinline__ void wave_sum16_lds(double (&v)[16], int ch, double *buf, int lane, double scale) {
   const int j = lane & 15, g = lane >> 4;
@@ -99,20 +100,42 @@ __device__ __forceinline__ void wave_sum16_lds(double (&v)[16], int ch, double *
     if (q < ch) buf[q * kSumStride + lane] = v[q];
   wave_lds_sync();
   // lanes j >= ch add stale values; their results are never read
-  double p[16];
+  double sum;
+  if (ch <= 8) {
+    // at most 8 values: lane j + 8 s (j < 8) adds value j over the 8 lanes
+    // 8 s .. 8 s + 7 (half the reads), and the lane 8 apart in its row
+    // (the same value, the other half of the row's sources) is added by a
+    // rotation of the row by 8, which pairs the two lanes both ways
+    const double2 *part8 = reinterpret_cast<const double2 *>(buf + (lane & 7) * kSumStride + 8 * (lane >> 3));
+    double p[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const double2 t = part[i];
-    p[2 * i] = t.x;
-    p[2 * i + 1] = t.y;
+    for (int i = 0; i < 4; ++i) {
+      const double2 t = part8[i];
+      p[2 * i] = t.x;
+      p[2 * i + 1] = t.y;
+    }
+#pragma unroll
+    for (int h = 4; h >= 1; h >>= 1)
+#pragma unroll
+      for (int i = 0; i < h; ++i) p[i] = p[i] + p[i + h];
+    const double r = p[0] + dpp_d<0x128>(p[0]);  // row_ror:8
+    sum = swap_pair_sum<32>(swap_pair_sum<16>(r)) * scale;
+  } else {
+    double p[16];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const double2 t = part[i];
+      p[2 * i] = t.x;
+      p[2 * i + 1] = t.y;
+    }
+#pragma unroll
+    for (int h = 8; h >= 1; h >>= 1)
+#pragma unroll
+      for (int i = 0; i < h; ++i) p[i] = p[i] + p[i + h];
+    sum = swap_pair_sum<32>(swap_pair_sum<16>(p[0])) * scale;
   }
-#pragma unroll
-  for (int h = 8; h >= 1; h >>= 1)
-#pragma unroll
-    for (int i = 0; i < h; ++i) p[i] = p[i] + p[i + h];
-  const double sum = swap_pair_sum<32>(swap_pair_sum<16>(p[0])) * scale;
   if constexpr (BCAST_LDS) {
-    if (lane < 16) res[lane] = sum;
+    if (lane < 16) res[lane] = sum;  // ch <= 8: lanes 0..7 hold values 0..7
     wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < 16; q += 2) {
@@ -125,7 +148,7 @@ __device__ __forceinline__ void wave_sum16_lds(double (&v)[16], int ch, double *
   } else {
 #pragma unroll
     for (int q = 0; q < 16; ++q)
-      if (q < ch) v[q] = readlane_d(sum, q);
+      if (q < ch) v[q] = readlane_d(sum, q);  // ch <= 8: lane q holds value q as well
   }
   wave_lds_sync();  // the next call (or the caller) may rewrite buf
 }
