@@ -241,6 +241,16 @@ def stokes_main(args):
     print(json.dumps(line))
 
 
+def oracle_sample_size(n, m, dt, cpu_seconds):
+    """Targets for the oracle's timing leg, from a calibration run of m
+    targets that took dt seconds: every target when they are estimated to
+    take at most twice cpu_seconds (so that the all-target parity does not
+    hinge on the host's speed), else enough for about cpu_seconds."""
+    if dt * n / m <= 2 * cpu_seconds:
+        return n
+    return int(min(n, max(m, m * cpu_seconds / max(dt, 1e-3))))
+
+
 def host_info():
     """Host cores available to this job and the CPU model.  The oracle's
     timing uses every core of the job's CPU share: the affinity mask, capped
@@ -674,15 +684,12 @@ def main():
                                      nthreads=nthreads)[:2] + (None,) for bs in bases]
             return a_rp, a_col, a_eps, outs_
 
-        # calibrate on 1/64 of the targets, then size the sample for ~cpu_seconds;
-        # every target when they are estimated to take at most twice that, so
-        # that the all-target parity does not hinge on the host's speed
+        # calibrate on 1/64 of the targets, then size the sample
         m = max(1000, n // 64)
         t1 = time.perf_counter()
         oracle_run(m, threads)
         dt = time.perf_counter() - t1
-        est_all = dt * n / m
-        m2 = n if est_all <= 2 * args.cpu_seconds else int(min(n, max(m, m * args.cpu_seconds / max(dt, 1e-3))))
+        m2 = oracle_sample_size(n, m, dt, args.cpu_seconds)
         t1 = time.perf_counter()
         a_rp, a_col, a_eps, a_out = oracle_run(m2, threads)
         dt2 = time.perf_counter() - t1

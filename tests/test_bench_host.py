@@ -41,3 +41,15 @@ def test_shared_gram_is_counted_once_for_two_bases():
     only_s = bench.alg_flops_workload(nnz, n_tgt, 3, [s]) - gram
     only_v = bench.alg_flops_workload(nnz, n_tgt, 3, [v]) - gram
     assert abs(both - (gram + only_s + only_v)) < 1e-9 * both
+
+
+def test_oracle_sample_size():
+    """The oracle leg takes every target when they fit twice the timing
+    budget, and a sample sized for the budget otherwise."""
+    import bench
+    n, m = 2_000_000, 31_250
+    assert bench.oracle_sample_size(n, m, 0.10, 15.0) == n      # 6.4 s for all
+    assert bench.oracle_sample_size(n, m, 0.24, 15.0) == n      # 15.4 s for all: within 2 x 15 s
+    k = bench.oracle_sample_size(n, m, 1.0, 15.0)               # 64 s for all
+    assert k == int(m * 15.0 / 1.0) and m <= k < n
+    assert bench.oracle_sample_size(n, m, 100.0, 15.0) == m     # never below the calibration run
