@@ -155,7 +155,8 @@ __device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, boo
                                     double *mom) {
   constexpr int NM = num_mono(DIM, 2 * ORDER);
   constexpr int RS = 32;  // moments per LDS reduction round
-  __shared__ double red[64][RS + 1];
+  constexpr int RW = 66;  // row of the reduction tile: one moment, 64 lanes (+2: rows start in other banks)
+  __shared__ __align__(16) double red[RS * RW];
   const int64_t base = rc.base;
   const int N = rc.n;
   const double ie = rc.ie;
@@ -195,21 +196,28 @@ __device__ void pipe_moments_target(const StencilArgs &a, const PipeRec &rc, boo
 #pragma unroll
   for (int m = 0; m < NM; ++m) asm volatile("" : "+v"(mu[m]));
   // sum the G lanes' partial moments through LDS, RS moments per round:
-  // every lane writes its partials, then lane lg of the group adds column
-  // lg + G*k (< RS) over the group's rows, in lane order, and stores it
+  // every lane writes its partials (moment q of lane L at q * RW + L), then
+  // lane lg of the group adds moment lg + G*k (< RS) over the group's lanes,
+  // in lane order, reading them two at a time (the group's lanes are
+  // contiguous in a moment's row), and stores it
   const int lane = lane_id(), grp0 = lane - lg;
 #pragma unroll
   for (int r0 = 0; r0 < NM; r0 += RS) {
 #pragma unroll
-    for (int q = 0; q < RS; ++q) red[lane][q] = r0 + q < NM ? mu[r0 + q] : 0.0;
+    for (int q = 0; q < RS; ++q) red[q * RW + lane] = r0 + q < NM ? mu[r0 + q] : 0.0;
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < (RS + G - 1) / G; ++k) {
       const int q = lg + G * k;
       if (q < RS) {
+        const double2 *row = reinterpret_cast<const double2 *>(red + q * RW + grp0);
         double acc = 0.0;
 #pragma unroll
-        for (int l = 0; l < G; ++l) acc += red[grp0 + l][q];
+        for (int l = 0; l < G / 2; ++l) {
+          const double2 t = row[l];
+          acc += t.x;
+          acc += t.y;
+        }
         if (valid && r0 + q < NM) mom[(int64_t)slot * NM + r0 + q] = acc;
       }
     }
