@@ -187,28 +187,37 @@ __device__ __forceinline__ bool sweep_inverse(double (&a)[Q], double *col, doubl
 }
 
 // Moments mu_g (lexicographic order) of the rows held by the wavefront into
-// mu[]; red is the LDS reduction buffer (64 x (RS + 1) doubles).  One step per
+// mu[]; red is the LDS reduction buffer (64 x (RS + 1) doubles, 16-byte aligned).  One step per
 // moment, unrolled by template recursion so that every exponent, register
 // index and round boundary is a compile-time constant.  RS moments go
 // through LDS per round (8, 16 or 32: the autotuner's choice, a trade of
 // registers and LDS for barriers).
 
-// sum one round over the wavefront: every lane stores its partials, then
-// lanes q + RS p add rows RS p .. RS p + RS - 1 of column q and butterfly
-// steps combine the 64 / RS parts (fixed order)
+// sum one round over the wavefront: every lane stores its partials
+// (moment q of lane L at q * 66 + L: a moment's partials are contiguous),
+// then lanes q + RS p add lanes RS p .. RS p + RS - 1 of moment q, read 16
+// bytes at a time, and butterfly steps combine the 64 / RS parts (fixed
+// order).  red: 16-byte aligned, RS * 66 <= 64 * (RS + 1) doubles.
 template <int NM, int RS>
 __device__ __forceinline__ void wave_round(const double (&acc)[RS], int g0, double *red, double *mu) {
   static_assert(RS == 8 || RS == 16 || RS == 32, "round size");
+  constexpr int W = 66;
+  static_assert(RS * W <= 64 * (RS + 1), "the tile fits the reduction buffer");
   const int lane = lane_id();
 #pragma unroll
-  for (int q = 0; q < RS; ++q) red[lane * (RS + 1) + q] = acc[q];
+  for (int q = 0; q < RS; ++q) red[q * W + lane] = acc[q];
   __syncthreads();
   const int q = lane & (RS - 1), part = lane / RS;
-  // pairwise sum of the RS rows (fixed order; a chain of log2 RS dependent
-  // adds instead of RS)
+  // pairwise sum of the RS lanes' values (fixed order; a chain of log2 RS
+  // dependent adds instead of RS)
   double v[RS];
+  const double2 *row = reinterpret_cast<const double2 *>(red + q * W + part * RS);
 #pragma unroll
-  for (int l = 0; l < RS; ++l) v[l] = red[(part * RS + l) * (RS + 1) + q];
+  for (int l = 0; l < RS / 2; ++l) {
+    const double2 t = row[l];
+    v[2 * l] = t.x;
+    v[2 * l + 1] = t.y;
+  }
 #pragma unroll
   for (int h = RS / 2; h >= 1; h >>= 1)
 #pragma unroll
@@ -512,7 +521,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWaveCand[CA
   static_assert(QS <= 64, "one basis function per lane");
   static_assert(!DIVF || DivBuf<DIM, ORDER>::SIZE <= BIG, "divergence-free buffers fit");
   static_assert(5 * 64 <= BIG, "scalar coefficients fit");
-  __shared__ double big[BIG];      // moment reduction, then (divergence-free) -E^-1
+  __shared__ __align__(16) double big[BIG];  // moment reduction, then (divergence-free) -E^-1
   __shared__ double mu[NM];        // moments, lexicographic order
   __shared__ double vb[4][64];     // broadcast vectors
   __shared__ __align__(16) double colb[4 * 64];  // pivot columns of the sweeps
