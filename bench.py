@@ -296,7 +296,7 @@ def main():
         stokes_main(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not a launched path)"}))
         sys.exit(2)
     import torch

@@ -13,7 +13,7 @@
  *    selected here either as the k nearest (ties broken by index) or as all
  *    points closer than a fixed radius, floored to the k_min nearest;
  *  - the kernel W(r) = (1 - r/eps)^p for r < eps, else 0 (Section 2.1, kernel
- *    equation; the outer power p is the reading taken for this build);
+ *    equation; the outer power p is a parameter of every call);
  *  - the eps-scaled Taylor monomials p_a(x) = prod_i ((x_i - xT_i)/eps)^a_i/a_i!
  *    (Section 2.1, 1D and 3D basis equations), or a divergence-free vector
  *    basis psi_i = sum_{a,c} T[(a,c),i] p_a e_c (Section 2.2);
