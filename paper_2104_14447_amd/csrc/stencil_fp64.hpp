@@ -291,6 +291,37 @@ __device__ __forceinline__ double tri_solve_rtr(const double *Rm, const double *
   return b;
 }
 
+// tri_solve_rtr for NR right-hand sides at once (b[r] on lane a: entry a of
+// right-hand side r): the same operations for each, interleaved, so that the
+// 2Q dependent steps are walked once and each step's row of R is read once.
+template <int Q, int NR>
+__device__ __forceinline__ void tri_solve_rtr_multi(const double *Rm, const double *Rt, double (&b)[NR],
+                                                    double rdiag, int lane) {
+  const double rinv = lane < Q ? 1.0 / rdiag : 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const double ik = readlane_d(rinv, k);
+    const double rm = Rm[k * Q + (lane < Q ? lane : 0)];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double zk = readlane_d(b[r], k) * ik;
+      if (lane == k) b[r] = zk;
+      if (lane > k && lane < Q) b[r] -= rm * zk;
+    }
+  }
+#pragma unroll
+  for (int k = Q - 1; k >= 0; --k) {
+    const double ik = readlane_d(rinv, k);
+    const double rt = Rt[k * Q + (lane < Q ? lane : 0)];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double yk = readlane_d(b[r], k) * ik;
+      if (lane == k) b[r] = yk;
+      if (lane < k) b[r] -= rt * yk;
+    }
+  }
+}
+
 // The target's rows, its weighted sample matrix and the Householder factor:
 // on return lane k < Q holds row k of R in M[0][k..Q-1] and rdiag = R_kk.
 // A row of more than 64 RPL neighbours is factored chunk by chunk (tall-skinny
@@ -405,7 +436,31 @@ __device__ __forceinline__ void qr_scalar_solve(const StencilArgs &a, const RowK
       sF = uniform_d(wave_sum(lane < Q ? Fq * zc : 0.0));
     }
   }
-  for (int f = 0; f < F; ++f) {
+  int f = 0;
+  if (!con) {
+    // two to four functionals at once: one walk of the dependent steps
+    for (; f + 1 < F; f += 4) {
+      double bb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bb[u] = 0.0;
+        if (f + u < F) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q)
+            if (lane == q) bb[u] = scalar_lambda<DIM, ORDER>(rk.kind[f + u], q + SKIP, ie);
+        }
+      }
+      tri_solve_rtr_multi<Q, 4>(Rm, Rt, bb, rdiag, lane);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (f + u < F) {
+          if (SKIP == 0 && a.hweights && lane == 0) a.hweights[(int64_t)t * F + f + u] = 0.0;
+          if (lane < Q) Y[(f + u) * Q + lane] = bb[u];
+        }
+      }
+    }
+  }
+  for (; f < F; ++f) {
     double b = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q)
